@@ -1,0 +1,372 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each check is an independent
+formulation (exact diagonalization, brute-force HF-GKBA, the paper's second
+formulation of the same term, a closed form) or an exact invariant.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ed, general as G, gkba, hubbard as H, integrate as I, observables as O
+from workloads import (aufbau_gless, chain_hopping, factorized_w, gue, hubbard_chain_system,
+                       hubbard_spin_orbital_w, random_g2, random_gless, rng)
+
+T = lambda x: torch.as_tensor(np.asarray(x), dtype=torch.complex128)  # noqa: E731
+
+
+def _blk(g, ns, a, b, c, d):
+    return g[a * ns:(a + 1) * ns, b * ns:(b + 1) * ns, c * ns:(c + 1) * ns, d * ns:(d + 1) * ns]
+
+
+# --------------------------------------------------------------------------- P9 inputs
+def test_generated_inputs_symmetries():
+    r = rng(1)
+    w = factorized_w(6, 5, r)
+    assert np.abs(w - w.transpose(1, 0, 3, 2)).max() == 0.0          # eq:wsymm_a
+    assert np.abs(w - w.transpose(2, 3, 0, 1).conj()).max() == 0.0   # eq:wsymm_b
+    g = random_gless(6, r)
+    assert np.abs(g + g.conj().T).max() == 0.0                        # G^< anti-Hermitian
+    ev = np.linalg.eigvalsh(-1j * g)
+    assert ev.min() > -1e-12 and ev.max() < 1 + 1e-12
+    g2 = random_g2(5, r)
+    m = g2.reshape(25, 25)
+    assert np.abs(m - m.conj().T).max() == 0.0                        # eq:Gsymm_b
+    assert np.abs(g2 - g2.transpose(1, 0, 3, 2)).max() == 0.0        # eq:Gsymm_a
+    s = hubbard_chain_system()
+    for sig in range(2):
+        n = -1j * s.g1[sig]
+        assert abs(np.trace(n).real - 4) < 1e-12
+        assert np.abs(n @ n - n).max() < 1e-12
+
+
+# --------------------------------------------------------------------------- P2 + Sec. VII reformulations
+def test_hubbard_reformulations_match_direct_forms():
+    """eq:soa-cubic-scheme == eq:phi-hubbard; Sec. VII.B/C reformulated Pi, L^pp, L^ph
+    == eq:pihubbardtrans, eq:lambdapp_hubb, eq:lambdaph_hubb."""
+    r = rng(11)
+    for ns in (3, 5):
+        X, Y = T(random_gless(ns, r)), T(random_gless(ns, r))
+        A = T(random_g2(ns, r, exchange=False))
+        B = T(random_g2(ns, r))
+        U = 0.8
+        assert (H.phi_direct(X, Y) - H.phi_cubic(X, Y)).abs().max() < 1e-14
+        assert (H.ladder_pp_direct(X, Y, U, A) - H.ladder_pp(X, Y, U, A)).abs().max() < 1e-14
+        assert (H.ladder_ph_direct(X, Y, U, A) - H.ladder_ph(X, Y, U, A)).abs().max() < 1e-14
+        assert (H.polarization_direct(Y, B, U) - H.polarization(Y, B, U)).abs().max() < 1e-14
+
+
+# --------------------------------------------------------------------------- P1 cross-basis identity
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw"])
+def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
+    """The general-basis equations (Secs. III.C, IV.C, V.A, V.B) with the Hubbard
+    interaction of eq:wmatrix-hubbard in the spin-orbital basis reproduce the
+    spin-resolved Hubbard equations, for a random symmetric state in which every
+    spin block of G2 is populated."""
+    ns, U = 4, 0.7
+    r = rng(12, ns)
+    X, Y = T(random_gless(ns, r)), T(random_gless(ns, r))
+    h0 = T(chain_hopping(ns) + np.diag(r.uniform(-0.3, 0.3, ns)))
+    nb = 2 * ns
+    gl = torch.zeros((nb, nb), dtype=torch.complex128)
+    gl[:ns, :ns], gl[ns:, ns:] = X, Y
+    g2 = T(random_g2(nb, r))
+    A = _blk(g2, ns, 0, 1, 0, 1).clone()
+    B = _blk(g2, ns, 0, 0, 0, 0).clone()
+    C = _blk(g2, ns, 1, 1, 1, 1).clone()
+    dg1, dg2 = G.rhs(torch.block_diag(h0, h0), T(hubbard_spin_orbital_w(ns, U)), gl, g2, se)
+    if se == "gw":
+        dX, dY, dA, dB, dC = H.rhs(h0, h0, U, X, Y, A, "gw", B=B, C=C)
+        assert (_blk(dg2, ns, 0, 0, 0, 0) - dB).abs().max() < 1e-13
+        assert (_blk(dg2, ns, 1, 1, 1, 1) - dC).abs().max() < 1e-13
+    else:
+        dX, dY, dA = H.rhs(h0, h0, U, X, Y, A, se)
+    scale = dA.abs().max()
+    assert scale > 1e-2
+    assert (dg1[:ns, :ns] - dX).abs().max() < 1e-13
+    assert (dg1[ns:, ns:] - dY).abs().max() < 1e-13
+    assert (_blk(dg2, ns, 0, 1, 0, 1) - dA).abs().max() < 1e-13 * scale * 10
+
+
+# --------------------------------------------------------------------------- compact vs Pi/Lambda forms
+def _compact_gw(h, w, gl, g2, exchange):
+    gg = G.greater(gl)
+    n = h.shape[0]
+    d = torch.eye(n, dtype=torch.complex128)
+    heps = (torch.einsum("il,jk->ijkl", d, h) - torch.einsum("jk,il->ijkl", d, h)   # eq:HF-gw
+            + G.gw_hcorr(w, gg, gl))
+    t = (torch.einsum("qjpl,qkpi->ijkl", heps, g2.conj())
+         - torch.einsum("qjpl,qkpi->ijkl", g2, heps.conj()))
+    return G.source(G.w_minus(w) if exchange else w, gg, gl) + t               # eq:g2-eq-gw
+
+
+def _compact_tpp(h, w, gl, g2):
+    gg = G.greater(gl)
+    n = h.shape[0]
+    d = torch.eye(n, dtype=torch.complex128)
+    h2 = torch.einsum("jl,ik->ijkl", d, h) + torch.einsum("ik,jl->ijkl", d, h)
+    hpp = h2 + G.tpp_hcorr(w, gg, gl)
+    t = (torch.einsum("ijpq,klpq->ijkl", hpp, g2.conj())
+         - torch.einsum("ijpq,klpq->ijkl", g2, hpp.conj()))
+    return G.source(G.w_minus(w), gg, gl) + t                                  # eq:g2-eq-tpp
+
+
+def _compact_tph(h, w, gl, g2):
+    gg = G.greater(gl)
+    n = h.shape[0]
+    d = torch.eye(n, dtype=torch.complex128)
+    hph = torch.einsum("jl,ik->ijkl", d, h) - torch.einsum("ik,jl->ijkl", d, h)
+    hph = hph + G.tph_hcorr(w, gg, gl)
+    t = (torch.einsum("ipql,kpqj->ijkl", hph, g2.conj())
+         - torch.einsum("ipql,kpqj->ijkl", g2, hph.conj()))
+    return G.source(G.w_minus(w), gg, gl) + t                                  # eq:g2-eq-tph
+
+
+@pytest.mark.parametrize("se", ["gw", "gw_x", "tpp", "tph"])
+def test_compact_forms_equal_polarization_ladder_forms(se):
+    """The paper gives each G2 equation twice: a compact form with the combined
+    quasi-Hamiltonian (eq:g2-eq-gw, eq:g2-eq-tpp, eq:g2-eq-tph) and a form with
+    the HF commutator split off plus Pi / Lambda (eq:g2-eq-gw-pi,
+    eq:g2-eq-tpp-lambda, eq:g2-eq-tph-lambda).  They agree on symmetric states."""
+    nb = 5
+    r = rng(13, nb)
+    h = T(gue(nb, r))
+    w = T(factorized_w(nb, 4, r))
+    gl = T(random_gless(nb, r))
+    g2 = T(random_g2(nb, r))
+    hhf = G.hf_hamiltonian(h, w, gl)
+    _, dg2 = G.rhs(h, w, gl, g2, se)
+    lhs = 1j * dg2                           # i dG2/dt
+    if se in ("gw", "gw_x"):
+        ref = _compact_gw(hhf, w, gl, g2, exchange=(se == "gw_x"))
+    elif se == "tpp":
+        ref = _compact_tpp(hhf, w, gl, g2)
+    else:
+        ref = _compact_tph(hhf, w, gl, g2)
+    assert (lhs - ref).abs().max() < 1e-12 * max(1.0, ref.abs().max())
+
+
+def test_soa_source_pair_matrix_identity():
+    """Psi^- written as four successive one-index sums (eq:soa-skalierung) equals
+    the pair-matrix form -(T - T^dagger), T = (G>xG>) W^- (G<xG<), which holds
+    because G^><are anti-Hermitian and W^- is a Hermitian pair matrix (eq:wsymm_b)."""
+    nb = 5
+    r = rng(14)
+    w = T(factorized_w(nb, 3, r))
+    gl = T(random_gless(nb, r))
+    gg = G.greater(gl)
+    wm = G.w_minus(w).reshape(nb * nb, nb * nb)
+    kg = torch.kron(gg, gg)
+    kl = torch.kron(gl, gl)
+    tt = kg @ wm @ kl
+    ref = -(tt - tt.conj().T).reshape((nb,) * 4)
+    assert (G.source(G.w_minus(w), gg, gl) - ref).abs().max() < 1e-13
+
+
+# --------------------------------------------------------------------------- P4 exact diagonalization
+def _ed_error_hubbard(ns, U, se, tmax=1.6, dt=0.01):
+    s = hubbard_chain_system(ns=ns, U=U, dt=dt, nsteps=int(round(tmax / dt)))
+    nb = 2 * ns
+    h = np.zeros((nb, nb), complex)
+    h[:ns, :ns], h[ns:, ns:] = s.h0[0], s.h0[1]
+    n0 = np.zeros((nb, nb), complex)
+    n0[:ns, :ns], n0[ns:, ns:] = -1j * s.g1[0], -1j * s.g1[1]
+    fs = ed.FockSystem(h, hubbard_spin_orbital_w(ns, U))
+    psi0 = fs.slater(n0)
+    f = I.hubbard_rhs_fn(s, se)
+    y = I.hubbard_initial(s, se)
+    err, t = 0.0, 0.0
+    for n in range(s.nsteps):
+        y = list(I.rk4_step(f, t, y, dt))
+        t = (n + 1) * dt
+        if (n + 1) % 20 == 0:
+            ne = fs.density_matrix(fs.evolve(psi0, t))
+            err = max(err, np.abs(-1j * y[0].numpy() - ne[:ns, :ns]).max(),
+                      np.abs(-1j * y[1].numpy() - ne[ns:, ns:]).max())
+    return err
+
+
+def _slope(us, errs):
+    return np.polyfit(np.log(us), np.log(errs), 1)[0]
+
+
+@pytest.mark.parametrize("ns,se", [(2, "soa"), (4, "soa"), (2, "tpp"), (2, "tph"), (2, "gw")])
+def test_ed_perturbative_order_hubbard(ns, se):
+    """Starting from an uncorrelated state, every G1-G2 closure contains all
+    O(w^2) terms of dn/dt, so |n - n_ED| = O(U^3) on a fixed time window."""
+    us = [0.025, 0.05, 0.1]
+    errs = [_ed_error_hubbard(ns, U, se) for U in us]
+    assert 2.8 < _slope(us, errs) < 3.25, errs
+
+
+def _ed_error_general(h, w, n0, se, tmax=1.6, dt=0.01):
+    fs = ed.FockSystem(h, w)
+    psi0 = fs.slater(n0)
+    nb = h.shape[0]
+    g1 = T(1j * n0)
+    g2 = torch.zeros((nb,) * 4, dtype=torch.complex128)
+    f = lambda t, y: G.rhs(T(h), T(w), y[0], y[1], se)  # noqa: E731
+    err, t = 0.0, 0.0
+    for n in range(int(round(tmax / dt))):
+        g1, g2 = I.rk4_step(f, t, (g1, g2), dt)
+        t = (n + 1) * dt
+        if (n + 1) % 20 == 0:
+            ne = fs.density_matrix(fs.evolve(psi0, t))
+            err = max(err, np.abs(-1j * g1.numpy() - ne).max())
+    return err
+
+
+@pytest.mark.parametrize("se,lo,hi", [("soa", 2.8, 3.25), ("tpp", 2.7, 3.25), ("gw_x", 2.7, 3.25),
+                                       ("gw", 1.6, 2.2)])
+def test_ed_perturbative_order_general_basis(se, lo, hi):
+    """Random general basis (Nb=5 spin orbitals, w -> lambda w): SOA, TPP and GW
+    with exchange are exact to O(w^2) in n (slope 3).  GW without exchange drops
+    the second-order exchange term, so its error is O(w^2) (slope 2)."""
+    r = rng(7, 5)
+    nb = 5
+    h = gue(nb, r)
+    w0 = factorized_w(nb, 4, r)
+    n0 = -1j * aufbau_gless(h + gue(nb, r), 2)
+    lams = [0.0125, 0.025, 0.05]
+    errs = [_ed_error_general(h, lam * w0, n0, se) for lam in lams]
+    assert lo < _slope(lams, errs) < hi, errs
+
+
+# --------------------------------------------------------------------------- P3 brute-force HF-GKBA
+def _gkba_difference(h, w, g1, dt, tend):
+    n = int(round(tend / dt))
+    nb = h.shape[0]
+    g2 = torch.zeros((nb,) * 4, dtype=torch.complex128)
+    f = lambda t, y: G.rhs(h, w, y[0], y[1], "soa")  # noqa: E731
+    gls, hs = [g1], [G.hf_hamiltonian(h, w, g1)]
+    t = 0.0
+    for k in range(n):
+        g1, g2 = I.rk4_step(f, t, (g1, g2), dt)
+        t = (k + 1) * dt
+        gls.append(g1)
+        hs.append(G.hf_hamiltonian(h, w, g1))
+    return gkba.collision_integral(w, gls, hs, dt, n), G.collision_integral(w, g2)
+
+
+@pytest.mark.parametrize("case", ["dimer", "general"])
+def test_g1g2_equals_brute_force_hf_gkba(case):
+    """The collision integral of the time-local scheme equals the memory
+    integral of ordinary HF-GKBA (second Born) on the same G1 history; the
+    difference is the quadrature error of the brute-force side, O(dt^2)."""
+    if case == "dimer":
+        s = hubbard_chain_system(ns=2, U=1.0)          # Hubbard dimer, U = J, half filling
+        h = np.zeros((4, 4), complex)
+        h[:2, :2], h[2:, 2:] = s.h0[0], s.h0[1]
+        g1 = np.zeros((4, 4), complex)
+        g1[:2, :2], g1[2:, 2:] = s.g1[0], s.g1[1]
+        w = hubbard_spin_orbital_w(2, 1.0)
+    else:
+        r = rng(8)
+        h = gue(4, r)
+        w = 0.3 * factorized_w(4, 3, r)
+        g1 = aufbau_gless(h + gue(4, r), 2)
+    ib1, ig1 = _gkba_difference(T(h), T(w), T(g1), 0.02, 0.8)
+    ib2, ig2 = _gkba_difference(T(h), T(w), T(g1), 0.01, 0.8)
+    d1 = (ib1 - ig1).abs().max().item()
+    d2 = (ib2 - ig2).abs().max().item()
+    assert 3.6 < d1 / d2 < 4.4                     # second-order convergence
+    rich = (4.0 * ib2 - ib1) / 3.0                 # Richardson extrapolation
+    assert (rich - ig2).abs().max() < 1e-7 * ig2.abs().max() * 100
+    assert ig2.abs().max() > 1e-3
+
+
+# --------------------------------------------------------------------------- P5 invariants, P6/P7 special cases
+@pytest.mark.parametrize("se", ["soa", "gw", "tpp", "tph", "dsl"])
+def test_conservation_and_symmetry_general(se):
+    s_nb = 5
+    r = rng(15, s_nb)
+    h = gue(s_nb, r)
+    w = 0.5 * factorized_w(s_nb, 4, r)
+    g1 = T(aufbau_gless(h + gue(s_nb, r), 2))
+    g2 = torch.zeros((s_nb,) * 4, dtype=torch.complex128)
+    f = lambda t, y: G.rhs(T(h), T(w), y[0], y[1], se)  # noqa: E731
+    o0 = O.general_observables(T(h), T(w), g1, g2)
+    t = 0.0
+    for n in range(100):
+        g1, g2 = I.rk4_step(f, t, (g1, g2), 0.01)
+        t += 0.01
+    o1 = O.general_observables(T(h), T(w), g1, g2)
+    assert abs(o1["N"] - o0["N"]) < 1e-12
+    assert o1["herm_resid"] < 1e-12
+    assert o1["exch_resid"] < 1e-12
+    assert abs(o1["E_tot"] - o0["E_tot"]) < 1e-8
+    assert abs(o1["E_corr"]) > 1e-4
+
+
+def test_energy_drift_is_fourth_order():
+    """For a time-independent Hamiltonian the scheme conserves the total energy
+    (Sec. VIII); with RK4 the drift over a fixed time falls at least as dt^4."""
+    s = hubbard_chain_system(ns=6, U=2.0)
+    drifts = []
+    for dt in (0.08, 0.04):
+        s.dt = dt
+        _, rec = I.propagate_hubbard(s, nsteps=int(round(4.0 / dt)), observables_every=int(round(4.0 / dt)))
+        drifts.append(abs(rec[-1]["E_tot"] - rec[0]["E_tot"]))
+        assert abs(rec[-1]["N_up"] - rec[0]["N_up"]) < 1e-12
+    assert drifts[0] / drifts[1] > 14.0, drifts
+    assert drifts[1] < 1e-7
+
+
+def test_noninteracting_limit_closed_form():
+    """w = 0 and G2(t0) = 0: G2 stays exactly zero and G^<(t) = e^{-iht} G^<(0) e^{iht}
+    up to the RK4 error, which falls as dt^4."""
+    nb = 6
+    r = rng(16)
+    h = gue(nb, r)
+    g10 = aufbau_gless(h + gue(nb, r), 3)
+    w = np.zeros((nb,) * 4, complex)
+    e, v = np.linalg.eigh(h)
+    u = (v * np.exp(-1j * e * 1.0)) @ v.conj().T
+    exact = u @ g10 @ u.conj().T
+    errs = []
+    for dt in (0.02, 0.01):
+        g1 = T(g10)
+        g2 = torch.zeros((nb,) * 4, dtype=torch.complex128)
+        f = lambda t, y: G.rhs(T(h), T(w), y[0], y[1], "dsl")  # noqa: E731
+        t = 0.0
+        for n in range(int(round(1.0 / dt))):
+            g1, g2 = I.rk4_step(f, t, (g1, g2), dt)
+            t += dt
+        assert g2.abs().max().item() == 0.0
+        errs.append(np.abs(g1.numpy() - exact).max())
+    assert errs[1] < 1e-6
+    assert 12.0 < errs[0] / errs[1] < 20.0, errs
+
+
+def test_ladder_and_polarization_vanish_without_correlations():
+    """With G2 = 0 the Pi and Lambda terms vanish, so every selfenergy with
+    exchange gives the SOA right-hand side (eq:g2-eq-gw-pi, eq:g2-eq-tpp-lambda)."""
+    nb = 5
+    r = rng(17)
+    h = T(gue(nb, r))
+    w = T(factorized_w(nb, 3, r))
+    gl = T(random_gless(nb, r))
+    g2 = torch.zeros((nb,) * 4, dtype=torch.complex128)
+    ref = G.rhs(h, w, gl, g2, "soa")
+    for se in ("gw_x", "tpp", "tph", "dsl"):
+        out = G.rhs(h, w, gl, g2, se)
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+
+
+# --------------------------------------------------------------------------- planted mistakes
+def test_planted_mistakes_are_caught(monkeypatch):
+    """Plant plausible mistakes in the oracle (CPU only) and check that the
+    exact-diagonalization order test or the invariants reject them."""
+    us = [0.025, 0.05, 0.1]
+    base = [_ed_error_hubbard(2, U, "soa") for U in us]
+    assert 2.8 < _slope(us, base) < 3.25
+    orig_source = H.source
+    monkeypatch.setattr(H, "source", lambda X, Y, U, direct=False: -orig_source(X, Y, U, direct))
+    bad = [_ed_error_hubbard(2, U, "soa") for U in us]
+    assert _slope(us, bad) < 2.5                    # wrong sign of Psi -> error O(U^2)
+    monkeypatch.setattr(H, "source", orig_source)
+    orig_coll = H.collision_integrals
+    monkeypatch.setattr(H, "collision_integrals",
+                        lambda A, U: tuple(x.T for x in orig_coll(A, U)))
+    bad = [_ed_error_hubbard(2, U, "soa") for U in us]
+    assert _slope(us, bad) < 2.5 or max(bad) > 10 * max(base)   # transposed I
