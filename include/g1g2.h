@@ -1,0 +1,162 @@
+/*
+ * g1g2.h -- C ABI of the MI355X G1-G2 propagator.
+ *
+ * The library propagates the time-diagonal one-particle Green function
+ * G1 = G^<(t) together with the correlated two-particle Green function
+ * G2 = script-G(t) of the G1-G2 scheme (Joost, Schluenzen, Bonitz,
+ * arXiv:2002.12717) within the Hartree-Fock generalized Kadanoff-Baym ansatz.
+ *
+ * Units and conventions (fixed by the paper, Sec. II):
+ *   hbar = 1; fermions; G^< = i n with n the one-particle density matrix
+ *   (eq:g-glsymm); the pair interaction w_ijkl multiplies
+ *   1/2 c+_i c+_j c_l c_k in the Hamiltonian (eq:h).
+ *
+ * Memory layout of every array crossing this boundary: row-major, last index
+ * fastest, complex numbers as interleaved (re, im) IEEE doubles (the layout of
+ * C99 double complex and of torch.complex128).
+ *   general basis (nb spin orbitals):  h0, G1: [nb][nb];  w, G2: [nb]^4
+ *   Hubbard basis (nb sites):          h0, G1: [2][nb][nb] (spin up, spin down);
+ *                                      G2 = G2^{up down up down}: [nb]^4
+ *
+ * Pointers are host memory unless G1G2_PTR_DEVICE is set in desc.flags (then
+ * they are device pointers on the current HIP device, e.g. torch data_ptr()).
+ * g1g2_rhs always takes device pointers.  Inputs are copied; the caller keeps
+ * ownership of everything it passes.  The context owns all device memory it
+ * allocates and frees it in g1g2_destroy.  All work is ordered on the stream
+ * given to g1g2_init (NULL = the default stream); calls that return host data
+ * (observables, get_state) synchronize that stream.
+ *
+ * Errors: every call returns a g1g2_status; nothing throws or aborts across
+ * this boundary.  The text of the last error of a context is available from
+ * g1g2_last_error.  A context is not thread-safe.
+ */
+#ifndef G1G2_H
+#define G1G2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    G1G2_OK = 0,
+    G1G2_EINVAL = -1,       /* bad argument, shape or flag                         */
+    G1G2_ENOMEM = -2,       /* device allocation failed                            */
+    G1G2_EDEVICE = -3,      /* HIP runtime error or no usable device               */
+    G1G2_EUNSUPPORTED = -4, /* basis x selfenergy x precision not implemented      */
+    G1G2_EDIVERGED = -5,    /* non-finite state or occupation outside [-0.5, 1.5]  */
+    G1G2_ESTATE = -6        /* call not valid in the current state of the context  */
+} g1g2_status;
+
+/* Selfenergy closing the G2 equation:
+ *   SOA: second Born, eq:result_eom_soa (source Psi^-).
+ *   GW : eq:g2-eq-gw-pi (source Psi without exchange unless G1G2_GW_EXCHANGE).
+ *   TPP: particle-particle T matrix, eq:g2-eq-tpp-lambda.                         */
+typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2 } g1g2_selfenergy;
+
+/* GENERAL: arbitrary orthonormal basis with a four-index w (Sec. III.C).
+ * HUBBARD: Fermi-Hubbard model with on-site U (Sec. III.D); h0 per spin may be
+ *          any Hermitian matrix (hopping plus on-site potentials).            */
+typedef enum { G1G2_GENERAL = 0, G1G2_HUBBARD = 1 } g1g2_basis;
+
+/* FP64: every operation in binary64.
+ * MIXED: the O(nb^5) tensor contractions of the general basis run in binary32
+ *        on the matrix cores with binary64 accumulation across blocks; G1, the
+ *        Runge-Kutta registers, h^HF, the collision integral and all
+ *        observables stay binary64.                                            */
+typedef enum { G1G2_FP64 = 0, G1G2_MIXED = 1 } g1g2_precision;
+
+enum {
+    G1G2_PTR_DEVICE = 1,    /* host-side pointer arguments are device pointers      */
+    G1G2_GW_EXCHANGE = 2    /* GW: use Psi^- instead of Psi (end of Sec. IV.B)      */
+};
+
+typedef struct {
+    int32_t basis;          /* g1g2_basis                                          */
+    int32_t selfenergy;     /* g1g2_selfenergy                                     */
+    int32_t precision;      /* g1g2_precision                                      */
+    int32_t flags;          /* bitwise OR of the flags above                        */
+    int32_t nb;             /* general: spin orbitals; Hubbard: sites per spin      */
+    double U;               /* Hubbard on-site interaction (ignored for general)   */
+} g1g2_desc;
+
+typedef struct {
+    double t;               /* current time                                        */
+    double N[2];            /* particle numbers Tr n (general: N[0], N[1] = 0)      */
+    double E_kin;           /* Tr(h0 n), summed over spins                          */
+    double E_mf;            /* Hartree-Fock interaction energy                      */
+    double E_corr;          /* correlation energy -1/2 Re sum w_ijkl G2_klij        */
+    double E_tot;           /* E_kin + E_mf + E_corr                                */
+    double docc;            /* Hubbard: mean double occupation                      */
+    double herm_resid;      /* max |G2_ijkl - conj(G2_klij)| / max |G2|            */
+    int32_t diverged;       /* 1 once the divergence guard has fired                */
+    int64_t step;           /* completed Runge-Kutta steps                          */
+} g1g2_obs;
+
+typedef struct g1g2_ctx g1g2_ctx;
+
+/* Create a propagator.  h0 and G1_0 are required; w is required for the
+ * general basis and ignored (may be NULL) for Hubbard; G2_0 = NULL means an
+ * uncorrelated initial state (G2 = 0, eq:ini-g2 with n_ijkl factorized).
+ * hip_stream is a hipStream_t owned by the caller (NULL = default stream).
+ * Returns EINVAL for inconsistent shapes or a non-Hermitian h0, EUNSUPPORTED
+ * for combinations that are not implemented (Hubbard GW, general TPP).     */
+g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, const void* w,
+                      const void* G1_0, const void* G2_0, void* hip_stream);
+
+/* One evaluation of the right-hand side (dG1/dt, dG2/dt) of the closed system
+ * eq:eom_gone-2 + eq:eom_gone-I + the G2 equation of the selfenergy, at time t
+ * with the context's current h0, U and drive.  G1, G2 in, dG1, dG2 out: device
+ * pointers in the layouts above.  Does not change the propagated state.     */
+g1g2_status g1g2_rhs(g1g2_ctx* ctx, double t, const void* G1, const void* G2,
+                     void* dG1, void* dG2);
+
+/* Advance the internal state by nsteps classical fourth-order Runge-Kutta
+ * steps of size dt (h0(t) and U evaluated at the stage times).  Returns
+ * EDIVERGED (state kept, step count in g1g2_obs.step) when the guard fires. */
+g1g2_status g1g2_step_rk4(g1g2_ctx* ctx, double dt, int64_t nsteps);
+
+/* Observables of the current state; synchronizes the stream. */
+g1g2_status g1g2_observables(g1g2_ctx* ctx, g1g2_obs* out);
+
+/* Hubbard only: site-resolved densities n^up_ii, n^dn_ii and double
+ * occupations n^up_ii n^dn_ii - Re G2_iiii (host arrays of nb doubles).   */
+g1g2_status g1g2_site_observables(g1g2_ctx* ctx, double* n_up, double* n_dn, double* docc);
+
+/* Copy the current state out / in (layouts above; G2 may be NULL on get). */
+g1g2_status g1g2_get_state(g1g2_ctx* ctx, void* G1, void* G2, double* t);
+g1g2_status g1g2_set_state(g1g2_ctx* ctx, const void* G1, const void* G2, double t);
+
+/* Replace the one-particle Hamiltonian (same layout and sparsity rules as in
+ * g1g2_init); used for excitations between calls of g1g2_step_rk4.         */
+g1g2_status g1g2_set_h0(g1g2_ctx* ctx, const void* h0);
+
+/* Hubbard: change the on-site interaction U. */
+g1g2_status g1g2_set_U(g1g2_ctx* ctx, double U);
+
+/* Hubbard: time-dependent on-site drive added to h0 for both spins,
+ *   v_i(t) = sum_{m<M} c_m exp(-(t - t_center_m)^2 / (2 tau^2)) x_i.
+ * Host arrays x[nb], c[M], t_center[M]; M = 0 removes the drive.            */
+g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const double* c,
+                           const double* t_center, double tau);
+
+/* Profiling aid: evaluates the right-hand side of the current state `reps`
+ * times with a HIP event recorded on the context's stream after every kernel
+ * launch, and returns in ms[k] the average time between consecutive events,
+ * i.e. the duration of the k-th kernel of one evaluation (launch order; at
+ * most max_kernels values, the number of kernels in *count).  The kernel
+ * names are given by g1g2_profile_name(ctx, k).  Synchronizes the stream.   */
+g1g2_status g1g2_profile_rhs(g1g2_ctx* ctx, int32_t reps, double* ms, int32_t max_kernels,
+                             int32_t* count);
+const char* g1g2_profile_name(const g1g2_ctx* ctx, int32_t k);
+
+void g1g2_destroy(g1g2_ctx* ctx);
+const char* g1g2_strerror(g1g2_status status);
+const char* g1g2_last_error(const g1g2_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* G1G2_H */

@@ -1,0 +1,204 @@
+"""Thin ctypes binding of libg1g2.so (argument marshalling only).
+
+Every numerical step runs inside the HIP library; this module only converts
+Python arguments (numpy arrays on the host, torch tensors on the device) into
+the plain pointers and sizes of the C ABI declared in include/g1g2.h.  It
+raises if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(PKG, "libg1g2.so")
+
+GENERAL, HUBBARD = 0, 1
+SOA, GW, TPP = 0, 1, 2
+FP64, MIXED = 0, 1
+PTR_DEVICE, GW_EXCHANGE = 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("basis", c_int32), ("selfenergy", c_int32), ("precision", c_int32),
+                ("flags", c_int32), ("nb", c_int32), ("U", c_double)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("t", c_double), ("N", c_double * 2), ("E_kin", c_double), ("E_mf", c_double),
+                ("E_corr", c_double), ("E_tot", c_double), ("docc", c_double),
+                ("herm_resid", c_double), ("diverged", c_int32), ("step", c_int64)]
+
+
+_SIGS = {
+    "g1g2_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_void_p]),
+    "g1g2_rhs": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "g1g2_step_rk4": (c_int32, [c_void_p, c_double, c_int64]),
+    "g1g2_observables": (c_int32, [c_void_p, POINTER(Obs)]),
+    "g1g2_site_observables": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "g1g2_get_state": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+    "g1g2_set_state": (c_int32, [c_void_p, c_void_p, c_void_p, c_double]),
+    "g1g2_set_h0": (c_int32, [c_void_p, c_void_p]),
+    "g1g2_set_U": (c_int32, [c_void_p, c_double]),
+    "g1g2_set_drive": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_double]),
+    "g1g2_profile_rhs": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, POINTER(c_int32)]),
+    "g1g2_profile_name": (ctypes.c_char_p, [c_void_p, c_int32]),
+    "g1g2_destroy": (None, [c_void_p]),
+    "g1g2_strerror": (ctypes.c_char_p, [c_int32]),
+    "g1g2_last_error": (ctypes.c_char_p, [c_void_p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIBPATH):
+    """dlopen libg1g2.so and declare the signatures of every exported call."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2002_12717_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class G1G2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(x):
+    """Raw pointer of a contiguous complex128/float64 numpy array or torch tensor."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(type(x))
+
+
+def _c128(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+class Propagator:
+    """One g1g2_ctx.  Host numpy inputs by default; ``device=True`` passes the
+    data pointers of device tensors instead (flag G1G2_PTR_DEVICE)."""
+
+    def __init__(self, basis: int, selfenergy: int, nb: int, h0, G1_0, w=None, G2_0=None,
+                 U: float = 0.0, precision: int = FP64, flags: int = 0, stream: int = 0,
+                 device: bool = False):
+        self.lib = load()
+        self.basis, self.nb = basis, nb
+        self.flags = flags | (PTR_DEVICE if device else 0)
+        self.desc = Desc(basis, selfenergy, precision, self.flags, nb, float(U))
+        self._keep = [_c128(h0), _c128(G1_0), _c128(w), _c128(G2_0)]
+        ctx = c_void_p()
+        st = self.lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(self.desc), _ptr(self._keep[0]),
+                                _ptr(self._keep[2]), _ptr(self._keep[1]), _ptr(self._keep[3]),
+                                c_void_p(stream) if stream else None)
+        self._keep = None
+        if st != OK:
+            raise G1G2Error(st, self.lib.g1g2_strerror(st).decode())
+        self.ctx = ctx
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, st: int):
+        if st != OK:
+            raise G1G2Error(st, self.lib.g1g2_last_error(self.ctx).decode()
+                            or self.lib.g1g2_strerror(st).decode())
+
+    def shapes(self):
+        nb = self.nb
+        g1 = (2, nb, nb) if self.basis == HUBBARD else (nb, nb)
+        return g1, (nb, nb, nb, nb)
+
+    # ------------------------------------------------------------------ ABI calls
+    def rhs(self, t: float, G1, G2, dG1, dG2):
+        self._check(self.lib.g1g2_rhs(self.ctx, float(t), _ptr(G1), _ptr(G2), _ptr(dG1), _ptr(dG2)))
+
+    def step(self, dt: float, nsteps: int):
+        self._check(self.lib.g1g2_step_rk4(self.ctx, float(dt), int(nsteps)))
+
+    def observables(self) -> dict:
+        o = Obs()
+        self._check(self.lib.g1g2_observables(self.ctx, ctypes.byref(o)))
+        return dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
+                    E_tot=o.E_tot, docc=o.docc, herm_resid=o.herm_resid, diverged=o.diverged,
+                    step=o.step)
+
+    def site_observables(self):
+        nu, nd, dc = (np.zeros(self.nb) for _ in range(3))
+        self._check(self.lib.g1g2_site_observables(self.ctx, _ptr(nu), _ptr(nd), _ptr(dc)))
+        return nu, nd, dc
+
+    def get_state(self, G1=None, G2=None):
+        """Copy the state out; host numpy arrays are allocated when not given."""
+        s1, s2 = self.shapes()
+        if G1 is None:
+            G1 = np.zeros(s1, np.complex128)
+        if G2 is None and not (self.flags & PTR_DEVICE):
+            G2 = np.zeros(s2, np.complex128)
+        t = c_double()
+        self._check(self.lib.g1g2_get_state(self.ctx, _ptr(G1), _ptr(G2), ctypes.byref(t)))
+        return G1, G2, t.value
+
+    def set_state(self, G1, G2=None, t: float = 0.0):
+        G1, G2 = _c128(G1), _c128(G2)
+        self._check(self.lib.g1g2_set_state(self.ctx, _ptr(G1), _ptr(G2), float(t)))
+
+    def set_h0(self, h0):
+        h0 = _c128(h0)
+        self._check(self.lib.g1g2_set_h0(self.ctx, _ptr(h0)))
+
+    def set_U(self, U: float):
+        self._check(self.lib.g1g2_set_U(self.ctx, float(U)))
+
+    def set_drive(self, x, c, t_center, tau: float):
+        x = np.ascontiguousarray(x, np.float64)
+        c = np.ascontiguousarray(c, np.float64)
+        tc = np.ascontiguousarray(t_center, np.float64)
+        self._check(self.lib.g1g2_set_drive(self.ctx, _ptr(x), int(len(c)), _ptr(c), _ptr(tc),
+                                             float(tau)))
+
+    def profile_rhs(self, reps: int = 10) -> dict:
+        """Average duration (ms) of every kernel of one right-hand-side evaluation."""
+        ms = np.zeros(64)
+        n = c_int32()
+        self._check(self.lib.g1g2_profile_rhs(self.ctx, int(reps), _ptr(ms), 64, ctypes.byref(n)))
+        out = {}
+        for k in range(n.value):
+            name = self.lib.g1g2_profile_name(self.ctx, k).decode()
+            out[name] = out.get(name, 0.0) + float(ms[k])
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.g1g2_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,370 @@
+// C-ABI entry points of the G1-G2 library (declared in include/g1g2.h).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ctx.h"
+
+g1g2_status set_error(g1g2_ctx* c, g1g2_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+void prof_mark(g1g2_ctx* c, const char* name) {
+    if (!c->prof) return;
+    if (c->prof_used == c->prof_ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->prof_ev.push_back(e);
+        c->prof_name.push_back(name);
+    }
+    c->prof_name[c->prof_used] = name;
+    (void)hipEventRecord(c->prof_ev[c->prof_used], c->stream);
+    ++c->prof_used;
+}
+
+namespace {
+
+struct HostCopy {
+    std::vector<cd> v;
+    const cd* p = nullptr;
+};
+
+// Bring an input array to the host (it may be a device pointer).
+g1g2_status fetch(g1g2_ctx* c, const void* src, size_t n, HostCopy& out) {
+    if (!src) {
+        out.p = nullptr;
+        return G1G2_OK;
+    }
+    if (c->d.flags & G1G2_PTR_DEVICE) {
+        out.v.resize(n);
+        HIP_OK(c, hipMemcpyAsync(out.v.data(), src, n * sizeof(cd), hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        out.p = out.v.data();
+    } else {
+        out.p = (const cd*)src;
+    }
+    return G1G2_OK;
+}
+
+size_t g1_count(const g1g2_ctx* c) {
+    const size_t nb = c->d.nb;
+    return c->d.basis == G1G2_HUBBARD ? 2 * nb * nb : nb * nb;
+}
+size_t g2_count(const g1g2_ctx* c) {
+    const size_t nb = c->d.nb;
+    return nb * nb * nb * nb;
+}
+
+g1g2_status alloc_regs(g1g2_ctx* c, Regs& r) {
+    HIP_OK(c, hipMalloc(&r.g1, c->n1 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&r.g2, c->n2 * sizeof(cd)));
+    HIP_OK(c, hipMemsetAsync(r.g1, 0, c->n1 * sizeof(cd), c->stream));
+    HIP_OK(c, hipMemsetAsync(r.g2, 0, c->n2 * sizeof(cd), c->stream));
+    return G1G2_OK;
+}
+
+void free_regs(Regs& r) {
+    if (r.g1) (void)hipFree(r.g1);
+    if (r.g2) (void)hipFree(r.g2);
+    r = Regs();
+}
+
+// Copy an ABI-layout array (host or device as given by `device`) into an
+// internal register component.
+g1g2_status load_component(g1g2_ctx* c, const void* src, bool device, cd* dst, int rank) {
+    const size_t n = rank == 2 ? g1_count(c) : g2_count(c);
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (c->d.basis == G1G2_HUBBARD) {
+        HIP_OK(c, hipMemcpyAsync(dst, src, n * sizeof(cd), kind, c->stream));
+        return G1G2_OK;
+    }
+    cd* tmp = (rank == 2) ? c->io.g1 : c->io.g2;  // unpadded staging in scratch
+    HIP_OK(c, hipMemcpyAsync(tmp, src, n * sizeof(cd), kind, c->stream));
+    return gen_pad(c, tmp, dst, rank);
+}
+
+g1g2_status store_component(g1g2_ctx* c, const cd* src, void* dst, bool device, int rank) {
+    const size_t n = rank == 2 ? g1_count(c) : g2_count(c);
+    const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (c->d.basis == G1G2_HUBBARD) {
+        HIP_OK(c, hipMemcpyAsync(dst, src, n * sizeof(cd), kind, c->stream));
+        return G1G2_OK;
+    }
+    cd* tmp = (rank == 2) ? c->io.g1 : c->io.g2;
+    g1g2_status s = gen_unpad(c, src, tmp, rank);
+    if (s != G1G2_OK) return s;
+    HIP_OK(c, hipMemcpyAsync(dst, tmp, n * sizeof(cd), kind, c->stream));
+    return G1G2_OK;
+}
+
+g1g2_status stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y, const Regs& acc,
+                  const Regs& out, double cb, double cc) {
+    if (c->d.basis == G1G2_HUBBARD) return hub_stage(c, mode, t, in, y, acc, out, cb, cc);
+    return gen_stage(c, mode, t, in, y, acc, out, cb, cc);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* g1g2_strerror(g1g2_status s) {
+    switch (s) {
+        case G1G2_OK: return "ok";
+        case G1G2_EINVAL: return "invalid argument";
+        case G1G2_ENOMEM: return "out of device memory";
+        case G1G2_EDEVICE: return "HIP device error";
+        case G1G2_EUNSUPPORTED: return "unsupported configuration";
+        case G1G2_EDIVERGED: return "propagation diverged";
+        case G1G2_ESTATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char* g1g2_last_error(const g1g2_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void g1g2_destroy(g1g2_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_regs(c->y);
+    free_regs(c->acc);
+    free_regs(c->s0);
+    free_regs(c->s1);
+    free_regs(c->io);
+    if (c->dflag) (void)hipFree(c->dflag);
+    if (c->dscratch) (void)hipFree(c->dscratch);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    HubbardData& H = c->hub;
+    void* hp[] = {H.nbr, H.hop, H.d0, H.xdrv};
+    for (void* p : hp)
+        if (p) (void)hipFree(p);
+    gen_free(c);
+    delete c;
+}
+
+g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const void* w,
+                      const void* G1_0, const void* G2_0, void* hip_stream) {
+    if (!out || !d || !h0 || !G1_0) return G1G2_EINVAL;
+    *out = nullptr;
+    if (d->nb <= 0) return G1G2_EINVAL;
+    if (d->basis != G1G2_GENERAL && d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
+    if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_TPP) return G1G2_EINVAL;
+    if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
+    if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
+    if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_GW) return G1G2_EUNSUPPORTED;
+    if (d->basis == G1G2_HUBBARD && d->precision != G1G2_FP64) return G1G2_EUNSUPPORTED;
+    if (d->basis == G1G2_GENERAL && d->selfenergy == G1G2_TPP) return G1G2_EUNSUPPORTED;
+    if (d->basis == G1G2_GENERAL && d->nb > 64) return G1G2_EUNSUPPORTED;
+    if (d->basis == G1G2_HUBBARD && (long long)d->nb * d->nb * d->nb * d->nb > (1LL << 30))
+        return G1G2_EUNSUPPORTED;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return G1G2_EDEVICE;
+
+    g1g2_ctx* c = new (std::nothrow) g1g2_ctx();
+    if (!c) return G1G2_ENOMEM;
+    c->d = *d;
+    c->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&c->device);
+    g1g2_status s = G1G2_OK;
+    const size_t nb = d->nb;
+    if (d->basis == G1G2_HUBBARD) {
+        c->n1 = 2 * nb * nb;
+        c->n2 = nb * nb * nb * nb;
+    } else {
+        const size_t nbp = ((nb + 15) / 16) * 16;
+        c->n1 = nbp * nbp;
+        c->n2 = nbp * nbp * nbp * nbp;
+    }
+    auto fail = [&](g1g2_status st) {
+        std::string e = c->err;
+        g1g2_destroy(c);
+        (void)e;
+        return st;
+    };
+    for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1, &c->io})
+        if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
+    if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
+    if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    c->nscratch = 8 + 2 * 256 + 3 * (int)nb + 64;
+    if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
+
+    HostCopy hh0, hw;
+    const size_t nh0 = g1_count(c);
+    if ((s = fetch(c, h0, nh0, hh0)) != G1G2_OK) return fail(s);
+    if (d->basis == G1G2_HUBBARD) {
+        if ((s = hub_setup(c, hh0.p)) != G1G2_OK) return fail(s);
+    } else {
+        if ((s = fetch(c, w, g2_count(c), hw)) != G1G2_OK) return fail(s);
+        if ((s = gen_setup(c, hh0.p, hw.p)) != G1G2_OK) return fail(s);
+    }
+    const bool dev = d->flags & G1G2_PTR_DEVICE;
+    if ((s = load_component(c, G1_0, dev, c->y.g1, 2)) != G1G2_OK) return fail(s);
+    if (G2_0) {
+        if ((s = load_component(c, G2_0, dev, c->y.g2, 4)) != G1G2_OK) return fail(s);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    *out = c;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_rhs(g1g2_ctx* c, double t, const void* G1, const void* G2, void* dG1, void* dG2) {
+    if (!c || !G1 || !G2 || !dG1 || !dG2) return G1G2_EINVAL;
+    g1g2_status s;
+    if (c->d.basis == G1G2_HUBBARD) {
+        Regs in{(cd*)G1, (cd*)G2};
+        Regs out{(cd*)dG1, (cd*)dG2};
+        s = hub_stage(c, RK_RHS, t, in, in, in, out, 0.0, 0.0);
+        if (s != G1G2_OK) return s;
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        return G1G2_OK;
+    }
+    // general: pad into s0 (dead between steps), evaluate into s1, unpad
+    if ((s = load_component(c, G1, true, c->s0.g1, 2)) != G1G2_OK) return s;
+    if ((s = load_component(c, G2, true, c->s0.g2, 4)) != G1G2_OK) return s;
+    if ((s = gen_stage(c, RK_RHS, t, c->s0, c->s0, c->s0, c->s1, 0.0, 0.0)) != G1G2_OK) return s;
+    if ((s = store_component(c, c->s1.g1, dG1, true, 2)) != G1G2_OK) return s;
+    if ((s = store_component(c, c->s1.g2, dG2, true, 4)) != G1G2_OK) return s;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
+    if (!c || nsteps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return G1G2_EINVAL;
+    const double t0 = c->t;
+    const int64_t step0 = c->step;
+    g1g2_status s;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        const double t = t0 + (double)n * dt;
+        if ((s = stage(c, RK_FIRST, t, c->y, c->y, c->acc, c->s0, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
+        if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s0, c->y, c->acc, c->s1, dt / 3.0, dt / 2.0)) != G1G2_OK)
+            return s;
+        if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s1, c->y, c->acc, c->s0, dt / 3.0, dt)) != G1G2_OK)
+            return s;
+        if ((s = stage(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0)) != G1G2_OK) return s;
+    }
+    c->t = t0 + (double)nsteps * dt;
+    c->step = step0 + nsteps;
+    int flag = 0;
+    HIP_OK(c, hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (flag) return set_error(c, G1G2_EDIVERGED, "non-finite state or occupation outside [-0.5, 1.5]");
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
+    if (!c || !o) return G1G2_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    g1g2_status s = c->d.basis == G1G2_HUBBARD ? hub_observables(c, c->y, c->t, o)
+                                               : gen_observables(c, c->y, c->t, o);
+    if (s != G1G2_OK) return s;
+    int flag = 0;
+    HIP_OK(c, hipMemcpy(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost));
+    o->t = c->t;
+    o->step = c->step;
+    o->diverged = flag;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_site_observables(g1g2_ctx* c, double* nu, double* nd, double* docc) {
+    if (!c) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    return hub_site_observables(c, c->y, nu, nd, docc);
+}
+
+g1g2_status g1g2_get_state(g1g2_ctx* c, void* G1, void* G2, double* t) {
+    if (!c || !G1) return G1G2_EINVAL;
+    const bool dev = c->d.flags & G1G2_PTR_DEVICE;
+    g1g2_status s;
+    if ((s = store_component(c, c->y.g1, G1, dev, 2)) != G1G2_OK) return s;
+    if (G2 && (s = store_component(c, c->y.g2, G2, dev, 4)) != G1G2_OK) return s;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (t) *t = c->t;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_set_state(g1g2_ctx* c, const void* G1, const void* G2, double t) {
+    if (!c || !G1) return G1G2_EINVAL;
+    const bool dev = c->d.flags & G1G2_PTR_DEVICE;
+    g1g2_status s;
+    if ((s = load_component(c, G1, dev, c->y.g1, 2)) != G1G2_OK) return s;
+    if (G2) {
+        if ((s = load_component(c, G2, dev, c->y.g2, 4)) != G1G2_OK) return s;
+    } else {
+        HIP_OK(c, hipMemsetAsync(c->y.g2, 0, c->n2 * sizeof(cd), c->stream));
+    }
+    HIP_OK(c, hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->t = t;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_set_h0(g1g2_ctx* c, const void* h0) {
+    if (!c || !h0) return G1G2_EINVAL;
+    HostCopy hh;
+    g1g2_status s = fetch(c, h0, g1_count(c), hh);
+    if (s != G1G2_OK) return s;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return c->d.basis == G1G2_HUBBARD ? hub_setup(c, hh.p) : gen_set_h0(c, hh.p);
+}
+
+g1g2_status g1g2_set_U(g1g2_ctx* c, double U) {
+    if (!c || !std::isfinite(U)) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->d.U = U;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double* cm,
+                           const double* tc, double tau) {
+    if (!c || M < 0) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    HubbardData& H = c->hub;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (M == 0) {
+        H.drive_c.clear();
+        H.drive_tc.clear();
+        return G1G2_OK;
+    }
+    if (!x || !cm || !tc || !(tau > 0.0)) return G1G2_EINVAL;
+    H.drive_c.assign(cm, cm + M);
+    H.drive_tc.assign(tc, tc + M);
+    H.drive_x.assign(x, x + c->d.nb);
+    H.drive_tau = tau;
+    HIP_OK(c, hipMemcpy(H.xdrv, x, c->d.nb * sizeof(double), hipMemcpyHostToDevice));
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_profile_rhs(g1g2_ctx* c, int32_t reps, double* ms, int32_t max_kernels,
+                             int32_t* count) {
+    if (!c || reps < 1 || !ms || max_kernels < 1 || !count) return G1G2_EINVAL;
+    std::vector<double> tot;
+    int n = 0;
+    for (int r = 0; r < reps; ++r) {
+        c->prof = true;
+        c->prof_used = 0;
+        prof_mark(c, "start");
+        g1g2_status s = stage(c, RK_RHS, c->t, c->y, c->y, c->y, c->s1, 0.0, 0.0);
+        c->prof = false;
+        if (s != G1G2_OK) return s;
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        n = (int)c->prof_used - 1;
+        tot.resize(n, 0.0);
+        for (int k = 0; k < n; ++k) {
+            float m = 0.f;
+            HIP_OK(c, hipEventElapsedTime(&m, c->prof_ev[k], c->prof_ev[k + 1]));
+            tot[k] += m;
+        }
+    }
+    *count = n;
+    for (int k = 0; k < n && k < max_kernels; ++k) ms[k] = tot[k] / reps;
+    return G1G2_OK;
+}
+
+const char* g1g2_profile_name(const g1g2_ctx* c, int32_t k) {
+    if (!c || k < 0 || (size_t)k + 1 >= c->prof_name.size()) return "";
+    return c->prof_name[k + 1];
+}
+
+}  // extern "C"

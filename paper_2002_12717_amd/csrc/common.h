@@ -1,0 +1,56 @@
+// Device helpers shared by the kernels of the G1-G2 library (complex binary64
+// arithmetic on double2, Runge-Kutta register update modes).
+#pragma once
+#include <hip/hip_runtime.h>
+
+typedef double2 cd;
+
+__host__ __device__ __forceinline__ cd cmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ __forceinline__ cd cadd(cd a, cd b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ cd csub(cd a, cd b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ cd cmul(cd a, cd b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ cd cconj(cd a) { return cmk(a.x, -a.y); }
+__host__ __device__ __forceinline__ cd cscale(cd a, double s) { return cmk(a.x * s, a.y * s); }
+// i * a and -i * a
+__host__ __device__ __forceinline__ cd cmul_i(cd a) { return cmk(-a.y, a.x); }
+__host__ __device__ __forceinline__ cd cmul_mi(cd a) { return cmk(a.y, -a.x); }
+// acc + a * b
+__host__ __device__ __forceinline__ cd cfma(cd acc, cd a, cd b) {
+    return cmk(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc + a * conj(b)
+__host__ __device__ __forceinline__ cd cfma_conjb(cd acc, cd a, cd b) {
+    return cmk(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
+}
+
+// Classical RK4 as a sequence of fused register updates.  With registers y
+// (state at t_n), acc (running sum) and a stage input/output pair:
+//   RK_RHS   : out = f
+//   RK_FIRST : acc = y + cb f ; out = y + cc f          (stage input is y)
+//   RK_MID   : acc = acc + cb f ; out = y + cc f
+//   RK_LAST  : y = acc + cb f                          (out aliases y)
+// with cb = dt/6, dt/3, dt/3, dt/6 and cc = dt/2, dt/2, dt for stages 1..4.
+enum { RK_RHS = 0, RK_FIRST = 1, RK_MID = 2, RK_LAST = 3 };
+
+template <int MODE>
+__device__ __forceinline__ void rk_update(int e, cd f, cd yin_if_first, const cd* __restrict__ y,
+                                          cd* __restrict__ acc, cd* __restrict__ out,
+                                          double cb, double cc) {
+    if (MODE == RK_RHS) {
+        out[e] = f;
+    } else if (MODE == RK_FIRST) {
+        cd yv = yin_if_first;
+        acc[e] = cmk(fma(cb, f.x, yv.x), fma(cb, f.y, yv.y));
+        out[e] = cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y));
+    } else if (MODE == RK_MID) {
+        cd av = acc[e];
+        cd yv = y[e];
+        acc[e] = cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y));
+        out[e] = cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y));
+    } else {
+        cd av = acc[e];
+        out[e] = cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y));
+    }
+}

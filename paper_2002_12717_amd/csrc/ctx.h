@@ -1,0 +1,110 @@
+// Internal context of the G1-G2 library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "g1g2.h"
+
+struct Regs {
+    cd* g1 = nullptr;
+    cd* g2 = nullptr;
+};
+
+// Hubbard model: h0 per spin stored as a real diagonal plus an ELL list of
+// off-diagonal entries (row i: neighbours nbr[i][z] with h0_{i,nbr}); the
+// drive adds s(t) * x_i to the diagonal of both spins.
+struct HubbardData {
+    int ns = 0;
+    int zmax = 0;
+    int* nbr = nullptr;        // [2][ns][zmax], -1 = empty slot
+    cd* hop = nullptr;         // [2][ns][zmax]
+    double* d0 = nullptr;      // [2][ns]
+    double* xdrv = nullptr;    // [ns]
+    std::vector<double> h_d0;  // host copies for observables
+    std::vector<double> drive_c, drive_tc, drive_x;
+    double drive_tau = 1.0;
+    double drive_value(double t) const;
+};
+
+// General basis: internal tensors are padded to nbp = roundup(nb, 16) so that
+// every matrix-core tile is full; padding entries are kept exactly zero.
+struct GeneralData {
+    int nb = 0, nbp = 0;
+    cd* h0 = nullptr;        // [nbp][nbp]
+    cd* wm_rows = nullptr;   // W^- as pair matrix rows: [p][q][r][s] = w^-_pqrs   (nbp^4)
+    cd* w_coll = nullptr;    // collision layout: [l][p][i][k] = w_iklp           (nbp^4)
+    cd* w_hf = nullptr;      // mean-field layout: [i][j][k][l] = w^-_ikjl        (nbp^4)
+    cd* vt = nullptr;        // scratch: transposed right sandwich                (nbp^4)
+    cd* dmat = nullptr;      // scratch: D = T^dagger - R                         (nbp^4)
+    cd* hhf = nullptr;       // scratch: h^HF of the current stage [nbp][nbp]
+    cd* gg = nullptr;        // scratch: G^> of the current stage [nbp][nbp]
+    double* ipart = nullptr; // scratch: collision-integral partial sums
+    int nipart = 0;
+    // GW
+    cd* heps = nullptr;      // [(p,q)][(j,l)] = h^eps_qjpl                        (nbp^4)
+    cd* bmat = nullptr;      // [(i,k)][(p,q)] = G2_ipkq                           (nbp^4)
+    cd* pimat = nullptr;     // [(i,k)][(j,l)] = Pi_ijkl                           (nbp^4)
+    cd* w_gw = nullptr;      // GW layout: [p][q][s][r] = w_sqrp                   (nbp^4)
+    cd* icoll = nullptr;     // collision integral of the last RHS evaluation [nbp][nbp]
+    // mixed precision copies of the constant layouts
+    float2* wm_rows32 = nullptr;
+    float2* w_coll32 = nullptr;
+    float2* w_gw32 = nullptr;
+};
+
+struct g1g2_ctx {
+    g1g2_desc d{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    double t = 0.0;
+    int64_t step = 0;
+    size_t n1 = 0, n2 = 0;     // internal element counts of G1 and G2
+    Regs y, acc, s0, s1, io;   // RK4 registers; io = scratch for g1g2_rhs
+    int* dflag = nullptr;      // divergence flag (device int)
+    double* dscratch = nullptr;  // small device scratch for reductions
+    int nscratch = 0;
+    HubbardData hub;
+    GeneralData gen;
+    // kernel timing (g1g2_profile_rhs): events recorded after every launch
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<const char*> prof_name;
+    size_t prof_used = 0;
+};
+
+// Record a timing event after the kernel `name` when profiling is active.
+void prof_mark(g1g2_ctx* c, const char* name);
+
+g1g2_status set_error(g1g2_ctx* c, g1g2_status s, const std::string& msg);
+
+#define HIP_OK(ctx, expr)                                                                  \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return set_error((ctx), _e == hipErrorOutOfMemory ? G1G2_ENOMEM : G1G2_EDEVICE, \
+                             std::string(#expr) + ": " + hipGetErrorString(_e));           \
+    } while (0)
+
+// ---- Hubbard basis (hubbard.hip)
+g1g2_status hub_setup(g1g2_ctx* c, const cd* h0_host);
+// One RK4 stage (or a plain RHS evaluation, mode RK_RHS) of the Hubbard system.
+g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
+                      const Regs& acc, const Regs& out, double cb, double cc);
+g1g2_status hub_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
+g1g2_status hub_site_observables(g1g2_ctx* c, const Regs& s, double* nu, double* nd, double* docc);
+
+// ---- general basis (general.hip)
+g1g2_status gen_setup(g1g2_ctx* c, const cd* h0_host, const cd* w_host);
+g1g2_status gen_set_h0(g1g2_ctx* c, const cd* h0_host);
+g1g2_status gen_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
+                      const Regs& acc, const Regs& out, double cb, double cc);
+g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
+// layout conversions between the unpadded ABI layout and the padded internal one
+g1g2_status gen_pad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
+g1g2_status gen_unpad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
+void gen_free(g1g2_ctx* c);

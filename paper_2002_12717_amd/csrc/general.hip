@@ -1,0 +1,833 @@
+// General-basis G1-G2 kernels (Secs. III.C and IV.C) on the gfx950 matrix cores.
+//
+// Internally every index runs over nbp = roundup(nb, 16) values; G2 and the
+// interaction are nbp^2 x nbp^2 "pair matrices" [(ij),(kl)] built from
+// contiguous nbp x nbp row blocks X_ab = X[a][b][:][:].
+//
+// Right-hand side of the G2 equation of the second-Born selfenergy
+// (eq:result_eom_soa), i dG2/dt = [h2, G2] + Psi^-, evaluated as
+//     [h2, G2] + Psi^- = D - D^dagger,   D = T^dagger - R,
+//     R = G2 h2                    (row action: R_ab = h^T C_ab + C_ab h)
+//     T = (G>xG>) W^- (G<xG<)      (Psi^- = T^dagger - T, eq:psi-pm-def)
+// which uses the Hermiticity of G2, h2, W^- and the anti-Hermiticity of G^><
+// (eq:Gsymm_b, eq:wsymm_b).  T is a two-sided sandwich; it is computed as
+//     V_pq = G<^T W^-_pq G<   on row blocks of W^- (kernel gen_vt), stored
+//                             transposed: Vt[k][l][p][q] = V_pq[k][l],
+//     T^dagger row block ab = conj(G> Vt_ab G>^T)       (kernel gen_main).
+// gen_main also accumulates the collision integral eq:eom_gone-I,
+//     I = -i sum_{lp} Wc_lp C_lp^T,   Wc_lp[i][k] = w_iklp,
+// from the same row blocks.  gen_combine forms -i (D - D^dagger) with an
+// LDS-tiled pair transpose and applies the Runge-Kutta register update.
+//
+// GW (eq:g2-eq-gw-pi) adds Pi - [Pi_lkji]^*, Pi_ijkl = sum_pq h^eps_qjpl G2_ipkq
+// (eq:gwpi), evaluated as one (nbp^2)^3 complex GEMM
+//     Pi[(i,k)][(j,l)] = sum_(p,q) B[(i,k)][(p,q)] H[(p,q)][(j,l)],
+//     B[(i,k)][(p,q)] = G2_ipkq,   H[(p,q)][(j,l)] = h^eps_qjpl,
+// with h^eps (eq:gwhcorr) built per (p,q) block as H_pq = i [G<, M_pq],
+// M_pq[s][r] = w_sqrp (G^> = G^< - i 1 removes the G<...G< terms).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "mfma.h"
+
+namespace {
+
+template <int NB>
+struct Shape {
+    static constexpr int NT = NB / 16;
+    static constexpr int TILES = NT * NT;
+    static constexpr int WAVES = (TILES % 4 == 0) ? 4 : ((TILES % 3 == 0) ? 3 : 1);
+    static constexpr int TPW = TILES / WAVES;
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int LD = NB + 1;
+};
+
+template <typename T>
+__device__ __forceinline__ void ldc(const cd* p, T& r, T& i) {
+    cd v = *p;
+    r = (T)v.x;
+    i = (T)v.y;
+}
+template <typename T>
+__device__ __forceinline__ void ldc(const float2* p, T& r, T& i) {
+    float2 v = *p;
+    r = (T)v.x;
+    i = (T)v.y;
+}
+__device__ __forceinline__ void stc(cd* p, double r, double i) { *p = make_double2(r, i); }
+__device__ __forceinline__ void stc(float2* p, double r, double i) { *p = make_float2((float)r, (float)i); }
+
+template <typename T, typename S, int NB>
+__device__ __forceinline__ void stage_block(const S* __restrict__ src, T* re, T* im) {
+    constexpr int LD = Shape<NB>::LD;
+    for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
+        int r = idx / NB, c = idx % NB;
+        T a, b;
+        ldc(src + idx, a, b);
+        re[r * LD + c] = a;
+        im[r * LD + c] = b;
+    }
+}
+
+// --------------------------------------------------------------------------- K1
+// h^HF_ij = h0_ij - i sum_kl w^-_ikjl G^<_lk (eq:h_HF) and G^> = G^< - i 1.
+__global__ __launch_bounds__(256) void gen_hf_kernel(const cd* __restrict__ whf,
+                                                    const cd* __restrict__ h0,
+                                                    const cd* __restrict__ gl, cd* __restrict__ hhf,
+                                                    cd* __restrict__ gg, int nbp, int nb) {
+    __shared__ double sr[256], si[256];
+    const int ij = blockIdx.x;
+    const int n2 = nbp * nbp;
+    const cd* row = whf + (size_t)ij * n2;
+    double ar = 0.0, ai = 0.0;
+    for (int kl = threadIdx.x; kl < n2; kl += blockDim.x) {
+        int k = kl / nbp, l = kl % nbp;
+        cd w = row[kl], g = gl[l * nbp + k];
+        ar = fma(w.x, g.x, fma(-w.y, g.y, ar));
+        ai = fma(w.x, g.y, fma(w.y, g.x, ai));
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sr[threadIdx.x] += sr[threadIdx.x + s];
+            si[threadIdx.x] += si[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cd h = h0[ij];
+        // h0 - i (ar + i ai) = h0 + ai - i ar
+        hhf[ij] = make_double2(h.x + si[0], h.y - sr[0]);
+        int i = ij / nbp, j = ij % nbp;
+        cd g = gl[ij];
+        gg[ij] = (i == j && i < nb) ? make_double2(g.x, g.y - 1.0) : g;
+    }
+}
+
+// --------------------------------------------------------------------------- K2
+// Right sandwich on row blocks of W: Vt[k][l][p][q] = (G<^T W_pq G<)[k][l].
+template <typename T, typename S, int NB>
+__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __restrict__ wrows,
+                                                                   const cd* __restrict__ gl,
+                                                                   S* __restrict__ vt) {
+    typedef Shape<NB> SH;
+    constexpr int LD = SH::LD;
+    __shared__ T w_re[NB * LD], w_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
+    const int wave = threadIdx.x >> 6;
+    for (int blk = blockIdx.x; blk < NB * NB; blk += gridDim.x) {
+        stage_block<T, S, NB>(wrows + (size_t)blk * NB * NB, w_re, w_im);
+        __syncthreads();
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+            CAcc<T> acc;
+            acc.clear();
+            cgemm_tile<T, NB>(
+                acc, [&](int i, int k, T& r, T& m) { ldc(gl + k * NB + i, r, m); },
+                [&](int k, int j, T& r, T& m) {
+                    r = w_re[k * LD + j];
+                    m = w_im[k * LD + j];
+                },
+                ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                q_re[row * LD + col] = acc.re[r4];
+                q_im[row * LD + col] = acc.im[r4];
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+            CAcc<T> acc;
+            acc.clear();
+            cgemm_tile<T, NB>(
+                acc,
+                [&](int i, int k, T& r, T& m) {
+                    r = q_re[i * LD + k];
+                    m = q_im[i * LD + k];
+                },
+                [&](int k, int j, T& r, T& m) { ldc(gl + k * NB + j, r, m); }, ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re[r4], acc.im[r4]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------- K3
+// Per row block ab:  D_ab = conj(G> Vt_ab G>^T) - (h^T C_ab + C_ab h),
+// and the collision partial  sum_ab Wc_ab C_ab^T  (binary64 across blocks).
+template <typename T, typename S, int NB>
+__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
+    const cd* __restrict__ g2, const S* __restrict__ vt, const S* __restrict__ wcoll,
+    const cd* __restrict__ gg, const cd* __restrict__ hhf, S* __restrict__ dout,
+    double* __restrict__ ipart) {
+    typedef Shape<NB> SH;
+    constexpr int LD = SH::LD;
+    __shared__ T b0_re[NB * LD], b0_im[NB * LD], b1_re[NB * LD], b1_im[NB * LD];
+    const int wave = threadIdx.x >> 6;
+    double isum[SH::TPW][2][4];
+    for (int t = 0; t < SH::TPW; ++t)
+        for (int r4 = 0; r4 < 4; ++r4) isum[t][0][r4] = isum[t][1][r4] = 0.0;
+
+    for (int blk = blockIdx.x; blk < NB * NB; blk += gridDim.x) {
+        stage_block<T, S, NB>(vt + (size_t)blk * NB * NB, b0_re, b0_im);
+        __syncthreads();
+        // P = G> Vt_ab
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+            CAcc<T> acc;
+            acc.clear();
+            cgemm_tile<T, NB>(
+                acc, [&](int i, int k, T& r, T& m) { ldc(gg + i * NB + k, r, m); },
+                [&](int k, int j, T& r, T& m) {
+                    r = b0_re[k * LD + j];
+                    m = b0_im[k * LD + j];
+                },
+                ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                b1_re[row * LD + col] = acc.re[r4];
+                b1_im[row * LD + col] = acc.im[r4];
+            }
+        }
+        __syncthreads();
+        stage_block<T, cd, NB>(g2 + (size_t)blk * NB * NB, b0_re, b0_im);  // C = G2 row block
+        __syncthreads();
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+            CAcc<T> acc;
+            acc.clear();
+            // P G>^T
+            cgemm_tile<T, NB>(
+                acc,
+                [&](int i, int k, T& r, T& m) {
+                    r = b1_re[i * LD + k];
+                    m = b1_im[i * LD + k];
+                },
+                [&](int k, int j, T& r, T& m) { ldc(gg + j * NB + k, r, m); }, ti * 16, tj * 16);
+            acc.im = -acc.im;  // conj
+            // - h^T C
+            cgemm_tile<T, NB>(
+                acc,
+                [&](int i, int k, T& r, T& m) {
+                    ldc(hhf + k * NB + i, r, m);
+                    r = -r;
+                    m = -m;
+                },
+                [&](int k, int j, T& r, T& m) {
+                    r = b0_re[k * LD + j];
+                    m = b0_im[k * LD + j];
+                },
+                ti * 16, tj * 16);
+            // - C h
+            cgemm_tile<T, NB>(
+                acc,
+                [&](int i, int k, T& r, T& m) {
+                    r = -b0_re[i * LD + k];
+                    m = -b0_im[i * LD + k];
+                },
+                [&](int k, int j, T& r, T& m) { ldc(hhf + k * NB + j, r, m); }, ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                stc(dout + (size_t)blk * NB * NB + row * NB + col, acc.re[r4], acc.im[r4]);
+            }
+            // collision partial: Wc_ab C_ab^T
+            CAcc<T> ic;
+            ic.clear();
+            const S* wc = wcoll + (size_t)blk * NB * NB;
+            cgemm_tile<T, NB>(
+                ic, [&](int i, int k, T& r, T& m) { ldc(wc + i * NB + k, r, m); },
+                [&](int k, int j, T& r, T& m) {
+                    r = b0_re[j * LD + k];
+                    m = b0_im[j * LD + k];
+                },
+                ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                isum[t][0][r4] += (double)ic.re[r4];
+                isum[t][1][r4] += (double)ic.im[r4];
+            }
+        }
+        __syncthreads();
+    }
+    double* part = ipart + (size_t)blockIdx.x * NB * NB * 2;
+    for (int t = 0; t < SH::TPW; ++t) {
+        const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+#pragma unroll
+        for (int r4 = 0; r4 < 4; ++r4) {
+            int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+            part[2 * (row * NB + col)] = isum[t][0][r4];
+            part[2 * (row * NB + col) + 1] = isum[t][1][r4];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------- K5
+// G1 equation eq:eom_gone-2 with I from the partials; writes I for observables.
+template <int MODE>
+__global__ __launch_bounds__(256) void gen_g1_kernel(const double* __restrict__ ipart, int nparts,
+                                                    const cd* __restrict__ hhf,
+                                                    const cd* __restrict__ gl,
+                                                    const cd* __restrict__ y, cd* __restrict__ acc,
+                                                    cd* __restrict__ out, cd* __restrict__ icoll,
+                                                    double cb, double cc, int nbp, int nb,
+                                                    int* __restrict__ flag) {
+    const int n2 = nbp * nbp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += gridDim.x * blockDim.x) {
+        const int i = e / nbp, j = e % nbp;
+        double sr = 0, si = 0, tr = 0, ti = 0;
+        for (int g = 0; g < nparts; ++g) {
+            const double* p = ipart + (size_t)g * n2 * 2;
+            sr += p[2 * e];
+            si += p[2 * e + 1];
+            tr += p[2 * (j * nbp + i)];
+            ti += p[2 * (j * nbp + i) + 1];
+        }
+        cd Iij = make_double2(si, -sr);  // -i (sr + i si)
+        cd Iji = make_double2(ti, -tr);
+        cd c = make_double2(0.0, 0.0);
+        for (int p = 0; p < nbp; ++p) {
+            c = cfma(c, hhf[i * nbp + p], gl[p * nbp + j]);
+            c = csub(c, cmul(gl[i * nbp + p], hhf[p * nbp + j]));
+        }
+        cd f = cmul_mi(cadd(c, cadd(Iij, cconj(Iji))));
+        if (MODE == RK_RHS) icoll[e] = Iij;
+        rk_update<MODE>(e, f, gl[e], y, acc, out, cb, cc);
+        if (MODE == RK_LAST && i < nb) {
+            cd v = out[e];
+            bool bad = !(isfinite(v.x) && isfinite(v.y));
+            if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
+            if (bad) atomicOr(flag, 1);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------- K4
+// dG2 = -i (D - D^dagger) [+ -i (Pi - conj(Pi_lkji)) for GW], fused RK4 update.
+template <int MODE, typename S, bool GW>
+__global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ D, int n,
+                                                         const cd* __restrict__ in,
+                                                         const cd* __restrict__ y,
+                                                         cd* __restrict__ acc, cd* __restrict__ out,
+                                                         const cd* __restrict__ pim, int nbp,
+                                                         double cb, double cc) {
+    __shared__ double t1r[32][33], t1i[32][33], t2r[32][33], t2i[32][33];
+    const int nt = n / 32;
+    const int bx = blockIdx.x % nt, by = blockIdx.x / nt;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        double a, b;
+        ldc(D + (size_t)(by * 32 + r) * n + bx * 32 + tx, a, b);
+        t1r[r][tx] = a;
+        t1i[r][tx] = b;
+        ldc(D + (size_t)(bx * 32 + r) * n + by * 32 + tx, a, b);
+        t2r[r][tx] = a;
+        t2i[r][tx] = b;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int row = by * 32 + r, col = bx * 32 + tx;
+        const size_t e = (size_t)row * n + col;
+        // D_rc - conj(D_cr)
+        double zr = t1r[r][tx] - t2r[tx][r];
+        double zi = t1i[r][tx] + t2i[tx][r];
+        if (GW) {
+            const int i = row / nbp, j = row % nbp, k = col / nbp, l = col % nbp;
+            cd p1 = pim[e];
+            cd p2 = pim[(((size_t)l * nbp + k) * nbp + j) * nbp + i];
+            zr += p1.x - p2.x;
+            zi += p1.y + p2.y;
+        }
+        cd f = make_double2(zi, -zr);  // -i z
+        cd yin = make_double2(0.0, 0.0);
+        if (MODE == RK_FIRST) yin = in[e];
+        rk_update<MODE>((int)e, f, yin, y, acc, out, cb, cc);
+    }
+}
+
+// --------------------------------------------------------------------------- GW kernels
+// H[(p,q)][(j,l)] = h^eps_qjpl = i (G< M_pq - M_pq G<)[j][l], M_pq[s][r] = w_sqrp.
+template <typename T, typename S, int NB>
+__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* __restrict__ wgw,
+                                                                     const cd* __restrict__ gl,
+                                                                     S* __restrict__ heps) {
+    typedef Shape<NB> SH;
+    constexpr int LD = SH::LD;
+    __shared__ T m_re[NB * LD], m_im[NB * LD];
+    const int wave = threadIdx.x >> 6;
+    for (int blk = blockIdx.x; blk < NB * NB; blk += gridDim.x) {
+        stage_block<T, S, NB>(wgw + (size_t)blk * NB * NB, m_re, m_im);
+        __syncthreads();
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+            CAcc<T> acc;
+            acc.clear();
+            cgemm_tile<T, NB>(
+                acc, [&](int i, int k, T& r, T& m) { ldc(gl + i * NB + k, r, m); },
+                [&](int k, int j, T& r, T& m) {
+                    r = m_re[k * LD + j];
+                    m = m_im[k * LD + j];
+                },
+                ti * 16, tj * 16);
+            cgemm_tile<T, NB>(
+                acc,
+                [&](int i, int k, T& r, T& m) {
+                    r = -m_re[i * LD + k];
+                    m = -m_im[i * LD + k];
+                },
+                [&](int k, int j, T& r, T& m) { ldc(gl + k * NB + j, r, m); }, ti * 16, tj * 16);
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                // i * acc
+                stc(heps + (size_t)blk * NB * NB + row * NB + col, -(double)acc.im[r4],
+                    (double)acc.re[r4]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// B[(i,k)][(p,q)] = G2_ipkq
+template <typename S>
+__global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2, S* __restrict__ b,
+                                                      int nbp) {
+    const size_t n4 = (size_t)nbp * nbp * nbp * nbp;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n4;
+         e += (size_t)gridDim.x * blockDim.x) {
+        size_t q = e % nbp, t = e / nbp;
+        size_t p = t % nbp;
+        t /= nbp;
+        size_t k = t % nbp, i = t / nbp;
+        cd v = g2[((i * nbp + p) * nbp + k) * nbp + q];
+        stc(b + e, v.x, v.y);
+    }
+}
+
+// Pi[(i,k)][(j,l)] = sum_K B[(i,k)][K] H[K][(j,l)], stored as pim[i][j][k][l].
+// 64x64 output tile per work-group, four waves of 32x32, K staged in slices of 16.
+// With T = float the products are accumulated in binary32 over 64-deep chunks
+// and the chunk sums are added in binary64 (chunked compensated summation).
+template <typename T, typename S>
+__global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
+                                                      cd* __restrict__ pim, int n, int nbp) {
+    __shared__ T a_re[64][17], a_im[64][17], b_re[16][65], b_im[16][65];
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+    const int wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    CAcc<T> acc[2][2];
+    double accd[2][2][2][4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            acc[a][b].clear();
+            for (int r4 = 0; r4 < 4; ++r4) accd[a][b][0][r4] = accd[a][b][1][r4] = 0.0;
+        }
+    for (int k0 = 0; k0 < n; k0 += 16) {
+        for (int idx = threadIdx.x; idx < 64 * 16; idx += 256) {
+            int r = idx / 16, c = idx % 16;
+            T x, yv;
+            ldc(A + (size_t)(bm + r) * n + k0 + c, x, yv);
+            a_re[r][c] = x;
+            a_im[r][c] = yv;
+            int r2 = idx / 64, c2 = idx % 64;
+            ldc(B + (size_t)(k0 + r2) * n + bn + c2, x, yv);
+            b_re[r2][c2] = x;
+            b_im[r2][c2] = yv;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                cgemm_tile<T, 16>(
+                    acc[a][b],
+                    [&](int i, int k, T& r, T& m) {
+                        r = a_re[i][k];
+                        m = a_im[i][k];
+                    },
+                    [&](int k, int j, T& r, T& m) {
+                        r = b_re[k][j];
+                        m = b_im[k][j];
+                    },
+                    wm + a * 16, wn + b * 16);
+        __syncthreads();
+        if (sizeof(T) == 4 && ((k0 + 16) % 64 == 0 || k0 + 16 >= n)) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    for (int r4 = 0; r4 < 4; ++r4) {
+                        accd[a][b][0][r4] += (double)acc[a][b].re[r4];
+                        accd[a][b][1][r4] += (double)acc[a][b].im[r4];
+                    }
+                    acc[a][b].clear();
+                }
+        }
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int row = bm + wm + a * 16 + tile_row<T>(r4);
+                const int col = bn + wn + b * 16 + tile_col();
+                const int i = row / nbp, k = row % nbp, j = col / nbp, l = col % nbp;
+                double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)acc[a][b].re[r4];
+                double vi = sizeof(T) == 4 ? accd[a][b][1][r4] : (double)acc[a][b].im[r4];
+                pim[(((size_t)i * nbp + j) * nbp + k) * nbp + l] = make_double2(vr, vi);
+            }
+}
+
+// --------------------------------------------------------------------------- layout helpers
+__global__ void pad_kernel(const cd* __restrict__ src, cd* __restrict__ dst, int nb, int nbp, int rank,
+                           int unpad) {
+    size_t total = 1;
+    for (int r = 0; r < rank; ++r) total *= (size_t)(unpad ? nb : nbp);
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int n_from = unpad ? nb : nbp;
+        size_t t = e, ip = 0, iu = 0, mul_p = 1, mul_u = 1;
+        bool inside = true;
+        for (int r = 0; r < rank; ++r) {
+            size_t idx = t % n_from;
+            t /= n_from;
+            if ((int)idx >= nb) inside = false;
+            ip += idx * mul_p;
+            iu += idx * mul_u;
+            mul_p *= nbp;
+            mul_u *= nb;
+        }
+        if (unpad)
+            dst[e] = src[ip];
+        else
+            dst[e] = inside ? src[iu] : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ __launch_bounds__(256) void gen_obs_kernel(const cd* __restrict__ gl,
+                                                     const cd* __restrict__ h0,
+                                                     const cd* __restrict__ hhf,
+                                                     const cd* __restrict__ icoll, int nbp,
+                                                     double* __restrict__ res) {
+    __shared__ double sh[4][256];
+    const int n2 = nbp * nbp;
+    double N = 0, ekin = 0, emf = 0, ecorr = 0;
+    for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+        const int i = e / nbp, j = e % nbp;
+        cd g = gl[j * nbp + i];
+        cd nji = make_double2(g.y, -g.x);  // n = -i G^<
+        cd h = h0[e], s = csub(hhf[e], h);
+        ekin += h.x * nji.x - h.y * nji.y;
+        emf += 0.5 * (s.x * nji.x - s.y * nji.y);
+        if (i == j) {
+            N += gl[e].y;
+            ecorr += 0.5 * icoll[e].y;  // E_corr = 1/2 Im Tr I
+        }
+    }
+    sh[0][threadIdx.x] = N;
+    sh[1][threadIdx.x] = ekin;
+    sh[2][threadIdx.x] = emf;
+    sh[3][threadIdx.x] = ecorr;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 4; ++q) res[q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(256) void herm_kernel(const cd* __restrict__ A, int n, long long nn,
+                                                  double* __restrict__ part) {
+    __shared__ double s1[256], s2[256];
+    double m1 = 0, m2 = 0;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+         e += (long long)gridDim.x * blockDim.x) {
+        long long r = e / n, col = e % n;
+        cd v = A[e], w = A[col * n + r];
+        double dx = v.x - w.x, dy = v.y + w.y;
+        m1 = fmax(m1, sqrt(dx * dx + dy * dy));
+        m2 = fmax(m2, sqrt(v.x * v.x + v.y * v.y));
+    }
+    s1[threadIdx.x] = m1;
+    s2[threadIdx.x] = m2;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// --------------------------------------------------------------------------- host side
+int main_grid(int nbp) { return std::min(nbp * nbp, 512); }
+
+template <typename T, typename S, int NB>
+g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
+    GeneralData& g = c->gen;
+    const bool mixed = sizeof(T) == 4;
+    const S* wrows = mixed ? (const S*)g.wm_rows32 : (const S*)g.wm_rows;
+    const S* wcoll = mixed ? (const S*)g.w_coll32 : (const S*)g.w_coll;
+    const int grid_vt = std::min(NB * NB, 1024);
+    hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0, c->stream,
+                       wrows, in.g1, (S*)g.vt);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "gen_vt");
+    if (c->d.selfenergy == G1G2_GW) {
+        const S* wgw = mixed ? (const S*)g.w_gw32 : (const S*)g.w_gw;
+        hipLaunchKernelGGL((gen_heps_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+                           c->stream, wgw, in.g1, (S*)g.heps);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_heps");
+        hipLaunchKernelGGL((gen_bmat_kernel<S>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
+                           NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_bmat");
+        const int n = NB * NB;
+        hipLaunchKernelGGL((gen_gemm_kernel<T, S>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                           (const S*)g.bmat, (const S*)g.heps, g.pimat, n, NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_gemm");
+    }
+    hipLaunchKernelGGL((gen_main_kernel<T, S, NB>), dim3(g.nipart), dim3(Shape<NB>::THREADS), 0,
+                       c->stream, in.g2, (const S*)g.vt, wcoll, g.gg, g.hhf, (S*)g.dmat, g.ipart);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "gen_main");
+    return G1G2_OK;
+}
+
+template <typename S, int MODE>
+g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& acc,
+                        const Regs& out, double cb, double cc) {
+    GeneralData& g = c->gen;
+    const int n = g.nbp * g.nbp;
+    const int nt = n / 32;
+    if (c->d.selfenergy == G1G2_GW)
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(nt * nt), dim3(256), 0, c->stream,
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc);
+    else
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(nt * nt), dim3(256), 0, c->stream,
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "gen_combine");
+    const int n2 = g.nbp * g.nbp;
+    hipLaunchKernelGGL((gen_g1_kernel<MODE>), dim3((n2 + 255) / 256), dim3(256), 0, c->stream, g.ipart,
+                       g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1, g.icoll, cb, cc, g.nbp, g.nb,
+                       c->dflag);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "gen_g1");
+    return G1G2_OK;
+}
+
+template <typename T, typename S>
+g1g2_status dispatch_blocks(g1g2_ctx* c, const Regs& in) {
+    switch (c->gen.nbp) {
+        case 16: return run_blocks<T, S, 16>(c, in);
+        case 32: return run_blocks<T, S, 32>(c, in);
+        case 48: return run_blocks<T, S, 48>(c, in);
+        case 64: return run_blocks<T, S, 64>(c, in);
+        default: return set_error(c, G1G2_EUNSUPPORTED, "general basis supports nb <= 64");
+    }
+}
+
+template <typename S>
+g1g2_status dispatch_combine(g1g2_ctx* c, int mode, const Regs& in, const Regs& y, const Regs& acc,
+                             const Regs& out, double cb, double cc) {
+    switch (mode) {
+        case RK_RHS: return run_combine<S, RK_RHS>(c, in, y, acc, out, cb, cc);
+        case RK_FIRST: return run_combine<S, RK_FIRST>(c, in, y, acc, out, cb, cc);
+        case RK_MID: return run_combine<S, RK_MID>(c, in, y, acc, out, cb, cc);
+        default: return run_combine<S, RK_LAST>(c, in, y, acc, out, cb, cc);
+    }
+}
+
+template <typename V>
+g1g2_status upload(g1g2_ctx* c, V** dst, const std::vector<V>& h) {
+    HIP_OK(c, hipMalloc(dst, h.size() * sizeof(V)));
+    HIP_OK(c, hipMemcpyAsync(*dst, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+    return G1G2_OK;
+}
+
+std::vector<float2> to_f32(const std::vector<cd>& v) {
+    std::vector<float2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2((float)v[i].x, (float)v[i].y);
+    return o;
+}
+
+}  // namespace
+
+g1g2_status gen_set_h0(g1g2_ctx* c, const cd* h0) {
+    GeneralData& g = c->gen;
+    const int nb = g.nb, nbp = g.nbp;
+    std::vector<cd> hp((size_t)nbp * nbp, cmk(0, 0));
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j) {
+            cd v = h0[i * nb + j], vt = h0[j * nb + i];
+            if (std::fabs(v.x - vt.x) > 1e-12 * (1 + std::fabs(v.x)) ||
+                std::fabs(v.y + vt.y) > 1e-12 * (1 + std::fabs(v.y)))
+                return set_error(c, G1G2_EINVAL, "h0 is not Hermitian");
+            hp[i * nbp + j] = v;
+        }
+    if (!g.h0) HIP_OK(c, hipMalloc(&g.h0, hp.size() * sizeof(cd)));
+    HIP_OK(c, hipMemcpyAsync(g.h0, hp.data(), hp.size() * sizeof(cd), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return G1G2_OK;
+}
+
+g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
+    GeneralData& g = c->gen;
+    const int nb = c->d.nb;
+    const int nbp = ((nb + 15) / 16) * 16;
+    if (nbp > 64) return set_error(c, G1G2_EUNSUPPORTED, "general basis supports nb <= 64");
+    g.nb = nb;
+    g.nbp = nbp;
+    const size_t n4 = (size_t)nbp * nbp * nbp * nbp;
+    const bool gw = c->d.selfenergy == G1G2_GW;
+    const bool exch = !gw || (c->d.flags & G1G2_GW_EXCHANGE);
+    auto W = [&](int i, int j, int k, int l) -> cd { return w[(((size_t)i * nb + j) * nb + k) * nb + l]; };
+    // symmetry checks of the interaction (eq:wsymm_a, eq:wsymm_b)
+    double wmax = 0, e1 = 0, e2 = 0;
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k < nb; ++k)
+                for (int l = 0; l < nb; ++l) {
+                    cd a = W(i, j, k, l), b = W(j, i, l, k), d = W(k, l, i, j);
+                    wmax = std::max(wmax, std::hypot(a.x, a.y));
+                    e1 = std::max(e1, std::hypot(a.x - b.x, a.y - b.y));
+                    e2 = std::max(e2, std::hypot(a.x - d.x, a.y + d.y));
+                }
+    if (e1 > 1e-12 * (1 + wmax) || e2 > 1e-12 * (1 + wmax))
+        return set_error(c, G1G2_EINVAL, "w violates w_ijkl = w_jilk or w_ijkl = conj(w_klij)");
+    std::vector<cd> rows(n4, cmk(0, 0)), coll(n4, cmk(0, 0)), hf(n4, cmk(0, 0));
+    auto P4 = [&](int a, int b, int cc, int d) { return (((size_t)a * nbp + b) * nbp + cc) * nbp + d; };
+    for (int i = 0; i < nb; ++i)
+        for (int j = 0; j < nb; ++j)
+            for (int k = 0; k < nb; ++k)
+                for (int l = 0; l < nb; ++l) {
+                    cd v = W(i, j, k, l), vx = W(i, j, l, k);
+                    rows[P4(i, j, k, l)] = exch ? csub(v, vx) : v;   // W^-_pqrs (or W for GW)
+                    coll[P4(k, l, i, j)] = v;                         // [l][p][i][k] = w_iklp
+                    hf[P4(i, k, j, l)] = csub(v, vx);                 // [i][j][k][l] = w^-_ikjl
+                }
+    g1g2_status s;
+    if ((s = upload(c, &g.wm_rows, rows)) != G1G2_OK) return s;
+    if ((s = upload(c, &g.w_coll, coll)) != G1G2_OK) return s;
+    if ((s = upload(c, &g.w_hf, hf)) != G1G2_OK) return s;
+    const bool mixed = c->d.precision == G1G2_MIXED;
+    if (mixed) {
+        if ((s = upload(c, &g.wm_rows32, to_f32(rows))) != G1G2_OK) return s;
+        if ((s = upload(c, &g.w_coll32, to_f32(coll))) != G1G2_OK) return s;
+    }
+    if (gw) {
+        std::vector<cd> wg(n4, cmk(0, 0));
+        for (int s1 = 0; s1 < nb; ++s1)
+            for (int q = 0; q < nb; ++q)
+                for (int r = 0; r < nb; ++r)
+                    for (int p = 0; p < nb; ++p) wg[P4(p, q, s1, r)] = W(s1, q, r, p);  // M_pq[s][r] = w_sqrp
+        if ((s = upload(c, &g.w_gw, wg)) != G1G2_OK) return s;
+        if (mixed && (s = upload(c, &g.w_gw32, to_f32(wg))) != G1G2_OK) return s;
+        const size_t es = mixed ? sizeof(float2) : sizeof(cd);
+        HIP_OK(c, hipMalloc(&g.heps, n4 * es));
+        HIP_OK(c, hipMalloc(&g.bmat, n4 * es));
+        HIP_OK(c, hipMalloc(&g.pimat, n4 * sizeof(cd)));
+    }
+    const size_t es = mixed ? sizeof(float2) : sizeof(cd);
+    HIP_OK(c, hipMalloc(&g.vt, n4 * es));
+    HIP_OK(c, hipMalloc(&g.dmat, n4 * es));
+    HIP_OK(c, hipMalloc(&g.hhf, (size_t)nbp * nbp * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&g.gg, (size_t)nbp * nbp * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&g.icoll, (size_t)nbp * nbp * sizeof(cd)));
+    g.nipart = main_grid(nbp);
+    HIP_OK(c, hipMalloc(&g.ipart, (size_t)g.nipart * nbp * nbp * 2 * sizeof(double)));
+    return gen_set_h0(c, h0);
+}
+
+g1g2_status gen_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
+                      const Regs& acc, const Regs& out, double cb, double cc) {
+    (void)t;
+    GeneralData& g = c->gen;
+    const int nbp = g.nbp;
+    hipLaunchKernelGGL(gen_hf_kernel, dim3(nbp * nbp), dim3(256), 0, c->stream, g.w_hf, g.h0, in.g1,
+                       g.hhf, g.gg, nbp, g.nb);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "gen_hf");
+    g1g2_status s;
+    if (c->d.precision == G1G2_MIXED) {
+        if ((s = dispatch_blocks<float, float2>(c, in)) != G1G2_OK) return s;
+        return dispatch_combine<float2>(c, mode, in, y, acc, out, cb, cc);
+    }
+    if ((s = dispatch_blocks<double, cd>(c, in)) != G1G2_OK) return s;
+    return dispatch_combine<cd>(c, mode, in, y, acc, out, cb, cc);
+}
+
+g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o) {
+    (void)t;
+    GeneralData& g = c->gen;
+    // one right-hand-side evaluation refreshes h^HF and the collision integral
+    g1g2_status st = gen_stage(c, RK_RHS, c->t, s, s, s, c->io, 0.0, 0.0);
+    if (st != G1G2_OK) return st;
+    hipLaunchKernelGGL(gen_obs_kernel, dim3(1), dim3(256), 0, c->stream, s.g1, g.h0, g.hhf, g.icoll,
+                       g.nbp, c->dscratch);
+    HIP_OK(c, hipGetLastError());
+    const int n = g.nbp * g.nbp;
+    const int nblk = 256;
+    hipLaunchKernelGGL(herm_kernel, dim3(nblk), dim3(256), 0, c->stream, s.g2, n, (long long)n * n,
+                       c->dscratch + 8);
+    HIP_OK(c, hipGetLastError());
+    std::vector<double> h(8 + 2 * nblk);
+    HIP_OK(c, hipMemcpyAsync(h.data(), c->dscratch, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    double m1 = 0, m2 = 0;
+    for (int b = 0; b < nblk; ++b) {
+        m1 = std::max(m1, h[8 + 2 * b]);
+        m2 = std::max(m2, h[8 + 2 * b + 1]);
+    }
+    o->N[0] = h[0];
+    o->N[1] = 0.0;
+    o->E_kin = h[1];
+    o->E_mf = h[2];
+    o->E_corr = h[3];
+    o->E_tot = h[1] + h[2] + h[3];
+    o->docc = 0.0;
+    o->herm_resid = m2 > 0 ? m1 / m2 : 0.0;
+    return G1G2_OK;
+}
+
+g1g2_status gen_pad(g1g2_ctx* c, const cd* src, cd* dst, int rank) {
+    hipLaunchKernelGGL(pad_kernel, dim3(1024), dim3(256), 0, c->stream, src, dst, c->gen.nb, c->gen.nbp,
+                       rank, 0);
+    HIP_OK(c, hipGetLastError());
+    return G1G2_OK;
+}
+
+g1g2_status gen_unpad(g1g2_ctx* c, const cd* src, cd* dst, int rank) {
+    hipLaunchKernelGGL(pad_kernel, dim3(1024), dim3(256), 0, c->stream, src, dst, c->gen.nb, c->gen.nbp,
+                       rank, 1);
+    HIP_OK(c, hipGetLastError());
+    return G1G2_OK;
+}
+
+void gen_free(g1g2_ctx* c) {
+    GeneralData& g = c->gen;
+    void* ptrs[] = {g.h0, g.wm_rows, g.w_coll, g.w_hf, g.vt, g.dmat, g.hhf, g.gg, g.ipart, g.heps,
+                    g.bmat, g.pimat, g.wm_rows32, g.w_coll32, g.w_gw, g.w_gw32, g.icoll};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    g = GeneralData();
+}

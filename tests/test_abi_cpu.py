@@ -1,0 +1,62 @@
+"""CPU checks of the C-ABI library: it builds for gfx950, loads, and exports
+every function that include/g1g2.h declares (no compute call needs a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "g1g2.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(g1g2_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def so_path():
+    from paper_2002_12717_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    return build.LIB
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("g1g2_init", "g1g2_rhs", "g1g2_step_rk4", "g1g2_observables", "g1g2_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(so_path):
+    lib = ctypes.CDLL(so_path)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_header(so_path):
+    from paper_2002_12717_amd import binding
+    lib = binding.load(so_path)
+    for n in _declared():
+        assert n in binding._SIGS, n
+        assert getattr(lib, n).argtypes is not None or n in ("g1g2_strerror",)
+
+
+def test_strerror_needs_no_device(so_path):
+    from paper_2002_12717_amd import binding
+    lib = binding.load(so_path)
+    assert lib.g1g2_strerror(-5) == b"propagation diverged"
+    assert lib.g1g2_strerror(0) == b"ok"
+
+
+def test_init_rejects_bad_arguments_without_device(so_path):
+    """Argument validation happens before any device call."""
+    from paper_2002_12717_amd import binding
+    lib = binding.load(so_path)
+    ctx = ctypes.c_void_p()
+    d = binding.Desc(0, 0, 0, 0, 0, 0.0)       # nb = 0
+    assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), None, None, None, None, None) == binding.EINVAL
+    d = binding.Desc(1, 1, 0, 0, 4, 1.0)       # Hubbard GW is not implemented
+    buf = (ctypes.c_double * 64)()
+    assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, None, buf, None, None) == binding.EUNSUPPORTED
