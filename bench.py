@@ -1,14 +1,16 @@
 """Benchmark of the G1-G2 hot path on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): general-basis
-second-Born G1-G2 propagation, Nb = 32 spin orbitals, random GUE h (sigma=1),
-w = sum_Q B^Q x B^Q from a rank-64 Hermitian factor, 8 particles in the
-Aufbau state of h, G2(0) = 0, RK4 with dt = 0.01.  Inputs are seeded and
+Default workload (the configuration the headline metric is quoted on):
+general-basis second-Born G1-G2 propagation, Nb = 32 spin orbitals, random GUE
+h (sigma = 1), w = sum_Q B^Q x B^Q from a rank-64 Hermitian factor, 8 particles
+in the Aufbau state of h, G2(0) = 0, RK4 with dt = 0.01.  Inputs are seeded and
 synthetic (workloads.general_system).
 
-One "step" = one full RK4 step (4 right-hand sides) of G1 and G2.  The binary64
-path is the headline value; the mixed path (binary32 matrix-core contractions,
-binary64 state) is reported beside it with its error against the binary64 run.
+One "step" = one full RK4 step (four right-hand sides) of G1 and G2.  The
+binary64 path is the headline value; the mixed path (binary32 matrix-core
+contractions, binary64 state) is reported beside it with its error against
+the binary64 run.  Other workloads of the paper's shape are available with
+--workload (hubbard_chain, hubbard_2d, general_gw).
 
 Prints ONE JSON line.
 """
@@ -29,16 +31,27 @@ PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0          # GB/s
 
 
-def flops_per_rhs(nb: int) -> dict:
-    """Algorithmic real flops of one general-basis SOA right-hand side: 8 per
-    complex multiply-add, Hermiticity halving assumed:
-    gen_vt 2 nb^5, gen_main 5 nb^5 (T sandwich 2, commutator 2, collision 1)."""
+def soa_flops(nb: int) -> dict:
+    """Algorithmic real flops of one general-basis right-hand side (8 per complex
+    multiply-add; Hermiticity halving assumed): gen_vt 2 nb^5, gen_main 5 nb^5
+    (T sandwich 2, commutator 2, collision integral 1)."""
     n5 = float(nb) ** 5
-    return {"gen_vt": 8 * 2 * n5, "gen_main": 8 * 5 * n5, "total": 8 * 7 * n5}
+    return {"gen_vt": 16 * n5, "gen_main": 40 * n5, "soa_total": 56 * n5}
 
 
-def time_propagator(p, dt, steps, warmup, stream, torch):
-    p.step(dt, warmup)
+def gw_flops(nb: int) -> dict:
+    """GW adds h^eps (2 nb^5) and the polarization GEMM (nb^6) per RHS."""
+    d = soa_flops(nb)
+    d["gen_heps"] = 16 * float(nb) ** 5
+    d["gen_gemm"] = 8 * float(nb) ** 6
+    d["total"] = d["soa_total"] + d["gen_heps"] + d["gen_gemm"]
+    return d
+
+
+def timed_steps(p, dt, steps, warmup, stream, torch):
+    """Wall and event time of `steps` RK4 steps after `warmup` steps."""
+    if warmup:
+        p.step(dt, warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -51,9 +64,13 @@ def time_propagator(p, dt, steps, warmup, stream, torch):
     return ev0.elapsed_time(ev1), (w1 - w0) * 1e3
 
 
-def cpu_baseline(system, seconds: float = 15.0):
-    """The FP64 oracle on the host cores, timed on a bounded number of RK4
-    steps of the same workload (starting from the same initial state)."""
+def kernel_table(prof: dict) -> dict:
+    return {k: {"ms_avg": round(v[0] / max(v[1], 1), 6), "launches": v[1]} for k, v in prof.items()}
+
+
+def cpu_baseline_general(system, seconds: float = 15.0):
+    """The FP64 oracle on the host cores, timed on a bounded number of RK4 steps
+    of the same workload from the same initial state."""
     import torch
     from oracle import integrate as OI
     nthreads = torch.get_num_threads()
@@ -68,9 +85,133 @@ def cpu_baseline(system, seconds: float = 15.0):
         el = time.perf_counter() - t0
         if el > seconds or n >= 200:
             break
-    return {"value": n / el, "unit": "RK4 steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{n} RK4 steps of the Nb=32 SOA workload (torch CPU complex128, "
-                      f"{nthreads} threads), {el:.1f} s"}
+    return {"value": round(n / el, 4), "unit": "RK4 steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} RK4 steps of the Nb=32 SOA workload from t=0 (torch CPU complex128, "
+                      f"{nthreads} threads, {el:.1f} s)"}
+
+
+def cpu_baseline_hubbard(system, seconds: float = 15.0):
+    import torch
+    from oracle import integrate as OI
+    nthreads = torch.get_num_threads()
+    f = OI.hubbard_rhs_fn(system, "soa")
+    y = OI.hubbard_initial(system, "soa")
+    y = list(OI.rk4_step(f, 0.0, y, system.dt))
+    n, t0 = 0, time.perf_counter()
+    while True:
+        y = list(OI.rk4_step(f, n * system.dt, y, system.dt))
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds or n >= 2000:
+            break
+    return {"value": round(n / el, 4), "unit": "RK4 steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} RK4 steps of the {system.name} workload (torch CPU, {nthreads} threads, "
+                      f"{el:.1f} s)"}
+
+
+def base_line(args, steps_per_s, ms_step, dtype, config):
+    return {"metric": METRIC, "value": round(steps_per_s, 3), "unit": "RK4 steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 6),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+# --------------------------------------------------------------------------- workloads
+def run_general(args, torch, B, gw=False):
+    import numpy as np
+    from workloads import general_system, gw_system
+    system = gw_system() if gw else general_system()
+    nb = system.nb
+    stream = torch.cuda.Stream()
+    fl = gw_flops(nb) if gw else soa_flops(nb)
+    se = B.GW if gw else B.SOA
+    res = {}
+    for prec in ("fp64", "mixed"):
+        p = B.Propagator(B.GENERAL, se, nb, system.h0, system.g1, w=system.w,
+                         precision=B.FP64 if prec == "fp64" else B.MIXED, stream=stream.cuda_stream)
+        if system.kick is not None:          # one-step kick, then the static h0
+            p.set_h0(system.h0 + system.kick)
+            p.step(system.dt, 1)
+            p.set_h0(system.h0)
+        ms, wall = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
+        g1, _, t = p.get_state()
+        obs = p.observables()
+        prof = p.profile(system.dt, args.profile_steps)
+        res[prec] = dict(ms=ms, wall=wall, g1=g1, obs=obs, prof=prof, t=t)
+        p.close()
+    f64, mx = res["fp64"], res["mixed"]
+    ms_step = f64["ms"] / args.steps
+    mx_step = mx["ms"] / args.steps
+    dom = "gen_gemm" if gw else "gen_main"
+    tot_ms, cnt = f64["prof"][dom]
+    achieved = fl[dom] * cnt / (tot_ms * 1e-3) / 1e12
+    rhs_flops = fl["total"] if gw else fl["soa_total"]
+    config = {"workload": (f"general-basis {'GW' if gw else 'SOA'} G1-G2, Nb={nb} spin orbitals, "
+                           f"rank-{system.meta['rank']} w, {system.meta['nocc']} particles, "
+                           f"dt={system.dt}, RK4"),
+              "nb": nb, "rank": system.meta["rank"], "nocc": system.meta["nocc"], "dt": system.dt,
+              "selfenergy": "GW" if gw else "SOA", "parallelism": "single GPU"}
+    out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    mx_tot, mx_cnt = mx["prof"][dom]
+    mx_ach = fl[dom] * mx_cnt / (mx_tot * 1e-3) / 1e12
+    out.update({
+        "g2_rhs_tflops": round(4 * rhs_flops / (ms_step * 1e-3) / 1e12, 3),
+        "roofline": {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
+                     "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
+                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "flop_per_launch": fl[dom], "launches": cnt},
+        "kernels": kernel_table(f64["prof"]),
+        "mixed": {"dtype": "f32 contractions / f64 state", "value": round(1e3 / mx_step, 3),
+                  "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
+                  "g2_rhs_tflops": round(4 * rhs_flops / (mx_step * 1e-3) / 1e12, 3),
+                  "err_G1_vs_fp64": float(np.abs(mx["g1"] - f64["g1"]).max() / np.abs(f64["g1"]).max()),
+                  "err_E_vs_fp64": abs(mx["obs"]["E_tot"] - f64["obs"]["E_tot"])
+                  / max(abs(f64["obs"]["E_tot"]), 1.0),
+                  "roofline": {"kernel": dom, "achieved": round(mx_ach, 3), "peak": PEAK_FP32_MFMA,
+                               "unit": "TFLOP/s", "frac": round(mx_ach / PEAK_FP32_MFMA, 4)},
+                  "kernels": kernel_table(mx["prof"])},
+        "sim_time": f64["t"],
+    })
+    if not args.no_cpu_baseline and not gw:
+        out["cpu_baseline"] = cpu_baseline_general(system)
+    return out
+
+
+def run_hubbard(args, torch, B, kind):
+    from workloads import adjoint_system, hubbard_chain_system
+    system = hubbard_chain_system() if kind == "hubbard_chain" else adjoint_system()
+    ns = system.ns
+    stream = torch.cuda.Stream()
+    p = B.Propagator(B.HUBBARD, B.SOA, ns, system.h0, system.g1, U=system.U, stream=stream.cuda_stream)
+    if system.drive is not None:
+        d = system.drive
+        p.set_drive(d.x, d.c, d.t_center, d.tau)
+    ms, wall = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
+    prof = p.profile(system.dt, args.profile_steps)
+    obs = p.observables()
+    p.close()
+    ms_step = ms / args.steps
+    n4 = float(ns) ** 4
+    tot_ms, cnt = prof["hub_g2"]
+    # algorithmic bytes: 256 B per complex128 G2 element per RK4 step (4 launches)
+    bytes_per_launch = 64.0 * n4
+    achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
+    name = "1D chain, 8 sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
+    config = {"workload": f"Hubbard SOA G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
+              "ns": ns, "U": system.U, "dt": system.dt, "selfenergy": "SOA",
+              "parallelism": "single GPU"}
+    out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    out.update({
+        "roofline": {"kernel": "hub_g2", "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "bytes_per_launch": bytes_per_launch, "launches": cnt},
+        "kernels": kernel_table(prof),
+        "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
+    })
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_hubbard(system)
+    return out
 
 
 def main():
@@ -78,82 +219,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--workload", default="general_soa",
+                    choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the G1-G2 workload here runs on a single "
-              "MI355X (see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: this G1-G2 workload runs on a single MI355X "
+              "(DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
     import torch
     from paper_2002_12717_amd import binding as B
-    from workloads import general_system
-
     torch.cuda.set_device(0)
-    system = general_system()
-    nb = system.nb
-    stream = torch.cuda.Stream()
-    fl = flops_per_rhs(nb)
-
-    res = {}
-    for prec in ("fp64", "mixed"):
-        p = B.Propagator(B.GENERAL, B.SOA, nb, system.h0, system.g1, w=system.w,
-                         precision=B.FP64 if prec == "fp64" else B.MIXED, stream=stream.cuda_stream)
-        ms, wall_ms = time_propagator(p, system.dt, args.steps, args.warmup, stream, torch)
-        g1, _, t = p.get_state()
-        prof = p.profile_rhs(reps=20)
-        obs = p.observables()
-        res[prec] = dict(ms=ms, wall_ms=wall_ms, g1=g1, prof=prof, obs=obs, t=t)
-        p.close()
-
-    f64, mx = res["fp64"], res["mixed"]
-    ms_step = f64["ms"] / args.steps
-    steps_per_s = 1e3 / ms_step
-    mx_ms_step = mx["ms"] / args.steps
-    err_mixed = float(np.abs(mx["g1"] - f64["g1"]).max() / np.abs(f64["g1"]).max())
-    e_err_mixed = abs(mx["obs"]["E_tot"] - f64["obs"]["E_tot"]) / max(abs(f64["obs"]["E_tot"]), 1.0)
-
-    main_ms = f64["prof"].get("gen_main")
-    achieved = fl["gen_main"] / (main_ms * 1e-3) / 1e12
-    roofline = {"kernel": "gen_main", "bound": "mfma", "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
-                "traffic": None, "kernel_ms": round(main_ms, 5),
-                "flop_per_launch": fl["gen_main"]}
-    rhs_ms = sum(f64["prof"].values())
-    out = {
-        "metric": METRIC,
-        "value": round(steps_per_s, 2),
-        "unit": "RK4 steps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "general-basis SOA G1-G2, Nb=32 spin orbitals, rank-64 w, "
-                               "8 particles, dt=0.01, RK4",
-                   "nb": nb, "rank": 64, "nocc": 8, "dt": system.dt, "selfenergy": "SOA",
-                   "parallelism": "single GPU"},
-        "g2_rhs_tflops": round(4 * fl["total"] / (ms_step * 1e-3) / 1e12, 3),
-        "roofline": roofline,
-        "kernels_ms_per_rhs": {k: round(v, 5) for k, v in f64["prof"].items()},
-        "rhs_ms_sum": round(rhs_ms, 5),
-        "mixed": {"dtype": "f32 contractions / f64 state",
-                  "value": round(1e3 / mx_ms_step, 2), "ms_per_step": round(mx_ms_step, 5),
-                  "speedup_vs_fp64": round(ms_step / mx_ms_step, 3),
-                  "g2_rhs_tflops": round(4 * fl["total"] / (mx_ms_step * 1e-3) / 1e12, 3),
-                  "err_G1_vs_fp64": err_mixed, "err_E_vs_fp64": e_err_mixed,
-                  "kernels_ms_per_rhs": {k: round(v, 5) for k, v in mx["prof"].items()},
-                  "peak": PEAK_FP32_MFMA},
-        "sim_time": f64["t"],
-        "wall_ms_fp64": round(f64["wall_ms"], 3),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(system)
+    if args.workload == "general_soa":
+        out = run_general(args, torch, B)
+    elif args.workload == "general_gw":
+        out = run_general(args, torch, B, gw=True)
+    else:
+        out = run_hubbard(args, torch, B, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -141,14 +141,16 @@ g1g2_status g1g2_set_U(g1g2_ctx* ctx, double U);
 g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const double* c,
                            const double* t_center, double tau);
 
-/* Profiling aid: evaluates the right-hand side of the current state `reps`
- * times with a HIP event recorded on the context's stream after every kernel
- * launch, and returns in ms[k] the average time between consecutive events,
- * i.e. the duration of the k-th kernel of one evaluation (launch order; at
- * most max_kernels values, the number of kernels in *count).  The kernel
- * names are given by g1g2_profile_name(ctx, k).  Synchronizes the stream.   */
-g1g2_status g1g2_profile_rhs(g1g2_ctx* ctx, int32_t reps, double* ms, int32_t max_kernels,
-                             int32_t* count);
+/* Profiling aid.  Runs nsteps Runge-Kutta steps of size dt exactly like
+ * g1g2_step_rk4 (advancing the state), or, for nsteps = 0, one right-hand-side
+ * evaluation of the current state, with a HIP event recorded on the context's
+ * stream after every kernel launch.  For each distinct kernel k (at most
+ * max_kernels, the number in *count) it returns the summed time between the
+ * event before and after its launches, ms_total[k], and the number of
+ * launches, launches[k]; g1g2_profile_name(ctx, k) names the kernel.
+ * Synchronizes the stream.                                                  */
+g1g2_status g1g2_profile(g1g2_ctx* ctx, double dt, int64_t nsteps, int32_t max_kernels,
+                         double* ms_total, int32_t* launches, int32_t* count);
 const char* g1g2_profile_name(const g1g2_ctx* ctx, int32_t k);
 
 void g1g2_destroy(g1g2_ctx* ctx);

@@ -46,7 +46,8 @@ _SIGS = {
     "g1g2_set_h0": (c_int32, [c_void_p, c_void_p]),
     "g1g2_set_U": (c_int32, [c_void_p, c_double]),
     "g1g2_set_drive": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_double]),
-    "g1g2_profile_rhs": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, POINTER(c_int32)]),
+    "g1g2_profile": (c_int32, [c_void_p, c_double, c_int64, c_int32, c_void_p, c_void_p,
+                               POINTER(c_int32)]),
     "g1g2_profile_name": (ctypes.c_char_p, [c_void_p, c_int32]),
     "g1g2_destroy": (None, [c_void_p]),
     "g1g2_strerror": (ctypes.c_char_p, [c_int32]),
@@ -181,16 +182,16 @@ class Propagator:
         self._check(self.lib.g1g2_set_drive(self.ctx, _ptr(x), int(len(c)), _ptr(c), _ptr(tc),
                                              float(tau)))
 
-    def profile_rhs(self, reps: int = 10) -> dict:
-        """Average duration (ms) of every kernel of one right-hand-side evaluation."""
+    def profile(self, dt: float = 0.0, nsteps: int = 0) -> dict:
+        """Per-kernel time of nsteps RK4 steps (or of one RHS for nsteps = 0):
+        {name: (total_ms, launches)}."""
         ms = np.zeros(64)
+        cnt = np.zeros(64, np.int32)
         n = c_int32()
-        self._check(self.lib.g1g2_profile_rhs(self.ctx, int(reps), _ptr(ms), 64, ctypes.byref(n)))
-        out = {}
-        for k in range(n.value):
-            name = self.lib.g1g2_profile_name(self.ctx, k).decode()
-            out[name] = out.get(name, 0.0) + float(ms[k])
-        return out
+        self._check(self.lib.g1g2_profile(self.ctx, float(dt), int(nsteps), 64, _ptr(ms), _ptr(cnt),
+                                          ctypes.byref(n)))
+        return {self.lib.g1g2_profile_name(self.ctx, k).decode(): (float(ms[k]), int(cnt[k]))
+                for k in range(n.value)}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -336,35 +336,52 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
     return G1G2_OK;
 }
 
-g1g2_status g1g2_profile_rhs(g1g2_ctx* c, int32_t reps, double* ms, int32_t max_kernels,
-                             int32_t* count) {
-    if (!c || reps < 1 || !ms || max_kernels < 1 || !count) return G1G2_EINVAL;
-    std::vector<double> tot;
-    int n = 0;
-    for (int r = 0; r < reps; ++r) {
-        c->prof = true;
-        c->prof_used = 0;
-        prof_mark(c, "start");
-        g1g2_status s = stage(c, RK_RHS, c->t, c->y, c->y, c->y, c->s1, 0.0, 0.0);
-        c->prof = false;
-        if (s != G1G2_OK) return s;
-        HIP_OK(c, hipStreamSynchronize(c->stream));
-        n = (int)c->prof_used - 1;
-        tot.resize(n, 0.0);
-        for (int k = 0; k < n; ++k) {
-            float m = 0.f;
-            HIP_OK(c, hipEventElapsedTime(&m, c->prof_ev[k], c->prof_ev[k + 1]));
-            tot[k] += m;
-        }
+g1g2_status g1g2_profile(g1g2_ctx* c, double dt, int64_t nsteps, int32_t max_kernels,
+                         double* ms_total, int32_t* launches, int32_t* count) {
+    if (!c || nsteps < 0 || max_kernels < 1 || !ms_total || !launches || !count) return G1G2_EINVAL;
+    if (nsteps > 0 && !(dt > 0.0)) return G1G2_EINVAL;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->prof = true;
+    c->prof_used = 0;
+    prof_mark(c, "start");
+    g1g2_status s;
+    if (nsteps == 0) {
+        s = stage(c, RK_RHS, c->t, c->y, c->y, c->y, c->s1, 0.0, 0.0);
+    } else {
+        s = g1g2_step_rk4(c, dt, nsteps);
     }
-    *count = n;
-    for (int k = 0; k < n && k < max_kernels; ++k) ms[k] = tot[k] / reps;
+    c->prof = false;
+    if (s != G1G2_OK) return s;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->prof_kernels.clear();
+    std::vector<double> tot;
+    std::vector<int> cnt;
+    for (size_t k = 1; k < c->prof_used; ++k) {
+        const char* nm = c->prof_name[k];
+        if (std::strcmp(nm, "start") == 0) continue;
+        float m = 0.f;
+        HIP_OK(c, hipEventElapsedTime(&m, c->prof_ev[k - 1], c->prof_ev[k]));
+        size_t q = 0;
+        while (q < c->prof_kernels.size() && std::strcmp(c->prof_kernels[q], nm) != 0) ++q;
+        if (q == c->prof_kernels.size()) {
+            c->prof_kernels.push_back(nm);
+            tot.push_back(0.0);
+            cnt.push_back(0);
+        }
+        tot[q] += m;
+        cnt[q] += 1;
+    }
+    *count = (int32_t)c->prof_kernels.size();
+    for (size_t q = 0; q < c->prof_kernels.size() && (int)q < max_kernels; ++q) {
+        ms_total[q] = tot[q];
+        launches[q] = cnt[q];
+    }
     return G1G2_OK;
 }
 
 const char* g1g2_profile_name(const g1g2_ctx* c, int32_t k) {
-    if (!c || k < 0 || (size_t)k + 1 >= c->prof_name.size()) return "";
-    return c->prof_name[k + 1];
+    if (!c || k < 0 || (size_t)k >= c->prof_kernels.size()) return "";
+    return c->prof_kernels[k];
 }
 
 }  // extern "C"

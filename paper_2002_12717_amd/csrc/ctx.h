@@ -75,6 +75,7 @@ struct g1g2_ctx {
     std::vector<hipEvent_t> prof_ev;
     std::vector<const char*> prof_name;
     size_t prof_used = 0;
+    std::vector<const char*> prof_kernels;   // distinct kernel names of the last profile
 };
 
 // Record a timing event after the kernel `name` when profiling is active.

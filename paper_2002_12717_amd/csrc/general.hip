@@ -60,6 +60,12 @@ __device__ __forceinline__ void ldc(const float2* p, T& r, T& i) {
 __device__ __forceinline__ void stc(cd* p, double r, double i) { *p = make_double2(r, i); }
 __device__ __forceinline__ void stc(float2* p, double r, double i) { *p = make_float2((float)r, (float)i); }
 
+// Work-groups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Logical block b of a grid of g work-groups (g a multiple of 8) is
+// mapped so that each XCD owns a contiguous range of logical blocks, which
+// keeps neighbouring blocks (adjacent output lines) in one L2.
+__device__ __forceinline__ int xcd_block(int b, int g) { return (b & 7) * (g >> 3) + (b >> 3); }
+
 template <typename T, typename S, int NB>
 __device__ __forceinline__ void stage_block(const S* __restrict__ src, T* re, T* im) {
     constexpr int LD = Shape<NB>::LD;
@@ -119,7 +125,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
     constexpr int LD = SH::LD;
     __shared__ T w_re[NB * LD], w_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
     const int wave = threadIdx.x >> 6;
-    for (int blk = blockIdx.x; blk < NB * NB; blk += gridDim.x) {
+    const int b0 = xcd_block(blockIdx.x, gridDim.x);
+    for (int blk = b0; blk < NB * NB; blk += gridDim.x) {
         stage_block<T, S, NB>(wrows + (size_t)blk * NB * NB, w_re, w_im);
         __syncthreads();
         for (int t = 0; t < SH::TPW; ++t) {
@@ -165,6 +172,15 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
 // --------------------------------------------------------------------------- K3
 // Per row block ab:  D_ab = conj(G> Vt_ab G>^T) - (h^T C_ab + C_ab h),
 // and the collision partial  sum_ab Wc_ab C_ab^T  (binary64 across blocks).
+// For nb <= 32 the small operators G^> and h^HF are staged in LDS once per
+// work-group; for larger blocks they are read through the caches.
+template <typename T, int NB, bool STAGE>
+struct SmallOps {
+    static constexpr int LD = Shape<NB>::LD;
+    T g_re[STAGE ? NB * LD : 1], g_im[STAGE ? NB * LD : 1];
+    T h_re[STAGE ? NB * LD : 1], h_im[STAGE ? NB * LD : 1];
+};
+
 template <typename T, typename S, int NB>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
     const cd* __restrict__ g2, const S* __restrict__ vt, const S* __restrict__ wcoll,
@@ -172,13 +188,36 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
     double* __restrict__ ipart) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
+    constexpr bool STAGE = NB <= 32;
     __shared__ T b0_re[NB * LD], b0_im[NB * LD], b1_re[NB * LD], b1_im[NB * LD];
+    __shared__ SmallOps<T, NB, STAGE> ops;
+    if constexpr (STAGE) {
+        stage_block<T, cd, NB>(gg, ops.g_re, ops.g_im);
+        stage_block<T, cd, NB>(hhf, ops.h_re, ops.h_im);
+    }
+    auto G = [&](int i, int k, T& r, T& m) {   // G^>[i][k]
+        if constexpr (STAGE) {
+            r = ops.g_re[i * LD + k];
+            m = ops.g_im[i * LD + k];
+        } else {
+            ldc(gg + i * NB + k, r, m);
+        }
+    };
+    auto H = [&](int i, int k, T& r, T& m) {   // h^HF[i][k]
+        if constexpr (STAGE) {
+            r = ops.h_re[i * LD + k];
+            m = ops.h_im[i * LD + k];
+        } else {
+            ldc(hhf + i * NB + k, r, m);
+        }
+    };
     const int wave = threadIdx.x >> 6;
     double isum[SH::TPW][2][4];
     for (int t = 0; t < SH::TPW; ++t)
         for (int r4 = 0; r4 < 4; ++r4) isum[t][0][r4] = isum[t][1][r4] = 0.0;
 
-    for (int blk = blockIdx.x; blk < NB * NB; blk += gridDim.x) {
+    const int bfirst = xcd_block(blockIdx.x, gridDim.x);
+    for (int blk = bfirst; blk < NB * NB; blk += gridDim.x) {
         stage_block<T, S, NB>(vt + (size_t)blk * NB * NB, b0_re, b0_im);
         __syncthreads();
         // P = G> Vt_ab
@@ -187,7 +226,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
             CAcc<T> acc;
             acc.clear();
             cgemm_tile<T, NB>(
-                acc, [&](int i, int k, T& r, T& m) { ldc(gg + i * NB + k, r, m); },
+                acc, G,
                 [&](int k, int j, T& r, T& m) {
                     r = b0_re[k * LD + j];
                     m = b0_im[k * LD + j];
@@ -214,13 +253,13 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
                     r = b1_re[i * LD + k];
                     m = b1_im[i * LD + k];
                 },
-                [&](int k, int j, T& r, T& m) { ldc(gg + j * NB + k, r, m); }, ti * 16, tj * 16);
+                [&](int k, int j, T& r, T& m) { G(j, k, r, m); }, ti * 16, tj * 16);
             acc.im = -acc.im;  // conj
             // - h^T C
             cgemm_tile<T, NB>(
                 acc,
                 [&](int i, int k, T& r, T& m) {
-                    ldc(hhf + k * NB + i, r, m);
+                    H(k, i, r, m);
                     r = -r;
                     m = -m;
                 },
@@ -236,7 +275,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
                     r = -b0_re[i * LD + k];
                     m = -b0_im[i * LD + k];
                 },
-                [&](int k, int j, T& r, T& m) { ldc(hhf + k * NB + j, r, m); }, ti * 16, tj * 16);
+                H, ti * 16, tj * 16);
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
@@ -275,6 +314,14 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
 
 // --------------------------------------------------------------------------- K5
 // G1 equation eq:eom_gone-2 with I from the partials; writes I for observables.
+// One wavefront per element (i,j): the lanes share the sums over partials and
+// over the commutator index, then combine with cross-lane reductions.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void gen_g1_kernel(const double* __restrict__ ipart, int nparts,
                                                     const cd* __restrict__ hhf,
@@ -284,32 +331,43 @@ __global__ __launch_bounds__(256) void gen_g1_kernel(const double* __restrict__ 
                                                     double cb, double cc, int nbp, int nb,
                                                     int* __restrict__ flag) {
     const int n2 = nbp * nbp;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n2; e += gridDim.x * blockDim.x) {
-        const int i = e / nbp, j = e % nbp;
-        double sr = 0, si = 0, tr = 0, ti = 0;
-        for (int g = 0; g < nparts; ++g) {
-            const double* p = ipart + (size_t)g * n2 * 2;
-            sr += p[2 * e];
-            si += p[2 * e + 1];
-            tr += p[2 * (j * nbp + i)];
-            ti += p[2 * (j * nbp + i) + 1];
-        }
-        cd Iij = make_double2(si, -sr);  // -i (sr + i si)
-        cd Iji = make_double2(ti, -tr);
-        cd c = make_double2(0.0, 0.0);
-        for (int p = 0; p < nbp; ++p) {
-            c = cfma(c, hhf[i * nbp + p], gl[p * nbp + j]);
-            c = csub(c, cmul(gl[i * nbp + p], hhf[p * nbp + j]));
-        }
-        cd f = cmul_mi(cadd(c, cadd(Iij, cconj(Iji))));
-        if (MODE == RK_RHS) icoll[e] = Iij;
-        rk_update<MODE>(e, f, gl[e], y, acc, out, cb, cc);
-        if (MODE == RK_LAST && i < nb) {
-            cd v = out[e];
-            bool bad = !(isfinite(v.x) && isfinite(v.y));
-            if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
-            if (bad) atomicOr(flag, 1);
-        }
+    const int lane = threadIdx.x & 63;
+    const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (e >= n2) return;
+    const int i = e / nbp, j = e % nbp;
+    const int et = j * nbp + i;
+    double sr = 0, si = 0, tr = 0, ti = 0;
+    for (int g = lane; g < nparts; g += 64) {
+        const double* p = ipart + (size_t)g * n2 * 2;
+        sr += p[2 * e];
+        si += p[2 * e + 1];
+        tr += p[2 * et];
+        ti += p[2 * et + 1];
+    }
+    double cr = 0, ci = 0;
+    for (int p = lane; p < nbp; p += 64) {
+        cd a = cmul(hhf[i * nbp + p], gl[p * nbp + j]);
+        cd b = cmul(gl[i * nbp + p], hhf[p * nbp + j]);
+        cr += a.x - b.x;
+        ci += a.y - b.y;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    tr = wave_sum(tr);
+    ti = wave_sum(ti);
+    cr = wave_sum(cr);
+    ci = wave_sum(ci);
+    if (lane != 0) return;
+    cd Iij = make_double2(si, -sr);  // -i (sr + i si)
+    cd Iji = make_double2(ti, -tr);
+    cd f = cmul_mi(cadd(make_double2(cr, ci), cadd(Iij, cconj(Iji))));
+    if (MODE == RK_RHS) icoll[e] = Iij;
+    rk_update<MODE>(e, f, gl[e], y, acc, out, cb, cc);
+    if (MODE == RK_LAST && i < nb) {
+        cd v = out[e];
+        bool bad = !(isfinite(v.x) && isfinite(v.y));
+        if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
+        if (bad) atomicOr(flag, 1);
     }
 }
 
@@ -626,7 +684,7 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_combine");
     const int n2 = g.nbp * g.nbp;
-    hipLaunchKernelGGL((gen_g1_kernel<MODE>), dim3((n2 + 255) / 256), dim3(256), 0, c->stream, g.ipart,
+    hipLaunchKernelGGL((gen_g1_kernel<MODE>), dim3((n2 + 3) / 4), dim3(256), 0, c->stream, g.ipart,
                        g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1, g.icoll, cb, cc, g.nbp, g.nb,
                        c->dflag);
     HIP_OK(c, hipGetLastError());
