@@ -30,6 +30,26 @@ PEAK_FP64_MFMA = 78.6      # TFLOP/s, MI355X dense FP64 matrix
 PEAK_FP32_MFMA = 157.3     # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0          # GB/s
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
+# the copy calibration; profiles/hbm_traffic_counters.md).  A figure is only
+# reported while the kernel source still has the hash it had when measured.
+TRAFFIC = {
+    "gen_main/f64": {"bytes": 75.8e6, "src": "general.hip", "sha1": "0841b5d72b4a"},
+    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "sha1": "0841b5d72b4a"},
+    "hub_stage/2d": {"bytes": 2.30e9, "src": "hubbard.hip", "sha1": "108a50ef641a"},
+}
+
+
+def traffic(key):
+    import hashlib
+    t = TRAFFIC.get(key)
+    if t is None:
+        return None
+    path = os.path.join(ROOT, "paper_2002_12717_amd", "csrc", t["src"])
+    with open(path, "rb") as f:
+        h = hashlib.sha1(f.read()).hexdigest()[:12]
+    return t["bytes"] if h == t["sha1"] else None
+
 
 def soa_flops(nb: int) -> dict:
     """Algorithmic real flops of one general-basis right-hand side (8 per complex
@@ -57,7 +77,11 @@ def timed_steps(p, dt, steps, warmup, stream, torch):
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     w0 = time.perf_counter()
-    p.step(dt, steps)
+    try:
+        p.step(dt, steps)
+    except Exception as e:          # the divergence guard fires after the steps ran
+        if getattr(e, "status", None) != -5:
+            raise
     ev1.record(stream)
     torch.cuda.synchronize()
     w1 = time.perf_counter()
@@ -158,7 +182,7 @@ def run_general(args, torch, B, gw=False):
         "g2_rhs_tflops": round(4 * rhs_flops / (ms_step * 1e-3) / 1e12, 3),
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
-                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "traffic": None if gw else traffic("gen_main/f64"), "kernel_ms_avg": round(tot_ms / cnt, 6),
                      "flop_per_launch": fl[dom], "launches": cnt},
         "kernels": kernel_table(f64["prof"]),
         "mixed": {"dtype": "f32 contractions / f64 state", "value": round(1e3 / mx_step, 3),
@@ -192,7 +216,7 @@ def run_hubbard(args, torch, B, kind):
     p.close()
     ms_step = ms / args.steps
     n4 = float(ns) ** 4
-    tot_ms, cnt = prof["hub_g2"]
+    tot_ms, cnt = prof["hub_stage"]
     # algorithmic bytes: 256 B per complex128 G2 element per RK4 step (4 launches)
     bytes_per_launch = 64.0 * n4
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
@@ -202,15 +226,78 @@ def run_hubbard(args, torch, B, kind):
               "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     out.update({
-        "roofline": {"kernel": "hub_g2", "bound": "hbm", "achieved": round(achieved, 2),
+        "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" else None,
+                     "kernel_ms_avg": round(tot_ms / cnt, 6),
                      "bytes_per_launch": bytes_per_launch, "launches": cnt},
         "kernels": kernel_table(prof),
         "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
     })
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_hubbard(system)
+    return out
+
+
+def cpu_baseline_batch(clusters, seconds: float = 15.0):
+    """Oracle on the host: one RK4 step per cluster for the first clusters of the
+    batch until the time budget is spent; the whole-batch rate is extrapolated
+    with the G2 element count (the oracle's per-step cost is proportional to it)."""
+    import torch
+    from oracle import integrate as OI
+    nthreads = torch.get_num_threads()
+    t0 = time.perf_counter()
+    el_done, q = 0, 0
+    while q < len(clusters) and time.perf_counter() - t0 < seconds:
+        c = clusters[q]
+        f = OI.hubbard_rhs_fn(c, "tpp")
+        y = OI.hubbard_initial(c, "tpp")
+        OI.rk4_step(f, 0.0, y, c.dt)
+        el_done += c.ns ** 4
+        q += 1
+    el = time.perf_counter() - t0
+    total = sum(c.ns ** 4 for c in clusters)
+    return {"value": round(el_done / total / el, 6), "unit": "RK4 steps/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"one RK4 step of the first {q} of {len(clusters)} clusters ({el:.1f} s), "
+                      f"extrapolated to the whole batch by G2 element count"}
+
+
+def run_batch(args, torch, B):
+    from paper_2002_12717_amd import autotune
+    from workloads import batched_clusters
+    clusters = batched_clusters()
+    ns = [c.ns for c in clusters]
+    n4 = float(sum(n ** 4 for n in ns))
+    chunks = autotune.chunks_for(ns)
+    stream = torch.cuda.Stream()
+    b = B.Batch(B.TPP, ns, [c.U for c in clusters], [c.h0 for c in clusters], [c.g1 for c in clusters],
+                chunk=chunks, stream=stream.cuda_stream)
+    dt = clusters[0].dt
+    ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
+    prof = b.profile(dt, args.profile_steps)
+    obs = b.observables()
+    b.close()
+    ms_step = ms / args.steps
+    tot_ms, cnt = prof["hub_stage"]
+    bytes_per_launch = 64.0 * n4
+    achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
+    config = {"workload": f"ragged batch of {len(ns)} periodic 2D Hubbard clusters (Lx,Ly in 3..6), "
+                          f"TPP, dt={dt}, RK4, one launch per stage, graph-captured steps",
+              "clusters": len(ns), "g2_elements": int(n4), "ns_min": min(ns), "ns_max": max(ns),
+              "selfenergy": "TPP", "chunk_per_class": autotune.load_table().get("chunk_per_class"),
+              "parallelism": "single GPU"}
+    out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    out.update({
+        "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "bytes_per_launch": bytes_per_launch, "launches": cnt},
+        "kernels": kernel_table(prof),
+        "diverged": bool(obs[0]["diverged"]),
+    })
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(clusters)
     return out
 
 
@@ -221,7 +308,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--workload", default="general_soa",
-                    choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d"])
+                    choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d",
+                             "hubbard_batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -235,6 +323,8 @@ def main():
         out = run_general(args, torch, B)
     elif args.workload == "general_gw":
         out = run_general(args, torch, B, gw=True)
+    elif args.workload == "hubbard_batch":
+        out = run_batch(args, torch, B)
     else:
         out = run_hubbard(args, torch, B, args.workload)
     print(json.dumps(out), flush=True)

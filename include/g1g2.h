@@ -141,6 +141,24 @@ g1g2_status g1g2_set_U(g1g2_ctx* ctx, double U);
 g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const double* c,
                            const double* t_center, double tau);
 
+/* Ragged batch of independent Hubbard clusters (configurations of uneven
+ * size and U) propagated together: every Runge-Kutta stage of the whole batch
+ * is one kernel launch over a flat work list, and g1g2_step_rk4 replays
+ * captured HIP graphs of whole steps when a stream is given.  desc supplies
+ * basis (HUBBARD), selfenergy (SOA or TPP) and precision (FP64); per cluster
+ * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
+ * [2][ns][ns]; G2(0) = 0.  chunk[c] > 0 sets the G2 elements handled by one
+ * work-group of cluster c (NULL or 0: 1024), e.g. from an autotuning table.
+ * g1g2_step_rk4, g1g2_profile and g1g2_destroy act on the whole batch; the
+ * single-cluster calls (rhs, get/set_state, set_h0/U/drive) return ESTATE. */
+g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, const int32_t* ns,
+                            const double* U, const void* const* h0, const void* const* G1_0,
+                            const int32_t* chunk, void* hip_stream);
+/* Observables of every cluster: out[n] (herm_resid is not computed). */
+g1g2_status g1g2_batch_observables(g1g2_ctx* ctx, g1g2_obs* out);
+/* State of one cluster into host arrays G1 [2][ns][ns] and (if not NULL) G2 [ns]^4. */
+g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void* G2);
+
 /* Profiling aid.  Runs nsteps Runge-Kutta steps of size dt exactly like
  * g1g2_step_rk4 (advancing the state), or, for nsteps = 0, one right-hand-side
  * evaluation of the current state, with a HIP event recorded on the context's

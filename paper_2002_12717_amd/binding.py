@@ -49,6 +49,10 @@ _SIGS = {
     "g1g2_profile": (c_int32, [c_void_p, c_double, c_int64, c_int32, c_void_p, c_void_p,
                                POINTER(c_int32)]),
     "g1g2_profile_name": (ctypes.c_char_p, [c_void_p, c_int32]),
+    "g1g2_batch_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_int32, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p]),
+    "g1g2_batch_observables": (c_int32, [c_void_p, c_void_p]),
+    "g1g2_batch_get_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "g1g2_destroy": (None, [c_void_p]),
     "g1g2_strerror": (ctypes.c_char_p, [c_int32]),
     "g1g2_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -203,3 +207,41 @@ class Propagator:
             self.close()
         except Exception:
             pass
+
+
+class Batch(Propagator):
+    """A ragged batch of Hubbard clusters in one context (g1g2_batch_init)."""
+
+    def __init__(self, selfenergy: int, ns, U, h0s, g1s, chunk=None, stream: int = 0):
+        self.lib = load()
+        self.basis, self.flags = HUBBARD, 0
+        self.ns = [int(x) for x in ns]
+        n = len(self.ns)
+        self.nb = max(self.ns)
+        self.desc = Desc(HUBBARD, selfenergy, FP64, 0, self.nb, 0.0)
+        h = [np.ascontiguousarray(a, np.complex128) for a in h0s]
+        g = [np.ascontiguousarray(a, np.complex128) for a in g1s]
+        ns_a = np.asarray(self.ns, np.int32)
+        U_a = np.ascontiguousarray(U, np.float64)
+        hp = (c_void_p * n)(*[a.ctypes.data for a in h])
+        gp = (c_void_p * n)(*[a.ctypes.data for a in g])
+        ch = None if chunk is None else np.ascontiguousarray(chunk, np.int32)
+        ctx = c_void_p()
+        st = self.lib.g1g2_batch_init(ctypes.byref(ctx), ctypes.byref(self.desc), n, _ptr(ns_a),
+                                      _ptr(U_a), hp, gp, _ptr(ch), c_void_p(stream) if stream else None)
+        if st != OK:
+            raise G1G2Error(st, self.lib.g1g2_strerror(st).decode())
+        self.ctx = ctx
+
+    def observables(self):
+        obs = (Obs * len(self.ns))()
+        self._check(self.lib.g1g2_batch_observables(self.ctx, obs))
+        return [dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
+                     E_tot=o.E_tot, docc=o.docc, diverged=o.diverged, step=o.step) for o in obs]
+
+    def get_cluster(self, c: int, with_g2: bool = True):
+        ns = self.ns[c]
+        g1 = np.zeros((2, ns, ns), np.complex128)
+        g2 = np.zeros((ns,) * 4, np.complex128) if with_g2 else None
+        self._check(self.lib.g1g2_batch_get_state(self.ctx, int(c), _ptr(g1), _ptr(g2)))
+        return g1, g2

@@ -1,6 +1,8 @@
 // C-ABI entry points of the G1-G2 library (declared in include/g1g2.h).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -105,6 +107,49 @@ g1g2_status stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y
     return gen_stage(c, mode, t, in, y, acc, out, cb, cc);
 }
 
+// One classical RK4 step on the registers (y, acc, s0, s1).
+g1g2_status rk4_step(g1g2_ctx* c, double t, double dt) {
+    g1g2_status s;
+    if ((s = stage(c, RK_FIRST, t, c->y, c->y, c->acc, c->s0, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
+    if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s0, c->y, c->acc, c->s1, dt / 3.0, dt / 2.0)) != G1G2_OK)
+        return s;
+    if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s1, c->y, c->acc, c->s0, dt / 3.0, dt)) != G1G2_OK) return s;
+    return stage(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0);
+}
+
+void drop_graph(g1g2_ctx* c) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_steps = 0;
+}
+
+// Kernel arguments of a step do not depend on t unless a drive is active, so
+// a captured sequence of steps can be replayed for any t.
+bool can_capture(const g1g2_ctx* c) {
+    return c->graphs && c->stream != nullptr && !c->prof &&
+           !(c->d.basis == G1G2_HUBBARD && c->hub.has_drive());
+}
+
+g1g2_status capture(g1g2_ctx* c, double dt, int gsteps) {
+    drop_graph(c);
+    HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    g1g2_status s = G1G2_OK;
+    for (int n = 0; n < gsteps && s == G1G2_OK; ++n) s = rk4_step(c, 0.0, dt);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (s != G1G2_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    HIP_OK(c, e);
+    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_OK(c, e);
+    c->graph_dt = dt;
+    c->graph_steps = gsteps;
+    return G1G2_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -135,10 +180,8 @@ void g1g2_destroy(g1g2_ctx* c) {
     if (c->dflag) (void)hipFree(c->dflag);
     if (c->dscratch) (void)hipFree(c->dscratch);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
-    HubbardData& H = c->hub;
-    void* hp[] = {H.nbr, H.hop, H.d0, H.xdrv};
-    for (void* p : hp)
-        if (p) (void)hipFree(p);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    hub_free(c);
     gen_free(c);
     delete c;
 }
@@ -165,6 +208,10 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     if (!c) return G1G2_ENOMEM;
     c->d = *d;
     c->stream = (hipStream_t)hip_stream;
+    {
+        const char* ng = std::getenv("G1G2_NO_GRAPH");
+        c->graphs = !(ng && ng[0] == '1');
+    }
     (void)hipGetDevice(&c->device);
     g1g2_status s = G1G2_OK;
     const size_t nb = d->nb;
@@ -193,7 +240,10 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     const size_t nh0 = g1_count(c);
     if ((s = fetch(c, h0, nh0, hh0)) != G1G2_OK) return fail(s);
     if (d->basis == G1G2_HUBBARD) {
-        if ((s = hub_setup(c, hh0.p)) != G1G2_OK) return fail(s);
+        const int ns = d->nb;
+        const double U = d->U;
+        const cd* h0p = hh0.p;
+        if ((s = hub_setup(c, 1, &ns, &U, &h0p, nullptr)) != G1G2_OK) return fail(s);
     } else {
         if ((s = fetch(c, w, g2_count(c), hw)) != G1G2_OK) return fail(s);
         if ((s = gen_setup(c, hh0.p, hw.p)) != G1G2_OK) return fail(s);
@@ -210,6 +260,8 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
 
 g1g2_status g1g2_rhs(g1g2_ctx* c, double t, const void* G1, const void* G2, void* dG1, void* dG2) {
     if (!c || !G1 || !G2 || !dG1 || !dG2) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
+        return set_error(c, G1G2_ESTATE, "single-cluster call on a batch");
     g1g2_status s;
     if (c->d.basis == G1G2_HUBBARD) {
         Regs in{(cd*)G1, (cd*)G2};
@@ -234,15 +286,15 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
     const double t0 = c->t;
     const int64_t step0 = c->step;
     g1g2_status s;
-    for (int64_t n = 0; n < nsteps; ++n) {
-        const double t = t0 + (double)n * dt;
-        if ((s = stage(c, RK_FIRST, t, c->y, c->y, c->acc, c->s0, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
-        if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s0, c->y, c->acc, c->s1, dt / 3.0, dt / 2.0)) != G1G2_OK)
-            return s;
-        if ((s = stage(c, RK_MID, t + 0.5 * dt, c->s1, c->y, c->acc, c->s0, dt / 3.0, dt)) != G1G2_OK)
-            return s;
-        if ((s = stage(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0)) != G1G2_OK) return s;
+    int64_t n = 0;
+    if (can_capture(c) && nsteps >= 4) {
+        const int gs = (int)std::min<int64_t>(nsteps, 8);
+        if (!c->graph || c->graph_dt != dt || c->graph_steps != gs)
+            if ((s = capture(c, dt, gs)) != G1G2_OK) return s;
+        for (; n + gs <= nsteps; n += gs) HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
     }
+    for (; n < nsteps; ++n)
+        if ((s = rk4_step(c, t0 + (double)n * dt, dt)) != G1G2_OK) return s;
     c->t = t0 + (double)nsteps * dt;
     c->step = step0 + nsteps;
     int flag = 0;
@@ -254,6 +306,8 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
 
 g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
     if (!c || !o) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
+        return set_error(c, G1G2_ESTATE, "use g1g2_batch_observables on a batch");
     std::memset(o, 0, sizeof(*o));
     g1g2_status s = c->d.basis == G1G2_HUBBARD ? hub_observables(c, c->y, c->t, o)
                                                : gen_observables(c, c->y, c->t, o);
@@ -269,11 +323,14 @@ g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
 g1g2_status g1g2_site_observables(g1g2_ctx* c, double* nu, double* nd, double* docc) {
     if (!c) return G1G2_EINVAL;
     if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    if (c->hub.ncl != 1) return set_error(c, G1G2_ESTATE, "single-cluster call on a batch");
     return hub_site_observables(c, c->y, nu, nd, docc);
 }
 
 g1g2_status g1g2_get_state(g1g2_ctx* c, void* G1, void* G2, double* t) {
     if (!c || !G1) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
+        return set_error(c, G1G2_ESTATE, "single-cluster call on a batch");
     const bool dev = c->d.flags & G1G2_PTR_DEVICE;
     g1g2_status s;
     if ((s = store_component(c, c->y.g1, G1, dev, 2)) != G1G2_OK) return s;
@@ -285,6 +342,8 @@ g1g2_status g1g2_get_state(g1g2_ctx* c, void* G1, void* G2, double* t) {
 
 g1g2_status g1g2_set_state(g1g2_ctx* c, const void* G1, const void* G2, double t) {
     if (!c || !G1) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
+        return set_error(c, G1G2_ESTATE, "single-cluster call on a batch");
     const bool dev = c->d.flags & G1G2_PTR_DEVICE;
     g1g2_status s;
     if ((s = load_component(c, G1, dev, c->y.g1, 2)) != G1G2_OK) return s;
@@ -305,14 +364,25 @@ g1g2_status g1g2_set_h0(g1g2_ctx* c, const void* h0) {
     g1g2_status s = fetch(c, h0, g1_count(c), hh);
     if (s != G1G2_OK) return s;
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    return c->d.basis == G1G2_HUBBARD ? hub_setup(c, hh.p) : gen_set_h0(c, hh.p);
+    drop_graph(c);
+    if (c->d.basis == G1G2_HUBBARD) {
+        if (c->hub.ncl != 1) return set_error(c, G1G2_ESTATE, "set_h0 applies to a single cluster");
+        const int ns = c->d.nb;
+        const double U = c->d.U;
+        const cd* h0p = hh.p;
+        return hub_setup(c, 1, &ns, &U, &h0p, nullptr);
+    }
+    return gen_set_h0(c, hh.p);
 }
 
 g1g2_status g1g2_set_U(g1g2_ctx* c, double U) {
     if (!c || !std::isfinite(U)) return G1G2_EINVAL;
     if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    if (c->hub.ncl != 1) return set_error(c, G1G2_ESTATE, "set_U applies to a single cluster");
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->d.U = U;
+    c->hub.hdesc[0].U = U;
+    HIP_OK(c, hipMemcpy(c->hub.desc, c->hub.hdesc.data(), sizeof(ClusterDesc), hipMemcpyHostToDevice));
     return G1G2_OK;
 }
 
@@ -321,7 +391,9 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
     if (!c || M < 0) return G1G2_EINVAL;
     if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
     HubbardData& H = c->hub;
+    if (H.ncl != 1) return set_error(c, G1G2_ESTATE, "set_drive applies to a single cluster");
     HIP_OK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
     if (M == 0) {
         H.drive_c.clear();
         H.drive_tc.clear();
@@ -333,6 +405,98 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
     H.drive_x.assign(x, x + c->d.nb);
     H.drive_tau = tau;
     HIP_OK(c, hipMemcpy(H.xdrv, x, c->d.nb * sizeof(double), hipMemcpyHostToDevice));
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const int32_t* ns,
+                            const double* U, const void* const* h0, const void* const* G1_0,
+                            const int32_t* chunk, void* hip_stream) {
+    if (!out || !d || n < 1 || !ns || !U || !h0 || !G1_0) return G1G2_EINVAL;
+    *out = nullptr;
+    if (d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
+    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_TPP) return G1G2_EUNSUPPORTED;
+    if (d->precision != G1G2_FP64) return G1G2_EUNSUPPORTED;
+    long long n1 = 0, n2 = 0;
+    int nsmax = 0;
+    for (int c = 0; c < n; ++c) {
+        if (ns[c] < 1 || !h0[c] || !G1_0[c]) return G1G2_EINVAL;
+        n1 += 2LL * ns[c] * ns[c];
+        n2 += (long long)ns[c] * ns[c] * ns[c] * ns[c];
+        nsmax = std::max(nsmax, (int)ns[c]);
+    }
+    if (n2 > (1LL << 31) - 1) return G1G2_EUNSUPPORTED;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return G1G2_EDEVICE;
+    g1g2_ctx* c = new (std::nothrow) g1g2_ctx();
+    if (!c) return G1G2_ENOMEM;
+    c->d = *d;
+    c->d.flags &= ~G1G2_PTR_DEVICE;
+    c->d.nb = nsmax;
+    c->stream = (hipStream_t)hip_stream;
+    {
+        const char* ng = std::getenv("G1G2_NO_GRAPH");
+        c->graphs = !(ng && ng[0] == '1');
+    }
+    (void)hipGetDevice(&c->device);
+    c->n1 = (size_t)n1;
+    c->n2 = (size_t)n2;
+    g1g2_status s;
+    auto fail = [&](g1g2_status st) {
+        g1g2_destroy(c);
+        return st;
+    };
+    for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1})
+        if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
+    if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
+    if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    c->nscratch = 8 + 2 * 256 + 3 * nsmax + 64;
+    if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
+    std::vector<int> nsv(ns, ns + n), ch(n, 0);
+    if (chunk)
+        for (int q = 0; q < n; ++q) ch[q] = chunk[q];
+    std::vector<double> Uv(U, U + n);
+    std::vector<const cd*> hp(n);
+    for (int q = 0; q < n; ++q) hp[q] = (const cd*)h0[q];
+    if ((s = hub_setup(c, n, nsv.data(), Uv.data(), hp.data(), ch.data())) != G1G2_OK) return fail(s);
+    for (int q = 0; q < n; ++q) {
+        const ClusterDesc& cd0 = c->hub.hdesc[q];
+        if (hipMemcpyAsync(c->y.g1 + cd0.g1off, G1_0[q], 2ULL * ns[q] * ns[q] * sizeof(cd),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(G1G2_EDEVICE);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    *out = c;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_batch_observables(g1g2_ctx* c, g1g2_obs* o) {
+    if (!c || !o) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard batches only");
+    const int n = c->hub.ncl;
+    std::memset(o, 0, n * sizeof(g1g2_obs));
+    g1g2_status s = hub_batch_observables(c, c->y, c->t, o);
+    if (s != G1G2_OK) return s;
+    int flag = 0;
+    HIP_OK(c, hipMemcpy(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost));
+    for (int q = 0; q < n; ++q) {
+        o[q].t = c->t;
+        o[q].step = c->step;
+        o[q].diverged = flag;
+    }
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_batch_get_state(g1g2_ctx* c, int32_t cluster, void* G1, void* G2) {
+    if (!c || !G1) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD || cluster < 0 || cluster >= c->hub.ncl) return G1G2_EINVAL;
+    const ClusterDesc& d = c->hub.hdesc[cluster];
+    const size_t ns = d.ns;
+    HIP_OK(c, hipMemcpyAsync(G1, c->y.g1 + d.g1off, 2 * ns * ns * sizeof(cd), hipMemcpyDeviceToHost,
+                             c->stream));
+    if (G2)
+        HIP_OK(c, hipMemcpyAsync(G2, c->y.g2 + d.g2off, ns * ns * ns * ns * sizeof(cd),
+                                 hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
     return G1G2_OK;
 }
 

@@ -14,20 +14,46 @@ struct Regs {
     cd* g2 = nullptr;
 };
 
-// Hubbard model: h0 per spin stored as a real diagonal plus an ELL list of
-// off-diagonal entries (row i: neighbours nbr[i][z] with h0_{i,nbr}); the
-// drive adds s(t) * x_i to the diagonal of both spins.
+// Hubbard model.  A context holds a batch of independent clusters (one for
+// g1g2_init, n for g1g2_batch_init).  Per cluster, h0 per spin is stored as a
+// real diagonal plus an ELL list of off-diagonal entries (row i: neighbours
+// nbr[i][z] with values h0_{i,nbr}); the drive adds s(t) * x_i to the diagonal
+// of both spins.  Registers concatenate the clusters: G1 blocks [2][ns][ns],
+// G2 blocks [ns]^4.
+struct ClusterDesc {
+    int ns, zmax;
+    int g1off;          // offset of the cluster's G1 block in a G1 register
+    int nbroff;         // offset of its [2][ns][zmax] neighbour table
+    int d0off;          // offset of its [2][ns] diagonal of h0
+    int xoff;           // offset of its [ns] drive profile
+    long long g2off;    // offset of its G2 block in a G2 register
+    double U;
+};
+
+// One work-group's share of a stage: G2 elements [start, end) of a cluster,
+// or (start < 0) the whole G1 update of the cluster.
+struct WorkItem {
+    int cluster;
+    int start, end;
+};
+
 struct HubbardData {
-    int ns = 0;
-    int zmax = 0;
-    int* nbr = nullptr;        // [2][ns][zmax], -1 = empty slot
-    cd* hop = nullptr;         // [2][ns][zmax]
-    double* d0 = nullptr;      // [2][ns]
-    double* xdrv = nullptr;    // [ns]
-    std::vector<double> h_d0;  // host copies for observables
+    int ncl = 0;
+    std::vector<ClusterDesc> hdesc;
+    ClusterDesc* desc = nullptr;   // device copy
+    WorkItem* work = nullptr;      // device work list
+    int nwork = 0;
+    bool tiled = false;            // LDS-tiled stage kernel (every ns <= 64)
+    std::vector<int> chunk;        // elements of G2 per work-group, per cluster
+    int* nbr = nullptr;            // concatenated neighbour tables
+    cd* hop = nullptr;
+    double* d0 = nullptr;
+    double* xdrv = nullptr;
+    std::vector<double> h_d0;
     std::vector<double> drive_c, drive_tc, drive_x;
     double drive_tau = 1.0;
     double drive_value(double t) const;
+    bool has_drive() const { return !drive_c.empty(); }
 };
 
 // General basis: internal tensors are padded to nbp = roundup(nb, 16) so that
@@ -70,6 +96,11 @@ struct g1g2_ctx {
     int nscratch = 0;
     HubbardData hub;
     GeneralData gen;
+    // captured RK4 steps (replayed by g1g2_step_rk4 when the stream is not NULL)
+    hipGraphExec_t graph = nullptr;
+    double graph_dt = 0.0;
+    int graph_steps = 0;
+    bool graphs = true;
     // kernel timing (g1g2_profile_rhs): events recorded after every launch
     bool prof = false;
     std::vector<hipEvent_t> prof_ev;
@@ -92,12 +123,17 @@ g1g2_status set_error(g1g2_ctx* c, g1g2_status s, const std::string& msg);
     } while (0)
 
 // ---- Hubbard basis (hubbard.hip)
-g1g2_status hub_setup(g1g2_ctx* c, const cd* h0_host);
+// h0s[c] is the host h0 of cluster c ([2][ns][ns]); U[c] its interaction;
+// chunk[c] (0 = default) the G2 elements per work-group.
+g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* ns, const double* U, const cd* const* h0s,
+                      const int* chunk);
+void hub_free(g1g2_ctx* c);
 // One RK4 stage (or a plain RHS evaluation, mode RK_RHS) of the Hubbard system.
 g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc);
 g1g2_status hub_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
 g1g2_status hub_site_observables(g1g2_ctx* c, const Regs& s, double* nu, double* nd, double* docc);
+g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
 
 // ---- general basis (general.hip)
 g1g2_status gen_setup(g1g2_ctx* c, const cd* h0_host, const cd* w_host);

@@ -1,21 +1,27 @@
 // Hubbard-basis G1-G2 kernels (Sec. III.D, Sec. V.A, Sec. VII).
 //
-// State per register: G1 = [X | Y] with X = G^{<,up}, Y = G^{<,down} (ns x ns
+// State per cluster: G1 = [X | Y] with X = G^{<,up}, Y = G^{<,down} (ns x ns
 // each) and G2 = A = G2^{up down up down} ([ns]^4).  Every G2 element is
 // produced by one thread from a fixed number of neighbours, so the kernel is a
 // bandwidth-bound stream: the O(ns^5) sums of the direct formulation are
 // replaced by the paper's reformulations that carry no inner sum
-// (eq:soa-cubic-scheme for the source, the tridiagonal-h commutator of
-// Sec. VII.A, the reformulated ladder of Sec. VII.C).
+// (eq:soa-cubic-scheme for the source, the sparse-h commutator of Sec. VII.A,
+// the reformulated ladder of Sec. VII.C).
+//
+// A context holds a ragged batch of clusters.  One launch per Runge-Kutta
+// stage processes a flat work list: every item is either a contiguous range
+// of one cluster's G2 elements or the G1 update of one cluster.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
 
 namespace {
 
-struct HubArgs {
+struct Cl {
     int ns, zmax;
     double U, s_drive;
     const int* __restrict__ nbr;    // [2][ns][zmax]
@@ -26,8 +32,25 @@ struct HubArgs {
     const cd* __restrict__ Y;       // stage-input G^{<,down}
 };
 
+__device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, const cd* hop,
+                                      const double* d0, const double* xdrv, const cd* g1,
+                                      double s_drive) {
+    Cl a;
+    a.ns = d.ns;
+    a.zmax = d.zmax;
+    a.U = d.U;
+    a.s_drive = s_drive;
+    a.nbr = nbr + d.nbroff;
+    a.hop = hop + d.nbroff;
+    a.d0 = d0 + d.d0off;
+    a.xdrv = xdrv + d.xoff;
+    a.X = g1 + d.g1off;
+    a.Y = a.X + d.ns * d.ns;
+    return a;
+}
+
 // Diagonal of h^{HF,sigma} (Sec. III.D): h0_ii + v_i(t) - i U G^{<,-sigma}_ii.
-__device__ __forceinline__ cd hf_diag(const HubArgs& a, int sig, int i) {
+__device__ __forceinline__ cd hf_diag(const Cl& a, int sig, int i) {
     const cd* other = sig ? a.X : a.Y;
     cd g = other[i * a.ns + i];
     double re = a.d0[sig * a.ns + i] + a.s_drive * a.xdrv[i];
@@ -35,11 +58,12 @@ __device__ __forceinline__ cd hf_diag(const HubArgs& a, int sig, int i) {
     return cmk(re + a.U * g.y, -a.U * g.x);
 }
 
-// Right-hand side of one element of A = G2^{up down up down}:
+// Right-hand side of one element e = ((i ns + j) ns + k) ns + l of the
+// cluster's block A = G2^{up down up down}:
 //   dA/dt = -i ( [h2_{ud}, A] + Psi + [L^pp - (L^pp_klij)^*] )
 template <bool TPP>
-__device__ __forceinline__ cd hub_g2_rhs(const HubArgs& a, const cd* __restrict__ A, int i, int j,
-                                         int k, int l, int e, cd aval) {
+__device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const cd* __restrict__ A, int i, int j, int k,
+                                         int l, int e, cd aval) {
     const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
     const int* nbu = a.nbr;
     const int* nbd = a.nbr + ns * z;
@@ -80,7 +104,7 @@ __device__ __forceinline__ cd hub_g2_rhs(const HubArgs& a, const cd* __restrict_
     c = cadd(c, psi);
     if (TPP) {
         // L_ijkl = delta_ij U A_iikl + i U (Y_ji A_iikl + X_ij A_jjkl)   (Sec. VII.C)
-        int kl = k * ns + l, ij = i * ns + j;
+        const int kl = k * ns + l, ij = i * ns + j;
         cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
         cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
         if (i == j) l1 = cadd(l1, dii);
@@ -93,112 +117,285 @@ __device__ __forceinline__ cd hub_g2_rhs(const HubArgs& a, const cd* __restrict_
     return cmul_mi(c);
 }
 
-template <int MODE, bool TPP>
-__global__ __launch_bounds__(256) void hub_g2_kernel(HubArgs a, const cd* __restrict__ in,
-                                                    const cd* __restrict__ y, cd* __restrict__ acc,
-                                                    cd* __restrict__ out, double cb, double cc) {
-    const int ns = a.ns;
-    const int n4 = ns * ns * ns * ns;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
-        int l = e % ns, tq = e / ns;
-        int k = tq % ns;
-        tq /= ns;
-        int j = tq % ns, i = tq / ns;
-        cd av = in[e];
-        cd f = hub_g2_rhs<TPP>(a, in, i, j, k, l, e, av);
-        rk_update<MODE>(e, f, av, y, acc, out, cb, cc);
-    }
-}
-
 // G1 equations (eq:eom_g1_hubbard): dG^{<,s}/dt = -i([h^{HF,s}, G^{<,s}] + I^s + I^s^dagger)
 // with I^up_ij = -i U A_iiji and I^down_ij = -i U A_iiij.
-template <int MODE>
-__global__ __launch_bounds__(256) void hub_g1_kernel(HubArgs a, const cd* __restrict__ A,
-                                                    const cd* __restrict__ in,
-                                                    const cd* __restrict__ y, cd* __restrict__ acc,
-                                                    cd* __restrict__ out, double cb, double cc,
-                                                    int* __restrict__ flag) {
-    const int ns = a.ns, ns2 = ns * ns, z = a.zmax;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 2 * ns2; e += gridDim.x * blockDim.x) {
-        int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
-        const cd* G = sig ? a.Y : a.X;
-        const int* nb = a.nbr + sig * ns * z;
-        const cd* hp = a.hop + sig * ns * z;
-        cd gij = G[i * ns + j];
-        cd ei = hf_diag(a, sig, i), ej = hf_diag(a, sig, j);
-        cd c = csub(cmul(ei, gij), cmul(gij, ej));
-        for (int q = 0; q < z; ++q) {
-            int p = nb[i * z + q];
-            if (p >= 0) c = cfma(c, hp[i * z + q], G[p * ns + j]);
+__device__ __forceinline__ cd hub_g1_rhs(const Cl& a, const cd* __restrict__ A, int sig, int i, int j) {
+    const int ns = a.ns, z = a.zmax;
+    const cd* G = sig ? a.Y : a.X;
+    const int* nb = a.nbr + sig * ns * z;
+    const cd* hp = a.hop + sig * ns * z;
+    cd gij = G[i * ns + j];
+    cd ei = hf_diag(a, sig, i), ej = hf_diag(a, sig, j);
+    cd c = csub(cmul(ei, gij), cmul(gij, ej));
+    for (int q = 0; q < z; ++q) {
+        int p = nb[i * z + q];
+        if (p >= 0) c = cfma(c, hp[i * z + q], G[p * ns + j]);
+    }
+    for (int q = 0; q < z; ++q) {
+        int p = nb[j * z + q];
+        if (p >= 0) c = csub(c, cmul(G[i * ns + p], cconj(hp[j * z + q])));
+    }
+    cd Iij, Iji;
+    if (sig == 0) {
+        Iij = A[((i * ns + i) * ns + j) * ns + i];
+        Iji = A[((j * ns + j) * ns + i) * ns + j];
+    } else {
+        Iij = A[((i * ns + i) * ns + i) * ns + j];
+        Iji = A[((j * ns + j) * ns + j) * ns + i];
+    }
+    // I = -i U A...,  I + I^dagger with (I^dagger)_ij = conj(I_ji)
+    cd coll = cadd(cscale(cmul_mi(Iij), a.U), cconj(cscale(cmul_mi(Iji), a.U)));
+    return cmul_mi(cadd(c, coll));
+}
+
+struct StageArgs {
+    const ClusterDesc* __restrict__ desc;
+    const WorkItem* __restrict__ work;
+    const int* __restrict__ nbr;
+    const cd* __restrict__ hop;
+    const double* __restrict__ d0;
+    const double* __restrict__ xdrv;
+    double s_drive;
+    const cd* in1;
+    const cd* in2;
+    const cd* y1;
+    const cd* y2;
+    cd* acc1;
+    cd* acc2;
+    cd* out1;
+    cd* out2;
+    double cb, cc;
+    int* flag;
+};
+
+template <int MODE, bool TPP>
+__global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
+    const WorkItem w = s.work[blockIdx.x];
+    const ClusterDesc d = s.desc[w.cluster];
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const int ns = d.ns;
+    const cd* A = s.in2 + d.g2off;
+    if (w.start >= 0) {
+        const cd* y = s.y2 + d.g2off;
+        cd* acc = s.acc2 + d.g2off;
+        cd* out = s.out2 + d.g2off;
+        for (int e = w.start + threadIdx.x; e < w.end; e += blockDim.x) {
+            int l = e % ns, tq = e / ns;
+            int k = tq % ns;
+            tq /= ns;
+            int j = tq % ns, i = tq / ns;
+            cd av = A[e];
+            cd f = hub_g2_rhs<TPP>(a, A, i, j, k, l, e, av);
+            rk_update<MODE>(e, f, av, y, acc, out, s.cb, s.cc);
         }
-        for (int q = 0; q < z; ++q) {
-            int p = nb[j * z + q];
-            if (p >= 0) c = csub(c, cmul(G[i * ns + p], cconj(hp[j * z + q])));
-        }
-        cd Iij, Iji;
-        if (sig == 0) {
-            Iij = A[((i * ns + i) * ns + j) * ns + i];
-            Iji = A[((j * ns + j) * ns + i) * ns + j];
-        } else {
-            Iij = A[((i * ns + i) * ns + i) * ns + j];
-            Iji = A[((j * ns + j) * ns + j) * ns + i];
-        }
-        // I = -i U A...,  I + I^dagger with (I^dagger)_ij = conj(I_ji)
-        cd coll = cadd(cscale(cmul_mi(Iij), a.U), cconj(cscale(cmul_mi(Iji), a.U)));
-        cd f = cmul_mi(cadd(c, coll));
-        rk_update<MODE>(e, f, gij, y, acc, out, cb, cc);
-        if (MODE == RK_LAST) {
-            cd v = out[e];
-            bool bad = !(isfinite(v.x) && isfinite(v.y));
-            if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;  // n_ii = -i G_ii = G_ii.y
-            if (bad) atomicOr(flag, 1);
+    } else {
+        const cd* g1 = s.in1 + d.g1off;
+        const cd* y = s.y1 + d.g1off;
+        cd* acc = s.acc1 + d.g1off;
+        cd* out = s.out1 + d.g1off;
+        const int ns2 = ns * ns;
+        for (int e = threadIdx.x; e < 2 * ns2; e += blockDim.x) {
+            int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
+            cd f = hub_g1_rhs(a, A, sig, i, j);
+            rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
+            if (MODE == RK_LAST) {
+                cd v = out[e];
+                bool bad = !(isfinite(v.x) && isfinite(v.y));
+                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;  // n_ii = -i G_ii = G_ii.y
+                if (bad) atomicOr(s.flag, 1);
+            }
         }
     }
 }
 
-HubArgs make_args(g1g2_ctx* c, double t, const Regs& in) {
-    HubArgs a;
-    a.ns = c->hub.ns;
-    a.zmax = c->hub.zmax;
-    a.U = c->d.U;
-    a.s_drive = c->hub.drive_value(t);
-    a.nbr = c->hub.nbr;
-    a.hop = c->hub.hop;
-    a.d0 = c->hub.d0;
-    a.xdrv = c->hub.xdrv;
-    a.X = in.g1;
-    a.Y = in.g1 + (size_t)a.ns * a.ns;
-    return a;
+// Tile version of the stage (clusters with ns <= 64): a work item is a run of
+// whole (i, j) tiles A[i][j][:][:] of one cluster, staged in LDS together with
+// the diagonal of h^HF and the cluster's neighbour tables.  The k- and
+// l-neighbour terms of the commutator then read LDS; i- and j-neighbours read
+// LDS when their tile is staged, global memory otherwise.
+constexpr int TILE_MAX = 4096;   // staged G2 elements per work-group (64 KiB)
+constexpr int NS_MAX_TILE = 64;
+constexpr int Z_MAX_TILE = 4;
+
+__device__ __forceinline__ void divmod(int x, int d, float inv, int& q, int& r) {
+    q = (int)((float)x * inv);
+    r = x - q * d;
+    if (r < 0) {
+        q -= 1;
+        r += d;
+    } else if (r >= d) {
+        q += 1;
+        r -= d;
+    }
+}
+
+template <int MODE, bool TPP>
+__global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
+    __shared__ cd tA[TILE_MAX];
+    __shared__ cd eu[NS_MAX_TILE], ed[NS_MAX_TILE];
+    __shared__ int snb[2 * NS_MAX_TILE * Z_MAX_TILE];
+    __shared__ cd shp[2 * NS_MAX_TILE * Z_MAX_TILE];
+    const int gsz = gridDim.x;
+    const int wid = (gsz % 8 == 0) ? ((blockIdx.x & 7) * (gsz >> 3) + (blockIdx.x >> 3)) : blockIdx.x;
+    const WorkItem w = s.work[wid];
+    if (w.cluster < 0) return;
+    const ClusterDesc d = s.desc[w.cluster];
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
+    const cd* A = s.in2 + d.g2off;
+    const int tid = threadIdx.x;
+    if (w.start < 0) {  // G1 update of the cluster
+        const cd* g1 = s.in1 + d.g1off;
+        const cd* y = s.y1 + d.g1off;
+        cd* acc = s.acc1 + d.g1off;
+        cd* out = s.out1 + d.g1off;
+        for (int e = tid; e < 2 * ns2; e += blockDim.x) {
+            int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
+            cd f = hub_g1_rhs(a, A, sig, i, j);
+            rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
+            if (MODE == RK_LAST) {
+                cd v = out[e];
+                bool bad = !(isfinite(v.x) && isfinite(v.y));
+                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
+                if (bad) atomicOr(s.flag, 1);
+            }
+        }
+        return;
+    }
+    // stage: tiles [t0, t1) of the cluster = elements [t0 ns2, t1 ns2)
+    const int base = w.start, cnt = w.end - w.start;   // element range (whole tiles)
+    for (int q = tid; q < cnt; q += blockDim.x) tA[q] = A[base + q];
+    for (int q = tid; q < ns; q += blockDim.x) {
+        eu[q] = hf_diag(a, 0, q);
+        ed[q] = hf_diag(a, 1, q);
+    }
+    for (int q = tid; q < 2 * ns * z; q += blockDim.x) {
+        snb[q] = a.nbr[q];
+        shp[q] = a.hop[q];
+    }
+    __syncthreads();
+    const int* nbu = snb;
+    const int* nbd = snb + ns * z;
+    const cd* hu = shp;
+    const cd* hd = shp + ns * z;
+    const float inv_ns = 1.0f / (float)ns, inv_ns2 = 1.0f / (float)ns2;
+    const cd* X = a.X;
+    const cd* Y = a.Y;
+    const cd* y = s.y2 + d.g2off;
+    cd* acc = s.acc2 + d.g2off;
+    cd* out = s.out2 + d.g2off;
+    for (int q = tid; q < cnt; q += blockDim.x) {
+        const int e = base + q;
+        int ij, kl, i, j, k, l;
+        divmod(e, ns2, inv_ns2, ij, kl);
+        divmod(ij, ns, inv_ns, i, j);
+        divmod(kl, ns, inv_ns, k, l);
+        const cd av = tA[q];
+        cd ei = eu[i], ej = ed[j], ek = eu[k], el = ed[l];
+        cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
+        for (int qq = 0; qq < z; ++qq) {
+            int p = nbu[i * z + qq];
+            if (p >= 0) {
+                int qn = q + (p - i) * ns3;
+                cd v = (qn >= 0 && qn < cnt) ? tA[qn] : A[e + (p - i) * ns3];
+                c = cfma(c, hu[i * z + qq], v);
+            }
+        }
+        for (int qq = 0; qq < z; ++qq) {
+            int p = nbd[j * z + qq];
+            if (p >= 0) {
+                int qn = q + (p - j) * ns2;
+                cd v = (qn >= 0 && qn < cnt) ? tA[qn] : A[e + (p - j) * ns2];
+                c = cfma(c, hd[j * z + qq], v);
+            }
+        }
+        cd r = cmk(0.0, 0.0);
+        for (int qq = 0; qq < z; ++qq) {  // same tile: LDS
+            int p = nbu[k * z + qq];
+            if (p >= 0) r = cfma_conjb(r, tA[q + (p - k) * ns], hu[k * z + qq]);
+        }
+        for (int qq = 0; qq < z; ++qq) {
+            int p = nbd[l * z + qq];
+            if (p >= 0) r = cfma_conjb(r, tA[q + (p - l)], hd[l * z + qq]);
+        }
+        c = csub(c, r);
+        cd xik = X[i * ns + k], xij = X[i * ns + j], xjk = X[j * ns + k], xlk = X[l * ns + k],
+           xil = X[i * ns + l];
+        cd yjl = Y[j * ns + l], yji = Y[j * ns + i], yil = Y[i * ns + l], ykl = Y[k * ns + l],
+           yjk = Y[j * ns + k];
+        double dd = (double)(i == j) - (double)(k == l);
+        cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+        cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+        c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+        if (TPP) {
+            cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
+            cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
+            if (i == j) l1 = cadd(l1, dii);
+            cd dkk = A[(k * ns + k) * ns2 + ij], dll = A[(l * ns + l) * ns2 + ij];
+            cd ylk = Y[l * ns + k], xkl = X[k * ns + l];
+            cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
+            if (k == l) l2 = cadd(l2, dkk);
+            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+        }
+        rk_update<MODE>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
+    }
+}
+
+StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const Regs& acc,
+                     const Regs& out, double cb, double cc) {
+    HubbardData& H = c->hub;
+    StageArgs s;
+    s.desc = H.desc;
+    s.work = H.work;
+    s.nbr = H.nbr;
+    s.hop = H.hop;
+    s.d0 = H.d0;
+    s.xdrv = H.xdrv;
+    s.s_drive = H.drive_value(t);
+    s.in1 = in.g1;
+    s.in2 = in.g2;
+    s.y1 = y.g1;
+    s.y2 = y.g2;
+    s.acc1 = acc.g1;
+    s.acc2 = acc.g2;
+    s.out1 = out.g1;
+    s.out2 = out.g2;
+    s.cb = cb;
+    s.cc = cc;
+    s.flag = c->dflag;
+    return s;
 }
 
 template <int MODE>
-g1g2_status launch_stage(g1g2_ctx* c, const HubArgs& a, const Regs& in, const Regs& y,
-                         const Regs& acc, const Regs& out, double cb, double cc) {
-    const int ns = a.ns;
-    const int n4 = ns * ns * ns * ns;
-    int blocks = (n4 + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    bool tpp = c->d.selfenergy == G1G2_TPP;
-    if (tpp)
-        hipLaunchKernelGGL((hub_g2_kernel<MODE, true>), dim3(blocks), dim3(256), 0, c->stream, a,
-                           in.g2, y.g2, acc.g2, out.g2, cb, cc);
+g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
+    const bool tpp = c->d.selfenergy == G1G2_TPP;
+    if (c->hub.tiled) {
+        if (tpp)
+            hipLaunchKernelGGL((hub_tile_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+        else
+            hipLaunchKernelGGL((hub_tile_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+    } else if (tpp)
+        hipLaunchKernelGGL((hub_stage_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     else
-        hipLaunchKernelGGL((hub_g2_kernel<MODE, false>), dim3(blocks), dim3(256), 0, c->stream, a,
-                           in.g2, y.g2, acc.g2, out.g2, cb, cc);
+        hipLaunchKernelGGL((hub_stage_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     HIP_OK(c, hipGetLastError());
-    prof_mark(c, "hub_g2");
-    int b1 = (2 * ns * ns + 255) / 256;
-    hipLaunchKernelGGL((hub_g1_kernel<MODE>), dim3(b1), dim3(256), 0, c->stream, a, in.g2, in.g1,
-                       y.g1, acc.g1, out.g1, cb, cc, c->dflag);
-    HIP_OK(c, hipGetLastError());
-    prof_mark(c, "hub_g1");
+    prof_mark(c, "hub_stage");
     return G1G2_OK;
 }
 
-// Observables: one work-group; partial sums in binary64.
-__global__ __launch_bounds__(256) void hub_obs_kernel(HubArgs a, const cd* __restrict__ A,
+// Observables: one work-group per cluster; partial sums in binary64.
+__global__ __launch_bounds__(256) void hub_obs_kernel(const ClusterDesc* __restrict__ desc,
+                                                     const int* __restrict__ nbr,
+                                                     const cd* __restrict__ hop,
+                                                     const double* __restrict__ d0,
+                                                     const double* __restrict__ xdrv, double s_drive,
+                                                     const cd* __restrict__ g1,
+                                                     const cd* __restrict__ g2,
                                                      double* __restrict__ res) {
-    __shared__ double sh[8][256];
+    __shared__ double sh[6][256];
+    const ClusterDesc d = desc[blockIdx.x];
+    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, s_drive);
+    const cd* A = g2 + d.g2off;
     const int ns = a.ns, z = a.zmax, tid = threadIdx.x;
     double nu = 0, nd = 0, ekin = 0, emf = 0, ecorr = 0, docc = 0;
     for (int i = tid; i < ns; i += blockDim.x) {
@@ -227,13 +424,13 @@ __global__ __launch_bounds__(256) void hub_obs_kernel(HubArgs a, const cd* __res
     double v[6] = {nu, nd, ekin, emf, ecorr, docc};
     for (int q = 0; q < 6; ++q) sh[q][tid] = v[q];
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s)
-            for (int q = 0; q < 6; ++q) sh[q][tid] += sh[q][tid + s];
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int q = 0; q < 6; ++q) sh[q][tid] += sh[q][tid + st];
         __syncthreads();
     }
     if (tid == 0)
-        for (int q = 0; q < 6; ++q) res[q] = sh[q][0];
+        for (int q = 0; q < 6; ++q) res[blockIdx.x * 8 + q] = sh[q][0];
 }
 
 // max |A_(r,c) - conj(A_(c,r))| and max |A| per block, A an n x n pair matrix
@@ -265,7 +462,13 @@ __global__ __launch_bounds__(256) void herm_resid_kernel(const cd* __restrict__ 
     }
 }
 
-__global__ void hub_site_kernel(HubArgs a, const cd* __restrict__ A, double* __restrict__ out) {
+__global__ void hub_site_kernel(const ClusterDesc* __restrict__ desc, const int* __restrict__ nbr,
+                                const cd* __restrict__ hop, const double* __restrict__ d0,
+                                const double* __restrict__ xdrv, const cd* __restrict__ g1,
+                                const cd* __restrict__ g2, double* __restrict__ out) {
+    const ClusterDesc d = desc[0];
+    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, 0.0);
+    const cd* A = g2 + d.g2off;
     const int ns = a.ns;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
         double niu = a.X[i * ns + i].y, nid = a.Y[i * ns + i].y;
@@ -273,6 +476,16 @@ __global__ void hub_site_kernel(HubArgs a, const cd* __restrict__ A, double* __r
         out[ns + i] = nid;
         out[2 * ns + i] = niu * nid - A[((i * ns + i) * ns + i) * ns + i].x;
     }
+}
+
+template <typename V>
+g1g2_status upload(g1g2_ctx* c, V** dst, const std::vector<V>& h) {
+    if (*dst) (void)hipFree(*dst);
+    *dst = nullptr;
+    HIP_OK(c, hipMalloc(dst, std::max<size_t>(h.size(), 1) * sizeof(V)));
+    if (!h.empty())
+        HIP_OK(c, hipMemcpyAsync(*dst, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, c->stream));
+    return G1G2_OK;
 }
 
 }  // namespace
@@ -286,105 +499,199 @@ double HubbardData::drive_value(double t) const {
     return s;
 }
 
-g1g2_status hub_setup(g1g2_ctx* c, const cd* h0) {
-    const int ns = c->d.nb;
-    // Hermiticity check and sparsity pattern
-    int zmax = 0;
-    std::vector<std::vector<std::pair<int, cd>>> rows(2 * ns);
-    std::vector<double> d0(2 * ns);
-    for (int s = 0; s < 2; ++s)
-        for (int i = 0; i < ns; ++i)
-            for (int j = 0; j < ns; ++j) {
-                cd v = h0[(size_t)s * ns * ns + i * ns + j];
-                cd vt = h0[(size_t)s * ns * ns + j * ns + i];
-                if (std::fabs(v.x - vt.x) > 1e-12 * (1 + std::fabs(v.x)) ||
-                    std::fabs(v.y + vt.y) > 1e-12 * (1 + std::fabs(v.y)))
-                    return set_error(c, G1G2_EINVAL, "h0 is not Hermitian");
-                if (i == j) {
-                    d0[s * ns + i] = v.x;
-                } else if (v.x != 0.0 || v.y != 0.0) {
-                    rows[s * ns + i].push_back({j, v});
+void hub_free(g1g2_ctx* c) {
+    HubbardData& H = c->hub;
+    void* ptrs[] = {H.desc, H.work, H.nbr, H.hop, H.d0, H.xdrv};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    std::vector<double> dc = H.drive_c, dtc = H.drive_tc, dx = H.drive_x;
+    double tau = H.drive_tau;
+    H = HubbardData();
+    H.drive_c = dc;
+    H.drive_tc = dtc;
+    H.drive_x = dx;
+    H.drive_tau = tau;
+}
+
+g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, const cd* const* h0s,
+                      const int* chunk_in) {
+    HubbardData& H = c->hub;
+    std::vector<ClusterDesc> desc(ncl);
+    std::vector<int> nbr_all;
+    std::vector<cd> hop_all;
+    std::vector<double> d0_all;
+    std::vector<WorkItem> work;
+    std::vector<int> chunks(ncl);
+    bool tiled = true;
+    for (int cl = 0; cl < ncl; ++cl) {
+        if (nsv[cl] > NS_MAX_TILE) tiled = false;
+        // neighbour tables must fit the LDS copy
+        const cd* h0 = h0s[cl];
+        const int ns = nsv[cl];
+        for (int sgm = 0; sgm < 2 && tiled; ++sgm)
+            for (int i = 0; i < ns && tiled; ++i) {
+                int z = 0;
+                for (int j = 0; j < ns; ++j) {
+                    cd v = h0[(size_t)sgm * ns * ns + i * ns + j];
+                    if (i != j && (v.x != 0.0 || v.y != 0.0)) ++z;
                 }
+                if (z > Z_MAX_TILE) tiled = false;
             }
-    for (auto& r : rows) zmax = std::max<int>(zmax, (int)r.size());
-    if (zmax < 1) zmax = 1;
-    std::vector<int> nbr((size_t)2 * ns * zmax, -1);
-    std::vector<cd> hop((size_t)2 * ns * zmax, cmk(0, 0));
-    for (int r = 0; r < 2 * ns; ++r)
-        for (size_t q = 0; q < rows[r].size(); ++q) {
-            nbr[(size_t)r * zmax + q] = rows[r][q].first;
-            hop[(size_t)r * zmax + q] = rows[r][q].second;
+    }
+    long long g2off = 0;
+    long long g1off = 0, xoff = 0;
+    for (int cl = 0; cl < ncl; ++cl) {
+        const int ns = nsv[cl];
+        const cd* h0 = h0s[cl];
+        std::vector<std::vector<std::pair<int, cd>>> rows(2 * ns);
+        std::vector<double> d0(2 * ns);
+        for (int s = 0; s < 2; ++s)
+            for (int i = 0; i < ns; ++i)
+                for (int j = 0; j < ns; ++j) {
+                    cd v = h0[(size_t)s * ns * ns + i * ns + j];
+                    cd vt = h0[(size_t)s * ns * ns + j * ns + i];
+                    if (std::fabs(v.x - vt.x) > 1e-12 * (1 + std::fabs(v.x)) ||
+                        std::fabs(v.y + vt.y) > 1e-12 * (1 + std::fabs(v.y)))
+                        return set_error(c, G1G2_EINVAL,
+                                         "h0 is not Hermitian (cluster " + std::to_string(cl) + ")");
+                    if (i == j)
+                        d0[s * ns + i] = v.x;
+                    else if (v.x != 0.0 || v.y != 0.0)
+                        rows[s * ns + i].push_back({j, v});
+                }
+        int zmax = 1;
+        for (auto& r : rows) zmax = std::max<int>(zmax, (int)r.size());
+        ClusterDesc& d = desc[cl];
+        d.ns = ns;
+        d.zmax = zmax;
+        d.g1off = (int)g1off;
+        d.nbroff = (int)nbr_all.size();
+        d.d0off = (int)d0_all.size();
+        d.xoff = (int)xoff;
+        d.g2off = g2off;
+        d.U = Uv[cl];
+        for (int r = 0; r < 2 * ns; ++r)
+            for (int q = 0; q < zmax; ++q) {
+                bool has = q < (int)rows[r].size();
+                nbr_all.push_back(has ? rows[r][q].first : -1);
+                hop_all.push_back(has ? rows[r][q].second : cmk(0, 0));
+            }
+        d0_all.insert(d0_all.end(), d0.begin(), d0.end());
+        const long long n4 = (long long)ns * ns * ns * ns;
+        if (tiled) {
+            // whole (i,j) tiles of ns^2 elements, at most TILE_MAX elements per item
+            const int n2 = ns * ns;
+            int want = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : TILE_MAX;
+            int tiles = std::max(1, std::min(want, TILE_MAX) / n2);
+            chunks[cl] = tiles * n2;
+            for (long long t0 = 0; t0 < (long long)n2; t0 += tiles) {
+                long long t1 = std::min<long long>(n2, t0 + tiles);
+                work.push_back({cl, (int)(t0 * n2), (int)(t1 * n2)});
+            }
+        } else {
+            int ch = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : 1024;
+            chunks[cl] = ch;
+            for (long long st = 0; st < n4; st += ch)
+                work.push_back({cl, (int)st, (int)std::min<long long>(n4, st + ch)});
         }
-    auto& H = c->hub;
-    if (H.nbr) {
-        (void)hipFree(H.nbr);
-        (void)hipFree(H.hop);
-        H.nbr = nullptr;
-        H.hop = nullptr;
+        work.push_back({cl, -1, -1});
+        g2off += n4;
+        g1off += 2LL * ns * ns;
+        xoff += ns;
     }
-    H.ns = ns;
-    H.zmax = zmax;
-    HIP_OK(c, hipMalloc(&H.nbr, nbr.size() * sizeof(int)));
-    HIP_OK(c, hipMalloc(&H.hop, hop.size() * sizeof(cd)));
-    if (!H.d0) HIP_OK(c, hipMalloc(&H.d0, 2 * ns * sizeof(double)));
-    if (!H.xdrv) {
-        HIP_OK(c, hipMalloc(&H.xdrv, ns * sizeof(double)));
-        HIP_OK(c, hipMemsetAsync(H.xdrv, 0, ns * sizeof(double), c->stream));
-    }
-    HIP_OK(c, hipMemcpyAsync(H.nbr, nbr.data(), nbr.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(H.hop, hop.data(), hop.size() * sizeof(cd), hipMemcpyHostToDevice, c->stream));
-    HIP_OK(c, hipMemcpyAsync(H.d0, d0.data(), d0.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (tiled)
+        while (work.size() % 8 != 0) work.push_back({-1, 0, 0});   // XCD-aware order needs 8 | grid
+    hub_free(c);
+    H.ncl = ncl;
+    H.tiled = tiled;
+    H.hdesc = desc;
+    H.chunk = chunks;
+    H.nwork = (int)work.size();
+    H.h_d0 = d0_all;
+    g1g2_status s;
+    if ((s = upload(c, &H.desc, desc)) != G1G2_OK) return s;
+    if ((s = upload(c, &H.work, work)) != G1G2_OK) return s;
+    if ((s = upload(c, &H.nbr, nbr_all)) != G1G2_OK) return s;
+    if ((s = upload(c, &H.hop, hop_all)) != G1G2_OK) return s;
+    if ((s = upload(c, &H.d0, d0_all)) != G1G2_OK) return s;
+    HIP_OK(c, hipMalloc(&H.xdrv, std::max<long long>(xoff, 1) * sizeof(double)));
+    HIP_OK(c, hipMemsetAsync(H.xdrv, 0, std::max<long long>(xoff, 1) * sizeof(double), c->stream));
+    if (ncl == 1 && (long long)H.drive_x.size() == xoff)
+        HIP_OK(c, hipMemcpyAsync(H.xdrv, H.drive_x.data(), xoff * sizeof(double), hipMemcpyHostToDevice,
+                                 c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    H.h_d0 = d0;
     return G1G2_OK;
 }
 
 g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc) {
-    HubArgs a = make_args(c, t, in);
+    StageArgs s = make_stage(c, t, in, y, acc, out, cb, cc);
     switch (mode) {
-        case RK_RHS: return launch_stage<RK_RHS>(c, a, in, y, acc, out, cb, cc);
-        case RK_FIRST: return launch_stage<RK_FIRST>(c, a, in, y, acc, out, cb, cc);
-        case RK_MID: return launch_stage<RK_MID>(c, a, in, y, acc, out, cb, cc);
-        default: return launch_stage<RK_LAST>(c, a, in, y, acc, out, cb, cc);
+        case RK_RHS: return launch_stage<RK_RHS>(c, s);
+        case RK_FIRST: return launch_stage<RK_FIRST>(c, s);
+        case RK_MID: return launch_stage<RK_MID>(c, s);
+        default: return launch_stage<RK_LAST>(c, s);
     }
 }
 
+g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o) {
+    HubbardData& H = c->hub;
+    const int n = H.ncl;
+    double* res = nullptr;
+    HIP_OK(c, hipMalloc((void**)&res, (size_t)n * 8 * sizeof(double)));
+    hipLaunchKernelGGL(hub_obs_kernel, dim3(n), dim3(256), 0, c->stream, H.desc, H.nbr, H.hop, H.d0,
+                       H.xdrv, H.drive_value(t), s.g1, s.g2, res);
+    hipError_t e1 = hipGetLastError();
+    std::vector<double> h((size_t)n * 8);
+    hipError_t e2 = hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream);
+    hipError_t e3 = hipStreamSynchronize(c->stream);
+    (void)hipFree(res);
+    HIP_OK(c, e1);
+    HIP_OK(c, e2);
+    HIP_OK(c, e3);
+    for (int cl = 0; cl < n; ++cl) {
+        const double* r = &h[(size_t)cl * 8];
+        g1g2_obs& ob = o[cl];
+        ob.N[0] = r[0];
+        ob.N[1] = r[1];
+        ob.E_kin = r[2];
+        ob.E_mf = r[3];
+        ob.E_corr = r[4];
+        ob.E_tot = r[2] + r[3] + r[4];
+        ob.docc = r[5] / H.hdesc[cl].ns;
+        ob.herm_resid = 0.0;
+    }
+    return G1G2_OK;
+}
+
 g1g2_status hub_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o) {
-    HubArgs a = make_args(c, t, s);
-    hipLaunchKernelGGL(hub_obs_kernel, dim3(1), dim3(256), 0, c->stream, a, s.g2, c->dscratch);
-    HIP_OK(c, hipGetLastError());
-    const int ns = a.ns;
+    g1g2_status st = hub_batch_observables(c, s, t, o);
+    if (st != G1G2_OK) return st;
+    const int ns = c->hub.hdesc[0].ns;
     long long n4 = (long long)ns * ns * ns * ns;
-    int nblk = 256;
+    const int nblk = 256;
     hipLaunchKernelGGL(herm_resid_kernel, dim3(nblk), dim3(256), 0, c->stream, s.g2, ns * ns, n4,
                        c->dscratch + 8);
     HIP_OK(c, hipGetLastError());
-    std::vector<double> h(8 + 2 * nblk);
-    HIP_OK(c, hipMemcpyAsync(h.data(), c->dscratch, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+    std::vector<double> h(2 * nblk);
+    HIP_OK(c, hipMemcpyAsync(h.data(), c->dscratch + 8, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     double m1 = 0, m2 = 0;
     for (int b = 0; b < nblk; ++b) {
-        m1 = std::max(m1, h[8 + 2 * b]);
-        m2 = std::max(m2, h[8 + 2 * b + 1]);
+        m1 = std::max(m1, h[2 * b]);
+        m2 = std::max(m2, h[2 * b + 1]);
     }
-    o->N[0] = h[0];
-    o->N[1] = h[1];
-    o->E_kin = h[2];
-    o->E_mf = h[3];
-    o->E_corr = h[4];
-    o->E_tot = h[2] + h[3] + h[4];
-    o->docc = h[5] / ns;
     o->herm_resid = m2 > 0 ? m1 / m2 : 0.0;
     return G1G2_OK;
 }
 
 g1g2_status hub_site_observables(g1g2_ctx* c, const Regs& s, double* nu, double* nd, double* docc) {
-    HubArgs a = make_args(c, c->t, s);
-    const int ns = a.ns;
-    hipLaunchKernelGGL(hub_site_kernel, dim3((ns + 255) / 256), dim3(256), 0, c->stream, a, s.g2,
-                       c->dscratch);
+    HubbardData& H = c->hub;
+    const int ns = H.hdesc[0].ns;
+    hipLaunchKernelGGL(hub_site_kernel, dim3((ns + 255) / 256), dim3(256), 0, c->stream, H.desc, H.nbr,
+                       H.hop, H.d0, H.xdrv, s.g1, s.g2, c->dscratch);
     HIP_OK(c, hipGetLastError());
     std::vector<double> h(3 * ns);
     HIP_OK(c, hipMemcpyAsync(h.data(), c->dscratch, h.size() * sizeof(double), hipMemcpyDeviceToHost,
