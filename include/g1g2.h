@@ -159,6 +159,24 @@ g1g2_status g1g2_batch_observables(g1g2_ctx* ctx, g1g2_obs* out);
 /* State of one cluster into host arrays G1 [2][ns][ns] and (if not NULL) G2 [ns]^4. */
 g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void* G2);
 
+/* Discrete adjoint of the Runge-Kutta propagation (single-cluster Hubbard,
+ * SOA, with or without drive).  g1g2_forward_checkpointed advances the state
+ * by nsteps steps of size dt exactly like g1g2_step_rk4 and keeps a device
+ * copy of the state every `interval` steps (interval <= 0: ceil(sqrt(nsteps)));
+ * device memory grows by about (nsteps/interval + interval + 8) states.
+ * g1g2_adjoint then returns the loss
+ *   L = sum_i a[i] d_i(T) + sum_i b[i] (n^up_ii(T) + n^dn_ii(T)),
+ *   n_ii = Im G^<_ii,  d_i = n^up_ii n^dn_ii - Re G2_iiii,
+ * and its exact derivatives with respect to the drive coefficients c_m
+ * (grad_c[M], M as given to g1g2_set_drive; may be NULL) and U (grad_U),
+ * by the reverse sweep of the discrete RK4 map with each checkpoint segment
+ * recomputed once.  a, b: host arrays of nb doubles.  The final state is left
+ * in place.  ESTATE without a preceding forward_checkpointed;
+ * EUNSUPPORTED for other bases, selfenergies or batches.                   */
+g1g2_status g1g2_forward_checkpointed(g1g2_ctx* ctx, double dt, int64_t nsteps, int32_t interval);
+g1g2_status g1g2_adjoint(g1g2_ctx* ctx, const double* a, const double* b, double* grad_c,
+                         double* grad_U, double* loss);
+
 /* Profiling aid.  Runs nsteps Runge-Kutta steps of size dt exactly like
  * g1g2_step_rk4 (advancing the state), or, for nsteps = 0, one right-hand-side
  * evaluation of the current state, with a HIP event recorded on the context's

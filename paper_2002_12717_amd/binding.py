@@ -53,6 +53,9 @@ _SIGS = {
                                   c_void_p, c_void_p, c_void_p, c_void_p]),
     "g1g2_batch_observables": (c_int32, [c_void_p, c_void_p]),
     "g1g2_batch_get_state": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "g1g2_forward_checkpointed": (c_int32, [c_void_p, c_double, c_int64, c_int32]),
+    "g1g2_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_double),
+                               POINTER(c_double)]),
     "g1g2_destroy": (None, [c_void_p]),
     "g1g2_strerror": (ctypes.c_char_p, [c_int32]),
     "g1g2_last_error": (ctypes.c_char_p, [c_void_p]),
@@ -185,6 +188,19 @@ class Propagator:
         tc = np.ascontiguousarray(t_center, np.float64)
         self._check(self.lib.g1g2_set_drive(self.ctx, _ptr(x), int(len(c)), _ptr(c), _ptr(tc),
                                              float(tau)))
+
+    def forward_checkpointed(self, dt: float, nsteps: int, interval: int = 0):
+        self._check(self.lib.g1g2_forward_checkpointed(self.ctx, float(dt), int(nsteps), int(interval)))
+
+    def adjoint(self, a, b, n_drive: int = 0):
+        """(loss, dL/dc [n_drive], dL/dU) after forward_checkpointed."""
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        gc = np.zeros(max(n_drive, 1))
+        gU, L = c_double(), c_double()
+        self._check(self.lib.g1g2_adjoint(self.ctx, _ptr(a), _ptr(b), _ptr(gc), ctypes.byref(gU),
+                                          ctypes.byref(L)))
+        return L.value, gc[:n_drive], gU.value
 
     def profile(self, dt: float = 0.0, nsteps: int = 0) -> dict:
         """Per-kernel time of nsteps RK4 steps (or of one RHS for nsteps = 0):

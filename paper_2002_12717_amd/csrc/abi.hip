@@ -181,6 +181,7 @@ void g1g2_destroy(g1g2_ctx* c) {
     if (c->dscratch) (void)hipFree(c->dscratch);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    adj_free(c);
     hub_free(c);
     gen_free(c);
     delete c;

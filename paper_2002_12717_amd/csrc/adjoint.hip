@@ -1,0 +1,544 @@
+// Discrete adjoint of the RK4 propagation of the driven Hubbard SOA system.
+//
+// Loss  L = sum_i a_i d_i(T) + sum_i b_i (n^up_ii(T) + n^dn_ii(T)),
+// n_ii = Im G^<_ii (n = -i G^<), d_i = n^up_ii n^dn_ii - Re A_iiii.
+// Parameters: drive coefficients c_m (through s(t) = sum_m c_m phi_m(t), which
+// adds s(t) x_i to the diagonal of h0 for both spins) and U.
+//
+// Complex cotangents follow zbar = dL/dRe z + i dL/dIm z: for w = M z
+// (complex linear) zbar += M^H wbar; for w = a b, abar += conj(b) wbar.
+//
+// One RK4 step y -> y + dt/6 (k1 + 2 k2 + 2 k3 + k4), k_s = f(Y_s, t_s), is
+// reversed as
+//   g4 = dt/6 l, m4 = J(Y4)^T g4, g3 = dt/3 l + dt m4, m3 = J(Y3)^T g3,
+//   g2 = dt/3 l + dt/2 m3, m2 = J(Y2)^T g2, g1 = dt/6 l + dt/2 m2,
+//   m1 = J(Y1)^T g1,  l <- l + m1 + m2 + m3 + m4,
+// with the stage states Y_s recomputed from y_n (checkpointed every K steps,
+// each segment recomputed forward once).  The vector-Jacobian product of the
+// right-hand side of eq:g2-hubbard / eq:eom_g1_hubbard is split into
+//   adj_a   : the G2 cotangent (stencil of the commutator applied to the
+//             cotangent, which is its own adjoint up to conj of the diagonal,
+//             plus the collision-integral entries),
+//   adj_red : the source Psi (eq:soa-cubic-scheme) differentiated with respect
+//             to X and Y: six reductions over pairs of G2 indices,
+//   adj_g1  : the G1 cotangents, the diagonal of h^HF, dL/ds and dL/dU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "hub_common.h"
+
+using hub::Cl;
+using hub::hf_diag;
+using hub::make_cl;
+
+namespace {
+
+struct AdjArgs {
+    Cl a;                       // stage state (X, Y) and model data
+    const cd* A;                // stage state G2
+    const cd* gin1;             // cotangent of dG1 (scaled by gscale)
+    const cd* gin2;             // cotangent of dG2
+    double gscale;
+    const cd* lam1;             // lambda (running cotangent of y_n)
+    const cd* lam2;
+    cd* lacc1;                  // lambda accumulator
+    cd* lacc2;
+    cd* gnext1;                 // next stage cotangent = alpha lambda + beta mu
+    cd* gnext2;
+    double alpha, beta;
+    int init, has_next;
+    cd* red;                    // reduction buffers (see adj_red)
+    double* grads;              // [2]: dL/ds, dL/dU of this stage
+};
+
+// reduction buffer layout (each ns^2 complex): RX[6], RY[6], M02, M13, UPART
+enum { R_X = 0, R_Y = 6, R_M02 = 12, R_M13 = 13, R_UP = 14, R_N = 15 };
+
+__device__ __forceinline__ cd cmul3(cd a, cd b, cd c) { return cmul(cmul(a, b), c); }
+
+// G2 cotangent: mu = conj(E) B + hop(B) + collision entries, B = i g.
+__global__ __launch_bounds__(256) void adj_a_kernel(AdjArgs s) {
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, n4 = ns2 * ns2, z = a.zmax;
+    const int* nbu = a.nbr;
+    const int* nbd = a.nbr + ns * z;
+    const cd* hu = a.hop;
+    const cd* hd = a.hop + ns * z;
+    const cd* G = s.gin2;
+    const double gs = s.gscale;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
+        int l = e % ns, tq = e / ns;
+        int k = tq % ns;
+        tq /= ns;
+        int j = tq % ns, i = tq / ns;
+        cd ei = hf_diag(a, 0, i), ej = hf_diag(a, 1, j), ek = hf_diag(a, 0, k), el = hf_diag(a, 1, l);
+        cd E = cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y);
+        // hop stencil applied to g (B = i gs g is applied at the end)
+        cd hsum = cmul(cconj(E), G[e]);
+        for (int q = 0; q < z; ++q) {
+            int p = nbu[i * z + q];
+            if (p >= 0) hsum = cfma(hsum, hu[i * z + q], G[e + (p - i) * ns3]);
+        }
+        for (int q = 0; q < z; ++q) {
+            int p = nbd[j * z + q];
+            if (p >= 0) hsum = cfma(hsum, hd[j * z + q], G[e + (p - j) * ns2]);
+        }
+        for (int q = 0; q < z; ++q) {
+            int p = nbu[k * z + q];
+            if (p >= 0) hsum = csub(hsum, cmul(G[e + (p - k) * ns], cconj(hu[k * z + q])));
+        }
+        for (int q = 0; q < z; ++q) {
+            int p = nbd[l * z + q];
+            if (p >= 0) hsum = csub(hsum, cmul(G[e + (p - l)], cconj(hd[l * z + q])));
+        }
+        cd mu = cscale(cmul_i(hsum), gs);
+        // collision integrals: I^up_ik = -iU A_iiki, I^dn_il = -iU A_iiil;
+        // Ibar_ab = BX_ab + conj(BX_ba), Abar += i U Ibar.
+        if (j == i && l == i) {
+            cd bxa = cscale(cmul_i(s.gin1[i * ns + k]), gs), bxb = cscale(cmul_i(s.gin1[k * ns + i]), gs);
+            mu = cadd(mu, cscale(cmul_i(cadd(bxa, cconj(bxb))), a.U));
+        }
+        if (j == i && k == i) {
+            const cd* gy = s.gin1 + ns2;
+            cd bya = cscale(cmul_i(gy[i * ns + l]), gs), byb = cscale(cmul_i(gy[l * ns + i]), gs);
+            mu = cadd(mu, cscale(cmul_i(cadd(bya, cconj(byb))), a.U));
+        }
+        cd base = s.init ? s.lam2[e] : s.lacc2[e];
+        s.lacc2[e] = cadd(base, mu);
+        if (s.has_next) {
+            cd lv = s.lam2[e];
+            s.gnext2[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
+        }
+    }
+}
+
+// Source-term reductions.  One work-group per output pair (p0, p1) of KIND;
+// threads sum over the complementary pair (c, d).  B = i gs g, G(.) = conj(.).
+template <int KIND>
+__global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
+    __shared__ double sh[7][256];
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns;
+    const int p0 = blockIdx.x / ns, p1 = blockIdx.x % ns;
+    const cd* X = a.X;
+    const cd* Y = a.Y;
+    const double U = a.U, gs = s.gscale;
+    cd accx = cmk(0, 0), accy = cmk(0, 0), accm = cmk(0, 0);
+    double up = 0.0;
+    for (int cdx = threadIdx.x; cdx < ns2; cdx += blockDim.x) {
+        const int c = cdx / ns, d = cdx % ns;
+        int i, j, k, l;
+        if (KIND == 0) { i = p0; k = p1; j = c; l = d; }        // free (i,k)
+        else if (KIND == 1) { i = p0; j = p1; k = c; l = d; }   // free (i,j)
+        else if (KIND == 2) { j = p0; k = p1; i = c; l = d; }   // free (j,k)
+        else if (KIND == 3) { k = p0; l = p1; i = c; j = d; }   // free (k,l)
+        else if (KIND == 4) { i = p0; l = p1; j = c; k = d; }   // free (i,l)
+        else { j = p0; l = p1; i = c; k = d; }                  // free (j,l)
+        const int e = ((i * ns + j) * ns + k) * ns + l;
+        const cd B = cscale(cmul_i(s.gin2[e]), gs);
+        if (KIND == 0) {
+            double dd = (double)(i == j) - (double)(k == l);
+            cd w = cscale(cconj(Y[j * ns + l]), U * dd);
+            w = cadd(w, cscale(cmul_i(cconj(cmul(Y[j * ns + i], Y[i * ns + l]))), -U));
+            w = cadd(w, cscale(cmul_i(cconj(cmul(Y[k * ns + l], Y[j * ns + k]))), U));
+            accx = cfma(accx, w, B);
+            accm = cfma(accm, cconj(s.A[e]), B);
+        } else if (KIND == 1) {
+            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[j * ns + k], Y[j * ns + l]))), -U), B);
+            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[i * ns + l], X[i * ns + k]))), -U), B);
+            // Psi / U at this element (eq:soa-cubic-scheme with U = 1)
+            cd xik = X[i * ns + k], xij = X[i * ns + j], xjk = X[j * ns + k], xlk = X[l * ns + k],
+               xil = X[i * ns + l];
+            cd yjl = Y[j * ns + l], yji = Y[j * ns + i], yil = Y[i * ns + l], ykl = Y[k * ns + l],
+               yjk = Y[j * ns + k];
+            double dd = (double)(i == j) - (double)(k == l);
+            cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+            cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+            cd psi1 = cadd(cscale(cmul(xik, yjl), dd), cmul_i(cadd(t1, t2)));
+            up += psi1.x * B.x + psi1.y * B.y;   // Re(conj(psi1) B)
+        } else if (KIND == 2) {
+            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[i * ns + j], Y[j * ns + l]))), -U), B);
+            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[k * ns + l], X[i * ns + k]))), U), B);
+        } else if (KIND == 3) {
+            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[i * ns + l], Y[j * ns + l]))), U), B);
+            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[j * ns + k], X[i * ns + k]))), U), B);
+        } else if (KIND == 4) {
+            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[l * ns + k], Y[j * ns + l]))), U), B);
+            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[j * ns + i], X[i * ns + k]))), -U), B);
+        } else {
+            double dd = (double)(i == j) - (double)(k == l);
+            cd w = cscale(cconj(X[i * ns + k]), U * dd);
+            w = cadd(w, cscale(cmul_i(cconj(cmul(X[i * ns + j], X[j * ns + k]))), -U));
+            w = cadd(w, cscale(cmul_i(cconj(cmul(X[l * ns + k], X[i * ns + l]))), U));
+            accy = cfma(accy, w, B);
+            accm = cfma(accm, cconj(s.A[e]), B);
+        }
+    }
+    const int t = threadIdx.x;
+    sh[0][t] = accx.x;
+    sh[1][t] = accx.y;
+    sh[2][t] = accy.x;
+    sh[3][t] = accy.y;
+    sh[4][t] = accm.x;
+    sh[5][t] = accm.y;
+    sh[6][t] = up;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (t < st)
+            for (int q = 0; q < 7; ++q) sh[q][t] += sh[q][t + st];
+        __syncthreads();
+    }
+    if (t == 0) {
+        cd* R = s.red;
+        cd vx = cmk(sh[0][0], sh[1][0]), vy = cmk(sh[2][0], sh[3][0]), vm = cmk(sh[4][0], sh[5][0]);
+        const int ab = p0 * ns + p1, ba = p1 * ns + p0;
+        if (KIND == 0) { R[(R_X + 0) * ns2 + ab] = vx; R[R_M02 * ns2 + ab] = vm; }
+        else if (KIND == 1) { R[(R_X + 1) * ns2 + ab] = vx; R[(R_Y + 1) * ns2 + ba] = vy;
+                              R[R_UP * ns2 + ab] = cmk(sh[6][0], 0.0); }
+        else if (KIND == 2) { R[(R_X + 2) * ns2 + ab] = vx; R[(R_Y + 2) * ns2 + ab] = vy; }
+        else if (KIND == 3) { R[(R_X + 3) * ns2 + ba] = vx; R[(R_Y + 3) * ns2 + ab] = vy; }
+        else if (KIND == 4) { R[(R_X + 4) * ns2 + ab] = vx; R[(R_Y + 4) * ns2 + ab] = vy; }
+        else { R[(R_Y + 5) * ns2 + ab] = vy; R[R_M13 * ns2 + ab] = vm; }
+    }
+}
+
+// G1 cotangents, diagonal of h^HF, dL/ds and dL/dU of one stage (one work-group).
+__global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
+    __shared__ cd ebu[64], ebd[64];
+    __shared__ double sh[3][256];
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns, z = a.zmax, t = threadIdx.x;
+    const cd* R = s.red;
+    const double gs = s.gscale;
+    const cd* X = a.X;
+    const cd* Y = a.Y;
+    const cd* gx = s.gin1;
+    const cd* gy = s.gin1 + ns2;
+    double sbar = 0.0, ubar = 0.0;
+    // ebar^up_i and ebar^dn_i
+    for (int i = t; i < ns; i += blockDim.x) {
+        cd eu = cmk(0, 0), ed = cmk(0, 0);
+        for (int p = 0; p < ns; ++p) {
+            // (BX X^H - X^H BX)_ii with BX = i gs gX
+            cd bx_ip = cscale(cmul_i(gx[i * ns + p]), gs), bx_pi = cscale(cmul_i(gx[p * ns + i]), gs);
+            eu = cadd(eu, csub(cmul(bx_ip, cconj(X[i * ns + p])), cmul(cconj(X[p * ns + i]), bx_pi)));
+            cd by_ip = cscale(cmul_i(gy[i * ns + p]), gs), by_pi = cscale(cmul_i(gy[p * ns + i]), gs);
+            ed = cadd(ed, csub(cmul(by_ip, cconj(Y[i * ns + p])), cmul(cconj(Y[p * ns + i]), by_pi)));
+            eu = cadd(eu, csub(R[R_M02 * ns2 + i * ns + p], R[R_M02 * ns2 + p * ns + i]));
+            ed = cadd(ed, csub(R[R_M13 * ns2 + i * ns + p], R[R_M13 * ns2 + p * ns + i]));
+        }
+        ebu[i] = eu;
+        ebd[i] = ed;
+        sbar += a.xdrv[i] * (eu.x + ed.x);
+        // e^up_i = ... - i U Y_ii, e^dn_i = ... - i U X_ii: Ubar += Re(conj(-i Y_ii) ebar)
+        cd myi = cmul_mi(Y[i * ns + i]), mxi = cmul_mi(X[i * ns + i]);
+        ubar += myi.x * eu.x + myi.y * eu.y + mxi.x * ed.x + mxi.y * ed.y;
+    }
+    __syncthreads();
+    for (int q = t; q < ns2; q += blockDim.x) ubar += R[R_UP * ns2 + q].x;
+    for (int e = t; e < 2 * ns2; e += blockDim.x) {
+        const int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
+        const cd* gg = sig ? gy : gx;
+        const cd* eb = sig ? ebu : ebd;    // X_ii enters e^dn, Y_ii enters e^up
+        const int* nb = a.nbr + sig * ns * z;
+        const cd* hp = a.hop + sig * ns * z;
+        // [h^H, B]_ij, B = i gs g
+        cd ei = hf_diag(a, sig, i), ej = hf_diag(a, sig, j);
+        cd bij = gg[r];
+        cd c = csub(cmul(cconj(ei), bij), cmul(bij, cconj(ej)));
+        for (int q = 0; q < z; ++q) {
+            int p = nb[i * z + q];
+            if (p >= 0) c = cfma(c, hp[i * z + q], gg[p * ns + j]);
+        }
+        for (int q = 0; q < z; ++q) {
+            int p = nb[j * z + q];
+            if (p >= 0) c = csub(c, cmul(gg[i * ns + p], cconj(hp[j * z + q])));
+        }
+        cd mu = cscale(cmul_i(c), gs);
+        for (int kd = 0; kd < 6; ++kd) mu = cadd(mu, R[((sig ? R_Y : R_X) + kd) * ns2 + r]);
+        if (i == j) mu = cadd(mu, cscale(cmul_i(eb[i]), a.U));
+        // collision-integral part of dL/dU: I_ij = -i U A..., Ibar_ij = B_ij + conj(B_ji)
+        {
+            cd bb = cadd(cscale(cmul_i(gg[r]), gs), cconj(cscale(cmul_i(gg[j * ns + i]), gs)));
+            cd av = sig == 0 ? s.A[((i * ns + i) * ns + j) * ns + i] : s.A[((i * ns + i) * ns + i) * ns + j];
+            cd dI = cmul_mi(av);   // dI/dU
+            ubar += dI.x * bb.x + dI.y * bb.y;
+        }
+        cd base = s.init ? s.lam1[e] : s.lacc1[e];
+        s.lacc1[e] = cadd(base, mu);
+        if (s.has_next) {
+            cd lv = s.lam1[e];
+            s.gnext1[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
+        }
+    }
+    sh[0][t] = sbar;
+    sh[1][t] = ubar;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (t < st) {
+            sh[0][t] += sh[0][t + st];
+            sh[1][t] += sh[1][t + st];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        s.grads[0] = sh[0][0];
+        s.grads[1] = sh[1][0];
+    }
+}
+
+// Terminal cotangent of the loss and its value.
+__global__ void adj_terminal_kernel(Cl a, const cd* __restrict__ A, const double* __restrict__ wa,
+                                    const double* __restrict__ wb, cd* __restrict__ l1,
+                                    cd* __restrict__ l2, double* __restrict__ loss) {
+    const int ns = a.ns;
+    double L = 0.0;
+    for (int i = 0; i < ns; ++i) {
+        const int ii = i * ns + i;
+        const int e = ((i * ns + i) * ns + i) * ns + i;
+        double nu = a.X[ii].y, nd = a.Y[ii].y;
+        L += wa[i] * (nu * nd - A[e].x) + wb[i] * (nu + nd);
+        l1[ii] = cmk(0.0, wa[i] * nd + wb[i]);            // dL/dIm X_ii
+        l1[ns * ns + ii] = cmk(0.0, wa[i] * nu + wb[i]);  // dL/dIm Y_ii
+        l2[e] = cmk(-wa[i], 0.0);                         // dL/dRe A_iiii
+    }
+    *loss = L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- host
+namespace {
+
+struct AdjState {
+    int64_t nsteps = 0;
+    int interval = 0;
+    double dt = 0.0, t0 = 0.0;
+    int nck = 0;
+    std::vector<Regs> ckpt, seg;
+    Regs S2, S3, S4, LAM, LACC, CA, CB, DUMMY;
+    cd* red = nullptr;
+    double* grads = nullptr;   // [4 nsteps][2]
+    double* dev_ab = nullptr;  // weights a, b and the loss
+};
+
+AdjState* adj_of(g1g2_ctx* c) { return reinterpret_cast<AdjState*>(c->adj); }
+
+g1g2_status alloc_reg(g1g2_ctx* c, Regs& r) {
+    HIP_OK(c, hipMalloc(&r.g1, c->n1 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&r.g2, c->n2 * sizeof(cd)));
+    return G1G2_OK;
+}
+
+void free_reg(Regs& r) {
+    if (r.g1) (void)hipFree(r.g1);
+    if (r.g2) (void)hipFree(r.g2);
+    r = Regs();
+}
+
+g1g2_status copy_reg(g1g2_ctx* c, const Regs& dst, const Regs& src) {
+    HIP_OK(c, hipMemcpyAsync(dst.g1, src.g1, c->n1 * sizeof(cd), hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(dst.g2, src.g2, c->n2 * sizeof(cd), hipMemcpyDeviceToDevice, c->stream));
+    return G1G2_OK;
+}
+
+AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double gscale, const Regs& lam,
+                 const Regs& lacc, const Regs& gnext, double alpha, double beta, int init, int has_next,
+                 double* grads) {
+    HubbardData& H = c->hub;
+    AdjState* st = adj_of(c);
+    const ClusterDesc& d = H.hdesc[0];
+    AdjArgs s;
+    Cl a;
+    a.ns = d.ns;
+    a.zmax = d.zmax;
+    a.U = d.U;
+    a.s_drive = H.drive_value(t);
+    a.nbr = H.nbr;
+    a.hop = H.hop;
+    a.d0 = H.d0;
+    a.xdrv = H.xdrv;
+    a.X = S.g1;
+    a.Y = S.g1 + d.ns * d.ns;
+    s.a = a;
+    s.A = S.g2;
+    s.gin1 = gin.g1;
+    s.gin2 = gin.g2;
+    s.gscale = gscale;
+    s.lam1 = lam.g1;
+    s.lam2 = lam.g2;
+    s.lacc1 = lacc.g1;
+    s.lacc2 = lacc.g2;
+    s.gnext1 = gnext.g1;
+    s.gnext2 = gnext.g2;
+    s.alpha = alpha;
+    s.beta = beta;
+    s.init = init;
+    s.has_next = has_next;
+    s.red = st->red;
+    s.grads = grads;
+    return s;
+}
+
+g1g2_status vjp(g1g2_ctx* c, const AdjArgs& s) {
+    const int ns = s.a.ns;
+    const int n4 = ns * ns * ns * ns;
+    hipLaunchKernelGGL((adj_red_kernel<0>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<1>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<2>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<3>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<4>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<5>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "adj_red");
+    int blocks = std::min((n4 + 255) / 256, 65536);
+    hipLaunchKernelGGL(adj_a_kernel, dim3(blocks), dim3(256), 0, c->stream, s);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "adj_a");
+    hipLaunchKernelGGL(adj_g1_kernel, dim3(1), dim3(256), 0, c->stream, s);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "adj_g1");
+    return G1G2_OK;
+}
+
+g1g2_status stage_fwd(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y, const Regs& acc,
+                      const Regs& out, double cb, double cc) {
+    return hub_stage(c, mode, t, in, y, acc, out, cb, cc);
+}
+
+}  // namespace
+
+void adj_free(g1g2_ctx* c) {
+    AdjState* st = adj_of(c);
+    if (!st) return;
+    for (auto& r : st->ckpt) free_reg(r);
+    for (auto& r : st->seg) free_reg(r);
+    for (Regs* r : {&st->S2, &st->S3, &st->S4, &st->LAM, &st->LACC, &st->CA, &st->CB, &st->DUMMY}) free_reg(*r);
+    if (st->red) (void)hipFree(st->red);
+    if (st->grads) (void)hipFree(st->grads);
+    if (st->dev_ab) (void)hipFree(st->dev_ab);
+    delete st;
+    c->adj = nullptr;
+}
+
+extern "C" {
+
+g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, int32_t interval) {
+    if (!c || nsteps < 1 || !(dt > 0.0)) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD || c->d.selfenergy != G1G2_SOA || c->hub.ncl != 1)
+        return set_error(c, G1G2_EUNSUPPORTED, "the adjoint covers the single-cluster Hubbard SOA system");
+    if (c->hub.hdesc[0].ns > 64) return set_error(c, G1G2_EUNSUPPORTED, "adjoint supports ns <= 64");
+    adj_free(c);
+    AdjState* st = new AdjState();
+    c->adj = st;
+    st->nsteps = nsteps;
+    st->interval = interval > 0 ? interval : std::max<int>(1, (int)std::ceil(std::sqrt((double)nsteps)));
+    st->dt = dt;
+    st->t0 = c->t;
+    st->nck = (int)((nsteps + st->interval - 1) / st->interval);
+    g1g2_status s;
+    st->ckpt.resize(st->nck + 1);       // last slot keeps the final state
+    for (auto& r : st->ckpt)
+        if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
+    st->seg.resize(st->interval);
+    for (auto& r : st->seg)
+        if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
+    for (Regs* r : {&st->S2, &st->S3, &st->S4, &st->LAM, &st->LACC, &st->CA, &st->CB, &st->DUMMY})
+        if ((s = alloc_reg(c, *r)) != G1G2_OK) return s;
+    const int ns = c->hub.hdesc[0].ns;
+    HIP_OK(c, hipMalloc(&st->red, (size_t)R_N * ns * ns * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&st->grads, (size_t)4 * nsteps * 2 * sizeof(double)));
+    HIP_OK(c, hipMalloc(&st->dev_ab, (size_t)(2 * ns + 8) * sizeof(double)));
+    for (int q = 0; q < st->nck; ++q) {
+        if ((s = copy_reg(c, st->ckpt[q], c->y)) != G1G2_OK) return s;
+        const int64_t n = std::min<int64_t>(st->interval, nsteps - (int64_t)q * st->interval);
+        if ((s = g1g2_step_rk4(c, dt, n)) != G1G2_OK) return s;
+    }
+    return copy_reg(c, st->ckpt[st->nck], c->y);
+}
+
+g1g2_status g1g2_adjoint(g1g2_ctx* c, const double* wa, const double* wb, double* grad_c,
+                         double* grad_U, double* loss) {
+    if (!c || !wa || !wb) return G1G2_EINVAL;
+    AdjState* st = adj_of(c);
+    if (!st) return set_error(c, G1G2_ESTATE, "call g1g2_forward_checkpointed first");
+    HubbardData& H = c->hub;
+    const int ns = H.hdesc[0].ns;
+    const double dt = st->dt;
+    g1g2_status s;
+    // terminal cotangent
+    HIP_OK(c, hipMemcpyAsync(st->dev_ab, wa, ns * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(st->dev_ab + ns, wb, ns * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemsetAsync(st->LAM.g1, 0, c->n1 * sizeof(cd), c->stream));
+    HIP_OK(c, hipMemsetAsync(st->LAM.g2, 0, c->n2 * sizeof(cd), c->stream));
+    {
+        const Regs& fin = st->ckpt[st->nck];
+        AdjArgs tmp = make_adj(c, st->t0 + st->nsteps * dt, fin, fin, 1.0, fin, fin, fin, 0, 0, 0, 0, nullptr);
+        hipLaunchKernelGGL(adj_terminal_kernel, dim3(1), dim3(1), 0, c->stream, tmp.a, fin.g2, st->dev_ab,
+                           st->dev_ab + ns, st->LAM.g1, st->LAM.g2, st->dev_ab + 2 * ns);
+        HIP_OK(c, hipGetLastError());
+    }
+    Regs lam = st->LAM, lacc = st->LACC;
+    for (int q = st->nck - 1; q >= 0; --q) {
+        const int64_t n0 = (int64_t)q * st->interval;
+        const int64_t n1 = std::min<int64_t>(n0 + st->interval, st->nsteps);
+        // recompute the segment forward, storing y_n
+        if ((s = copy_reg(c, c->y, st->ckpt[q])) != G1G2_OK) return s;
+        for (int64_t n = n0; n < n1; ++n) {
+            if ((s = copy_reg(c, st->seg[n - n0], c->y)) != G1G2_OK) return s;
+            const double t = st->t0 + (double)n * dt;
+            if (n + 1 < n1) {
+                if ((s = stage_fwd(c, RK_FIRST, t, c->y, c->y, c->acc, c->s0, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
+                if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, c->s0, c->y, c->acc, c->s1, dt / 3.0, dt / 2.0)) != G1G2_OK) return s;
+                if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, c->s1, c->y, c->acc, c->s0, dt / 3.0, dt)) != G1G2_OK) return s;
+                if ((s = stage_fwd(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0)) != G1G2_OK) return s;
+            }
+        }
+        // reverse over the segment
+        for (int64_t n = n1 - 1; n >= n0; --n) {
+            const Regs& y = st->seg[n - n0];
+            const double t = st->t0 + (double)n * dt;
+            // stage states Y2 = y + dt/2 k1, Y3 = y + dt/2 k2, Y4 = y + dt k3
+            if ((s = stage_fwd(c, RK_FIRST, t, y, y, st->DUMMY, st->S2, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
+            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->S2, y, st->DUMMY, st->S3, dt / 3.0, dt / 2.0)) != G1G2_OK) return s;
+            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->S3, y, st->DUMMY, st->S4, dt / 3.0, dt)) != G1G2_OK) return s;
+            double* g = st->grads + (size_t)8 * n;
+            if ((s = vjp(c, make_adj(c, t + dt, st->S4, lam, dt / 6.0, lam, lacc, st->CA, dt / 3.0, dt, 1, 1, g + 6))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->S3, st->CA, 1.0, lam, lacc, st->CB, dt / 3.0, dt / 2.0, 0, 1, g + 4))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->S2, st->CB, 1.0, lam, lacc, st->CA, dt / 6.0, dt / 2.0, 0, 1, g + 2))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t, y, st->CA, 1.0, lam, lacc, st->CB, 0.0, 0.0, 0, 0, g + 0))) != G1G2_OK) return s;
+            std::swap(lam, lacc);
+        }
+    }
+    // restore the final state
+    if ((s = copy_reg(c, c->y, st->ckpt[st->nck])) != G1G2_OK) return s;
+    std::vector<double> gr((size_t)8 * st->nsteps);
+    double L = 0.0;
+    HIP_OK(c, hipMemcpyAsync(gr.data(), st->grads, gr.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(&L, st->dev_ab + 2 * ns, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+    const int M = (int)H.drive_c.size();
+    double gU = 0.0;
+    if (grad_c)
+        for (int m = 0; m < M; ++m) grad_c[m] = 0.0;
+    for (int64_t n = 0; n < st->nsteps; ++n)
+        for (int q = 0; q < 4; ++q) {
+            const double sb = gr[8 * n + 2 * q], ub = gr[8 * n + 2 * q + 1];
+            gU += ub;
+            const double ts = st->t0 + ((double)n + cs[q]) * dt;
+            if (grad_c)
+                for (int m = 0; m < M; ++m) {
+                    const double d = ts - H.drive_tc[m];
+                    grad_c[m] += sb * std::exp(-d * d / (2.0 * H.drive_tau * H.drive_tau));
+                }
+        }
+    if (grad_U) *grad_U = gU;
+    if (loss) *loss = L;
+    return G1G2_OK;
+}
+
+}  // extern "C"

@@ -96,6 +96,7 @@ struct g1g2_ctx {
     int nscratch = 0;
     HubbardData hub;
     GeneralData gen;
+    void* adj = nullptr;       // adjoint state (adjoint.hip)
     // captured RK4 steps (replayed by g1g2_step_rk4 when the stream is not NULL)
     hipGraphExec_t graph = nullptr;
     double graph_dt = 0.0;
@@ -145,3 +146,6 @@ g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
 g1g2_status gen_pad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
 g1g2_status gen_unpad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
 void gen_free(g1g2_ctx* c);
+
+// ---- adjoint (adjoint.hip)
+void adj_free(g1g2_ctx* c);

@@ -294,3 +294,75 @@ def test_graph_replays_match_eager(lib, basis):
         assert np.array_equal(g1g, g1e) and np.array_equal(g2g, g2e) and tg == te, rep
     pg.close()
     pe.close()
+
+
+# --------------------------------------------------------------------------- adjoint
+def _adj_weights(s):
+    ns, lx = s.ns, s.meta["lx"]
+    a = np.full(ns, 1.0 / ns)
+    b = np.array([1.0 if (q % lx) < lx / 2 else -1.0 for q in range(ns)]) / ns
+    return a, b
+
+
+@pytest.mark.parametrize("shape,interval", [((3, 2, 50), 7), ((4, 3, 60), 0)])
+def test_adjoint_matches_oracle_gradient(lib, shape, interval):
+    """Discrete adjoint on the GPU against the oracle's exact gradient of the
+    same RK4 map (drive coefficients and U), ragged checkpoint segments."""
+    from oracle import adjoint as OA
+    from paper_2002_12717_amd import binding as B
+    lx, ly, nst = shape
+    s = adjoint_system(lx=lx, ly=ly, U=2.0, nmodes=8, T=nst * 0.02, dt=0.02)
+    say(f"[adjoint] {lx}x{ly} steps={nst} interval={interval}")
+    a, b = _adj_weights(s)
+    L0, gc0, gU0 = OA.loss_and_gradient(s, a, b)
+    p = B.Propagator(B.HUBBARD, B.SOA, s.ns, s.h0, s.g1, U=s.U)
+    d = s.drive
+    p.set_drive(d.x, d.c, d.t_center, d.tau)
+    p.forward_checkpointed(s.dt, nst, interval)
+    L, gc, gU = p.adjoint(a, b, len(d.c))
+    eL = abs(L - L0) / abs(L0)
+    ec = np.abs(gc - gc0).max() / np.abs(gc0).max()
+    eu = abs(gU - gU0) / abs(gU0)
+    say(f"   err L {eL:.2e}  err grad_c {ec:.2e}  err grad_U {eu:.2e}")
+    assert eL < 1e-10 and ec < 1e-10 and eu < 1e-10
+    p.close()
+
+
+def test_adjoint_autograd_function_and_finite_differences(lib):
+    """torch.autograd.Function wrapper on an 8x8 open cluster (config shape,
+    shortened to 200 steps): gradient against central differences (h=1e-6)
+    of the GPU forward map for U and two drive coefficients."""
+    from paper_2002_12717_amd import binding as B
+    from paper_2002_12717_amd.autograd import DrivenHubbardLoss
+    s = adjoint_system(lx=8, ly=8, U=2.0, nmodes=64, T=2.0, dt=0.01)
+    nst = s.nsteps
+    say(f"[adjoint] 8x8 autograd + FD, {nst} steps")
+    a, b = _adj_weights(s)
+    d = s.drive
+    drive = (d.x, d.t_center, d.tau)
+    p = B.Propagator(B.HUBBARD, B.SOA, s.ns, s.h0, s.g1, U=s.U)
+    c = torch.tensor(d.c, dtype=torch.float64, requires_grad=True)
+    U = torch.tensor(s.U, dtype=torch.float64, requires_grad=True)
+    L = DrivenHubbardLoss.apply(c, U, p, drive, a, b, s.dt, nst, 0)
+    L.backward()
+
+    def loss_at(cv, Uv):
+        q = B.Propagator(B.HUBBARD, B.SOA, s.ns, s.h0, s.g1, U=Uv)
+        q.set_drive(d.x, cv, d.t_center, d.tau)
+        q.step(s.dt, nst)
+        nu, nd, docc = q.site_observables()
+        q.close()
+        return float(np.dot(a, docc) + np.dot(b, nu + nd))
+
+    h = 1e-6
+    fd_u = (loss_at(d.c, s.U + h) - loss_at(d.c, s.U - h)) / (2 * h)
+    say(f"   dL/dU adjoint {U.grad.item():.10e} fd {fd_u:.10e}")
+    assert abs(fd_u - U.grad.item()) < 1e-6 * max(1e-3, abs(fd_u))
+    for m in (5, 20):
+        cp, cm = d.c.copy(), d.c.copy()
+        cp[m] += h
+        cm[m] -= h
+        fd = (loss_at(cp, s.U) - loss_at(cm, s.U)) / (2 * h)
+        say(f"   dL/dc{m} adjoint {c.grad[m].item():.10e} fd {fd:.10e}")
+        assert abs(fd - c.grad[m].item()) < 1e-6 * max(1e-3, abs(fd))
+    p.close()
