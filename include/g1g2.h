@@ -147,8 +147,12 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * captured HIP graphs of whole steps when a stream is given.  desc supplies
  * basis (HUBBARD), selfenergy (SOA or TPP) and precision (FP64); per cluster
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
- * [2][ns][ns]; G2(0) = 0.  chunk[c] > 0 sets the G2 elements handled by one
- * work-group of cluster c (NULL or 0: 1024), e.g. from an autotuning table.
+ * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
+ * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
+ * table: chunk > 0 selects the LDS-tiled stage kernel (rounded to whole
+ * (i,j) tiles of ns^2 elements, at most 4096), chunk < 0 the per-element
+ * kernel with |chunk| elements per work-group (any negative entry selects the
+ * per-element kernel for the whole batch).
  * g1g2_step_rk4, g1g2_profile and g1g2_destroy act on the whole batch; the
  * single-cluster calls (rhs, get/set_state, set_h0/U/drive) return ESTATE. */
 g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, const int32_t* ns,

@@ -1,6 +1,7 @@
 """Autotuner of the ragged Hubbard batch: chooses, per cluster size class, the
-number of G2 elements handled by one work-group (the tile of the flat work
-list of g1g2_batch_init).  Coordinate descent over the classes; each candidate
+number of G2 elements handled by one work-group of the flat work list of
+g1g2_batch_init (rounded down to whole (i,j) tiles of ns^2 elements, at least
+one tile, at most 4096 elements staged in LDS).  Coordinate descent over the classes; each candidate
 is timed with HIP events over whole RK4 steps on the real batch.  The table
 is written as JSON and read back by ``chunks_for``.
 """
@@ -14,8 +15,11 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuning", "hubbard_batch.json")
 CLASSES = [(1, 16), (17, 25), (26, 49)]          # ns ranges (inclusive)
-CANDIDATES = [256, 512, 1024, 2048, 4096, 8192]
-DEFAULT = 1024
+# > 0: LDS-tiled stage kernel (elements per work-group, whole tiles);
+# < 0: per-element stage kernel with |value| elements per work-group
+CANDIDATES_TILED = [1024, 2048, 4096]
+CANDIDATES_FLAT = [-256, -512, -1024, -2048]
+DEFAULT = 4096
 
 
 def class_of(ns: int) -> int:
@@ -62,14 +66,20 @@ def tune(n_clusters: int = 512, steps: int = 8, selfenergy_name: str = "tpp", ou
     clusters = batched_clusters(n=n_clusters)
     se = B.TPP if selfenergy_name == "tpp" else B.SOA
     stream = torch.cuda.Stream()
-    best = [DEFAULT] * len(CLASSES)
     ns = [c.ns for c in clusters]
     log = []
-    base = _time(B, torch, clusters, se, [best[class_of(n)] for n in ns], steps, stream)
-    log.append({"chunk_per_class": list(best), "ms_per_step": base})
-    print(f"start {best} {base:.3f} ms/step", flush=True)
+    # the kernel variant is global: pick it first with uniform chunks
+    best, base = None, float("inf")
+    for start in (DEFAULT, -256):
+        trial = [start] * len(CLASSES)
+        ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream)
+        log.append({"chunk_per_class": trial, "ms_per_step": ms})
+        print(f"start {trial} {ms:.3f} ms/step", flush=True)
+        if ms < base:
+            base, best = ms, trial
+    cands = CANDIDATES_TILED if best[0] > 0 else CANDIDATES_FLAT
     for q in range(len(CLASSES)):
-        for cand in CANDIDATES:
+        for cand in cands:
             if cand == best[q]:
                 continue
             trial = list(best)

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
             if (p >= 0) c = csub(c, cmul(gg[i * ns + p], cconj(hp[j * z + q])));
         }
         cd mu = cscale(cmul_i(c), gs);
-        for (int kd = 0; kd < 6; ++kd) mu = cadd(mu, R[((sig ? R_Y : R_X) + kd) * ns2 + r]);
+        // source-term reductions: X receives kinds 0-4, Y kinds 1-5
+        for (int kd = sig ? 1 : 0; kd < (sig ? 6 : 5); ++kd) mu = cadd(mu, R[((sig ? R_Y : R_X) + kd) * ns2 + r]);
         if (i == j) mu = cadd(mu, cscale(cmul_i(eb[i]), a.U));
         // collision-integral part of dL/dU: I_ij = -i U A..., Ibar_ij = B_ij + conj(B_ji)
         {
@@ -450,6 +451,7 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
         if ((s = alloc_reg(c, *r)) != G1G2_OK) return s;
     const int ns = c->hub.hdesc[0].ns;
     HIP_OK(c, hipMalloc(&st->red, (size_t)R_N * ns * ns * sizeof(cd)));
+    HIP_OK(c, hipMemsetAsync(st->red, 0, (size_t)R_N * ns * ns * sizeof(cd), c->stream));
     HIP_OK(c, hipMalloc(&st->grads, (size_t)4 * nsteps * 2 * sizeof(double)));
     HIP_OK(c, hipMalloc(&st->dev_ab, (size_t)(2 * ns + 8) * sizeof(double)));
     for (int q = 0; q < st->nck; ++q) {

@@ -44,6 +44,7 @@ struct HubbardData {
     WorkItem* work = nullptr;      // device work list
     int nwork = 0;
     bool tiled = false;            // LDS-tiled stage kernel (every ns <= 64)
+    int xcd_order = 0;             // XCD-contiguous dispatch of the work list
     std::vector<int> chunk;        // elements of G2 per work-group, per cluster
     int* nbr = nullptr;            // concatenated neighbour tables
     cd* hop = nullptr;

@@ -134,6 +134,7 @@ struct StageArgs {
     cd* out2;
     double cb, cc;
     int* flag;
+    int xcd_order;   // 1: map work-groups to XCD-contiguous runs of the work list
 };
 
 template <int MODE, bool TPP>
@@ -203,8 +204,10 @@ __global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
     __shared__ cd eu[NS_MAX_TILE], ed[NS_MAX_TILE];
     __shared__ int snb[2 * NS_MAX_TILE * Z_MAX_TILE];
     __shared__ cd shp[2 * NS_MAX_TILE * Z_MAX_TILE];
+    __shared__ cd dcol[TILE_MAX / 8];   // TPP: A_ppij for each staged tile (i,j)
     const int gsz = gridDim.x;
-    const int wid = (gsz % 8 == 0) ? ((blockIdx.x & 7) * (gsz >> 3) + (blockIdx.x >> 3)) : blockIdx.x;
+    const int wid = (s.xcd_order && gsz % 8 == 0) ? ((blockIdx.x & 7) * (gsz >> 3) + (blockIdx.x >> 3))
+                                                  : blockIdx.x;
     const WorkItem w = s.work[wid];
     if (w.cluster < 0) return;
     const ClusterDesc d = s.desc[w.cluster];
@@ -240,6 +243,14 @@ __global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
     for (int q = tid; q < 2 * ns * z; q += blockDim.x) {
         snb[q] = a.nbr[q];
         shp[q] = a.hop[q];
+    }
+    const int tile0 = base / ns2;
+    if (TPP) {   // dcol[t ns + p] = A_pp(ij) of the t-th staged tile
+        const int ntl = cnt / ns2;
+        for (int q = tid; q < ntl * ns; q += blockDim.x) {
+            const int t = q / ns, p = q % ns;
+            dcol[q] = A[(p * ns + p) * ns2 + tile0 + t];
+        }
     }
     __syncthreads();
     const int* nbu = snb;
@@ -299,7 +310,8 @@ __global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
             cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
             cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
             if (i == j) l1 = cadd(l1, dii);
-            cd dkk = A[(k * ns + k) * ns2 + ij], dll = A[(l * ns + l) * ns2 + ij];
+            const cd* dc = dcol + (ij - tile0) * ns;
+            cd dkk = dc[k], dll = dc[l];
             cd ylk = Y[l * ns + k], xkl = X[k * ns + l];
             cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
             if (k == l) l2 = cadd(l2, dkk);
@@ -331,6 +343,7 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.cb = cb;
     s.cc = cc;
     s.flag = c->dflag;
+    s.xcd_order = c->hub.xcd_order;
     return s;
 }
 
@@ -493,6 +506,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     bool tiled = true;
     for (int cl = 0; cl < ncl; ++cl) {
         if (nsv[cl] > NS_MAX_TILE) tiled = false;
+        if (chunk_in && chunk_in[cl] < 0) tiled = false;   // per-element kernel requested
         // neighbour tables must fit the LDS copy
         const cd* h0 = h0s[cl];
         const int ns = nsv[cl];
@@ -557,7 +571,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                 work.push_back({cl, (int)(t0 * n2), (int)(t1 * n2)});
             }
         } else {
-            int ch = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : 1024;
+            int ch = (chunk_in && chunk_in[cl] != 0) ? std::abs(chunk_in[cl]) : 1024;
             chunks[cl] = ch;
             for (long long st = 0; st < n4; st += ch)
                 work.push_back({cl, (int)st, (int)std::min<long long>(n4, st + ch)});
@@ -572,6 +586,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     hub_free(c);
     H.ncl = ncl;
     H.tiled = tiled;
+    H.xcd_order = tiled ? 1 : 0;
     H.hdesc = desc;
     H.chunk = chunks;
     H.nwork = (int)work.size();
