@@ -1,9 +1,10 @@
-"""Autotuner of the ragged Hubbard batch: chooses, per cluster size class, the
-number of G2 elements handled by one work-group of the flat work list of
-g1g2_batch_init (rounded down to whole (i,j) tiles of ns^2 elements, at least
-one tile, at most 4096 elements staged in LDS).  Coordinate descent over the classes; each candidate
-is timed with HIP events over whole RK4 steps on the real batch.  The table
-is written as JSON and read back by ``chunks_for``.
+"""Autotuner of the ragged Hubbard batch.  It first chooses the stage kernel
+(row kernel: positive chunks; per-element kernel: negative chunks), then, per
+cluster size class, the number of G2 elements handled by one work-group of
+the flat work list of g1g2_batch_init (the row kernel rounds it to whole wave
+units of rows).  Coordinate descent over the classes; each candidate is timed
+with HIP events over whole RK4 steps on the real batch.  The table is written
+as JSON and read back by ``chunks_for``.
 """
 from __future__ import annotations
 
@@ -15,11 +16,11 @@ import time
 PKG = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(PKG, "tuning", "hubbard_batch.json")
 CLASSES = [(1, 16), (17, 25), (26, 49)]          # ns ranges (inclusive)
-# > 0: LDS-tiled stage kernel (elements per work-group, whole tiles);
+# > 0: row stage kernel (elements per work-group, rounded to whole wave units);
 # < 0: per-element stage kernel with |value| elements per work-group
-CANDIDATES_TILED = [1024, 2048, 4096]
+CANDIDATES_ROW = [256, 512, 1024, 2048, 4096]
 CANDIDATES_FLAT = [-256, -512, -1024, -2048]
-DEFAULT = 4096
+DEFAULT = 1024
 
 
 def class_of(ns: int) -> int:
@@ -77,7 +78,7 @@ def tune(n_clusters: int = 512, steps: int = 8, selfenergy_name: str = "tpp", ou
         print(f"start {trial} {ms:.3f} ms/step", flush=True)
         if ms < base:
             base, best = ms, trial
-    cands = CANDIDATES_TILED if best[0] > 0 else CANDIDATES_FLAT
+    cands = CANDIDATES_ROW if best[0] > 0 else CANDIDATES_FLAT
     for q in range(len(CLASSES)):
         for cand in cands:
             if cand == best[q]:

@@ -30,8 +30,9 @@ struct ClusterDesc {
     double U;
 };
 
-// One work-group's share of a stage: G2 elements [start, end) of a cluster,
-// or (start < 0) the whole G1 update of the cluster.
+// One work-group's share of a stage: G2 elements [start, end) of a cluster
+// (per-element kernel) or wave units [start, end) (row kernel), or
+// (start < 0) the whole G1 update of the cluster.
 struct WorkItem {
     int cluster;
     int start, end;
@@ -43,8 +44,7 @@ struct HubbardData {
     ClusterDesc* desc = nullptr;   // device copy
     WorkItem* work = nullptr;      // device work list
     int nwork = 0;
-    bool tiled = false;            // LDS-tiled stage kernel (every ns <= 64)
-    int xcd_order = 0;             // XCD-contiguous dispatch of the work list
+    bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
     std::vector<int> chunk;        // elements of G2 per work-group, per cluster
     int* nbr = nullptr;            // concatenated neighbour tables
     cd* hop = nullptr;

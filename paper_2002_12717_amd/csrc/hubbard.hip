@@ -134,7 +134,6 @@ struct StageArgs {
     cd* out2;
     double cb, cc;
     int* flag;
-    int xcd_order;   // 1: map work-groups to XCD-contiguous runs of the work list
 };
 
 template <int MODE, bool TPP>
@@ -177,43 +176,43 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
     }
 }
 
-// Tile version of the stage (clusters with ns <= 64): a work item is a run of
-// whole (i, j) tiles A[i][j][:][:] of one cluster, staged in LDS together with
-// the diagonal of h^HF and the cluster's neighbour tables.  The k- and
-// l-neighbour terms of the commutator then read LDS; i- and j-neighbours read
-// LDS when their tile is staged, global memory otherwise.
-constexpr int TILE_MAX = 4096;   // staged G2 elements per work-group (64 KiB)
-constexpr int NS_MAX_TILE = 64;
-constexpr int Z_MAX_TILE = 4;
+// Row version of the stage (every cluster has ns <= 64 and at most Z_MAX_ROW
+// neighbours per site).  A wave evaluates rpw = min(64 / ns, ns) rows
+// A[i][j][k][:] of one (i, j) slice at a time, lane = r ns + l.  The
+// l-neighbours of the commutator are other lanes of the same row (cross-lane
+// permute); k-, i- and j-neighbours are whole rows read from global memory.
+// Values that depend only on (i, j) or on l are loaded once per slice.  The
+// source term reads X_lk as -conj(X_kl) and the ladder Y_lk as -conj(Y_kl)
+// (G^< is anti-Hermitian), so that every operand row is contiguous.
+//
+// A work item is a range [start, end) of wave units u = slice * nkb + kb,
+// nkb = ceil(ns / rpw); wave w of the work-group takes units start + w,
+// start + w + 4, ...
+constexpr int NS_MAX_ROW = 64;
+constexpr int Z_MAX_ROW = 4;
 
-__device__ __forceinline__ void divmod(int x, int d, float inv, int& q, int& r) {
-    q = (int)((float)x * inv);
-    r = x - q * d;
-    if (r < 0) {
-        q -= 1;
-        r += d;
-    } else if (r >= d) {
-        q += 1;
-        r -= d;
-    }
+// A wave-uniform value moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffLL));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
+__device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x), wave_uniform(v.y)); }
 
 template <int MODE, bool TPP>
-__global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
-    __shared__ cd tA[TILE_MAX];
-    __shared__ cd eu[NS_MAX_TILE], ed[NS_MAX_TILE];
-    __shared__ int snb[2 * NS_MAX_TILE * Z_MAX_TILE];
-    __shared__ cd shp[2 * NS_MAX_TILE * Z_MAX_TILE];
-    __shared__ cd dcol[TILE_MAX / 8];   // TPP: A_ppij for each staged tile (i,j)
-    const int gsz = gridDim.x;
-    const int wid = (s.xcd_order && gsz % 8 == 0) ? ((blockIdx.x & 7) * (gsz >> 3) + (blockIdx.x >> 3))
-                                                  : blockIdx.x;
-    const WorkItem w = s.work[wid];
-    if (w.cluster < 0) return;
+__global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
+    constexpr int ZR = Z_MAX_ROW;
+    __shared__ cd eu[NS_MAX_ROW], ed[NS_MAX_ROW];
+    // neighbour tables padded to ZR entries per site: a missing neighbour points
+    // at the site itself with hopping 0, so every neighbour sum is branch-free
+    __shared__ int snb[2 * NS_MAX_ROW * ZR];
+    __shared__ cd shp[2 * NS_MAX_ROW * ZR];
+    const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
-    const cd* A = s.in2 + d.g2off;
+    const cd* __restrict__ A = s.in2 + d.g2off;
     const int tid = threadIdx.x;
     if (w.start < 0) {  // G1 update of the cluster
         const cd* g1 = s.in1 + d.g1off;
@@ -233,91 +232,114 @@ __global__ __launch_bounds__(256) void hub_tile_kernel(StageArgs s) {
         }
         return;
     }
-    // stage: tiles [t0, t1) of the cluster = elements [t0 ns2, t1 ns2)
-    const int base = w.start, cnt = w.end - w.start;   // element range (whole tiles)
-    for (int q = tid; q < cnt; q += blockDim.x) tA[q] = A[base + q];
     for (int q = tid; q < ns; q += blockDim.x) {
         eu[q] = hf_diag(a, 0, q);
         ed[q] = hf_diag(a, 1, q);
     }
-    for (int q = tid; q < 2 * ns * z; q += blockDim.x) {
-        snb[q] = a.nbr[q];
-        shp[q] = a.hop[q];
-    }
-    const int tile0 = base / ns2;
-    if (TPP) {   // dcol[t ns + p] = A_pp(ij) of the t-th staged tile
-        const int ntl = cnt / ns2;
-        for (int q = tid; q < ntl * ns; q += blockDim.x) {
-            const int t = q / ns, p = q % ns;
-            dcol[q] = A[(p * ns + p) * ns2 + tile0 + t];
-        }
+    for (int q = tid; q < 2 * ns * ZR; q += blockDim.x) {
+        const int row = q / ZR, qq = q - row * ZR, site = row % ns;
+        const int p = qq < z ? a.nbr[row * z + qq] : -1;
+        snb[q] = p >= 0 ? p : site;
+        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
     }
     __syncthreads();
     const int* nbu = snb;
-    const int* nbd = snb + ns * z;
+    const int* nbd = snb + ns * ZR;
     const cd* hu = shp;
-    const cd* hd = shp + ns * z;
-    const float inv_ns = 1.0f / (float)ns, inv_ns2 = 1.0f / (float)ns2;
-    const cd* X = a.X;
-    const cd* Y = a.Y;
+    const cd* hd = shp + ns * ZR;
+    const cd* __restrict__ X = a.X;
+    const cd* __restrict__ Y = a.Y;
     const cd* y = s.y2 + d.g2off;
     cd* acc = s.acc2 + d.g2off;
     cd* out = s.out2 + d.g2off;
-    for (int q = tid; q < cnt; q += blockDim.x) {
-        const int e = base + q;
-        int ij, kl, i, j, k, l;
-        divmod(e, ns2, inv_ns2, ij, kl);
-        divmod(ij, ns, inv_ns, i, j);
-        divmod(kl, ns, inv_ns, k, l);
-        const cd av = tA[q];
-        cd ei = eu[i], ej = ed[j], ek = eu[k], el = ed[l];
-        cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
-        for (int qq = 0; qq < z; ++qq) {
-            int p = nbu[i * z + qq];
-            if (p >= 0) {
-                int qn = q + (p - i) * ns3;
-                cd v = (qn >= 0 && qn < cnt) ? tA[qn] : A[e + (p - i) * ns3];
-                c = cfma(c, hu[i * z + qq], v);
+    const int rpw = min(64 / ns, ns);
+    const int nkb = (ns + rpw - 1) / rpw;
+    const int lane = tid & 63;
+    const int sub = lane / ns, l = lane - sub * ns;
+    const bool lane_ok = sub < rpw;
+    // l-neighbours: source lanes of the permute (the lane itself where there is none)
+    int src[ZR];
+#pragma unroll
+    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? sub * ns + nbd[l * ZR + q] : lane;
+    const cd el = lane_ok ? ed[l] : cmk(0.0, 0.0);
+    // first unit of this wave
+    int u = w.start + __builtin_amdgcn_readfirstlane(tid >> 6);
+    int slice = u / nkb, kb = u - slice * nkb;
+    int cur = -1;
+    int i = 0, j = 0;
+    cd ei = cmk(0, 0), ej = cmk(0, 0), xij = cmk(0, 0), yji = cmk(0, 0);
+    cd xil = cmk(0, 0), yjl = cmk(0, 0), yil = cmk(0, 0), dll = cmk(0, 0);
+    double dij = 0.0;
+    for (; u < w.end; u += 4) {
+        if (slice != cur) {   // wave-uniform
+            cur = slice;
+            i = slice / ns;
+            j = slice - i * ns;
+            ei = wave_uniform(eu[i]);
+            ej = wave_uniform(ed[j]);
+            xij = wave_uniform(X[i * ns + j]);
+            yji = wave_uniform(Y[j * ns + i]);
+            dij = (double)(i == j);
+            if (lane_ok) {
+                xil = X[i * ns + l];
+                yjl = Y[j * ns + l];
+                yil = Y[i * ns + l];
+                if (TPP) dll = A[(l * ns + l) * ns2 + slice];
             }
         }
-        for (int qq = 0; qq < z; ++qq) {
-            int p = nbd[j * z + qq];
-            if (p >= 0) {
-                int qn = q + (p - j) * ns2;
-                cd v = (qn >= 0 && qn < cnt) ? tA[qn] : A[e + (p - j) * ns2];
-                c = cfma(c, hd[j * z + qq], v);
+        const int k = kb * rpw + sub;
+        const bool act = lane_ok && k < ns;
+        const int kk = act ? k : 0;
+        const int e = slice * ns2 + kk * ns + l;
+        const cd av = act ? A[e] : cmk(0.0, 0.0);
+        cd vl[ZR];
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            vl[q].x = __shfl(av.x, src[q], 64);
+            vl[q].y = __shfl(av.y, src[q], 64);
+        }
+        if (act) {
+            // sum_p A_ijpl h_pk + sum_p A_ijkp h_pl, with h_pk = conj(h_kp)
+            cd r = cmk(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < ZR; ++q) {
+                r = cfma_conjb(r, vl[q], hd[l * ZR + q]);
+                r = cfma_conjb(r, A[e + (nbu[kk * ZR + q] - kk) * ns], hu[kk * ZR + q]);
             }
+            const cd ek = eu[kk];
+            cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
+            c = csub(c, r);
+#pragma unroll
+            for (int q = 0; q < ZR; ++q) {
+                c = cfma(c, hu[i * ZR + q], A[e + (nbu[i * ZR + q] - i) * ns3]);
+                c = cfma(c, hd[j * ZR + q], A[e + (nbd[j * ZR + q] - j) * ns2]);
+            }
+            // source (eq:soa-cubic-scheme)
+            const cd xik = X[i * ns + kk], xjk = X[j * ns + kk], yjk = Y[j * ns + kk];
+            const cd xkl = X[kk * ns + l], ykl = Y[kk * ns + l];
+            const cd xlk = cmk(-xkl.x, xkl.y);
+            const double dd = dij - (double)(kk == l);
+            cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+            cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+            c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+            if (TPP) {   // ladder (Sec. VII.C) and its partner
+                const int kl = kk * ns + l;
+                cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
+                cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
+                if (i == j) l1 = cadd(l1, dii);
+                cd dkk = A[(kk * ns + kk) * ns2 + slice];
+                cd ylk = cmk(-ykl.x, ykl.y);
+                cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
+                if (kk == l) l2 = cadd(l2, dkk);
+                c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+            }
+            rk_update<MODE>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
         }
-        cd r = cmk(0.0, 0.0);
-        for (int qq = 0; qq < z; ++qq) {  // same tile: LDS
-            int p = nbu[k * z + qq];
-            if (p >= 0) r = cfma_conjb(r, tA[q + (p - k) * ns], hu[k * z + qq]);
+        kb += 4;
+        while (kb >= nkb) {
+            kb -= nkb;
+            ++slice;
         }
-        for (int qq = 0; qq < z; ++qq) {
-            int p = nbd[l * z + qq];
-            if (p >= 0) r = cfma_conjb(r, tA[q + (p - l)], hd[l * z + qq]);
-        }
-        c = csub(c, r);
-        cd xik = X[i * ns + k], xij = X[i * ns + j], xjk = X[j * ns + k], xlk = X[l * ns + k],
-           xil = X[i * ns + l];
-        cd yjl = Y[j * ns + l], yji = Y[j * ns + i], yil = Y[i * ns + l], ykl = Y[k * ns + l],
-           yjk = Y[j * ns + k];
-        double dd = (double)(i == j) - (double)(k == l);
-        cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
-        cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
-        c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
-        if (TPP) {
-            cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
-            cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
-            if (i == j) l1 = cadd(l1, dii);
-            const cd* dc = dcol + (ij - tile0) * ns;
-            cd dkk = dc[k], dll = dc[l];
-            cd ylk = Y[l * ns + k], xkl = X[k * ns + l];
-            cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
-            if (k == l) l2 = cadd(l2, dkk);
-            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
-        }
-        rk_update<MODE>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
     }
 }
 
@@ -343,18 +365,17 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.cb = cb;
     s.cc = cc;
     s.flag = c->dflag;
-    s.xcd_order = c->hub.xcd_order;
     return s;
 }
 
 template <int MODE>
 g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
     const bool tpp = c->d.selfenergy == G1G2_TPP;
-    if (c->hub.tiled) {
+    if (c->hub.rows) {
         if (tpp)
-            hipLaunchKernelGGL((hub_tile_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+            hipLaunchKernelGGL((hub_row_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
         else
-            hipLaunchKernelGGL((hub_tile_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+            hipLaunchKernelGGL((hub_row_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     } else if (tpp)
         hipLaunchKernelGGL((hub_stage_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     else
@@ -501,23 +522,23 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     std::vector<int> nbr_all;
     std::vector<cd> hop_all;
     std::vector<double> d0_all;
-    std::vector<WorkItem> work;
+    std::vector<WorkItem> work, g1work;
     std::vector<int> chunks(ncl);
-    bool tiled = true;
+    bool rowk = true;
     for (int cl = 0; cl < ncl; ++cl) {
-        if (nsv[cl] > NS_MAX_TILE) tiled = false;
-        if (chunk_in && chunk_in[cl] < 0) tiled = false;   // per-element kernel requested
-        // neighbour tables must fit the LDS copy
+        if (nsv[cl] > NS_MAX_ROW) rowk = false;
+        if (chunk_in && chunk_in[cl] < 0) rowk = false;   // per-element kernel requested
+        // the row kernel keeps at most Z_MAX_ROW l-neighbours per lane
         const cd* h0 = h0s[cl];
         const int ns = nsv[cl];
-        for (int sgm = 0; sgm < 2 && tiled; ++sgm)
-            for (int i = 0; i < ns && tiled; ++i) {
+        for (int sgm = 0; sgm < 2 && rowk; ++sgm)
+            for (int i = 0; i < ns && rowk; ++i) {
                 int z = 0;
                 for (int j = 0; j < ns; ++j) {
                     cd v = h0[(size_t)sgm * ns * ns + i * ns + j];
                     if (i != j && (v.x != 0.0 || v.y != 0.0)) ++z;
                 }
-                if (z > Z_MAX_TILE) tiled = false;
+                if (z > Z_MAX_ROW) rowk = false;
             }
     }
     long long g2off = 0;
@@ -560,33 +581,33 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             }
         d0_all.insert(d0_all.end(), d0.begin(), d0.end());
         const long long n4 = (long long)ns * ns * ns * ns;
-        if (tiled) {
-            // whole (i,j) tiles of ns^2 elements, at most TILE_MAX elements per item
-            const int n2 = ns * ns;
-            int want = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : TILE_MAX;
-            int tiles = std::max(1, std::min(want, TILE_MAX) / n2);
-            chunks[cl] = tiles * n2;
-            for (long long t0 = 0; t0 < (long long)n2; t0 += tiles) {
-                long long t1 = std::min<long long>(n2, t0 + tiles);
-                work.push_back({cl, (int)(t0 * n2), (int)(t1 * n2)});
-            }
+        if (rowk) {
+            // wave units of rpw rows (rpw ns elements); chunk = elements per work-group
+            const int rpw = std::min(64 / ns, ns);
+            const int nkb = (ns + rpw - 1) / rpw;
+            const long long nunits = (long long)ns * ns * nkb;
+            int want = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : 1024;
+            int upw = std::max(4, (int)std::lround((double)want / (rpw * ns)));
+            upw = (upw + 3) / 4 * 4;
+            chunks[cl] = upw * rpw * ns;
+            for (long long u0 = 0; u0 < nunits; u0 += upw)
+                work.push_back({cl, (int)u0, (int)std::min<long long>(nunits, u0 + upw)});
         } else {
             int ch = (chunk_in && chunk_in[cl] != 0) ? std::abs(chunk_in[cl]) : 1024;
             chunks[cl] = ch;
             for (long long st = 0; st < n4; st += ch)
                 work.push_back({cl, (int)st, (int)std::min<long long>(n4, st + ch)});
         }
-        work.push_back({cl, -1, -1});
+        g1work.push_back({cl, -1, -1});
         g2off += n4;
         g1off += 2LL * ns * ns;
         xoff += ns;
     }
-    if (tiled)
-        while (work.size() % 8 != 0) work.push_back({-1, 0, 0});   // XCD-aware order needs 8 | grid
+    // G1 updates first: they then overlap with the G2 items instead of trailing them
+    work.insert(work.begin(), g1work.begin(), g1work.end());
     hub_free(c);
     H.ncl = ncl;
-    H.tiled = tiled;
-    H.xcd_order = tiled ? 1 : 0;
+    H.rows = rowk;
     H.hdesc = desc;
     H.chunk = chunks;
     H.nwork = (int)work.size();

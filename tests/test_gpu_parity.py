@@ -241,16 +241,19 @@ def test_abi_errors(lib):
 
 
 # --------------------------------------------------------------------------- batches and graphs
-@pytest.mark.parametrize("se", ["soa", "tpp"])
-def test_hubbard_ragged_batch_parity(lib, se):
+@pytest.mark.parametrize("se,kernel", [("soa", "row"), ("tpp", "row"), ("tpp", "element")])
+def test_hubbard_ragged_batch_parity(lib, se, kernel):
     """Clusters of uneven size and U in one context: every cluster follows the
-    oracle's single-cluster propagation (and the graph-replayed steps)."""
+    oracle's single-cluster propagation (and the graph-replayed steps).  Positive
+    chunks select the row stage kernel, negative ones the per-element kernel."""
     from paper_2002_12717_amd import binding as B
     from workloads import batched_clusters
     cl = batched_clusters(n=7)
-    say(f"[batch] {se} sizes {[c.ns for c in cl]}")
+    say(f"[batch] {se} {kernel} kernel, sizes {[c.ns for c in cl]}")
     stream = torch.cuda.Stream()
     chunk = [256 if c.ns < 16 else 2048 for c in cl]
+    if kernel == "element":
+        chunk = [-ch for ch in chunk]
     b = B.Batch(B.SOA if se == "soa" else B.TPP, [c.ns for c in cl], [c.U for c in cl],
                 [c.h0 for c in cl], [c.g1 for c in cl], chunk=chunk, stream=stream.cuda_stream)
     dt, nst = cl[0].dt, 24
