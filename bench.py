@@ -264,6 +264,7 @@ def cpu_baseline_batch(clusters, seconds: float = 15.0):
 
 
 def run_batch(args, torch, B):
+    import numpy as np
     from paper_2002_12717_amd import autotune
     from workloads import batched_clusters
     clusters = batched_clusters()
@@ -271,17 +272,32 @@ def run_batch(args, torch, B):
     n4 = float(sum(n ** 4 for n in ns))
     chunks = autotune.chunks_for(ns)
     stream = torch.cuda.Stream()
-    b = B.Batch(B.TPP, ns, [c.U for c in clusters], [c.h0 for c in clusters], [c.g1 for c in clusters],
-                chunk=chunks, stream=stream.cuda_stream)
     dt = clusters[0].dt
-    ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
-    prof = b.profile(dt, args.profile_steps)
-    obs = b.observables()
-    b.close()
-    ms_step = ms / args.steps
-    tot_ms, cnt = prof["hub_stage"]
+    res = {}
+    for prec in ("fp64", "mixed"):
+        b = B.Batch(B.TPP, ns, [c.U for c in clusters], [c.h0 for c in clusters],
+                    [c.g1 for c in clusters], chunk=chunks, stream=stream.cuda_stream,
+                    precision=B.FP64 if prec == "fp64" else B.MIXED)
+        ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
+        g1 = [b.get_cluster(q, with_g2=False)[0] for q in range(len(ns))]
+        obs = b.observables()
+        prof = b.profile(dt, args.profile_steps)
+        b.close()
+        res[prec] = dict(ms=ms, g1=g1, obs=obs, prof=prof)
+    f64, mx = res["fp64"], res["mixed"]
+    ms_step = f64["ms"] / args.steps
+    mx_step = mx["ms"] / args.steps
+    tot_ms, cnt = f64["prof"]["hub_stage"]
+    # algorithmic bytes per G2 element and RK4 step: 256 (binary64 stage copies)
+    # or 208 (binary32 stage copies); the four stage launches share them
     bytes_per_launch = 64.0 * n4
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
+    mx_tot, mx_cnt = mx["prof"]["hub_stage"]
+    mx_bytes = 52.0 * n4
+    mx_ach = mx_bytes * mx_cnt / (mx_tot * 1e-3) / 1e9
+    err_g1 = max(float(np.abs(m - f).max() / np.abs(f).max()) for m, f in zip(mx["g1"], f64["g1"]))
+    err_e = max(abs(m["E_tot"] - f["E_tot"]) / max(abs(f["E_tot"]), 1.0)
+                for m, f in zip(mx["obs"], f64["obs"]))
     config = {"workload": f"ragged batch of {len(ns)} periodic 2D Hubbard clusters (Lx,Ly in 3..6), "
                           f"TPP, dt={dt}, RK4, one launch per stage, graph-captured steps",
               "clusters": len(ns), "g2_elements": int(n4), "ns_min": min(ns), "ns_max": max(ns),
@@ -293,8 +309,16 @@ def run_batch(args, torch, B):
                      "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
                      "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
                      "bytes_per_launch": bytes_per_launch, "launches": cnt},
-        "kernels": kernel_table(prof),
-        "diverged": bool(obs[0]["diverged"]),
+        "kernels": kernel_table(f64["prof"]),
+        "mixed": {"dtype": "f32 G2 stage copies / f64 state and arithmetic",
+                  "value": round(1e3 / mx_step, 3), "ms_per_step": round(mx_step, 6),
+                  "speedup_vs_fp64": round(ms_step / mx_step, 3),
+                  "err_G1_vs_fp64": err_g1, "err_E_vs_fp64": err_e,
+                  "roofline": {"kernel": "hub_stage", "achieved": round(mx_ach, 2), "peak": PEAK_HBM,
+                               "unit": "GB/s", "frac": round(mx_ach / PEAK_HBM, 4),
+                               "bytes_per_launch": mx_bytes},
+                  "kernels": kernel_table(mx["prof"])},
+        "diverged": any(bool(o["diverged"]) for o in f64["obs"]),
     })
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(clusters)

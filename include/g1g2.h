@@ -61,10 +61,13 @@ typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2 } g1g2_selfenergy;
 typedef enum { G1G2_GENERAL = 0, G1G2_HUBBARD = 1 } g1g2_basis;
 
 /* FP64: every operation in binary64.
- * MIXED: the O(nb^5) tensor contractions of the general basis run in binary32
- *        on the matrix cores with binary64 accumulation across blocks; G1, the
- *        Runge-Kutta registers, h^HF, the collision integral and all
- *        observables stay binary64.                                            */
+ * MIXED: general basis: the O(nb^5) and O(nb^6) tensor contractions run in
+ *        binary32 on the matrix cores with binary64 accumulation across
+ *        blocks.  Hubbard basis (no contractions): the G2 stage copies of the
+ *        Runge-Kutta step (inputs of stages 2-4) are stored in binary32 and
+ *        all arithmetic is binary64.  In both bases G1, the Runge-Kutta state
+ *        and running sum, h^HF, the collision integral and all observables
+ *        stay binary64, and g1g2_rhs evaluates in binary64.                    */
 typedef enum { G1G2_FP64 = 0, G1G2_MIXED = 1 } g1g2_precision;
 
 enum {
@@ -145,14 +148,15 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * size and U) propagated together: every Runge-Kutta stage of the whole batch
  * is one kernel launch over a flat work list, and g1g2_step_rk4 replays
  * captured HIP graphs of whole steps when a stream is given.  desc supplies
- * basis (HUBBARD), selfenergy (SOA or TPP) and precision (FP64); per cluster
+ * basis (HUBBARD), selfenergy (SOA or TPP) and precision (FP64 or MIXED); per cluster
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
- * table: chunk > 0 selects the LDS-tiled stage kernel (rounded to whole
- * (i,j) tiles of ns^2 elements, at most 4096), chunk < 0 the per-element
- * kernel with |chunk| elements per work-group (any negative entry selects the
- * per-element kernel for the whole batch).
+ * table: chunk > 0 selects the row stage kernel (one wave per G2 row
+ * A[i][j][k][:], rounded to whole wave units of rows; needs every ns <= 64
+ * and at most 4 neighbours per site, else the per-element kernel runs),
+ * chunk < 0 the per-element kernel with |chunk| elements per work-group (any
+ * negative entry selects the per-element kernel for the whole batch).
  * g1g2_step_rk4, g1g2_profile and g1g2_destroy act on the whole batch; the
  * single-cluster calls (rhs, get/set_state, set_h0/U/drive) return ESTATE. */
 g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, const int32_t* ns,
@@ -176,7 +180,7 @@ g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void*
  * by the reverse sweep of the discrete RK4 map with each checkpoint segment
  * recomputed once.  a, b: host arrays of nb doubles.  The final state is left
  * in place.  ESTATE without a preceding forward_checkpointed;
- * EUNSUPPORTED for other bases, selfenergies or batches.                   */
+ * EUNSUPPORTED for other bases, selfenergies, batches or MIXED precision.   */
 g1g2_status g1g2_forward_checkpointed(g1g2_ctx* ctx, double dt, int64_t nsteps, int32_t interval);
 g1g2_status g1g2_adjoint(g1g2_ctx* ctx, const double* a, const double* b, double* grad_c,
                          double* grad_U, double* loss);

@@ -228,13 +228,14 @@ class Propagator:
 class Batch(Propagator):
     """A ragged batch of Hubbard clusters in one context (g1g2_batch_init)."""
 
-    def __init__(self, selfenergy: int, ns, U, h0s, g1s, chunk=None, stream: int = 0):
+    def __init__(self, selfenergy: int, ns, U, h0s, g1s, chunk=None, stream: int = 0,
+                 precision: int = FP64):
         self.lib = load()
         self.basis, self.flags = HUBBARD, 0
         self.ns = [int(x) for x in ns]
         n = len(self.ns)
         self.nb = max(self.ns)
-        self.desc = Desc(HUBBARD, selfenergy, FP64, 0, self.nb, 0.0)
+        self.desc = Desc(HUBBARD, selfenergy, precision, 0, self.nb, 0.0)
         h = [np.ascontiguousarray(a, np.complex128) for a in h0s]
         g = [np.ascontiguousarray(a, np.complex128) for a in g1s]
         ns_a = np.asarray(self.ns, np.int32)

@@ -432,6 +432,8 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     if (c->d.basis != G1G2_HUBBARD || c->d.selfenergy != G1G2_SOA || c->hub.ncl != 1)
         return set_error(c, G1G2_EUNSUPPORTED, "the adjoint covers the single-cluster Hubbard SOA system");
     if (c->hub.hdesc[0].ns > 64) return set_error(c, G1G2_EUNSUPPORTED, "adjoint supports ns <= 64");
+    if (c->d.precision != G1G2_FP64)
+        return set_error(c, G1G2_EUNSUPPORTED, "the adjoint runs in binary64 only");
     adj_free(c);
     AdjState* st = new AdjState();
     c->adj = st;

@@ -25,6 +25,18 @@ __host__ __device__ __forceinline__ cd cfma_conjb(cd acc, cd a, cd b) {
     return cmk(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
 }
 
+// Complex loads and stores from binary64 or binary32 storage; arithmetic is
+// always binary64.
+__device__ __forceinline__ cd ld_c(const cd* __restrict__ p, long long i) { return p[i]; }
+__device__ __forceinline__ cd ld_c(const float2* __restrict__ p, long long i) {
+    const float2 v = p[i];
+    return cmk((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ void st_c(cd* __restrict__ p, long long i, cd v) { p[i] = v; }
+__device__ __forceinline__ void st_c(float2* __restrict__ p, long long i, cd v) {
+    p[i] = make_float2((float)v.x, (float)v.y);
+}
+
 // Classical RK4 as a sequence of fused register updates.  With registers y
 // (state at t_n), acc (running sum) and a stage input/output pair:
 //   RK_RHS   : out = f
@@ -34,23 +46,25 @@ __host__ __device__ __forceinline__ cd cfma_conjb(cd acc, cd a, cd b) {
 // with cb = dt/6, dt/3, dt/3, dt/6 and cc = dt/2, dt/2, dt for stages 1..4.
 enum { RK_RHS = 0, RK_FIRST = 1, RK_MID = 2, RK_LAST = 3 };
 
-template <int MODE>
+// The stage output `out` may be binary32 storage (mixed precision); y and acc
+// are always binary64.
+template <int MODE, typename TO>
 __device__ __forceinline__ void rk_update(int e, cd f, cd yin_if_first, const cd* __restrict__ y,
-                                          cd* __restrict__ acc, cd* __restrict__ out,
+                                          cd* __restrict__ acc, TO* __restrict__ out,
                                           double cb, double cc) {
     if (MODE == RK_RHS) {
-        out[e] = f;
+        st_c(out, e, f);
     } else if (MODE == RK_FIRST) {
         cd yv = yin_if_first;
         acc[e] = cmk(fma(cb, f.x, yv.x), fma(cb, f.y, yv.y));
-        out[e] = cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y));
+        st_c(out, e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
     } else if (MODE == RK_MID) {
         cd av = acc[e];
         cd yv = y[e];
         acc[e] = cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y));
-        out[e] = cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y));
+        st_c(out, e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
     } else {
         cd av = acc[e];
-        out[e] = cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y));
+        st_c(out, e, cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y)));
     }
 }

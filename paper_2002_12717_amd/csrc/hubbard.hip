@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -29,8 +30,8 @@ using hub::make_cl;
 // Right-hand side of one element e = ((i ns + j) ns + k) ns + l of the
 // cluster's block A = G2^{up down up down}:
 //   dA/dt = -i ( [h2_{ud}, A] + Psi + [L^pp - (L^pp_klij)^*] )
-template <bool TPP>
-__device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const cd* __restrict__ A, int i, int j, int k,
+template <bool TPP, typename TA>
+__device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, int i, int j, int k,
                                          int l, int e, cd aval) {
     const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
     const int* nbu = a.nbr;
@@ -42,20 +43,20 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const cd* __restrict__ A, 
     cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), aval);
     for (int q = 0; q < z; ++q) {
         int p = nbu[i * z + q];
-        if (p >= 0) c = cfma(c, hu[i * z + q], A[e + (p - i) * ns3]);
+        if (p >= 0) c = cfma(c, hu[i * z + q], ld_c(A, e + (p - i) * ns3));
     }
     for (int q = 0; q < z; ++q) {
         int p = nbd[j * z + q];
-        if (p >= 0) c = cfma(c, hd[j * z + q], A[e + (p - j) * ns2]);
+        if (p >= 0) c = cfma(c, hd[j * z + q], ld_c(A, e + (p - j) * ns2));
     }
     cd r = cmk(0.0, 0.0);
     for (int q = 0; q < z; ++q) {  // sum_p A_ijpl h_pk, h_pk = conj(h_kp)
         int p = nbu[k * z + q];
-        if (p >= 0) r = cfma_conjb(r, A[e + (p - k) * ns], hu[k * z + q]);
+        if (p >= 0) r = cfma_conjb(r, ld_c(A, e + (p - k) * ns), hu[k * z + q]);
     }
     for (int q = 0; q < z; ++q) {  // sum_p A_ijkp h_pl
         int p = nbd[l * z + q];
-        if (p >= 0) r = cfma_conjb(r, A[e + (p - l)], hd[l * z + q]);
+        if (p >= 0) r = cfma_conjb(r, ld_c(A, e + (p - l)), hd[l * z + q]);
     }
     c = csub(c, r);
     // source Psi = U Phi / (i)^2 with Phi from eq:soa-cubic-scheme
@@ -73,10 +74,10 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const cd* __restrict__ A, 
     if (TPP) {
         // L_ijkl = delta_ij U A_iikl + i U (Y_ji A_iikl + X_ij A_jjkl)   (Sec. VII.C)
         const int kl = k * ns + l, ij = i * ns + j;
-        cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
+        cd dii = ld_c(A, (i * ns + i) * ns2 + kl), djj = ld_c(A, (j * ns + j) * ns2 + kl);
         cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
         if (i == j) l1 = cadd(l1, dii);
-        cd dkk = A[(k * ns + k) * ns2 + ij], dll = A[(l * ns + l) * ns2 + ij];
+        cd dkk = ld_c(A, (k * ns + k) * ns2 + ij), dll = ld_c(A, (l * ns + l) * ns2 + ij);
         cd ylk = Y[l * ns + k], xkl = X[k * ns + l];
         cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
         if (k == l) l2 = cadd(l2, dkk);
@@ -87,7 +88,8 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const cd* __restrict__ A, 
 
 // G1 equations (eq:eom_g1_hubbard): dG^{<,s}/dt = -i([h^{HF,s}, G^{<,s}] + I^s + I^s^dagger)
 // with I^up_ij = -i U A_iiji and I^down_ij = -i U A_iiij.
-__device__ __forceinline__ cd hub_g1_rhs(const Cl& a, const cd* __restrict__ A, int sig, int i, int j) {
+template <typename TA>
+__device__ __forceinline__ cd hub_g1_rhs(const Cl& a, const TA* __restrict__ A, int sig, int i, int j) {
     const int ns = a.ns, z = a.zmax;
     const cd* G = sig ? a.Y : a.X;
     const int* nb = a.nbr + sig * ns * z;
@@ -105,11 +107,11 @@ __device__ __forceinline__ cd hub_g1_rhs(const Cl& a, const cd* __restrict__ A, 
     }
     cd Iij, Iji;
     if (sig == 0) {
-        Iij = A[((i * ns + i) * ns + j) * ns + i];
-        Iji = A[((j * ns + j) * ns + i) * ns + j];
+        Iij = ld_c(A, ((i * ns + i) * ns + j) * ns + i);
+        Iji = ld_c(A, ((j * ns + j) * ns + i) * ns + j);
     } else {
-        Iij = A[((i * ns + i) * ns + i) * ns + j];
-        Iji = A[((j * ns + j) * ns + j) * ns + i];
+        Iij = ld_c(A, ((i * ns + i) * ns + i) * ns + j);
+        Iji = ld_c(A, ((j * ns + j) * ns + j) * ns + i);
     }
     // I = -i U A...,  I + I^dagger with (I^dagger)_ij = conj(I_ji)
     cd coll = cadd(cscale(cmul_mi(Iij), a.U), cconj(cscale(cmul_mi(Iji), a.U)));
@@ -136,24 +138,35 @@ struct StageArgs {
     int* flag;
 };
 
-template <int MODE, bool TPP>
+// Storage of the G2 stage registers.  Mixed precision keeps the stage copies
+// (the inputs of stages 2-4 and the outputs of stages 1-3) in binary32; y and
+// acc, and every G1 register, stay binary64.
+template <int MODE, bool MIXED>
+struct StageTypes {
+    using In = typename std::conditional<MIXED && (MODE == RK_MID || MODE == RK_LAST), float2, cd>::type;
+    using Out = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
+};
+
+template <int MODE, bool TPP, bool MIXED>
 __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
+    using TI = typename StageTypes<MODE, MIXED>::In;
+    using TO = typename StageTypes<MODE, MIXED>::Out;
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
     const int ns = d.ns;
-    const cd* A = s.in2 + d.g2off;
+    const TI* A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     if (w.start >= 0) {
         const cd* y = s.y2 + d.g2off;
         cd* acc = s.acc2 + d.g2off;
-        cd* out = s.out2 + d.g2off;
+        TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
         for (int e = w.start + threadIdx.x; e < w.end; e += blockDim.x) {
             int l = e % ns, tq = e / ns;
             int k = tq % ns;
             tq /= ns;
             int j = tq % ns, i = tq / ns;
-            cd av = A[e];
-            cd f = hub_g2_rhs<TPP>(a, A, i, j, k, l, e, av);
+            cd av = ld_c(A, e);
+            cd f = hub_g2_rhs<TPP, TI>(a, A, i, j, k, l, e, av);
             rk_update<MODE>(e, f, av, y, acc, out, s.cb, s.cc);
         }
     } else {
@@ -200,8 +213,10 @@ __device__ __forceinline__ double wave_uniform(double v) {
 }
 __device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x), wave_uniform(v.y)); }
 
-template <int MODE, bool TPP>
+template <int MODE, bool TPP, bool MIXED>
 __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
+    using TI = typename StageTypes<MODE, MIXED>::In;
+    using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
     __shared__ cd eu[NS_MAX_ROW], ed[NS_MAX_ROW];
     // neighbour tables padded to ZR entries per site: a missing neighbour points
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     const ClusterDesc d = s.desc[w.cluster];
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
-    const cd* __restrict__ A = s.in2 + d.g2off;
+    const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     const int tid = threadIdx.x;
     if (w.start < 0) {  // G1 update of the cluster
         const cd* g1 = s.in1 + d.g1off;
@@ -251,7 +266,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     const cd* __restrict__ Y = a.Y;
     const cd* y = s.y2 + d.g2off;
     cd* acc = s.acc2 + d.g2off;
-    cd* out = s.out2 + d.g2off;
+    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
     const int rpw = min(64 / ns, ns);
     const int nkb = (ns + rpw - 1) / rpw;
     const int lane = tid & 63;
@@ -284,14 +299,14 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 xil = X[i * ns + l];
                 yjl = Y[j * ns + l];
                 yil = Y[i * ns + l];
-                if (TPP) dll = A[(l * ns + l) * ns2 + slice];
+                if (TPP) dll = ld_c(A, (l * ns + l) * ns2 + slice);
             }
         }
         const int k = kb * rpw + sub;
         const bool act = lane_ok && k < ns;
         const int kk = act ? k : 0;
         const int e = slice * ns2 + kk * ns + l;
-        const cd av = act ? A[e] : cmk(0.0, 0.0);
+        const cd av = act ? ld_c(A, e) : cmk(0.0, 0.0);
         cd vl[ZR];
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
@@ -304,15 +319,15 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
                 r = cfma_conjb(r, vl[q], hd[l * ZR + q]);
-                r = cfma_conjb(r, A[e + (nbu[kk * ZR + q] - kk) * ns], hu[kk * ZR + q]);
+                r = cfma_conjb(r, ld_c(A, e + (nbu[kk * ZR + q] - kk) * ns), hu[kk * ZR + q]);
             }
             const cd ek = eu[kk];
             cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
             c = csub(c, r);
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
-                c = cfma(c, hu[i * ZR + q], A[e + (nbu[i * ZR + q] - i) * ns3]);
-                c = cfma(c, hd[j * ZR + q], A[e + (nbd[j * ZR + q] - j) * ns2]);
+                c = cfma(c, hu[i * ZR + q], ld_c(A, e + (nbu[i * ZR + q] - i) * ns3));
+                c = cfma(c, hd[j * ZR + q], ld_c(A, e + (nbd[j * ZR + q] - j) * ns2));
             }
             // source (eq:soa-cubic-scheme)
             const cd xik = X[i * ns + kk], xjk = X[j * ns + kk], yjk = Y[j * ns + kk];
@@ -324,10 +339,10 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
             if (TPP) {   // ladder (Sec. VII.C) and its partner
                 const int kl = kk * ns + l;
-                cd dii = A[(i * ns + i) * ns2 + kl], djj = A[(j * ns + j) * ns2 + kl];
+                cd dii = ld_c(A, (i * ns + i) * ns2 + kl), djj = ld_c(A, (j * ns + j) * ns2 + kl);
                 cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
                 if (i == j) l1 = cadd(l1, dii);
-                cd dkk = A[(kk * ns + kk) * ns2 + slice];
+                cd dkk = ld_c(A, (kk * ns + kk) * ns2 + slice);
                 cd ylk = cmk(-ykl.x, ykl.y);
                 cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
                 if (kk == l) l2 = cadd(l2, dkk);
@@ -368,18 +383,26 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     return s;
 }
 
+template <int MODE, bool TPP, bool MIXED>
+void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
+    if (c->hub.rows)
+        hipLaunchKernelGGL((hub_row_kernel<MODE, TPP, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+    else
+        hipLaunchKernelGGL((hub_stage_kernel<MODE, TPP, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+}
+
 template <int MODE>
 g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
     const bool tpp = c->d.selfenergy == G1G2_TPP;
-    if (c->hub.rows) {
-        if (tpp)
-            hipLaunchKernelGGL((hub_row_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
-        else
-            hipLaunchKernelGGL((hub_row_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
-    } else if (tpp)
-        hipLaunchKernelGGL((hub_stage_kernel<MODE, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
-    else
-        hipLaunchKernelGGL((hub_stage_kernel<MODE, false>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+    // a plain right-hand side (g1g2_rhs) always works on binary64 caller buffers
+    const bool mixed = MODE != RK_RHS && c->d.precision == G1G2_MIXED;
+    if (tpp) {
+        if (mixed) launch_stage_t<MODE, true, true>(c, s);
+        else launch_stage_t<MODE, true, false>(c, s);
+    } else {
+        if (mixed) launch_stage_t<MODE, false, true>(c, s);
+        else launch_stage_t<MODE, false, false>(c, s);
+    }
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "hub_stage");
     return G1G2_OK;
