@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "ctx.h"
@@ -143,8 +144,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                q_re[row * LD + col] = acc.re[r4];
-                q_im[row * LD + col] = acc.im[r4];
+                q_re[row * LD + col] = acc.re(r4);
+                q_im[row * LD + col] = acc.im(r4);
             }
         }
         __syncthreads();
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re[r4], acc.im[r4]);
+                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re(r4), acc.im(r4));
             }
         }
         __syncthreads();
@@ -188,6 +189,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
     double* __restrict__ ipart) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
+    using Acc = typename std::conditional<SH::TPW == 1, CAcc4<T>, CAcc<T>>::type;
     constexpr bool STAGE = NB <= 32;
     __shared__ T b0_re[NB * LD], b0_im[NB * LD], b1_re[NB * LD], b1_im[NB * LD];
     __shared__ SmallOps<T, NB, STAGE> ops;
@@ -217,13 +219,37 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
         for (int r4 = 0; r4 < 4; ++r4) isum[t][0][r4] = isum[t][1][r4] = 0.0;
 
     const int bfirst = xcd_block(blockIdx.x, gridDim.x);
+    // Nb <= 32: the next operand blocks are prefetched into registers, so their
+    // global loads overlap the matrix-core work of the current phase
+    constexpr bool PRE = SH::TPW == 1;
+    constexpr int PER = PRE ? NB * NB / SH::THREADS : 1;
+    T pv_re[PER], pv_im[PER], pc_re[PER], pc_im[PER];
+    auto fetch = [&](auto src, T* re, T* im) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) ldc(src + threadIdx.x + q * SH::THREADS, re[q], im[q]);
+    };
+    auto put = [&](const T* re, const T* im, T* dre, T* dim) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = threadIdx.x + q * SH::THREADS, r = idx / NB, cc = idx % NB;
+            dre[r * LD + cc] = re[q];
+            dim[r * LD + cc] = im[q];
+        }
+    };
+    if constexpr (PRE)
+        if (bfirst < NB * NB) fetch(vt + (size_t)bfirst * NB * NB, pv_re, pv_im);
     for (int blk = bfirst; blk < NB * NB; blk += gridDim.x) {
-        stage_block<T, S, NB>(vt + (size_t)blk * NB * NB, b0_re, b0_im);
+        if constexpr (PRE) {
+            put(pv_re, pv_im, b0_re, b0_im);
+            fetch(g2 + (size_t)blk * NB * NB, pc_re, pc_im);
+        } else {
+            stage_block<T, S, NB>(vt + (size_t)blk * NB * NB, b0_re, b0_im);
+        }
         __syncthreads();
         // P = G> Vt_ab
         for (int t = 0; t < SH::TPW; ++t) {
             const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
-            CAcc<T> acc;
+            Acc acc;
             acc.clear();
             cgemm_tile<T, NB>(
                 acc, G,
@@ -235,16 +261,22 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                b1_re[row * LD + col] = acc.re[r4];
-                b1_im[row * LD + col] = acc.im[r4];
+                b1_re[row * LD + col] = acc.re(r4);
+                b1_im[row * LD + col] = acc.im(r4);
             }
         }
         __syncthreads();
-        stage_block<T, cd, NB>(g2 + (size_t)blk * NB * NB, b0_re, b0_im);  // C = G2 row block
+        if constexpr (PRE) {   // C = G2 row block; the next Vt block starts loading
+            put(pc_re, pc_im, b0_re, b0_im);
+            const int nxt = blk + gridDim.x;
+            if (nxt < NB * NB) fetch(vt + (size_t)nxt * NB * NB, pv_re, pv_im);
+        } else {
+            stage_block<T, cd, NB>(g2 + (size_t)blk * NB * NB, b0_re, b0_im);  // C = G2 row block
+        }
         __syncthreads();
         for (int t = 0; t < SH::TPW; ++t) {
             const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
-            CAcc<T> acc;
+            Acc acc;
             acc.clear();
             // P G>^T
             cgemm_tile<T, NB>(
@@ -254,7 +286,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
                     m = b1_im[i * LD + k];
                 },
                 [&](int k, int j, T& r, T& m) { G(j, k, r, m); }, ti * 16, tj * 16);
-            acc.im = -acc.im;  // conj
+            acc.conj();
             // - h^T C
             cgemm_tile<T, NB>(
                 acc,
@@ -279,10 +311,10 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(dout + (size_t)blk * NB * NB + row * NB + col, acc.re[r4], acc.im[r4]);
+                stc(dout + (size_t)blk * NB * NB + row * NB + col, acc.re(r4), acc.im(r4));
             }
             // collision partial: Wc_ab C_ab^T
-            CAcc<T> ic;
+            Acc ic;
             ic.clear();
             const S* wc = wcoll + (size_t)blk * NB * NB;
             cgemm_tile<T, NB>(
@@ -294,8 +326,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
                 ti * 16, tj * 16);
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
-                isum[t][0][r4] += (double)ic.re[r4];
-                isum[t][1][r4] += (double)ic.im[r4];
+                isum[t][0][r4] += (double)ic.re(r4);
+                isum[t][1][r4] += (double)ic.im(r4);
             }
         }
         __syncthreads();
@@ -449,8 +481,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* _
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
                 // i * acc
-                stc(heps + (size_t)blk * NB * NB + row * NB + col, -(double)acc.im[r4],
-                    (double)acc.re[r4]);
+                stc(heps + (size_t)blk * NB * NB + row * NB + col, -(double)acc.im(r4),
+                    (double)acc.re(r4));
             }
         }
         __syncthreads();
@@ -524,8 +556,8 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
             for (int a = 0; a < 2; ++a)
                 for (int b = 0; b < 2; ++b) {
                     for (int r4 = 0; r4 < 4; ++r4) {
-                        accd[a][b][0][r4] += (double)acc[a][b].re[r4];
-                        accd[a][b][1][r4] += (double)acc[a][b].im[r4];
+                        accd[a][b][0][r4] += (double)acc[a][b].re(r4);
+                        accd[a][b][1][r4] += (double)acc[a][b].im(r4);
                     }
                     acc[a][b].clear();
                 }
@@ -538,8 +570,8 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
                 const int row = bm + wm + a * 16 + tile_row<T>(r4);
                 const int col = bn + wn + b * 16 + tile_col();
                 const int i = row / nbp, k = row % nbp, j = col / nbp, l = col % nbp;
-                double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)acc[a][b].re[r4];
-                double vi = sizeof(T) == 4 ? accd[a][b][1][r4] : (double)acc[a][b].im[r4];
+                double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)acc[a][b].re(r4);
+                double vi = sizeof(T) == 4 ? accd[a][b][1][r4] : (double)acc[a][b].im(r4);
                 pim[(((size_t)i * nbp + j) * nbp + k) * nbp + l] = make_double2(vr, vi);
             }
 }
@@ -604,31 +636,42 @@ __global__ __launch_bounds__(256) void gen_obs_kernel(const cd* __restrict__ gl,
         for (int q = 0; q < 4; ++q) res[q] = sh[q][0];
 }
 
-__global__ __launch_bounds__(256) void herm_kernel(const cd* __restrict__ A, int n, long long nn,
+// Symmetry residuals of an n x n pair matrix A (n = nbp^2): per block the
+// maxima of |A_(r,c) - conj(A_(c,r))| (eq:Gsymm_b), of |A| and of
+// |A_ijkl - A_jilk| (eq:Gsymm_a).
+__global__ __launch_bounds__(256) void herm_kernel(const cd* __restrict__ A, int nbp, long long nn,
                                                   double* __restrict__ part) {
-    __shared__ double s1[256], s2[256];
-    double m1 = 0, m2 = 0;
+    __shared__ double s1[256], s2[256], s3[256];
+    const long long n = (long long)nbp * nbp;
+    double m1 = 0, m2 = 0, m3 = 0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
          e += (long long)gridDim.x * blockDim.x) {
-        long long r = e / n, col = e % n;
-        cd v = A[e], w = A[col * n + r];
-        double dx = v.x - w.x, dy = v.y + w.y;
+        const long long r = e / n, col = e % n;
+        const cd v = A[e], w = A[col * n + r];
+        const double dx = v.x - w.x, dy = v.y + w.y;
         m1 = fmax(m1, sqrt(dx * dx + dy * dy));
         m2 = fmax(m2, sqrt(v.x * v.x + v.y * v.y));
+        const long long rx = (r % nbp) * nbp + r / nbp, cx = (col % nbp) * nbp + col / nbp;
+        const cd u = A[rx * n + cx];
+        const double ex = v.x - u.x, ey = v.y - u.y;
+        m3 = fmax(m3, sqrt(ex * ex + ey * ey));
     }
     s1[threadIdx.x] = m1;
     s2[threadIdx.x] = m2;
+    s3[threadIdx.x] = m3;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) {
             s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + s]);
             s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + s]);
+            s3[threadIdx.x] = fmax(s3[threadIdx.x], s3[threadIdx.x + s]);
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s1[0];
-        part[2 * blockIdx.x + 1] = s2[0];
+        part[3 * blockIdx.x] = s1[0];
+        part[3 * blockIdx.x + 1] = s2[0];
+        part[3 * blockIdx.x + 2] = s3[0];
     }
 }
 
@@ -844,17 +887,18 @@ g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o) {
     HIP_OK(c, hipGetLastError());
     const int n = g.nbp * g.nbp;
     const int nblk = 256;
-    hipLaunchKernelGGL(herm_kernel, dim3(nblk), dim3(256), 0, c->stream, s.g2, n, (long long)n * n,
+    hipLaunchKernelGGL(herm_kernel, dim3(nblk), dim3(256), 0, c->stream, s.g2, g.nbp, (long long)n * n,
                        c->dscratch + 8);
     HIP_OK(c, hipGetLastError());
-    std::vector<double> h(8 + 2 * nblk);
+    std::vector<double> h(8 + 3 * nblk);
     HIP_OK(c, hipMemcpyAsync(h.data(), c->dscratch, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                              c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    double m1 = 0, m2 = 0;
+    double m1 = 0, m2 = 0, m3 = 0;
     for (int b = 0; b < nblk; ++b) {
-        m1 = std::max(m1, h[8 + 2 * b]);
-        m2 = std::max(m2, h[8 + 2 * b + 1]);
+        m1 = std::max(m1, h[8 + 3 * b]);
+        m2 = std::max(m2, h[8 + 3 * b + 1]);
+        m3 = std::max(m3, h[8 + 3 * b + 2]);
     }
     o->N[0] = h[0];
     o->N[1] = 0.0;
@@ -864,6 +908,7 @@ g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o) {
     o->E_tot = h[1] + h[2] + h[3];
     o->docc = 0.0;
     o->herm_resid = m2 > 0 ? m1 / m2 : 0.0;
+    o->exch_resid = m2 > 0 ? m3 / m2 : 0.0;
     return G1G2_OK;
 }
 

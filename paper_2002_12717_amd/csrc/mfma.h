@@ -39,11 +39,14 @@ struct MF<float> {
 
 template <typename T>
 struct CAcc {
-    typename MF<T>::acc re, im;
+    typename MF<T>::acc vr, vi;
     __device__ __forceinline__ void clear() {
-        re = MF<T>::zero();
-        im = MF<T>::zero();
+        vr = MF<T>::zero();
+        vi = MF<T>::zero();
     }
+    __device__ __forceinline__ T re(int r) const { return vr[r]; }
+    __device__ __forceinline__ T im(int r) const { return vi[r]; }
+    __device__ __forceinline__ void conj() { vi = -vi; }
 };
 
 // c += A(i0.., 0..K) * B(0..K, j0..) for a 16x16 tile.  fa(i, k, re, im) and
@@ -57,10 +60,55 @@ __device__ __forceinline__ void cgemm_tile(CAcc<T>& c, const FA& fa, const FB& f
         T ar, ai, br, bi;
         fa(i0 + li, k0 + lk, ar, ai);
         fb(k0 + lk, j0 + li, br, bi);
-        c.re = MF<T>::mac(ar, br, c.re);
-        c.re = MF<T>::mac(-ai, bi, c.re);
-        c.im = MF<T>::mac(ar, bi, c.im);
-        c.im = MF<T>::mac(ai, br, c.im);
+        c.vr = MF<T>::mac(ar, br, c.vr);
+        c.vr = MF<T>::mac(-ai, bi, c.vr);
+        c.vi = MF<T>::mac(ar, bi, c.vi);
+        c.vi = MF<T>::mac(ai, br, c.vi);
+    }
+}
+
+// The same tile product with four independent accumulation chains
+// (Ar Br, Ai Bi, Ar Bi, Ai Br): the four matrix-core instructions of a k-step
+// do not depend on each other, so none waits for the previous result.  It
+// pays where a wave owns a single output tile; with several tiles per wave the
+// two-chain form keeps enough independent work at fewer registers.
+template <typename T>
+struct CAcc4 {
+    typename MF<T>::acc rr, ii, ri, ir;
+    __device__ __forceinline__ void clear() {
+        rr = MF<T>::zero();
+        ii = MF<T>::zero();
+        ri = MF<T>::zero();
+        ir = MF<T>::zero();
+    }
+    // c += a b for one complex operand pair of a k-step
+    __device__ __forceinline__ void mac(T ar, T ai, T br, T bi) {
+        rr = MF<T>::mac(ar, br, rr);
+        ii = MF<T>::mac(ai, bi, ii);
+        ri = MF<T>::mac(ar, bi, ri);
+        ir = MF<T>::mac(ai, br, ir);
+    }
+    __device__ __forceinline__ T re(int r) const { return rr[r] - ii[r]; }
+    __device__ __forceinline__ T im(int r) const { return ri[r] + ir[r]; }
+    __device__ __forceinline__ void conj() {
+        ri = -ri;
+        ir = -ir;
+    }
+};
+
+template <typename T, int K, typename FA, typename FB>
+__device__ __forceinline__ void cgemm_tile(CAcc4<T>& c, const FA& fa, const FB& fb, int i0, int j0) {
+    const int lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        T ar, ai, br, bi;
+        fa(i0 + li, k0 + lk, ar, ai);
+        fb(k0 + lk, j0 + li, br, bi);
+        c.rr = MF<T>::mac(ar, br, c.rr);
+        c.ii = MF<T>::mac(ai, bi, c.ii);
+        c.ri = MF<T>::mac(ar, bi, c.ri);
+        c.ir = MF<T>::mac(ai, br, c.ir);
     }
 }
 
