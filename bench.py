@@ -10,7 +10,7 @@ One "step" = one full RK4 step (four right-hand sides) of G1 and G2.  The
 binary64 path is the headline value; the mixed path (binary32 matrix-core
 contractions, binary64 state) is reported beside it with its error against
 the binary64 run.  Other workloads of the paper's shape are available with
---workload (hubbard_chain, hubbard_2d, general_gw).
+--workload (hubbard_chain, hubbard_2d, hubbard_batch, hubbard_adjoint, general_gw).
 
 Prints ONE JSON line.
 """
@@ -325,6 +325,94 @@ def run_batch(args, torch, B):
     return out
 
 
+def cpu_baseline_adjoint(seconds: float = 15.0):
+    """The oracle's gradient (torch autograd through the RK4 map, CPU, binary64)
+    on the reduced 4x4 driven cluster, as many steps as fit the time budget,
+    extrapolated to the 8x8 cluster by the G2 element count (64^4 / 16^4)."""
+    import numpy as np
+    import torch
+    from oracle import adjoint as OA
+    from workloads import adjoint_system
+    nthreads = torch.get_num_threads()
+    s = adjoint_system(lx=4, ly=4, nmodes=16, T=0.4, dt=0.01)
+    a = np.full(s.ns, 1.0 / s.ns)
+    b = np.zeros(s.ns)
+    n = 10
+    t0 = time.perf_counter()
+    OA.loss_and_gradient(s, a, b, nsteps=n)
+    el = time.perf_counter() - t0
+    if el < seconds / 4:
+        n = max(n, int(n * seconds / max(el, 1e-3) / 2))
+        t0 = time.perf_counter()
+        OA.loss_and_gradient(s, a, b, nsteps=n)
+        el = time.perf_counter() - t0
+    scale = (16.0 / 64.0) ** 4
+    return {"value": round(n / el * scale, 6), "unit": "gradient RK4 steps/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"autograd gradient of the mean double occupation over {n} RK4 steps of the "
+                      f"4x4 driven cluster ({el:.1f} s), scaled by (16/64)^4 to the 8x8 cluster"}
+
+
+def run_adjoint(args, torch, B):
+    """Gradients of the final-time mean double occupation and of the density
+    imbalance of the driven 8x8 cluster with respect to the 64 drive
+    coefficients and U: one checkpointed forward pass and two reverse sweeps."""
+    import numpy as np
+    from workloads import adjoint_system
+    s = adjoint_system()
+    ns = s.ns
+    stream = torch.cuda.Stream()
+    p = B.Propagator(B.HUBBARD, B.SOA, ns, s.h0, s.g1, U=s.U, stream=stream.cuda_stream)
+    d = s.drive
+    p.set_drive(d.x, d.c, d.t_center, d.tau)
+    nmodes = len(d.c)
+    a_docc, b_docc = np.full(ns, 1.0 / ns), np.zeros(ns)
+    npart = float(np.trace(-1j * s.g1[0]).real + np.trace(-1j * s.g1[1]).real)
+    side = (d.x < 0).astype(np.float64) - (d.x > 0).astype(np.float64)
+    a_imb, b_imb = np.zeros(ns), side / npart
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.forward_checkpointed(s.dt, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L1, g1c, g1U = p.adjoint(a_docc, b_docc, nmodes)
+    t2 = time.perf_counter()
+    L2, g2c, g2U = p.adjoint(a_imb, b_imb, nmodes)
+    t3 = time.perf_counter()
+    obs = p.observables()
+    prof = p.profile(s.dt, args.profile_steps)
+    p.close()
+    fwd_ms = (t1 - t0) * 1e3
+    rev_ms = (t3 - t1) * 1e3 / 2
+    total_ms = fwd_ms + 2 * rev_ms
+    ms_step = total_ms / args.steps
+    tot_ms, cnt = prof["hub_stage"]
+    bytes_per_launch = 64.0 * float(ns) ** 4
+    achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
+    config = {"workload": f"gradient of the final-time mean double occupation and density imbalance "
+                          f"of the driven 8x8 Hubbard cluster (SOA, U={s.U}, {nmodes} Gaussian pulses) "
+                          f"with respect to the pulse coefficients and U, checkpointed discrete adjoint "
+                          f"of RK4, dt={s.dt}",
+              "ns": ns, "U": s.U, "dt": s.dt, "nsteps": args.steps, "selfenergy": "SOA",
+              "parallelism": "single GPU"}
+    out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    out["unit"] = "gradient RK4 steps/s"
+    out.update({
+        "forward_ms": round(fwd_ms, 3), "reverse_ms_per_loss": round(rev_ms, 3),
+        "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "bytes_per_launch": bytes_per_launch, "launches": cnt},
+        "losses": {"docc": L1, "imbalance": L2},
+        "grad_norms": {"docc_c": float(np.linalg.norm(g1c)), "docc_U": g1U,
+                       "imbalance_c": float(np.linalg.norm(g2c)), "imbalance_U": g2U},
+        "observables": {k: obs[k] for k in ("t", "E_tot", "docc", "imbalance")},
+    })
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_adjoint()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,7 +421,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--workload", default="general_soa",
                     choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d",
-                             "hubbard_batch"])
+                             "hubbard_batch", "hubbard_adjoint"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -349,6 +437,8 @@ def main():
         out = run_general(args, torch, B, gw=True)
     elif args.workload == "hubbard_batch":
         out = run_batch(args, torch, B)
+    elif args.workload == "hubbard_adjoint":
+        out = run_adjoint(args, torch, B)
     else:
         out = run_hubbard(args, torch, B, args.workload)
     print(json.dumps(out), flush=True)

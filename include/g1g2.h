@@ -92,7 +92,13 @@ typedef struct {
     double E_corr;          /* correlation energy -1/2 Re sum w_ijkl G2_klij        */
     double E_tot;           /* E_kin + E_mf + E_corr                                */
     double docc;            /* Hubbard: mean double occupation                      */
-    double herm_resid;      /* max |G2_ijkl - conj(G2_klij)| / max |G2|            */
+    double herm_resid;      /* max |G2_ijkl - conj(G2_klij)| / max |G2| (eq:Gsymm_b) */
+    double exch_resid;      /* general: max |G2_ijkl - G2_jilk| / max |G2|
+                               (eq:Gsymm_a); Hubbard: 0 (the exchange partner of
+                               the stored up-down-up-down block is another block) */
+    double imbalance;       /* Hubbard: (N_left - N_right) / N with left/right the
+                               sites of negative/positive drive profile x_i
+                               (g1g2_set_drive); 0 without a drive profile      */
     int32_t diverged;       /* 1 once the divergence guard has fired                */
     int64_t step;           /* completed Runge-Kutta steps                          */
 } g1g2_obs;
@@ -170,8 +176,11 @@ g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void*
 /* Discrete adjoint of the Runge-Kutta propagation (single-cluster Hubbard,
  * SOA, with or without drive).  g1g2_forward_checkpointed advances the state
  * by nsteps steps of size dt exactly like g1g2_step_rk4 and keeps a device
- * copy of the state every `interval` steps (interval <= 0: ceil(sqrt(nsteps)));
- * device memory grows by about (nsteps/interval + interval + 8) states.
+ * copy of the state every `interval` steps (interval <= 0:
+ * ceil(sqrt(nsteps / 4))); g1g2_adjoint recomputes one segment at a time and
+ * keeps its states and Runge-Kutta stage states, so device memory grows by
+ * about (nsteps/interval + 4 interval + 8) states (a state of ns = 64 is
+ * 268 MB: 4000 steps hold about 70 GB).
  * g1g2_adjoint then returns the loss
  *   L = sum_i a[i] d_i(T) + sum_i b[i] (n^up_ii(T) + n^dn_ii(T)),
  *   n_ii = Im G^<_ii,  d_i = n^up_ii n^dn_ii - Re G2_iiii,

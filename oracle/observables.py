@@ -49,3 +49,13 @@ def hubbard_observables(h0u, h0d, U, X, Y, A, t=0.0):
                 N_dn=float(torch.real(torch.trace(nd))), E_kin=float(e_kin),
                 E_mf=float(e_mf), E_corr=float(e_corr), E_tot=float(e_kin + e_mf + e_corr),
                 docc=docc.detach(), herm_resid=float(herm))
+
+
+def hubbard_imbalance(X, Y, x):
+    """Density imbalance (N_left - N_right) / N, left/right being the sites with
+    negative/positive profile x_i (for the 8x8 drive x_i = i_x - 3.5 this is the
+    difference of the two halves of the cluster)."""
+    n = torch.real(torch.diagonal(-1j * X)) + torch.real(torch.diagonal(-1j * Y))
+    x = torch.as_tensor(x, dtype=torch.float64)
+    s = (x < 0).to(torch.float64) - (x > 0).to(torch.float64)
+    return float((s * n).sum() / n.sum())

@@ -31,7 +31,8 @@ class Desc(ctypes.Structure):
 class Obs(ctypes.Structure):
     _fields_ = [("t", c_double), ("N", c_double * 2), ("E_kin", c_double), ("E_mf", c_double),
                 ("E_corr", c_double), ("E_tot", c_double), ("docc", c_double),
-                ("herm_resid", c_double), ("diverged", c_int32), ("step", c_int64)]
+                ("herm_resid", c_double), ("exch_resid", c_double), ("imbalance", c_double),
+                ("diverged", c_int32), ("step", c_int64)]
 
 
 _SIGS = {
@@ -152,8 +153,8 @@ class Propagator:
         o = Obs()
         self._check(self.lib.g1g2_observables(self.ctx, ctypes.byref(o)))
         return dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
-                    E_tot=o.E_tot, docc=o.docc, herm_resid=o.herm_resid, diverged=o.diverged,
-                    step=o.step)
+                    E_tot=o.E_tot, docc=o.docc, herm_resid=o.herm_resid, exch_resid=o.exch_resid,
+                    imbalance=o.imbalance, diverged=o.diverged, step=o.step)
 
     def site_observables(self):
         nu, nd, dc = (np.zeros(self.nb) for _ in range(3))
@@ -254,7 +255,8 @@ class Batch(Propagator):
         obs = (Obs * len(self.ns))()
         self._check(self.lib.g1g2_batch_observables(self.ctx, obs))
         return [dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
-                     E_tot=o.E_tot, docc=o.docc, diverged=o.diverged, step=o.step) for o in obs]
+                     E_tot=o.E_tot, docc=o.docc, imbalance=o.imbalance, diverged=o.diverged,
+                     step=o.step) for o in obs]
 
     def get_cluster(self, c: int, with_g2: bool = True):
         ns = self.ns[c]

@@ -233,7 +233,7 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
     if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
     if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
-    c->nscratch = 8 + 2 * 256 + 3 * (int)nb + 64;
+    c->nscratch = 8 + 3 * 256 + 3 * (int)nb + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
 
     HostCopy hh0, hw;
@@ -449,7 +449,7 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
     if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
     if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
-    c->nscratch = 8 + 2 * 256 + 3 * nsmax + 64;
+    c->nscratch = 8 + 3 * 256 + 3 * nsmax + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
     std::vector<int> nsv(ns, ns + n), ch(n, 0);
     if (chunk)

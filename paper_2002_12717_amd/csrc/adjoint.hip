@@ -13,15 +13,17 @@
 //   g4 = dt/6 l, m4 = J(Y4)^T g4, g3 = dt/3 l + dt m4, m3 = J(Y3)^T g3,
 //   g2 = dt/3 l + dt/2 m3, m2 = J(Y2)^T g2, g1 = dt/6 l + dt/2 m2,
 //   m1 = J(Y1)^T g1,  l <- l + m1 + m2 + m3 + m4,
-// with the stage states Y_s recomputed from y_n (checkpointed every K steps,
-// each segment recomputed forward once).  The vector-Jacobian product of the
-// right-hand side of eq:g2-hubbard / eq:eom_g1_hubbard is split into
-//   adj_a   : the G2 cotangent (stencil of the commutator applied to the
-//             cotangent, which is its own adjoint up to conj of the diagonal,
-//             plus the collision-integral entries),
-//   adj_red : the source Psi (eq:soa-cubic-scheme) differentiated with respect
-//             to X and Y: six reductions over pairs of G2 indices,
-//   adj_g1  : the G1 cotangents, the diagonal of h^HF, dL/ds and dL/dU.
+// with y_n checkpointed every K steps; each segment is recomputed forward
+// once, keeping y_n and the stage states Y2, Y3, Y4 of every step in device
+// memory (four states per step of a segment).  The vector-Jacobian product of
+// the right-hand side of eq:g2-hubbard / eq:eom_g1_hubbard is split into
+//   adj_a_row : the G2 cotangent (stencil of the commutator applied to the
+//               cotangent, plus the collision-integral entries),
+//   adj_red, adj_lane_red : the source Psi (eq:soa-cubic-scheme)
+//               differentiated with respect to X and Y: six reductions over
+//               pairs of G2 indices, each reading contiguous rows,
+//   adj_e, adj_g1e, adj_gsum : the G1 cotangents, the diagonal of h^HF,
+//               dL/ds and dL/dU.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -51,6 +53,10 @@ struct AdjArgs {
     double alpha, beta;
     int init, has_next;
     cd* red;                    // reduction buffers (see adj_red)
+    cd* part;                   // partial sums of the lane reductions [3][nparts][ns][ns][2]
+    int pairs_per_part, nparts;
+    cd* ebar;                   // [2][ns] cotangents of the h^HF diagonals
+    double* gpart;              // [2 + blocks of adj_g1e]: partial dL/ds, dL/dU
     double* grads;              // [2]: dL/ds, dL/dU of this stage
 };
 
@@ -59,64 +65,10 @@ enum { R_X = 0, R_Y = 6, R_M02 = 12, R_M13 = 13, R_UP = 14, R_N = 15 };
 
 __device__ __forceinline__ cd cmul3(cd a, cd b, cd c) { return cmul(cmul(a, b), c); }
 
-// G2 cotangent: mu = conj(E) B + hop(B) + collision entries, B = i g.
-__global__ __launch_bounds__(256) void adj_a_kernel(AdjArgs s) {
-    const Cl& a = s.a;
-    const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, n4 = ns2 * ns2, z = a.zmax;
-    const int* nbu = a.nbr;
-    const int* nbd = a.nbr + ns * z;
-    const cd* hu = a.hop;
-    const cd* hd = a.hop + ns * z;
-    const cd* G = s.gin2;
-    const double gs = s.gscale;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
-        int l = e % ns, tq = e / ns;
-        int k = tq % ns;
-        tq /= ns;
-        int j = tq % ns, i = tq / ns;
-        cd ei = hf_diag(a, 0, i), ej = hf_diag(a, 1, j), ek = hf_diag(a, 0, k), el = hf_diag(a, 1, l);
-        cd E = cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y);
-        // hop stencil applied to g (B = i gs g is applied at the end)
-        cd hsum = cmul(cconj(E), G[e]);
-        for (int q = 0; q < z; ++q) {
-            int p = nbu[i * z + q];
-            if (p >= 0) hsum = cfma(hsum, hu[i * z + q], G[e + (p - i) * ns3]);
-        }
-        for (int q = 0; q < z; ++q) {
-            int p = nbd[j * z + q];
-            if (p >= 0) hsum = cfma(hsum, hd[j * z + q], G[e + (p - j) * ns2]);
-        }
-        for (int q = 0; q < z; ++q) {
-            int p = nbu[k * z + q];
-            if (p >= 0) hsum = csub(hsum, cmul(G[e + (p - k) * ns], cconj(hu[k * z + q])));
-        }
-        for (int q = 0; q < z; ++q) {
-            int p = nbd[l * z + q];
-            if (p >= 0) hsum = csub(hsum, cmul(G[e + (p - l)], cconj(hd[l * z + q])));
-        }
-        cd mu = cscale(cmul_i(hsum), gs);
-        // collision integrals: I^up_ik = -iU A_iiki, I^dn_il = -iU A_iiil;
-        // Ibar_ab = BX_ab + conj(BX_ba), Abar += i U Ibar.
-        if (j == i && l == i) {
-            cd bxa = cscale(cmul_i(s.gin1[i * ns + k]), gs), bxb = cscale(cmul_i(s.gin1[k * ns + i]), gs);
-            mu = cadd(mu, cscale(cmul_i(cadd(bxa, cconj(bxb))), a.U));
-        }
-        if (j == i && k == i) {
-            const cd* gy = s.gin1 + ns2;
-            cd bya = cscale(cmul_i(gy[i * ns + l]), gs), byb = cscale(cmul_i(gy[l * ns + i]), gs);
-            mu = cadd(mu, cscale(cmul_i(cadd(bya, cconj(byb))), a.U));
-        }
-        cd base = s.init ? s.lam2[e] : s.lacc2[e];
-        s.lacc2[e] = cadd(base, mu);
-        if (s.has_next) {
-            cd lv = s.lam2[e];
-            s.gnext2[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
-        }
-    }
-}
-
-// Source-term reductions.  One work-group per output pair (p0, p1) of KIND;
-// threads sum over the complementary pair (c, d).  B = i gs g, G(.) = conj(.).
+// Source-term reductions whose free pair excludes l (kinds 0, 1, 2; kinds 3,
+// 4, 5 are adj_lane_red_kernel).  One work-group per output pair (p0, p1);
+// threads sum over the complementary pair (c, d), which includes l, so the
+// loads are contiguous.  B = i gs g.
 template <int KIND>
 __global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
     __shared__ double sh[7][256];
@@ -131,12 +83,10 @@ __global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
     for (int cdx = threadIdx.x; cdx < ns2; cdx += blockDim.x) {
         const int c = cdx / ns, d = cdx % ns;
         int i, j, k, l;
+        static_assert(KIND >= 0 && KIND <= 2, "kinds 3-5 are adj_lane_red_kernel");
         if (KIND == 0) { i = p0; k = p1; j = c; l = d; }        // free (i,k)
         else if (KIND == 1) { i = p0; j = p1; k = c; l = d; }   // free (i,j)
-        else if (KIND == 2) { j = p0; k = p1; i = c; l = d; }   // free (j,k)
-        else if (KIND == 3) { k = p0; l = p1; i = c; j = d; }   // free (k,l)
-        else if (KIND == 4) { i = p0; l = p1; j = c; k = d; }   // free (i,l)
-        else { j = p0; l = p1; i = c; k = d; }                  // free (j,l)
+        else { j = p0; k = p1; i = c; l = d; }                  // free (j,k)
         const int e = ((i * ns + j) * ns + k) * ns + l;
         const cd B = cscale(cmul_i(s.gin2[e]), gs);
         if (KIND == 0) {
@@ -159,22 +109,9 @@ __global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
             cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
             cd psi1 = cadd(cscale(cmul(xik, yjl), dd), cmul_i(cadd(t1, t2)));
             up += psi1.x * B.x + psi1.y * B.y;   // Re(conj(psi1) B)
-        } else if (KIND == 2) {
+        } else {
             accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[i * ns + j], Y[j * ns + l]))), -U), B);
             accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[k * ns + l], X[i * ns + k]))), U), B);
-        } else if (KIND == 3) {
-            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[i * ns + l], Y[j * ns + l]))), U), B);
-            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[j * ns + k], X[i * ns + k]))), U), B);
-        } else if (KIND == 4) {
-            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[l * ns + k], Y[j * ns + l]))), U), B);
-            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[j * ns + i], X[i * ns + k]))), -U), B);
-        } else {
-            double dd = (double)(i == j) - (double)(k == l);
-            cd w = cscale(cconj(X[i * ns + k]), U * dd);
-            w = cadd(w, cscale(cmul_i(cconj(cmul(X[i * ns + j], X[j * ns + k]))), -U));
-            w = cadd(w, cscale(cmul_i(cconj(cmul(X[l * ns + k], X[i * ns + l]))), U));
-            accy = cfma(accy, w, B);
-            accm = cfma(accm, cconj(s.A[e]), B);
         }
     }
     const int t = threadIdx.x;
@@ -198,19 +135,174 @@ __global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
         if (KIND == 0) { R[(R_X + 0) * ns2 + ab] = vx; R[R_M02 * ns2 + ab] = vm; }
         else if (KIND == 1) { R[(R_X + 1) * ns2 + ab] = vx; R[(R_Y + 1) * ns2 + ba] = vy;
                               R[R_UP * ns2 + ab] = cmk(sh[6][0], 0.0); }
-        else if (KIND == 2) { R[(R_X + 2) * ns2 + ab] = vx; R[(R_Y + 2) * ns2 + ab] = vy; }
-        else if (KIND == 3) { R[(R_X + 3) * ns2 + ba] = vx; R[(R_Y + 3) * ns2 + ab] = vy; }
-        else if (KIND == 4) { R[(R_X + 4) * ns2 + ab] = vx; R[(R_Y + 4) * ns2 + ab] = vy; }
-        else { R[(R_Y + 5) * ns2 + ab] = vy; R[R_M13 * ns2 + ab] = vm; }
+        else { R[(R_X + 2) * ns2 + ab] = vx; R[(R_Y + 2) * ns2 + ab] = vy; }
     }
 }
 
-// G1 cotangents, diagonal of h^HF, dL/ds and dL/dU of one stage (one work-group).
-__global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
-    __shared__ cd ebu[64], ebd[64];
-    __shared__ double sh[3][256];
+// G2 cotangent mu = i gs [conj(E) g + hop stencil applied to g] + collision
+// entries (the commutator stencil is its own adjoint up to the conjugate of
+// the diagonal).  One wave per row g[i][j][k][:] (ns <= 64), lane = l.  The l-neighbours of the stencil are other lanes (cross-lane permute);
+// neighbour tables are staged in LDS padded to four entries (a missing
+// neighbour is the site itself with hopping 0), so all loads of a row issue
+// together.  Same result as adj_a_kernel up to summation order.
+__global__ __launch_bounds__(256) void adj_a_row_kernel(AdjArgs s, int rows_per_wave) {
+    constexpr int ZR = 4;
+    __shared__ cd eu[64], ed[64];
+    __shared__ int snb[2 * 64 * ZR];
+    __shared__ cd shp[2 * 64 * ZR];
     const Cl& a = s.a;
-    const int ns = a.ns, ns2 = ns * ns, z = a.zmax, t = threadIdx.x;
+    const int ns = a.ns, z = a.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < ns; q += blockDim.x) {
+        eu[q] = hf_diag(a, 0, q);
+        ed[q] = hf_diag(a, 1, q);
+    }
+    for (int q = tid; q < 2 * ns * ZR; q += blockDim.x) {
+        const int row = q / ZR, qq = q - row * ZR, site = row % ns;
+        const int p = qq < z ? a.nbr[row * z + qq] : -1;
+        snb[q] = p >= 0 ? p : site;
+        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    const int* nbu = snb;
+    const int* nbd = snb + ns * ZR;
+    const cd* hu = shp;
+    const cd* hd = shp + ns * ZR;
+    const cd* __restrict__ G = s.gin2;
+    const double gs = s.gscale;
+    const int lane = tid & 63;
+    const bool lane_ok = lane < ns;
+    const int l = lane_ok ? lane : 0;
+    int src[ZR];
+#pragma unroll
+    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? nbd[l * ZR + q] : lane;
+    const cd el = ed[l];
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (tid >> 6));
+    for (int r = 0; r < rows_per_wave; ++r) {
+        const int row = wave * rows_per_wave + r;
+        if (row >= ns3) break;
+        const int k = row % ns, ij = row / ns, j = ij % ns, i = ij / ns;
+        const int e = row * ns + l;
+        const cd g = lane_ok ? G[e] : cmk(0.0, 0.0);
+        cd vl[ZR];
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            vl[q].x = __shfl(g.x, src[q], 64);
+            vl[q].y = __shfl(g.y, src[q], 64);
+        }
+        if (!lane_ok) continue;
+        const cd ei = eu[i], ej = ed[j], ek = eu[k];
+        const cd E = cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y);
+        cd hsum = cmul(cconj(E), g);
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            hsum = cfma(hsum, hu[i * ZR + q], G[e + (nbu[i * ZR + q] - i) * ns3]);
+            hsum = cfma(hsum, hd[j * ZR + q], G[e + (nbd[j * ZR + q] - j) * ns2]);
+            hsum = csub(hsum, cmul(G[e + (nbu[k * ZR + q] - k) * ns], cconj(hu[k * ZR + q])));
+            hsum = csub(hsum, cmul(vl[q], cconj(hd[l * ZR + q])));
+        }
+        cd mu = cscale(cmul_i(hsum), gs);
+        if (j == i && l == i) {
+            cd bxa = cscale(cmul_i(s.gin1[i * ns + k]), gs), bxb = cscale(cmul_i(s.gin1[k * ns + i]), gs);
+            mu = cadd(mu, cscale(cmul_i(cadd(bxa, cconj(bxb))), a.U));
+        }
+        if (j == i && k == i) {
+            const cd* gy = s.gin1 + ns2;
+            cd bya = cscale(cmul_i(gy[i * ns + l]), gs), byb = cscale(cmul_i(gy[l * ns + i]), gs);
+            mu = cadd(mu, cscale(cmul_i(cadd(bya, cconj(byb))), a.U));
+        }
+        cd base = s.init ? s.lam2[e] : s.lacc2[e];
+        s.lacc2[e] = cadd(base, mu);
+        if (s.has_next) {
+            cd lv = s.lam2[e];
+            s.gnext2[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
+        }
+    }
+}
+
+// Source-term reductions whose free pair contains l (kinds 3, 4, 5 of
+// adj_red_kernel), with lane = l so that every load is a contiguous row.
+// Work-group (f, part): f is the other free index (k, i or j), part a range of
+// the summed pairs split over the four waves; per-part sums go to s.part and
+// adj_lane_fin_kernel adds them up.
+template <int KIND>
+__global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
+    __shared__ cd sh[4][2][64];
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns;
+    const int f = blockIdx.x % ns, part = blockIdx.x / ns;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool lane_ok = lane < ns;
+    const int l = lane_ok ? lane : 0;
+    const cd* X = a.X;
+    const cd* Y = a.Y;
+    const double U = a.U, gs = s.gscale;
+    cd v0 = cmk(0, 0), v1 = cmk(0, 0);
+    const int p0 = part * s.pairs_per_part, p1 = min(ns2, p0 + s.pairs_per_part);
+    if (lane_ok) {
+        for (int pr = p0 + wave; pr < p1; pr += 4) {
+            const int c = pr / ns, d = pr % ns;
+            int i, j, k;
+            if (KIND == 3) { k = f; i = c; j = d; }
+            else if (KIND == 4) { i = f; j = c; k = d; }
+            else { j = f; i = c; k = d; }
+            const int e = ((i * ns + j) * ns + k) * ns + l;
+            const cd B = cscale(cmul_i(s.gin2[e]), gs);
+            if (KIND == 3) {
+                v0 = cfma(v0, cscale(cmul_i(cconj(cmul(X[i * ns + l], Y[j * ns + l]))), U), B);
+                v1 = cfma(v1, cscale(cmul_i(cconj(cmul(Y[j * ns + k], X[i * ns + k]))), U), B);
+            } else if (KIND == 4) {
+                v0 = cfma(v0, cscale(cmul_i(cconj(cmul(X[l * ns + k], Y[j * ns + l]))), U), B);
+                v1 = cfma(v1, cscale(cmul_i(cconj(cmul(Y[j * ns + i], X[i * ns + k]))), -U), B);
+            } else {
+                double dd = (double)(i == j) - (double)(k == l);
+                cd w = cscale(cconj(X[i * ns + k]), U * dd);
+                w = cadd(w, cscale(cmul_i(cconj(cmul(X[i * ns + j], X[j * ns + k]))), -U));
+                w = cadd(w, cscale(cmul_i(cconj(cmul(X[l * ns + k], X[i * ns + l]))), U));
+                v0 = cfma(v0, w, B);                       // Y cotangent
+                v1 = cfma(v1, cconj(s.A[e]), B);            // M13
+            }
+        }
+    }
+    sh[wave][0][lane] = v0;
+    sh[wave][1][lane] = v1;
+    __syncthreads();
+    if (wave == 0 && lane_ok) {
+        cd t0 = cadd(cadd(sh[0][0][lane], sh[1][0][lane]), cadd(sh[2][0][lane], sh[3][0][lane]));
+        cd t1 = cadd(cadd(sh[0][1][lane], sh[1][1][lane]), cadd(sh[2][1][lane], sh[3][1][lane]));
+        cd* P = s.part + ((size_t)((KIND - 3) * s.nparts + part) * ns2 + f * ns + l) * 2;
+        P[0] = t0;
+        P[1] = t1;
+    }
+}
+
+// Sums the per-part results of adj_lane_red_kernel into the reduction slots
+// (same slots and pair orientation as adj_red_kernel).
+__global__ __launch_bounds__(256) void adj_lane_fin_kernel(AdjArgs s) {
+    const int ns = s.a.ns, ns2 = ns * ns;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * ns2) return;
+    const int kind = 3 + t / ns2, fl = t % ns2, f = fl / ns, l = fl % ns;
+    cd v0 = cmk(0, 0), v1 = cmk(0, 0);
+    for (int p = 0; p < s.nparts; ++p) {
+        const cd* P = s.part + ((size_t)((kind - 3) * s.nparts + p) * ns2 + fl) * 2;
+        v0 = cadd(v0, P[0]);
+        v1 = cadd(v1, P[1]);
+    }
+    cd* R = s.red;
+    const int ab = f * ns + l, ba = l * ns + f;
+    if (kind == 3) { R[(R_X + 3) * ns2 + ba] = v0; R[(R_Y + 3) * ns2 + ab] = v1; }
+    else if (kind == 4) { R[(R_X + 4) * ns2 + ab] = v0; R[(R_Y + 4) * ns2 + ab] = v1; }
+    else { R[(R_Y + 5) * ns2 + ab] = v0; R[R_M13 * ns2 + ab] = v1; }
+}
+
+// Cotangents of the h^HF diagonals (ebar), the drive and U parts that depend
+// on them, and the sum of the U partials of the source (one work-group; four
+// threads per site).
+__global__ __launch_bounds__(256) void adj_e_kernel(AdjArgs s) {
+    __shared__ double sh[2][256];
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns, t = threadIdx.x;
     const cd* R = s.red;
     const double gs = s.gscale;
     const cd* X = a.X;
@@ -218,10 +310,10 @@ __global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
     const cd* gx = s.gin1;
     const cd* gy = s.gin1 + ns2;
     double sbar = 0.0, ubar = 0.0;
-    // ebar^up_i and ebar^dn_i
-    for (int i = t; i < ns; i += blockDim.x) {
-        cd eu = cmk(0, 0), ed = cmk(0, 0);
-        for (int p = 0; p < ns; ++p) {
+    const int i = t >> 2, sub = t & 3;
+    cd eu = cmk(0, 0), ed = cmk(0, 0);
+    if (i < ns) {
+        for (int p = sub; p < ns; p += 4) {
             // (BX X^H - X^H BX)_ii with BX = i gs gX
             cd bx_ip = cscale(cmul_i(gx[i * ns + p]), gs), bx_pi = cscale(cmul_i(gx[p * ns + i]), gs);
             eu = cadd(eu, csub(cmul(bx_ip, cconj(X[i * ns + p])), cmul(cconj(X[p * ns + i]), bx_pi)));
@@ -230,19 +322,55 @@ __global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
             eu = cadd(eu, csub(R[R_M02 * ns2 + i * ns + p], R[R_M02 * ns2 + p * ns + i]));
             ed = cadd(ed, csub(R[R_M13 * ns2 + i * ns + p], R[R_M13 * ns2 + p * ns + i]));
         }
-        ebu[i] = eu;
-        ebd[i] = ed;
-        sbar += a.xdrv[i] * (eu.x + ed.x);
+    }
+    // sum the four partial sums of a site (lanes 4i .. 4i+3)
+    for (int o = 1; o < 4; o <<= 1) {
+        eu.x += __shfl_xor(eu.x, o, 64);
+        eu.y += __shfl_xor(eu.y, o, 64);
+        ed.x += __shfl_xor(ed.x, o, 64);
+        ed.y += __shfl_xor(ed.y, o, 64);
+    }
+    if (i < ns && sub == 0) {
+        s.ebar[i] = eu;
+        s.ebar[ns + i] = ed;
+        sbar = a.xdrv[i] * (eu.x + ed.x);
         // e^up_i = ... - i U Y_ii, e^dn_i = ... - i U X_ii: Ubar += Re(conj(-i Y_ii) ebar)
         cd myi = cmul_mi(Y[i * ns + i]), mxi = cmul_mi(X[i * ns + i]);
-        ubar += myi.x * eu.x + myi.y * eu.y + mxi.x * ed.x + mxi.y * ed.y;
+        ubar = myi.x * eu.x + myi.y * eu.y + mxi.x * ed.x + mxi.y * ed.y;
     }
-    __syncthreads();
     for (int q = t; q < ns2; q += blockDim.x) ubar += R[R_UP * ns2 + q].x;
-    for (int e = t; e < 2 * ns2; e += blockDim.x) {
+    sh[0][t] = sbar;
+    sh[1][t] = ubar;
+    __syncthreads();
+    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+        if (t < st) {
+            sh[0][t] += sh[0][t + st];
+            sh[1][t] += sh[1][t + st];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        s.gpart[0] = sh[0][0];
+        s.gpart[1] = sh[1][0];
+    }
+}
+
+// G1 cotangents, one thread per element of [X | Y]; partial dL/dU of the
+// collision integral per work-group into s.gpart[2 + block].
+__global__ __launch_bounds__(256) void adj_g1e_kernel(AdjArgs s) {
+    __shared__ double sh[256];
+    const Cl& a = s.a;
+    const int ns = a.ns, ns2 = ns * ns, z = a.zmax;
+    const cd* R = s.red;
+    const double gs = s.gscale;
+    const cd* gx = s.gin1;
+    const cd* gy = s.gin1 + ns2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double ubar = 0.0;
+    if (e < 2 * ns2) {
         const int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
         const cd* gg = sig ? gy : gx;
-        const cd* eb = sig ? ebu : ebd;    // X_ii enters e^dn, Y_ii enters e^up
+        const cd* eb = s.ebar + (sig ? 0 : ns);   // X_ii enters e^dn, Y_ii enters e^up
         const int* nb = a.nbr + sig * ns * z;
         const cd* hp = a.hop + sig * ns * z;
         // [h^H, B]_ij, B = i gs g
@@ -262,12 +390,10 @@ __global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
         for (int kd = sig ? 1 : 0; kd < (sig ? 6 : 5); ++kd) mu = cadd(mu, R[((sig ? R_Y : R_X) + kd) * ns2 + r]);
         if (i == j) mu = cadd(mu, cscale(cmul_i(eb[i]), a.U));
         // collision-integral part of dL/dU: I_ij = -i U A..., Ibar_ij = B_ij + conj(B_ji)
-        {
-            cd bb = cadd(cscale(cmul_i(gg[r]), gs), cconj(cscale(cmul_i(gg[j * ns + i]), gs)));
-            cd av = sig == 0 ? s.A[((i * ns + i) * ns + j) * ns + i] : s.A[((i * ns + i) * ns + i) * ns + j];
-            cd dI = cmul_mi(av);   // dI/dU
-            ubar += dI.x * bb.x + dI.y * bb.y;
-        }
+        cd bb = cadd(cscale(cmul_i(gg[r]), gs), cconj(cscale(cmul_i(gg[j * ns + i]), gs)));
+        cd av = sig == 0 ? s.A[((i * ns + i) * ns + j) * ns + i] : s.A[((i * ns + i) * ns + i) * ns + j];
+        cd dI = cmul_mi(av);   // dI/dU
+        ubar = dI.x * bb.x + dI.y * bb.y;
         cd base = s.init ? s.lam1[e] : s.lacc1[e];
         s.lacc1[e] = cadd(base, mu);
         if (s.has_next) {
@@ -275,20 +401,22 @@ __global__ __launch_bounds__(256) void adj_g1_kernel(AdjArgs s) {
             s.gnext1[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
         }
     }
-    sh[0][t] = sbar;
-    sh[1][t] = ubar;
+    sh[threadIdx.x] = ubar;
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if (t < st) {
-            sh[0][t] += sh[0][t + st];
-            sh[1][t] += sh[1][t + st];
-        }
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
-    if (t == 0) {
-        s.grads[0] = sh[0][0];
-        s.grads[1] = sh[1][0];
-    }
+    if (threadIdx.x == 0) s.gpart[2 + blockIdx.x] = sh[0];
+}
+
+// dL/ds and dL/dU of the stage from the partials (fixed summation order).
+__global__ void adj_gsum_kernel(AdjArgs s, int nblocks) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double u = s.gpart[1];
+    for (int b = 0; b < nblocks; ++b) u += s.gpart[2 + b];
+    s.grads[0] = s.gpart[0];
+    s.grads[1] = u;
 }
 
 // Terminal cotangent of the loss and its value.
@@ -319,12 +447,21 @@ struct AdjState {
     int interval = 0;
     double dt = 0.0, t0 = 0.0;
     int nck = 0;
-    std::vector<Regs> ckpt, seg;
-    Regs S2, S3, S4, LAM, LACC, CA, CB, DUMMY;
+    std::vector<Regs> ckpt;
+    // one segment of the forward pass, recomputed from its checkpoint: the
+    // state y_n and the stage states Y2, Y3, Y4 of every step
+    std::vector<Regs> seg, seg2, seg3, seg4;
+    Regs LAM, LACC, CA, CB;
     cd* red = nullptr;
+    cd* part = nullptr;        // lane-reduction partials
+    int nparts = 0, pairs_per_part = 0;
+    cd* ebar = nullptr;
+    double* gpart = nullptr;
     double* grads = nullptr;   // [4 nsteps][2]
     double* dev_ab = nullptr;  // weights a, b and the loss
 };
+
+constexpr int ADJ_PAIRS_PER_PART = 64;
 
 AdjState* adj_of(g1g2_ctx* c) { return reinterpret_cast<AdjState*>(c->adj); }
 
@@ -380,26 +517,35 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
     s.init = init;
     s.has_next = has_next;
     s.red = st->red;
+    s.part = st->part;
+    s.pairs_per_part = st->pairs_per_part;
+    s.nparts = st->nparts;
+    s.ebar = st->ebar;
+    s.gpart = st->gpart;
     s.grads = grads;
     return s;
 }
 
 g1g2_status vjp(g1g2_ctx* c, const AdjArgs& s) {
-    const int ns = s.a.ns;
-    const int n4 = ns * ns * ns * ns;
-    hipLaunchKernelGGL((adj_red_kernel<0>), dim3(ns * ns), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<1>), dim3(ns * ns), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<2>), dim3(ns * ns), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<3>), dim3(ns * ns), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<4>), dim3(ns * ns), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<5>), dim3(ns * ns), dim3(256), 0, c->stream, s);
+    const int ns = s.a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    hipLaunchKernelGGL((adj_red_kernel<0>), dim3(ns2), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<1>), dim3(ns2), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_red_kernel<2>), dim3(ns2), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_lane_red_kernel<3>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_lane_red_kernel<4>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL((adj_lane_red_kernel<5>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_lane_fin_kernel, dim3((3 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "adj_red");
-    int blocks = std::min((n4 + 255) / 256, 65536);
-    hipLaunchKernelGGL(adj_a_kernel, dim3(blocks), dim3(256), 0, c->stream, s);
+    constexpr int RPW = 4;
+    const int waves = (ns3 + RPW - 1) / RPW;
+    hipLaunchKernelGGL(adj_a_row_kernel, dim3((waves + 3) / 4), dim3(256), 0, c->stream, s, RPW);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "adj_a");
-    hipLaunchKernelGGL(adj_g1_kernel, dim3(1), dim3(256), 0, c->stream, s);
+    const int g1blocks = (2 * ns2 + 255) / 256;
+    hipLaunchKernelGGL(adj_e_kernel, dim3(1), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_g1e_kernel, dim3(g1blocks), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_gsum_kernel, dim3(1), dim3(64), 0, c->stream, s, g1blocks);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "adj_g1");
     return G1G2_OK;
@@ -415,10 +561,13 @@ g1g2_status stage_fwd(g1g2_ctx* c, int mode, double t, const Regs& in, const Reg
 void adj_free(g1g2_ctx* c) {
     AdjState* st = adj_of(c);
     if (!st) return;
-    for (auto& r : st->ckpt) free_reg(r);
-    for (auto& r : st->seg) free_reg(r);
-    for (Regs* r : {&st->S2, &st->S3, &st->S4, &st->LAM, &st->LACC, &st->CA, &st->CB, &st->DUMMY}) free_reg(*r);
+    for (auto* v : {&st->ckpt, &st->seg, &st->seg2, &st->seg3, &st->seg4})
+        for (auto& r : *v) free_reg(r);
+    for (Regs* r : {&st->LAM, &st->LACC, &st->CA, &st->CB}) free_reg(*r);
     if (st->red) (void)hipFree(st->red);
+    if (st->part) (void)hipFree(st->part);
+    if (st->ebar) (void)hipFree(st->ebar);
+    if (st->gpart) (void)hipFree(st->gpart);
     if (st->grads) (void)hipFree(st->grads);
     if (st->dev_ab) (void)hipFree(st->dev_ab);
     delete st;
@@ -438,7 +587,9 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     AdjState* st = new AdjState();
     c->adj = st;
     st->nsteps = nsteps;
-    st->interval = interval > 0 ? interval : std::max<int>(1, (int)std::ceil(std::sqrt((double)nsteps)));
+    // default: the interval that minimizes checkpoints + four states per segment step
+    st->interval = interval > 0 ? interval
+                                : std::max<int>(1, (int)std::ceil(std::sqrt((double)nsteps / 4.0)));
     st->dt = dt;
     st->t0 = c->t;
     st->nck = (int)((nsteps + st->interval - 1) / st->interval);
@@ -446,14 +597,21 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     st->ckpt.resize(st->nck + 1);       // last slot keeps the final state
     for (auto& r : st->ckpt)
         if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
-    st->seg.resize(st->interval);
-    for (auto& r : st->seg)
-        if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
-    for (Regs* r : {&st->S2, &st->S3, &st->S4, &st->LAM, &st->LACC, &st->CA, &st->CB, &st->DUMMY})
+    for (auto* v : {&st->seg, &st->seg2, &st->seg3, &st->seg4}) {
+        v->resize(st->interval);
+        for (auto& r : *v)
+            if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
+    }
+    for (Regs* r : {&st->LAM, &st->LACC, &st->CA, &st->CB})
         if ((s = alloc_reg(c, *r)) != G1G2_OK) return s;
     const int ns = c->hub.hdesc[0].ns;
     HIP_OK(c, hipMalloc(&st->red, (size_t)R_N * ns * ns * sizeof(cd)));
     HIP_OK(c, hipMemsetAsync(st->red, 0, (size_t)R_N * ns * ns * sizeof(cd), c->stream));
+    st->pairs_per_part = ADJ_PAIRS_PER_PART;
+    st->nparts = (ns * ns + ADJ_PAIRS_PER_PART - 1) / ADJ_PAIRS_PER_PART;
+    HIP_OK(c, hipMalloc(&st->part, (size_t)3 * st->nparts * ns * ns * 2 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&st->ebar, (size_t)2 * ns * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&st->gpart, (size_t)(2 + (2 * ns * ns + 255) / 256) * sizeof(double)));
     HIP_OK(c, hipMalloc(&st->grads, (size_t)4 * nsteps * 2 * sizeof(double)));
     HIP_OK(c, hipMalloc(&st->dev_ab, (size_t)(2 * ns + 8) * sizeof(double)));
     for (int q = 0; q < st->nck; ++q) {
@@ -489,30 +647,27 @@ g1g2_status g1g2_adjoint(g1g2_ctx* c, const double* wa, const double* wb, double
     for (int q = st->nck - 1; q >= 0; --q) {
         const int64_t n0 = (int64_t)q * st->interval;
         const int64_t n1 = std::min<int64_t>(n0 + st->interval, st->nsteps);
-        // recompute the segment forward, storing y_n
+        // recompute the segment forward, keeping y_n and the stage states of every step
         if ((s = copy_reg(c, c->y, st->ckpt[q])) != G1G2_OK) return s;
         for (int64_t n = n0; n < n1; ++n) {
-            if ((s = copy_reg(c, st->seg[n - n0], c->y)) != G1G2_OK) return s;
+            const int m = (int)(n - n0);
+            if ((s = copy_reg(c, st->seg[m], c->y)) != G1G2_OK) return s;
             const double t = st->t0 + (double)n * dt;
-            if (n + 1 < n1) {
-                if ((s = stage_fwd(c, RK_FIRST, t, c->y, c->y, c->acc, c->s0, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
-                if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, c->s0, c->y, c->acc, c->s1, dt / 3.0, dt / 2.0)) != G1G2_OK) return s;
-                if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, c->s1, c->y, c->acc, c->s0, dt / 3.0, dt)) != G1G2_OK) return s;
-                if ((s = stage_fwd(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0)) != G1G2_OK) return s;
-            }
+            if ((s = stage_fwd(c, RK_FIRST, t, c->y, c->y, c->acc, st->seg2[m], dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
+            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->seg2[m], c->y, c->acc, st->seg3[m], dt / 3.0, dt / 2.0)) != G1G2_OK) return s;
+            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->seg3[m], c->y, c->acc, st->seg4[m], dt / 3.0, dt)) != G1G2_OK) return s;
+            if (n + 1 < n1)
+                if ((s = stage_fwd(c, RK_LAST, t + dt, st->seg4[m], c->y, c->acc, c->y, dt / 6.0, 0.0)) != G1G2_OK) return s;
         }
-        // reverse over the segment
+        // reverse over the segment: Y2 = y + dt/2 k1, Y3 = y + dt/2 k2, Y4 = y + dt k3
         for (int64_t n = n1 - 1; n >= n0; --n) {
-            const Regs& y = st->seg[n - n0];
+            const int m = (int)(n - n0);
+            const Regs& y = st->seg[m];
             const double t = st->t0 + (double)n * dt;
-            // stage states Y2 = y + dt/2 k1, Y3 = y + dt/2 k2, Y4 = y + dt k3
-            if ((s = stage_fwd(c, RK_FIRST, t, y, y, st->DUMMY, st->S2, dt / 6.0, dt / 2.0)) != G1G2_OK) return s;
-            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->S2, y, st->DUMMY, st->S3, dt / 3.0, dt / 2.0)) != G1G2_OK) return s;
-            if ((s = stage_fwd(c, RK_MID, t + 0.5 * dt, st->S3, y, st->DUMMY, st->S4, dt / 3.0, dt)) != G1G2_OK) return s;
             double* g = st->grads + (size_t)8 * n;
-            if ((s = vjp(c, make_adj(c, t + dt, st->S4, lam, dt / 6.0, lam, lacc, st->CA, dt / 3.0, dt, 1, 1, g + 6))) != G1G2_OK) return s;
-            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->S3, st->CA, 1.0, lam, lacc, st->CB, dt / 3.0, dt / 2.0, 0, 1, g + 4))) != G1G2_OK) return s;
-            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->S2, st->CB, 1.0, lam, lacc, st->CA, dt / 6.0, dt / 2.0, 0, 1, g + 2))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + dt, st->seg4[m], lam, dt / 6.0, lam, lacc, st->CA, dt / 3.0, dt, 1, 1, g + 6))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg3[m], st->CA, 1.0, lam, lacc, st->CB, dt / 3.0, dt / 2.0, 0, 1, g + 4))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg2[m], st->CB, 1.0, lam, lacc, st->CA, dt / 6.0, dt / 2.0, 0, 1, g + 2))) != G1G2_OK) return s;
             if ((s = vjp(c, make_adj(c, t, y, st->CA, 1.0, lam, lacc, st->CB, 0.0, 0.0, 0, 0, g + 0))) != G1G2_OK) return s;
             std::swap(lam, lacc);
         }

@@ -417,16 +417,20 @@ __global__ __launch_bounds__(256) void hub_obs_kernel(const ClusterDesc* __restr
                                                      const cd* __restrict__ g1,
                                                      const cd* __restrict__ g2,
                                                      double* __restrict__ res) {
-    __shared__ double sh[6][256];
+    constexpr int NV = 7;
+    __shared__ double sh[NV][256];
     const ClusterDesc d = desc[blockIdx.x];
     const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, s_drive);
     const cd* A = g2 + d.g2off;
     const int ns = a.ns, z = a.zmax, tid = threadIdx.x;
-    double nu = 0, nd = 0, ekin = 0, emf = 0, ecorr = 0, docc = 0;
+    double nu = 0, nd = 0, ekin = 0, emf = 0, ecorr = 0, docc = 0, imb = 0;
     for (int i = tid; i < ns; i += blockDim.x) {
         double niu = a.X[i * ns + i].y, nid = a.Y[i * ns + i].y;
         nu += niu;
         nd += nid;
+        // sites with negative drive profile count as left, positive as right
+        const double xi = a.xdrv[i];
+        imb += (xi < 0.0 ? 1.0 : (xi > 0.0 ? -1.0 : 0.0)) * (niu + nid);
         for (int sig = 0; sig < 2; ++sig) {
             const cd* G = sig ? a.Y : a.X;
             double dii = a.d0[sig * ns + i] + a.s_drive * a.xdrv[i];
@@ -446,16 +450,16 @@ __global__ __launch_bounds__(256) void hub_obs_kernel(const ClusterDesc* __restr
         ecorr += -a.U * aiiii;
         docc += niu * nid - aiiii;
     }
-    double v[6] = {nu, nd, ekin, emf, ecorr, docc};
-    for (int q = 0; q < 6; ++q) sh[q][tid] = v[q];
+    double v[NV] = {nu, nd, ekin, emf, ecorr, docc, imb};
+    for (int q = 0; q < NV; ++q) sh[q][tid] = v[q];
     __syncthreads();
     for (int st = blockDim.x / 2; st > 0; st >>= 1) {
         if (tid < st)
-            for (int q = 0; q < 6; ++q) sh[q][tid] += sh[q][tid + st];
+            for (int q = 0; q < NV; ++q) sh[q][tid] += sh[q][tid + st];
         __syncthreads();
     }
     if (tid == 0)
-        for (int q = 0; q < 6; ++q) res[blockIdx.x * 8 + q] = sh[q][0];
+        for (int q = 0; q < NV; ++q) res[blockIdx.x * 8 + q] = sh[q][0];
 }
 
 // max |A_(r,c) - conj(A_(c,r))| and max |A| per block, A an n x n pair matrix
@@ -687,7 +691,9 @@ g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs
         ob.E_corr = r[4];
         ob.E_tot = r[2] + r[3] + r[4];
         ob.docc = r[5] / H.hdesc[cl].ns;
+        ob.imbalance = (r[0] + r[1]) > 0.0 ? r[6] / (r[0] + r[1]) : 0.0;
         ob.herm_resid = 0.0;
+        ob.exch_resid = 0.0;
     }
     return G1G2_OK;
 }

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import general as OG, hubbard as OH, integrate as OI
+from oracle import general as OG, hubbard as OH, integrate as OI, observables as OO
 from workloads import (adjoint_system, chain_hopping, factorized_w, gue, hubbard_chain_system,
                        random_g2, random_gless, rng, square_hopping, general_system)
 
@@ -93,6 +93,11 @@ def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol):
         errs_g.append(rel(g1, ref))
         og = p.observables()
         errs_e.append(abs(og["E_tot"] - rec[-1]["E_tot"]) / e_scale)
+        if system.drive is not None:
+            imb = OO.hubbard_imbalance(y[0], y[1], system.drive.x)
+            assert abs(og["imbalance"] - imb) < tol, (og["imbalance"], imb)
+        else:
+            assert og["imbalance"] == 0.0
         assert abs(tg - t) < 1e-12
     say(f"   max err G1 {max(errs_g):.2e}  max err E {max(errs_e):.2e}")
     assert max(errs_g) < tol and max(errs_e) < tol
@@ -206,6 +211,7 @@ def test_general_soa_invariants_full_size(lib):
     say(f"   N {o0['N'][0]} -> {o1['N'][0]}, E {o0['E_tot']} -> {o1['E_tot']}, Ecorr {o1['E_corr']:.3e}")
     assert abs(o1["N"][0] - o0["N"][0]) < 1e-10
     assert o1["herm_resid"] == 0.0
+    assert o1["exch_resid"] < 1e-12                 # eq:Gsymm_a kept to rounding
     assert abs(o1["E_tot"] - o0["E_tot"]) < 1e-6 * max(1.0, abs(o0["E_tot"]))
     assert abs(o1["E_corr"]) > 1e-6
     p.close()

@@ -370,3 +370,17 @@ def test_planted_mistakes_are_caught(monkeypatch):
                         lambda A, U: tuple(x.T for x in orig_coll(A, U)))
     bad = [_ed_error_hubbard(2, U, "soa") for U in us]
     assert _slope(us, bad) < 2.5 or max(bad) > 10 * max(base)   # transposed I
+
+
+def test_imbalance_definition():
+    """Density imbalance: zero for a uniform density, +1 with every particle on
+    the sites of negative profile, -1 on the positive side."""
+    x = np.array([-1.5, -0.5, 0.5, 1.5])
+    uni = np.diag(np.full(4, 0.5j))
+    assert abs(O.hubbard_imbalance(T(uni), T(uni), x)) < 1e-15
+    left = np.diag([1j, 1j, 0, 0])
+    assert abs(O.hubbard_imbalance(T(left), T(left), x) - 1.0) < 1e-15
+    flip = left[::-1, ::-1].copy()
+    assert abs(O.hubbard_imbalance(T(flip), T(flip), -x) - 1.0) < 1e-15
+    right = np.diag([0, 0, 1j, 1j])
+    assert abs(O.hubbard_imbalance(T(right), T(right), x) + 1.0) < 1e-15
