@@ -39,6 +39,9 @@ TRAFFIC = {
     "hub_stage/2d": {"bytes": 2.25e9, "src": "hubbard.hip", "sha1": "69605f286e68"},
 }
 
+SE_CODES = {"soa": lambda B: B.SOA, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
+
+
 def traffic(key):
     import hashlib
     t = TRAFFIC.get(key)
@@ -113,12 +116,12 @@ def cpu_baseline_general(system, seconds: float = 15.0):
                       f"{nthreads} threads, {el:.1f} s)"}
 
 
-def cpu_baseline_hubbard(system, seconds: float = 15.0):
+def cpu_baseline_hubbard(system, seconds: float = 15.0, selfenergy: str = "soa"):
     import torch
     from oracle import integrate as OI
     nthreads = torch.get_num_threads()
-    f = OI.hubbard_rhs_fn(system, "soa")
-    y = OI.hubbard_initial(system, "soa")
+    f = OI.hubbard_rhs_fn(system, selfenergy)
+    y = OI.hubbard_initial(system, selfenergy)
     y = list(OI.rk4_step(f, 0.0, y, system.dt))
     n, t0 = 0, time.perf_counter()
     while True:
@@ -206,7 +209,9 @@ def run_hubbard(args, torch, B, kind):
     system = hubbard_chain_system() if kind == "hubbard_chain" else adjoint_system()
     ns = system.ns
     stream = torch.cuda.Stream()
-    p = B.Propagator(B.HUBBARD, B.SOA, ns, system.h0, system.g1, U=system.U, stream=stream.cuda_stream)
+    se = args.selfenergy or "soa"
+    p = B.Propagator(B.HUBBARD, SE_CODES[se](B), ns, system.h0, system.g1, U=system.U,
+                     stream=stream.cuda_stream)
     if system.drive is not None:
         d = system.drive
         p.set_drive(d.x, d.c, d.t_center, d.tau)
@@ -221,8 +226,8 @@ def run_hubbard(args, torch, B, kind):
     bytes_per_launch = 64.0 * n4
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
     name = "1D chain, 8 sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
-    config = {"workload": f"Hubbard SOA G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
-              "ns": ns, "U": system.U, "dt": system.dt, "selfenergy": "SOA",
+    config = {"workload": f"Hubbard {se.upper()} G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
+              "ns": ns, "U": system.U, "dt": system.dt, "selfenergy": se.upper(),
               "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     out.update({
@@ -235,11 +240,11 @@ def run_hubbard(args, torch, B, kind):
         "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
     })
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_hubbard(system)
+        out["cpu_baseline"] = cpu_baseline_hubbard(system, selfenergy=se)
     return out
 
 
-def cpu_baseline_batch(clusters, seconds: float = 15.0):
+def cpu_baseline_batch(clusters, seconds: float = 15.0, selfenergy: str = "tpp"):
     """Oracle on the host: one RK4 step per cluster for the first clusters of the
     batch until the time budget is spent; the whole-batch rate is extrapolated
     with the G2 element count (the oracle's per-step cost is proportional to it)."""
@@ -250,8 +255,8 @@ def cpu_baseline_batch(clusters, seconds: float = 15.0):
     el_done, q = 0, 0
     while q < len(clusters) and time.perf_counter() - t0 < seconds:
         c = clusters[q]
-        f = OI.hubbard_rhs_fn(c, "tpp")
-        y = OI.hubbard_initial(c, "tpp")
+        f = OI.hubbard_rhs_fn(c, selfenergy)
+        y = OI.hubbard_initial(c, selfenergy)
         OI.rk4_step(f, 0.0, y, c.dt)
         el_done += c.ns ** 4
         q += 1
@@ -273,9 +278,10 @@ def run_batch(args, torch, B):
     chunks = autotune.chunks_for(ns)
     stream = torch.cuda.Stream()
     dt = clusters[0].dt
+    se = args.selfenergy or "tpp"
     res = {}
     for prec in ("fp64", "mixed"):
-        b = B.Batch(B.TPP, ns, [c.U for c in clusters], [c.h0 for c in clusters],
+        b = B.Batch(SE_CODES[se](B), ns, [c.U for c in clusters], [c.h0 for c in clusters],
                     [c.g1 for c in clusters], chunk=chunks, stream=stream.cuda_stream,
                     precision=B.FP64 if prec == "fp64" else B.MIXED)
         ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
@@ -299,9 +305,9 @@ def run_batch(args, torch, B):
     err_e = max(abs(m["E_tot"] - f["E_tot"]) / max(abs(f["E_tot"]), 1.0)
                 for m, f in zip(mx["obs"], f64["obs"]))
     config = {"workload": f"ragged batch of {len(ns)} periodic 2D Hubbard clusters (Lx,Ly in 3..6), "
-                          f"TPP, dt={dt}, RK4, one launch per stage, graph-captured steps",
+                          f"{se.upper()}, dt={dt}, RK4, one launch per stage, graph-captured steps",
               "clusters": len(ns), "g2_elements": int(n4), "ns_min": min(ns), "ns_max": max(ns),
-              "selfenergy": "TPP", "chunk_per_class": autotune.load_table().get("chunk_per_class"),
+              "selfenergy": se.upper(), "chunk_per_class": autotune.load_table().get("chunk_per_class"),
               "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     out.update({
@@ -321,7 +327,7 @@ def run_batch(args, torch, B):
         "diverged": any(bool(o["diverged"]) for o in f64["obs"]),
     })
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_batch(clusters)
+        out["cpu_baseline"] = cpu_baseline_batch(clusters, selfenergy=se)
     return out
 
 
@@ -422,6 +428,9 @@ def main():
     ap.add_argument("--workload", default="general_soa",
                     choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d",
                              "hubbard_batch", "hubbard_adjoint"])
+    ap.add_argument("--selfenergy", default=None, choices=["soa", "tpp", "tph"],
+                    help="Hubbard workloads only: override the workload's selfenergy "
+                         "(hubbard_batch: TPP, hubbard_chain/hubbard_2d: SOA)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -52,8 +52,11 @@ typedef enum {
 /* Selfenergy closing the G2 equation:
  *   SOA: second Born, eq:result_eom_soa (source Psi^-).
  *   GW : eq:g2-eq-gw-pi (source Psi without exchange unless G1G2_GW_EXCHANGE).
- *   TPP: particle-particle T matrix, eq:g2-eq-tpp-lambda.                         */
-typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2 } g1g2_selfenergy;
+ *   TPP: particle-particle T matrix, eq:g2-eq-tpp-lambda.
+ *   TPH: particle-hole T matrix, eq:g2-eq-tph-lambda.
+ * Implemented: general basis SOA, GW; Hubbard basis SOA, TPP, TPH.  Other
+ * combinations return G1G2_EUNSUPPORTED.                                        */
+typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3 } g1g2_selfenergy;
 
 /* GENERAL: arbitrary orthonormal basis with a four-index w (Sec. III.C).
  * HUBBARD: Fermi-Hubbard model with on-site U (Sec. III.D); h0 per spin may be
@@ -154,7 +157,7 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * size and U) propagated together: every Runge-Kutta stage of the whole batch
  * is one kernel launch over a flat work list, and g1g2_step_rk4 replays
  * captured HIP graphs of whole steps when a stream is given.  desc supplies
- * basis (HUBBARD), selfenergy (SOA or TPP) and precision (FP64 or MIXED); per cluster
+ * basis (HUBBARD), selfenergy (SOA, TPP or TPH) and precision (FP64 or MIXED); per cluster
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning

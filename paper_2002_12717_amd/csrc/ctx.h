@@ -27,6 +27,7 @@ struct ClusterDesc {
     int d0off;          // offset of its [2][ns] diagonal of h0
     int xoff;           // offset of its [ns] drive profile
     long long g2off;    // offset of its G2 block in a G2 register
+    long long doff;     // TPH: offset (in units of ns^3 pairs) of its diagonal tensors
     double U;
 };
 
@@ -45,6 +46,9 @@ struct HubbardData {
     WorkItem* work = nullptr;      // device work list
     int nwork = 0;
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
+    WorkItem* dwork = nullptr;     // TPH: work list of the diagonal gather
+    int ndwork = 0;
+    cd* diag = nullptr;            // TPH: per cluster R [ns]^3 and S [ns]^3
     std::vector<int> chunk;        // elements of G2 per work-group, per cluster
     int* nbr = nullptr;            // concatenated neighbour tables
     cd* hop = nullptr;

@@ -27,10 +27,14 @@ using hub::Cl;
 using hub::hf_diag;
 using hub::make_cl;
 
+// Selfenergies of the stage kernels.
+enum { SE_SOA = 0, SE_TPP = 1, SE_TPH = 2 };
+
 // Right-hand side of one element e = ((i ns + j) ns + k) ns + l of the
 // cluster's block A = G2^{up down up down}:
-//   dA/dt = -i ( [h2_{ud}, A] + Psi + [L^pp - (L^pp_klij)^*] )
-template <bool TPP, typename TA>
+//   dA/dt = -i ( [h2_{ud}, A] + Psi + [L - (L_klij)^*] ),
+// L the particle-particle (TPP) or particle-hole (TPH) ladder, none for SOA.
+template <int SE, typename TA>
 __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, int i, int j, int k,
                                          int l, int e, cd aval) {
     const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
@@ -71,7 +75,16 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, 
     cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
     cd psi = cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U));
     c = cadd(c, psi);
-    if (TPP) {
+    if (SE == SE_TPH) {
+        // L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)   (Sec. VII.C)
+        cd a1 = ld_c(A, ((i * ns + j) * ns + k) * ns + i), a2 = ld_c(A, ((l * ns + j) * ns + k) * ns + l);
+        cd l1 = cmul_i(csub(cmul(yil, a1), cmul(xil, a2)));
+        cd b1 = ld_c(A, ((k * ns + l) * ns + i) * ns + k), b2 = ld_c(A, ((j * ns + l) * ns + i) * ns + j);
+        cd ykj = Y[k * ns + j], xkj = X[k * ns + j];
+        cd l2 = cmul_i(csub(cmul(ykj, b1), cmul(xkj, b2)));
+        c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+    }
+    if (SE == SE_TPP) {
         // L_ijkl = delta_ij U A_iikl + i U (Y_ji A_iikl + X_ij A_jjkl)   (Sec. VII.C)
         const int kl = k * ns + l, ij = i * ns + j;
         cd dii = ld_c(A, (i * ns + i) * ns2 + kl), djj = ld_c(A, (j * ns + j) * ns2 + kl);
@@ -136,6 +149,7 @@ struct StageArgs {
     cd* out2;
     double cb, cc;
     int* flag;
+    const cd* diag;   // TPH: per cluster R [ns]^3 then S [ns]^3 of the stage input
 };
 
 // Storage of the G2 stage registers.  Mixed precision keeps the stage copies
@@ -147,7 +161,7 @@ struct StageTypes {
     using Out = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
 };
 
-template <int MODE, bool TPP, bool MIXED>
+template <int MODE, int SE, bool MIXED>
 __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
@@ -166,7 +180,7 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
             tq /= ns;
             int j = tq % ns, i = tq / ns;
             cd av = ld_c(A, e);
-            cd f = hub_g2_rhs<TPP, TI>(a, A, i, j, k, l, e, av);
+            cd f = hub_g2_rhs<SE, TI>(a, A, i, j, k, l, e, av);
             rk_update<MODE>(e, f, av, y, acc, out, s.cb, s.cc);
         }
     } else {
@@ -186,6 +200,29 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
                 if (bad) atomicOr(s.flag, 1);
             }
         }
+    }
+}
+
+// TPH: the "diagonal" elements of the stage input that the particle-hole
+// ladder needs, A_cabc (first index = last index), in two layouts,
+//   R[a][b][c] = A[c][a][b][c],   S[b][c][a] = A[c][a][b][c],
+// so that the stage kernel reads them as contiguous rows.  A work item is a
+// range [start, end) of the ns^3 triples (a, b, c) of one cluster.
+template <typename TI>
+__global__ __launch_bounds__(256) void hub_diag_kernel(const ClusterDesc* __restrict__ desc,
+                                                      const WorkItem* __restrict__ dwork,
+                                                      const cd* __restrict__ in2, cd* __restrict__ diag) {
+    const WorkItem w = dwork[blockIdx.x];
+    const ClusterDesc d = desc[w.cluster];
+    const int ns = d.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const TI* A = reinterpret_cast<const TI*>(in2) + d.g2off;
+    cd* R = diag + 2 * d.doff;
+    cd* S = R + ns3;
+    for (int t = w.start + threadIdx.x; t < w.end; t += blockDim.x) {
+        const int a = t / ns2, b = (t / ns) % ns, c = t % ns;
+        const cd v = ld_c(A, ((c * ns + a) * ns + b) * ns + c);
+        R[t] = v;
+        S[(b * ns + c) * ns + a] = v;
     }
 }
 
@@ -213,8 +250,9 @@ __device__ __forceinline__ double wave_uniform(double v) {
 }
 __device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x), wave_uniform(v.y)); }
 
-template <int MODE, bool TPP, bool MIXED>
+template <int MODE, int SE, bool MIXED>
 __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
+    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH;
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
@@ -283,8 +321,10 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     int cur = -1;
     int i = 0, j = 0;
     cd ei = cmk(0, 0), ej = cmk(0, 0), xij = cmk(0, 0), yji = cmk(0, 0);
-    cd xil = cmk(0, 0), yjl = cmk(0, 0), yil = cmk(0, 0), dll = cmk(0, 0);
+    cd xil = cmk(0, 0), yjl = cmk(0, 0), yil = cmk(0, 0), dll = cmk(0, 0), sijl = cmk(0, 0);
     double dij = 0.0;
+    const cd* __restrict__ DR = TPH ? s.diag + 2 * d.doff : nullptr;   // R[a][b][c]
+    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;               // S[b][c][a]
     for (; u < w.end; u += 4) {
         if (slice != cur) {   // wave-uniform
             cur = slice;
@@ -300,6 +340,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 yjl = Y[j * ns + l];
                 yil = Y[i * ns + l];
                 if (TPP) dll = ld_c(A, (l * ns + l) * ns2 + slice);
+                if (TPH) sijl = DS[(i * ns + j) * ns + l];
             }
         }
         const int k = kb * rpw + sub;
@@ -348,6 +389,16 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 if (kk == l) l2 = cadd(l2, dkk);
                 c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
             }
+            if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner
+                //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
+                //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
+                const cd rjki = DR[(j * ns + kk) * ns + i], rjkl = DR[(j * ns + kk) * ns + l];
+                const cd sikl = DS[(i * ns + kk) * ns + l];
+                const cd ykj = Y[kk * ns + j], xkj = X[kk * ns + j];
+                cd l1 = cmul_i(csub(cmul(yil, rjki), cmul(xil, rjkl)));
+                cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
+                c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+            }
             rk_update<MODE>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
         }
         kb += 4;
@@ -380,28 +431,37 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.cb = cb;
     s.cc = cc;
     s.flag = c->dflag;
+    s.diag = H.diag;
     return s;
 }
 
-template <int MODE, bool TPP, bool MIXED>
+template <int MODE, int SE, bool MIXED>
 void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
+    if (SE == SE_TPH) {
+        using TI = typename StageTypes<MODE, MIXED>::In;
+        hipLaunchKernelGGL((hub_diag_kernel<TI>), dim3(c->hub.ndwork), dim3(256), 0, c->stream, c->hub.desc,
+                           c->hub.dwork, s.in2, c->hub.diag);
+    }
     if (c->hub.rows)
-        hipLaunchKernelGGL((hub_row_kernel<MODE, TPP, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+        hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     else
-        hipLaunchKernelGGL((hub_stage_kernel<MODE, TPP, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+        hipLaunchKernelGGL((hub_stage_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+}
+
+template <int MODE, int SE>
+void launch_stage_p(g1g2_ctx* c, const StageArgs& s, bool mixed) {
+    if (mixed) launch_stage_t<MODE, SE, true>(c, s);
+    else launch_stage_t<MODE, SE, false>(c, s);
 }
 
 template <int MODE>
 g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
-    const bool tpp = c->d.selfenergy == G1G2_TPP;
     // a plain right-hand side (g1g2_rhs) always works on binary64 caller buffers
     const bool mixed = MODE != RK_RHS && c->d.precision == G1G2_MIXED;
-    if (tpp) {
-        if (mixed) launch_stage_t<MODE, true, true>(c, s);
-        else launch_stage_t<MODE, true, false>(c, s);
-    } else {
-        if (mixed) launch_stage_t<MODE, false, true>(c, s);
-        else launch_stage_t<MODE, false, false>(c, s);
+    switch (c->d.selfenergy) {
+        case G1G2_TPP: launch_stage_p<MODE, SE_TPP>(c, s, mixed); break;
+        case G1G2_TPH: launch_stage_p<MODE, SE_TPH>(c, s, mixed); break;
+        default: launch_stage_p<MODE, SE_SOA>(c, s, mixed); break;
     }
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "hub_stage");
@@ -530,7 +590,7 @@ double HubbardData::drive_value(double t) const {
 
 void hub_free(g1g2_ctx* c) {
     HubbardData& H = c->hub;
-    void* ptrs[] = {H.desc, H.work, H.nbr, H.hop, H.d0, H.xdrv};
+    void* ptrs[] = {H.desc, H.work, H.dwork, H.diag, H.nbr, H.hop, H.d0, H.xdrv};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     std::vector<double> dc = H.drive_c, dtc = H.drive_tc, dx = H.drive_x;
@@ -549,7 +609,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     std::vector<int> nbr_all;
     std::vector<cd> hop_all;
     std::vector<double> d0_all;
-    std::vector<WorkItem> work, g1work;
+    std::vector<WorkItem> work, g1work, dwork;
     std::vector<int> chunks(ncl);
     bool rowk = true;
     for (int cl = 0; cl < ncl; ++cl) {
@@ -569,7 +629,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             }
     }
     long long g2off = 0;
-    long long g1off = 0, xoff = 0;
+    long long g1off = 0, xoff = 0, doff = 0;
     for (int cl = 0; cl < ncl; ++cl) {
         const int ns = nsv[cl];
         const cd* h0 = h0s[cl];
@@ -599,6 +659,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         d.d0off = (int)d0_all.size();
         d.xoff = (int)xoff;
         d.g2off = g2off;
+        d.doff = doff;
         d.U = Uv[cl];
         for (int r = 0; r < 2 * ns; ++r)
             for (int q = 0; q < zmax; ++q) {
@@ -626,6 +687,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                 work.push_back({cl, (int)st, (int)std::min<long long>(n4, st + ch)});
         }
         g1work.push_back({cl, -1, -1});
+        const int n3 = ns * ns * ns;
+        for (int t0 = 0; t0 < n3; t0 += 4096) dwork.push_back({cl, t0, std::min(n3, t0 + 4096)});
+        doff += n3;
         g2off += n4;
         g1off += 2LL * ns * ns;
         xoff += ns;
@@ -635,6 +699,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     hub_free(c);
     H.ncl = ncl;
     H.rows = rowk;
+    H.ndwork = (int)dwork.size();
     H.hdesc = desc;
     H.chunk = chunks;
     H.nwork = (int)work.size();
@@ -642,6 +707,10 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     g1g2_status s;
     if ((s = upload(c, &H.desc, desc)) != G1G2_OK) return s;
     if ((s = upload(c, &H.work, work)) != G1G2_OK) return s;
+    if (c->d.selfenergy == G1G2_TPH) {
+        if ((s = upload(c, &H.dwork, dwork)) != G1G2_OK) return s;
+        HIP_OK(c, hipMalloc(&H.diag, std::max<long long>(2 * doff, 1) * sizeof(cd)));
+    }
     if ((s = upload(c, &H.nbr, nbr_all)) != G1G2_OK) return s;
     if ((s = upload(c, &H.hop, hop_all)) != G1G2_OK) return s;
     if ((s = upload(c, &H.d0, d0_all)) != G1G2_OK) return s;

@@ -47,8 +47,13 @@ def _hubbard_h0(kind, r):
     return np.stack([h + np.diag(r.uniform(-0.5, 0.5, ns)), h + np.diag(r.uniform(-0.5, 0.5, ns))])
 
 
+def _se(se):
+    from paper_2002_12717_amd import binding as B
+    return {"soa": B.SOA, "tpp": B.TPP, "tph": B.TPH, "gw": B.GW}[se]
+
+
 @pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2"])
-@pytest.mark.parametrize("se", ["soa", "tpp"])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
 def test_hubbard_rhs_parity(lib, kind, se):
     from paper_2002_12717_amd import binding as B
     say(f"[hubbard rhs] lattice={kind} se={se}")
@@ -59,7 +64,7 @@ def test_hubbard_rhs_parity(lib, kind, se):
     A = random_g2(ns, r, scale=0.1, exchange=False)
     U = 1.3
     g1 = np.stack([X, Y])
-    p = B.Propagator(B.HUBBARD, B.SOA if se == "soa" else B.TPP, ns, h0, g1, U=U)
+    p = B.Propagator(B.HUBBARD, _se(se), ns, h0, g1, U=U)
     G1d, G2d = cuda(g1), cuda(A)
     dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
     p.rhs(0.0, G1d, G2d, dG1d, dG2d)
@@ -73,7 +78,7 @@ def test_hubbard_rhs_parity(lib, kind, se):
 
 def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol):
     from paper_2002_12717_amd import binding as B
-    p = B.Propagator(B.HUBBARD, B.SOA if se == "soa" else B.TPP, system.ns, system.h0, system.g1,
+    p = B.Propagator(B.HUBBARD, _se(se), system.ns, system.h0, system.g1,
                      U=system.U)
     if system.drive is not None:
         d = system.drive
@@ -110,11 +115,12 @@ def test_hubbard_chain_full_trajectory(lib):
     _compare_hubbard_trajectory(hubbard_chain_system(), "soa", 10, 100, 1e-10)
 
 
-def test_hubbard_tpp_cluster_trajectory(lib):
+@pytest.mark.parametrize("se", ["tpp", "tph"])
+def test_hubbard_ladder_cluster_trajectory(lib, se):
     from workloads import batched_clusters
     s = batched_clusters(n=3)[2]
-    say(f"[hubbard trajectory] cluster {s.meta} TPP 200 steps")
-    _compare_hubbard_trajectory(s, "tpp", 4, 50, 1e-10)
+    say(f"[hubbard trajectory] cluster {s.meta} {se} 200 steps")
+    _compare_hubbard_trajectory(s, se, 4, 50, 1e-10)
 
 
 def test_hubbard_driven_trajectory(lib):
@@ -275,7 +281,8 @@ def test_hubbard_mixed_chain_full_trajectory(lib):
 # --------------------------------------------------------------------------- batches and graphs
 @pytest.mark.parametrize("se,kernel,prec", [("soa", "row", "fp64"), ("tpp", "row", "fp64"),
                                             ("tpp", "element", "fp64"), ("tpp", "row", "mixed"),
-                                            ("tpp", "element", "mixed")])
+                                            ("tpp", "element", "mixed"), ("tph", "row", "fp64"),
+                                            ("tph", "element", "fp64"), ("tph", "row", "mixed")])
 def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     """Clusters of uneven size and U in one context: every cluster follows the
     oracle's single-cluster propagation (and the graph-replayed steps).  Positive
@@ -289,7 +296,7 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     chunk = [256 if c.ns < 16 else 2048 for c in cl]
     if kernel == "element":
         chunk = [-ch for ch in chunk]
-    b = B.Batch(B.SOA if se == "soa" else B.TPP, [c.ns for c in cl], [c.U for c in cl],
+    b = B.Batch(_se(se), [c.ns for c in cl], [c.U for c in cl],
                 [c.h0 for c in cl], [c.g1 for c in cl], chunk=chunk, stream=stream.cuda_stream,
                 precision=B.FP64 if prec == "fp64" else B.MIXED)
     dt, nst = cl[0].dt, 24
@@ -310,7 +317,7 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     b.close()
 
 
-@pytest.mark.parametrize("basis", ["hubbard", "general"])
+@pytest.mark.parametrize("basis", ["hubbard", "hubbard_tph", "general"])
 def test_graph_replays_match_eager(lib, basis):
     """Steps replayed from captured HIP graphs (stream given) equal eager
     launches bit for bit, across several replays with synchronizations and
@@ -318,9 +325,10 @@ def test_graph_replays_match_eager(lib, basis):
     from paper_2002_12717_amd import binding as B
     say(f"[graphs] {basis}")
     stream = torch.cuda.Stream()
-    if basis == "hubbard":
+    if basis.startswith("hubbard"):
         s = hubbard_chain_system(ns=6)
-        mk = lambda st: B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=s.U, stream=st)  # noqa: E731
+        se = B.TPH if basis == "hubbard_tph" else B.TPP
+        mk = lambda st: B.Propagator(B.HUBBARD, se, s.ns, s.h0, s.g1, U=s.U, stream=st)  # noqa: E731
     else:
         s = general_system(nb=12, rank=10, nocc=4)
         mk = lambda st: B.Propagator(B.GENERAL, B.SOA, s.nb, s.h0, s.g1, w=s.w, stream=st)  # noqa: E731
