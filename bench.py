@@ -10,7 +10,8 @@ One "step" = one full RK4 step (four right-hand sides) of G1 and G2.  The
 binary64 path is the headline value; the mixed path (binary32 matrix-core
 contractions, binary64 state) is reported beside it with its error against
 the binary64 run.  Other workloads of the paper's shape are available with
---workload (hubbard_chain, hubbard_2d, hubbard_batch, hubbard_adjoint, general_gw).
+--workload (hubbard_chain, hubbard_2d, hubbard_batch, hubbard_adjoint, general_gw,
+general_ladder).
 
 Prints ONE JSON line.
 """
@@ -67,6 +68,21 @@ def gw_flops(nb: int) -> dict:
     d["gen_heps"] = 16 * float(nb) ** 5
     d["gen_gemm"] = 8 * float(nb) ** 6
     d["total"] = d["soa_total"] + d["gen_heps"] + d["gen_gemm"]
+    return d
+
+
+def ladder_flops(nb: int, se: str) -> dict:
+    """Each T-matrix ladder adds its quasi-Hamiltonian (two one-sided products
+    per side of the sandwich: 4 nb^5) and one GEMM (nb^6); DSL adds GW's
+    polarization as well.  gen_gemm is the flops of one GEMM launch."""
+    d = soa_flops(nb)
+    n5, n6 = float(nb) ** 5, float(nb) ** 6
+    nlad = {"tpp": 1, "tph": 1, "dsl": 2}[se]
+    ngemm = nlad + (1 if se == "dsl" else 0)
+    d["gen_hlad"] = 32 * n5
+    d["gen_gemm"] = 8 * n6
+    d["total"] = d["soa_total"] + nlad * d["gen_hlad"] + ngemm * d["gen_gemm"] + \
+        (16 * n5 if se == "dsl" else 0.0)
     return d
 
 
@@ -143,17 +159,18 @@ def base_line(args, steps_per_s, ms_step, dtype, config):
 
 
 # --------------------------------------------------------------------------- workloads
-def run_general(args, torch, B, gw=False):
+def run_general(args, torch, B, se="soa"):
     import numpy as np
     from workloads import general_system, gw_system
+    gw = se != "soa"               # every closure beyond SOA runs on the Nb = 64 system
     system = gw_system() if gw else general_system()
     nb = system.nb
     stream = torch.cuda.Stream()
-    fl = gw_flops(nb) if gw else soa_flops(nb)
-    se = B.GW if gw else B.SOA
+    fl = soa_flops(nb) if se == "soa" else (gw_flops(nb) if se == "gw" else ladder_flops(nb, se))
+    code = {"soa": B.SOA, "gw": B.GW, "tpp": B.TPP, "tph": B.TPH, "dsl": B.DSL}[se]
     res = {}
     for prec in ("fp64", "mixed"):
-        p = B.Propagator(B.GENERAL, se, nb, system.h0, system.g1, w=system.w,
+        p = B.Propagator(B.GENERAL, code, nb, system.h0, system.g1, w=system.w,
                          precision=B.FP64 if prec == "fp64" else B.MIXED, stream=stream.cuda_stream)
         if system.kick is not None:          # one-step kick, then the static h0
             p.set_h0(system.h0 + system.kick)
@@ -172,11 +189,11 @@ def run_general(args, torch, B, gw=False):
     tot_ms, cnt = f64["prof"][dom]
     achieved = fl[dom] * cnt / (tot_ms * 1e-3) / 1e12
     rhs_flops = fl["total"] if gw else fl["soa_total"]
-    config = {"workload": (f"general-basis {'GW' if gw else 'SOA'} G1-G2, Nb={nb} spin orbitals, "
+    config = {"workload": (f"general-basis {se.upper()} G1-G2, Nb={nb} spin orbitals, "
                            f"rank-{system.meta['rank']} w, {system.meta['nocc']} particles, "
                            f"dt={system.dt}, RK4"),
               "nb": nb, "rank": system.meta["rank"], "nocc": system.meta["nocc"], "dt": system.dt,
-              "selfenergy": "GW" if gw else "SOA", "parallelism": "single GPU"}
+              "selfenergy": se.upper(), "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     mx_tot, mx_cnt = mx["prof"][dom]
     mx_ach = fl[dom] * mx_cnt / (mx_tot * 1e-3) / 1e12
@@ -426,11 +443,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--workload", default="general_soa",
-                    choices=["general_soa", "general_gw", "hubbard_chain", "hubbard_2d",
-                             "hubbard_batch", "hubbard_adjoint"])
-    ap.add_argument("--selfenergy", default=None, choices=["soa", "tpp", "tph"],
-                    help="Hubbard workloads only: override the workload's selfenergy "
-                         "(hubbard_batch: TPP, hubbard_chain/hubbard_2d: SOA)")
+                    choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
+                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint"])
+    ap.add_argument("--selfenergy", default=None, choices=["soa", "tpp", "tph", "dsl"],
+                    help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
+                         "TPP, hubbard_chain/hubbard_2d: SOA; soa, tpp, tph); general_ladder: "
+                         "tpp, tph or dsl (default dsl)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -443,7 +461,12 @@ def main():
     if args.workload == "general_soa":
         out = run_general(args, torch, B)
     elif args.workload == "general_gw":
-        out = run_general(args, torch, B, gw=True)
+        out = run_general(args, torch, B, se="gw")
+    elif args.workload == "general_ladder":
+        se = args.selfenergy or "dsl"
+        if se not in ("tpp", "tph", "dsl"):
+            ap.error("general_ladder takes --selfenergy tpp, tph or dsl")
+        out = run_general(args, torch, B, se=se)
     elif args.workload == "hubbard_batch":
         out = run_batch(args, torch, B)
     elif args.workload == "hubbard_adjoint":

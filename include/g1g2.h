@@ -54,9 +54,13 @@ typedef enum {
  *   GW : eq:g2-eq-gw-pi (source Psi without exchange unless G1G2_GW_EXCHANGE).
  *   TPP: particle-particle T matrix, eq:g2-eq-tpp-lambda.
  *   TPH: particle-hole T matrix, eq:g2-eq-tph-lambda.
- * Implemented: general basis SOA, GW; Hubbard basis SOA, TPP, TPH.  Other
- * combinations return G1G2_EUNSUPPORTED.                                        */
-typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3 } g1g2_selfenergy;
+ *   DSL: dynamically screened ladder (Sec. VI): GW with exchange plus both
+ *        T-matrix ladders, eq:g2-dsl-equation-pi-lambda.
+ * Implemented: general basis SOA, GW, TPP, TPH, DSL; Hubbard basis SOA, TPP,
+ * TPH.  Other combinations return G1G2_EUNSUPPORTED.  The general-basis
+ * GW, T-matrix and DSL closures cost one (nb^2 x nb^2 x nb^2) complex GEMM per
+ * polarization or ladder and right-hand side.                                  */
+typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3, G1G2_DSL = 4 } g1g2_selfenergy;
 
 /* GENERAL: arbitrary orthonormal basis with a four-index w (Sec. III.C).
  * HUBBARD: Fermi-Hubbard model with on-site U (Sec. III.D); h0 per spin may be

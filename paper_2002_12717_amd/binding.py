@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(PKG, "libg1g2.so")
 
 GENERAL, HUBBARD = 0, 1
-SOA, GW, TPP, TPH = 0, 1, 2, 3
+SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 PTR_DEVICE, GW_EXCHANGE = 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6

@@ -193,12 +193,11 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     *out = nullptr;
     if (d->nb <= 0) return G1G2_EINVAL;
     if (d->basis != G1G2_GENERAL && d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
-    if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_TPH) return G1G2_EINVAL;
+    if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
     if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_GW) return G1G2_EUNSUPPORTED;
-    if (d->basis == G1G2_GENERAL && (d->selfenergy == G1G2_TPP || d->selfenergy == G1G2_TPH))
-        return G1G2_EUNSUPPORTED;
+    if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_DSL) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_GENERAL && d->nb > 64) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_HUBBARD && (long long)d->nb * d->nb * d->nb * d->nb > (1LL << 30))
         return G1G2_EUNSUPPORTED;

@@ -75,16 +75,20 @@ struct GeneralData {
     cd* gg = nullptr;        // scratch: G^> of the current stage [nbp][nbp]
     double* ipart = nullptr; // scratch: collision-integral partial sums
     int nipart = 0;
-    // GW
-    cd* heps = nullptr;      // [(p,q)][(j,l)] = h^eps_qjpl                        (nbp^4)
-    cd* bmat = nullptr;      // [(i,k)][(p,q)] = G2_ipkq                           (nbp^4)
+    // GW and the ladders: quasi-Hamiltonian and permuted G2 operand of a GEMM
+    cd* heps = nullptr;      // GW: [(p,q)][(j,l)] = h^eps_qjpl; ladders: h^pp, h^ph (nbp^4)
+    cd* bmat = nullptr;      // GW: [(i,k)][(p,q)] = G2_ipkq; ladders: see gen_bmat  (nbp^4)
     cd* pimat = nullptr;     // [(i,k)][(j,l)] = Pi_ijkl                           (nbp^4)
     cd* w_gw = nullptr;      // GW layout: [p][q][s][r] = w_sqrp                   (nbp^4)
+    cd* w_pp = nullptr;      // TPP layout: [k][l][p][q] = w_pqkl                  (nbp^4)
+    cd* w_ph = nullptr;      // TPH layout: [j][k][p][q] = w_pjkq                  (nbp^4)
     cd* icoll = nullptr;     // collision integral of the last RHS evaluation [nbp][nbp]
     // mixed precision copies of the constant layouts
     float2* wm_rows32 = nullptr;
     float2* w_coll32 = nullptr;
     float2* w_gw32 = nullptr;
+    float2* w_pp32 = nullptr;
+    float2* w_ph32 = nullptr;
 };
 
 struct g1g2_ctx {

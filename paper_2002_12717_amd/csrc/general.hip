@@ -490,17 +490,106 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* _
 }
 
 // B[(i,k)][(p,q)] = G2_ipkq
-template <typename S>
+// Quasi-Hamiltonians of the two T-matrix ladders, one column-pair block of
+// the interaction at a time (G^> = G^< - i):
+//   KIND 0, eq:HTPPcorr:  h^pp_ijkl = -sum_pq (G>_ip G>_jq - G<_ip G<_jq) w_pqkl
+//                         = [-(G> M G>^T) + (G< M G<^T)]_ij,  M_pq = w_pqkl, block (k,l)
+//   KIND 1, eq:HTPHcorr:  h^ph_ijkl = -sum_pq (G>_ip G<_ql - G<_ip G>_ql) w_pjkq
+//                         = [-(G> M G<) + (G< M G>)]_il,      M_pq = w_pjkq, block (j,k)
+// wl holds the blocks M contiguously (w_pp / w_ph layouts).  The NB x NB
+// result (r, c) of block blk is stored at out[(r NB + c) NB^2 + blk], which is
+// h^pp as the pair matrix [(ij)][(kl)] and h^ph as the left GEMM operand
+// [(il)][(jk)] of Lambda^ph_ijkl = sum_pq h^ph_ipql G2_qjkp (eq:lambdaph).
+template <typename T, typename S, int NB, int KIND>
+__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_hlad_kernel(const S* __restrict__ wl,
+                                                                     const cd* __restrict__ gl,
+                                                                     const cd* __restrict__ gg,
+                                                                     S* __restrict__ out) {
+    typedef Shape<NB> SH;
+    constexpr int LD = SH::LD;
+    __shared__ T m_re[NB * LD], m_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
+    const int wave = threadIdx.x >> 6;
+    const int b0 = xcd_block(blockIdx.x, gridDim.x);
+    auto Ggt = [&](int i, int k, T& r, T& m) { ldc(gg + i * NB + k, r, m); };   // G>[i][k]
+    auto Glt = [&](int i, int k, T& r, T& m) { ldc(gl + i * NB + k, r, m); };   // G<[i][k]
+    auto Mop = [&](int k, int j, T& r, T& m) {
+        r = m_re[k * LD + j];
+        m = m_im[k * LD + j];
+    };
+    auto Qop = [&](int i, int k, T& r, T& m) {
+        r = q_re[i * LD + k];
+        m = q_im[i * LD + k];
+    };
+    for (int blk = b0; blk < NB * NB; blk += gridDim.x) {
+        stage_block<T, S, NB>(wl + (size_t)blk * NB * NB, m_re, m_im);
+        __syncthreads();
+        CAcc<T> acc[SH::TPW];
+#pragma unroll
+        for (int t = 0; t < SH::TPW; ++t) acc[t].clear();
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            // q = -G> M (half 0) or +G< M (half 1)
+#pragma unroll
+            for (int t = 0; t < SH::TPW; ++t) {
+                const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+                CAcc<T> p;
+                p.clear();
+                if (half == 0) cgemm_tile<T, NB>(p, Ggt, Mop, ti * 16, tj * 16);
+                else cgemm_tile<T, NB>(p, Glt, Mop, ti * 16, tj * 16);
+                const T sg = half == 0 ? (T)-1 : (T)1;
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                    q_re[row * LD + col] = sg * p.re(r4);
+                    q_im[row * LD + col] = sg * p.im(r4);
+                }
+            }
+            __syncthreads();
+            // acc += q R:  pp R = G>^T (half 0), G<^T (half 1);  ph R = G< (half 0), G> (half 1)
+#pragma unroll
+            for (int t = 0; t < SH::TPW; ++t) {
+                const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+                if (KIND == 0) {
+                    if (half == 0) cgemm_tile<T, NB>(acc[t], Qop, [&](int k, int j, T& r, T& m) { Ggt(j, k, r, m); }, ti * 16, tj * 16);
+                    else cgemm_tile<T, NB>(acc[t], Qop, [&](int k, int j, T& r, T& m) { Glt(j, k, r, m); }, ti * 16, tj * 16);
+                } else {
+                    if (half == 0) cgemm_tile<T, NB>(acc[t], Qop, Glt, ti * 16, tj * 16);
+                    else cgemm_tile<T, NB>(acc[t], Qop, Ggt, ti * 16, tj * 16);
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < SH::TPW; ++t) {
+            const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                stc(out + (size_t)(row * NB + col) * NB * NB + blk, acc[t].re(r4), acc[t].im(r4));
+            }
+        }
+    }
+}
+
+// Permuted copy of G2 (binary64 or binary32) as the right operand of a GEMM:
+//   MODE 0 (GW):   b[(i,k)][(p,q)] = G2_ipkq
+//   MODE 1 (TPP):  b[(p,q)][(k,l)] = G2_pqkl
+//   MODE 2 (TPH):  b[(p,q)][(j,k)] = G2_qjkp
+template <typename S, int MODE>
 __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2, S* __restrict__ b,
                                                       int nbp) {
     const size_t n4 = (size_t)nbp * nbp * nbp * nbp;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n4;
          e += (size_t)gridDim.x * blockDim.x) {
-        size_t q = e % nbp, t = e / nbp;
-        size_t p = t % nbp;
+        size_t x3 = e % nbp, t = e / nbp;
+        size_t x2 = t % nbp;
         t /= nbp;
-        size_t k = t % nbp, i = t / nbp;
-        cd v = g2[((i * nbp + p) * nbp + k) * nbp + q];
+        size_t x1 = t % nbp, x0 = t / nbp;
+        size_t src;
+        if (MODE == 0) src = ((x0 * nbp + x2) * nbp + x1) * nbp + x3;        // (i,k,p,q) <- G2_ipkq
+        else if (MODE == 1) src = e;
+        else src = ((x1 * nbp + x2) * nbp + x3) * nbp + x0;                  // (p,q,j,k) <- G2_qjkp
+        cd v = g2[src];
         stc(b + e, v.x, v.y);
     }
 }
@@ -509,9 +598,13 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
 // 64x64 output tile per work-group, four waves of 32x32, K staged in slices of 16.
 // With T = float the products are accumulated in binary32 over 64-deep chunks
 // and the chunk sums are added in binary64 (chunked compensated summation).
-template <typename T, typename S>
+// OUT selects the epilogue:
+//   0 (GW):  pim[i][j][k][l] = C[(i,k)][(j,l)]                (binary64 buffer)
+//   1 (TPP): D[(i,j)][(k,l)] += C[(i,j)][(k,l)]               (D in storage S)
+//   2 (TPH): D[(i,j)][(k,l)] += C[(i,l)][(j,k)]
+template <typename T, typename S, int OUT>
 __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
-                                                      cd* __restrict__ pim, int n, int nbp) {
+                                                      void* __restrict__ dst, int n, int nbp) {
     __shared__ T a_re[64][17], a_im[64][17], b_re[16][65], b_im[16][65];
     const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
     const int wave = threadIdx.x >> 6;
@@ -569,10 +662,24 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int row = bm + wm + a * 16 + tile_row<T>(r4);
                 const int col = bn + wn + b * 16 + tile_col();
-                const int i = row / nbp, k = row % nbp, j = col / nbp, l = col % nbp;
                 double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)acc[a][b].re(r4);
                 double vi = sizeof(T) == 4 ? accd[a][b][1][r4] : (double)acc[a][b].im(r4);
-                pim[(((size_t)i * nbp + j) * nbp + k) * nbp + l] = make_double2(vr, vi);
+                if (OUT == 0) {
+                    const int i = row / nbp, k = row % nbp, j = col / nbp, l = col % nbp;
+                    ((cd*)dst)[(((size_t)i * nbp + j) * nbp + k) * nbp + l] = make_double2(vr, vi);
+                } else {
+                    size_t e;
+                    if (OUT == 1) {
+                        e = (size_t)row * n + col;
+                    } else {
+                        const int i = row / nbp, l = row % nbp, j = col / nbp, k = col % nbp;
+                        e = (((size_t)i * nbp + j) * nbp + k) * nbp + l;
+                    }
+                    S* D = (S*)dst;
+                    T dr, di;
+                    ldc(D + e, dr, di);
+                    stc(D + e, (double)dr + vr, (double)di + vi);
+                }
             }
 }
 
@@ -689,19 +796,20 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
                        wrows, in.g1, (S*)g.vt);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_vt");
-    if (c->d.selfenergy == G1G2_GW) {
+    const int se = c->d.selfenergy;
+    const int n = NB * NB;
+    if (se == G1G2_GW || se == G1G2_DSL) {
         const S* wgw = mixed ? (const S*)g.w_gw32 : (const S*)g.w_gw;
         hipLaunchKernelGGL((gen_heps_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
                            c->stream, wgw, in.g1, (S*)g.heps);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_heps");
-        hipLaunchKernelGGL((gen_bmat_kernel<S>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
+        hipLaunchKernelGGL((gen_bmat_kernel<S, 0>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
                            NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_bmat");
-        const int n = NB * NB;
-        hipLaunchKernelGGL((gen_gemm_kernel<T, S>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
-                           (const S*)g.bmat, (const S*)g.heps, g.pimat, n, NB);
+        hipLaunchKernelGGL((gen_gemm_kernel<T, S, 0>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                           (const S*)g.bmat, (const S*)g.heps, (void*)g.pimat, n, NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_gemm");
     }
@@ -709,6 +817,34 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
                        c->stream, in.g2, (const S*)g.vt, wcoll, g.gg, g.hhf, (S*)g.dmat, g.ipart);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_main");
+    // T-matrix ladders: D += Lambda, so that the combine forms Lambda - Lambda^dagger,
+    // the partner [Lambda_klij]^* of eq:g2-eq-tpp-lambda / eq:g2-eq-tph-lambda
+    if (se == G1G2_TPP || se == G1G2_DSL) {
+        const S* wpp = mixed ? (const S*)g.w_pp32 : (const S*)g.w_pp;
+        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 0>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+                           c->stream, wpp, in.g1, g.gg, (S*)g.heps);
+        hipLaunchKernelGGL((gen_bmat_kernel<S, 1>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
+                           NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_hlad");
+        hipLaunchKernelGGL((gen_gemm_kernel<T, S, 1>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                           (const S*)g.heps, (const S*)g.bmat, (void*)g.dmat, n, NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_gemm");
+    }
+    if (se == G1G2_TPH || se == G1G2_DSL) {
+        const S* wph = mixed ? (const S*)g.w_ph32 : (const S*)g.w_ph;
+        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 1>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+                           c->stream, wph, in.g1, g.gg, (S*)g.heps);
+        hipLaunchKernelGGL((gen_bmat_kernel<S, 2>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
+                           NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_hlad");
+        hipLaunchKernelGGL((gen_gemm_kernel<T, S, 2>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                           (const S*)g.heps, (const S*)g.bmat, (void*)g.dmat, n, NB);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "gen_gemm");
+    }
     return G1G2_OK;
 }
 
@@ -718,7 +854,7 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     GeneralData& g = c->gen;
     const int n = g.nbp * g.nbp;
     const int nt = n / 32;
-    if (c->d.selfenergy == G1G2_GW)
+    if (c->d.selfenergy == G1G2_GW || c->d.selfenergy == G1G2_DSL)
         hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(nt * nt), dim3(256), 0, c->stream,
                            (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc);
     else
@@ -798,8 +934,12 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
     g.nb = nb;
     g.nbp = nbp;
     const size_t n4 = (size_t)nbp * nbp * nbp * nbp;
-    const bool gw = c->d.selfenergy == G1G2_GW;
-    const bool exch = !gw || (c->d.flags & G1G2_GW_EXCHANGE);
+    const int se = c->d.selfenergy;
+    const bool gw = se == G1G2_GW || se == G1G2_DSL;           // polarization Pi
+    const bool pp = se == G1G2_TPP || se == G1G2_DSL;          // particle-particle ladder
+    const bool ph = se == G1G2_TPH || se == G1G2_DSL;          // particle-hole ladder
+    // the source is Psi^- except for GW without exchange; DSL includes the exchange
+    const bool exch = se != G1G2_GW || (c->d.flags & G1G2_GW_EXCHANGE);
     auto W = [&](int i, int j, int k, int l) -> cd { return w[(((size_t)i * nb + j) * nb + k) * nb + l]; };
     // symmetry checks of the interaction (eq:wsymm_a, eq:wsymm_b)
     double wmax = 0, e1 = 0, e2 = 0;
@@ -842,10 +982,31 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
                     for (int p = 0; p < nb; ++p) wg[P4(p, q, s1, r)] = W(s1, q, r, p);  // M_pq[s][r] = w_sqrp
         if ((s = upload(c, &g.w_gw, wg)) != G1G2_OK) return s;
         if (mixed && (s = upload(c, &g.w_gw32, to_f32(wg))) != G1G2_OK) return s;
+        HIP_OK(c, hipMalloc(&g.pimat, n4 * sizeof(cd)));
+    }
+    if (pp || ph) {
+        std::vector<cd> wl(n4, cmk(0, 0));
+        if (pp) {
+            for (int p = 0; p < nb; ++p)
+                for (int q = 0; q < nb; ++q)
+                    for (int k = 0; k < nb; ++k)
+                        for (int l = 0; l < nb; ++l) wl[P4(k, l, p, q)] = W(p, q, k, l);   // M_pq = w_pqkl
+            if ((s = upload(c, &g.w_pp, wl)) != G1G2_OK) return s;
+            if (mixed && (s = upload(c, &g.w_pp32, to_f32(wl))) != G1G2_OK) return s;
+        }
+        if (ph) {
+            for (int p = 0; p < nb; ++p)
+                for (int j = 0; j < nb; ++j)
+                    for (int k = 0; k < nb; ++k)
+                        for (int q = 0; q < nb; ++q) wl[P4(j, k, p, q)] = W(p, j, k, q);   // M_pq = w_pjkq
+            if ((s = upload(c, &g.w_ph, wl)) != G1G2_OK) return s;
+            if (mixed && (s = upload(c, &g.w_ph32, to_f32(wl))) != G1G2_OK) return s;
+        }
+    }
+    if (gw || pp || ph) {
         const size_t es = mixed ? sizeof(float2) : sizeof(cd);
         HIP_OK(c, hipMalloc(&g.heps, n4 * es));
         HIP_OK(c, hipMalloc(&g.bmat, n4 * es));
-        HIP_OK(c, hipMalloc(&g.pimat, n4 * sizeof(cd)));
     }
     const size_t es = mixed ? sizeof(float2) : sizeof(cd);
     HIP_OK(c, hipMalloc(&g.vt, n4 * es));
@@ -928,8 +1089,9 @@ g1g2_status gen_unpad(g1g2_ctx* c, const cd* src, cd* dst, int rank) {
 
 void gen_free(g1g2_ctx* c) {
     GeneralData& g = c->gen;
-    void* ptrs[] = {g.h0, g.wm_rows, g.w_coll, g.w_hf, g.vt, g.dmat, g.hhf, g.gg, g.ipart, g.heps,
-                    g.bmat, g.pimat, g.wm_rows32, g.w_coll32, g.w_gw, g.w_gw32, g.icoll};
+    void* ptrs[] = {g.h0,    g.wm_rows,   g.w_coll, g.w_hf,  g.vt,     g.dmat,   g.hhf,
+                    g.gg,    g.ipart,     g.heps,   g.bmat,  g.pimat,  g.wm_rows32, g.w_coll32,
+                    g.w_gw,  g.w_gw32,    g.icoll,  g.w_pp,  g.w_ph,   g.w_pp32, g.w_ph32};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     g = GeneralData();

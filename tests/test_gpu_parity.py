@@ -139,15 +139,22 @@ def _general_inputs(nb, key):
     return h, w, gl, g2
 
 
+def _gen_se(se):
+    """Library selfenergy code and flags of an oracle selfenergy name."""
+    from paper_2002_12717_amd import binding as B
+    return {"soa": (B.SOA, 0), "gw": (B.GW, 0), "gw_x": (B.GW, B.GW_EXCHANGE), "tpp": (B.TPP, 0),
+            "tph": (B.TPH, 0), "dsl": (B.DSL, 0)}[se]
+
+
 @pytest.mark.parametrize("nb", [6, 20, 32])
-@pytest.mark.parametrize("se", ["soa", "gw", "gw_x"])
+@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph", "dsl"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_general_rhs_parity(lib, nb, se, prec):
     from paper_2002_12717_amd import binding as B
     say(f"[general rhs] nb={nb} se={se} prec={prec}")
     h, w, gl, g2 = _general_inputs(nb, len(se))
-    flags = B.GW_EXCHANGE if se == "gw_x" else 0
-    p = B.Propagator(B.GENERAL, B.SOA if se == "soa" else B.GW, nb, h, gl, w=w,
+    code, flags = _gen_se(se)
+    p = B.Propagator(B.GENERAL, code, nb, h, gl, w=w,
                      precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
     G1d, G2d = cuda(gl), cuda(g2)
     dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
@@ -163,8 +170,9 @@ def test_general_rhs_parity(lib, nb, se, prec):
 
 def _compare_general_trajectory(system, se, chunks, chunk_steps, prec, tol):
     from paper_2002_12717_amd import binding as B
-    p = B.Propagator(B.GENERAL, B.SOA if se == "soa" else B.GW, system.nb, system.h0, system.g1,
-                     w=system.w, precision=B.FP64 if prec == "fp64" else B.MIXED)
+    code, flags = _gen_se(se)
+    p = B.Propagator(B.GENERAL, code, system.nb, system.h0, system.g1, w=system.w,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
     f = OI.general_rhs_fn(system.h0, system.w, se)
     g1, g2 = T(system.g1), torch.zeros((system.nb,) * 4, dtype=torch.complex128)
     t = 0.0
@@ -188,6 +196,19 @@ def test_general_soa_trajectory_small(lib, prec):
     s = general_system(nb=12, rank=10, nocc=4, dt=0.01)
     say(f"[general trajectory] nb=12 SOA 100 steps {prec}")
     _compare_general_trajectory(s, "soa", 4, 25, prec, 1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("se,prec", [("tpp", "fp64"), ("tph", "fp64"), ("dsl", "fp64"), ("dsl", "mixed")])
+def test_general_ladder_trajectory_small(lib, se, prec):
+    """T-matrix and DSL closures in the general basis, 100 steps at nb=12.  The
+    interaction is halved: at full strength the DSL closure of this random
+    system itself diverges before t = 1 (the oracle reaches NaN), the
+    strong-coupling instability of the scheme, not a property of the kernels."""
+    import dataclasses
+    s = general_system(nb=12, rank=10, nocc=4, dt=0.01)
+    s = dataclasses.replace(s, w=0.5 * s.w)
+    say(f"[general trajectory] nb=12 {se} 100 steps {prec}")
+    _compare_general_trajectory(s, se, 4, 25, prec, 1e-10 if prec == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
