@@ -40,7 +40,7 @@ TRAFFIC = {
     "hub_stage/2d": {"bytes": 2.25e9, "src": "hubbard.hip", "sha1": "69605f286e68"},
 }
 
-SE_CODES = {"soa": lambda B: B.SOA, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
+SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
 
 
 def traffic(key):
@@ -239,8 +239,9 @@ def run_hubbard(args, torch, B, kind):
     ms_step = ms / args.steps
     n4 = float(ns) ** 4
     tot_ms, cnt = prof["hub_stage"]
-    # algorithmic bytes: 256 B per complex128 G2 element per RK4 step (4 launches)
-    bytes_per_launch = 64.0 * n4
+    # algorithmic bytes: 256 B per complex128 G2 element per RK4 step (4 launches);
+    # Hubbard GW propagates three G2 channels
+    bytes_per_launch = 64.0 * n4 * (3 if se == "gw" else 1)
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
     name = "1D chain, 8 sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
     config = {"workload": f"Hubbard {se.upper()} G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
@@ -445,7 +446,7 @@ def main():
     ap.add_argument("--workload", default="general_soa",
                     choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
                              "hubbard_2d", "hubbard_batch", "hubbard_adjoint"])
-    ap.add_argument("--selfenergy", default=None, choices=["soa", "tpp", "tph", "dsl"],
+    ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
                          "TPP, hubbard_chain/hubbard_2d: SOA; soa, tpp, tph); general_ladder: "
                          "tpp, tph or dsl (default dsl)")

@@ -56,8 +56,12 @@ typedef enum {
  *   TPH: particle-hole T matrix, eq:g2-eq-tph-lambda.
  *   DSL: dynamically screened ladder (Sec. VI): GW with exchange plus both
  *        T-matrix ladders, eq:g2-dsl-equation-pi-lambda.
- * Implemented: general basis SOA, GW, TPP, TPH, DSL; Hubbard basis SOA, TPP,
- * TPH.  Other combinations return G1G2_EUNSUPPORTED.  The general-basis
+ * Implemented: general basis SOA, GW, TPP, TPH, DSL; Hubbard basis SOA, GW,
+ * TPP, TPH (Hubbard GW needs ns <= 64 and at most 4 neighbours per site, and
+ * is not available for batches).  Other combinations return
+ * G1G2_EUNSUPPORTED.  Hubbard GW stores three G2 channels, [3][ns]^4 in every
+ * G2 argument: up-down-up-down, up-up-up-up, down-down-down-down (the spin of
+ * each slot attached to its index, eq:g2-gw-hubbard1/2).  The general-basis
  * GW, T-matrix and DSL closures cost one (nb^2 x nb^2 x nb^2) complex GEMM per
  * polarization or ladder and right-hand side.                                  */
 typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3, G1G2_DSL = 4 } g1g2_selfenergy;

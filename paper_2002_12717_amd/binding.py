@@ -138,8 +138,12 @@ class Propagator:
                             or self.lib.g1g2_strerror(st).decode())
 
     def shapes(self):
+        """G1 and G2 shapes of the ABI layout; Hubbard GW stores three G2 channels
+        (up-down-up-down, up-up-up-up, down-down-down-down)."""
         nb = self.nb
         g1 = (2, nb, nb) if self.basis == HUBBARD else (nb, nb)
+        if self.basis == HUBBARD and self.desc.selfenergy == GW:
+            return g1, (3, nb, nb, nb, nb)
         return g1, (nb, nb, nb, nb)
 
     # ------------------------------------------------------------------ ABI calls

@@ -54,9 +54,14 @@ size_t g1_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
     return c->d.basis == G1G2_HUBBARD ? 2 * nb * nb : nb * nb;
 }
+// Channels of the stored G2: Hubbard GW keeps up-down-up-down, up-up-up-up
+// and down-down-down-down; every other closure one block.
+size_t g2_channels(const g1g2_desc& d) {
+    return d.basis == G1G2_HUBBARD && d.selfenergy == G1G2_GW ? 3 : 1;
+}
 size_t g2_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
-    return nb * nb * nb * nb;
+    return g2_channels(c->d) * nb * nb * nb * nb;
 }
 
 g1g2_status alloc_regs(g1g2_ctx* c, Regs& r) {
@@ -196,7 +201,6 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
-    if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_GW) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_DSL) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_GENERAL && d->nb > 64) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_HUBBARD && (long long)d->nb * d->nb * d->nb * d->nb > (1LL << 30))
@@ -217,7 +221,7 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     const size_t nb = d->nb;
     if (d->basis == G1G2_HUBBARD) {
         c->n1 = 2 * nb * nb;
-        c->n2 = nb * nb * nb * nb;
+        c->n2 = g2_channels(*d) * nb * nb * nb * nb;
     } else {
         const size_t nbp = ((nb + 15) / 16) * 16;
         c->n1 = nbp * nbp;

@@ -28,7 +28,11 @@ using hub::hf_diag;
 using hub::make_cl;
 
 // Selfenergies of the stage kernels.
-enum { SE_SOA = 0, SE_TPP = 1, SE_TPH = 2 };
+enum { SE_SOA = 0, SE_TPP = 1, SE_TPH = 2, SE_GW = 3 };
+
+// G2 channels stored per cluster and diagonal tensors gathered per stage.
+__host__ __device__ constexpr int n_channels(int se) { return se == SE_GW ? 3 : 1; }
+__host__ __device__ constexpr int n_diag(int se) { return se == SE_TPH ? 2 : (se == SE_GW ? 6 : 0); }
 
 // Right-hand side of one element e = ((i ns + j) ns + k) ns + l of the
 // cluster's block A = G2^{up down up down}:
@@ -203,26 +207,44 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
     }
 }
 
-// TPH: the "diagonal" elements of the stage input that the particle-hole
-// ladder needs, A_cabc (first index = last index), in two layouts,
-//   R[a][b][c] = A[c][a][b][c],   S[b][c][a] = A[c][a][b][c],
-// so that the stage kernel reads them as contiguous rows.  A work item is a
-// range [start, end) of the ns^3 triples (a, b, c) of one cluster.
-template <typename TI>
+// "Diagonal" elements of the stage input that the ladder and polarization
+// terms need, gathered once per stage into contiguous layouts so that the
+// stage kernel reads them as rows (a work item is a range [start, end) of the
+// ns^3 index triples of one cluster):
+//   TPH (channel A = G2^{up dn up dn}):
+//     R[a][b][c] = A_cabc,  S[b][c][a] = A_cabc
+//   GW (channels A, B = G2^{up up up up}, C = G2^{dn dn dn dn}):
+//     UA[a][c][b] = A_abcb, TA[b][c][a] = A_abcb, VA[b][d][a] = A_abad,
+//     WA[a][d][b] = A_abad, UB[a][c][b] = B_abcb, TC[b][c][a] = C_abcb
+template <typename TI, int SE>
 __global__ __launch_bounds__(256) void hub_diag_kernel(const ClusterDesc* __restrict__ desc,
                                                       const WorkItem* __restrict__ dwork,
                                                       const cd* __restrict__ in2, cd* __restrict__ diag) {
     const WorkItem w = dwork[blockIdx.x];
     const ClusterDesc d = desc[w.cluster];
     const int ns = d.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const long long n4 = (long long)ns2 * ns2;
     const TI* A = reinterpret_cast<const TI*>(in2) + d.g2off;
-    cd* R = diag + 2 * d.doff;
-    cd* S = R + ns3;
+    cd* D = diag + (long long)n_diag(SE) * d.doff;
     for (int t = w.start + threadIdx.x; t < w.end; t += blockDim.x) {
-        const int a = t / ns2, b = (t / ns) % ns, c = t % ns;
-        const cd v = ld_c(A, ((c * ns + a) * ns + b) * ns + c);
-        R[t] = v;
-        S[(b * ns + c) * ns + a] = v;
+        const int x = t / ns2, y = (t / ns) % ns, z = t % ns;
+        if (SE == SE_TPH) {   // (x, y, z) = (a, b, c)
+            const cd v = ld_c(A, ((z * ns + x) * ns + y) * ns + z);
+            D[t] = v;
+            D[ns3 + (y * ns + z) * ns + x] = v;
+        } else {
+            // (x, y, z) = (a, b, c): P_abcb of A, B, C
+            const long long e1 = ((x * ns + y) * ns + z) * ns + y;
+            const cd va = ld_c(A, e1), vb = ld_c(A, n4 + e1), vc = ld_c(A, 2 * n4 + e1);
+            D[(x * ns + z) * ns + y] = va;                   // UA
+            D[ns3 + (y * ns + z) * ns + x] = va;             // TA
+            D[4 * ns3 + (x * ns + z) * ns + y] = vb;         // UB
+            D[5 * ns3 + (y * ns + z) * ns + x] = vc;         // TC
+            // (x, y, z) = (a, b, d): A_abad
+            const cd vd = ld_c(A, ((x * ns + y) * ns + x) * ns + z);
+            D[2 * ns3 + (y * ns + z) * ns + x] = vd;         // VA
+            D[3 * ns3 + (x * ns + z) * ns + y] = vd;         // WA
+        }
     }
 }
 
@@ -252,7 +274,7 @@ __device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x),
 
 template <int MODE, int SE, bool MIXED>
 __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
-    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH;
+    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH, GW = SE == SE_GW;
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
@@ -296,15 +318,19 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
         shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
     }
     __syncthreads();
+    // neighbour tables and h^HF diagonals per index slot (i, j, k, l): spin
+    // up on i, k and down on j, l for A; the equal-spin GW channels B and C
+    // use spin up or spin down on all four
     const int* nbu = snb;
     const int* nbd = snb + ns * ZR;
     const cd* hu = shp;
     const cd* hd = shp + ns * ZR;
+    const int *nbI = nbu, *nbJ = nbd, *nbK = nbu, *nbL = nbd;
+    const cd *hI = hu, *hJ = hd, *hK = hu, *hL = hd;
+    const cd *eI = eu, *eJ = ed, *eK = eu, *eL = ed;
     const cd* __restrict__ X = a.X;
     const cd* __restrict__ Y = a.Y;
-    const cd* y = s.y2 + d.g2off;
-    cd* acc = s.acc2 + d.g2off;
-    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
+    const long long n4 = (long long)ns2 * ns2;
     const int rpw = min(64 / ns, ns);
     const int nkb = (ns + rpw - 1) / rpw;
     const int lane = tid & 63;
@@ -313,13 +339,20 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     // l-neighbours: source lanes of the permute (the lane itself where there is none)
     int src[ZR];
 #pragma unroll
-    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? sub * ns + nbd[l * ZR + q] : lane;
-    const cd el = lane_ok ? ed[l] : cmk(0.0, 0.0);
-    // first unit of this wave
+    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? sub * ns + nbL[l * ZR + q] : lane;
+    cd el = lane_ok ? eL[l] : cmk(0.0, 0.0);
+    // first unit of this wave; units run over channel, slice, k-block
     int u = w.start + __builtin_amdgcn_readfirstlane(tid >> 6);
-    int slice = u / nkb, kb = u - slice * nkb;
-    int cur = -1;
+    int slice = u / nkb, kb = u - slice * nkb;   // slice counts (channel, i, j)
+    int cur = -1, ch = 0;
     int i = 0, j = 0;
+    const TI* __restrict__ Ach = A;
+    const cd* y = s.y2 + d.g2off;
+    cd* acc = s.acc2 + d.g2off;
+    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
+    // GW: diagonal tensors and the G1 blocks of the two polarization terms
+    const cd* __restrict__ DG = GW ? s.diag + (long long)n_diag(SE) * d.doff : nullptr;
+    const cd *D1 = nullptr, *D2 = nullptr, *S1 = Y, *S2 = X;
     cd ei = cmk(0, 0), ej = cmk(0, 0), xij = cmk(0, 0), yji = cmk(0, 0);
     cd xil = cmk(0, 0), yjl = cmk(0, 0), yil = cmk(0, 0), dll = cmk(0, 0), sijl = cmk(0, 0);
     double dij = 0.0;
@@ -328,10 +361,46 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     for (; u < w.end; u += 4) {
         if (slice != cur) {   // wave-uniform
             cur = slice;
-            i = slice / ns;
-            j = slice - i * ns;
-            ei = wave_uniform(eu[i]);
-            ej = wave_uniform(ed[j]);
+            if (GW) {
+                const int nch = slice / ns2;
+                if (nch != ch || D1 == nullptr) {
+                    ch = nch;
+                    const int* nbs = ch == 2 ? nbd : nbu;
+                    const cd* hs = ch == 2 ? hd : hu;
+                    const cd* es = ch == 2 ? ed : eu;
+                    nbI = ch == 0 ? nbu : nbs;
+                    nbJ = ch == 0 ? nbd : nbs;
+                    nbK = nbI;
+                    nbL = nbJ;
+                    hI = ch == 0 ? hu : hs;
+                    hJ = ch == 0 ? hd : hs;
+                    hK = hI;
+                    hL = hJ;
+                    eI = ch == 0 ? eu : es;
+                    eJ = ch == 0 ? ed : es;
+                    eK = eI;
+                    eL = eJ;
+#pragma unroll
+                    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? sub * ns + nbL[l * ZR + q] : lane;
+                    el = lane_ok ? eL[l] : cmk(0.0, 0.0);
+                    Ach = A + ch * n4;
+                    y = s.y2 + d.g2off + ch * n4;
+                    acc = s.acc2 + d.g2off + ch * n4;
+                    out = reinterpret_cast<TO*>(s.out2) + d.g2off + ch * n4;
+                    // Pi_1 = -i U S1_jl (D1[i][k][j] - D1[i][k][l]),
+                    // Pi_2 = -i U S2_ki (D2[k][j][l] - D2[i][j][l]), term Pi_1 - conj(Pi_2)
+                    const long long n3 = (long long)ns2 * ns;
+                    D1 = DG + (ch == 0 ? 4 : (ch == 1 ? 0 : 2)) * n3;   // UB, UA, VA
+                    D2 = DG + (ch == 0 ? 5 : (ch == 1 ? 1 : 3)) * n3;   // TC, TA, WA
+                    S1 = ch == 1 ? X : Y;
+                    S2 = ch == 2 ? Y : X;
+                }
+            }
+            const int sl = GW ? slice - ch * ns2 : slice;
+            i = sl / ns;
+            j = sl - i * ns;
+            ei = wave_uniform(eI[i]);
+            ej = wave_uniform(eJ[j]);
             xij = wave_uniform(X[i * ns + j]);
             yji = wave_uniform(Y[j * ns + i]);
             dij = (double)(i == j);
@@ -339,15 +408,16 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 xil = X[i * ns + l];
                 yjl = Y[j * ns + l];
                 yil = Y[i * ns + l];
-                if (TPP) dll = ld_c(A, (l * ns + l) * ns2 + slice);
+                if (TPP) dll = ld_c(A, (l * ns + l) * ns2 + sl);
                 if (TPH) sijl = DS[(i * ns + j) * ns + l];
             }
         }
         const int k = kb * rpw + sub;
         const bool act = lane_ok && k < ns;
         const int kk = act ? k : 0;
-        const int e = slice * ns2 + kk * ns + l;
-        const cd av = act ? ld_c(A, e) : cmk(0.0, 0.0);
+        const int slc = GW ? slice - ch * ns2 : slice;   // (i, j) of this channel
+        const int e = slc * ns2 + kk * ns + l;
+        const cd av = act ? ld_c(Ach, e) : cmk(0.0, 0.0);
         cd vl[ZR];
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
@@ -359,25 +429,32 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             cd r = cmk(0.0, 0.0);
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
-                r = cfma_conjb(r, vl[q], hd[l * ZR + q]);
-                r = cfma_conjb(r, ld_c(A, e + (nbu[kk * ZR + q] - kk) * ns), hu[kk * ZR + q]);
+                r = cfma_conjb(r, vl[q], hL[l * ZR + q]);
+                r = cfma_conjb(r, ld_c(Ach, e + (nbK[kk * ZR + q] - kk) * ns), hK[kk * ZR + q]);
             }
-            const cd ek = eu[kk];
+            const cd ek = eK[kk];
             cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
             c = csub(c, r);
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
-                c = cfma(c, hu[i * ZR + q], ld_c(A, e + (nbu[i * ZR + q] - i) * ns3));
-                c = cfma(c, hd[j * ZR + q], ld_c(A, e + (nbd[j * ZR + q] - j) * ns2));
+                c = cfma(c, hI[i * ZR + q], ld_c(Ach, e + (nbI[i * ZR + q] - i) * ns3));
+                c = cfma(c, hJ[j * ZR + q], ld_c(Ach, e + (nbJ[j * ZR + q] - j) * ns2));
             }
-            // source (eq:soa-cubic-scheme)
-            const cd xik = X[i * ns + kk], xjk = X[j * ns + kk], yjk = Y[j * ns + kk];
+            if (GW) {   // polarization terms of the channel (Sec. VII.B, reading of the partner spins)
+                const cd s1 = S1[j * ns + l], s2 = S2[kk * ns + i];
+                const cd p1 = cmul_mi(cmul(s1, csub(D1[(i * ns + kk) * ns + j], D1[(i * ns + kk) * ns + l])));
+                const cd p2 = cmul_mi(cmul(s2, csub(D2[(kk * ns + j) * ns + l], D2[(i * ns + j) * ns + l])));
+                c = cadd(c, cscale(csub(p1, cconj(p2)), a.U));
+            }
             const cd xkl = X[kk * ns + l], ykl = Y[kk * ns + l];
+            if (!GW || ch == 0) {   // source (eq:soa-cubic-scheme), channel A only
+            const cd xik = X[i * ns + kk], xjk = X[j * ns + kk], yjk = Y[j * ns + kk];
             const cd xlk = cmk(-xkl.x, xkl.y);
             const double dd = dij - (double)(kk == l);
             cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
             cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
             c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+            }
             if (TPP) {   // ladder (Sec. VII.C) and its partner
                 const int kl = kk * ns + l;
                 cd dii = ld_c(A, (i * ns + i) * ns2 + kl), djj = ld_c(A, (j * ns + j) * ns2 + kl);
@@ -437,12 +514,12 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
 
 template <int MODE, int SE, bool MIXED>
 void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
-    if (SE == SE_TPH) {
+    if (n_diag(SE) > 0) {
         using TI = typename StageTypes<MODE, MIXED>::In;
-        hipLaunchKernelGGL((hub_diag_kernel<TI>), dim3(c->hub.ndwork), dim3(256), 0, c->stream, c->hub.desc,
-                           c->hub.dwork, s.in2, c->hub.diag);
+        hipLaunchKernelGGL((hub_diag_kernel<TI, SE>), dim3(c->hub.ndwork), dim3(256), 0, c->stream,
+                           c->hub.desc, c->hub.dwork, s.in2, c->hub.diag);
     }
-    if (c->hub.rows)
+    if (c->hub.rows || SE == SE_GW)   // GW runs on the row kernel only (checked at setup)
         hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
     else
         hipLaunchKernelGGL((hub_stage_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
@@ -461,6 +538,7 @@ g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
     switch (c->d.selfenergy) {
         case G1G2_TPP: launch_stage_p<MODE, SE_TPP>(c, s, mixed); break;
         case G1G2_TPH: launch_stage_p<MODE, SE_TPH>(c, s, mixed); break;
+        case G1G2_GW: launch_stage_p<MODE, SE_GW>(c, s, mixed); break;
         default: launch_stage_p<MODE, SE_SOA>(c, s, mixed); break;
     }
     HIP_OK(c, hipGetLastError());
@@ -605,6 +683,8 @@ void hub_free(g1g2_ctx* c) {
 g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, const cd* const* h0s,
                       const int* chunk_in) {
     HubbardData& H = c->hub;
+    const int se = c->d.selfenergy == G1G2_GW ? SE_GW : (c->d.selfenergy == G1G2_TPH ? SE_TPH : SE_SOA);
+    const int nch = n_channels(se);
     std::vector<ClusterDesc> desc(ncl);
     std::vector<int> nbr_all;
     std::vector<cd> hop_all;
@@ -670,10 +750,11 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         d0_all.insert(d0_all.end(), d0.begin(), d0.end());
         const long long n4 = (long long)ns * ns * ns * ns;
         if (rowk) {
-            // wave units of rpw rows (rpw ns elements); chunk = elements per work-group
+            // wave units of rpw rows (rpw ns elements) over (channel, i, j, k-block);
+            // chunk = elements per work-group
             const int rpw = std::min(64 / ns, ns);
             const int nkb = (ns + rpw - 1) / rpw;
-            const long long nunits = (long long)ns * ns * nkb;
+            const long long nunits = (long long)nch * ns * ns * nkb;
             int want = (chunk_in && chunk_in[cl] > 0) ? chunk_in[cl] : 1024;
             int upw = std::max(4, (int)std::lround((double)want / (rpw * ns)));
             upw = (upw + 3) / 4 * 4;
@@ -690,12 +771,15 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         const int n3 = ns * ns * ns;
         for (int t0 = 0; t0 < n3; t0 += 4096) dwork.push_back({cl, t0, std::min(n3, t0 + 4096)});
         doff += n3;
-        g2off += n4;
+        g2off += nch * n4;
         g1off += 2LL * ns * ns;
         xoff += ns;
     }
     // G1 updates first: they then overlap with the G2 items instead of trailing them
     work.insert(work.begin(), g1work.begin(), g1work.end());
+    if (se == SE_GW && !rowk)
+        return set_error(c, G1G2_EUNSUPPORTED,
+                         "Hubbard GW needs ns <= 64, at most 4 neighbours per site and chunk > 0");
     hub_free(c);
     H.ncl = ncl;
     H.rows = rowk;
@@ -707,9 +791,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     g1g2_status s;
     if ((s = upload(c, &H.desc, desc)) != G1G2_OK) return s;
     if ((s = upload(c, &H.work, work)) != G1G2_OK) return s;
-    if (c->d.selfenergy == G1G2_TPH) {
+    if (n_diag(se) > 0) {
         if ((s = upload(c, &H.dwork, dwork)) != G1G2_OK) return s;
-        HIP_OK(c, hipMalloc(&H.diag, std::max<long long>(2 * doff, 1) * sizeof(cd)));
+        HIP_OK(c, hipMalloc(&H.diag, std::max<long long>(n_diag(se) * doff, 1) * sizeof(cd)));
     }
     if ((s = upload(c, &H.nbr, nbr_all)) != G1G2_OK) return s;
     if ((s = upload(c, &H.hop, hop_all)) != G1G2_OK) return s;

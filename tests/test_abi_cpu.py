@@ -57,9 +57,7 @@ def test_init_rejects_bad_arguments_without_device(so_path):
     ctx = ctypes.c_void_p()
     d = binding.Desc(0, 0, 0, 0, 0, 0.0)       # nb = 0
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), None, None, None, None, None) == binding.EINVAL
-    d = binding.Desc(1, 1, 0, 0, 4, 1.0)       # Hubbard GW is not implemented
     buf = (ctypes.c_double * 64)()
-    assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, None, buf, None, None) == binding.EUNSUPPORTED
     d = binding.Desc(1, binding.DSL, 0, 0, 4, 1.0)   # DSL is a general-basis closure
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, None, buf, None, None) == binding.EUNSUPPORTED
     d = binding.Desc(0, 5, 0, 0, 4, 0.0)             # no such selfenergy
