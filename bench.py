@@ -33,25 +33,42 @@ PEAK_HBM = 8000.0          # GB/s
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration; profiles/hbm_traffic_counters.md).  A figure is only
-# reported while the kernel source still has the hash it had when measured.
+# reported while the kernel's source text still has the hash it had when the
+# counters were taken (kernel_hash below: the text of the kernel function).
 TRAFFIC = {
-    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "sha1": "329c4eea1c5f"},
-    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "sha1": "329c4eea1c5f"},
-    "hub_stage/2d": {"bytes": 2.25e9, "src": "hubbard.hip", "sha1": "69605f286e68"},
+    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "cf444c39557a"},
+    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "cf444c39557a"},
+    "hub_stage/2d": {"bytes": 2.25e9, "src": "hubbard.hip", "kernel": "hub_row_kernel", "sha1": "?"},
 }
 
-SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
+
+def kernel_hash(src: str, kernel: str) -> str:
+    """sha1 (first 12 hex digits) of the text of a kernel function: from its
+    name to the brace that closes its body."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2002_12717_amd", "csrc", src)) as f:
+        text = f.read()
+    a = text.index(kernel + "(")
+    b = text.index("{", a)
+    depth = 0
+    for q in range(b, len(text)):
+        if text[q] == "{":
+            depth += 1
+        elif text[q] == "}":
+            depth -= 1
+            if depth == 0:
+                return hashlib.sha1(text[a:q + 1].encode()).hexdigest()[:12]
+    raise ValueError(kernel)
 
 
 def traffic(key):
-    import hashlib
     t = TRAFFIC.get(key)
     if t is None:
         return None
-    path = os.path.join(ROOT, "paper_2002_12717_amd", "csrc", t["src"])
-    with open(path, "rb") as f:
-        h = hashlib.sha1(f.read()).hexdigest()[:12]
-    return t["bytes"] if h == t["sha1"] else None
+    return t["bytes"] if kernel_hash(t["src"], t["kernel"]) == t["sha1"] else None
+
+
+SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
 
 
 def soa_flops(nb: int) -> dict:
