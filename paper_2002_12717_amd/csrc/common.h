@@ -46,25 +46,44 @@ __device__ __forceinline__ void st_c(float2* __restrict__ p, long long i, cd v) 
 // with cb = dt/6, dt/3, dt/3, dt/6 and cc = dt/2, dt/2, dt for stages 1..4.
 enum { RK_RHS = 0, RK_FIRST = 1, RK_MID = 2, RK_LAST = 3 };
 
+// Streaming (non-temporal) loads and stores: data touched once per kernel,
+// kept from displacing operands that are reused from the caches.
+__device__ __forceinline__ cd ld_nt(const cd* p) {
+    return cmk(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ void st_nt(cd* p, cd v) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ void st_nt(float2* p, cd v) {
+    __builtin_nontemporal_store((float)v.x, &p->x);
+    __builtin_nontemporal_store((float)v.y, &p->y);
+}
+
 // The stage output `out` may be binary32 storage (mixed precision); y and acc
-// are always binary64.
-template <int MODE, typename TO>
+// are always binary64.  NT streams y, acc and out past the caches.
+template <int MODE, typename TO, bool NT = false>
 __device__ __forceinline__ void rk_update(int e, cd f, cd yin_if_first, const cd* __restrict__ y,
                                           cd* __restrict__ acc, TO* __restrict__ out,
                                           double cb, double cc) {
+    auto ld = [&](const cd* p) { return NT ? ld_nt(p) : *p; };
+    auto st = [&](auto* p, cd v) {
+        if (NT) st_nt(p, v);
+        else st_c(p, 0, v);
+    };
     if (MODE == RK_RHS) {
-        st_c(out, e, f);
+        st(out + e, f);
     } else if (MODE == RK_FIRST) {
         cd yv = yin_if_first;
-        acc[e] = cmk(fma(cb, f.x, yv.x), fma(cb, f.y, yv.y));
-        st_c(out, e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
+        st(acc + e, cmk(fma(cb, f.x, yv.x), fma(cb, f.y, yv.y)));
+        st(out + e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
     } else if (MODE == RK_MID) {
-        cd av = acc[e];
-        cd yv = y[e];
-        acc[e] = cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y));
-        st_c(out, e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
+        cd av = ld(acc + e);
+        cd yv = ld(y + e);
+        st(acc + e, cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y)));
+        st(out + e, cmk(fma(cc, f.x, yv.x), fma(cc, f.y, yv.y)));
     } else {
-        cd av = acc[e];
-        st_c(out, e, cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y)));
+        cd av = ld(acc + e);
+        st(out + e, cmk(fma(cb, f.x, av.x), fma(cb, f.y, av.y)));
     }
 }

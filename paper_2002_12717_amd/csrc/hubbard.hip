@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
                 c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
             }
-            rk_update<MODE>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
+            rk_update<MODE, TO, true>(e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
         }
         kb += 4;
         while (kb >= nkb) {
