@@ -62,3 +62,13 @@ def test_init_rejects_bad_arguments_without_device(so_path):
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, None, buf, None, None) == binding.EUNSUPPORTED
     d = binding.Desc(0, 5, 0, 0, 4, 0.0)             # no such selfenergy
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, buf, buf, None, None) == binding.EINVAL
+
+
+def test_batch_init_rejects_empty_batch(so_path):
+    """A batch needs at least one cluster; checked before any device call."""
+    from paper_2002_12717_amd import binding
+    lib = binding.load(so_path)
+    ctx = ctypes.c_void_p()
+    d = binding.Desc(1, binding.TPP, 0, 0, 4, 0.0)
+    assert lib.g1g2_batch_init(ctypes.byref(ctx), ctypes.byref(d), 0, None, None, None, None, None,
+                               None) == binding.EINVAL

@@ -470,3 +470,183 @@ def test_adjoint_autograd_function_and_finite_differences(lib):
         say(f"   dL/dc{m} adjoint {c.grad[m].item():.10e} fd {fd:.10e}")
         assert abs(fd - c.grad[m].item()) < 1e-6 * max(1e-3, abs(fd))
     p.close()
+
+
+# --------------------------------------------------------------------------- full sizes and edge cases
+@pytest.mark.parametrize("se", ["soa", "tph", "gw"])
+def test_full_size_hubbard_8x8_driven_rhs(lib, se):
+    """The 8x8 workload (ns = 64) with its drive switched on, at a random
+    correlated state: every element of one right-hand side, in the launch
+    configuration of the benchmark (row kernel, one launch per stage)."""
+    from paper_2002_12717_amd import binding as B
+    s = adjoint_system()
+    ns, d = s.ns, s.drive
+    say(f"[full size] 8x8 {se} rhs with drive")
+    r = rng(104, len(se))
+    X, Y = random_gless(ns, r), random_gless(ns, r)
+    nch = 3 if se == "gw" else 1
+    g2 = [random_g2(ns, r, scale=0.05, exchange=False) for _ in range(nch)]
+    t = 13.7
+    p = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, np.stack([X, Y]), U=s.U)
+    p.set_drive(d.x, d.c, d.t_center, d.tau)
+    G1d = cuda(np.stack([X, Y]))
+    G2d = cuda(np.stack(g2) if nch == 3 else g2[0])
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(t, G1d, G2d, dG1d, dG2d)
+    v = np.diag(d.potential(t))
+    hu, hd = T(s.h0[0] + v), T(s.h0[1] + v)
+    extra = dict(B=T(g2[1]), C=T(g2[2])) if se == "gw" else {}
+    ref = OH.rhs(hu, hd, s.U, T(X), T(Y), T(g2[0]), se, **extra)
+    e1 = rel(dG1d.cpu().numpy(), np.stack([ref[0].numpy(), ref[1].numpy()]))
+    got2 = dG2d.cpu().numpy()
+    ref2 = np.stack([x.numpy() for x in ref[2:]]) if se == "gw" else ref[2].numpy()
+    e2 = rel(got2, ref2)
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    assert e1 < 1e-12 and e2 < 1e-12
+    p.close()
+
+
+def test_full_size_batch_sampled_clusters(lib):
+    """The 512-cluster TPP batch in the benchmark's launch configuration
+    (autotuned chunks, graph-replayed steps): after 8 steps, the largest and a
+    sample of other clusters against the oracle's single-cluster runs."""
+    from paper_2002_12717_amd import autotune
+    from paper_2002_12717_amd import binding as B
+    from workloads import batched_clusters
+    cl = batched_clusters()
+    ns = [c.ns for c in cl]
+    say(f"[full size] batch of {len(cl)} clusters, TPP, 8 graph-replayed steps")
+    stream = torch.cuda.Stream()
+    b = B.Batch(B.TPP, ns, [c.U for c in cl], [c.h0 for c in cl], [c.g1 for c in cl],
+                chunk=autotune.chunks_for(ns), stream=stream.cuda_stream)
+    b.step(cl[0].dt, 8)
+    order = sorted(range(len(cl)), key=lambda q: -ns[q])
+    sample = order[:3] + [order[len(order) // 2], order[-1], 7, 123, 400]
+    worst = 0.0
+    for q in sample:
+        y, _ = OI.propagate_hubbard(cl[q], nsteps=8, selfenergy="tpp")
+        g1, g2 = b.get_cluster(q)
+        e = max(rel(g1, np.stack([y[0].numpy(), y[1].numpy()])), rel(g2, y[2].numpy()))
+        worst = max(worst, e)
+    say(f"   clusters {sample}: worst rel err {worst:.2e}")
+    assert worst < 1e-10
+    b.close()
+
+
+@pytest.mark.parametrize("se,prec", [("gw", "fp64"), ("dsl", "fp64"), ("dsl", "mixed")])
+def test_full_size_general_nb64_sampled(lib, se, prec):
+    """The Nb = 64 workload at a random correlated state: dG1 complete and 20
+    sampled dG2 elements against the element-wise oracle."""
+    from oracle import elements as OE
+    from paper_2002_12717_amd import binding as B
+    from workloads import gw_system
+    s = gw_system()
+    nb = s.nb
+    say(f"[full size] nb=64 {se} {prec} rhs, sampled")
+    r = rng(105, len(se))
+    gl = random_gless(nb, r)
+    g2 = random_g2(nb, r, scale=0.02)
+    code, flags = _gen_se(se)
+    p = B.Propagator(B.GENERAL, code, nb, s.h0, gl, w=s.w, flags=flags,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED)
+    G1d, G2d = cuda(gl), cuda(g2)
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(0.0, G1d, G2d, dG1d, dG2d)
+    p.close()
+    Th, Tw, Tgl, Tg2 = T(s.h0), T(s.w), T(gl), T(g2)
+    ref1 = OG.g1_rhs(OG.hf_hamiltonian(Th, Tw, Tgl), Tgl, OG.collision_integral(Tw, Tg2)).numpy()
+    idx = [tuple(int(v) for v in r.integers(0, nb, 4)) for _ in range(14)]
+    idx += [(3, 3, 7, 7), (5, 9, 9, 5), (0, 63, 63, 0), (12, 12, 12, 12), (1, 2, 1, 2), (63, 0, 31, 32)]
+    ref2 = OE.g2_rhs_elements(Th, Tw, Tgl, Tg2, se, idx).numpy()
+    got2 = dG2d.cpu().numpy()
+    got2 = np.array([got2[e] for e in idx])
+    e1 = rel(dG1d.cpu().numpy(), ref1)
+    e2 = float(np.abs(got2 - ref2).max() / np.abs(ref2).max())
+    say(f"   err G1 {e1:.2e}  err G2 (sampled) {e2:.2e}")
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert e1 < tol and e2 < tol
+
+
+def test_hubbard_single_site(lib):
+    """Degenerate cluster: one site, no hopping (every neighbour table empty)."""
+    from workloads import HubbardSystem
+    h0 = np.zeros((2, 1, 1), complex)
+    h0[0, 0, 0], h0[1, 0, 0] = 0.3, -0.2
+    g1 = np.zeros((2, 1, 1), complex)
+    g1[0, 0, 0], g1[1, 0, 0] = 0.6j, 0.4j
+    s = HubbardSystem("site", 1, 2.0, h0, g1, 0.02, 50)
+    say("[edge] single Hubbard site, SOA and TPP, 50 steps")
+    for se in ("soa", "tpp"):
+        _compare_hubbard_trajectory(s, se, 2, 25, 1e-10)
+
+
+@pytest.mark.parametrize("se", ["soa", "tpp"])
+def test_hubbard_beyond_row_kernel(lib, se):
+    """ns = 65 exceeds the row kernel (one row per wave): the per-element stage
+    kernel runs; one right-hand side against the oracle."""
+    from paper_2002_12717_amd import binding as B
+    say(f"[edge] 65-site chain {se} rhs (per-element kernel)")
+    r = rng(106, len(se))
+    h = chain_hopping(65)
+    h0 = np.stack([h, h])
+    X, Y = random_gless(65, r), random_gless(65, r)
+    A = random_g2(65, r, scale=0.05, exchange=False)
+    p = B.Propagator(B.HUBBARD, _se(se), 65, h0, np.stack([X, Y]), U=1.1)
+    G1d, G2d = cuda(np.stack([X, Y])), cuda(A)
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(0.0, G1d, G2d, dG1d, dG2d)
+    dX, dY, dA = OH.rhs(T(h), T(h), 1.1, T(X), T(Y), T(A), se)
+    e1 = rel(dG1d.cpu().numpy(), np.stack([dX.numpy(), dY.numpy()]))
+    e2 = rel(dG2d.cpu().numpy(), dA.numpy())
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    assert e1 < 1e-12 and e2 < 1e-12
+    p.close()
+
+
+@pytest.mark.parametrize("nb", [1, 2])
+@pytest.mark.parametrize("se", ["soa", "dsl"])
+def test_general_tiny_basis(lib, nb, se):
+    """One and two spin orbitals (padded to one 16-wide tile)."""
+    from paper_2002_12717_amd import binding as B
+    say(f"[edge] general nb={nb} {se} rhs")
+    h, w, gl, g2 = _general_inputs(nb, 3)
+    code, flags = _gen_se(se)
+    p = B.Propagator(B.GENERAL, code, nb, h, gl, w=w, flags=flags)
+    G1d, G2d = cuda(gl), cuda(g2)
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(0.0, G1d, G2d, dG1d, dG2d)
+    d1, d2 = OG.rhs(T(h), T(w), T(gl), T(g2), se)
+    e1 = rel(dG1d.cpu().numpy(), d1.numpy())
+    e2 = rel(dG2d.cpu().numpy(), d2.numpy()) if np.abs(d2.numpy()).max() > 0 else 0.0
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    assert e1 < 1e-12 and e2 < 1e-12
+    p.close()
+
+
+def test_zero_steps_and_uncorrelated_limits(lib):
+    """nsteps = 0 leaves the state untouched; without interaction (U = 0,
+    w = 0) and without initial correlations G2 stays exactly zero."""
+    from paper_2002_12717_amd import binding as B
+    say("[edge] zero steps; U = 0 and w = 0 keep G2 = 0")
+    s = hubbard_chain_system(ns=6, U=0.0)
+    p = B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=0.0)
+    g1a, g2a, ta = p.get_state()
+    p.step(s.dt, 0)
+    g1b, g2b, tb = p.get_state()
+    assert np.array_equal(g1a, g1b) and np.array_equal(g2a, g2b) and ta == tb
+    p.step(s.dt, 50)
+    _, g2c, _ = p.get_state()
+    assert not np.any(g2c)
+    p.close()
+    g = general_system(nb=10, rank=6, nocc=3)
+    p = B.Propagator(B.GENERAL, B.DSL, g.nb, g.h0, g.g1, w=np.zeros_like(g.w))
+    p.step(g.dt, 20)
+    g1d, g2d, _ = p.get_state()
+    assert not np.any(g2d)
+    # the one-particle motion is then the free evolution e^{-iht} G^< e^{iht},
+    # up to the RK4 truncation error (about 1e-7 here)
+    ev, V = np.linalg.eigh(g.h0)
+    Ut = V @ np.diag(np.exp(-1j * ev * 20 * g.dt)) @ V.conj().T
+    ref = Ut @ g.g1 @ Ut.conj().T
+    assert rel(g1d, ref) < 1e-6
+    p.close()

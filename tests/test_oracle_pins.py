@@ -384,3 +384,21 @@ def test_imbalance_definition():
     assert abs(O.hubbard_imbalance(T(flip), T(flip), -x) - 1.0) < 1e-15
     right = np.diag([0, 0, 1j, 1j])
     assert abs(O.hubbard_imbalance(T(right), T(right), x) + 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph", "dsl"])
+def test_elementwise_rhs_equals_full_rhs(se):
+    """The element-wise evaluation used for sampled parity at Nb = 64 equals the
+    full-tensor right-hand side on a small random system (all elements)."""
+    from oracle import elements as E
+    r = rng(11, len(se))
+    nb = 4
+    h = T(gue(nb, r))
+    w = T(factorized_w(nb, 3, r))
+    gl = T(random_gless(nb, r))
+    g2 = T(random_g2(nb, r, scale=0.1))
+    _, d2 = G.rhs(h, w, gl, g2, se)
+    idx = [(i, j, k, l) for i in range(nb) for j in range(nb) for k in range(nb) for l in range(nb)]
+    got = E.g2_rhs_elements(h, w, gl, g2, se, idx)
+    ref = torch.stack([d2[e] for e in idx])
+    assert float((got - ref).abs().max()) < 1e-13 * max(1.0, float(ref.abs().max()))
