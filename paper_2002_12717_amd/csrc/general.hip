@@ -605,7 +605,9 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
 template <typename T, typename S, int OUT>
 __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
                                                       void* __restrict__ dst, int n, int nbp) {
-    __shared__ T a_re[64][17], a_im[64][17], b_re[16][65], b_im[16][65];
+    constexpr int KS = 16;                    // depth of one staged K slice
+    constexpr int PER = 64 * KS / 256;          // elements of A (and of B) per thread and slice
+    __shared__ T a_re[64][KS + 1], a_im[64][KS + 1], b_re[KS][65], b_im[KS][65];
     const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
     const int wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -616,24 +618,33 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
             acc[a][b].clear();
             for (int r4 = 0; r4 < 4; ++r4) accd[a][b][0][r4] = accd[a][b][1][r4] = 0.0;
         }
-    for (int k0 = 0; k0 < n; k0 += 16) {
-        for (int idx = threadIdx.x; idx < 64 * 16; idx += 256) {
-            int r = idx / 16, c = idx % 16;
-            T x, yv;
-            ldc(A + (size_t)(bm + r) * n + k0 + c, x, yv);
-            a_re[r][c] = x;
-            a_im[r][c] = yv;
-            int r2 = idx / 64, c2 = idx % 64;
-            ldc(B + (size_t)(k0 + r2) * n + bn + c2, x, yv);
-            b_re[r2][c2] = x;
-            b_im[r2][c2] = yv;
+    // the next K slice is loaded into registers while the current one runs
+    T pa_re[PER], pa_im[PER], pb_re[PER], pb_im[PER];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = threadIdx.x + q * 256;
+            ldc(A + (size_t)(bm + idx / KS) * n + k0 + idx % KS, pa_re[q], pa_im[q]);
+            ldc(B + (size_t)(k0 + idx / 64) * n + bn + idx % 64, pb_re[q], pb_im[q]);
+        }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < n; k0 += KS) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int idx = threadIdx.x + q * 256;
+            a_re[idx / KS][idx % KS] = pa_re[q];
+            a_im[idx / KS][idx % KS] = pa_im[q];
+            b_re[idx / 64][idx % 64] = pb_re[q];
+            b_im[idx / 64][idx % 64] = pb_im[q];
         }
         __syncthreads();
+        if (k0 + KS < n) fetch(k0 + KS);
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
-                cgemm_tile<T, 16>(
+                cgemm_tile<T, KS>(
                     acc[a][b],
                     [&](int i, int k, T& r, T& m) {
                         r = a_re[i][k];
@@ -645,7 +656,7 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
                     },
                     wm + a * 16, wn + b * 16);
         __syncthreads();
-        if (sizeof(T) == 4 && ((k0 + 16) % 64 == 0 || k0 + 16 >= n)) {
+        if (sizeof(T) == 4 && ((k0 + KS) % 64 == 0 || k0 + KS >= n)) {
             for (int a = 0; a < 2; ++a)
                 for (int b = 0; b < 2; ++b) {
                     for (int r4 = 0; r4 < 4; ++r4) {
