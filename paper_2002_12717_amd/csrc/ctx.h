@@ -68,12 +68,12 @@ struct GeneralData {
     cd* h0 = nullptr;        // [nbp][nbp]
     cd* wm_rows = nullptr;   // W^- as pair matrix rows: [p][q][r][s] = w^-_pqrs   (nbp^4)
     cd* w_coll = nullptr;    // collision layout: [l][p][i][k] = w_iklp           (nbp^4)
-    cd* w_hf = nullptr;      // mean-field layout: [i][j][k][l] = w^-_ikjl        (nbp^4)
+    cd* w_hf = nullptr;      // mean-field layout: [i][j][l][k] = w^-_ikjl        (nbp^4)
     cd* vt = nullptr;        // scratch: transposed right sandwich                (nbp^4)
     cd* dmat = nullptr;      // scratch: D = T^dagger - R                         (nbp^4)
     cd* hhf = nullptr;       // scratch: h^HF of the current stage [nbp][nbp]
     cd* gg = nullptr;        // scratch: G^> of the current stage [nbp][nbp]
-    double* ipart = nullptr; // scratch: collision-integral partial sums
+    cd* ipart = nullptr;     // scratch: collision-integral partial sums [nbp^2][nipart]
     int nipart = 0;
     // GW and the ladders: quasi-Hamiltonian and permuted G2 operand of a GEMM
     cd* heps = nullptr;      // GW: [(p,q)][(j,l)] = h^eps_qjpl; ladders: h^pp, h^ph (nbp^4)

@@ -81,53 +81,145 @@ __device__ __forceinline__ void stage_block(const S* __restrict__ src, T* re, T*
 
 // --------------------------------------------------------------------------- K1
 // h^HF_ij = h0_ij - i sum_kl w^-_ikjl G^<_lk (eq:h_HF) and G^> = G^< - i 1.
-__global__ __launch_bounds__(256) void gen_hf_kernel(const cd* __restrict__ whf,
-                                                    const cd* __restrict__ h0,
-                                                    const cd* __restrict__ gl, cd* __restrict__ hhf,
-                                                    cd* __restrict__ gg, int nbp, int nb) {
-    __shared__ double sr[256], si[256];
-    const int ij = blockIdx.x;
-    const int n2 = nbp * nbp;
-    const cd* row = whf + (size_t)ij * n2;
-    double ar = 0.0, ai = 0.0;
-    for (int kl = threadIdx.x; kl < n2; kl += blockDim.x) {
-        int k = kl / nbp, l = kl % nbp;
-        cd w = row[kl], g = gl[l * nbp + k];
-        ar = fma(w.x, g.x, fma(-w.y, g.y, ar));
-        ai = fma(w.x, g.y, fma(w.y, g.x, ai));
-    }
-    sr[threadIdx.x] = ar;
-    si[threadIdx.x] = ai;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            sr[threadIdx.x] += sr[threadIdx.x + s];
-            si[threadIdx.x] += si[threadIdx.x + s];
+// One work-group per element (ij): coalesced reads of the row (ij) of w^-,
+// cross-lane sums and one barrier.  The rows run as extra work-groups of the
+// gen_vt launch (K2), which does not depend on them: the memory-bound mean
+// field overlaps the matrix-core sandwich.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct HfArgs {
+    const cd* whf;   // [i][j][l][k] = w^-_ikjl
+    const cd* h0;
+    const cd* gl;
+    cd* hhf;
+    cd* gg;          // G^>
+    int nbp, nb;
+};
+
+// Row (ij) of h^HF by one work-group of THREADS threads.
+template <int THREADS>
+__device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
+    constexpr int NW = THREADS / 64;
+    __shared__ double part[2][NW];
+    const int nbp = a.nbp, n2 = nbp * nbp;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // row (ij) of whf is stored in the order (l,k) of G^<_lk, so both operands
+    // are read contiguously
+    const cd* row = a.whf + (size_t)ij * n2;
+    double ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+    for (int m0 = threadIdx.x; m0 < n2; m0 += 4 * THREADS) {
+        cd w[4], g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int m = m0 + THREADS * u;
+            w[u] = m < n2 ? row[m] : make_double2(0.0, 0.0);
+            g[u] = m < n2 ? a.gl[m] : make_double2(0.0, 0.0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ar[u & 1] = fma(w[u].x, g[u].x, fma(-w[u].y, g[u].y, ar[u & 1]));
+            ai[u & 1] = fma(w[u].x, g[u].y, fma(w[u].y, g[u].x, ai[u & 1]));
+        }
     }
-    if (threadIdx.x == 0) {
-        cd h = h0[ij];
-        // h0 - i (ar + i ai) = h0 + ai - i ar
-        hhf[ij] = make_double2(h.x + si[0], h.y - sr[0]);
-        int i = ij / nbp, j = ij % nbp;
-        cd g = gl[ij];
-        gg[ij] = (i == j && i < nb) ? make_double2(g.x, g.y - 1.0) : g;
+    const double wr = wave_sum(ar[0] + ar[1]), wi = wave_sum(ai[0] + ai[1]);
+    if (lane == 0) {
+        part[0][wave] = wr;
+        part[1][wave] = wi;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        sr += part[0][w];
+        si += part[1][w];
+    }
+    const cd h = a.h0[ij];
+    // h0 - i (sr + i si) = h0 + si - i sr
+    a.hhf[ij] = make_double2(h.x + si, h.y - sr);
+    const int i = ij / nbp, j = ij % nbp;
+    const cd g = a.gl[ij];
+    a.gg[ij] = (i == j && i < a.nb) ? make_double2(g.x, g.y - 1.0) : g;
 }
 
 // --------------------------------------------------------------------------- K2
 // Right sandwich on row blocks of W: Vt[k][l][p][q] = (G<^T W_pq G<)[k][l].
+// Work-groups nvt.. of the launch compute the rows of h^HF (K1).
 template <typename T, typename S, int NB>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __restrict__ wrows,
                                                                    const cd* __restrict__ gl,
-                                                                   S* __restrict__ vt) {
+                                                                   S* __restrict__ vt, int nvt,
+                                                                   HfArgs hf) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
+    if ((int)blockIdx.x >= nvt) {
+        hf_row<SH::THREADS>(hf, blockIdx.x - nvt);
+        return;
+    }
     __shared__ T w_re[NB * LD], w_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
     const int wave = threadIdx.x >> 6;
-    const int b0 = xcd_block(blockIdx.x, gridDim.x);
-    for (int blk = b0; blk < NB * NB; blk += gridDim.x) {
+    const int b0 = xcd_block(blockIdx.x, nvt);
+    if constexpr (SH::TPW == 1) {
+        constexpr int PER = NB * NB / SH::THREADS;
+        const int ti = wave / SH::NT, tj = wave % SH::NT;
+        const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+        T ga_re[NB / 4], ga_im[NB / 4], gb_re[NB / 4], gb_im[NB / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < NB / 4; ++s4) {
+            ldc(gl + (4 * s4 + lk) * NB + ti * 16 + li, ga_re[s4], ga_im[s4]);
+            ldc(gl + (4 * s4 + lk) * NB + tj * 16 + li, gb_re[s4], gb_im[s4]);
+        }
+        T pw_re[PER], pw_im[PER];
+        auto fetch = [&](int blk) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                ldc(wrows + (size_t)blk * NB * NB + threadIdx.x + q * SH::THREADS, pw_re[q], pw_im[q]);
+        };
+        if (b0 < NB * NB) fetch(b0);
+        for (int blk = b0; blk < NB * NB; blk += nvt) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = threadIdx.x + q * SH::THREADS, r = idx / NB, cc = idx % NB;
+                w_re[r * LD + cc] = pw_re[q];
+                w_im[r * LD + cc] = pw_im[q];
+            }
+            __syncthreads();
+            const int nxt = blk + nvt;
+            if (nxt < NB * NB) fetch(nxt);
+            CAcc4<T> acc;
+            acc.clear();
+#pragma unroll
+            for (int s4 = 0; s4 < NB / 4; ++s4) {
+                const int k = 4 * s4 + lk, j = tj * 16 + li;
+                acc.mac(ga_re[s4], ga_im[s4], w_re[k * LD + j], w_im[k * LD + j]);
+            }
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                q_re[row * LD + col] = acc.re(r4);
+                q_im[row * LD + col] = acc.im(r4);
+            }
+            __syncthreads();
+            acc.clear();
+#pragma unroll
+            for (int s4 = 0; s4 < NB / 4; ++s4) {
+                const int k = 4 * s4 + lk, i = ti * 16 + li;
+                acc.mac(q_re[i * LD + k], q_im[i * LD + k], gb_re[s4], gb_im[s4]);
+            }
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
+                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re(r4), acc.im(r4));
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    for (int blk = b0; blk < NB * NB; blk += nvt) {
         stage_block<T, S, NB>(wrows + (size_t)blk * NB * NB, w_re, w_im);
         __syncthreads();
         for (int t = 0; t < SH::TPW; ++t) {
@@ -186,7 +278,7 @@ template <typename T, typename S, int NB>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
     const cd* __restrict__ g2, const S* __restrict__ vt, const S* __restrict__ wcoll,
     const cd* __restrict__ gg, const cd* __restrict__ hhf, S* __restrict__ dout,
-    double* __restrict__ ipart) {
+    cd* __restrict__ ipart) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
     using Acc = typename std::conditional<SH::TPW == 1, CAcc4<T>, CAcc<T>>::type;
@@ -332,56 +424,81 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
         }
         __syncthreads();
     }
-    double* part = ipart + (size_t)blockIdx.x * NB * NB * 2;
+    // collision partials element-major, ipart[(i,j)][part], with the logical
+    // (XCD-contiguous) block number as the part: one element's parts are one
+    // contiguous read for the reduction, and a cache line of them is written
+    // from a single XCD
     for (int t = 0; t < SH::TPW; ++t) {
         const int tile = wave * SH::TPW + t, ti = tile / SH::NT, tj = tile % SH::NT;
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
             int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-            part[2 * (row * NB + col)] = isum[t][0][r4];
-            part[2 * (row * NB + col) + 1] = isum[t][1][r4];
+            ipart[(size_t)(row * NB + col) * gridDim.x + bfirst] = make_double2(isum[t][0][r4], isum[t][1][r4]);
         }
     }
 }
 
 // --------------------------------------------------------------------------- K5
-// G1 equation eq:eom_gone-2 with I from the partials; writes I for observables.
-// One wavefront per element (i,j): the lanes share the sums over partials and
-// over the commutator index, then combine with cross-lane reductions.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// G1 equation eq:eom_gone-2, evaluated by one wavefront per element pair:
+// I_ij and I_ji from the collision partials, [h^HF, G^<], the Runge-Kutta
+// update of G1 and, at the last stage, the divergence check.  Runs inside the
+// combine kernel, after its G2 work.
+struct G1Args {
+    const cd* ipart;   // [nbp^2][nparts] partial sums of sum_lp Wc_lp C_lp^T
+    int nparts;
+    const cd* hhf;
+    const cd* gl;      // G^< of the stage
+    const cd* y;
+    cd* acc;
+    cd* out;
+    cd* icoll;         // I, written by right-hand-side evaluations
+    int nb;
+    int* flag;
+};
 
 template <int MODE>
-__global__ __launch_bounds__(256) void gen_g1_kernel(const double* __restrict__ ipart, int nparts,
-                                                    const cd* __restrict__ hhf,
-                                                    const cd* __restrict__ gl,
-                                                    const cd* __restrict__ y, cd* __restrict__ acc,
-                                                    cd* __restrict__ out, cd* __restrict__ icoll,
-                                                    double cb, double cc, int nbp, int nb,
-                                                    int* __restrict__ flag) {
-    const int n2 = nbp * nbp;
-    const int lane = threadIdx.x & 63;
-    const int e = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (e >= n2) return;
+__device__ __forceinline__ void g1_update(const G1Args& g, int e, cd comm, cd Iij, cd Iji, int nbp,
+                                          double cb, double cc) {
+    const cd f = cmul_mi(cadd(comm, cadd(Iij, cconj(Iji))));
+    if (MODE == RK_RHS) g.icoll[e] = Iij;
+    rk_update<MODE>(e, f, g.gl[e], g.y, g.acc, g.out, cb, cc);
     const int i = e / nbp, j = e % nbp;
-    const int et = j * nbp + i;
-    double sr = 0, si = 0, tr = 0, ti = 0;
-    for (int g = lane; g < nparts; g += 64) {
-        const double* p = ipart + (size_t)g * n2 * 2;
-        sr += p[2 * e];
-        si += p[2 * e + 1];
-        tr += p[2 * et];
-        ti += p[2 * et + 1];
+    if (MODE == RK_LAST && i < g.nb) {
+        cd v = g.out[e];
+        bool bad = !(isfinite(v.x) && isfinite(v.y));
+        if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
+        if (bad) atomicOr(g.flag, 1);
     }
-    double cr = 0, ci = 0;
+}
+
+// The elements (i,j) and (j,i), i <= j: both need I_ij and I_ji, so each
+// partial row is read once.
+template <int MODE>
+__device__ __forceinline__ void g1_pair(const G1Args& g, int i, int j, int lane, int nbp, double cb,
+                                        double cc) {
+    const int e = i * nbp + j, et = j * nbp + i;
+    const cd* pe = g.ipart + (size_t)e * g.nparts;
+    const cd* pt = g.ipart + (size_t)et * g.nparts;
+    double sr = 0, si = 0, tr = 0, ti = 0;
+#pragma unroll 4
+    for (int p = lane; p < g.nparts; p += 64) {
+        const cd a = pe[p], b = pt[p];
+        sr += a.x;
+        si += a.y;
+        tr += b.x;
+        ti += b.y;
+    }
+    // [h^HF, G^<] at (i,j) and (j,i)
+    double cr = 0, ci = 0, dr = 0, di = 0;
     for (int p = lane; p < nbp; p += 64) {
-        cd a = cmul(hhf[i * nbp + p], gl[p * nbp + j]);
-        cd b = cmul(gl[i * nbp + p], hhf[p * nbp + j]);
+        const cd a = cmul(g.hhf[i * nbp + p], g.gl[p * nbp + j]);
+        const cd b = cmul(g.gl[i * nbp + p], g.hhf[p * nbp + j]);
+        const cd a2 = cmul(g.hhf[j * nbp + p], g.gl[p * nbp + i]);
+        const cd b2 = cmul(g.gl[j * nbp + p], g.hhf[p * nbp + i]);
         cr += a.x - b.x;
         ci += a.y - b.y;
+        dr += a2.x - b2.x;
+        di += a2.y - b2.y;
     }
     sr = wave_sum(sr);
     si = wave_sum(si);
@@ -389,29 +506,25 @@ __global__ __launch_bounds__(256) void gen_g1_kernel(const double* __restrict__ 
     ti = wave_sum(ti);
     cr = wave_sum(cr);
     ci = wave_sum(ci);
+    dr = wave_sum(dr);
+    di = wave_sum(di);
     if (lane != 0) return;
-    cd Iij = make_double2(si, -sr);  // -i (sr + i si)
-    cd Iji = make_double2(ti, -tr);
-    cd f = cmul_mi(cadd(make_double2(cr, ci), cadd(Iij, cconj(Iji))));
-    if (MODE == RK_RHS) icoll[e] = Iij;
-    rk_update<MODE>(e, f, gl[e], y, acc, out, cb, cc);
-    if (MODE == RK_LAST && i < nb) {
-        cd v = out[e];
-        bool bad = !(isfinite(v.x) && isfinite(v.y));
-        if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
-        if (bad) atomicOr(flag, 1);
-    }
+    const cd Iij = make_double2(si, -sr);  // -i (sr + i si)
+    const cd Iji = make_double2(ti, -tr);
+    g1_update<MODE>(g, e, make_double2(cr, ci), Iij, Iji, nbp, cb, cc);
+    if (et != e) g1_update<MODE>(g, et, make_double2(dr, di), Iji, Iij, nbp, cb, cc);
 }
 
 // --------------------------------------------------------------------------- K4
-// dG2 = -i (D - D^dagger) [+ -i (Pi - conj(Pi_lkji)) for GW], fused RK4 update.
+// dG2 = -i (D - D^dagger) [+ -i (Pi - conj(Pi_lkji)) for GW], fused RK4 update;
+// then the G1 equation (K5) on the same launch.
 template <int MODE, typename S, bool GW>
 __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ D, int n,
                                                          const cd* __restrict__ in,
                                                          const cd* __restrict__ y,
                                                          cd* __restrict__ acc, cd* __restrict__ out,
                                                          const cd* __restrict__ pim, int nbp,
-                                                         double cb, double cc) {
+                                                         double cb, double cc, G1Args g1) {
     __shared__ double t1r[32][33], t1i[32][33], t2r[32][33], t2i[32][33];
     const int nt = n / 32;
     const int bx = blockIdx.x % nt, by = blockIdx.x / nt;
@@ -443,6 +556,12 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
         cd yin = make_double2(0.0, 0.0);
         if (MODE == RK_FIRST) yin = in[e];
         rk_update<MODE>((int)e, f, yin, y, acc, out, cb, cc);
+    }
+    // the G1 element pairs (i <= j), one per wavefront, spread over the work-groups
+    const int n1 = nbp * nbp;
+    for (int e1 = (threadIdx.x >> 6) * gridDim.x + blockIdx.x; e1 < n1; e1 += 4 * gridDim.x) {
+        const int i = e1 / nbp, j = e1 - i * nbp;
+        if (i <= j) g1_pair<MODE>(g1, i, j, threadIdx.x & 63, nbp, cb, cc);
     }
 }
 
@@ -802,9 +921,12 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
     const bool mixed = sizeof(T) == 4;
     const S* wrows = mixed ? (const S*)g.wm_rows32 : (const S*)g.wm_rows;
     const S* wcoll = mixed ? (const S*)g.w_coll32 : (const S*)g.w_coll;
-    const int grid_vt = std::min(NB * NB, 1024);
-    hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0, c->stream,
-                       wrows, in.g1, (S*)g.vt);
+    // a single-tile-per-wave shape prefetches the next row block in registers and
+    // wants several blocks per work-group; the larger shapes want the wider grid
+    const int grid_vt = std::min(NB * NB, Shape<NB>::TPW == 1 ? 512 : 1024);
+    const HfArgs hf{g.w_hf, g.h0, in.g1, g.hhf, g.gg, g.nbp, g.nb};
+    hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt + NB * NB), dim3(Shape<NB>::THREADS), 0,
+                       c->stream, wrows, in.g1, (S*)g.vt, grid_vt, hf);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_vt");
     const int se = c->d.selfenergy;
@@ -865,20 +987,16 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     GeneralData& g = c->gen;
     const int n = g.nbp * g.nbp;
     const int nt = n / 32;
+    const G1Args g1{g.ipart, g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1,
+                    g.icoll, g.nb, c->dflag};
     if (c->d.selfenergy == G1G2_GW || c->d.selfenergy == G1G2_DSL)
         hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(nt * nt), dim3(256), 0, c->stream,
-                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc);
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
     else
         hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(nt * nt), dim3(256), 0, c->stream,
-                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc);
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_combine");
-    const int n2 = g.nbp * g.nbp;
-    hipLaunchKernelGGL((gen_g1_kernel<MODE>), dim3((n2 + 3) / 4), dim3(256), 0, c->stream, g.ipart,
-                       g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1, g.icoll, cb, cc, g.nbp, g.nb,
-                       c->dflag);
-    HIP_OK(c, hipGetLastError());
-    prof_mark(c, "gen_g1");
     return G1G2_OK;
 }
 
@@ -974,7 +1092,7 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
                     cd v = W(i, j, k, l), vx = W(i, j, l, k);
                     rows[P4(i, j, k, l)] = exch ? csub(v, vx) : v;   // W^-_pqrs (or W for GW)
                     coll[P4(k, l, i, j)] = v;                         // [l][p][i][k] = w_iklp
-                    hf[P4(i, k, j, l)] = csub(v, vx);                 // [i][j][k][l] = w^-_ikjl
+                    hf[P4(i, k, l, j)] = csub(v, vx);                 // [i][j][l][k] = w^-_ikjl
                 }
     g1g2_status s;
     if ((s = upload(c, &g.wm_rows, rows)) != G1G2_OK) return s;
@@ -1026,19 +1144,13 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
     HIP_OK(c, hipMalloc(&g.gg, (size_t)nbp * nbp * sizeof(cd)));
     HIP_OK(c, hipMalloc(&g.icoll, (size_t)nbp * nbp * sizeof(cd)));
     g.nipart = main_grid(nbp);
-    HIP_OK(c, hipMalloc(&g.ipart, (size_t)g.nipart * nbp * nbp * 2 * sizeof(double)));
+    HIP_OK(c, hipMalloc(&g.ipart, (size_t)g.nipart * nbp * nbp * sizeof(cd)));
     return gen_set_h0(c, h0);
 }
 
 g1g2_status gen_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc) {
     (void)t;
-    GeneralData& g = c->gen;
-    const int nbp = g.nbp;
-    hipLaunchKernelGGL(gen_hf_kernel, dim3(nbp * nbp), dim3(256), 0, c->stream, g.w_hf, g.h0, in.g1,
-                       g.hhf, g.gg, nbp, g.nb);
-    HIP_OK(c, hipGetLastError());
-    prof_mark(c, "gen_hf");
     g1g2_status s;
     if (c->d.precision == G1G2_MIXED) {
         if ((s = dispatch_blocks<float, float2>(c, in)) != G1G2_OK) return s;
