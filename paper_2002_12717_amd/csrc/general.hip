@@ -526,8 +526,13 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
                                                          const cd* __restrict__ pim, int nbp,
                                                          double cb, double cc, G1Args g1) {
     __shared__ double t1r[32][33], t1i[32][33], t2r[32][33], t2i[32][33];
-    const int nt = n / 32;
-    const int bx = blockIdx.x % nt, by = blockIdx.x / nt;
+    // work-group -> tile pair (by, bx), bx <= by, in triangular order; both
+    // tiles of the pair are updated from one read of D_(by,bx) and D_(bx,by)
+    const int tb = blockIdx.x;
+    int by = (int)((sqrtf(8.0f * (float)tb + 1.0f) - 1.0f) * 0.5f);
+    while ((by + 1) * (by + 2) / 2 <= tb) ++by;
+    while (by * (by + 1) / 2 > tb) --by;
+    const int bx = tb - by * (by + 1) / 2;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         double a, b;
@@ -539,12 +544,8 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
         t2i[r][tx] = b;
     }
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int row = by * 32 + r, col = bx * 32 + tx;
+    auto update = [&](int row, int col, double zr, double zi) {
         const size_t e = (size_t)row * n + col;
-        // D_rc - conj(D_cr)
-        double zr = t1r[r][tx] - t2r[tx][r];
-        double zi = t1i[r][tx] + t2i[tx][r];
         if (GW) {
             const int i = row / nbp, j = row % nbp, k = col / nbp, l = col % nbp;
             cd p1 = pim[e];
@@ -556,6 +557,11 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
         cd yin = make_double2(0.0, 0.0);
         if (MODE == RK_FIRST) yin = in[e];
         rk_update<MODE>((int)e, f, yin, y, acc, out, cb, cc);
+    };
+    for (int r = ty; r < 32; r += 8) {
+        // D_rc - conj(D_cr) on tile (by, bx) and, off the diagonal, on (bx, by)
+        update(by * 32 + r, bx * 32 + tx, t1r[r][tx] - t2r[tx][r], t1i[r][tx] + t2i[tx][r]);
+        if (bx != by) update(bx * 32 + r, by * 32 + tx, t2r[r][tx] - t1r[tx][r], t2i[r][tx] + t1i[tx][r]);
     }
     // the G1 element pairs (i <= j), one per wavefront, spread over the work-groups
     const int n1 = nbp * nbp;
@@ -986,14 +992,14 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
                         const Regs& out, double cb, double cc) {
     GeneralData& g = c->gen;
     const int n = g.nbp * g.nbp;
-    const int nt = n / 32;
+    const int nt = n / 32, ntiles = nt * (nt + 1) / 2;
     const G1Args g1{g.ipart, g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1,
                     g.icoll, g.nb, c->dflag};
     if (c->d.selfenergy == G1G2_GW || c->d.selfenergy == G1G2_DSL)
-        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(nt * nt), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(ntiles), dim3(256), 0, c->stream,
                            (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
     else
-        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(nt * nt), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(ntiles), dim3(256), 0, c->stream,
                            (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_combine");
