@@ -268,7 +268,8 @@ def run_hubbard(args, torch, B, kind):
     out.update({
         "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                     "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" else None,
+                     # the counters were taken on the SOA instantiation
+                     "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" and se == "soa" else None,
                      "kernel_ms_avg": round(tot_ms / cnt, 6),
                      "bytes_per_launch": bytes_per_launch, "launches": cnt},
         "kernels": kernel_table(prof),
