@@ -46,6 +46,7 @@ struct HubbardData {
     WorkItem* work = nullptr;      // device work list
     int nwork = 0;
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
+    bool realhop = false;          // every hopping (off-diagonal h0) is real
     WorkItem* dwork = nullptr;     // TPH: work list of the diagonal gather
     int ndwork = 0;
     cd* diag = nullptr;            // TPH: per cluster R [ns]^3 and S [ns]^3

@@ -272,7 +272,17 @@ __device__ __forceinline__ double wave_uniform(double v) {
 }
 __device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x), wave_uniform(v.y)); }
 
-template <int MODE, int SE, bool MIXED>
+// Element i of an array below 4 GiB, addressed as base + 32-bit byte offset:
+// with a wave-uniform base the load takes the scalar-base + vector-offset form
+// and needs no 64-bit address arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ cd ldo(const T* __restrict__ p, unsigned i) {
+    return ld_c(reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + i * (unsigned)sizeof(T)), 0);
+}
+
+// REALH: every hopping of the launch is real (h_pq = h_qp), so each neighbour
+// term is a real-by-complex product.
+template <int MODE, int SE, bool MIXED, bool REALH>
 __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH, GW = SE == SE_GW;
     using TI = typename StageTypes<MODE, MIXED>::In;
@@ -282,6 +292,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     // neighbour tables padded to ZR entries per site: a missing neighbour points
     // at the site itself with hopping 0, so every neighbour sum is branch-free
     __shared__ int snb[2 * NS_MAX_ROW * ZR];
+    __shared__ int sok[2 * NS_MAX_ROW * ZR];   // (p - site) ns: element offset of a k-neighbour row
     __shared__ cd shp[2 * NS_MAX_ROW * ZR];
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
@@ -315,6 +326,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
         const int row = q / ZR, qq = q - row * ZR, site = row % ns;
         const int p = qq < z ? a.nbr[row * z + qq] : -1;
         snb[q] = p >= 0 ? p : site;
+        sok[q] = p >= 0 ? (p - site) * ns : 0;
         shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
     }
     __syncthreads();
@@ -325,7 +337,8 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     const int* nbd = snb + ns * ZR;
     const cd* hu = shp;
     const cd* hd = shp + ns * ZR;
-    const int *nbI = nbu, *nbJ = nbd, *nbK = nbu, *nbL = nbd;
+    const int *nbI = nbu, *nbJ = nbd, *nbL = nbd;
+    const int* okK = sok;   // k-neighbour offsets for the spin of the k index
     const cd *hI = hu, *hJ = hd, *hK = hu, *hL = hd;
     const cd *eI = eu, *eJ = ed, *eK = eu, *eL = ed;
     const cd* __restrict__ X = a.X;
@@ -341,6 +354,8 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 #pragma unroll
     for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? sub * ns + nbL[l * ZR + q] : lane;
     cd el = lane_ok ? eL[l] : cmk(0.0, 0.0);
+    // per slice: element offsets of the i- and j-neighbour rows (wave-uniform)
+    int oI[ZR], oJ[ZR];
     // first unit of this wave; units run over channel, slice, k-block
     int u = w.start + __builtin_amdgcn_readfirstlane(tid >> 6);
     int slice = u / nkb, kb = u - slice * nkb;   // slice counts (channel, i, j)
@@ -370,7 +385,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                     const cd* es = ch == 2 ? ed : eu;
                     nbI = ch == 0 ? nbu : nbs;
                     nbJ = ch == 0 ? nbd : nbs;
-                    nbK = nbI;
+                    okK = (ch == 2) ? sok + ns * ZR : sok;
                     nbL = nbJ;
                     hI = ch == 0 ? hu : hs;
                     hJ = ch == 0 ? hd : hs;
@@ -401,15 +416,20 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             j = sl - i * ns;
             ei = wave_uniform(eI[i]);
             ej = wave_uniform(eJ[j]);
+#pragma unroll
+            for (int q = 0; q < ZR; ++q) {
+                oI[q] = __builtin_amdgcn_readfirstlane((nbI[i * ZR + q] - i) * ns3);
+                oJ[q] = __builtin_amdgcn_readfirstlane((nbJ[j * ZR + q] - j) * ns2);
+            }
             xij = wave_uniform(X[i * ns + j]);
             yji = wave_uniform(Y[j * ns + i]);
             dij = (double)(i == j);
             if (lane_ok) {
-                xil = X[i * ns + l];
-                yjl = Y[j * ns + l];
-                yil = Y[i * ns + l];
-                if (TPP) dll = ld_c(A, (l * ns + l) * ns2 + sl);
-                if (TPH) sijl = DS[(i * ns + j) * ns + l];
+                xil = ldo(X, i * ns + l);
+                yjl = ldo(Y, j * ns + l);
+                yil = ldo(Y, i * ns + l);
+                if (TPP) dll = ldo(A, (l * ns + l) * ns2 + sl);
+                if (TPH) sijl = ldo(DS, (i * ns + j) * ns + l);
             }
         }
         const int k = kb * rpw + sub;
@@ -417,7 +437,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
         const int kk = act ? k : 0;
         const int slc = GW ? slice - ch * ns2 : slice;   // (i, j) of this channel
         const int e = slc * ns2 + kk * ns + l;
-        const cd av = act ? ld_c(Ach, e) : cmk(0.0, 0.0);
+        const cd av = act ? ldo(Ach, e) : cmk(0.0, 0.0);
         cd vl[ZR];
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
@@ -427,28 +447,45 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
         if (act) {
             // sum_p A_ijpl h_pk + sum_p A_ijkp h_pl, with h_pk = conj(h_kp)
             cd r = cmk(0.0, 0.0);
+            const int* okk = okK + kk * ZR;
+            const cd* hkk = hK + kk * ZR;
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
-                r = cfma_conjb(r, vl[q], hL[l * ZR + q]);
-                r = cfma_conjb(r, ld_c(Ach, e + (nbK[kk * ZR + q] - kk) * ns), hK[kk * ZR + q]);
+                const cd vk = ldo(Ach, e + okk[q]);
+                if (REALH) {
+                    const double hq = hL[l * ZR + q].x;
+                    r.x = fma(vl[q].x, hq, fma(vk.x, hkk[q].x, r.x));
+                    r.y = fma(vl[q].y, hq, fma(vk.y, hkk[q].x, r.y));
+                } else {
+                    r = cfma_conjb(r, vl[q], hL[l * ZR + q]);
+                    r = cfma_conjb(r, vk, hkk[q]);
+                }
             }
             const cd ek = eK[kk];
             cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
             c = csub(c, r);
+            const cd* hii = hI + i * ZR;
+            const cd* hjj = hJ + j * ZR;
 #pragma unroll
             for (int q = 0; q < ZR; ++q) {
-                c = cfma(c, hI[i * ZR + q], ld_c(Ach, e + (nbI[i * ZR + q] - i) * ns3));
-                c = cfma(c, hJ[j * ZR + q], ld_c(Ach, e + (nbJ[j * ZR + q] - j) * ns2));
+                const cd vi = ldo(Ach, e + oI[q]), vj = ldo(Ach, e + oJ[q]);
+                if (REALH) {
+                    c.x = fma(hii[q].x, vi.x, fma(hjj[q].x, vj.x, c.x));
+                    c.y = fma(hii[q].x, vi.y, fma(hjj[q].x, vj.y, c.y));
+                } else {
+                    c = cfma(c, hii[q], vi);
+                    c = cfma(c, hjj[q], vj);
+                }
             }
             if (GW) {   // polarization terms of the channel (Sec. VII.B, reading of the partner spins)
-                const cd s1 = S1[j * ns + l], s2 = S2[kk * ns + i];
-                const cd p1 = cmul_mi(cmul(s1, csub(D1[(i * ns + kk) * ns + j], D1[(i * ns + kk) * ns + l])));
-                const cd p2 = cmul_mi(cmul(s2, csub(D2[(kk * ns + j) * ns + l], D2[(i * ns + j) * ns + l])));
+                const cd s1 = ldo(S1, j * ns + l), s2 = ldo(S2, kk * ns + i);
+                const cd p1 = cmul_mi(cmul(s1, csub(ldo(D1, (i * ns + kk) * ns + j), ldo(D1, (i * ns + kk) * ns + l))));
+                const cd p2 = cmul_mi(cmul(s2, csub(ldo(D2, (kk * ns + j) * ns + l), ldo(D2, (i * ns + j) * ns + l))));
                 c = cadd(c, cscale(csub(p1, cconj(p2)), a.U));
             }
-            const cd xkl = X[kk * ns + l], ykl = Y[kk * ns + l];
+            const cd xkl = ldo(X, kk * ns + l), ykl = ldo(Y, kk * ns + l);
             if (!GW || ch == 0) {   // source (eq:soa-cubic-scheme), channel A only
-            const cd xik = X[i * ns + kk], xjk = X[j * ns + kk], yjk = Y[j * ns + kk];
+            const cd xik = ldo(X, i * ns + kk), xjk = ldo(X, j * ns + kk), yjk = ldo(Y, j * ns + kk);
             const cd xlk = cmk(-xkl.x, xkl.y);
             const double dd = dij - (double)(kk == l);
             cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
@@ -457,10 +494,10 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             }
             if (TPP) {   // ladder (Sec. VII.C) and its partner
                 const int kl = kk * ns + l;
-                cd dii = ld_c(A, (i * ns + i) * ns2 + kl), djj = ld_c(A, (j * ns + j) * ns2 + kl);
+                cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
                 cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
                 if (i == j) l1 = cadd(l1, dii);
-                cd dkk = ld_c(A, (kk * ns + kk) * ns2 + slice);
+                cd dkk = ldo(A, (kk * ns + kk) * ns2 + slice);
                 cd ylk = cmk(-ykl.x, ykl.y);
                 cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
                 if (kk == l) l2 = cadd(l2, dkk);
@@ -469,9 +506,9 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner
                 //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
                 //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
-                const cd rjki = DR[(j * ns + kk) * ns + i], rjkl = DR[(j * ns + kk) * ns + l];
-                const cd sikl = DS[(i * ns + kk) * ns + l];
-                const cd ykj = Y[kk * ns + j], xkj = X[kk * ns + j];
+                const cd rjki = ldo(DR, (j * ns + kk) * ns + i), rjkl = ldo(DR, (j * ns + kk) * ns + l);
+                const cd sikl = ldo(DS, (i * ns + kk) * ns + l);
+                const cd ykj = ldo(Y, kk * ns + j), xkj = ldo(X, kk * ns + j);
                 cd l1 = cmul_i(csub(cmul(yil, rjki), cmul(xil, rjkl)));
                 cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
                 c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
@@ -519,9 +556,14 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
         hipLaunchKernelGGL((hub_diag_kernel<TI, SE>), dim3(c->hub.ndwork), dim3(256), 0, c->stream,
                            c->hub.desc, c->hub.dwork, s.in2, c->hub.diag);
     }
-    if (c->hub.rows || SE == SE_GW)   // GW runs on the row kernel only (checked at setup)
-        hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
-    else
+    if (c->hub.rows || SE == SE_GW) {   // GW runs on the row kernel only (checked at setup)
+        if (c->hub.realhop)
+            hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork), dim3(256), 0,
+                               c->stream, s);
+        else
+            hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork), dim3(256), 0,
+                               c->stream, s);
+    } else
         hipLaunchKernelGGL((hub_stage_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
 }
 
@@ -680,6 +722,45 @@ void hub_free(g1g2_ctx* c) {
     H.drive_tau = tau;
 }
 
+// Work-groups are dispatched round-robin over the 8 XCDs of the device
+// (work-group b runs on XCD b mod 8), each XCD with its own L2.  For a batch,
+// the G2 work items (in cluster order) are split into 8 contiguous groups of
+// equal cost, one per XCD, and interleaved so that work-group b takes the next
+// item of group b mod 8.  A cluster's rows, and the neighbour rows its
+// commutator stencil re-reads, are then all processed behind one L2 (on the
+// 512-cluster batch this halves the fabric reads of a stage).  Each group
+// starts with the G1 updates of its clusters, which then overlap the G2 items
+// instead of trailing them; shorter groups are padded with empty items.
+std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& g2, const std::vector<long long>& cost,
+                                const std::vector<WorkItem>& g1) {
+    constexpr int NX = 8;
+    long long total = 0;
+    for (long long v : cost) total += v;
+    std::vector<std::vector<WorkItem>> grp(NX), g2grp(NX);
+    std::vector<int> first_group(g1.size(), -1);
+    long long prefix = 0;
+    for (size_t q = 0; q < g2.size(); ++q) {
+        const long long mid2 = 2 * prefix + cost[q];   // twice the item's midpoint
+        const int x = total > 0 ? (int)std::min<long long>(NX - 1, mid2 * NX / (2 * total)) : 0;
+        prefix += cost[q];
+        g2grp[x].push_back(g2[q]);
+        if (first_group[g2[q].cluster] < 0) first_group[g2[q].cluster] = x;
+    }
+    for (size_t cl = 0; cl < g1.size(); ++cl) grp[std::max(first_group[cl], 0)].push_back(g1[cl]);
+    size_t m = 0;
+    for (int x = 0; x < NX; ++x) {
+        grp[x].insert(grp[x].end(), g2grp[x].begin(), g2grp[x].end());
+        m = std::max(m, grp[x].size());
+    }
+    std::vector<WorkItem> out(m * NX);
+    for (size_t b = 0; b < out.size(); ++b) {
+        const std::vector<WorkItem>& gx = grp[b % NX];
+        const size_t r = b / NX;
+        out[b] = r < gx.size() ? gx[r] : WorkItem{gx.empty() ? 0 : gx[0].cluster, 0, 0};
+    }
+    return out;
+}
+
 g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, const cd* const* h0s,
                       const int* chunk_in) {
     HubbardData& H = c->hub;
@@ -690,6 +771,8 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     std::vector<cd> hop_all;
     std::vector<double> d0_all;
     std::vector<WorkItem> work, g1work, dwork;
+    std::vector<long long> wcost;   // elements of each G2 work item
+    bool realhop = true;            // every hopping of every cluster is real
     std::vector<int> chunks(ncl);
     bool rowk = true;
     for (int cl = 0; cl < ncl; ++cl) {
@@ -726,8 +809,10 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                                          "h0 is not Hermitian (cluster " + std::to_string(cl) + ")");
                     if (i == j)
                         d0[s * ns + i] = v.x;
-                    else if (v.x != 0.0 || v.y != 0.0)
+                    else if (v.x != 0.0 || v.y != 0.0) {
                         rows[s * ns + i].push_back({j, v});
+                        if (v.y != 0.0) realhop = false;
+                    }
                 }
         int zmax = 1;
         for (auto& r : rows) zmax = std::max<int>(zmax, (int)r.size());
@@ -759,13 +844,19 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             int upw = std::max(4, (int)std::lround((double)want / (rpw * ns)));
             upw = (upw + 3) / 4 * 4;
             chunks[cl] = upw * rpw * ns;
-            for (long long u0 = 0; u0 < nunits; u0 += upw)
-                work.push_back({cl, (int)u0, (int)std::min<long long>(nunits, u0 + upw)});
+            for (long long u0 = 0; u0 < nunits; u0 += upw) {
+                const long long u1 = std::min<long long>(nunits, u0 + upw);
+                work.push_back({cl, (int)u0, (int)u1});
+                wcost.push_back((u1 - u0) * rpw * ns);
+            }
         } else {
             int ch = (chunk_in && chunk_in[cl] != 0) ? std::abs(chunk_in[cl]) : 1024;
             chunks[cl] = ch;
-            for (long long st = 0; st < n4; st += ch)
-                work.push_back({cl, (int)st, (int)std::min<long long>(n4, st + ch)});
+            for (long long st = 0; st < n4; st += ch) {
+                const long long e1 = std::min<long long>(n4, st + ch);
+                work.push_back({cl, (int)st, (int)e1});
+                wcost.push_back(e1 - st);
+            }
         }
         g1work.push_back({cl, -1, -1});
         const int n3 = ns * ns * ns;
@@ -775,14 +866,18 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         g1off += 2LL * ns * ns;
         xoff += ns;
     }
-    // G1 updates first: they then overlap with the G2 items instead of trailing them
-    work.insert(work.begin(), g1work.begin(), g1work.end());
+    if (ncl > 1) {
+        work = xcd_order(work, wcost, g1work);
+    } else {   // one cluster: its G1 update first, then the rows in order
+        work.insert(work.begin(), g1work.begin(), g1work.end());
+    }
     if (se == SE_GW && !rowk)
         return set_error(c, G1G2_EUNSUPPORTED,
                          "Hubbard GW needs ns <= 64, at most 4 neighbours per site and chunk > 0");
     hub_free(c);
     H.ncl = ncl;
     H.rows = rowk;
+    H.realhop = realhop;
     H.ndwork = (int)dwork.size();
     H.hdesc = desc;
     H.chunk = chunks;
