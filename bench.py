@@ -38,7 +38,7 @@ PEAK_HBM = 8000.0          # GB/s
 TRAFFIC = {
     "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
     "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
-    "hub_stage/2d": {"bytes": 2.12e9, "src": "hubbard.hip", "kernel": "hub_row_kernel", "sha1": "22da4f6f1238"},
+    "hub_stage/2d": {"bytes": 0.0, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "?"},
 }
 
 

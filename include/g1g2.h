@@ -83,7 +83,15 @@ typedef enum { G1G2_FP64 = 0, G1G2_MIXED = 1 } g1g2_precision;
 
 enum {
     G1G2_PTR_DEVICE = 1,    /* host-side pointer arguments are device pointers      */
-    G1G2_GW_EXCHANGE = 2    /* GW: use Psi^- instead of Psi (end of Sec. IV.B)      */
+    G1G2_GW_EXCHANGE = 2,   /* GW: use Psi^- instead of Psi (end of Sec. IV.B)      */
+    /* Hubbard stage kernel (both set: EINVAL).  By default SOA, TPP and TPH use
+     * the slice kernel (a work-group stages whole (i,j) slices of G2 in LDS)
+     * when the clusters hold at least 2^20 G2 elements in all, else the row
+     * kernel (one wave per G2 row); GW always uses the row kernel.  Both need
+     * ns <= 64 and at most 4 neighbours per site, else the per-element kernel
+     * runs. */
+    G1G2_HUB_ROW_KERNEL = 4,    /* Hubbard: row kernel whatever the size          */
+    G1G2_HUB_SLICE_KERNEL = 8   /* Hubbard SOA/TPP/TPH: slice kernel whatever the size */
 };
 
 typedef struct {
@@ -169,11 +177,11 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
- * table: chunk > 0 selects the row stage kernel (one wave per G2 row
- * A[i][j][k][:], rounded to whole wave units of rows; needs every ns <= 64
- * and at most 4 neighbours per site, else the per-element kernel runs),
- * chunk < 0 the per-element kernel with |chunk| elements per work-group (any
- * negative entry selects the per-element kernel for the whole batch).
+ * table: chunk > 0 is the granularity of the row stage kernel (one wave per
+ * G2 row A[i][j][k][:], rounded to whole wave units of rows; the slice kernel
+ * always stages whole slices, see G1G2_HUB_SLICE_KERNEL), chunk < 0 selects
+ * the per-element kernel with |chunk| elements per work-group (any negative
+ * entry selects the per-element kernel for the whole batch).
  * g1g2_step_rk4, g1g2_profile and g1g2_destroy act on the whole batch; the
  * single-cluster calls (rhs, get/set_state, set_h0/U/drive) return ESTATE. */
 g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, const int32_t* ns,

@@ -19,7 +19,7 @@ LIBPATH = os.path.join(PKG, "libg1g2.so")
 GENERAL, HUBBARD = 0, 1
 SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
-PTR_DEVICE, GW_EXCHANGE = 1, 2
+PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL = 1, 2, 4, 8
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
 
@@ -234,13 +234,13 @@ class Batch(Propagator):
     """A ragged batch of Hubbard clusters in one context (g1g2_batch_init)."""
 
     def __init__(self, selfenergy: int, ns, U, h0s, g1s, chunk=None, stream: int = 0,
-                 precision: int = FP64):
+                 precision: int = FP64, flags: int = 0):
         self.lib = load()
-        self.basis, self.flags = HUBBARD, 0
+        self.basis, self.flags = HUBBARD, flags
         self.ns = [int(x) for x in ns]
         n = len(self.ns)
         self.nb = max(self.ns)
-        self.desc = Desc(HUBBARD, selfenergy, precision, 0, self.nb, 0.0)
+        self.desc = Desc(HUBBARD, selfenergy, precision, flags, self.nb, 0.0)
         h = [np.ascontiguousarray(a, np.complex128) for a in h0s]
         g = [np.ascontiguousarray(a, np.complex128) for a in g1s]
         ns_a = np.asarray(self.ns, np.int32)

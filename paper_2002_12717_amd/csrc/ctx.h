@@ -47,6 +47,7 @@ struct HubbardData {
     int nwork = 0;
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
     bool realhop = false;          // every hopping (off-diagonal h0) is real
+    bool slices = false;           // slice stage kernel (SOA, TPP, TPH on row-kernel clusters)
     WorkItem* dwork = nullptr;     // TPH: work list of the diagonal gather
     int ndwork = 0;
     cd* diag = nullptr;            // TPH: per cluster R [ns]^3 and S [ns]^3

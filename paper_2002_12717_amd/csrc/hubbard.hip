@@ -523,6 +523,170 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     }
 }
 
+// Slice version of the stage (SOA, TPP, TPH; every cluster with ns <= 64 and at
+// most Z_MAX_ROW neighbours per site).  A work-group of SLICE_THREADS threads
+// stages up to floor(SLICE_ELEMS / ns^2) consecutive (i, j) slices
+// A[i][j][:][:] of the stage input in LDS with coalesced loads and then gives
+// one element to each thread (m = tid, tid + SLICE_THREADS, ... over the staged
+// elements), so the lanes are filled whatever ns is.  The k- and
+// l-neighbours of the commutator lie in the same slice and are read from LDS;
+// the i- and j-neighbours, the ladder's diagonal slices and the Runge-Kutta
+// registers come from global memory.  A work item is a range [start, end) of
+// slices of one cluster, at most floor(SLICE_ELEMS / ns^2) long.
+constexpr int SLICE_THREADS = 512;
+constexpr int SLICE_ELEMS = 4096;
+// below this many G2 elements in all, the row kernel is the default: whole
+// slices would give too few work-groups
+constexpr long long SLICE_MIN_ELEMS = 1LL << 20;
+
+// n / d for n < 2^16 and 1 <= d <= 4096, with mg = slice_magic(d)
+__host__ __device__ constexpr unsigned slice_magic(unsigned d) { return d == 1 ? 0u : 0xffffffffu / d + 1u; }
+__device__ __forceinline__ int slice_div(int n, unsigned mg) {
+    return mg == 0u ? n : (int)__umulhi((unsigned)n, mg);
+}
+
+template <int MODE, int SE, bool MIXED, bool REALH>
+__global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s) {
+    static_assert(SE != SE_GW, "GW runs on the row kernel");
+    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH;
+    using TI = typename StageTypes<MODE, MIXED>::In;
+    using TO = typename StageTypes<MODE, MIXED>::Out;
+    constexpr int ZR = Z_MAX_ROW;
+    __shared__ cd P[SLICE_ELEMS];
+    __shared__ cd eu[NS_MAX_ROW], ed[NS_MAX_ROW];
+    // per site and neighbour slot (padded to ZR; a missing neighbour has offset
+    // 0 and hopping 0): element offsets of the neighbour along l (spin down),
+    // k (spin up, (p - k) ns), i (spin up, (p - i) ns^3), j (spin down, (p - j) ns^2)
+    __shared__ int ofl[NS_MAX_ROW * ZR], ofk[NS_MAX_ROW * ZR];
+    __shared__ int ofi[NS_MAX_ROW * ZR], ofj[NS_MAX_ROW * ZR];
+    __shared__ cd shp[2 * NS_MAX_ROW * ZR];   // hoppings [spin][site][slot]
+    const WorkItem w = s.work[blockIdx.x];
+    const ClusterDesc d = s.desc[w.cluster];
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
+    const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
+    const int tid = threadIdx.x;
+    if (w.start < 0) {   // G1 update of the cluster
+        const cd* g1 = s.in1 + d.g1off;
+        const cd* y = s.y1 + d.g1off;
+        cd* acc = s.acc1 + d.g1off;
+        cd* out = s.out1 + d.g1off;
+        for (int e = tid; e < 2 * ns2; e += SLICE_THREADS) {
+            int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
+            cd f = hub_g1_rhs(a, A, sig, i, j);
+            rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
+            if (MODE == RK_LAST) {
+                cd v = out[e];
+                bool bad = !(isfinite(v.x) && isfinite(v.y));
+                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
+                if (bad) atomicOr(s.flag, 1);
+            }
+        }
+        return;
+    }
+    for (int q = tid; q < ns; q += SLICE_THREADS) {
+        eu[q] = hf_diag(a, 0, q);
+        ed[q] = hf_diag(a, 1, q);
+    }
+    for (int q = tid; q < 2 * ns * ZR; q += SLICE_THREADS) {
+        const int row = q / ZR, qq = q - row * ZR, spin = row / ns, site = row - spin * ns;
+        const int p = qq < z ? a.nbr[row * z + qq] : -1;
+        const int dp = p >= 0 ? p - site : 0;
+        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
+        if (spin == 0) {
+            ofk[site * ZR + qq] = dp * ns;
+            ofi[site * ZR + qq] = dp * ns3;
+        } else {
+            ofl[site * ZR + qq] = dp;
+            ofj[site * ZR + qq] = dp * ns2;
+        }
+    }
+    // stage the slices [start, end)
+    const int E = (w.end - w.start) * ns2;
+    const unsigned e0 = (unsigned)w.start * (unsigned)ns2;
+    for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(A, e0 + (unsigned)m);
+    __syncthreads();
+    const unsigned mg2 = slice_magic((unsigned)ns2), mg1 = slice_magic((unsigned)ns);
+    const cd* hu = shp;
+    const cd* hd = shp + ns * ZR;
+    const cd* __restrict__ X = a.X;
+    const cd* __restrict__ Y = a.Y;
+    const cd* y = s.y2 + d.g2off;
+    cd* acc = s.acc2 + d.g2off;
+    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
+    const cd* __restrict__ DR = TPH ? s.diag + 2 * d.doff : nullptr;   // R[a][b][c]
+    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;               // S[b][c][a]
+    for (int m = tid; m < E; m += SLICE_THREADS) {
+        const int sl = slice_div(m, mg2), r = m - sl * ns2;
+        const int k = slice_div(r, mg1), l = r - k * ns;
+        const int slice = w.start + sl;
+        const int i = slice_div(slice, mg1), j = slice - i * ns;
+        const unsigned e = e0 + (unsigned)m;
+        const cd av = P[m];
+        // sum_p A_ijpl h_pk + sum_p A_ijkp h_pl, with h_pk = conj(h_kp)
+        cd rr = cmk(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            const cd vl = P[m + ofl[l * ZR + q]], vk = P[m + ofk[k * ZR + q]];
+            const cd hl = hd[l * ZR + q], hk = hu[k * ZR + q];
+            if (REALH) {
+                rr.x = fma(vl.x, hl.x, fma(vk.x, hk.x, rr.x));
+                rr.y = fma(vl.y, hl.x, fma(vk.y, hk.x, rr.y));
+            } else {
+                rr = cfma_conjb(rr, vl, hl);
+                rr = cfma_conjb(rr, vk, hk);
+            }
+        }
+        const cd ei = eu[i], ej = ed[j], ek = eu[k], el = ed[l];
+        cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
+        c = csub(c, rr);
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            const cd vi = ldo(A, e + ofi[i * ZR + q]), vj = ldo(A, e + ofj[j * ZR + q]);
+            const cd hi = hu[i * ZR + q], hj = hd[j * ZR + q];
+            if (REALH) {
+                c.x = fma(hi.x, vi.x, fma(hj.x, vj.x, c.x));
+                c.y = fma(hi.x, vi.y, fma(hj.x, vj.y, c.y));
+            } else {
+                c = cfma(c, hi, vi);
+                c = cfma(c, hj, vj);
+            }
+        }
+        // source (eq:soa-cubic-scheme), X_lk = -conj(X_kl)
+        const cd xij = ldo(X, i * ns + j), yji = ldo(Y, j * ns + i);
+        const cd xil = ldo(X, i * ns + l), yjl = ldo(Y, j * ns + l), yil = ldo(Y, i * ns + l);
+        const cd xkl = ldo(X, k * ns + l), ykl = ldo(Y, k * ns + l);
+        const cd xik = ldo(X, i * ns + k), xjk = ldo(X, j * ns + k), yjk = ldo(Y, j * ns + k);
+        const cd xlk = cmk(-xkl.x, xkl.y);
+        const double dd = (double)(i == j) - (double)(k == l);
+        const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+        const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+        c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+        if (TPP) {   // ladder (Sec. VII.C) and its partner
+            const int kl = k * ns + l;
+            const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
+            cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
+            if (i == j) l1 = cadd(l1, dii);
+            const cd dkk = ldo(A, (k * ns + k) * ns2 + slice), dll = ldo(A, (l * ns + l) * ns2 + slice);
+            const cd ylk = cmk(-ykl.x, ykl.y);
+            cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
+            if (k == l) l2 = cadd(l2, dkk);
+            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+        }
+        if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner
+            //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
+            //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
+            const cd rjki = ldo(DR, (j * ns + k) * ns + i), rjkl = ldo(DR, (j * ns + k) * ns + l);
+            const cd sikl = ldo(DS, (i * ns + k) * ns + l), sijl = ldo(DS, (i * ns + j) * ns + l);
+            const cd ykj = ldo(Y, k * ns + j), xkj = ldo(X, k * ns + j);
+            const cd l1 = cmul_i(csub(cmul(yil, rjki), cmul(xil, rjkl)));
+            const cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
+            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+        }
+        rk_update<MODE, TO, true>((int)e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
+    }
+}
+
 StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const Regs& acc,
                      const Regs& out, double cb, double cc) {
     HubbardData& H = c->hub;
@@ -555,6 +719,17 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
         using TI = typename StageTypes<MODE, MIXED>::In;
         hipLaunchKernelGGL((hub_diag_kernel<TI, SE>), dim3(c->hub.ndwork), dim3(256), 0, c->stream,
                            c->hub.desc, c->hub.dwork, s.in2, c->hub.diag);
+    }
+    if constexpr (SE != SE_GW) {
+        if (c->hub.slices) {
+            if (c->hub.realhop)
+                hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork),
+                                   dim3(SLICE_THREADS), 0, c->stream, s);
+            else
+                hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork),
+                                   dim3(SLICE_THREADS), 0, c->stream, s);
+            return;
+        }
     }
     if (c->hub.rows || SE == SE_GW) {   // GW runs on the row kernel only (checked at setup)
         if (c->hub.realhop)
@@ -791,6 +966,15 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                 if (z > Z_MAX_ROW) rowk = false;
             }
     }
+    // the slice kernel takes SOA, TPP and TPH wherever the row kernel could run,
+    // by default for systems of at least SLICE_MIN_ELEMS G2 elements
+    const int fl = c->d.flags;
+    if ((fl & G1G2_HUB_ROW_KERNEL) && (fl & G1G2_HUB_SLICE_KERNEL))
+        return set_error(c, G1G2_EINVAL, "G1G2_HUB_ROW_KERNEL and G1G2_HUB_SLICE_KERNEL exclude each other");
+    long long total = 0;
+    for (int cl = 0; cl < ncl; ++cl) total += (long long)nsv[cl] * nsv[cl] * nsv[cl] * nsv[cl];
+    const bool slicek = rowk && se != SE_GW && !(fl & G1G2_HUB_ROW_KERNEL) &&
+                        ((fl & G1G2_HUB_SLICE_KERNEL) || total >= SLICE_MIN_ELEMS);
     long long g2off = 0;
     long long g1off = 0, xoff = 0, doff = 0;
     for (int cl = 0; cl < ncl; ++cl) {
@@ -834,7 +1018,17 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             }
         d0_all.insert(d0_all.end(), d0.begin(), d0.end());
         const long long n4 = (long long)ns * ns * ns * ns;
-        if (rowk) {
+        if (slicek) {
+            // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices each
+            const int per = SLICE_ELEMS / (ns * ns);
+            const int nsl = ns * ns;
+            chunks[cl] = per * ns * ns;
+            for (int s0 = 0; s0 < nsl; s0 += per) {
+                const int s1 = std::min(nsl, s0 + per);
+                work.push_back({cl, s0, s1});
+                wcost.push_back((long long)(s1 - s0) * ns * ns);
+            }
+        } else if (rowk) {
             // wave units of rpw rows (rpw ns elements) over (channel, i, j, k-block);
             // chunk = elements per work-group
             const int rpw = std::min(64 / ns, ns);
@@ -877,6 +1071,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     hub_free(c);
     H.ncl = ncl;
     H.rows = rowk;
+    H.slices = slicek;
     H.realhop = realhop;
     H.ndwork = (int)dwork.size();
     H.hdesc = desc;

@@ -39,12 +39,20 @@ def _hubbard_h0(kind, r):
         h = chain_hopping(5)
     elif kind == "ring7":
         h = chain_hopping(7, periodic=True)
-    elif kind == "sq3x3":
+    elif kind in ("sq3x3", "peierls3x3"):
         h = square_hopping(3, 3, periodic=True)
     else:
         h = square_hopping(4, 2, periodic=False)
     ns = h.shape[0]
-    return np.stack([h + np.diag(r.uniform(-0.5, 0.5, ns)), h + np.diag(r.uniform(-0.5, 0.5, ns))])
+    hs = []
+    for _ in range(2):
+        hh = h.astype(complex)
+        if kind == "peierls3x3":
+            # a phase on every bond (h_qp = conj(h_pq)): complex hoppings, h0 Hermitian
+            th = np.triu(r.uniform(-np.pi, np.pi, (ns, ns)), 1)
+            hh = hh * np.exp(1j * (th - th.T))
+        hs.append(hh + np.diag(r.uniform(-0.5, 0.5, ns)))
+    return np.stack(hs)
 
 
 def _se(se):
@@ -52,11 +60,12 @@ def _se(se):
     return {"soa": B.SOA, "tpp": B.TPP, "tph": B.TPH, "gw": B.GW}[se]
 
 
-@pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2"])
+@pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2", "peierls3x3"])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
-def test_hubbard_rhs_parity(lib, kind, se):
+@pytest.mark.parametrize("kern", ["row", "slice"])
+def test_hubbard_rhs_parity(lib, kind, se, kern):
     from paper_2002_12717_amd import binding as B
-    say(f"[hubbard rhs] lattice={kind} se={se}")
+    say(f"[hubbard rhs] lattice={kind} se={se} kernel={kern}")
     r = rng(101, len(kind), len(se))
     h0 = _hubbard_h0(kind, r)
     ns = h0.shape[1]
@@ -64,7 +73,8 @@ def test_hubbard_rhs_parity(lib, kind, se):
     A = random_g2(ns, r, scale=0.1, exchange=False)
     U = 1.3
     g1 = np.stack([X, Y])
-    p = B.Propagator(B.HUBBARD, _se(se), ns, h0, g1, U=U)
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    p = B.Propagator(B.HUBBARD, _se(se), ns, h0, g1, U=U, flags=flags)
     G1d, G2d = cuda(g1), cuda(A)
     dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
     p.rhs(0.0, G1d, G2d, dG1d, dG2d)
@@ -76,7 +86,7 @@ def test_hubbard_rhs_parity(lib, kind, se):
     p.close()
 
 
-@pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2"])
+@pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2", "peierls3x3"])
 def test_hubbard_gw_rhs_parity(lib, kind):
     """Hubbard GW with the three channels of reading 8 (up-down-up-down,
     up-up-up-up, down-down-down-down): one right-hand side against the oracle."""
@@ -286,6 +296,9 @@ def test_abi_errors(lib):
     with pytest.raises(B.G1G2Error) as e:
         B.Batch(B.GW, [4, 4], [1.0, 1.0], [s.h0, s.h0], [s.g1, s.g1])
     assert e.value.status == B.EUNSUPPORTED
+    with pytest.raises(B.G1G2Error) as e:   # the two stage-kernel flags exclude each other
+        B.Propagator(B.HUBBARD, B.SOA, 4, s.h0, s.g1, U=1.0, flags=B.HUB_ROW_KERNEL | B.HUB_SLICE_KERNEL)
+    assert e.value.status == B.EINVAL
     bad = s.h0.copy()
     bad[0, 0, 1] = 5.0   # not Hermitian
     with pytest.raises(B.G1G2Error) as e:
@@ -337,12 +350,16 @@ def test_hubbard_mixed_chain_full_trajectory(lib):
 @pytest.mark.parametrize("se,kernel,prec", [("soa", "row", "fp64"), ("tpp", "row", "fp64"),
                                             ("tpp", "element", "fp64"), ("tpp", "row", "mixed"),
                                             ("tpp", "element", "mixed"), ("tph", "row", "fp64"),
-                                            ("tph", "element", "fp64"), ("tph", "row", "mixed")])
+                                            ("tph", "element", "fp64"), ("tph", "row", "mixed"),
+                                            ("soa", "slice", "fp64"), ("tpp", "slice", "fp64"),
+                                            ("tpp", "slice", "mixed"), ("tph", "slice", "fp64"),
+                                            ("tph", "slice", "mixed")])
 def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     """Clusters of uneven size and U in one context: every cluster follows the
-    oracle's single-cluster propagation (and the graph-replayed steps).  Positive
-    chunks select the row stage kernel, negative ones the per-element kernel.
-    Mixed precision is held to 1e-5 relative, binary64 to 1e-10."""
+    oracle's single-cluster propagation (and the graph-replayed steps).  The
+    flags force the row or the slice stage kernel; negative chunks select the
+    per-element kernel.  Mixed precision is held to 1e-5 relative, binary64 to
+    1e-10."""
     from paper_2002_12717_amd import binding as B
     from workloads import batched_clusters
     cl = batched_clusters(n=7)
@@ -351,9 +368,10 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     chunk = [256 if c.ns < 16 else 2048 for c in cl]
     if kernel == "element":
         chunk = [-ch for ch in chunk]
+    flags = {"row": B.HUB_ROW_KERNEL, "slice": B.HUB_SLICE_KERNEL, "element": 0}[kernel]
     b = B.Batch(_se(se), [c.ns for c in cl], [c.U for c in cl],
                 [c.h0 for c in cl], [c.g1 for c in cl], chunk=chunk, stream=stream.cuda_stream,
-                precision=B.FP64 if prec == "fp64" else B.MIXED)
+                precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
     dt, nst = cl[0].dt, 24
     b.step(dt, nst)
     obs = b.observables()
@@ -372,7 +390,7 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     b.close()
 
 
-@pytest.mark.parametrize("basis", ["hubbard", "hubbard_tph", "general"])
+@pytest.mark.parametrize("basis", ["hubbard", "hubbard_tph", "hubbard_slice", "general"])
 def test_graph_replays_match_eager(lib, basis):
     """Steps replayed from captured HIP graphs (stream given) equal eager
     launches bit for bit, across several replays with synchronizations and
@@ -383,7 +401,8 @@ def test_graph_replays_match_eager(lib, basis):
     if basis.startswith("hubbard"):
         s = hubbard_chain_system(ns=6)
         se = B.TPH if basis == "hubbard_tph" else B.TPP
-        mk = lambda st: B.Propagator(B.HUBBARD, se, s.ns, s.h0, s.g1, U=s.U, stream=st)  # noqa: E731
+        fl = B.HUB_SLICE_KERNEL if basis == "hubbard_slice" else 0
+        mk = lambda st: B.Propagator(B.HUBBARD, se, s.ns, s.h0, s.g1, U=s.U, stream=st, flags=fl)  # noqa: E731
     else:
         s = general_system(nb=12, rank=10, nocc=4)
         mk = lambda st: B.Propagator(B.GENERAL, B.SOA, s.nb, s.h0, s.g1, w=s.w, stream=st)  # noqa: E731
