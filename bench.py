@@ -38,7 +38,7 @@ PEAK_HBM = 8000.0          # GB/s
 TRAFFIC = {
     "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
     "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
-    "hub_stage/2d": {"bytes": 0.0, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "?"},
+    "hub_stage/2d": {"bytes": 2.36e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "539ec63e7c02"},
 }
 
 
@@ -312,6 +312,7 @@ def run_batch(args, torch, B):
     ns = [c.ns for c in clusters]
     n4 = float(sum(n ** 4 for n in ns))
     chunks = autotune.chunks_for(ns)
+    flags = autotune.flags_for()
     stream = torch.cuda.Stream()
     dt = clusters[0].dt
     se = args.selfenergy or "tpp"
@@ -319,7 +320,7 @@ def run_batch(args, torch, B):
     for prec in ("fp64", "mixed"):
         b = B.Batch(SE_CODES[se](B), ns, [c.U for c in clusters], [c.h0 for c in clusters],
                     [c.g1 for c in clusters], chunk=chunks, stream=stream.cuda_stream,
-                    precision=B.FP64 if prec == "fp64" else B.MIXED)
+                    precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
         ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
         g1 = [b.get_cluster(q, with_g2=False)[0] for q in range(len(ns))]
         obs = b.observables()
@@ -343,7 +344,8 @@ def run_batch(args, torch, B):
     config = {"workload": f"ragged batch of {len(ns)} periodic 2D Hubbard clusters (Lx,Ly in 3..6), "
                           f"{se.upper()}, dt={dt}, RK4, one launch per stage, graph-captured steps",
               "clusters": len(ns), "g2_elements": int(n4), "ns_min": min(ns), "ns_max": max(ns),
-              "selfenergy": se.upper(), "chunk_per_class": autotune.load_table().get("chunk_per_class"),
+              "selfenergy": se.upper(), "stage_kernel": autotune.load_table().get("kernel", "library default"),
+              "chunk_per_class": autotune.load_table().get("chunk_per_class"),
               "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     out.update({

@@ -1,10 +1,12 @@
 """Autotuner of the ragged Hubbard batch.  It first chooses the stage kernel
-(row kernel: positive chunks; per-element kernel: negative chunks), then, per
-cluster size class, the number of G2 elements handled by one work-group of
-the flat work list of g1g2_batch_init (the row kernel rounds it to whole wave
-units of rows).  Coordinate descent over the classes; each candidate is timed
-with HIP events over whole RK4 steps on the real batch.  The table is written
-as JSON and read back by ``chunks_for``.
+(the slice kernel, the row kernel, or the per-element kernel, which negative
+chunks select), then, for the row and per-element kernels, per cluster size
+class, the number of G2 elements handled by one work-group of the flat work
+list of g1g2_batch_init (the row kernel rounds it to whole wave units of
+rows; the slice kernel always stages whole slices and has no such knob).
+Coordinate descent over the classes; each candidate is timed with HIP events
+over whole RK4 steps on the real batch.  The table is written as JSON and read
+back by ``chunks_for`` and ``flags_for``.
 """
 from __future__ import annotations
 
@@ -37,16 +39,26 @@ def load_table(path: str = TABLE) -> dict:
     return {}
 
 
+KERNELS = ("slice", "row", "element")
+
+
 def chunks_for(ns_list, table=None):
     table = load_table() if table is None else table
     per = table.get("chunk_per_class", [DEFAULT] * len(CLASSES))
     return [int(per[class_of(n)]) for n in ns_list]
 
 
-def _time(B, torch, clusters, selfenergy, chunks, steps, stream):
+def flags_for(table=None) -> int:
+    """g1g2_desc flags that select the tuned stage kernel (0: the library's choice)."""
+    from . import binding as B
+    table = load_table() if table is None else table
+    return {"slice": B.HUB_SLICE_KERNEL, "row": B.HUB_ROW_KERNEL}.get(table.get("kernel"), 0)
+
+
+def _time(B, torch, clusters, selfenergy, chunks, steps, stream, flags=0):
     b = B.Batch(selfenergy, [c.ns for c in clusters], [c.U for c in clusters],
                 [c.h0 for c in clusters], [c.g1 for c in clusters], chunk=chunks,
-                stream=stream.cuda_stream)
+                stream=stream.cuda_stream, flags=flags)
     dt = clusters[0].dt
     b.step(dt, 2)
     torch.cuda.synchronize()
@@ -70,34 +82,36 @@ def tune(n_clusters: int = 512, steps: int = 8, selfenergy_name: str = "tpp", ou
     ns = [c.ns for c in clusters]
     log = []
     # the kernel variant is global: pick it first with uniform chunks
-    best, base = None, float("inf")
-    for start in (DEFAULT, -256):
-        trial = [start] * len(CLASSES)
-        ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream)
-        log.append({"chunk_per_class": trial, "ms_per_step": ms})
-        print(f"start {trial} {ms:.3f} ms/step", flush=True)
+    kflags = {"slice": B.HUB_SLICE_KERNEL, "row": B.HUB_ROW_KERNEL, "element": 0}
+    best, base, kernel = None, float("inf"), None
+    for kern in KERNELS:
+        trial = [-256 if kern == "element" else DEFAULT] * len(CLASSES)
+        ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream, kflags[kern])
+        log.append({"kernel": kern, "chunk_per_class": trial, "ms_per_step": ms})
+        print(f"kernel {kern} {trial} {ms:.3f} ms/step", flush=True)
         if ms < base:
-            base, best = ms, trial
-    cands = CANDIDATES_ROW if best[0] > 0 else CANDIDATES_FLAT
+            base, best, kernel = ms, trial, kern
+    cands = {"row": CANDIDATES_ROW, "element": CANDIDATES_FLAT}.get(kernel, [])
     for q in range(len(CLASSES)):
         for cand in cands:
             if cand == best[q]:
                 continue
             trial = list(best)
             trial[q] = cand
-            ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream)
-            log.append({"chunk_per_class": trial, "ms_per_step": ms})
+            ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream,
+                       kflags[kernel])
+            log.append({"kernel": kernel, "chunk_per_class": trial, "ms_per_step": ms})
             print(f"class {q} chunk {cand}: {ms:.3f} ms/step", flush=True)
             if ms < base:
                 base, best = ms, trial
-    table = {"chunk_per_class": best, "classes_ns": CLASSES, "ms_per_step": base,
+    table = {"kernel": kernel, "chunk_per_class": best, "classes_ns": CLASSES, "ms_per_step": base,
              "workload": f"{n_clusters} periodic 2D Hubbard clusters, {selfenergy_name.upper()}",
              "device": torch.cuda.get_device_name(0), "date": time.strftime("%Y-%m-%d"),
              "trials": log}
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as f:
         json.dump(table, f, indent=1)
-    print("best", best, f"{base:.3f} ms/step ->", out, flush=True)
+    print("best", kernel, best, f"{base:.3f} ms/step ->", out, flush=True)
     return table
 
 

@@ -72,3 +72,16 @@ def test_batch_init_rejects_empty_batch(so_path):
     d = binding.Desc(1, binding.TPP, 0, 0, 4, 0.0)
     assert lib.g1g2_batch_init(ctypes.byref(ctx), ctypes.byref(d), 0, None, None, None, None, None,
                                None) == binding.EINVAL
+
+
+def test_autotune_table_lookup():
+    """The autotuner's table maps cluster sizes to chunks by class and names
+    the stage kernel by its g1g2_desc flag."""
+    from paper_2002_12717_amd import autotune
+    from paper_2002_12717_amd import binding as B
+    table = {"kernel": "row", "chunk_per_class": [256, 512, 4096]}
+    assert autotune.chunks_for([9, 16, 17, 25, 26, 36], table) == [256, 256, 512, 512, 4096, 4096]
+    assert autotune.flags_for(table) == B.HUB_ROW_KERNEL
+    assert autotune.flags_for({"kernel": "slice"}) == B.HUB_SLICE_KERNEL
+    assert autotune.flags_for({"kernel": "element"}) == 0
+    assert autotune.flags_for({}) == 0

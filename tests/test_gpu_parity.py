@@ -537,7 +537,7 @@ def test_full_size_batch_sampled_clusters(lib):
     say(f"[full size] batch of {len(cl)} clusters, TPP, 8 graph-replayed steps")
     stream = torch.cuda.Stream()
     b = B.Batch(B.TPP, ns, [c.U for c in cl], [c.h0 for c in cl], [c.g1 for c in cl],
-                chunk=autotune.chunks_for(ns), stream=stream.cuda_stream)
+                chunk=autotune.chunks_for(ns), stream=stream.cuda_stream, flags=autotune.flags_for())
     b.step(cl[0].dt, 8)
     order = sorted(range(len(cl)), key=lambda q: -ns[q])
     sample = order[:3] + [order[len(order) // 2], order[-1], 7, 123, 400]
