@@ -239,20 +239,27 @@ def run_general(args, torch, B, se="soa"):
 
 
 def run_hubbard(args, torch, B, kind):
+    import numpy as np
     from workloads import adjoint_system, hubbard_chain_system
     system = hubbard_chain_system() if kind == "hubbard_chain" else adjoint_system()
     ns = system.ns
     stream = torch.cuda.Stream()
     se = args.selfenergy or "soa"
-    p = B.Propagator(B.HUBBARD, SE_CODES[se](B), ns, system.h0, system.g1, U=system.U,
-                     stream=stream.cuda_stream)
-    if system.drive is not None:
-        d = system.drive
-        p.set_drive(d.x, d.c, d.t_center, d.tau)
-    ms, wall = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
-    prof = p.profile(system.dt, args.profile_steps)
-    obs = p.observables()
-    p.close()
+
+    def run(prec):
+        p = B.Propagator(B.HUBBARD, SE_CODES[se](B), ns, system.h0, system.g1, U=system.U,
+                         stream=stream.cuda_stream, precision=prec)
+        if system.drive is not None:
+            d = system.drive
+            p.set_drive(d.x, d.c, d.t_center, d.tau)
+        ms, _ = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
+        prof = p.profile(system.dt, args.profile_steps)
+        obs = p.observables()
+        g1, _, _ = p.get_state()
+        p.close()
+        return ms, prof, obs, g1
+
+    ms, prof, obs, g1_64 = run(B.FP64)
     ms_step = ms / args.steps
     n4 = float(ns) ** 4
     tot_ms, cnt = prof["hub_stage"]
@@ -275,6 +282,18 @@ def run_hubbard(args, torch, B, kind):
         "kernels": kernel_table(prof),
         "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
     })
+    # mixed precision: binary32 G2 stage copies, 52 B per element and launch
+    # (binary64 y and acc, binary32 stage input and output)
+    mx_ms, mx_prof, mx_obs, g1_mx = run(B.MIXED)
+    mx_step = mx_ms / args.steps
+    mx_tot, mx_cnt = mx_prof["hub_stage"]
+    mx_ach = 52.0 * n4 * (3 if se == "gw" else 1) * mx_cnt / (mx_tot * 1e-3) / 1e9
+    out["mixed"] = {"dtype": "f64 state, f32 G2 stage copies", "value": round(1e3 / mx_step, 3),
+                    "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
+                    "err_G1_vs_fp64": float(np.abs(g1_mx - g1_64).max() / np.abs(g1_64).max()),
+                    "err_E_vs_fp64": abs(mx_obs["E_tot"] - obs["E_tot"]) / max(abs(obs["E_tot"]), 1.0),
+                    "roofline": {"kernel": "hub_stage", "achieved": round(mx_ach, 2), "peak": PEAK_HBM,
+                                 "unit": "GB/s", "frac": round(mx_ach / PEAK_HBM, 4), "traffic": None}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_hubbard(system, selfenergy=se)
     return out

@@ -346,6 +346,28 @@ def test_hubbard_mixed_chain_full_trajectory(lib):
     p.close()
 
 
+@pytest.mark.parametrize("se,kern", [("soa", "slice"), ("tpp", "slice"), ("tph", "slice"), ("tph", "row"),
+                                     ("gw", "row")])
+def test_hubbard_mixed_selfenergies(lib, se, kern):
+    """Mixed precision with every Hubbard selfenergy and both row-type stage
+    kernels: 200 steps of a 6-site chain against the binary64 oracle, to the
+    1e-5 bar (and visibly different from binary64, so the binary32 stage
+    copies are in use)."""
+    from paper_2002_12717_amd import binding as B
+    say(f"[hubbard mixed] chain6 {se} {kern} kernel, 200 steps")
+    s = hubbard_chain_system(ns=6)
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    p = B.Propagator(B.HUBBARD, _se(se), s.ns, s.h0, s.g1, U=s.U, precision=B.MIXED, flags=flags)
+    p.step(s.dt, 200)
+    y, rec = OI.propagate_hubbard(s, nsteps=200, selfenergy=se, observables_every=200)
+    g1, _, _ = p.get_state()
+    err = rel(g1, np.stack([y[0].numpy(), y[1].numpy()]))
+    err_e = abs(p.observables()["E_tot"] - rec[-1]["E_tot"]) / max(abs(rec[0]["E_tot"]), 1.0)
+    say(f"   err G1 {err:.2e}  err E {err_e:.2e}")
+    assert 1e-12 < err < 1e-5 and err_e < 1e-5
+    p.close()
+
+
 # --------------------------------------------------------------------------- batches and graphs
 @pytest.mark.parametrize("se,kernel,prec", [("soa", "row", "fp64"), ("tpp", "row", "fp64"),
                                             ("tpp", "element", "fp64"), ("tpp", "row", "mixed"),
