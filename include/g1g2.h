@@ -84,14 +84,13 @@ typedef enum { G1G2_FP64 = 0, G1G2_MIXED = 1 } g1g2_precision;
 enum {
     G1G2_PTR_DEVICE = 1,    /* host-side pointer arguments are device pointers      */
     G1G2_GW_EXCHANGE = 2,   /* GW: use Psi^- instead of Psi (end of Sec. IV.B)      */
-    /* Hubbard stage kernel (both set: EINVAL).  By default SOA, TPP and TPH use
-     * the slice kernel (a work-group stages whole (i,j) slices of G2 in LDS)
-     * when the clusters hold at least 2^20 G2 elements in all, else the row
-     * kernel (one wave per G2 row); GW always uses the row kernel.  Both need
-     * ns <= 64 and at most 4 neighbours per site, else the per-element kernel
-     * runs. */
+    /* Hubbard stage kernel (both set: EINVAL).  By default the slice kernel (a
+     * work-group stages whole (i,j) slices of G2 in LDS) runs when the clusters
+     * hold at least 2^20 G2 elements in all (counting GW's three channels),
+     * else the row kernel (one wave per G2 row).  Both need ns <= 64 and at
+     * most 4 neighbours per site, else the per-element kernel runs. */
     G1G2_HUB_ROW_KERNEL = 4,    /* Hubbard: row kernel whatever the size          */
-    G1G2_HUB_SLICE_KERNEL = 8   /* Hubbard SOA/TPP/TPH: slice kernel whatever the size */
+    G1G2_HUB_SLICE_KERNEL = 8   /* Hubbard: slice kernel whatever the size        */
 };
 
 typedef struct {

@@ -523,16 +523,17 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     }
 }
 
-// Slice version of the stage (SOA, TPP, TPH; every cluster with ns <= 64 and at
-// most Z_MAX_ROW neighbours per site).  A work-group of SLICE_THREADS threads
+// Slice version of the stage (every selfenergy; every cluster with ns <= 64 and
+// at most Z_MAX_ROW neighbours per site).  A work-group of SLICE_THREADS threads
 // stages up to floor(SLICE_ELEMS / ns^2) consecutive (i, j) slices
-// A[i][j][:][:] of the stage input in LDS with coalesced loads and then gives
+// A[i][j][:][:] of one channel of the stage input in LDS with coalesced loads and then gives
 // one element to each thread (m = tid, tid + SLICE_THREADS, ... over the staged
 // elements), so the lanes are filled whatever ns is.  The k- and
 // l-neighbours of the commutator lie in the same slice and are read from LDS;
 // the i- and j-neighbours, the ladder's diagonal slices and the Runge-Kutta
 // registers come from global memory.  A work item is a range [start, end) of
-// slices of one cluster, at most floor(SLICE_ELEMS / ns^2) long.
+// slices (channel ns^2 + i ns + j) of one channel of one cluster, at most
+// floor(SLICE_ELEMS / ns^2) long.
 constexpr int SLICE_THREADS = 512;
 constexpr int SLICE_ELEMS = 4096;
 // below this many G2 elements in all, the row kernel is the default: whole
@@ -547,16 +548,16 @@ __device__ __forceinline__ int slice_div(int n, unsigned mg) {
 
 template <int MODE, int SE, bool MIXED, bool REALH>
 __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s) {
-    static_assert(SE != SE_GW, "GW runs on the row kernel");
-    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH;
+    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH, GW = SE == SE_GW;
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
     __shared__ cd P[SLICE_ELEMS];
     __shared__ cd eu[NS_MAX_ROW], ed[NS_MAX_ROW];
     // per site and neighbour slot (padded to ZR; a missing neighbour has offset
-    // 0 and hopping 0): element offsets of the neighbour along l (spin down),
-    // k (spin up, (p - k) ns), i (spin up, (p - i) ns^3), j (spin down, (p - j) ns^2)
+    // 0 and hopping 0): element offsets of the neighbour along l (p - l),
+    // k ((p - k) ns), i ((p - i) ns^3) and j ((p - j) ns^2), each for the spin
+    // that index carries in the work item's channel
     __shared__ int ofl[NS_MAX_ROW * ZR], ofk[NS_MAX_ROW * ZR];
     __shared__ int ofi[NS_MAX_ROW * ZR], ofj[NS_MAX_ROW * ZR];
     __shared__ cd shp[2 * NS_MAX_ROW * ZR];   // hoppings [spin][site][slot]
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
     const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     const int tid = threadIdx.x;
-    if (w.start < 0) {   // G1 update of the cluster
+    if (w.start < 0) {   // G1 update of the cluster (the collision integral reads channel A)
         const cd* g1 = s.in1 + d.g1off;
         const cd* y = s.y1 + d.g1off;
         cd* acc = s.acc1 + d.g1off;
@@ -588,38 +589,58 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
         eu[q] = hf_diag(a, 0, q);
         ed[q] = hf_diag(a, 1, q);
     }
+    // channel of the work item (items do not cross channels) and the spin of
+    // the indices (i, j, k, l): A = (up, dn, up, dn); GW's B and C are all up
+    // and all down
+    const int ch = GW ? w.start / ns2 : 0;
+    const int sI = ch == 2 ? 1 : 0, sJ = ch == 1 ? 0 : 1;
     for (int q = tid; q < 2 * ns * ZR; q += SLICE_THREADS) {
         const int row = q / ZR, qq = q - row * ZR, spin = row / ns, site = row - spin * ns;
         const int p = qq < z ? a.nbr[row * z + qq] : -1;
         const int dp = p >= 0 ? p - site : 0;
         shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
-        if (spin == 0) {
+        if (spin == sI) {
             ofk[site * ZR + qq] = dp * ns;
             ofi[site * ZR + qq] = dp * ns3;
-        } else {
+        }
+        if (spin == sJ) {
             ofl[site * ZR + qq] = dp;
             ofj[site * ZR + qq] = dp * ns2;
         }
     }
-    // stage the slices [start, end)
+    // stage the slices [start, end) of the channel
+    const long long n4 = (long long)ns2 * ns2;
+    const TI* __restrict__ Ach = A + ch * n4;
     const int E = (w.end - w.start) * ns2;
-    const unsigned e0 = (unsigned)w.start * (unsigned)ns2;
-    for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(A, e0 + (unsigned)m);
+    const int slice0 = w.start - ch * ns2;   // first (i, j) of the item
+    const unsigned e0 = (unsigned)slice0 * (unsigned)ns2;
+    for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(Ach, e0 + (unsigned)m);
     __syncthreads();
     const unsigned mg2 = slice_magic((unsigned)ns2), mg1 = slice_magic((unsigned)ns);
-    const cd* hu = shp;
-    const cd* hd = shp + ns * ZR;
+    const cd* hI = shp + sI * ns * ZR;   // hoppings of the spin of i and k
+    const cd* hJ = shp + sJ * ns * ZR;   // of j and l
+    const cd* eI = sI ? ed : eu;
+    const cd* eJ = sJ ? ed : eu;
     const cd* __restrict__ X = a.X;
     const cd* __restrict__ Y = a.Y;
-    const cd* y = s.y2 + d.g2off;
-    cd* acc = s.acc2 + d.g2off;
-    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off;
+    const cd* y = s.y2 + d.g2off + ch * n4;
+    cd* acc = s.acc2 + d.g2off + ch * n4;
+    TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off + ch * n4;
     const cd* __restrict__ DR = TPH ? s.diag + 2 * d.doff : nullptr;   // R[a][b][c]
     const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;               // S[b][c][a]
+    // GW: diagonal tensors of the channel's two polarization terms
+    //   Pi_1 = -i U S1_jl (D1[i][k][j] - D1[i][k][l]),
+    //   Pi_2 = -i U S2_ki (D2[k][j][l] - D2[i][j][l]), term Pi_1 - conj(Pi_2)
+    const cd* __restrict__ DG = GW ? s.diag + (long long)n_diag(SE) * d.doff : nullptr;
+    const long long n3 = ns3;
+    const cd* __restrict__ D1 = GW ? DG + (ch == 0 ? 4 : (ch == 1 ? 0 : 2)) * n3 : nullptr;   // UB, UA, VA
+    const cd* __restrict__ D2 = GW ? DG + (ch == 0 ? 5 : (ch == 1 ? 1 : 3)) * n3 : nullptr;   // TC, TA, WA
+    const cd* __restrict__ S1 = ch == 1 ? X : Y;
+    const cd* __restrict__ S2 = ch == 2 ? Y : X;
     for (int m = tid; m < E; m += SLICE_THREADS) {
         const int sl = slice_div(m, mg2), r = m - sl * ns2;
         const int k = slice_div(r, mg1), l = r - k * ns;
-        const int slice = w.start + sl;
+        const int slice = slice0 + sl;
         const int i = slice_div(slice, mg1), j = slice - i * ns;
         const unsigned e = e0 + (unsigned)m;
         const cd av = P[m];
@@ -628,7 +649,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
             const cd vl = P[m + ofl[l * ZR + q]], vk = P[m + ofk[k * ZR + q]];
-            const cd hl = hd[l * ZR + q], hk = hu[k * ZR + q];
+            const cd hl = hJ[l * ZR + q], hk = hI[k * ZR + q];
             if (REALH) {
                 rr.x = fma(vl.x, hl.x, fma(vk.x, hk.x, rr.x));
                 rr.y = fma(vl.y, hl.x, fma(vk.y, hk.x, rr.y));
@@ -637,13 +658,13 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
                 rr = cfma_conjb(rr, vk, hk);
             }
         }
-        const cd ei = eu[i], ej = ed[j], ek = eu[k], el = ed[l];
+        const cd ei = eI[i], ej = eJ[j], ek = eI[k], el = eJ[l];
         cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
         c = csub(c, rr);
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
-            const cd vi = ldo(A, e + ofi[i * ZR + q]), vj = ldo(A, e + ofj[j * ZR + q]);
-            const cd hi = hu[i * ZR + q], hj = hd[j * ZR + q];
+            const cd vi = ldo(Ach, e + ofi[i * ZR + q]), vj = ldo(Ach, e + ofj[j * ZR + q]);
+            const cd hi = hI[i * ZR + q], hj = hJ[j * ZR + q];
             if (REALH) {
                 c.x = fma(hi.x, vi.x, fma(hj.x, vj.x, c.x));
                 c.y = fma(hi.x, vi.y, fma(hj.x, vj.y, c.y));
@@ -652,16 +673,24 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
                 c = cfma(c, hj, vj);
             }
         }
-        // source (eq:soa-cubic-scheme), X_lk = -conj(X_kl)
-        const cd xij = ldo(X, i * ns + j), yji = ldo(Y, j * ns + i);
-        const cd xil = ldo(X, i * ns + l), yjl = ldo(Y, j * ns + l), yil = ldo(Y, i * ns + l);
+        if (GW) {   // polarization terms of the channel (Sec. VII.B, reading of the partner spins)
+            const cd s1 = ldo(S1, j * ns + l), s2 = ldo(S2, k * ns + i);
+            const cd p1 = cmul_mi(cmul(s1, csub(ldo(D1, (i * ns + k) * ns + j), ldo(D1, (i * ns + k) * ns + l))));
+            const cd p2 = cmul_mi(cmul(s2, csub(ldo(D2, (k * ns + j) * ns + l), ldo(D2, (i * ns + j) * ns + l))));
+            c = cadd(c, cscale(csub(p1, cconj(p2)), a.U));
+        }
+        const cd xil = ldo(X, i * ns + l), yil = ldo(Y, i * ns + l);
         const cd xkl = ldo(X, k * ns + l), ykl = ldo(Y, k * ns + l);
-        const cd xik = ldo(X, i * ns + k), xjk = ldo(X, j * ns + k), yjk = ldo(Y, j * ns + k);
-        const cd xlk = cmk(-xkl.x, xkl.y);
-        const double dd = (double)(i == j) - (double)(k == l);
-        const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
-        const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
-        c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+        const cd xij = ldo(X, i * ns + j), yji = ldo(Y, j * ns + i);
+        if (!GW || ch == 0) {   // source (eq:soa-cubic-scheme), channel A only; X_lk = -conj(X_kl)
+            const cd yjl = ldo(Y, j * ns + l);
+            const cd xik = ldo(X, i * ns + k), xjk = ldo(X, j * ns + k), yjk = ldo(Y, j * ns + k);
+            const cd xlk = cmk(-xkl.x, xkl.y);
+            const double dd = (double)(i == j) - (double)(k == l);
+            const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+            const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+            c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+        }
         if (TPP) {   // ladder (Sec. VII.C) and its partner
             const int kl = k * ns + l;
             const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
@@ -720,16 +749,14 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
         hipLaunchKernelGGL((hub_diag_kernel<TI, SE>), dim3(c->hub.ndwork), dim3(256), 0, c->stream,
                            c->hub.desc, c->hub.dwork, s.in2, c->hub.diag);
     }
-    if constexpr (SE != SE_GW) {
-        if (c->hub.slices) {
-            if (c->hub.realhop)
-                hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork),
-                                   dim3(SLICE_THREADS), 0, c->stream, s);
-            else
-                hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork),
-                                   dim3(SLICE_THREADS), 0, c->stream, s);
-            return;
-        }
+    if (c->hub.slices) {
+        if (c->hub.realhop)
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork),
+                               dim3(SLICE_THREADS), 0, c->stream, s);
+        else
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork),
+                               dim3(SLICE_THREADS), 0, c->stream, s);
+        return;
     }
     if (c->hub.rows || SE == SE_GW) {   // GW runs on the row kernel only (checked at setup)
         if (c->hub.realhop)
@@ -966,15 +993,15 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                 if (z > Z_MAX_ROW) rowk = false;
             }
     }
-    // the slice kernel takes SOA, TPP and TPH wherever the row kernel could run,
+    // the slice kernel takes every selfenergy wherever the row kernel could run,
     // by default for systems of at least SLICE_MIN_ELEMS G2 elements
     const int fl = c->d.flags;
     if ((fl & G1G2_HUB_ROW_KERNEL) && (fl & G1G2_HUB_SLICE_KERNEL))
         return set_error(c, G1G2_EINVAL, "G1G2_HUB_ROW_KERNEL and G1G2_HUB_SLICE_KERNEL exclude each other");
     long long total = 0;
     for (int cl = 0; cl < ncl; ++cl) total += (long long)nsv[cl] * nsv[cl] * nsv[cl] * nsv[cl];
-    const bool slicek = rowk && se != SE_GW && !(fl & G1G2_HUB_ROW_KERNEL) &&
-                        ((fl & G1G2_HUB_SLICE_KERNEL) || total >= SLICE_MIN_ELEMS);
+    const bool slicek = rowk && !(fl & G1G2_HUB_ROW_KERNEL) &&
+                        ((fl & G1G2_HUB_SLICE_KERNEL) || total * nch >= SLICE_MIN_ELEMS);
     long long g2off = 0;
     long long g1off = 0, xoff = 0, doff = 0;
     for (int cl = 0; cl < ncl; ++cl) {
@@ -1019,15 +1046,17 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         d0_all.insert(d0_all.end(), d0.begin(), d0.end());
         const long long n4 = (long long)ns * ns * ns * ns;
         if (slicek) {
-            // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices each
+            // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices of
+            // one channel each; slice index = channel ns^2 + i ns + j
             const int per = SLICE_ELEMS / (ns * ns);
             const int nsl = ns * ns;
             chunks[cl] = per * ns * ns;
-            for (int s0 = 0; s0 < nsl; s0 += per) {
-                const int s1 = std::min(nsl, s0 + per);
-                work.push_back({cl, s0, s1});
-                wcost.push_back((long long)(s1 - s0) * ns * ns);
-            }
+            for (int chn = 0; chn < nch; ++chn)
+                for (int s0 = 0; s0 < nsl; s0 += per) {
+                    const int s1 = std::min(nsl, s0 + per);
+                    work.push_back({cl, chn * nsl + s0, chn * nsl + s1});
+                    wcost.push_back((long long)(s1 - s0) * ns * ns);
+                }
         } else if (rowk) {
             // wave units of rpw rows (rpw ns elements) over (channel, i, j, k-block);
             // chunk = elements per work-group

@@ -87,11 +87,12 @@ def test_hubbard_rhs_parity(lib, kind, se, kern):
 
 
 @pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2", "peierls3x3"])
-def test_hubbard_gw_rhs_parity(lib, kind):
+@pytest.mark.parametrize("kern", ["row", "slice"])
+def test_hubbard_gw_rhs_parity(lib, kind, kern):
     """Hubbard GW with the three channels of reading 8 (up-down-up-down,
     up-up-up-up, down-down-down-down): one right-hand side against the oracle."""
     from paper_2002_12717_amd import binding as B
-    say(f"[hubbard rhs] lattice={kind} se=gw")
+    say(f"[hubbard rhs] lattice={kind} se=gw kernel={kern}")
     r = rng(103, len(kind))
     h0 = _hubbard_h0(kind, r)
     ns = h0.shape[1]
@@ -99,7 +100,8 @@ def test_hubbard_gw_rhs_parity(lib, kind):
     A, Bc, C = (random_g2(ns, r, scale=0.1, exchange=False) for _ in range(3))
     U = 1.3
     g1 = np.stack([X, Y])
-    p = B.Propagator(B.HUBBARD, B.GW, ns, h0, g1, U=U)
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    p = B.Propagator(B.HUBBARD, B.GW, ns, h0, g1, U=U, flags=flags)
     G1d, G2d = cuda(g1), cuda(np.stack([A, Bc, C]))
     dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
     p.rhs(0.0, G1d, G2d, dG1d, dG2d)
@@ -111,10 +113,10 @@ def test_hubbard_gw_rhs_parity(lib, kind):
     p.close()
 
 
-def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol):
+def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol, flags=0):
     from paper_2002_12717_amd import binding as B
     p = B.Propagator(B.HUBBARD, _se(se), system.ns, system.h0, system.g1,
-                     U=system.U)
+                     U=system.U, flags=flags)
     if system.drive is not None:
         d = system.drive
         p.set_drive(d.x, d.c, d.t_center, d.tau)
@@ -157,17 +159,23 @@ def test_hubbard_gw_chain_trajectory(lib):
 
 
 @pytest.mark.parametrize("se", ["tpp", "tph", "gw"])
-def test_hubbard_ladder_cluster_trajectory(lib, se):
+@pytest.mark.parametrize("kern", ["row", "slice"])
+def test_hubbard_ladder_cluster_trajectory(lib, se, kern):
+    from paper_2002_12717_amd import binding as B
     from workloads import batched_clusters
     s = batched_clusters(n=3)[2]
-    say(f"[hubbard trajectory] cluster {s.meta} {se} 200 steps")
-    _compare_hubbard_trajectory(s, se, 4, 50, 1e-10)
+    say(f"[hubbard trajectory] cluster {s.meta} {se} {kern} kernel 200 steps")
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    _compare_hubbard_trajectory(s, se, 4, 50, 1e-10, flags)
 
 
-def test_hubbard_driven_trajectory(lib):
+@pytest.mark.parametrize("kern", ["row", "slice"])
+def test_hubbard_driven_trajectory(lib, kern):
+    from paper_2002_12717_amd import binding as B
     s = adjoint_system(lx=4, ly=3, U=2.0, nmodes=16, T=2.0, dt=0.01)
-    say("[hubbard trajectory] driven 4x3 SOA 200 steps")
-    _compare_hubbard_trajectory(s, "soa", 4, 50, 1e-10)
+    say(f"[hubbard trajectory] driven 4x3 SOA {kern} kernel 200 steps")
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    _compare_hubbard_trajectory(s, "soa", 4, 50, 1e-10, flags)
 
 
 # --------------------------------------------------------------------------- general basis
@@ -347,7 +355,7 @@ def test_hubbard_mixed_chain_full_trajectory(lib):
 
 
 @pytest.mark.parametrize("se,kern", [("soa", "slice"), ("tpp", "slice"), ("tph", "slice"), ("tph", "row"),
-                                     ("gw", "row")])
+                                     ("gw", "row"), ("gw", "slice")])
 def test_hubbard_mixed_selfenergies(lib, se, kern):
     """Mixed precision with every Hubbard selfenergy and both row-type stage
     kernels: 200 steps of a 6-site chain against the binary64 oracle, to the
