@@ -38,7 +38,8 @@ PEAK_HBM = 8000.0          # GB/s
 TRAFFIC = {
     "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
     "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
-    "hub_stage/2d": {"bytes": 2.36e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "539ec63e7c02"},
+    "hub_stage/2d": {"bytes": 2.37e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "0706a59a8d91"},
+    "hub_stage/2d/mixed": {"bytes": 1.63e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "0706a59a8d91"},
 }
 
 
@@ -293,7 +294,9 @@ def run_hubbard(args, torch, B, kind):
                     "err_G1_vs_fp64": float(np.abs(g1_mx - g1_64).max() / np.abs(g1_64).max()),
                     "err_E_vs_fp64": abs(mx_obs["E_tot"] - obs["E_tot"]) / max(abs(obs["E_tot"]), 1.0),
                     "roofline": {"kernel": "hub_stage", "achieved": round(mx_ach, 2), "peak": PEAK_HBM,
-                                 "unit": "GB/s", "frac": round(mx_ach / PEAK_HBM, 4), "traffic": None}}
+                                 "unit": "GB/s", "frac": round(mx_ach / PEAK_HBM, 4),
+                                 "traffic": traffic("hub_stage/2d/mixed")
+                                 if kind == "hubbard_2d" and se == "soa" else None}}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_hubbard(system, selfenergy=se)
     return out
