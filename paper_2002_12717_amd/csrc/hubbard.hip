@@ -1,16 +1,20 @@
 // Hubbard-basis G1-G2 kernels (Sec. III.D, Sec. V.A, Sec. VII).
 //
 // State per cluster: G1 = [X | Y] with X = G^{<,up}, Y = G^{<,down} (ns x ns
-// each) and G2 = A = G2^{up down up down} ([ns]^4).  Every G2 element is
-// produced by one thread from a fixed number of neighbours, so the kernel is a
-// bandwidth-bound stream: the O(ns^5) sums of the direct formulation are
-// replaced by the paper's reformulations that carry no inner sum
-// (eq:soa-cubic-scheme for the source, the sparse-h commutator of Sec. VII.A,
-// the reformulated ladder of Sec. VII.C).
+// each) and G2 = A = G2^{up down up down} ([ns]^4; GW adds the equal-spin
+// channels B and C).  Every G2 element is produced from a fixed number of
+// neighbours, so a stage is a bandwidth-bound stream: the O(ns^5) sums of the
+// direct formulation are replaced by the paper's reformulations that carry no
+// inner sum (eq:soa-cubic-scheme for the source, the sparse-h commutator of
+// Sec. VII.A, the reformulated ladders of Sec. VII.C, the polarization of
+// Sec. VII.B).  Three stage kernels compute the same right-hand side: the
+// slice kernel (whole (i,j) slices staged in LDS), the row kernel (one wave
+// per G2 row) and the per-element kernel (any lattice).
 //
 // A context holds a ragged batch of clusters.  One launch per Runge-Kutta
-// stage processes a flat work list: every item is either a contiguous range
-// of one cluster's G2 elements or the G1 update of one cluster.
+// stage processes a flat work list: every item is either a range of one
+// cluster's G2 (slices, rows or elements, by kernel) or the G1 update of one
+// cluster.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -536,6 +540,9 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 // floor(SLICE_ELEMS / ns^2) long.
 constexpr int SLICE_THREADS = 512;
 constexpr int SLICE_ELEMS = 4096;
+// TPP: the diagonal entries A_ppij of the staged slices (p < ns), kept in LDS;
+// a TPP item holds at most SLICE_DIAG / ns slices
+constexpr int SLICE_DIAG = 128;
 // below this many G2 elements in all, the row kernel is the default: whole
 // slices would give too few work-groups
 constexpr long long SLICE_MIN_ELEMS = 1LL << 20;
@@ -561,6 +568,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     __shared__ int ofl[NS_MAX_ROW * ZR], ofk[NS_MAX_ROW * ZR];
     __shared__ int ofi[NS_MAX_ROW * ZR], ofj[NS_MAX_ROW * ZR];
     __shared__ cd shp[2 * NS_MAX_ROW * ZR];   // hoppings [spin][site][slot]
+    __shared__ cd DK[TPP ? SLICE_DIAG : 1];    // TPP: DK[slice][p] = A_pp,ij
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
@@ -615,6 +623,11 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const int slice0 = w.start - ch * ns2;   // first (i, j) of the item
     const unsigned e0 = (unsigned)slice0 * (unsigned)ns2;
     for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(Ach, e0 + (unsigned)m);
+    if (TPP)   // the host keeps (end - start) ns <= SLICE_DIAG for TPP items
+        for (int q = tid; q < min((w.end - w.start) * ns, SLICE_DIAG); q += SLICE_THREADS) {
+            const int sl = q / ns, p = q - sl * ns;
+            DK[q] = ldo(A, (p * ns + p) * ns2 + slice0 + sl);
+        }
     __syncthreads();
     const unsigned mg2 = slice_magic((unsigned)ns2), mg1 = slice_magic((unsigned)ns);
     const cd* hI = shp + sI * ns * ZR;   // hoppings of the spin of i and k
@@ -696,7 +709,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
             const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
             cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
             if (i == j) l1 = cadd(l1, dii);
-            const cd dkk = ldo(A, (k * ns + k) * ns2 + slice), dll = ldo(A, (l * ns + l) * ns2 + slice);
+            const cd dkk = DK[sl * ns + k], dll = DK[sl * ns + l];
             const cd ylk = cmk(-ykl.x, ykl.y);
             cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
             if (k == l) l2 = cadd(l2, dkk);
@@ -1048,7 +1061,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         if (slicek) {
             // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices of
             // one channel each; slice index = channel ns^2 + i ns + j
-            const int per = SLICE_ELEMS / (ns * ns);
+            int per = SLICE_ELEMS / (ns * ns);
+            // (se above folds TPP into SOA: the two share channels and diagonals)
+            if (c->d.selfenergy == G1G2_TPP) per = std::max(1, std::min(per, SLICE_DIAG / ns));
             const int nsl = ns * ns;
             chunks[cl] = per * ns * ns;
             for (int chn = 0; chn < nch; ++chn)
