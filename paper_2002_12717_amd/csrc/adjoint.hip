@@ -19,9 +19,10 @@
 // the right-hand side of eq:g2-hubbard / eq:eom_g1_hubbard is split into
 //   adj_a_row : the G2 cotangent (stencil of the commutator applied to the
 //               cotangent, plus the collision-integral entries),
-//   adj_red, adj_lane_red : the source Psi (eq:soa-cubic-scheme)
+//   adj_slice_red, adj_lane_red : the source Psi (eq:soa-cubic-scheme)
 //               differentiated with respect to X and Y: six reductions over
-//               pairs of G2 indices, each reading contiguous rows,
+//               pairs of G2 indices, five of them from one pass over the
+//               cotangent (per-slice partials), each reading contiguous rows,
 //   adj_e, adj_g1e, adj_gsum : the G1 cotangents, the diagonal of h^HF,
 //               dL/ds and dL/dU.
 #include <algorithm>
@@ -53,8 +54,9 @@ struct AdjArgs {
     double alpha, beta;
     int init, has_next;
     cd* red;                    // reduction buffers (see adj_red)
-    cd* part;                   // partial sums of the lane reductions [3][nparts][ns][ns][2]
+    cd* part;                   // partial sums of the kind-3 lane reduction [nparts][ns][ns][2]
     int pairs_per_part, nparts;
+    cd* spart;                  // per-slice partials of kinds 0, 2, 4, 5 [8][ns^3]
     cd* ebar;                   // [2][ns] cotangents of the h^HF diagonals
     double* gpart;              // [2 + blocks of adj_g1e]: partial dL/ds, dL/dU
     double* grads;              // [2]: dL/ds, dL/dU of this stage
@@ -65,78 +67,138 @@ enum { R_X = 0, R_Y = 6, R_M02 = 12, R_M13 = 13, R_UP = 14, R_N = 15 };
 
 __device__ __forceinline__ cd cmul3(cd a, cd b, cd c) { return cmul(cmul(a, b), c); }
 
-// Source-term reductions whose free pair excludes l (kinds 0, 1, 2; kinds 3,
-// 4, 5 are adj_lane_red_kernel).  One work-group per output pair (p0, p1);
-// threads sum over the complementary pair (c, d), which includes l, so the
-// loads are contiguous.  B = i gs g.
-template <int KIND>
-__global__ __launch_bounds__(256) void adj_red_kernel(AdjArgs s) {
-    __shared__ double sh[7][256];
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ cd wsum(cd v) { return cmk(wsum(v.x), wsum(v.y)); }
+
+// Reductions of the source term (eq:soa-cubic-scheme) differentiated with
+// respect to X and Y, B = i gs g the scaled cotangent.  Each kind sums over the
+// pair complementary to its free pair:
+//   kind 0 free (i,k): X cotangent and M02 = sum conj(A) B
+//   kind 1 free (i,j): X and Y cotangents and the U partial Re(conj(Psi/U) B)
+//   kind 2 free (j,k), kind 3 free (k,l), kind 4 free (i,l): X and Y cotangents
+//   kind 5 free (j,l): Y cotangent and M13 = sum conj(A) B
+// Kinds 0, 1, 2, 4 and 5 come from one pass over the cotangent: one work-group
+// per (i, j) slice, wave w over the rows k = w, w + 4, ... with lane = l.  Kind
+// 1 is summed over the slice; kinds 0 and 2 over l within a row, leaving
+// partials per (i, j, k) that adj_slice_fin_kernel sums over j or i; kinds 4
+// and 5 over k, leaving partials per (i, j, l).  Kind 3 is adj_lane_red_kernel.
+__global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
+    __shared__ cd sh4[4][4][64];   // per wave and lane: kinds 4 (X, Y) and 5 (Y, M13)
+    __shared__ double sh1[4][5];   // per wave: kind 1 (X re, im, Y re, im, U)
     const Cl& a = s.a;
-    const int ns = a.ns, ns2 = ns * ns;
-    const int p0 = blockIdx.x / ns, p1 = blockIdx.x % ns;
+    const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const int i = blockIdx.x / ns, j = blockIdx.x % ns;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool lane_ok = lane < ns;
+    const int l = lane_ok ? lane : 0;
     const cd* X = a.X;
     const cd* Y = a.Y;
     const double U = a.U, gs = s.gscale;
-    cd accx = cmk(0, 0), accy = cmk(0, 0), accm = cmk(0, 0);
+    const cd xij = X[i * ns + j], yji = Y[j * ns + i];
+    const cd xil = X[i * ns + l], yjl = Y[j * ns + l], yil = Y[i * ns + l];
+    cd x1 = cmk(0, 0), y1 = cmk(0, 0);
     double up = 0.0;
-    for (int cdx = threadIdx.x; cdx < ns2; cdx += blockDim.x) {
-        const int c = cdx / ns, d = cdx % ns;
-        int i, j, k, l;
-        static_assert(KIND >= 0 && KIND <= 2, "kinds 3-5 are adj_lane_red_kernel");
-        if (KIND == 0) { i = p0; k = p1; j = c; l = d; }        // free (i,k)
-        else if (KIND == 1) { i = p0; j = p1; k = c; l = d; }   // free (i,j)
-        else { j = p0; k = p1; i = c; l = d; }                  // free (j,k)
-        const int e = ((i * ns + j) * ns + k) * ns + l;
-        const cd B = cscale(cmul_i(s.gin2[e]), gs);
-        if (KIND == 0) {
-            double dd = (double)(i == j) - (double)(k == l);
-            cd w = cscale(cconj(Y[j * ns + l]), U * dd);
-            w = cadd(w, cscale(cmul_i(cconj(cmul(Y[j * ns + i], Y[i * ns + l]))), -U));
-            w = cadd(w, cscale(cmul_i(cconj(cmul(Y[k * ns + l], Y[j * ns + k]))), U));
-            accx = cfma(accx, w, B);
-            accm = cfma(accm, cconj(s.A[e]), B);
-        } else if (KIND == 1) {
-            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[j * ns + k], Y[j * ns + l]))), -U), B);
-            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[i * ns + l], X[i * ns + k]))), -U), B);
-            // Psi / U at this element (eq:soa-cubic-scheme with U = 1)
-            cd xik = X[i * ns + k], xij = X[i * ns + j], xjk = X[j * ns + k], xlk = X[l * ns + k],
-               xil = X[i * ns + l];
-            cd yjl = Y[j * ns + l], yji = Y[j * ns + i], yil = Y[i * ns + l], ykl = Y[k * ns + l],
-               yjk = Y[j * ns + k];
-            double dd = (double)(i == j) - (double)(k == l);
-            cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
-            cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
-            cd psi1 = cadd(cscale(cmul(xik, yjl), dd), cmul_i(cadd(t1, t2)));
-            up += psi1.x * B.x + psi1.y * B.y;   // Re(conj(psi1) B)
-        } else {
-            accx = cfma(accx, cscale(cmul_i(cconj(cmul(X[i * ns + j], Y[j * ns + l]))), -U), B);
-            accy = cfma(accy, cscale(cmul_i(cconj(cmul(Y[k * ns + l], X[i * ns + k]))), U), B);
+    cd a4x = cmk(0, 0), a4y = cmk(0, 0), a5y = cmk(0, 0), a5m = cmk(0, 0);
+    cd* P = s.spart;
+    for (int k = wave; k < ns; k += 4) {
+        cd r0x = cmk(0, 0), r0m = cmk(0, 0), r2x = cmk(0, 0), r2y = cmk(0, 0);
+        if (lane_ok) {
+            const int e = ((i * ns + j) * ns + k) * ns + l;
+            const cd B = cscale(cmul_i(s.gin2[e]), gs);
+            const cd cav = cconj(s.A[e]);
+            const cd xik = X[i * ns + k], xjk = X[j * ns + k], yjk = Y[j * ns + k];
+            const cd xlk = X[l * ns + k], ykl = Y[k * ns + l];
+            const double dd = (double)(i == j) - (double)(k == l);
+            // kind 0
+            cd w0 = cscale(cconj(yjl), U * dd);
+            w0 = cadd(w0, cscale(cmul_i(cconj(cmul(yji, yil))), -U));
+            w0 = cadd(w0, cscale(cmul_i(cconj(cmul(ykl, yjk))), U));
+            r0x = cmul(w0, B);
+            r0m = cmul(cav, B);
+            // kind 1
+            x1 = cfma(x1, cscale(cmul_i(cconj(cmul(xjk, yjl))), -U), B);
+            y1 = cfma(y1, cscale(cmul_i(cconj(cmul(yil, xik))), -U), B);
+            const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+            const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+            const cd psi1 = cadd(cscale(cmul(xik, yjl), dd), cmul_i(cadd(t1, t2)));   // Psi / U
+            up += psi1.x * B.x + psi1.y * B.y;
+            // kind 2
+            r2x = cmul(cscale(cmul_i(cconj(cmul(xij, yjl))), -U), B);
+            r2y = cmul(cscale(cmul_i(cconj(cmul(ykl, xik))), U), B);
+            // kind 4
+            a4x = cfma(a4x, cscale(cmul_i(cconj(cmul(xlk, yjl))), U), B);
+            a4y = cfma(a4y, cscale(cmul_i(cconj(cmul(yji, xik))), -U), B);
+            // kind 5
+            cd w5 = cscale(cconj(xik), U * dd);
+            w5 = cadd(w5, cscale(cmul_i(cconj(cmul(xij, xjk))), -U));
+            w5 = cadd(w5, cscale(cmul_i(cconj(cmul(xlk, xil))), U));
+            a5y = cfma(a5y, w5, B);
+            a5m = cfma(a5m, cav, B);
+        }
+        r0x = wsum(r0x);
+        r0m = wsum(r0m);
+        r2x = wsum(r2x);
+        r2y = wsum(r2y);
+        if (lane == 0) {
+            const size_t o = ((size_t)i * ns + j) * ns + k;
+            P[0 * (size_t)ns3 + o] = r0x;
+            P[1 * (size_t)ns3 + o] = r0m;
+            P[2 * (size_t)ns3 + o] = r2x;
+            P[3 * (size_t)ns3 + o] = r2y;
         }
     }
-    const int t = threadIdx.x;
-    sh[0][t] = accx.x;
-    sh[1][t] = accx.y;
-    sh[2][t] = accy.x;
-    sh[3][t] = accy.y;
-    sh[4][t] = accm.x;
-    sh[5][t] = accm.y;
-    sh[6][t] = up;
+    sh4[wave][0][lane] = a4x;
+    sh4[wave][1][lane] = a4y;
+    sh4[wave][2][lane] = a5y;
+    sh4[wave][3][lane] = a5m;
+    x1 = wsum(x1);
+    y1 = wsum(y1);
+    up = wsum(up);
+    if (lane == 0) {
+        sh1[wave][0] = x1.x;
+        sh1[wave][1] = x1.y;
+        sh1[wave][2] = y1.x;
+        sh1[wave][3] = y1.y;
+        sh1[wave][4] = up;
+    }
     __syncthreads();
-    for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-        if (t < st)
-            for (int q = 0; q < 7; ++q) sh[q][t] += sh[q][t + st];
-        __syncthreads();
+    if (wave != 0) return;
+    if (lane_ok) {
+        const size_t o = ((size_t)i * ns + j) * ns + l;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            P[(4 + q) * (size_t)ns3 + o] = cadd(cadd(sh4[0][q][lane], sh4[1][q][lane]),
+                                                cadd(sh4[2][q][lane], sh4[3][q][lane]));
     }
-    if (t == 0) {
+    if (lane == 0) {
+        double v[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[q] = (sh1[0][q] + sh1[1][q]) + (sh1[2][q] + sh1[3][q]);
         cd* R = s.red;
-        cd vx = cmk(sh[0][0], sh[1][0]), vy = cmk(sh[2][0], sh[3][0]), vm = cmk(sh[4][0], sh[5][0]);
-        const int ab = p0 * ns + p1, ba = p1 * ns + p0;
-        if (KIND == 0) { R[(R_X + 0) * ns2 + ab] = vx; R[R_M02 * ns2 + ab] = vm; }
-        else if (KIND == 1) { R[(R_X + 1) * ns2 + ab] = vx; R[(R_Y + 1) * ns2 + ba] = vy;
-                              R[R_UP * ns2 + ab] = cmk(sh[6][0], 0.0); }
-        else { R[(R_X + 2) * ns2 + ab] = vx; R[(R_Y + 2) * ns2 + ab] = vy; }
+        R[(R_X + 1) * ns2 + i * ns + j] = cmk(v[0], v[1]);
+        R[(R_Y + 1) * ns2 + j * ns + i] = cmk(v[2], v[3]);
+        R[R_UP * ns2 + i * ns + j] = cmk(v[4], 0.0);
     }
+}
+
+// Kinds 0, 2, 4, 5 from the per-slice partials: one thread per output pair;
+// kinds 0 and 4 sum over j, kinds 2 and 5 over i (fixed order).
+__global__ __launch_bounds__(256) void adj_slice_fin_kernel(AdjArgs s) {
+    const int ns = s.a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 8 * ns2) return;
+    const int q = t / ns2, o = t - q * ns2, p0 = o / ns, p1 = o - p0 * ns;
+    const bool over_j = q == 0 || q == 1 || q == 4 || q == 5;
+    const cd* P = s.spart + (size_t)q * ns3;
+    cd v = cmk(0, 0);
+    for (int r = 0; r < ns; ++r)
+        v = cadd(v, over_j ? P[((size_t)p0 * ns + r) * ns + p1] : P[((size_t)r * ns + p0) * ns + p1]);
+    static constexpr int slot[8] = {R_X + 0, R_M02, R_X + 2, R_Y + 2, R_X + 4, R_Y + 4, R_Y + 5, R_M13};
+    s.red[slot[q] * ns2 + o] = v;
 }
 
 // G2 cotangent mu = i gs [conj(E) g + hop stencil applied to g] + collision
@@ -220,17 +282,15 @@ __global__ __launch_bounds__(256) void adj_a_row_kernel(AdjArgs s, int rows_per_
     }
 }
 
-// Source-term reductions whose free pair contains l (kinds 3, 4, 5 of
-// adj_red_kernel), with lane = l so that every load is a contiguous row.
-// Work-group (f, part): f is the other free index (k, i or j), part a range of
-// the summed pairs split over the four waves; per-part sums go to s.part and
+// Kind 3 of the source-term reductions (free (k,l)), with lane = l so that
+// every load is a contiguous row.  Work-group (k, part): part a range of the
+// summed pairs (i, j) split over the four waves; per-part sums go to s.part and
 // adj_lane_fin_kernel adds them up.
-template <int KIND>
 __global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
     __shared__ cd sh[4][2][64];
     const Cl& a = s.a;
     const int ns = a.ns, ns2 = ns * ns;
-    const int f = blockIdx.x % ns, part = blockIdx.x / ns;
+    const int k = blockIdx.x % ns, part = blockIdx.x / ns;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool lane_ok = lane < ns;
     const int l = lane_ok ? lane : 0;
@@ -241,27 +301,11 @@ __global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
     const int p0 = part * s.pairs_per_part, p1 = min(ns2, p0 + s.pairs_per_part);
     if (lane_ok) {
         for (int pr = p0 + wave; pr < p1; pr += 4) {
-            const int c = pr / ns, d = pr % ns;
-            int i, j, k;
-            if (KIND == 3) { k = f; i = c; j = d; }
-            else if (KIND == 4) { i = f; j = c; k = d; }
-            else { j = f; i = c; k = d; }
+            const int i = pr / ns, j = pr % ns;
             const int e = ((i * ns + j) * ns + k) * ns + l;
             const cd B = cscale(cmul_i(s.gin2[e]), gs);
-            if (KIND == 3) {
-                v0 = cfma(v0, cscale(cmul_i(cconj(cmul(X[i * ns + l], Y[j * ns + l]))), U), B);
-                v1 = cfma(v1, cscale(cmul_i(cconj(cmul(Y[j * ns + k], X[i * ns + k]))), U), B);
-            } else if (KIND == 4) {
-                v0 = cfma(v0, cscale(cmul_i(cconj(cmul(X[l * ns + k], Y[j * ns + l]))), U), B);
-                v1 = cfma(v1, cscale(cmul_i(cconj(cmul(Y[j * ns + i], X[i * ns + k]))), -U), B);
-            } else {
-                double dd = (double)(i == j) - (double)(k == l);
-                cd w = cscale(cconj(X[i * ns + k]), U * dd);
-                w = cadd(w, cscale(cmul_i(cconj(cmul(X[i * ns + j], X[j * ns + k]))), -U));
-                w = cadd(w, cscale(cmul_i(cconj(cmul(X[l * ns + k], X[i * ns + l]))), U));
-                v0 = cfma(v0, w, B);                       // Y cotangent
-                v1 = cfma(v1, cconj(s.A[e]), B);            // M13
-            }
+            v0 = cfma(v0, cscale(cmul_i(cconj(cmul(X[i * ns + l], Y[j * ns + l]))), U), B);
+            v1 = cfma(v1, cscale(cmul_i(cconj(cmul(Y[j * ns + k], X[i * ns + k]))), U), B);
         }
     }
     sh[wave][0][lane] = v0;
@@ -270,30 +314,27 @@ __global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
     if (wave == 0 && lane_ok) {
         cd t0 = cadd(cadd(sh[0][0][lane], sh[1][0][lane]), cadd(sh[2][0][lane], sh[3][0][lane]));
         cd t1 = cadd(cadd(sh[0][1][lane], sh[1][1][lane]), cadd(sh[2][1][lane], sh[3][1][lane]));
-        cd* P = s.part + ((size_t)((KIND - 3) * s.nparts + part) * ns2 + f * ns + l) * 2;
+        cd* P = s.part + ((size_t)part * ns2 + k * ns + l) * 2;
         P[0] = t0;
         P[1] = t1;
     }
 }
 
-// Sums the per-part results of adj_lane_red_kernel into the reduction slots
-// (same slots and pair orientation as adj_red_kernel).
+// Sums the per-part results of adj_lane_red_kernel into the kind-3 slots: the
+// X cotangent at (l, k), the Y cotangent at (k, l).
 __global__ __launch_bounds__(256) void adj_lane_fin_kernel(AdjArgs s) {
     const int ns = s.a.ns, ns2 = ns * ns;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * ns2) return;
-    const int kind = 3 + t / ns2, fl = t % ns2, f = fl / ns, l = fl % ns;
+    if (t >= ns2) return;
+    const int k = t / ns, l = t % ns;
     cd v0 = cmk(0, 0), v1 = cmk(0, 0);
     for (int p = 0; p < s.nparts; ++p) {
-        const cd* P = s.part + ((size_t)((kind - 3) * s.nparts + p) * ns2 + fl) * 2;
+        const cd* P = s.part + ((size_t)p * ns2 + t) * 2;
         v0 = cadd(v0, P[0]);
         v1 = cadd(v1, P[1]);
     }
-    cd* R = s.red;
-    const int ab = f * ns + l, ba = l * ns + f;
-    if (kind == 3) { R[(R_X + 3) * ns2 + ba] = v0; R[(R_Y + 3) * ns2 + ab] = v1; }
-    else if (kind == 4) { R[(R_X + 4) * ns2 + ab] = v0; R[(R_Y + 4) * ns2 + ab] = v1; }
-    else { R[(R_Y + 5) * ns2 + ab] = v0; R[R_M13 * ns2 + ab] = v1; }
+    s.red[(R_X + 3) * ns2 + l * ns + k] = v0;
+    s.red[(R_Y + 3) * ns2 + k * ns + l] = v1;
 }
 
 // Cotangents of the h^HF diagonals (ebar), the drive and U parts that depend
@@ -453,7 +494,8 @@ struct AdjState {
     std::vector<Regs> seg, seg2, seg3, seg4;
     Regs LAM, LACC, CA, CB;
     cd* red = nullptr;
-    cd* part = nullptr;        // lane-reduction partials
+    cd* part = nullptr;        // kind-3 lane-reduction partials
+    cd* spart = nullptr;       // per-slice partials of kinds 0, 2, 4, 5
     int nparts = 0, pairs_per_part = 0;
     cd* ebar = nullptr;
     double* gpart = nullptr;
@@ -518,6 +560,7 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
     s.has_next = has_next;
     s.red = st->red;
     s.part = st->part;
+    s.spart = st->spart;
     s.pairs_per_part = st->pairs_per_part;
     s.nparts = st->nparts;
     s.ebar = st->ebar;
@@ -528,13 +571,10 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
 
 g1g2_status vjp(g1g2_ctx* c, const AdjArgs& s) {
     const int ns = s.a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
-    hipLaunchKernelGGL((adj_red_kernel<0>), dim3(ns2), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<1>), dim3(ns2), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_red_kernel<2>), dim3(ns2), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_lane_red_kernel<3>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_lane_red_kernel<4>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL((adj_lane_red_kernel<5>), dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL(adj_lane_fin_kernel, dim3((3 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_slice_red_kernel, dim3(ns2), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_slice_fin_kernel, dim3((8 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_lane_red_kernel, dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_lane_fin_kernel, dim3((ns2 + 255) / 256), dim3(256), 0, c->stream, s);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "adj_red");
     constexpr int RPW = 4;
@@ -566,6 +606,7 @@ void adj_free(g1g2_ctx* c) {
     for (Regs* r : {&st->LAM, &st->LACC, &st->CA, &st->CB}) free_reg(*r);
     if (st->red) (void)hipFree(st->red);
     if (st->part) (void)hipFree(st->part);
+    if (st->spart) (void)hipFree(st->spart);
     if (st->ebar) (void)hipFree(st->ebar);
     if (st->gpart) (void)hipFree(st->gpart);
     if (st->grads) (void)hipFree(st->grads);
@@ -609,7 +650,8 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     HIP_OK(c, hipMemsetAsync(st->red, 0, (size_t)R_N * ns * ns * sizeof(cd), c->stream));
     st->pairs_per_part = ADJ_PAIRS_PER_PART;
     st->nparts = (ns * ns + ADJ_PAIRS_PER_PART - 1) / ADJ_PAIRS_PER_PART;
-    HIP_OK(c, hipMalloc(&st->part, (size_t)3 * st->nparts * ns * ns * 2 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&st->part, (size_t)st->nparts * ns * ns * 2 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&st->spart, (size_t)8 * ns * ns * ns * sizeof(cd)));
     HIP_OK(c, hipMalloc(&st->ebar, (size_t)2 * ns * sizeof(cd)));
     HIP_OK(c, hipMalloc(&st->gpart, (size_t)(2 + (2 * ns * ns + 255) / 256) * sizeof(double)));
     HIP_OK(c, hipMalloc(&st->grads, (size_t)4 * nsteps * 2 * sizeof(double)));
