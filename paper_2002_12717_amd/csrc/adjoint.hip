@@ -17,12 +17,12 @@
 // once, keeping y_n and the stage states Y2, Y3, Y4 of every step in device
 // memory (four states per step of a segment).  The vector-Jacobian product of
 // the right-hand side of eq:g2-hubbard / eq:eom_g1_hubbard is split into
-//   adj_a_row : the G2 cotangent (stencil of the commutator applied to the
-//               cotangent, plus the collision-integral entries),
-//   adj_slice_red, adj_lane_red : the source Psi (eq:soa-cubic-scheme)
-//               differentiated with respect to X and Y: six reductions over
-//               pairs of G2 indices, five of them from one pass over the
-//               cotangent (per-slice partials), each reading contiguous rows,
+//   adj_slice_red : in one pass over the cotangent, the G2 cotangent
+//               (stencil of the commutator applied to the cotangent, plus the
+//               collision-integral entries) and five of the six reductions of
+//               the source Psi (eq:soa-cubic-scheme) differentiated with
+//               respect to X and Y (per-slice partials),
+//   adj_lane_red : the sixth reduction, reading contiguous rows,
 //   adj_e, adj_g1e, adj_gsum : the G1 cotangents, the diagonal of h^HF,
 //               dL/ds and dL/dU.
 #include <algorithm>
@@ -86,18 +86,50 @@ __device__ __forceinline__ cd wsum(cd v) { return cmk(wsum(v.x), wsum(v.y)); }
 // 1 is summed over the slice; kinds 0 and 2 over l within a row, leaving
 // partials per (i, j, k) that adj_slice_fin_kernel sums over j or i; kinds 4
 // and 5 over k, leaving partials per (i, j, l).  Kind 3 is adj_lane_red_kernel.
+//
+// The same pass computes the G2 cotangent mu = i gs [conj(E) g + hop stencil
+// applied to g] + collision entries (the commutator stencil is its own
+// adjoint up to the conjugate of the diagonal) and updates the running sum and
+// the next stage's cotangent: the l-neighbours of the stencil are other lanes
+// (cross-lane permute), the other neighbours whole rows; neighbour tables are
+// staged in LDS padded to four entries (a missing neighbour is the site itself
+// with hopping 0).
 __global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
+    constexpr int ZR = 4;
     __shared__ cd sh4[4][4][64];   // per wave and lane: kinds 4 (X, Y) and 5 (Y, M13)
     __shared__ double sh1[4][5];   // per wave: kind 1 (X re, im, Y re, im, U)
+    __shared__ cd eu[64], ed[64];
+    __shared__ int snb[2 * 64 * ZR];
+    __shared__ cd shp[2 * 64 * ZR];
     const Cl& a = s.a;
-    const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
     const int i = blockIdx.x / ns, j = blockIdx.x % ns;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool lane_ok = lane < ns;
     const int l = lane_ok ? lane : 0;
     const cd* X = a.X;
     const cd* Y = a.Y;
     const double U = a.U, gs = s.gscale;
+    for (int q = tid; q < ns; q += blockDim.x) {
+        eu[q] = hf_diag(a, 0, q);
+        ed[q] = hf_diag(a, 1, q);
+    }
+    for (int q = tid; q < 2 * ns * ZR; q += blockDim.x) {
+        const int row = q / ZR, qq = q - row * ZR, site = row % ns;
+        const int p = qq < z ? a.nbr[row * z + qq] : -1;
+        snb[q] = p >= 0 ? p : site;
+        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    const int* nbu = snb;
+    const int* nbd = snb + ns * ZR;
+    const cd* hu = shp;
+    const cd* hd = shp + ns * ZR;
+    const cd* __restrict__ G = s.gin2;
+    int src[ZR];
+#pragma unroll
+    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? nbd[l * ZR + q] : lane;
+    const cd ei = eu[i], ej = ed[j], el = ed[l];
     const cd xij = X[i * ns + j], yji = Y[j * ns + i];
     const cd xil = X[i * ns + l], yjl = Y[j * ns + l], yil = Y[i * ns + l];
     cd x1 = cmk(0, 0), y1 = cmk(0, 0);
@@ -106,9 +138,44 @@ __global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
     cd* P = s.spart;
     for (int k = wave; k < ns; k += 4) {
         cd r0x = cmk(0, 0), r0m = cmk(0, 0), r2x = cmk(0, 0), r2y = cmk(0, 0);
+        const int e = ((i * ns + j) * ns + k) * ns + l;
+        const cd g = lane_ok ? G[e] : cmk(0.0, 0.0);
+        cd vl[ZR];
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            vl[q].x = __shfl(g.x, src[q], 64);
+            vl[q].y = __shfl(g.y, src[q], 64);
+        }
         if (lane_ok) {
-            const int e = ((i * ns + j) * ns + k) * ns + l;
-            const cd B = cscale(cmul_i(s.gin2[e]), gs);
+            // G2 cotangent of this element
+            const cd ek = eu[k];
+            const cd E = cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y);
+            cd hsum = cmul(cconj(E), g);
+#pragma unroll
+            for (int q = 0; q < ZR; ++q) {
+                hsum = cfma(hsum, hu[i * ZR + q], G[e + (nbu[i * ZR + q] - i) * ns3]);
+                hsum = cfma(hsum, hd[j * ZR + q], G[e + (nbd[j * ZR + q] - j) * ns2]);
+                hsum = csub(hsum, cmul(G[e + (nbu[k * ZR + q] - k) * ns], cconj(hu[k * ZR + q])));
+                hsum = csub(hsum, cmul(vl[q], cconj(hd[l * ZR + q])));
+            }
+            cd mu = cscale(cmul_i(hsum), gs);
+            if (j == i && l == i) {
+                cd bxa = cscale(cmul_i(s.gin1[i * ns + k]), gs), bxb = cscale(cmul_i(s.gin1[k * ns + i]), gs);
+                mu = cadd(mu, cscale(cmul_i(cadd(bxa, cconj(bxb))), a.U));
+            }
+            if (j == i && k == i) {
+                const cd* gy = s.gin1 + ns2;
+                cd bya = cscale(cmul_i(gy[i * ns + l]), gs), byb = cscale(cmul_i(gy[l * ns + i]), gs);
+                mu = cadd(mu, cscale(cmul_i(cadd(bya, cconj(byb))), a.U));
+            }
+            const cd base = s.init ? s.lam2[e] : s.lacc2[e];
+            s.lacc2[e] = cadd(base, mu);
+            if (s.has_next) {
+                const cd lv = s.lam2[e];
+                s.gnext2[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
+            }
+            // source-term reductions
+            const cd B = cscale(cmul_i(g), gs);
             const cd cav = cconj(s.A[e]);
             const cd xik = X[i * ns + k], xjk = X[j * ns + k], yjk = Y[j * ns + k];
             const cd xlk = X[l * ns + k], ykl = Y[k * ns + l];
@@ -186,11 +253,24 @@ __global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
 }
 
 // Kinds 0, 2, 4, 5 from the per-slice partials: one thread per output pair;
-// kinds 0 and 4 sum over j, kinds 2 and 5 over i (fixed order).
+// kinds 0 and 4 sum over j, kinds 2 and 5 over i (fixed order).  Threads
+// 8 ns^2 .. 9 ns^2 - 1 add up the per-part sums of kind 3 (adj_lane_red).
 __global__ __launch_bounds__(256) void adj_slice_fin_kernel(AdjArgs s) {
     const int ns = s.a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 8 * ns2) return;
+    if (t >= 9 * ns2) return;
+    if (t >= 8 * ns2) {   // kind 3: the X cotangent at (l, k), the Y cotangent at (k, l)
+        const int kl = t - 8 * ns2, k = kl / ns, l = kl % ns;
+        cd v0 = cmk(0, 0), v1 = cmk(0, 0);
+        for (int p = 0; p < s.nparts; ++p) {
+            const cd* P = s.part + ((size_t)p * ns2 + kl) * 2;
+            v0 = cadd(v0, P[0]);
+            v1 = cadd(v1, P[1]);
+        }
+        s.red[(R_X + 3) * ns2 + l * ns + k] = v0;
+        s.red[(R_Y + 3) * ns2 + k * ns + l] = v1;
+        return;
+    }
     const int q = t / ns2, o = t - q * ns2, p0 = o / ns, p1 = o - p0 * ns;
     const bool over_j = q == 0 || q == 1 || q == 4 || q == 5;
     const cd* P = s.spart + (size_t)q * ns3;
@@ -201,91 +281,10 @@ __global__ __launch_bounds__(256) void adj_slice_fin_kernel(AdjArgs s) {
     s.red[slot[q] * ns2 + o] = v;
 }
 
-// G2 cotangent mu = i gs [conj(E) g + hop stencil applied to g] + collision
-// entries (the commutator stencil is its own adjoint up to the conjugate of
-// the diagonal).  One wave per row g[i][j][k][:] (ns <= 64), lane = l.  The l-neighbours of the stencil are other lanes (cross-lane permute);
-// neighbour tables are staged in LDS padded to four entries (a missing
-// neighbour is the site itself with hopping 0), so all loads of a row issue
-// together.  Same result as adj_a_kernel up to summation order.
-__global__ __launch_bounds__(256) void adj_a_row_kernel(AdjArgs s, int rows_per_wave) {
-    constexpr int ZR = 4;
-    __shared__ cd eu[64], ed[64];
-    __shared__ int snb[2 * 64 * ZR];
-    __shared__ cd shp[2 * 64 * ZR];
-    const Cl& a = s.a;
-    const int ns = a.ns, z = a.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
-    const int tid = threadIdx.x;
-    for (int q = tid; q < ns; q += blockDim.x) {
-        eu[q] = hf_diag(a, 0, q);
-        ed[q] = hf_diag(a, 1, q);
-    }
-    for (int q = tid; q < 2 * ns * ZR; q += blockDim.x) {
-        const int row = q / ZR, qq = q - row * ZR, site = row % ns;
-        const int p = qq < z ? a.nbr[row * z + qq] : -1;
-        snb[q] = p >= 0 ? p : site;
-        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    const int* nbu = snb;
-    const int* nbd = snb + ns * ZR;
-    const cd* hu = shp;
-    const cd* hd = shp + ns * ZR;
-    const cd* __restrict__ G = s.gin2;
-    const double gs = s.gscale;
-    const int lane = tid & 63;
-    const bool lane_ok = lane < ns;
-    const int l = lane_ok ? lane : 0;
-    int src[ZR];
-#pragma unroll
-    for (int q = 0; q < ZR; ++q) src[q] = lane_ok ? nbd[l * ZR + q] : lane;
-    const cd el = ed[l];
-    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (tid >> 6));
-    for (int r = 0; r < rows_per_wave; ++r) {
-        const int row = wave * rows_per_wave + r;
-        if (row >= ns3) break;
-        const int k = row % ns, ij = row / ns, j = ij % ns, i = ij / ns;
-        const int e = row * ns + l;
-        const cd g = lane_ok ? G[e] : cmk(0.0, 0.0);
-        cd vl[ZR];
-#pragma unroll
-        for (int q = 0; q < ZR; ++q) {
-            vl[q].x = __shfl(g.x, src[q], 64);
-            vl[q].y = __shfl(g.y, src[q], 64);
-        }
-        if (!lane_ok) continue;
-        const cd ei = eu[i], ej = ed[j], ek = eu[k];
-        const cd E = cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y);
-        cd hsum = cmul(cconj(E), g);
-#pragma unroll
-        for (int q = 0; q < ZR; ++q) {
-            hsum = cfma(hsum, hu[i * ZR + q], G[e + (nbu[i * ZR + q] - i) * ns3]);
-            hsum = cfma(hsum, hd[j * ZR + q], G[e + (nbd[j * ZR + q] - j) * ns2]);
-            hsum = csub(hsum, cmul(G[e + (nbu[k * ZR + q] - k) * ns], cconj(hu[k * ZR + q])));
-            hsum = csub(hsum, cmul(vl[q], cconj(hd[l * ZR + q])));
-        }
-        cd mu = cscale(cmul_i(hsum), gs);
-        if (j == i && l == i) {
-            cd bxa = cscale(cmul_i(s.gin1[i * ns + k]), gs), bxb = cscale(cmul_i(s.gin1[k * ns + i]), gs);
-            mu = cadd(mu, cscale(cmul_i(cadd(bxa, cconj(bxb))), a.U));
-        }
-        if (j == i && k == i) {
-            const cd* gy = s.gin1 + ns2;
-            cd bya = cscale(cmul_i(gy[i * ns + l]), gs), byb = cscale(cmul_i(gy[l * ns + i]), gs);
-            mu = cadd(mu, cscale(cmul_i(cadd(bya, cconj(byb))), a.U));
-        }
-        cd base = s.init ? s.lam2[e] : s.lacc2[e];
-        s.lacc2[e] = cadd(base, mu);
-        if (s.has_next) {
-            cd lv = s.lam2[e];
-            s.gnext2[e] = cmk(s.alpha * lv.x + s.beta * mu.x, s.alpha * lv.y + s.beta * mu.y);
-        }
-    }
-}
-
 // Kind 3 of the source-term reductions (free (k,l)), with lane = l so that
 // every load is a contiguous row.  Work-group (k, part): part a range of the
 // summed pairs (i, j) split over the four waves; per-part sums go to s.part and
-// adj_lane_fin_kernel adds them up.
+// adj_slice_fin_kernel adds them up.
 __global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
     __shared__ cd sh[4][2][64];
     const Cl& a = s.a;
@@ -320,23 +319,6 @@ __global__ __launch_bounds__(256) void adj_lane_red_kernel(AdjArgs s) {
     }
 }
 
-// Sums the per-part results of adj_lane_red_kernel into the kind-3 slots: the
-// X cotangent at (l, k), the Y cotangent at (k, l).
-__global__ __launch_bounds__(256) void adj_lane_fin_kernel(AdjArgs s) {
-    const int ns = s.a.ns, ns2 = ns * ns;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ns2) return;
-    const int k = t / ns, l = t % ns;
-    cd v0 = cmk(0, 0), v1 = cmk(0, 0);
-    for (int p = 0; p < s.nparts; ++p) {
-        const cd* P = s.part + ((size_t)p * ns2 + t) * 2;
-        v0 = cadd(v0, P[0]);
-        v1 = cadd(v1, P[1]);
-    }
-    s.red[(R_X + 3) * ns2 + l * ns + k] = v0;
-    s.red[(R_Y + 3) * ns2 + k * ns + l] = v1;
-}
-
 // Cotangents of the h^HF diagonals (ebar), the drive and U parts that depend
 // on them, and the sum of the U partials of the source (one work-group; four
 // threads per site).
@@ -354,6 +336,7 @@ __global__ __launch_bounds__(256) void adj_e_kernel(AdjArgs s) {
     const int i = t >> 2, sub = t & 3;
     cd eu = cmk(0, 0), ed = cmk(0, 0);
     if (i < ns) {
+#pragma unroll 4
         for (int p = sub; p < ns; p += 4) {
             // (BX X^H - X^H BX)_ii with BX = i gs gX
             cd bx_ip = cscale(cmul_i(gx[i * ns + p]), gs), bx_pi = cscale(cmul_i(gx[p * ns + i]), gs);
@@ -379,6 +362,7 @@ __global__ __launch_bounds__(256) void adj_e_kernel(AdjArgs s) {
         cd myi = cmul_mi(Y[i * ns + i]), mxi = cmul_mi(X[i * ns + i]);
         ubar = myi.x * eu.x + myi.y * eu.y + mxi.x * ed.x + mxi.y * ed.y;
     }
+#pragma unroll 4
     for (int q = t; q < ns2; q += blockDim.x) ubar += R[R_UP * ns2 + q].x;
     sh[0][t] = sbar;
     sh[1][t] = ubar;
@@ -570,18 +554,12 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
 }
 
 g1g2_status vjp(g1g2_ctx* c, const AdjArgs& s) {
-    const int ns = s.a.ns, ns2 = ns * ns, ns3 = ns2 * ns;
+    const int ns = s.a.ns, ns2 = ns * ns;
     hipLaunchKernelGGL(adj_slice_red_kernel, dim3(ns2), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL(adj_slice_fin_kernel, dim3((8 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
     hipLaunchKernelGGL(adj_lane_red_kernel, dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
-    hipLaunchKernelGGL(adj_lane_fin_kernel, dim3((ns2 + 255) / 256), dim3(256), 0, c->stream, s);
+    hipLaunchKernelGGL(adj_slice_fin_kernel, dim3((9 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "adj_red");
-    constexpr int RPW = 4;
-    const int waves = (ns3 + RPW - 1) / RPW;
-    hipLaunchKernelGGL(adj_a_row_kernel, dim3((waves + 3) / 4), dim3(256), 0, c->stream, s, RPW);
-    HIP_OK(c, hipGetLastError());
-    prof_mark(c, "adj_a");
     const int g1blocks = (2 * ns2 + 255) / 256;
     hipLaunchKernelGGL(adj_e_kernel, dim3(1), dim3(256), 0, c->stream, s);
     hipLaunchKernelGGL(adj_g1e_kernel, dim3(g1blocks), dim3(256), 0, c->stream, s);
