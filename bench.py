@@ -38,8 +38,8 @@ PEAK_HBM = 8000.0          # GB/s
 TRAFFIC = {
     "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
     "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "5997b069417f"},
-    "hub_stage/2d": {"bytes": 2.37e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "0706a59a8d91"},
-    "hub_stage/2d/mixed": {"bytes": 1.63e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "0706a59a8d91"},
+    "hub_stage/2d": {"bytes": 2.36e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "b49c38ca1bfc"},
+    "hub_stage/2d/mixed": {"bytes": 1.63e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "b49c38ca1bfc"},
 }
 
 
