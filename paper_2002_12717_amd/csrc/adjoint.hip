@@ -336,7 +336,6 @@ __global__ __launch_bounds__(256) void adj_e_kernel(AdjArgs s) {
     const int i = t >> 2, sub = t & 3;
     cd eu = cmk(0, 0), ed = cmk(0, 0);
     if (i < ns) {
-#pragma unroll 4
         for (int p = sub; p < ns; p += 4) {
             // (BX X^H - X^H BX)_ii with BX = i gs gX
             cd bx_ip = cscale(cmul_i(gx[i * ns + p]), gs), bx_pi = cscale(cmul_i(gx[p * ns + i]), gs);
@@ -362,7 +361,6 @@ __global__ __launch_bounds__(256) void adj_e_kernel(AdjArgs s) {
         cd myi = cmul_mi(Y[i * ns + i]), mxi = cmul_mi(X[i * ns + i]);
         ubar = myi.x * eu.x + myi.y * eu.y + mxi.x * ed.x + mxi.y * ed.y;
     }
-#pragma unroll 4
     for (int q = t; q < ns2; q += blockDim.x) ubar += R[R_UP * ns2 + q].x;
     sh[0][t] = sbar;
     sh[1][t] = ubar;
