@@ -495,8 +495,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this G1-G2 workload runs on a single MI355X "
-              "(DESIGN.md describes how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: this G1-G2 workload runs on a single MI355X; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2002_12717_amd import binding as B
