@@ -385,10 +385,29 @@ def run_batch(args, torch, B):
                                "bytes_per_launch": mx_bytes},
                   "kernels": kernel_table(mx["prof"])},
         "diverged": any(bool(o["diverged"]) for o in f64["obs"]),
+        "one_cluster_at_a_time": one_at_a_time(clusters, se, stream, torch, B, ms_step),
     })
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(clusters, selfenergy=se)
     return out
+
+
+def one_at_a_time(clusters, se, stream, torch, B, batch_ms_step, steps: int = 16):
+    """The same clusters propagated one after another, each in its own
+    single-cluster context (binary64, graph-captured steps): one context per
+    distinct cluster size is timed and the per-step times are summed over the
+    batch's clusters."""
+    per_ns = {}
+    for c in clusters:
+        if c.ns in per_ns:
+            continue
+        p = B.Propagator(B.HUBBARD, SE_CODES[se](B), c.ns, c.h0, c.g1, U=c.U, stream=stream.cuda_stream)
+        ms, _ = timed_steps(p, c.dt, steps, 2, stream, torch)
+        p.close()
+        per_ns[c.ns] = ms / steps
+    seq = sum(per_ns[c.ns] for c in clusters)
+    return {"ms_per_step": round(seq, 4), "batch_speedup": round(seq / batch_ms_step, 3),
+            "ms_per_step_by_ns": {str(k): round(v, 5) for k, v in sorted(per_ns.items())}}
 
 
 def cpu_baseline_adjoint(seconds: float = 15.0):
