@@ -355,10 +355,11 @@ def run_batch(args, torch, B):
     tot_ms, cnt = f64["prof"]["hub_stage"]
     # algorithmic bytes per G2 element and RK4 step: 256 (binary64 stage copies)
     # or 208 (binary32 stage copies); the four stage launches share them
-    bytes_per_launch = 64.0 * n4
+    nch = 3 if se == "gw" else 1   # GW propagates three G2 channels
+    bytes_per_launch = 64.0 * n4 * nch
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
     mx_tot, mx_cnt = mx["prof"]["hub_stage"]
-    mx_bytes = 52.0 * n4
+    mx_bytes = 52.0 * n4 * nch
     mx_ach = mx_bytes * mx_cnt / (mx_tot * 1e-3) / 1e9
     err_g1 = max(float(np.abs(m - f).max() / np.abs(f).max()) for m, f in zip(mx["g1"], f64["g1"]))
     err_e = max(abs(m["E_tot"] - f["E_tot"]) / max(abs(f["E_tot"]), 1.0)

@@ -172,7 +172,7 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * size and U) propagated together: every Runge-Kutta stage of the whole batch
  * is one kernel launch over a flat work list, and g1g2_step_rk4 replays
  * captured HIP graphs of whole steps when a stream is given.  desc supplies
- * basis (HUBBARD), selfenergy (SOA, TPP or TPH) and precision (FP64 or MIXED); per cluster
+ * basis (HUBBARD), selfenergy (SOA, TPP, TPH or GW) and precision (FP64 or MIXED); per cluster
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
@@ -188,7 +188,8 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, co
                             const int32_t* chunk, void* hip_stream);
 /* Observables of every cluster: out[n] (herm_resid is not computed). */
 g1g2_status g1g2_batch_observables(g1g2_ctx* ctx, g1g2_obs* out);
-/* State of one cluster into host arrays G1 [2][ns][ns] and (if not NULL) G2 [ns]^4. */
+/* State of one cluster into host arrays G1 [2][ns][ns] and (if not NULL) G2
+ * [nchan][ns]^4 (three channels for GW, one otherwise). */
 g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void* G2);
 
 /* Discrete adjoint of the Runge-Kutta propagation (single-cluster Hubbard,

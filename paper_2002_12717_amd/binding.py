@@ -265,6 +265,7 @@ class Batch(Propagator):
     def get_cluster(self, c: int, with_g2: bool = True):
         ns = self.ns[c]
         g1 = np.zeros((2, ns, ns), np.complex128)
-        g2 = np.zeros((ns,) * 4, np.complex128) if with_g2 else None
+        shape = ((3,) if self.desc.selfenergy == GW else ()) + (ns,) * 4
+        g2 = np.zeros(shape, np.complex128) if with_g2 else None
         self._check(self.lib.g1g2_batch_get_state(self.ctx, int(c), _ptr(g1), _ptr(g2)))
         return g1, g2

@@ -418,15 +418,17 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const
     if (!out || !d || n < 1 || !ns || !U || !h0 || !G1_0) return G1G2_EINVAL;
     *out = nullptr;
     if (d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
-    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_TPP && d->selfenergy != G1G2_TPH)
+    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_TPP && d->selfenergy != G1G2_TPH &&
+        d->selfenergy != G1G2_GW)
         return G1G2_EUNSUPPORTED;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     long long n1 = 0, n2 = 0;
     int nsmax = 0;
+    const long long nch = (long long)g2_channels(*d);
     for (int c = 0; c < n; ++c) {
         if (ns[c] < 1 || !h0[c] || !G1_0[c]) return G1G2_EINVAL;
         n1 += 2LL * ns[c] * ns[c];
-        n2 += (long long)ns[c] * ns[c] * ns[c] * ns[c];
+        n2 += nch * ns[c] * ns[c] * ns[c] * ns[c];
         nsmax = std::max(nsmax, (int)ns[c]);
     }
     if (n2 > (1LL << 31) - 1) return G1G2_EUNSUPPORTED;
@@ -498,8 +500,8 @@ g1g2_status g1g2_batch_get_state(g1g2_ctx* c, int32_t cluster, void* G1, void* G
     const size_t ns = d.ns;
     HIP_OK(c, hipMemcpyAsync(G1, c->y.g1 + d.g1off, 2 * ns * ns * sizeof(cd), hipMemcpyDeviceToHost,
                              c->stream));
-    if (G2)
-        HIP_OK(c, hipMemcpyAsync(G2, c->y.g2 + d.g2off, ns * ns * ns * ns * sizeof(cd),
+    if (G2)   // the cluster's channels are stored one after another
+        HIP_OK(c, hipMemcpyAsync(G2, c->y.g2 + d.g2off, g2_channels(c->d) * ns * ns * ns * ns * sizeof(cd),
                                  hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     return G1G2_OK;
