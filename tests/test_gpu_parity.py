@@ -274,6 +274,58 @@ def test_general_gw_trajectory_small(lib):
     _compare_general_trajectory(s, "gw", 2, 20, "fp64", 1e-10)
 
 
+@pytest.mark.parametrize("se,prec", [("gw", "fp64"), ("tpp", "fp64"), ("dsl", "mixed")])
+def test_general_trajectory_nb20(lib, se, prec):
+    """nb=20 pads to 32 (the padded layout and the Nb=32 kernel shapes): 6 steps
+    of the GW, ladder and DSL closures against the oracle (interaction halved as
+    in the nb=12 ladder test)."""
+    import dataclasses
+    s = general_system(nb=20, rank=12, nocc=6, dt=0.01, key=11)
+    s = dataclasses.replace(s, w=0.5 * s.w)
+    say(f"[general trajectory] nb=20 {se} 6 steps {prec}")
+    _compare_general_trajectory(s, se, 2, 3, prec, 1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("nb,se,prec", [(40, "soa", "fp64"), (40, "gw", "fp64"), (40, "tph", "mixed"),
+                                        (64, "soa", "fp64")])
+def test_general_stepper_matches_rhs(lib, nb, se, prec):
+    """Padded sizes 48 and 64, where no trajectory is cheap enough for the
+    oracle: four steps of the library's stepper (fused Runge-Kutta updates,
+    one captured graph of four steps) against RK4 assembled on the host from
+    the library's right-hand side, whose parity with the oracle is tested
+    above.  The stage arithmetic is the same, so the two agree to rounding."""
+    from paper_2002_12717_amd import binding as B
+    code, flags = _gen_se(se)
+    s = general_system(nb=nb, rank=16, nocc=nb // 4, dt=0.01, key=13)
+    r = rng(313, nb, len(se))
+    gl, g2 = random_gless(nb, r), random_g2(nb, r, scale=0.02)
+    say(f"[general stepper] nb={nb} {se} {prec} 4 steps vs host RK4 of the rhs")
+    p = B.Propagator(B.GENERAL, code, nb, s.h0, gl, w=s.w, flags=flags,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED)
+    dt = s.dt
+    y1, y2 = np.array(gl, np.complex128), np.array(g2, np.complex128)
+    for _ in range(4):
+        def f(a1, a2):
+            d1, d2 = np.zeros_like(a1), np.zeros_like(a2)
+            p.rhs(0.0, np.ascontiguousarray(a1), np.ascontiguousarray(a2), d1, d2)
+            return d1, d2
+        k1 = f(y1, y2)
+        k2 = f(y1 + 0.5 * dt * k1[0], y2 + 0.5 * dt * k1[1])
+        k3 = f(y1 + 0.5 * dt * k2[0], y2 + 0.5 * dt * k2[1])
+        k4 = f(y1 + dt * k3[0], y2 + dt * k3[1])
+        y1 = y1 + dt / 6 * (k1[0] + 2 * k2[0] + 2 * k3[0] + k4[0])
+        y2 = y2 + dt / 6 * (k1[1] + 2 * k2[1] + 2 * k3[1] + k4[1])
+        del k1, k2, k3, k4
+    p.set_state(gl, g2)
+    p.step(dt, 4)
+    G1, G2, _ = p.get_state()
+    p.close()
+    e1, e2 = rel(G1, y1), rel(G2, y2)
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert e1 < tol and e2 < tol
+
+
 def test_general_soa_invariants_full_size(lib):
     """Nb=32 molecule, 400 steps: particle number and Hermiticity of G2 exact,
     energy drift at the level of the RK4 error."""
