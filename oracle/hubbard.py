@@ -148,7 +148,7 @@ def _pl(x):
     return x.permute(3, 2, 1, 0).conj()
 
 
-SELFENERGIES = ("soa", "tpp", "tph", "gw")
+SELFENERGIES = ("soa", "tpp", "tph", "gw", "dsl")
 
 
 def rhs(h0u, h0d, U, X, Y, A, selfenergy: str = "soa", B=None, C=None, direct: bool = False):
@@ -163,7 +163,12 @@ def rhs(h0u, h0d, U, X, Y, A, selfenergy: str = "soa", B=None, C=None, direct: b
              spin attached to its index; Pi^{dudu} built from Y... see below)
     For gw the equal-spin channels B (up) and C (down) obey eq:g2-gw-hubbard2:
       dB/dt = -i([h2_uu, B] + Pi^{uuuu} - [Pi^{uuuu}_lkji]^*), same for C.
-    Returns (dX, dY, dA) or (dX, dY, dA, dB, dC) for gw.
+    dsl (Sec. VI: polarization and both ladders on top of the source): the gw
+    equations with, on A, the tpp and tph ladder terms added as well.  The
+    ladders vanish on B and C (their quasi-Hamiltonians need a pair of
+    opposite spins), and the exchange form of the source that DSL takes equals
+    Psi on A, because the exchanged on-site interaction pairs equal spins.
+    Returns (dX, dY, dA) or (dX, dY, dA, dB, dC) for gw and dsl.
     """
     if selfenergy not in SELFENERGIES:
         raise ValueError(selfenergy)
@@ -178,7 +183,11 @@ def rhs(h0u, h0d, U, X, Y, A, selfenergy: str = "soa", B=None, C=None, direct: b
     elif selfenergy == "tph":
         lam = ladder_ph_direct(X, Y, U, A) if direct else ladder_ph(X, Y, U, A)
         S = S + lam - _pk(lam)
-    elif selfenergy == "gw":
+    if selfenergy == "dsl":
+        for lam in ((ladder_pp_direct(X, Y, U, A) if direct else ladder_pp(X, Y, U, A)),
+                    (ladder_ph_direct(X, Y, U, A) if direct else ladder_ph(X, Y, U, A))):
+            S = S + lam - _pk(lam)
+    if selfenergy in ("gw", "dsl"):
         # Pi^{up dn up dn}_ijkl: spin down on slots j, l; partner channel B (up up).
         pi_udud = polarization(Y, B, U) if not direct else polarization_direct(Y, B, U)
         # Pi^{dn up dn up}_ijkl: spin up on slots j, l; partner channel C (down down).

@@ -95,8 +95,8 @@ def hubbard_rhs_fn(system, selfenergy="soa", U=None, c=None, direct=False):
 
     def f(t, y):
         h0u, h0d = hubbard_h0(system, t, c)
-        if selfenergy == "gw":
-            return hubbard.rhs(h0u, h0d, UU, y[0], y[1], y[2], "gw", B=y[3], C=y[4], direct=direct)
+        if selfenergy in ("gw", "dsl"):
+            return hubbard.rhs(h0u, h0d, UU, y[0], y[1], y[2], selfenergy, B=y[3], C=y[4], direct=direct)
         return hubbard.rhs(h0u, h0d, UU, y[0], y[1], y[2], selfenergy, direct=direct)
 
     return f
@@ -107,7 +107,7 @@ def hubbard_initial(system, selfenergy="soa", g2_0=None):
     Y = _t(system.g1[1])
     ns = X.shape[0]
     A = torch.zeros((ns,) * 4, dtype=torch.complex128) if g2_0 is None else _t(g2_0)
-    if selfenergy == "gw":
+    if selfenergy in ("gw", "dsl"):
         return [X, Y, A, torch.zeros_like(A), torch.zeros_like(A)]
     return [X, Y, A]
 

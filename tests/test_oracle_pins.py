@@ -57,12 +57,15 @@ def test_hubbard_reformulations_match_direct_forms():
 
 
 # --------------------------------------------------------------------------- P1 cross-basis identity
-@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw"])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw", "dsl"])
 def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
-    """The general-basis equations (Secs. III.C, IV.C, V.A, V.B) with the Hubbard
-    interaction of eq:wmatrix-hubbard in the spin-orbital basis reproduce the
-    spin-resolved Hubbard equations, for a random symmetric state in which every
-    spin block of G2 is populated."""
+    """The general-basis equations (Secs. III.C, IV.C, V.A, V.B, VI) with the
+    Hubbard interaction of eq:wmatrix-hubbard in the spin-orbital basis
+    reproduce the spin-resolved Hubbard equations, for a random symmetric state
+    in which every spin block of G2 is populated.  The spin-flip blocks
+    (up dn dn up, dn up up dn) are populated too and the Hubbard equations do
+    not see them, so for gw and dsl this also shows that the three stored
+    channels form a closed system."""
     ns, U = 4, 0.7
     r = rng(12, ns)
     X, Y = T(random_gless(ns, r)), T(random_gless(ns, r))
@@ -75,8 +78,8 @@ def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
     B = _blk(g2, ns, 0, 0, 0, 0).clone()
     C = _blk(g2, ns, 1, 1, 1, 1).clone()
     dg1, dg2 = G.rhs(torch.block_diag(h0, h0), T(hubbard_spin_orbital_w(ns, U)), gl, g2, se)
-    if se == "gw":
-        dX, dY, dA, dB, dC = H.rhs(h0, h0, U, X, Y, A, "gw", B=B, C=C)
+    if se in ("gw", "dsl"):
+        dX, dY, dA, dB, dC = H.rhs(h0, h0, U, X, Y, A, se, B=B, C=C)
         assert (_blk(dg2, ns, 0, 0, 0, 0) - dB).abs().max() < 1e-13
         assert (_blk(dg2, ns, 1, 1, 1, 1) - dC).abs().max() < 1e-13
     else:
@@ -190,13 +193,16 @@ def _slope(us, errs):
     return np.polyfit(np.log(us), np.log(errs), 1)[0]
 
 
-@pytest.mark.parametrize("ns,se", [(2, "soa"), (4, "soa"), (2, "tpp"), (2, "tph"), (2, "gw")])
-def test_ed_perturbative_order_hubbard(ns, se):
+@pytest.mark.parametrize("ns,se,hi", [(2, "soa", 3.25), (4, "soa", 3.25), (2, "tpp", 3.25), (2, "tph", 3.25),
+                                       (2, "gw", 3.25), (2, "dsl", 4.3)])
+def test_ed_perturbative_order_hubbard(ns, se, hi):
     """Starting from an uncorrelated state, every G1-G2 closure contains all
-    O(w^2) terms of dn/dt, so |n - n_ED| = O(U^3) on a fixed time window."""
+    O(w^2) terms of dn/dt, so |n - n_ED| = O(U^3) on a fixed time window.  On
+    the two-site chain the DSL error falls one order faster (measured slope
+    4.0), so only the lower bound is the paper's statement there."""
     us = [0.025, 0.05, 0.1]
     errs = [_ed_error_hubbard(ns, U, se) for U in us]
-    assert 2.8 < _slope(us, errs) < 3.25, errs
+    assert 2.8 < _slope(us, errs) < hi, errs
 
 
 def _ed_error_general(h, w, n0, se, tmax=1.6, dt=0.01):
