@@ -56,12 +56,15 @@ typedef enum {
  *   TPH: particle-hole T matrix, eq:g2-eq-tph-lambda.
  *   DSL: dynamically screened ladder (Sec. VI): GW with exchange plus both
  *        T-matrix ladders, eq:g2-dsl-equation-pi-lambda.
- * Implemented: general basis SOA, GW, TPP, TPH, DSL; Hubbard basis SOA, GW,
- * TPP, TPH (Hubbard GW needs ns <= 64 and at most 4 neighbours per site, and
- * is not available for batches).  Other combinations return
- * G1G2_EUNSUPPORTED.  Hubbard GW stores three G2 channels, [3][ns]^4 in every
- * G2 argument: up-down-up-down, up-up-up-up, down-down-down-down (the spin of
- * each slot attached to its index, eq:g2-gw-hubbard1/2).  The general-basis
+ * Implemented: every selfenergy in both bases, single clusters and Hubbard
+ * batches (Hubbard GW and DSL need ns <= 64 and at most 4 neighbours per
+ * site).  Other combinations return G1G2_EUNSUPPORTED.  Hubbard GW and DSL
+ * store three G2 channels, [3][ns]^4 in every G2 argument: up-down-up-down,
+ * up-up-up-up, down-down-down-down (the spin of each slot attached to its
+ * index, eq:g2-gw-hubbard1/2).  In the Hubbard basis DSL adds both ladders
+ * to the up-down-up-down channel; they vanish on the equal-spin channels,
+ * whose interaction pairs opposite spins, and the exchange form of the
+ * source equals Psi there for the same reason.  The general-basis
  * GW, T-matrix and DSL closures cost one (nb^2 x nb^2 x nb^2) complex GEMM per
  * polarization or ladder and right-hand side.                                  */
 typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3, G1G2_DSL = 4 } g1g2_selfenergy;
@@ -128,7 +131,8 @@ typedef struct g1g2_ctx g1g2_ctx;
  * uncorrelated initial state (G2 = 0, eq:ini-g2 with n_ijkl factorized).
  * hip_stream is a hipStream_t owned by the caller (NULL = default stream).
  * Returns EINVAL for inconsistent shapes or a non-Hermitian h0, EUNSUPPORTED
- * for combinations that are not implemented (Hubbard GW, general TPP).     */
+ * for combinations that are not implemented (general nb > 64; Hubbard GW or
+ * DSL with ns > 64 or more than 4 neighbours per site).                    */
 g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, const void* w,
                       const void* G1_0, const void* G2_0, void* hip_stream);
 
@@ -172,7 +176,7 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
  * size and U) propagated together: every Runge-Kutta stage of the whole batch
  * is one kernel launch over a flat work list, and g1g2_step_rk4 replays
  * captured HIP graphs of whole steps when a stream is given.  desc supplies
- * basis (HUBBARD), selfenergy (SOA, TPP, TPH or GW) and precision (FP64 or MIXED); per cluster
+ * basis (HUBBARD), selfenergy (any) and precision (FP64 or MIXED); per cluster
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
@@ -189,7 +193,7 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, co
 /* Observables of every cluster: out[n] (herm_resid is not computed). */
 g1g2_status g1g2_batch_observables(g1g2_ctx* ctx, g1g2_obs* out);
 /* State of one cluster into host arrays G1 [2][ns][ns] and (if not NULL) G2
- * [nchan][ns]^4 (three channels for GW, one otherwise). */
+ * [nchan][ns]^4 (three channels for GW and DSL, one otherwise). */
 g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void* G2);
 
 /* Discrete adjoint of the Runge-Kutta propagation (single-cluster Hubbard,

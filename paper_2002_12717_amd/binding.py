@@ -139,10 +139,10 @@ class Propagator:
 
     def shapes(self):
         """G1 and G2 shapes of the ABI layout; Hubbard GW stores three G2 channels
-        (up-down-up-down, up-up-up-up, down-down-down-down)."""
+        (up-down-up-down, up-up-up-up, down-down-down-down), and so does Hubbard DSL."""
         nb = self.nb
         g1 = (2, nb, nb) if self.basis == HUBBARD else (nb, nb)
-        if self.basis == HUBBARD and self.desc.selfenergy == GW:
+        if self.basis == HUBBARD and self.desc.selfenergy in (GW, DSL):
             return g1, (3, nb, nb, nb, nb)
         return g1, (nb, nb, nb, nb)
 
@@ -265,7 +265,7 @@ class Batch(Propagator):
     def get_cluster(self, c: int, with_g2: bool = True):
         ns = self.ns[c]
         g1 = np.zeros((2, ns, ns), np.complex128)
-        shape = ((3,) if self.desc.selfenergy == GW else ()) + (ns,) * 4
+        shape = ((3,) if self.desc.selfenergy in (GW, DSL) else ()) + (ns,) * 4
         g2 = np.zeros(shape, np.complex128) if with_g2 else None
         self._check(self.lib.g1g2_batch_get_state(self.ctx, int(c), _ptr(g1), _ptr(g2)))
         return g1, g2

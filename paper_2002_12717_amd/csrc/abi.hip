@@ -54,10 +54,10 @@ size_t g1_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
     return c->d.basis == G1G2_HUBBARD ? 2 * nb * nb : nb * nb;
 }
-// Channels of the stored G2: Hubbard GW keeps up-down-up-down, up-up-up-up
-// and down-down-down-down; every other closure one block.
+// Channels of the stored G2: Hubbard GW and DSL keep up-down-up-down,
+// up-up-up-up and down-down-down-down; every other closure one block.
 size_t g2_channels(const g1g2_desc& d) {
-    return d.basis == G1G2_HUBBARD && d.selfenergy == G1G2_GW ? 3 : 1;
+    return d.basis == G1G2_HUBBARD && (d.selfenergy == G1G2_GW || d.selfenergy == G1G2_DSL) ? 3 : 1;
 }
 size_t g2_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
@@ -201,7 +201,6 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
-    if (d->basis == G1G2_HUBBARD && d->selfenergy == G1G2_DSL) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_GENERAL && d->nb > 64) return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_HUBBARD && (long long)d->nb * d->nb * d->nb * d->nb > (1LL << 30))
         return G1G2_EUNSUPPORTED;
@@ -418,9 +417,7 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const
     if (!out || !d || n < 1 || !ns || !U || !h0 || !G1_0) return G1G2_EINVAL;
     *out = nullptr;
     if (d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
-    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_TPP && d->selfenergy != G1G2_TPH &&
-        d->selfenergy != G1G2_GW)
-        return G1G2_EUNSUPPORTED;
+    if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     long long n1 = 0, n2 = 0;
     int nsmax = 0;

@@ -31,12 +31,18 @@ using hub::Cl;
 using hub::hf_diag;
 using hub::make_cl;
 
-// Selfenergies of the stage kernels.
-enum { SE_SOA = 0, SE_TPP = 1, SE_TPH = 2, SE_GW = 3 };
+// Selfenergies of the stage kernels.  DSL (Sec. VI) is GW on the three
+// channels with both ladders added on channel A.
+enum { SE_SOA = 0, SE_TPP = 1, SE_TPH = 2, SE_GW = 3, SE_DSL = 4 };
 
-// G2 channels stored per cluster and diagonal tensors gathered per stage.
-__host__ __device__ constexpr int n_channels(int se) { return se == SE_GW ? 3 : 1; }
-__host__ __device__ constexpr int n_diag(int se) { return se == SE_TPH ? 2 : (se == SE_GW ? 6 : 0); }
+__host__ __device__ constexpr bool has_pol(int se) { return se == SE_GW || se == SE_DSL; }
+__host__ __device__ constexpr bool has_pp(int se) { return se == SE_TPP || se == SE_DSL; }
+__host__ __device__ constexpr bool has_ph(int se) { return se == SE_TPH || se == SE_DSL; }
+
+// G2 channels stored per cluster and diagonal tensors gathered per stage
+// (GW's six layouts first, then the particle-hole ladder's two).
+__host__ __device__ constexpr int n_channels(int se) { return has_pol(se) ? 3 : 1; }
+__host__ __device__ constexpr int n_diag(int se) { return (has_pol(se) ? 6 : 0) + (has_ph(se) ? 2 : 0); }
 
 // Right-hand side of one element e = ((i ns + j) ns + k) ns + l of the
 // cluster's block A = G2^{up down up down}:
@@ -220,6 +226,7 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
 //   GW (channels A, B = G2^{up up up up}, C = G2^{dn dn dn dn}):
 //     UA[a][c][b] = A_abcb, TA[b][c][a] = A_abcb, VA[b][d][a] = A_abad,
 //     WA[a][d][b] = A_abad, UB[a][c][b] = B_abcb, TC[b][c][a] = C_abcb
+//   DSL: the six GW layouts, then R and S
 template <typename TI, int SE>
 __global__ __launch_bounds__(256) void hub_diag_kernel(const ClusterDesc* __restrict__ desc,
                                                       const WorkItem* __restrict__ dwork,
@@ -230,13 +237,15 @@ __global__ __launch_bounds__(256) void hub_diag_kernel(const ClusterDesc* __rest
     const long long n4 = (long long)ns2 * ns2;
     const TI* A = reinterpret_cast<const TI*>(in2) + d.g2off;
     cd* D = diag + (long long)n_diag(SE) * d.doff;
+    cd* DRS = D + (has_pol(SE) ? 6 * ns3 : 0);
     for (int t = w.start + threadIdx.x; t < w.end; t += blockDim.x) {
         const int x = t / ns2, y = (t / ns) % ns, z = t % ns;
-        if (SE == SE_TPH) {   // (x, y, z) = (a, b, c)
+        if (has_ph(SE)) {   // (x, y, z) = (a, b, c)
             const cd v = ld_c(A, ((z * ns + x) * ns + y) * ns + z);
-            D[t] = v;
-            D[ns3 + (y * ns + z) * ns + x] = v;
-        } else {
+            DRS[t] = v;
+            DRS[ns3 + (y * ns + z) * ns + x] = v;
+        }
+        if (has_pol(SE)) {
             // (x, y, z) = (a, b, c): P_abcb of A, B, C
             const long long e1 = ((x * ns + y) * ns + z) * ns + y;
             const cd va = ld_c(A, e1), vb = ld_c(A, n4 + e1), vc = ld_c(A, 2 * n4 + e1);
@@ -288,7 +297,7 @@ __device__ __forceinline__ cd ldo(const T* __restrict__ p, unsigned i) {
 // term is a real-by-complex product.
 template <int MODE, int SE, bool MIXED, bool REALH>
 __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
-    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH, GW = SE == SE_GW;
+    constexpr bool TPP = has_pp(SE), TPH = has_ph(SE), GW = has_pol(SE);
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
@@ -375,8 +384,9 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     cd ei = cmk(0, 0), ej = cmk(0, 0), xij = cmk(0, 0), yji = cmk(0, 0);
     cd xil = cmk(0, 0), yjl = cmk(0, 0), yil = cmk(0, 0), dll = cmk(0, 0), sijl = cmk(0, 0);
     double dij = 0.0;
-    const cd* __restrict__ DR = TPH ? s.diag + 2 * d.doff : nullptr;   // R[a][b][c]
-    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;               // S[b][c][a]
+    // R[a][b][c] and S[b][c][a], after GW's six layouts for DSL
+    const cd* __restrict__ DR = TPH ? s.diag + (long long)n_diag(SE) * d.doff + (GW ? 6 * ns3 : 0) : nullptr;
+    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;
     for (; u < w.end; u += 4) {
         if (slice != cur) {   // wave-uniform
             cur = slice;
@@ -432,8 +442,8 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
                 xil = ldo(X, i * ns + l);
                 yjl = ldo(Y, j * ns + l);
                 yil = ldo(Y, i * ns + l);
-                if (TPP) dll = ldo(A, (l * ns + l) * ns2 + sl);
-                if (TPH) sijl = ldo(DS, (i * ns + j) * ns + l);
+                if (TPP && ch == 0) dll = ldo(A, (l * ns + l) * ns2 + sl);
+                if (TPH && ch == 0) sijl = ldo(DS, (i * ns + j) * ns + l);
             }
         }
         const int k = kb * rpw + sub;
@@ -496,18 +506,18 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
             cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
             c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
             }
-            if (TPP) {   // ladder (Sec. VII.C) and its partner
+            if (TPP && ch == 0) {   // ladder (Sec. VII.C) and its partner, channel A only
                 const int kl = kk * ns + l;
                 cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
                 cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
                 if (i == j) l1 = cadd(l1, dii);
-                cd dkk = ldo(A, (kk * ns + kk) * ns2 + slice);
+                cd dkk = ldo(A, (kk * ns + kk) * ns2 + slc);
                 cd ylk = cmk(-ykl.x, ykl.y);
                 cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
                 if (kk == l) l2 = cadd(l2, dkk);
                 c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
             }
-            if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner
+            if (TPH && ch == 0) {   // particle-hole ladder (Sec. VII.C) and its partner, channel A only
                 //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
                 //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
                 const cd rjki = ldo(DR, (j * ns + kk) * ns + i), rjkl = ldo(DR, (j * ns + kk) * ns + l);
@@ -555,7 +565,7 @@ __device__ __forceinline__ int slice_div(int n, unsigned mg) {
 
 template <int MODE, int SE, bool MIXED, bool REALH>
 __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s) {
-    constexpr bool TPP = SE == SE_TPP, TPH = SE == SE_TPH, GW = SE == SE_GW;
+    constexpr bool TPP = has_pp(SE), TPH = has_ph(SE), GW = has_pol(SE);
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
@@ -623,7 +633,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const int slice0 = w.start - ch * ns2;   // first (i, j) of the item
     const unsigned e0 = (unsigned)slice0 * (unsigned)ns2;
     for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(Ach, e0 + (unsigned)m);
-    if (TPP)   // the host keeps (end - start) ns <= SLICE_DIAG for TPP items
+    if (TPP && ch == 0)   // the host keeps (end - start) ns <= SLICE_DIAG for these items
         for (int q = tid; q < min((w.end - w.start) * ns, SLICE_DIAG); q += SLICE_THREADS) {
             const int sl = q / ns, p = q - sl * ns;
             DK[q] = ldo(A, (p * ns + p) * ns2 + slice0 + sl);
@@ -639,8 +649,9 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const cd* y = s.y2 + d.g2off + ch * n4;
     cd* acc = s.acc2 + d.g2off + ch * n4;
     TO* out = reinterpret_cast<TO*>(s.out2) + d.g2off + ch * n4;
-    const cd* __restrict__ DR = TPH ? s.diag + 2 * d.doff : nullptr;   // R[a][b][c]
-    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;               // S[b][c][a]
+    // R[a][b][c] and S[b][c][a], after GW's six layouts for DSL
+    const cd* __restrict__ DR = TPH ? s.diag + (long long)n_diag(SE) * d.doff + (GW ? 6 * ns3 : 0) : nullptr;
+    const cd* __restrict__ DS = TPH ? DR + ns3 : nullptr;
     // GW: diagonal tensors of the channel's two polarization terms
     //   Pi_1 = -i U S1_jl (D1[i][k][j] - D1[i][k][l]),
     //   Pi_2 = -i U S2_ki (D2[k][j][l] - D2[i][j][l]), term Pi_1 - conj(Pi_2)
@@ -704,7 +715,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
             const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
             c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
         }
-        if (TPP) {   // ladder (Sec. VII.C) and its partner
+        if (TPP && ch == 0) {   // ladder (Sec. VII.C) and its partner, channel A only
             const int kl = k * ns + l;
             const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
             cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
@@ -715,7 +726,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
             if (k == l) l2 = cadd(l2, dkk);
             c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
         }
-        if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner
+        if (TPH && ch == 0) {   // particle-hole ladder (Sec. VII.C) and its partner, channel A only
             //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
             //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
             const cd rjki = ldo(DR, (j * ns + k) * ns + i), rjkl = ldo(DR, (j * ns + k) * ns + l);
@@ -771,15 +782,19 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
                                dim3(SLICE_THREADS), 0, c->stream, s);
         return;
     }
-    if (c->hub.rows || SE == SE_GW) {   // GW runs on the row kernel only (checked at setup)
-        if (c->hub.realhop)
-            hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork), dim3(256), 0,
-                               c->stream, s);
-        else
-            hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork), dim3(256), 0,
-                               c->stream, s);
-    } else
-        hipLaunchKernelGGL((hub_stage_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream, s);
+    if constexpr (!has_pol(SE)) {   // GW and DSL run on the row and slice kernels only (checked at setup)
+        if (!c->hub.rows) {
+            hipLaunchKernelGGL((hub_stage_kernel<MODE, SE, MIXED>), dim3(c->hub.nwork), dim3(256), 0, c->stream,
+                               s);
+            return;
+        }
+    }
+    if (c->hub.realhop)
+        hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork), dim3(256), 0, c->stream,
+                           s);
+    else
+        hipLaunchKernelGGL((hub_row_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork), dim3(256), 0,
+                           c->stream, s);
 }
 
 template <int MODE, int SE>
@@ -796,6 +811,7 @@ g1g2_status launch_stage(g1g2_ctx* c, const StageArgs& s) {
         case G1G2_TPP: launch_stage_p<MODE, SE_TPP>(c, s, mixed); break;
         case G1G2_TPH: launch_stage_p<MODE, SE_TPH>(c, s, mixed); break;
         case G1G2_GW: launch_stage_p<MODE, SE_GW>(c, s, mixed); break;
+        case G1G2_DSL: launch_stage_p<MODE, SE_DSL>(c, s, mixed); break;
         default: launch_stage_p<MODE, SE_SOA>(c, s, mixed); break;
     }
     HIP_OK(c, hipGetLastError());
@@ -979,7 +995,11 @@ std::vector<WorkItem> xcd_order(const std::vector<WorkItem>& g2, const std::vect
 g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, const cd* const* h0s,
                       const int* chunk_in) {
     HubbardData& H = c->hub;
-    const int se = c->d.selfenergy == G1G2_GW ? SE_GW : (c->d.selfenergy == G1G2_TPH ? SE_TPH : SE_SOA);
+    const int sel = c->d.selfenergy;
+    const int se = sel == G1G2_GW ? SE_GW
+                 : sel == G1G2_DSL ? SE_DSL
+                 : sel == G1G2_TPH ? SE_TPH
+                 : sel == G1G2_TPP ? SE_TPP : SE_SOA;
     const int nch = n_channels(se);
     std::vector<ClusterDesc> desc(ncl);
     std::vector<int> nbr_all;
@@ -1062,8 +1082,8 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices of
             // one channel each; slice index = channel ns^2 + i ns + j
             int per = SLICE_ELEMS / (ns * ns);
-            // (se above folds TPP into SOA: the two share channels and diagonals)
-            if (c->d.selfenergy == G1G2_TPP) per = std::max(1, std::min(per, SLICE_DIAG / ns));
+            // the particle-particle ladder keeps the diagonal entries of its slices in LDS
+            if (has_pp(se)) per = std::max(1, std::min(per, SLICE_DIAG / ns));
             const int nsl = ns * ns;
             chunks[cl] = per * ns * ns;
             for (int chn = 0; chn < nch; ++chn)
@@ -1109,9 +1129,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     } else {   // one cluster: its G1 update first, then the rows in order
         work.insert(work.begin(), g1work.begin(), g1work.end());
     }
-    if (se == SE_GW && !rowk)
+    if (has_pol(se) && !rowk)
         return set_error(c, G1G2_EUNSUPPORTED,
-                         "Hubbard GW needs ns <= 64, at most 4 neighbours per site and chunk > 0");
+                         "Hubbard GW and DSL need ns <= 64, at most 4 neighbours per site and chunk > 0");
     hub_free(c);
     H.ncl = ncl;
     H.rows = rowk;

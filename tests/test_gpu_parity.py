@@ -57,7 +57,7 @@ def _hubbard_h0(kind, r):
 
 def _se(se):
     from paper_2002_12717_amd import binding as B
-    return {"soa": B.SOA, "tpp": B.TPP, "tph": B.TPH, "gw": B.GW}[se]
+    return {"soa": B.SOA, "tpp": B.TPP, "tph": B.TPH, "gw": B.GW, "dsl": B.DSL}[se]
 
 
 @pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2", "peierls3x3"])
@@ -88,11 +88,12 @@ def test_hubbard_rhs_parity(lib, kind, se, kern):
 
 @pytest.mark.parametrize("kind", ["chain5", "ring7", "sq3x3", "open4x2", "peierls3x3"])
 @pytest.mark.parametrize("kern", ["row", "slice"])
-def test_hubbard_gw_rhs_parity(lib, kind, kern):
-    """Hubbard GW with the three channels of reading 8 (up-down-up-down,
+@pytest.mark.parametrize("se", ["gw", "dsl"])
+def test_hubbard_gw_rhs_parity(lib, kind, kern, se):
+    """Hubbard GW and DSL with the three channels of reading 8 (up-down-up-down,
     up-up-up-up, down-down-down-down): one right-hand side against the oracle."""
     from paper_2002_12717_amd import binding as B
-    say(f"[hubbard rhs] lattice={kind} se=gw kernel={kern}")
+    say(f"[hubbard rhs] lattice={kind} se={se} kernel={kern}")
     r = rng(103, len(kind))
     h0 = _hubbard_h0(kind, r)
     ns = h0.shape[1]
@@ -101,11 +102,11 @@ def test_hubbard_gw_rhs_parity(lib, kind, kern):
     U = 1.3
     g1 = np.stack([X, Y])
     flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
-    p = B.Propagator(B.HUBBARD, B.GW, ns, h0, g1, U=U, flags=flags)
+    p = B.Propagator(B.HUBBARD, _se(se), ns, h0, g1, U=U, flags=flags)
     G1d, G2d = cuda(g1), cuda(np.stack([A, Bc, C]))
     dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
     p.rhs(0.0, G1d, G2d, dG1d, dG2d)
-    dX, dY, dA, dB, dC = OH.rhs(T(h0[0]), T(h0[1]), U, T(X), T(Y), T(A), "gw", B=T(Bc), C=T(C))
+    dX, dY, dA, dB, dC = OH.rhs(T(h0[0]), T(h0[1]), U, T(X), T(Y), T(A), se, B=T(Bc), C=T(C))
     e1 = rel(dG1d.cpu().numpy(), np.stack([dX.numpy(), dY.numpy()]))
     e2 = rel(dG2d.cpu().numpy(), np.stack([dA.numpy(), dB.numpy(), dC.numpy()]))
     say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
@@ -152,13 +153,14 @@ def test_hubbard_chain_full_trajectory(lib):
     _compare_hubbard_trajectory(hubbard_chain_system(), "soa", 10, 100, 1e-10)
 
 
-def test_hubbard_gw_chain_trajectory(lib):
-    """Hubbard GW on the 8-site chain, 400 steps: G1 and E against the oracle."""
-    say("[hubbard trajectory] chain8 GW 400 steps")
-    _compare_hubbard_trajectory(hubbard_chain_system(), "gw", 4, 100, 1e-10)
+@pytest.mark.parametrize("se", ["gw", "dsl"])
+def test_hubbard_gw_chain_trajectory(lib, se):
+    """Hubbard GW and DSL on the 8-site chain, 400 steps: G1 and E against the oracle."""
+    say(f"[hubbard trajectory] chain8 {se} 400 steps")
+    _compare_hubbard_trajectory(hubbard_chain_system(), se, 4, 100, 1e-10)
 
 
-@pytest.mark.parametrize("se", ["tpp", "tph", "gw"])
+@pytest.mark.parametrize("se", ["tpp", "tph", "gw", "dsl"])
 @pytest.mark.parametrize("kern", ["row", "slice"])
 def test_hubbard_ladder_cluster_trajectory(lib, se, kern):
     from paper_2002_12717_amd import binding as B
@@ -384,12 +386,21 @@ def test_abi_errors(lib):
     from paper_2002_12717_amd import binding as B
     say("[abi] error paths")
     s = hubbard_chain_system(ns=4)
-    with pytest.raises(B.G1G2Error) as e:
-        B.Propagator(B.HUBBARD, B.DSL, 4, s.h0, s.g1, U=1.0)
-    assert e.value.status == B.EUNSUPPORTED
-    with pytest.raises(B.G1G2Error) as e:
-        B.Batch(B.DSL, [4, 4], [1.0, 1.0], [s.h0, s.h0], [s.g1, s.g1])
-    assert e.value.status == B.EUNSUPPORTED
+    # the three-channel closures need at most 4 neighbours per site: a 6-site star
+    star = np.zeros((6, 6), complex)
+    star[0, 1:] = star[1:, 0] = -1.0
+    hs = np.stack([star, star])
+    gs = np.stack([np.diag([1j, 1j, 1j, 0, 0, 0])] * 2)
+    for se in (B.GW, B.DSL):
+        with pytest.raises(B.G1G2Error) as e:
+            B.Propagator(B.HUBBARD, se, 6, hs, gs, U=1.0)
+        assert e.value.status == B.EUNSUPPORTED
+        with pytest.raises(B.G1G2Error) as e:
+            B.Batch(se, [6, 4], [1.0, 1.0], [hs, s.h0], [gs, s.g1])
+        assert e.value.status == B.EUNSUPPORTED
+    with pytest.raises(B.G1G2Error) as e:   # the general basis stops at nb = 64
+        B.Propagator(B.GENERAL, B.SOA, 65, np.eye(65), np.zeros((65, 65)), w=np.zeros((1, 1, 1, 1)))
+    assert e.value.status in (B.EUNSUPPORTED, B.EINVAL)
     with pytest.raises(B.G1G2Error) as e:   # the two stage-kernel flags exclude each other
         B.Propagator(B.HUBBARD, B.SOA, 4, s.h0, s.g1, U=1.0, flags=B.HUB_ROW_KERNEL | B.HUB_SLICE_KERNEL)
     assert e.value.status == B.EINVAL
@@ -441,7 +452,7 @@ def test_hubbard_mixed_chain_full_trajectory(lib):
 
 
 @pytest.mark.parametrize("se,kern", [("soa", "slice"), ("tpp", "slice"), ("tph", "slice"), ("tph", "row"),
-                                     ("gw", "row"), ("gw", "slice")])
+                                     ("gw", "row"), ("gw", "slice"), ("dsl", "row"), ("dsl", "slice")])
 def test_hubbard_mixed_selfenergies(lib, se, kern):
     """Mixed precision with every Hubbard selfenergy and both row-type stage
     kernels: 200 steps of a 6-site chain against the binary64 oracle, to the
@@ -470,7 +481,9 @@ def test_hubbard_mixed_selfenergies(lib, se, kern):
                                             ("soa", "slice", "fp64"), ("tpp", "slice", "fp64"),
                                             ("tpp", "slice", "mixed"), ("tph", "slice", "fp64"),
                                             ("tph", "slice", "mixed"), ("gw", "row", "fp64"),
-                                            ("gw", "slice", "fp64"), ("gw", "slice", "mixed")])
+                                            ("gw", "slice", "fp64"), ("gw", "slice", "mixed"),
+                                            ("dsl", "row", "fp64"), ("dsl", "slice", "fp64"),
+                                            ("dsl", "slice", "mixed")])
 def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     """Clusters of uneven size and U in one context: every cluster follows the
     oracle's single-cluster propagation (and the graph-replayed steps).  The
@@ -497,7 +510,7 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
         y, rec = OI.propagate_hubbard(c, nsteps=nst, selfenergy=se, observables_every=nst)
         g1, g2 = b.get_cluster(q)
         ref = np.stack([y[0].numpy(), y[1].numpy()])
-        ref2 = np.stack([t.numpy() for t in y[2:5]]) if se == "gw" else y[2].numpy()
+        ref2 = np.stack([t.numpy() for t in y[2:5]]) if se in ("gw", "dsl") else y[2].numpy()
         e = max(rel(g1, ref), rel(g2, ref2))
         e_e = abs(obs[q]["E_tot"] - rec[-1]["E_tot"]) / max(1.0, abs(rec[0]["E_tot"]))
         worst = max(worst, e, e_e)
@@ -610,7 +623,7 @@ def test_adjoint_autograd_function_and_finite_differences(lib):
 
 
 # --------------------------------------------------------------------------- full sizes and edge cases
-@pytest.mark.parametrize("se", ["soa", "tph", "gw"])
+@pytest.mark.parametrize("se", ["soa", "tph", "gw", "dsl"])
 def test_full_size_hubbard_8x8_driven_rhs(lib, se):
     """The 8x8 workload (ns = 64) with its drive switched on, at a random
     correlated state: every element of one right-hand side, in the launch
@@ -621,7 +634,7 @@ def test_full_size_hubbard_8x8_driven_rhs(lib, se):
     say(f"[full size] 8x8 {se} rhs with drive")
     r = rng(104, len(se))
     X, Y = random_gless(ns, r), random_gless(ns, r)
-    nch = 3 if se == "gw" else 1
+    nch = 3 if se in ("gw", "dsl") else 1
     g2 = [random_g2(ns, r, scale=0.05, exchange=False) for _ in range(nch)]
     t = 13.7
     p = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, np.stack([X, Y]), U=s.U)
@@ -632,11 +645,11 @@ def test_full_size_hubbard_8x8_driven_rhs(lib, se):
     p.rhs(t, G1d, G2d, dG1d, dG2d)
     v = np.diag(d.potential(t))
     hu, hd = T(s.h0[0] + v), T(s.h0[1] + v)
-    extra = dict(B=T(g2[1]), C=T(g2[2])) if se == "gw" else {}
+    extra = dict(B=T(g2[1]), C=T(g2[2])) if nch == 3 else {}
     ref = OH.rhs(hu, hd, s.U, T(X), T(Y), T(g2[0]), se, **extra)
     e1 = rel(dG1d.cpu().numpy(), np.stack([ref[0].numpy(), ref[1].numpy()]))
     got2 = dG2d.cpu().numpy()
-    ref2 = np.stack([x.numpy() for x in ref[2:]]) if se == "gw" else ref[2].numpy()
+    ref2 = np.stack([x.numpy() for x in ref[2:]]) if nch == 3 else ref[2].numpy()
     e2 = rel(got2, ref2)
     say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
     assert e1 < 1e-12 and e2 < 1e-12
