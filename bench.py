@@ -69,7 +69,10 @@ def traffic(key):
     return t["bytes"] if kernel_hash(t["src"], t["kernel"]) == t["sha1"] else None
 
 
-SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH}
+SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH,
+            "dsl": lambda B: B.DSL}
+# Hubbard G2 channels per selfenergy: GW and DSL propagate three
+HUB_CHANNELS = {"soa": 1, "tpp": 1, "tph": 1, "gw": 3, "dsl": 3}
 
 
 def soa_flops(nb: int) -> dict:
@@ -265,8 +268,8 @@ def run_hubbard(args, torch, B, kind):
     n4 = float(ns) ** 4
     tot_ms, cnt = prof["hub_stage"]
     # algorithmic bytes: 256 B per complex128 G2 element per RK4 step (4 launches);
-    # Hubbard GW propagates three G2 channels
-    bytes_per_launch = 64.0 * n4 * (3 if se == "gw" else 1)
+    # Hubbard GW and DSL propagate three G2 channels
+    bytes_per_launch = 64.0 * n4 * HUB_CHANNELS[se]
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
     name = "1D chain, 8 sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
     config = {"workload": f"Hubbard {se.upper()} G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
@@ -288,7 +291,7 @@ def run_hubbard(args, torch, B, kind):
     mx_ms, mx_prof, mx_obs, g1_mx = run(B.MIXED)
     mx_step = mx_ms / args.steps
     mx_tot, mx_cnt = mx_prof["hub_stage"]
-    mx_ach = 52.0 * n4 * (3 if se == "gw" else 1) * mx_cnt / (mx_tot * 1e-3) / 1e9
+    mx_ach = 52.0 * n4 * HUB_CHANNELS[se] * mx_cnt / (mx_tot * 1e-3) / 1e9
     out["mixed"] = {"dtype": "f64 state, f32 G2 stage copies", "value": round(1e3 / mx_step, 3),
                     "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
                     "err_G1_vs_fp64": float(np.abs(g1_mx - g1_64).max() / np.abs(g1_64).max()),
@@ -355,7 +358,7 @@ def run_batch(args, torch, B):
     tot_ms, cnt = f64["prof"]["hub_stage"]
     # algorithmic bytes per G2 element and RK4 step: 256 (binary64 stage copies)
     # or 208 (binary32 stage copies); the four stage launches share them
-    nch = 3 if se == "gw" else 1   # GW propagates three G2 channels
+    nch = HUB_CHANNELS[se]
     bytes_per_launch = 64.0 * n4 * nch
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
     mx_tot, mx_cnt = mx["prof"]["hub_stage"]
@@ -510,7 +513,7 @@ def main():
                              "hubbard_2d", "hubbard_batch", "hubbard_adjoint"])
     ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
-                         "TPP, hubbard_chain/hubbard_2d: SOA; soa, tpp, tph); general_ladder: "
+                         "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
                          "tpp, tph or dsl (default dsl)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
