@@ -8,6 +8,7 @@ t, t+dt/2, t+dt/2, t+dt.
 """
 from __future__ import annotations
 
+import math
 from typing import Callable, Sequence, Tuple
 
 import numpy as np
@@ -75,6 +76,23 @@ def propagate_general(system, nsteps=None, selfenergy="soa", g2_0=None, record=N
 
 
 # --------------------------------------------------------------------------- Hubbard
+def switch_factor(t, switch=None):
+    """Adiabatic switching of the interaction, one way to prepare a correlated
+    initial state (Sec. III.F, Sec. IX): the interaction is turned on slowly
+    from an uncorrelated start.  switch = (t_on, tau): U(t) = U phi(t) with
+    phi = 0 before t_on, sin^2(pi x / 2), x = (t - t_on) / tau, during the
+    ramp and 1 after it; None: phi = 1."""
+    if switch is None:
+        return 1.0
+    t_on, tau = switch
+    x = (t - t_on) / tau
+    if x <= 0.0:
+        return 0.0
+    if x >= 1.0:
+        return 1.0
+    return math.sin(0.5 * math.pi * x) ** 2
+
+
 def hubbard_h0(system, t, c=None):
     """Spin-resolved h0(t): static part plus the optional drive on the diagonal.
     ``c`` overrides the drive coefficients (a real tensor, for gradients)."""
@@ -90,14 +108,15 @@ def hubbard_h0(system, t, c=None):
     return h0u + dv, h0d + dv
 
 
-def hubbard_rhs_fn(system, selfenergy="soa", U=None, c=None, direct=False):
+def hubbard_rhs_fn(system, selfenergy="soa", U=None, c=None, direct=False, switch=None):
     UU = system.U if U is None else U
 
     def f(t, y):
         h0u, h0d = hubbard_h0(system, t, c)
+        Ut = UU * switch_factor(t, switch) if switch is not None else UU
         if selfenergy in ("gw", "dsl"):
-            return hubbard.rhs(h0u, h0d, UU, y[0], y[1], y[2], selfenergy, B=y[3], C=y[4], direct=direct)
-        return hubbard.rhs(h0u, h0d, UU, y[0], y[1], y[2], selfenergy, direct=direct)
+            return hubbard.rhs(h0u, h0d, Ut, y[0], y[1], y[2], selfenergy, B=y[3], C=y[4], direct=direct)
+        return hubbard.rhs(h0u, h0d, Ut, y[0], y[1], y[2], selfenergy, direct=direct)
 
     return f
 
@@ -113,12 +132,13 @@ def hubbard_initial(system, selfenergy="soa", g2_0=None):
 
 
 def propagate_hubbard(system, nsteps=None, selfenergy="soa", U=None, c=None, g2_0=None,
-                      observables_every=0, direct=False, state=None, t0=0.0):
-    """Propagate a ``workloads.HubbardSystem`` with RK4; returns (state, records)."""
+                      observables_every=0, direct=False, state=None, t0=0.0, switch=None):
+    """Propagate a ``workloads.HubbardSystem`` with RK4; returns (state, records).
+    Observables use the interaction at their time (U phi(t) when switching)."""
     from .observables import hubbard_observables
     dt = system.dt
     nsteps = system.nsteps if nsteps is None else nsteps
-    f = hubbard_rhs_fn(system, selfenergy, U, c, direct)
+    f = hubbard_rhs_fn(system, selfenergy, U, c, direct, switch)
     y = hubbard_initial(system, selfenergy, g2_0) if state is None else list(state)
     UU = system.U if U is None else U
     rec = []
@@ -126,10 +146,10 @@ def propagate_hubbard(system, nsteps=None, selfenergy="soa", U=None, c=None, g2_
     for n in range(nsteps):
         if observables_every and n % observables_every == 0:
             h0u, h0d = hubbard_h0(system, t, c)
-            rec.append(hubbard_observables(h0u, h0d, UU, y[0], y[1], y[2], t))
+            rec.append(hubbard_observables(h0u, h0d, UU * switch_factor(t, switch), y[0], y[1], y[2], t))
         y = list(rk4_step(f, t, y, dt))
         t = t0 + (n + 1) * dt
     if observables_every:
         h0u, h0d = hubbard_h0(system, t, c)
-        rec.append(hubbard_observables(h0u, h0d, UU, y[0], y[1], y[2], t))
+        rec.append(hubbard_observables(h0u, h0d, UU * switch_factor(t, switch), y[0], y[1], y[2], t))
     return y, rec

@@ -282,6 +282,59 @@ def test_dsl_tracks_ed_on_four_site_chain():
     assert dsl.max() > 2 * dsl[:30].max(), dsl
 
 
+# --------------------------------------------------------------------------- adiabatic switching
+def test_switch_factor_shape():
+    """The switching function: 0 before the ramp, 1 after it, 1/2 halfway, monotone."""
+    f = lambda t: I.switch_factor(t, (1.0, 2.0))  # noqa: E731
+    assert f(0.0) == 0.0 and f(1.0) == 0.0 and f(3.0) == 1.0 and f(5.0) == 1.0
+    assert abs(f(2.0) - 0.5) < 1e-15
+    ts = np.linspace(1.0, 3.0, 101)
+    assert np.all(np.diff([f(t) for t in ts]) >= 0.0)
+    assert I.switch_factor(7.0, None) == 1.0
+
+
+def _switched_run(se, U, tau, t_on, tmax, dt):
+    s = hubbard_chain_system(ns=6, U=U, confinement=0.0, dt=dt)
+    _, rec = I.propagate_hubbard(s, nsteps=int(round(tmax / dt)), selfenergy=se, observables_every=1,
+                                 switch=(t_on, tau))
+    t = np.array([r["t"] for r in rec])
+    E = np.array([r["E_tot"] for r in rec])
+    D = np.array([float(r["docc"].sum()) for r in rec])
+    return t, E, D
+
+
+@pytest.mark.parametrize("se", ["soa", "tpp", "gw"])
+def test_switching_energy_balance(se):
+    """With U(t) = U phi(t) the scheme, which conserves the energy for a fixed
+    Hamiltonian, obeys dE/dt = U'(t) sum_i d_i (Hellmann-Feynman, d_i the
+    double occupation): the energy gained over the ramp equals the integral
+    of U'(t) D(t).  Every term has to see the same U(t) for this to hold."""
+    U, tau, t_on = 2.0, 2.0, 0.5
+    t, E, D = _switched_run(se, U, tau, t_on, 3.0, 0.01)
+    x = np.clip((t - t_on) / tau, 0.0, 1.0)
+    dU = U * np.pi / (2.0 * tau) * np.sin(np.pi * x)
+    g = dU * D
+    h = t[1] - t[0]
+    work = h / 3.0 * (g[0] + g[-1] + 4.0 * g[1:-1:2].sum() + 2.0 * g[2:-1:2].sum())   # Simpson
+    assert abs(E[-1] - E[0]) > 1.0
+    assert abs((E[-1] - E[0]) - work) < 1e-8 * abs(E[-1] - E[0])
+
+
+def test_slow_switching_is_adiabatic():
+    """Sec. III.F: a correlated state prepared by switching the interaction on
+    slowly from the uncorrelated ground state of h0.  A slow ramp leaves the
+    double occupation nearly stationary after it and ends at a lower energy
+    than a sudden one, which heats the chain."""
+    res = {}
+    for tau in (0.25, 8.0):
+        t, E, D = _switched_run("soa", 1.0, tau, 0.0, tau + 6.0, 0.02)
+        after = t >= tau + 2.0
+        res[tau] = (D[after].std(), E[-1], np.ptp(E[after]))
+    assert res[8.0][0] < 0.02 * res[0.25][0], res
+    assert res[8.0][1] < res[0.25][1] - 0.05, res
+    assert res[8.0][2] < 1e-12 and res[0.25][2] < 1e-12      # conserved once U is constant
+
+
 # --------------------------------------------------------------------------- P3 brute-force HF-GKBA
 def _gkba_difference(h, w, g1, dt, tend):
     n = int(round(tend / dt))
