@@ -47,6 +47,7 @@ _SIGS = {
     "g1g2_set_h0": (c_int32, [c_void_p, c_void_p]),
     "g1g2_set_U": (c_int32, [c_void_p, c_double]),
     "g1g2_set_drive": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_double]),
+    "g1g2_set_switch": (c_int32, [c_void_p, c_double, c_double]),
     "g1g2_profile": (c_int32, [c_void_p, c_double, c_int64, c_int32, c_void_p, c_void_p,
                                POINTER(c_int32)]),
     "g1g2_profile_name": (ctypes.c_char_p, [c_void_p, c_int32]),
@@ -193,6 +194,10 @@ class Propagator:
         tc = np.ascontiguousarray(t_center, np.float64)
         self._check(self.lib.g1g2_set_drive(self.ctx, _ptr(x), int(len(c)), _ptr(c), _ptr(tc),
                                              float(tau)))
+
+    def set_switch(self, t_on: float, tau: float):
+        """Adiabatic switching U(t) = U phi(t), a sin^2 ramp from t_on over tau (0: off)."""
+        self._check(self.lib.g1g2_set_switch(self.ctx, float(t_on), float(tau)))
 
     def forward_checkpointed(self, dt: float, nsteps: int, interval: int = 0):
         self._check(self.lib.g1g2_forward_checkpointed(self.ctx, float(dt), int(nsteps), int(interval)))

@@ -128,11 +128,11 @@ void drop_graph(g1g2_ctx* c) {
     c->graph_steps = 0;
 }
 
-// Kernel arguments of a step do not depend on t unless a drive is active, so
-// a captured sequence of steps can be replayed for any t.
+// Kernel arguments of a step do not depend on t unless a drive or a switching
+// ramp is set, so a captured sequence of steps can be replayed for any t.
 bool can_capture(const g1g2_ctx* c) {
     return c->graphs && c->stream != nullptr && !c->prof &&
-           !(c->d.basis == G1G2_HUBBARD && c->hub.has_drive());
+           !(c->d.basis == G1G2_HUBBARD && (c->hub.has_drive() || c->hub.has_switch()));
 }
 
 g1g2_status capture(g1g2_ctx* c, double dt, int gsteps) {
@@ -408,6 +408,16 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
     H.drive_x.assign(x, x + c->d.nb);
     H.drive_tau = tau;
     HIP_OK(c, hipMemcpy(H.xdrv, x, c->d.nb * sizeof(double), hipMemcpyHostToDevice));
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_set_switch(g1g2_ctx* c, double t_on, double tau) {
+    if (!c || !std::isfinite(t_on) || !std::isfinite(tau) || tau < 0.0) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    c->hub.switch_t_on = t_on;
+    c->hub.switch_tau = tau;
     return G1G2_OK;
 }
 

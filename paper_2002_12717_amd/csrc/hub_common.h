@@ -6,7 +6,7 @@ namespace hub {
 
 struct Cl {
     int ns, zmax;
-    double U, s_drive;
+    double U, s_drive;   // U of the cluster at the stage time (switching applied)
     const int* __restrict__ nbr;    // [2][ns][zmax]
     const cd* __restrict__ hop;     // [2][ns][zmax]
     const double* __restrict__ d0;  // [2][ns]
@@ -17,11 +17,11 @@ struct Cl {
 
 __device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, const cd* hop,
                                       const double* d0, const double* xdrv, const cd* g1,
-                                      double s_drive) {
+                                      double s_drive, double u_scale) {
     Cl a;
     a.ns = d.ns;
     a.zmax = d.zmax;
-    a.U = d.U;
+    a.U = d.U * u_scale;
     a.s_drive = s_drive;
     a.nbr = nbr + d.nbroff;
     a.hop = hop + d.nbroff;

@@ -153,6 +153,7 @@ struct StageArgs {
     const double* __restrict__ d0;
     const double* __restrict__ xdrv;
     double s_drive;
+    double u_scale;   // switching factor phi(t) of the stage
     const cd* in1;
     const cd* in2;
     const cd* y1;
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
     using TO = typename StageTypes<MODE, MIXED>::Out;
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
-    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive, s.u_scale);
     const int ns = d.ns;
     const TI* A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     if (w.start >= 0) {
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
     __shared__ cd shp[2 * NS_MAX_ROW * ZR];
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
-    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive, s.u_scale);
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
     const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     const int tid = threadIdx.x;
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     __shared__ cd DK[TPP ? SLICE_DIAG : 1];    // TPP: DK[slice][p] = A_pp,ij
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
-    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive);
+    const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive, s.u_scale);
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
     const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
     const int tid = threadIdx.x;
@@ -751,6 +752,7 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.d0 = H.d0;
     s.xdrv = H.xdrv;
     s.s_drive = H.drive_value(t);
+    s.u_scale = H.switch_value(t);
     s.in1 = in.g1;
     s.in2 = in.g2;
     s.y1 = y.g1;
@@ -825,13 +827,13 @@ __global__ __launch_bounds__(256) void hub_obs_kernel(const ClusterDesc* __restr
                                                      const cd* __restrict__ hop,
                                                      const double* __restrict__ d0,
                                                      const double* __restrict__ xdrv, double s_drive,
-                                                     const cd* __restrict__ g1,
+                                                     double u_scale, const cd* __restrict__ g1,
                                                      const cd* __restrict__ g2,
                                                      double* __restrict__ res) {
     constexpr int NV = 7;
     __shared__ double sh[NV][256];
     const ClusterDesc d = desc[blockIdx.x];
-    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, s_drive);
+    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, s_drive, u_scale);
     const cd* A = g2 + d.g2off;
     const int ns = a.ns, z = a.zmax, tid = threadIdx.x;
     double nu = 0, nd = 0, ekin = 0, emf = 0, ecorr = 0, docc = 0, imb = 0;
@@ -907,7 +909,7 @@ __global__ void hub_site_kernel(const ClusterDesc* __restrict__ desc, const int*
                                 const double* __restrict__ xdrv, const cd* __restrict__ g1,
                                 const cd* __restrict__ g2, double* __restrict__ out) {
     const ClusterDesc d = desc[0];
-    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, 0.0);
+    const Cl a = make_cl(d, nbr, hop, d0, xdrv, g1, 0.0, 1.0);   // U is not used
     const cd* A = g2 + d.g2off;
     const int ns = a.ns;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
@@ -929,6 +931,15 @@ g1g2_status upload(g1g2_ctx* c, V** dst, const std::vector<V>& h) {
 }
 
 }  // namespace
+
+double HubbardData::switch_value(double t) const {
+    if (switch_tau <= 0.0) return 1.0;
+    const double x = (t - switch_t_on) / switch_tau;
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    const double s = std::sin(0.5 * M_PI * x);
+    return s * s;
+}
 
 double HubbardData::drive_value(double t) const {
     double s = 0.0;
@@ -1178,7 +1189,7 @@ g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs
     double* res = nullptr;
     HIP_OK(c, hipMalloc((void**)&res, (size_t)n * 8 * sizeof(double)));
     hipLaunchKernelGGL(hub_obs_kernel, dim3(n), dim3(256), 0, c->stream, H.desc, H.nbr, H.hop, H.d0,
-                       H.xdrv, H.drive_value(t), s.g1, s.g2, res);
+                       H.xdrv, H.drive_value(t), H.switch_value(t), s.g1, s.g2, res);
     hipError_t e1 = hipGetLastError();
     std::vector<double> h((size_t)n * 8);
     hipError_t e2 = hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost,

@@ -114,13 +114,15 @@ def test_hubbard_gw_rhs_parity(lib, kind, kern, se):
     p.close()
 
 
-def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol, flags=0):
+def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol, flags=0, switch=None):
     from paper_2002_12717_amd import binding as B
     p = B.Propagator(B.HUBBARD, _se(se), system.ns, system.h0, system.g1,
                      U=system.U, flags=flags)
     if system.drive is not None:
         d = system.drive
         p.set_drive(d.x, d.c, d.t_center, d.tau)
+    if switch is not None:
+        p.set_switch(*switch)
     y = OI.hubbard_initial(system, se)
     t = 0.0
     o0 = p.observables()
@@ -129,7 +131,7 @@ def _compare_hubbard_trajectory(system, se, chunks, chunk_steps, tol, flags=0):
     for ch in range(chunks):
         p.step(system.dt, chunk_steps)
         y, rec = OI.propagate_hubbard(system, nsteps=chunk_steps, selfenergy=se, state=y, t0=t,
-                                      observables_every=chunk_steps)
+                                      observables_every=chunk_steps, switch=switch)
         t += chunk_steps * system.dt
         g1, g2, tg = p.get_state()
         ref = np.stack([y[0].numpy(), y[1].numpy()])
@@ -169,6 +171,16 @@ def test_hubbard_ladder_cluster_trajectory(lib, se, kern):
     say(f"[hubbard trajectory] cluster {s.meta} {se} {kern} kernel 200 steps")
     flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
     _compare_hubbard_trajectory(s, se, 4, 50, 1e-10, flags)
+
+
+@pytest.mark.parametrize("se", ["soa", "gw", "dsl"])
+def test_hubbard_switching_trajectory(lib, se):
+    """Adiabatic switching (Sec. III.F): the 6-site chain from the ground state
+    of h0, U ramped from 0 to 2 over t in [0.5, 2.5]; G1 and the energy at
+    U(t) against the oracle over 150 steps, through and past the ramp."""
+    s = hubbard_chain_system(ns=6, U=2.0, confinement=0.0, dt=0.02)
+    say(f"[hubbard trajectory] chain6 {se} with switching, 150 steps")
+    _compare_hubbard_trajectory(s, se, 3, 50, 1e-10, switch=(0.5, 2.0))
 
 
 @pytest.mark.parametrize("kern", ["row", "slice"])
@@ -398,6 +410,21 @@ def test_abi_errors(lib):
         with pytest.raises(B.G1G2Error) as e:
             B.Batch(se, [6, 4], [1.0, 1.0], [hs, s.h0], [gs, s.g1])
         assert e.value.status == B.EUNSUPPORTED
+    p = B.Propagator(B.HUBBARD, B.SOA, 4, s.h0, s.g1, U=1.0)
+    with pytest.raises(B.G1G2Error) as e:
+        p.set_switch(0.0, -1.0)
+    assert e.value.status == B.EINVAL
+    p.set_switch(0.0, 1.0)
+    with pytest.raises(B.G1G2Error) as e:   # the adjoint assumes a constant U
+        p.forward_checkpointed(0.01, 10)
+    assert e.value.status == B.EUNSUPPORTED
+    p.close()
+    g = general_system(nb=6, rank=4, nocc=2)
+    pg = B.Propagator(B.GENERAL, B.SOA, g.nb, g.h0, g.g1, w=g.w)
+    with pytest.raises(B.G1G2Error) as e:
+        pg.set_switch(0.0, 1.0)
+    assert e.value.status == B.EUNSUPPORTED
+    pg.close()
     with pytest.raises(B.G1G2Error) as e:   # the general basis stops at nb = 64
         B.Propagator(B.GENERAL, B.SOA, 65, np.eye(65), np.zeros((65, 65)), w=np.zeros((1, 1, 1, 1)))
     assert e.value.status in (B.EUNSUPPORTED, B.EINVAL)
@@ -518,6 +545,33 @@ def test_hubbard_ragged_batch_parity(lib, se, kernel, prec):
     assert worst < (1e-10 if prec == "fp64" else 1e-5)
     if prec == "mixed":
         assert worst > 1e-12            # the binary32 stage copies are in use
+    b.close()
+
+
+def test_hubbard_batch_switching(lib):
+    """A ragged TPP batch with the interaction switched on (every cluster's U
+    ramped at the same stage times) against the oracle's single-cluster runs."""
+    from paper_2002_12717_amd import binding as B
+    from workloads import batched_clusters
+    cl = batched_clusters(n=5)
+    sw = (0.1, 0.3)
+    say(f"[batch] TPP with switching {sw}, sizes {[c.ns for c in cl]}")
+    stream = torch.cuda.Stream()
+    b = B.Batch(B.TPP, [c.ns for c in cl], [c.U for c in cl], [c.h0 for c in cl], [c.g1 for c in cl],
+                stream=stream.cuda_stream, flags=B.HUB_SLICE_KERNEL)
+    b.set_switch(*sw)
+    nst = 24
+    b.step(cl[0].dt, nst)
+    obs = b.observables()
+    worst = 0.0
+    for q, c in enumerate(cl):
+        y, rec = OI.propagate_hubbard(c, nsteps=nst, selfenergy="tpp", observables_every=nst, switch=sw)
+        g1, g2 = b.get_cluster(q)
+        e = max(rel(g1, np.stack([y[0].numpy(), y[1].numpy()])), rel(g2, y[2].numpy()))
+        e_e = abs(obs[q]["E_tot"] - rec[-1]["E_tot"]) / max(1.0, abs(rec[0]["E_tot"]))
+        worst = max(worst, e, e_e)
+    say(f"   worst rel err {worst:.2e}")
+    assert worst < 1e-10
     b.close()
 
 
