@@ -175,7 +175,7 @@ g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const doub
 /* Hubbard (single clusters and batches): adiabatic switching of the
  * interaction, the preparation of a correlated initial state by turning the
  * interaction on slowly from an uncorrelated start (Sec. III.F and the
- * outlook of Sec. IX).  Every cluster's U becomes U(t) = U phi(t) with
+ * outlook of Sec. VIII).  Every cluster's U becomes U(t) = U phi(t) with
  *   phi = 0 for t <= t_on, sin^2(pi x / 2) with x = (t - t_on) / tau during
  *   the ramp, and 1 for t >= t_on + tau,
  * evaluated at every Runge-Kutta stage time; the observables use U(t) at the

@@ -78,7 +78,7 @@ def propagate_general(system, nsteps=None, selfenergy="soa", g2_0=None, record=N
 # --------------------------------------------------------------------------- Hubbard
 def switch_factor(t, switch=None):
     """Adiabatic switching of the interaction, one way to prepare a correlated
-    initial state (Sec. III.F, Sec. IX): the interaction is turned on slowly
+    initial state (Sec. III.F, Sec. VIII): the interaction is turned on slowly
     from an uncorrelated start.  switch = (t_on, tau): U(t) = U phi(t) with
     phi = 0 before t_on, sin^2(pi x / 2), x = (t - t_on) / tau, during the
     ramp and 1 after it; None: phi = 1."""
