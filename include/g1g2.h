@@ -172,17 +172,17 @@ g1g2_status g1g2_set_U(g1g2_ctx* ctx, double U);
 g1g2_status g1g2_set_drive(g1g2_ctx* ctx, const double* x, int32_t M, const double* c,
                            const double* t_center, double tau);
 
-/* Hubbard (single clusters and batches): adiabatic switching of the
- * interaction, the preparation of a correlated initial state by turning the
- * interaction on slowly from an uncorrelated start (Sec. III.F and the
- * outlook of Sec. VIII).  Every cluster's U becomes U(t) = U phi(t) with
+/* Adiabatic switching of the interaction (both bases, single clusters and
+ * Hubbard batches): the preparation of a correlated initial state by turning
+ * the interaction on slowly from an uncorrelated start (Sec. III.F and the
+ * outlook of Sec. VIII).  The interaction becomes U(t) = U phi(t) (every
+ * cluster) or w(t) = w phi(t) (general basis) with
  *   phi = 0 for t <= t_on, sin^2(pi x / 2) with x = (t - t_on) / tau during
  *   the ramp, and 1 for t >= t_on + tau,
  * evaluated at every Runge-Kutta stage time; the observables use U(t) at the
  * state's time.  tau = 0 switches it off (U constant).  Steps are not
  * graph-captured while a ramp is set, and the adjoint refuses it (its
- * gradient assumes a constant U).  EINVAL for tau < 0 or non-finite values,
- * EUNSUPPORTED for the general basis.                                       */
+ * gradient assumes a constant U).  EINVAL for tau < 0 or non-finite values. */
 g1g2_status g1g2_set_switch(g1g2_ctx* ctx, double t_on, double tau);
 
 /* Ragged batch of independent Hubbard clusters (configurations of uneven

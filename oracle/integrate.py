@@ -32,15 +32,17 @@ def _t(x):
 
 
 # --------------------------------------------------------------------------- general basis
-def general_rhs_fn(h0, w, selfenergy="soa", kick=None, kick_until=None):
-    """f(t, (G1, G2)) for a general-basis system; ``kick`` is added to h0 for t < kick_until."""
+def general_rhs_fn(h0, w, selfenergy="soa", kick=None, kick_until=None, switch=None):
+    """f(t, (G1, G2)) for a general-basis system; ``kick`` is added to h0 for t < kick_until;
+    ``switch`` = (t_on, tau) ramps the interaction, w(t) = w phi(t) (see switch_factor)."""
     h0 = _t(h0)
     w = _t(w)
     hk = None if kick is None else h0 + _t(kick)
 
     def f(t, y):
         h = hk if (hk is not None and t < kick_until) else h0
-        return general.rhs(h, w, y[0], y[1], selfenergy)
+        wt = w if switch is None else w * switch_factor(t, switch)
+        return general.rhs(h, wt, y[0], y[1], selfenergy)
 
     return f
 

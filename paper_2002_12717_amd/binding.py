@@ -196,7 +196,7 @@ class Propagator:
                                              float(tau)))
 
     def set_switch(self, t_on: float, tau: float):
-        """Adiabatic switching U(t) = U phi(t), a sin^2 ramp from t_on over tau (0: off)."""
+        """Adiabatic switching U(t) = U phi(t) or w(t) = w phi(t), a sin^2 ramp from t_on over tau (0: off)."""
         self._check(self.lib.g1g2_set_switch(self.ctx, float(t_on), float(tau)))
 
     def forward_checkpointed(self, dt: float, nsteps: int, interval: int = 0):

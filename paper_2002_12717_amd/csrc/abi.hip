@@ -132,7 +132,7 @@ void drop_graph(g1g2_ctx* c) {
 // ramp is set, so a captured sequence of steps can be replayed for any t.
 bool can_capture(const g1g2_ctx* c) {
     return c->graphs && c->stream != nullptr && !c->prof &&
-           !(c->d.basis == G1G2_HUBBARD && (c->hub.has_drive() || c->hub.has_switch()));
+           !c->has_switch() && !(c->d.basis == G1G2_HUBBARD && c->hub.has_drive());
 }
 
 g1g2_status capture(g1g2_ctx* c, double dt, int gsteps) {
@@ -413,12 +413,20 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
 
 g1g2_status g1g2_set_switch(g1g2_ctx* c, double t_on, double tau) {
     if (!c || !std::isfinite(t_on) || !std::isfinite(tau) || tau < 0.0) return G1G2_EINVAL;
-    if (c->d.basis != G1G2_HUBBARD) return set_error(c, G1G2_EUNSUPPORTED, "Hubbard basis only");
     HIP_OK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
-    c->hub.switch_t_on = t_on;
-    c->hub.switch_tau = tau;
+    c->switch_t_on = t_on;
+    c->switch_tau = tau;
     return G1G2_OK;
+}
+
+double g1g2_ctx::switch_value(double t) const {
+    if (switch_tau <= 0.0) return 1.0;
+    const double x = (t - switch_t_on) / switch_tau;
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    const double s = std::sin(0.5 * M_PI * x);
+    return s * s;
 }
 
 g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const int32_t* ns,

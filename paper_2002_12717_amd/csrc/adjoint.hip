@@ -600,7 +600,7 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     if (c->hub.hdesc[0].ns > 64) return set_error(c, G1G2_EUNSUPPORTED, "adjoint supports ns <= 64");
     if (c->d.precision != G1G2_FP64)
         return set_error(c, G1G2_EUNSUPPORTED, "the adjoint runs in binary64 only");
-    if (c->hub.has_switch())
+    if (c->has_switch())
         return set_error(c, G1G2_EUNSUPPORTED, "the adjoint takes a constant U (switching is set)");
     adj_free(c);
     AdjState* st = new AdjState();

@@ -61,11 +61,6 @@ struct HubbardData {
     double drive_tau = 1.0;
     double drive_value(double t) const;
     bool has_drive() const { return !drive_c.empty(); }
-    // adiabatic switching: U(t) = U phi(t), phi a sin^2 ramp from 0 at
-    // switch_t_on to 1 at switch_t_on + switch_tau; switch_tau = 0: off
-    double switch_t_on = 0.0, switch_tau = 0.0;
-    double switch_value(double t) const;
-    bool has_switch() const { return switch_tau > 0.0; }
 };
 
 // General basis: internal tensors are padded to nbp = roundup(nb, 16) so that
@@ -112,6 +107,11 @@ struct g1g2_ctx {
     int nscratch = 0;
     HubbardData hub;
     GeneralData gen;
+    // adiabatic switching of the interaction (U or w) by phi(t), a sin^2 ramp
+    // from 0 at switch_t_on to 1 at switch_t_on + switch_tau; switch_tau = 0: off
+    double switch_t_on = 0.0, switch_tau = 0.0;
+    double switch_value(double t) const;
+    bool has_switch() const { return switch_tau > 0.0; }
     void* adj = nullptr;       // adjoint state (adjoint.hip)
     // captured RK4 steps (replayed by g1g2_step_rk4 when the stream is not NULL)
     hipGraphExec_t graph = nullptr;

@@ -98,6 +98,7 @@ struct HfArgs {
     cd* hhf;
     cd* gg;          // G^>
     int nbp, nb;
+    double ws;       // switching factor phi(t) of the interaction (1 without a ramp)
 };
 
 // Row (ij) of h^HF by one work-group of THREADS threads.
@@ -140,7 +141,7 @@ __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
     }
     const cd h = a.h0[ij];
     // h0 - i (sr + i si) = h0 + si - i sr
-    a.hhf[ij] = make_double2(h.x + si, h.y - sr);
+    a.hhf[ij] = make_double2(h.x + a.ws * si, h.y - a.ws * sr);
     const int i = ij / nbp, j = ij % nbp;
     const cd g = a.gl[ij];
     a.gg[ij] = (i == j && i < a.nb) ? make_double2(g.x, g.y - 1.0) : g;
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re(r4), acc.im(r4));
+                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, hf.ws * acc.re(r4), hf.ws * acc.im(r4));
             }
             __syncthreads();
         }
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __r
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, acc.re(r4), acc.im(r4));
+                stc(vt + (size_t)(row * NB + col) * NB * NB + blk, hf.ws * acc.re(r4), hf.ws * acc.im(r4));
             }
         }
         __syncthreads();
@@ -278,7 +279,7 @@ template <typename T, typename S, int NB>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
     const cd* __restrict__ g2, const S* __restrict__ vt, const S* __restrict__ wcoll,
     const cd* __restrict__ gg, const cd* __restrict__ hhf, S* __restrict__ dout,
-    cd* __restrict__ ipart) {
+    cd* __restrict__ ipart, double ws) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
     using Acc = typename std::conditional<SH::TPW == 1, CAcc4<T>, CAcc<T>>::type;
@@ -433,7 +434,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
             int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-            ipart[(size_t)(row * NB + col) * gridDim.x + bfirst] = make_double2(isum[t][0][r4], isum[t][1][r4]);
+            ipart[(size_t)(row * NB + col) * gridDim.x + bfirst] =
+                make_double2(ws * isum[t][0][r4], ws * isum[t][1][r4]);
         }
     }
 }
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
 template <typename T, typename S, int NB>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* __restrict__ wgw,
                                                                      const cd* __restrict__ gl,
-                                                                     S* __restrict__ heps) {
+                                                                     S* __restrict__ heps, double ws) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
     __shared__ T m_re[NB * LD], m_im[NB * LD];
@@ -606,8 +608,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* _
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
                 // i * acc
-                stc(heps + (size_t)blk * NB * NB + row * NB + col, -(double)acc.im(r4),
-                    (double)acc.re(r4));
+                stc(heps + (size_t)blk * NB * NB + row * NB + col, -ws * (double)acc.im(r4),
+                    ws * (double)acc.re(r4));
             }
         }
         __syncthreads();
@@ -629,7 +631,7 @@ template <typename T, typename S, int NB, int KIND>
 __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_hlad_kernel(const S* __restrict__ wl,
                                                                      const cd* __restrict__ gl,
                                                                      const cd* __restrict__ gg,
-                                                                     S* __restrict__ out) {
+                                                                     S* __restrict__ out, double ws) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
     __shared__ T m_re[NB * LD], m_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_hlad_kernel(const S* _
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(out + (size_t)(row * NB + col) * NB * NB + blk, acc[t].re(r4), acc[t].im(r4));
+                stc(out + (size_t)(row * NB + col) * NB * NB + blk, ws * acc[t].re(r4), ws * acc[t].im(r4));
             }
         }
     }
@@ -921,8 +923,10 @@ __global__ __launch_bounds__(256) void herm_kernel(const cd* __restrict__ A, int
 // --------------------------------------------------------------------------- host side
 int main_grid(int nbp) { return std::min(nbp * nbp, 512); }
 
+// ws: the switching factor phi(t) of the stage; every w-dependent output
+// (sandwich, h^HF, collision partials, quasi-Hamiltonians) is linear in w
 template <typename T, typename S, int NB>
-g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
+g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     GeneralData& g = c->gen;
     const bool mixed = sizeof(T) == 4;
     const S* wrows = mixed ? (const S*)g.wm_rows32 : (const S*)g.wm_rows;
@@ -930,7 +934,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
     // a single-tile-per-wave shape prefetches the next row block in registers and
     // wants several blocks per work-group; the larger shapes want the wider grid
     const int grid_vt = std::min(NB * NB, Shape<NB>::TPW == 1 ? 512 : 1024);
-    const HfArgs hf{g.w_hf, g.h0, in.g1, g.hhf, g.gg, g.nbp, g.nb};
+    const HfArgs hf{g.w_hf, g.h0, in.g1, g.hhf, g.gg, g.nbp, g.nb, ws};
     hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt + NB * NB), dim3(Shape<NB>::THREADS), 0,
                        c->stream, wrows, in.g1, (S*)g.vt, grid_vt, hf);
     HIP_OK(c, hipGetLastError());
@@ -940,7 +944,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
     if (se == G1G2_GW || se == G1G2_DSL) {
         const S* wgw = mixed ? (const S*)g.w_gw32 : (const S*)g.w_gw;
         hipLaunchKernelGGL((gen_heps_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
-                           c->stream, wgw, in.g1, (S*)g.heps);
+                           c->stream, wgw, in.g1, (S*)g.heps, ws);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_heps");
         hipLaunchKernelGGL((gen_bmat_kernel<S, 0>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
@@ -953,7 +957,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
         prof_mark(c, "gen_gemm");
     }
     hipLaunchKernelGGL((gen_main_kernel<T, S, NB>), dim3(g.nipart), dim3(Shape<NB>::THREADS), 0,
-                       c->stream, in.g2, (const S*)g.vt, wcoll, g.gg, g.hhf, (S*)g.dmat, g.ipart);
+                       c->stream, in.g2, (const S*)g.vt, wcoll, g.gg, g.hhf, (S*)g.dmat, g.ipart, ws);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_main");
     // T-matrix ladders: D += Lambda, so that the combine forms Lambda - Lambda^dagger,
@@ -961,7 +965,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
     if (se == G1G2_TPP || se == G1G2_DSL) {
         const S* wpp = mixed ? (const S*)g.w_pp32 : (const S*)g.w_pp;
         hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 0>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
-                           c->stream, wpp, in.g1, g.gg, (S*)g.heps);
+                           c->stream, wpp, in.g1, g.gg, (S*)g.heps, ws);
         hipLaunchKernelGGL((gen_bmat_kernel<S, 1>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
                            NB);
         HIP_OK(c, hipGetLastError());
@@ -974,7 +978,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in) {
     if (se == G1G2_TPH || se == G1G2_DSL) {
         const S* wph = mixed ? (const S*)g.w_ph32 : (const S*)g.w_ph;
         hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 1>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
-                           c->stream, wph, in.g1, g.gg, (S*)g.heps);
+                           c->stream, wph, in.g1, g.gg, (S*)g.heps, ws);
         hipLaunchKernelGGL((gen_bmat_kernel<S, 2>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
                            NB);
         HIP_OK(c, hipGetLastError());
@@ -1007,12 +1011,12 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
 }
 
 template <typename T, typename S>
-g1g2_status dispatch_blocks(g1g2_ctx* c, const Regs& in) {
+g1g2_status dispatch_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     switch (c->gen.nbp) {
-        case 16: return run_blocks<T, S, 16>(c, in);
-        case 32: return run_blocks<T, S, 32>(c, in);
-        case 48: return run_blocks<T, S, 48>(c, in);
-        case 64: return run_blocks<T, S, 64>(c, in);
+        case 16: return run_blocks<T, S, 16>(c, in, ws);
+        case 32: return run_blocks<T, S, 32>(c, in, ws);
+        case 48: return run_blocks<T, S, 48>(c, in, ws);
+        case 64: return run_blocks<T, S, 64>(c, in, ws);
         default: return set_error(c, G1G2_EUNSUPPORTED, "general basis supports nb <= 64");
     }
 }
@@ -1156,13 +1160,13 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
 
 g1g2_status gen_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc) {
-    (void)t;
+    const double ws = c->switch_value(t);
     g1g2_status s;
     if (c->d.precision == G1G2_MIXED) {
-        if ((s = dispatch_blocks<float, float2>(c, in)) != G1G2_OK) return s;
+        if ((s = dispatch_blocks<float, float2>(c, in, ws)) != G1G2_OK) return s;
         return dispatch_combine<float2>(c, mode, in, y, acc, out, cb, cc);
     }
-    if ((s = dispatch_blocks<double, cd>(c, in)) != G1G2_OK) return s;
+    if ((s = dispatch_blocks<double, cd>(c, in, ws)) != G1G2_OK) return s;
     return dispatch_combine<cd>(c, mode, in, y, acc, out, cb, cc);
 }
 

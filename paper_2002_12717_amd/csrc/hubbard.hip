@@ -752,7 +752,7 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.d0 = H.d0;
     s.xdrv = H.xdrv;
     s.s_drive = H.drive_value(t);
-    s.u_scale = H.switch_value(t);
+    s.u_scale = c->switch_value(t);
     s.in1 = in.g1;
     s.in2 = in.g2;
     s.y1 = y.g1;
@@ -931,15 +931,6 @@ g1g2_status upload(g1g2_ctx* c, V** dst, const std::vector<V>& h) {
 }
 
 }  // namespace
-
-double HubbardData::switch_value(double t) const {
-    if (switch_tau <= 0.0) return 1.0;
-    const double x = (t - switch_t_on) / switch_tau;
-    if (x <= 0.0) return 0.0;
-    if (x >= 1.0) return 1.0;
-    const double s = std::sin(0.5 * M_PI * x);
-    return s * s;
-}
 
 double HubbardData::drive_value(double t) const {
     double s = 0.0;
@@ -1189,7 +1180,7 @@ g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs
     double* res = nullptr;
     HIP_OK(c, hipMalloc((void**)&res, (size_t)n * 8 * sizeof(double)));
     hipLaunchKernelGGL(hub_obs_kernel, dim3(n), dim3(256), 0, c->stream, H.desc, H.nbr, H.hop, H.d0,
-                       H.xdrv, H.drive_value(t), H.switch_value(t), s.g1, s.g2, res);
+                       H.xdrv, H.drive_value(t), c->switch_value(t), s.g1, s.g2, res);
     hipError_t e1 = hipGetLastError();
     std::vector<double> h((size_t)n * 8);
     hipError_t e2 = hipMemcpyAsync(h.data(), res, h.size() * sizeof(double), hipMemcpyDeviceToHost,

@@ -231,12 +231,14 @@ def test_general_rhs_parity(lib, nb, se, prec):
     p.close()
 
 
-def _compare_general_trajectory(system, se, chunks, chunk_steps, prec, tol):
+def _compare_general_trajectory(system, se, chunks, chunk_steps, prec, tol, switch=None):
     from paper_2002_12717_amd import binding as B
     code, flags = _gen_se(se)
     p = B.Propagator(B.GENERAL, code, system.nb, system.h0, system.g1, w=system.w,
                      precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
-    f = OI.general_rhs_fn(system.h0, system.w, se)
+    if switch is not None:
+        p.set_switch(*switch)
+    f = OI.general_rhs_fn(system.h0, system.w, se, switch=switch)
     g1, g2 = T(system.g1), torch.zeros((system.nb,) * 4, dtype=torch.complex128)
     t = 0.0
     errs = []
@@ -374,6 +376,16 @@ def test_general_dsl_four_site_chain_vs_ed(lib):
     assert errs.max() > 2 * errs[:30].max()
 
 
+@pytest.mark.parametrize("nb,se,prec", [(12, "soa", "fp64"), (12, "dsl", "mixed"), (20, "gw", "fp64")])
+def test_general_switching_trajectory(lib, nb, se, prec):
+    """Adiabatic switching in the general basis, w(t) = w phi(t) ramped over
+    t in [0.1, 0.5] from the uncorrelated ground state of h: the trajectory
+    through and past the ramp against the oracle (nb = 20 pads to 32)."""
+    s = general_system(nb=nb, rank=10, nocc=4, dt=0.01, key=17)   # G^< = Aufbau state of h
+    say(f"[general trajectory] nb={nb} {se} {prec} with switching, 60 steps")
+    _compare_general_trajectory(s, se, 3, 20, prec, 1e-10 if prec == "fp64" else 1e-5, switch=(0.1, 0.4))
+
+
 def test_general_soa_invariants_full_size(lib):
     """Nb=32 molecule, 400 steps: particle number and Hermiticity of G2 exact,
     energy drift at the level of the RK4 error."""
@@ -419,12 +431,6 @@ def test_abi_errors(lib):
         p.forward_checkpointed(0.01, 10)
     assert e.value.status == B.EUNSUPPORTED
     p.close()
-    g = general_system(nb=6, rank=4, nocc=2)
-    pg = B.Propagator(B.GENERAL, B.SOA, g.nb, g.h0, g.g1, w=g.w)
-    with pytest.raises(B.G1G2Error) as e:
-        pg.set_switch(0.0, 1.0)
-    assert e.value.status == B.EUNSUPPORTED
-    pg.close()
     with pytest.raises(B.G1G2Error) as e:   # the general basis stops at nb = 64
         B.Propagator(B.GENERAL, B.SOA, 65, np.eye(65), np.zeros((65, 65)), w=np.zeros((1, 1, 1, 1)))
     assert e.value.status in (B.EUNSUPPORTED, B.EINVAL)

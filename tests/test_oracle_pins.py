@@ -320,6 +320,35 @@ def test_switching_energy_balance(se):
     assert abs((E[-1] - E[0]) - work) < 1e-8 * abs(E[-1] - E[0])
 
 
+@pytest.mark.parametrize("se", ["soa", "gw", "dsl"])
+def test_switching_energy_balance_general(se):
+    """General basis with w(t) = w phi(t): the energy gained over the ramp
+    equals the integral of phi'(t) times the interaction energy at full w,
+    E_mf + E_corr of the unscaled w (Hellmann-Feynman; both are linear in w)."""
+    nb = 5
+    r = rng(15, nb)
+    h = gue(nb, r)
+    w = 0.5 * factorized_w(nb, 4, r)
+    sw, dt, n = (0.2, 1.0), 0.01, 150
+    f = I.general_rhs_fn(h, w, se, switch=sw)
+    y = (T(aufbau_gless(h, 2)), torch.zeros((nb,) * 4, dtype=torch.complex128))
+    E, Ei, t = [], [], 0.0
+    for k in range(n + 1):
+        o = O.general_observables(T(h), T(w) * I.switch_factor(t, sw), y[0], y[1])
+        o1 = O.general_observables(T(h), T(w), y[0], y[1])
+        E.append(o["E_tot"])
+        Ei.append(o1["E_mf"] + o1["E_corr"])
+        if k < n:
+            y = I.rk4_step(f, t, y, dt)
+            t = (k + 1) * dt
+    ts = dt * np.arange(n + 1)
+    x = np.clip((ts - sw[0]) / sw[1], 0.0, 1.0)
+    g = np.pi / (2.0 * sw[1]) * np.sin(np.pi * x) * np.array(Ei)
+    work = dt / 3.0 * (g[0] + g[-1] + 4.0 * g[1:-1:2].sum() + 2.0 * g[2:-1:2].sum())
+    assert abs(E[-1] - E[0]) > 0.1
+    assert abs((E[-1] - E[0]) - work) < 5e-8 * abs(E[-1] - E[0])
+
+
 def test_slow_switching_is_adiabatic():
     """Sec. III.F: a correlated state prepared by switching the interaction on
     slowly from the uncorrelated ground state of h0.  A slow ramp leaves the
