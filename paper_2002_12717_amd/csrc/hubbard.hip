@@ -1120,7 +1120,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         }
         g1work.push_back({cl, -1, -1});
         const int n3 = ns * ns * ns;
-        for (int t0 = 0; t0 < n3; t0 += 4096) dwork.push_back({cl, t0, std::min(n3, t0 + 4096)});
+        // diagonal gather items of 1024 index triples: its loads are strided, so it
+        // wants many work-groups in flight (256 for an 8x8 cluster)
+        for (int t0 = 0; t0 < n3; t0 += 1024) dwork.push_back({cl, t0, std::min(n3, t0 + 1024)});
         doff += n3;
         g2off += nch * n4;
         g1off += 2LL * ns * ns;
