@@ -111,7 +111,7 @@ def partner_klij(x: torch.Tensor) -> torch.Tensor:
     return x.permute(2, 3, 0, 1).conj()
 
 
-SELFENERGIES = ("soa", "gw", "gw_x", "tpp", "tph", "dsl")
+SELFENERGIES = ("soa", "gw", "gw_x", "tpp", "tph", "dsl", "dsl_x")
 
 
 def correlation_terms(selfenergy: str, w: torch.Tensor, gg: torch.Tensor, gl: torch.Tensor,
@@ -124,19 +124,25 @@ def correlation_terms(selfenergy: str, w: torch.Tensor, gg: torch.Tensor, gl: to
       tph : Psi^- + L^ph - [L^ph_klij]^*            (eq:g2-eq-tph-lambda)
       dsl : Psi^- + Pi - [Pi_lkji]^* + L - [L_klij]^*, L = L^pp + L^ph
                                                     (eq:g2-dsl-equation-pi-lambda)
+      dsl_x: dsl with w^- in place of w in h^eps and h^ph, the exchange
+             terms of the polarization and particle-hole channels; Sec. VI
+             equates DSL with neglecting three-particle correlations, and
+             only this form reaches that order in a general basis (for the
+             on-site Hubbard w the two coincide)
     """
     if selfenergy not in SELFENERGIES:
         raise ValueError(selfenergy)
     wm = w_minus(w)
+    wx = wm if selfenergy == "dsl_x" else w     # interaction of h^eps and h^ph
     s = source(w if selfenergy == "gw" else wm, gg, gl)
-    if selfenergy in ("gw", "gw_x", "dsl"):
-        pi = gw_polarization(gw_hcorr(w, gg, gl), g2)
+    if selfenergy in ("gw", "gw_x", "dsl", "dsl_x"):
+        pi = gw_polarization(gw_hcorr(wx, gg, gl), g2)
         s = s + pi - partner_lkji(pi)
     lam = None
-    if selfenergy in ("tpp", "dsl"):
+    if selfenergy in ("tpp", "dsl", "dsl_x"):
         lam = tpp_ladder(tpp_hcorr(w, gg, gl), g2)
-    if selfenergy in ("tph", "dsl"):
-        lph = tph_ladder(tph_hcorr(w, gg, gl), g2)
+    if selfenergy in ("tph", "dsl", "dsl_x"):
+        lph = tph_ladder(tph_hcorr(wx, gg, gl), g2)
         lam = lph if lam is None else lam + lph
     if lam is not None:
         s = s + lam - partner_klij(lam)
