@@ -127,8 +127,9 @@ def correlation_terms(selfenergy: str, w: torch.Tensor, gg: torch.Tensor, gl: to
       dsl_x: dsl with w^- in place of w in h^eps and h^ph, the exchange
              terms of the polarization and particle-hole channels; Sec. VI
              equates DSL with neglecting three-particle correlations, and
-             only this form reaches that order in a general basis (for the
-             on-site Hubbard w the two coincide)
+             in a general basis only this form reaches that order (with the
+             on-site Hubbard w both do; they differ there only in the
+             equal-spin and spin-flip channels)
     """
     if selfenergy not in SELFENERGIES:
         raise ValueError(selfenergy)

@@ -57,7 +57,7 @@ def test_hubbard_reformulations_match_direct_forms():
 
 
 # --------------------------------------------------------------------------- P1 cross-basis identity
-@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw", "dsl", "dsl_x"])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw", "dsl"])
 def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
     """The general-basis equations (Secs. III.C, IV.C, V.A, V.B, VI) with the
     Hubbard interaction of eq:wmatrix-hubbard in the spin-orbital basis
@@ -65,8 +65,7 @@ def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
     in which every spin block of G2 is populated.  The spin-flip blocks
     (up dn dn up, dn up up dn) are populated too and the Hubbard equations do
     not see them, so for gw and dsl this also shows that the three stored
-    channels form a closed system.  dsl_x (exchange in h^eps and h^ph) gives
-    the Hubbard DSL equations too: the on-site w has no exchange part there."""
+    channels form a closed system."""
     ns, U = 4, 0.7
     r = rng(12, ns)
     X, Y = T(random_gless(ns, r)), T(random_gless(ns, r))
@@ -79,8 +78,8 @@ def test_general_basis_with_hubbard_w_equals_hubbard_equations(se):
     B = _blk(g2, ns, 0, 0, 0, 0).clone()
     C = _blk(g2, ns, 1, 1, 1, 1).clone()
     dg1, dg2 = G.rhs(torch.block_diag(h0, h0), T(hubbard_spin_orbital_w(ns, U)), gl, g2, se)
-    if se in ("gw", "dsl", "dsl_x"):
-        dX, dY, dA, dB, dC = H.rhs(h0, h0, U, X, Y, A, se[:3] if se != "gw" else se, B=B, C=C)
+    if se in ("gw", "dsl"):
+        dX, dY, dA, dB, dC = H.rhs(h0, h0, U, X, Y, A, se, B=B, C=C)
         assert (_blk(dg2, ns, 0, 0, 0, 0) - dB).abs().max() < 1e-13
         assert (_blk(dg2, ns, 1, 1, 1, 1) - dC).abs().max() < 1e-13
     else:
