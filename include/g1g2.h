@@ -93,7 +93,15 @@ enum {
      * else the row kernel (one wave per G2 row).  Both need ns <= 64 and at
      * most 4 neighbours per site, else the per-element kernel runs. */
     G1G2_HUB_ROW_KERNEL = 4,    /* Hubbard: row kernel whatever the size          */
-    G1G2_HUB_SLICE_KERNEL = 8   /* Hubbard: slice kernel whatever the size        */
+    G1G2_HUB_SLICE_KERNEL = 8,  /* Hubbard: slice kernel whatever the size        */
+    /* General-basis DSL: build the polarization and particle-hole
+     * quasi-Hamiltonians (h^eps, h^ph) from w^- instead of w, i.e. with their
+     * exchange terms.  eq:g2-dsl-equation builds them from w; Sec. VI equates
+     * DSL with neglecting three-particle correlations, and against exact
+     * diagonalization only the exchange form reaches that order (density
+     * error O(w^4) instead of O(w^3)) in a general basis.  EUNSUPPORTED with
+     * any other basis or selfenergy. */
+    G1G2_DSL_EXCHANGE = 16
 };
 
 typedef struct {

@@ -19,7 +19,7 @@ LIBPATH = os.path.join(PKG, "libg1g2.so")
 GENERAL, HUBBARD = 0, 1
 SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
-PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL = 1, 2, 4, 8
+PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL, DSL_EXCHANGE = 1, 2, 4, 8, 16
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 
 

@@ -202,6 +202,8 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && d->nb > 64) return G1G2_EUNSUPPORTED;
+    if ((d->flags & G1G2_DSL_EXCHANGE) && !(d->basis == G1G2_GENERAL && d->selfenergy == G1G2_DSL))
+        return G1G2_EUNSUPPORTED;
     if (d->basis == G1G2_HUBBARD && (long long)d->nb * d->nb * d->nb * d->nb > (1LL << 30))
         return G1G2_EUNSUPPORTED;
     int ndev = 0;

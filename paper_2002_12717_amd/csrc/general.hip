@@ -1113,12 +1113,15 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
         if ((s = upload(c, &g.wm_rows32, to_f32(rows))) != G1G2_OK) return s;
         if ((s = upload(c, &g.w_coll32, to_f32(coll))) != G1G2_OK) return s;
     }
+    // DSL with its exchange terms: h^eps and h^ph from w^-_ijkl = w_ijkl - w_ijlk
+    const bool dslx = se == G1G2_DSL && (c->d.flags & G1G2_DSL_EXCHANGE);
+    auto WX = [&](int i, int j, int k, int l) -> cd { return dslx ? csub(W(i, j, k, l), W(i, j, l, k)) : W(i, j, k, l); };
     if (gw) {
         std::vector<cd> wg(n4, cmk(0, 0));
         for (int s1 = 0; s1 < nb; ++s1)
             for (int q = 0; q < nb; ++q)
                 for (int r = 0; r < nb; ++r)
-                    for (int p = 0; p < nb; ++p) wg[P4(p, q, s1, r)] = W(s1, q, r, p);  // M_pq[s][r] = w_sqrp
+                    for (int p = 0; p < nb; ++p) wg[P4(p, q, s1, r)] = WX(s1, q, r, p);  // M_pq[s][r] = w_sqrp
         if ((s = upload(c, &g.w_gw, wg)) != G1G2_OK) return s;
         if (mixed && (s = upload(c, &g.w_gw32, to_f32(wg))) != G1G2_OK) return s;
         HIP_OK(c, hipMalloc(&g.pimat, n4 * sizeof(cd)));
@@ -1137,7 +1140,7 @@ g1g2_status gen_setup(g1g2_ctx* c, const cd* h0, const cd* w) {
             for (int p = 0; p < nb; ++p)
                 for (int j = 0; j < nb; ++j)
                     for (int k = 0; k < nb; ++k)
-                        for (int q = 0; q < nb; ++q) wl[P4(j, k, p, q)] = W(p, j, k, q);   // M_pq = w_pjkq
+                        for (int q = 0; q < nb; ++q) wl[P4(j, k, p, q)] = WX(p, j, k, q);   // M_pq = w_pjkq
             if ((s = upload(c, &g.w_ph, wl)) != G1G2_OK) return s;
             if (mixed && (s = upload(c, &g.w_ph32, to_f32(wl))) != G1G2_OK) return s;
         }

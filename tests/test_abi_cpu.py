@@ -60,6 +60,8 @@ def test_init_rejects_bad_arguments_without_device(so_path):
     buf = (ctypes.c_double * 64)()
     d = binding.Desc(0, binding.SOA, 0, 0, 65, 0.0)  # the general basis stops at nb = 64
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, buf, buf, None, None) == binding.EUNSUPPORTED
+    d = binding.Desc(0, binding.SOA, 0, binding.DSL_EXCHANGE, 4, 0.0)   # a DSL-only flag
+    assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, buf, buf, None, None) == binding.EUNSUPPORTED
     d = binding.Desc(0, 5, 0, 0, 4, 0.0)             # no such selfenergy
     assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), buf, buf, buf, None, None) == binding.EINVAL
 

@@ -206,11 +206,11 @@ def _gen_se(se):
     """Library selfenergy code and flags of an oracle selfenergy name."""
     from paper_2002_12717_amd import binding as B
     return {"soa": (B.SOA, 0), "gw": (B.GW, 0), "gw_x": (B.GW, B.GW_EXCHANGE), "tpp": (B.TPP, 0),
-            "tph": (B.TPH, 0), "dsl": (B.DSL, 0)}[se]
+            "tph": (B.TPH, 0), "dsl": (B.DSL, 0), "dsl_x": (B.DSL, B.DSL_EXCHANGE)}[se]
 
 
 @pytest.mark.parametrize("nb", [6, 20, 32])
-@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph", "dsl"])
+@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph", "dsl", "dsl_x"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_general_rhs_parity(lib, nb, se, prec):
     from paper_2002_12717_amd import binding as B
@@ -263,7 +263,8 @@ def test_general_soa_trajectory_small(lib, prec):
     _compare_general_trajectory(s, "soa", 4, 25, prec, 1e-10 if prec == "fp64" else 1e-5)
 
 
-@pytest.mark.parametrize("se,prec", [("tpp", "fp64"), ("tph", "fp64"), ("dsl", "fp64"), ("dsl", "mixed")])
+@pytest.mark.parametrize("se,prec", [("tpp", "fp64"), ("tph", "fp64"), ("dsl", "fp64"), ("dsl", "mixed"),
+                                     ("dsl_x", "fp64")])
 def test_general_ladder_trajectory_small(lib, se, prec):
     """T-matrix and DSL closures in the general basis, 100 steps at nb=12.  The
     interaction is halved: at full strength the DSL closure of this random
@@ -431,6 +432,9 @@ def test_abi_errors(lib):
         p.forward_checkpointed(0.01, 10)
     assert e.value.status == B.EUNSUPPORTED
     p.close()
+    with pytest.raises(B.G1G2Error) as e:   # the exchange form of DSL is a general-basis option
+        B.Propagator(B.HUBBARD, B.DSL, 4, s.h0, s.g1, U=1.0, flags=B.DSL_EXCHANGE)
+    assert e.value.status == B.EUNSUPPORTED
     with pytest.raises(B.G1G2Error) as e:   # the general basis stops at nb = 64
         B.Propagator(B.GENERAL, B.SOA, 65, np.eye(65), np.zeros((65, 65)), w=np.zeros((1, 1, 1, 1)))
     assert e.value.status in (B.EUNSUPPORTED, B.EINVAL)
