@@ -27,7 +27,7 @@ struct ClusterDesc {
     int d0off;          // offset of its [2][ns] diagonal of h0
     int xoff;           // offset of its [ns] drive profile
     long long g2off;    // offset of its G2 block in a G2 register
-    long long doff;     // TPH: offset (in units of ns^3 pairs) of its diagonal tensors
+    long long doff;     // TPH, GW, DSL: offset (in units of ns^3 pairs) of its diagonal tensors
     double U;
 };
 
@@ -47,10 +47,10 @@ struct HubbardData {
     int nwork = 0;
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
     bool realhop = false;          // every hopping (off-diagonal h0) is real
-    bool slices = false;           // slice stage kernel (SOA, TPP, TPH on row-kernel clusters)
-    WorkItem* dwork = nullptr;     // TPH: work list of the diagonal gather
+    bool slices = false;           // slice stage kernel (every selfenergy, on row-kernel clusters)
+    WorkItem* dwork = nullptr;     // TPH, GW, DSL: work list of the diagonal gather
     int ndwork = 0;
-    cd* diag = nullptr;            // TPH: per cluster R [ns]^3 and S [ns]^3
+    cd* diag = nullptr;            // per cluster n_diag [ns]^3 gathered diagonal tensors
     std::vector<int> chunk;        // elements of G2 per work-group, per cluster
     int* nbr = nullptr;            // concatenated neighbour tables
     cd* hop = nullptr;

@@ -1,15 +1,15 @@
 // Hubbard-basis G1-G2 kernels (Sec. III.D, Sec. V.A, Sec. VII).
 //
 // State per cluster: G1 = [X | Y] with X = G^{<,up}, Y = G^{<,down} (ns x ns
-// each) and G2 = A = G2^{up down up down} ([ns]^4; GW adds the equal-spin
-// channels B and C).  Every G2 element is produced from a fixed number of
+// each) and G2 = A = G2^{up down up down} ([ns]^4; GW and DSL add the
+// equal-spin channels B and C).  Every G2 element is produced from a fixed number of
 // neighbours, so a stage is a bandwidth-bound stream: the O(ns^5) sums of the
 // direct formulation are replaced by the paper's reformulations that carry no
 // inner sum (eq:soa-cubic-scheme for the source, the sparse-h commutator of
 // Sec. VII.A, the reformulated ladders of Sec. VII.C, the polarization of
 // Sec. VII.B).  Three stage kernels compute the same right-hand side: the
 // slice kernel (whole (i,j) slices staged in LDS), the row kernel (one wave
-// per G2 row) and the per-element kernel (any lattice).
+// per G2 row) and the per-element kernel (any lattice; not GW or DSL).
 //
 // A context holds a ragged batch of clusters.  One launch per Runge-Kutta
 // stage processes a flat work list: every item is either a range of one
@@ -164,7 +164,7 @@ struct StageArgs {
     cd* out2;
     double cb, cc;
     int* flag;
-    const cd* diag;   // TPH: per cluster R [ns]^3 then S [ns]^3 of the stage input
+    const cd* diag;   // per cluster: GW's six [ns]^3 layouts, then TPH's R and S (hub_diag_kernel)
 };
 
 // Storage of the G2 stage registers.  Mixed precision keeps the stage copies
