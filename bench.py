@@ -329,6 +329,60 @@ def cpu_baseline_batch(clusters, seconds: float = 15.0, selfenergy: str = "tpp")
                       f"extrapolated to the whole batch by G2 element count"}
 
 
+def run_scaling(args, torch, B):
+    """Cost of an RK4 step against the basis size, fitted as a power law, next
+    to the paper's scalings (Sec. VII, Tab. I): general basis SOA ~ Nb^5, GW
+    ~ Nb^6; Hubbard basis ~ Ns^4 after the reformulations; and cost linear in
+    the number of steps.  Timing only (graph-replayed steps, binary64)."""
+    import numpy as np
+    from workloads import adjoint_system, general_system, gw_system
+    stream = torch.cuda.Stream()
+
+    def per_step(p, dt, steps, warm):
+        ms, _ = timed_steps(p, dt, steps, warm, stream, torch)
+        return ms / steps
+
+    def fit(rows):
+        x = np.log([r[0] for r in rows])
+        y = np.log([r[1] for r in rows])
+        return {"all_sizes": round(float(np.polyfit(x, y, 1)[0]), 3),
+                "two_largest": round(float((y[-1] - y[-2]) / (x[-1] - x[-2])), 3)}
+
+    res = {}
+    rows = []
+    for nb in (16, 32, 48, 64):
+        sy = general_system(nb=nb, rank=2 * nb, nocc=nb // 4)
+        p = B.Propagator(B.GENERAL, B.SOA, nb, sy.h0, sy.g1, w=sy.w, stream=stream.cuda_stream)
+        rows.append((nb, per_step(p, sy.dt, 48 if nb <= 32 else 16, 8)))
+        if nb == 32:   # linear in the number of steps
+            t1 = per_step(p, sy.dt, 64, 0) * 64
+            t2 = per_step(p, sy.dt, 128, 0) * 128
+            res["steps_ratio_128_over_64"] = round(t2 / t1, 3)
+        p.close()
+    res["general_soa"] = {"ms_per_step": {str(n): round(t, 5) for n, t in rows}, "exponent": fit(rows), "paper": 5}
+    rows = []
+    for nb in (16, 32, 48, 64):
+        sy = gw_system(nb=nb, rank=2 * nb, nocc=nb // 4)
+        p = B.Propagator(B.GENERAL, B.GW, nb, sy.h0, sy.g1, w=sy.w, stream=stream.cuda_stream)
+        rows.append((nb, per_step(p, sy.dt, 16 if nb <= 32 else 4, 4 if nb <= 32 else 1)))
+        p.close()
+    res["general_gw"] = {"ms_per_step": {str(n): round(t, 5) for n, t in rows}, "exponent": fit(rows), "paper": 6}
+    rows = []
+    for lx, ly in ((4, 4), (4, 6), (6, 6), (6, 8), (8, 8)):
+        sy = adjoint_system(lx=lx, ly=ly)    # open lx x ly cluster; its drive is not set
+        p = B.Propagator(B.HUBBARD, B.SOA, sy.ns, sy.h0, sy.g1, U=sy.U, stream=stream.cuda_stream)
+        rows.append((sy.ns, per_step(p, sy.dt, 40, 8)))
+        p.close()
+    res["hubbard_soa"] = {"ms_per_step": {str(n): round(t, 5) for n, t in rows}, "exponent": fit(rows), "paper": 4}
+    return {
+        "metric": "cost of an RK4 step against the basis size: fitted exponents (Tab. I)",
+        "value": res["general_soa"]["exponent"]["two_largest"], "unit": "exponent (general SOA, Nb 48 -> 64)",
+        "n_gpus": 1, "higher_is_better": False, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "general SOA Nb 16-64, general GW Nb 16-64, Hubbard SOA open clusters Ns 16-64"},
+        "scaling_fit": res,
+    }
+
+
 def run_batch(args, torch, B):
     import numpy as np
     from paper_2002_12717_amd import autotune
@@ -510,7 +564,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--workload", default="general_soa",
                     choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
-                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint"])
+                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "scaling"])
     ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
                          "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
@@ -535,6 +589,8 @@ def main():
         out = run_general(args, torch, B, se=se)
     elif args.workload == "hubbard_batch":
         out = run_batch(args, torch, B)
+    elif args.workload == "scaling":
+        out = run_scaling(args, torch, B)
     elif args.workload == "hubbard_adjoint":
         out = run_adjoint(args, torch, B)
     else:
