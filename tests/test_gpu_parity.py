@@ -837,6 +837,67 @@ def test_general_tiny_basis(lib, nb, se):
     p.close()
 
 
+@pytest.mark.parametrize("ns", [1, 2])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw", "dsl"])
+@pytest.mark.parametrize("kern", ["row", "slice"])
+def test_hubbard_tiny_cluster_rhs(lib, ns, se, kern):
+    """One site (no neighbour at all) and two sites: one right-hand side of
+    every Hubbard closure on both stage kernels against the oracle."""
+    from paper_2002_12717_amd import binding as B
+    say(f"[edge] hubbard ns={ns} {se} {kern} rhs")
+    r = rng(105, ns, len(se))
+    hop = chain_hopping(ns) + np.diag(r.uniform(-0.4, 0.4, ns))
+    h0 = np.stack([hop, hop])
+    X, Y = random_gless(ns, r), random_gless(ns, r)
+    nch = 3 if se in ("gw", "dsl") else 1
+    g2 = [random_g2(ns, r, scale=0.1, exchange=False) for _ in range(nch)]
+    if ns == 1:   # the symmetrized random pair function of one site is zero: any value will do
+        g2 = [np.full((1, 1, 1, 1), 0.13 + 0.07j * (c + 1)) for c in range(nch)]
+    U = 1.1
+    flags = B.HUB_ROW_KERNEL if kern == "row" else B.HUB_SLICE_KERNEL
+    p = B.Propagator(B.HUBBARD, _se(se), ns, h0, np.stack([X, Y]), U=U, flags=flags)
+    G1d, G2d = cuda(np.stack([X, Y])), cuda(np.stack(g2) if nch == 3 else g2[0])
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(0.0, G1d, G2d, dG1d, dG2d)
+    extra = dict(B=T(g2[1]), C=T(g2[2])) if nch == 3 else {}
+    ref = OH.rhs(T(h0[0]), T(h0[1]), U, T(X), T(Y), T(g2[0]), se, **extra)
+    ref1 = np.stack([ref[0].numpy(), ref[1].numpy()])
+    ref2 = np.stack([x.numpy() for x in ref[2:]]) if nch == 3 else ref[2].numpy()
+    # one site: the commutator and the source vanish, so dG2 can be rounding
+    # noise; both errors are taken relative to the largest output of the call
+    scale = max(np.abs(ref1).max(), np.abs(ref2).max())
+    e1 = np.abs(dG1d.cpu().numpy() - ref1).max() / scale
+    e2 = np.abs(dG2d.cpu().numpy() - ref2).max() / scale
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    assert scale > 1e-3
+    assert e1 < 1e-13 and e2 < 1e-13
+    p.close()
+
+
+@pytest.mark.parametrize("se", ["soa", "gw"])
+def test_hubbard_batch_with_tiny_clusters(lib, se):
+    """A ragged batch whose clusters range from one site to six, 30 steps,
+    every cluster against the oracle's single-cluster run."""
+    from paper_2002_12717_amd import binding as B
+    cl = [hubbard_chain_system(ns=k, U=1.5, nup=max(1, k // 2), ndn=max(1, k // 2), dt=0.02)
+          for k in (1, 2, 3, 6, 2)]
+    say(f"[edge] batch {se} of chains {[c.ns for c in cl]}")
+    stream = torch.cuda.Stream()
+    b = B.Batch(_se(se), [c.ns for c in cl], [c.U for c in cl], [c.h0 for c in cl], [c.g1 for c in cl],
+                stream=stream.cuda_stream)
+    b.step(cl[0].dt, 30)
+    worst = 0.0
+    for q, c in enumerate(cl):
+        y, _ = OI.propagate_hubbard(c, nsteps=30, selfenergy=se)
+        g1, g2 = b.get_cluster(q)
+        ref2 = np.stack([t.numpy() for t in y[2:5]]) if se == "gw" else y[2].numpy()
+        worst = max(worst, rel(g1, np.stack([y[0].numpy(), y[1].numpy()])),
+                    rel(g2, ref2) if np.abs(ref2).max() > 0 else float(np.abs(g2).max()))
+    say(f"   worst rel err {worst:.2e}")
+    assert worst < 1e-12
+    b.close()
+
+
 def test_zero_steps_and_uncorrelated_limits(lib):
     """nsteps = 0 leaves the state untouched; without interaction (U = 0,
     w = 0) and without initial correlations G2 stays exactly zero."""
