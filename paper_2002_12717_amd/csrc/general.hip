@@ -443,8 +443,8 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
 // --------------------------------------------------------------------------- K5
 // G1 equation eq:eom_gone-2, evaluated by one wavefront per element pair:
 // I_ij and I_ji from the collision partials, [h^HF, G^<], the Runge-Kutta
-// update of G1 and, at the last stage, the divergence check.  Runs inside the
-// combine kernel, after its G2 work.
+// update of G1 and, at the last stage, the divergence check.  Runs as the
+// leading work-groups of the combine launch, beside its G2 work.
 struct G1Args {
     const cd* ipart;   // [nbp^2][nparts] partial sums of sum_lp Wc_lp C_lp^T
     int nparts;
@@ -519,18 +519,37 @@ __device__ __forceinline__ void g1_pair(const G1Args& g, int i, int j, int lane,
 
 // --------------------------------------------------------------------------- K4
 // dG2 = -i (D - D^dagger) [+ -i (Pi - conj(Pi_lkji)) for GW], fused RK4 update;
-// then the G1 equation (K5) on the same launch.
+// the G1 equation (K5) on the same launch, in work-groups of its own, so that
+// the latency of its partial-sum reads overlaps the G2 streaming.
 template <int MODE, typename S, bool GW>
 __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ D, int n,
                                                          const cd* __restrict__ in,
                                                          const cd* __restrict__ y,
                                                          cd* __restrict__ acc, cd* __restrict__ out,
                                                          const cd* __restrict__ pim, int nbp,
-                                                         double cb, double cc, G1Args g1) {
+                                                         double cb, double cc, G1Args g1, int ng1) {
     __shared__ double t1r[32][33], t1i[32][33], t2r[32][33], t2i[32][33];
+    auto tri = [](int t, int& hi, int& lo) {   // t = hi (hi + 1) / 2 + lo, lo <= hi
+        int h = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while ((h + 1) * (h + 2) / 2 <= t) ++h;
+        while (h * (h + 1) / 2 > t) --h;
+        hi = h;
+        lo = t - h * (h + 1) / 2;
+    };
+    // the first ng1 work-groups: the G1 element pairs (i <= j), one per
+    // wavefront; they run beside the G2 tile work instead of after it
+    if ((int)blockIdx.x < ng1) {
+        const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+        if (pair < nbp * (nbp + 1) / 2) {
+            int j, i;
+            tri(pair, j, i);
+            g1_pair<MODE>(g1, i, j, threadIdx.x & 63, nbp, cb, cc);
+        }
+        return;
+    }
     // work-group -> tile pair (by, bx), bx <= by, in triangular order; both
     // tiles of the pair are updated from one read of D_(by,bx) and D_(bx,by)
-    const int tb = blockIdx.x;
+    const int tb = blockIdx.x - ng1;
     int by = (int)((sqrtf(8.0f * (float)tb + 1.0f) - 1.0f) * 0.5f);
     while ((by + 1) * (by + 2) / 2 <= tb) ++by;
     while (by * (by + 1) / 2 > tb) --by;
@@ -564,12 +583,6 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
         // D_rc - conj(D_cr) on tile (by, bx) and, off the diagonal, on (bx, by)
         update(by * 32 + r, bx * 32 + tx, t1r[r][tx] - t2r[tx][r], t1i[r][tx] + t2i[tx][r]);
         if (bx != by) update(bx * 32 + r, by * 32 + tx, t2r[r][tx] - t1r[tx][r], t2i[r][tx] + t1i[tx][r]);
-    }
-    // the G1 element pairs (i <= j), one per wavefront, spread over the work-groups
-    const int n1 = nbp * nbp;
-    for (int e1 = (threadIdx.x >> 6) * gridDim.x + blockIdx.x; e1 < n1; e1 += 4 * gridDim.x) {
-        const int i = e1 / nbp, j = e1 - i * nbp;
-        if (i <= j) g1_pair<MODE>(g1, i, j, threadIdx.x & 63, nbp, cb, cc);
     }
 }
 
@@ -999,12 +1012,13 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     const int nt = n / 32, ntiles = nt * (nt + 1) / 2;
     const G1Args g1{g.ipart, g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1,
                     g.icoll, g.nb, c->dflag};
+    const int ng1 = (g.nbp * (g.nbp + 1) / 2 + 3) / 4;   // work-groups of the G1 pairs
     if (c->d.selfenergy == G1G2_GW || c->d.selfenergy == G1G2_DSL)
-        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(ntiles), dim3(256), 0, c->stream,
-                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(ng1 + ntiles), dim3(256), 0, c->stream,
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1, ng1);
     else
-        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(ntiles), dim3(256), 0, c->stream,
-                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1);
+        hipLaunchKernelGGL((gen_combine_kernel<MODE, S, false>), dim3(ng1 + ntiles), dim3(256), 0, c->stream,
+                           (const S*)g.dmat, n, in.g2, y.g2, acc.g2, out.g2, g.pimat, g.nbp, cb, cc, g1, ng1);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_combine");
     return G1G2_OK;
