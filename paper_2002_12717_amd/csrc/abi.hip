@@ -292,7 +292,11 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
     const int64_t step0 = c->step;
     g1g2_status s;
     int64_t n = 0;
-    if (can_capture(c) && nsteps >= 4) {
+    if (c->d.basis == G1G2_HUBBARD && hub_persistent_ok(c)) {
+        if ((s = hub_step_persistent(c, dt, nsteps)) != G1G2_OK) return s;
+        n = nsteps;
+    }
+    if (n < nsteps && can_capture(c) && nsteps >= 4) {
         const int gs = (int)std::min<int64_t>(nsteps, 8);
         if (!c->graph || c->graph_dt != dt || c->graph_steps != gs)
             if ((s = capture(c, dt, gs)) != G1G2_OK) return s;

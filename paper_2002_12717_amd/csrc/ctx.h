@@ -145,6 +145,10 @@ g1g2_status set_error(g1g2_ctx* c, g1g2_status s, const std::string& msg);
 g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* ns, const double* U, const cd* const* h0s,
                       const int* chunk);
 void hub_free(g1g2_ctx* c);
+// Whole RK4 steps of one small single-channel cluster in one persistent
+// work-group (ns^4 <= 4096, binary64, no drive or ramp, no kernel flag).
+bool hub_persistent_ok(const g1g2_ctx* c);
+g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps);
 // One RK4 stage (or a plain RHS evaluation, mode RK_RHS) of the Hubbard system.
 g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc);

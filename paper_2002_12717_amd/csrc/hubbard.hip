@@ -741,6 +741,150 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     }
 }
 
+// Whole Runge-Kutta steps of one small cluster in one work-group (the
+// latency-bound case: up to a few thousand G2 elements, where four launches per
+// step cost more than their work; measured on chains, one work-group beats the
+// launched stages 4.5x at ns = 2 and 1.8x at ns = 7, and loses at ns = 8, where
+// 4096 elements on one compute unit take longer than the launches).  The stage input of G2 and G1 is double-buffered
+// in LDS; y and the running sum acc stay in the registers of the thread that
+// owns the element (PERSIST_PER G2 elements and at most one G1 element per
+// thread); a step is four stages separated by work-group barriers.  Each
+// element's right-hand side is the per-element one (hub_g2_rhs, hub_g1_rhs),
+// and the updates are those of rk_update, so the arithmetic is that of the
+// launched stages.  Single-channel closures (SOA, TPP, TPH), no drive, no
+// switching ramp.
+constexpr int PERSIST_THREADS = 1024;
+constexpr int PERSIST_G2 = 3072;   // ns^4 <= 3072: ns <= 7
+constexpr int PERSIST_G1 = 128;    // 2 ns^2
+constexpr int PERSIST_PER = PERSIST_G2 / PERSIST_THREADS;
+constexpr int PERSIST_NBR = 128;   // 2 ns zmax: neighbour table and hoppings, staged in LDS
+
+struct PersistArgs {
+    const ClusterDesc* desc;
+    const int* nbr;
+    const cd* hop;
+    const double* d0;
+    const double* xdrv;
+    cd* y1;        // G1 state [2][ns][ns]: read at the start, written at the end
+    cd* y2;        // G2 state [ns]^4
+    double dt;
+    int nsteps;
+    int* flag;
+};
+
+template <int SE>
+__global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(PersistArgs p) {
+    __shared__ cd sA[2][PERSIST_G2];
+    __shared__ cd sG[2][PERSIST_G1];
+    // the cluster's neighbour table, hoppings, h0 diagonal and drive profile
+    // (a few hundred bytes, read by every element every stage) in LDS
+    __shared__ int snbr[PERSIST_NBR];
+    __shared__ cd shop[PERSIST_NBR];
+    __shared__ double sd0[PERSIST_G1], sxd[PERSIST_G1];
+    const ClusterDesc d = p.desc[0];
+    const int ns = d.ns, ns2 = ns * ns, n2 = ns2 * ns2, n1 = 2 * ns2;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 2 * ns * d.zmax; q += PERSIST_THREADS) {
+        snbr[q] = p.nbr[d.nbroff + q];
+        shop[q] = p.hop[d.nbroff + q];
+    }
+    if (tid < 2 * ns) sd0[tid] = p.d0[d.d0off + tid];
+    if (tid < ns) sxd[tid] = p.xdrv[d.xoff + tid];
+    cd y2[PERSIST_PER], acc2[PERSIST_PER];
+    cd y1 = cmk(0.0, 0.0), acc1 = cmk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < PERSIST_PER; ++q) {
+        const int e = tid + q * PERSIST_THREADS;
+        y2[q] = e < n2 ? p.y2[e] : cmk(0.0, 0.0);
+        acc2[q] = cmk(0.0, 0.0);
+        if (e < n2) sA[0][e] = y2[q];
+    }
+    if (tid < n1) {
+        y1 = p.y1[tid];
+        sG[0][tid] = y1;
+    }
+    __syncthreads();
+    const double h = p.dt;
+    int cur = 0;
+    for (int step = 0; step < p.nsteps; ++step) {
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            // stage weights of the classical RK4 step: acc gets cb f, the next stage
+            // input is y + cc f (the last stage writes y = acc + cb f)
+            const double cb = (st == 0 || st == 3) ? h / 6.0 : h / 3.0;
+            const double cc = st < 2 ? 0.5 * h : h;
+            Cl a = make_cl(d, p.nbr, p.hop, p.d0, p.xdrv, sG[cur], 0.0, 1.0);
+            a.nbr = snbr;
+            a.hop = shop;
+            a.d0 = sd0;
+            a.xdrv = sxd;
+            const cd* A = sA[cur];
+            cd* outA = sA[cur ^ 1];
+            // an opaque copy of the thread index: the element indices are
+            // recomputed every stage instead of being hoisted out of the step
+            // loop, where holding them for all elements would spill registers
+            int tq = tid;
+            asm volatile("" : "+v"(tq));
+            cd* outG = sG[cur ^ 1];
+            // one element at a time (the barrier keeps the scheduler from
+            // overlapping the right-hand sides, whose registers would spill);
+            // the output goes to the other buffer, which no thread reads now
+#pragma unroll
+            for (int q = 0; q < PERSIST_PER; ++q) {
+                const int e = tq + q * PERSIST_THREADS;
+                if (e < n2) {
+                    const int l = e % ns, k = (e / ns) % ns, j = (e / ns2) % ns, i = e / (ns2 * ns);
+                    const cd f = hub_g2_rhs<SE, cd>(a, A, i, j, k, l, e, A[e]);
+                    cd o;
+                    if (st == 0) {
+                        acc2[q] = cmk(fma(cb, f.x, y2[q].x), fma(cb, f.y, y2[q].y));
+                        o = cmk(fma(cc, f.x, y2[q].x), fma(cc, f.y, y2[q].y));
+                    } else if (st < 3) {
+                        acc2[q] = cmk(fma(cb, f.x, acc2[q].x), fma(cb, f.y, acc2[q].y));
+                        o = cmk(fma(cc, f.x, y2[q].x), fma(cc, f.y, y2[q].y));
+                    } else {
+                        y2[q] = cmk(fma(cb, f.x, acc2[q].x), fma(cb, f.y, acc2[q].y));
+                        o = y2[q];
+                    }
+                    outA[e] = o;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            cd f1 = cmk(0.0, 0.0);
+            if (tq < n1) {
+                const int sig = tq / ns2, r = tq - sig * ns2;
+                f1 = hub_g1_rhs(a, A, sig, r / ns, r % ns);
+            }
+            if (tid < n1) {
+                cd o;
+                if (st == 0) {
+                    acc1 = cmk(fma(cb, f1.x, y1.x), fma(cb, f1.y, y1.y));
+                    o = cmk(fma(cc, f1.x, y1.x), fma(cc, f1.y, y1.y));
+                } else if (st < 3) {
+                    acc1 = cmk(fma(cb, f1.x, acc1.x), fma(cb, f1.y, acc1.y));
+                    o = cmk(fma(cc, f1.x, y1.x), fma(cc, f1.y, y1.y));
+                } else {
+                    y1 = cmk(fma(cb, f1.x, acc1.x), fma(cb, f1.y, acc1.y));
+                    o = y1;
+                    const int r = tid % ns2, i = r / ns, j = r % ns;
+                    bool bad = !(isfinite(o.x) && isfinite(o.y));
+                    if (i == j && (o.y < -0.5 || o.y > 1.5)) bad = true;
+                    if (bad) atomicOr(p.flag, 1);
+                }
+                outG[tid] = o;
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PERSIST_PER; ++q) {
+        const int e = tid + q * PERSIST_THREADS;
+        if (e < n2) p.y2[e] = y2[q];
+    }
+    if (tid < n1) p.y1[tid] = y1;
+}
+
 StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const Regs& acc,
                      const Regs& out, double cb, double cc) {
     HubbardData& H = c->hub;
@@ -1162,6 +1306,40 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         HIP_OK(c, hipMemcpyAsync(H.xdrv, H.drive_x.data(), xoff * sizeof(double), hipMemcpyHostToDevice,
                                  c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
+    return G1G2_OK;
+}
+
+bool hub_persistent_ok(const g1g2_ctx* c) {
+    const HubbardData& H = c->hub;
+    if (H.ncl != 1 || H.has_drive() || c->has_switch() || c->prof) return false;
+    if (c->d.precision != G1G2_FP64) return false;
+    if (c->d.flags & (G1G2_HUB_ROW_KERNEL | G1G2_HUB_SLICE_KERNEL)) return false;
+    const int sel = c->d.selfenergy;
+    if (sel != G1G2_SOA && sel != G1G2_TPP && sel != G1G2_TPH) return false;
+    const long long ns = H.hdesc[0].ns, z = H.hdesc[0].zmax;
+    return ns * ns * ns * ns <= PERSIST_G2 && 2 * ns * ns <= PERSIST_G1 && 2 * ns * z <= PERSIST_NBR;
+}
+
+g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
+    HubbardData& H = c->hub;
+    // bounded launches: at most 1024 steps (a few ms) per launch
+    for (int64_t n = 0; n < nsteps;) {
+        const int chunk = (int)std::min<int64_t>(nsteps - n, 1024);
+        PersistArgs p{H.desc, H.nbr, H.hop, H.d0, H.xdrv, c->y.g1, c->y.g2, dt, chunk, c->dflag};
+        switch (c->d.selfenergy) {
+            case G1G2_TPP:
+                hipLaunchKernelGGL((hub_persistent_kernel<SE_TPP>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
+                break;
+            case G1G2_TPH:
+                hipLaunchKernelGGL((hub_persistent_kernel<SE_TPH>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
+                break;
+            default:
+                hipLaunchKernelGGL((hub_persistent_kernel<SE_SOA>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
+                break;
+        }
+        HIP_OK(c, hipGetLastError());
+        n += chunk;
+    }
     return G1G2_OK;
 }
 

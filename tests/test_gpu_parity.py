@@ -155,6 +155,27 @@ def test_hubbard_chain_full_trajectory(lib):
     _compare_hubbard_trajectory(hubbard_chain_system(), "soa", 10, 100, 1e-10)
 
 
+@pytest.mark.parametrize("ns", [2, 3, 5, 7])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
+def test_hubbard_persistent_small_cluster(lib, ns, se):
+    """Clusters of at most 3072 G2 elements (ns <= 7) run whole Runge-Kutta
+    steps in one persistent work-group: 300 steps against the oracle, and
+    against the launched stages (row kernel) of the same library."""
+    from paper_2002_12717_amd import binding as B
+    s = hubbard_chain_system(ns=ns, U=1.5, nup=max(1, ns // 2), ndn=max(1, ns // 2), dt=0.02)
+    say(f"[hubbard persistent] chain{ns} {se} 300 steps")
+    _compare_hubbard_trajectory(s, se, 3, 100, 1e-10)
+    pp = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U)
+    pr = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    pp.step(s.dt, 300)
+    pr.step(s.dt, 300)
+    (g1p, g2p, tp), (g1r, g2r, tr) = pp.get_state(), pr.get_state()
+    say(f"   persistent vs row kernel: G1 {rel(g1p, g1r):.2e}  G2 {rel(g2p, g2r):.2e}")
+    assert rel(g1p, g1r) < 1e-12 and rel(g2p, g2r) < 1e-12 and tp == tr
+    pp.close()
+    pr.close()
+
+
 @pytest.mark.parametrize("se", ["gw", "dsl"])
 def test_hubbard_gw_chain_trajectory(lib, se):
     """Hubbard GW and DSL on the 8-site chain, 400 steps: G1 and E against the oracle."""
@@ -596,7 +617,9 @@ def test_graph_replays_match_eager(lib, basis):
     if basis.startswith("hubbard"):
         s = hubbard_chain_system(ns=6)
         se = B.TPH if basis == "hubbard_tph" else B.TPP
-        fl = B.HUB_SLICE_KERNEL if basis == "hubbard_slice" else 0
+        # explicit stage kernels: without a flag a cluster this small runs whole
+        # steps in one persistent work-group, with no graph to replay
+        fl = B.HUB_SLICE_KERNEL if basis == "hubbard_slice" else B.HUB_ROW_KERNEL
         mk = lambda st: B.Propagator(B.HUBBARD, se, s.ns, s.h0, s.g1, U=s.U, stream=st, flags=fl)  # noqa: E731
     else:
         s = general_system(nb=12, rank=10, nocc=4)
