@@ -10,8 +10,8 @@ One "step" = one full RK4 step (four right-hand sides) of G1 and G2.  The
 binary64 path is the headline value; the mixed path (binary32 matrix-core
 contractions, binary64 state) is reported beside it with its error against
 the binary64 run.  Other workloads of the paper's shape are available with
---workload (hubbard_chain, hubbard_2d, hubbard_batch, hubbard_adjoint, general_gw,
-general_ladder).
+--workload (hubbard_chain, with --ns for the chain length; hubbard_2d, hubbard_batch,
+hubbard_adjoint, general_gw, general_ladder, scaling).
 
 Prints ONE JSON line.
 """
@@ -245,8 +245,13 @@ def run_general(args, torch, B, se="soa"):
 def run_hubbard(args, torch, B, kind):
     import numpy as np
     from workloads import adjoint_system, hubbard_chain_system
-    system = hubbard_chain_system() if kind == "hubbard_chain" else adjoint_system()
+    system = hubbard_chain_system(ns=args.ns) if kind == "hubbard_chain" else adjoint_system()
     ns = system.ns
+    # one SOA/TPP/TPH cluster of at most 3,072 G2 elements with no drive runs whole
+    # steps in the persistent single-work-group kernel (both precisions); the per-launch
+    # profile below always times the launched stages
+    persistent = (ns ** 4 <= 3072 and system.drive is None and (args.selfenergy or "soa")
+                  in ("soa", "tpp", "tph"))
     stream = torch.cuda.Stream()
     se = args.selfenergy or "soa"
 
@@ -271,7 +276,7 @@ def run_hubbard(args, torch, B, kind):
     # Hubbard GW and DSL propagate three G2 channels
     bytes_per_launch = 64.0 * n4 * HUB_CHANNELS[se]
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
-    name = "1D chain, 8 sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
+    name = f"1D chain, {ns} sites" if kind == "hubbard_chain" else "2D 8x8 open cluster, driven"
     config = {"workload": f"Hubbard {se.upper()} G1-G2, {name}, U={system.U}, dt={system.dt}, RK4",
               "ns": ns, "U": system.U, "dt": system.dt, "selfenergy": se.upper(),
               "parallelism": "single GPU"}
@@ -286,6 +291,10 @@ def run_hubbard(args, torch, B, kind):
         "kernels": kernel_table(prof),
         "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
     })
+    if persistent:
+        out["path"] = ("hub_persistent_kernel (whole RK4 steps in one work-group, binary64 and "
+                       "mixed); the roofline entries are of the launched stages, timed by the "
+                       "per-launch profile")
     # mixed precision: binary32 G2 stage copies, 52 B per element and launch
     # (binary64 y and acc, binary32 stage input and output)
     mx_ms, mx_prof, mx_obs, g1_mx = run(B.MIXED)
@@ -569,6 +578,8 @@ def main():
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
                          "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
                          "tpp, tph or dsl (default dsl)")
+    ap.add_argument("--ns", type=int, default=8,
+                    help="hubbard_chain: number of sites (default 8; 2-7 take the persistent kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -752,7 +752,11 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // element's right-hand side is the per-element one (hub_g2_rhs, hub_g1_rhs),
 // and the updates are those of rk_update, so the arithmetic is that of the
 // launched stages.  Single-channel closures (SOA, TPP, TPH), no drive, no
-// switching ramp.
+// switching ramp.  MIXED keeps the G2 stage copies in binary32 as the launched
+// mixed stages do: sA[0] then holds the binary64 y (the input of stage 1) and
+// sA[1] two binary32 buffers F0, F1; stage 1 writes F0, stage 2 reads F0 and
+// writes F1, stage 3 reads F1 and writes F0, stage 4 reads F0 and writes the
+// new y to sA[0].
 constexpr int PERSIST_THREADS = 1024;
 constexpr int PERSIST_G2 = 3072;   // ns^4 <= 3072: ns <= 7
 constexpr int PERSIST_G1 = 128;    // 2 ns^2
@@ -772,9 +776,10 @@ struct PersistArgs {
     int* flag;
 };
 
-template <int SE>
+template <int SE, bool MIXED>
 __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(PersistArgs p) {
     __shared__ cd sA[2][PERSIST_G2];
+    float2* const sF = reinterpret_cast<float2*>(sA[1]);
     __shared__ cd sG[2][PERSIST_G1];
     // the cluster's neighbour table, hoppings, h0 diagonal and drive profile
     // (a few hundred bytes, read by every element every stage) in LDS
@@ -818,8 +823,10 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
             a.hop = shop;
             a.d0 = sd0;
             a.xdrv = sxd;
-            const cd* A = sA[cur];
-            cd* outA = sA[cur ^ 1];
+            const cd* A = MIXED ? sA[0] : sA[cur];
+            cd* outA = MIXED ? sA[0] : sA[cur ^ 1];
+            const float2* inF = sF + (st == 2 ? PERSIST_G2 : 0);
+            float2* outF = sF + (st == 1 ? PERSIST_G2 : 0);
             // an opaque copy of the thread index: the element indices are
             // recomputed every stage instead of being hoisted out of the step
             // loop, where holding them for all elements would spill registers
@@ -834,7 +841,9 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
                 const int e = tq + q * PERSIST_THREADS;
                 if (e < n2) {
                     const int l = e % ns, k = (e / ns) % ns, j = (e / ns2) % ns, i = e / (ns2 * ns);
-                    const cd f = hub_g2_rhs<SE, cd>(a, A, i, j, k, l, e, A[e]);
+                    cd f;
+                    if (MIXED && st > 0) f = hub_g2_rhs<SE, float2>(a, inF, i, j, k, l, e, ld_c(inF, e));
+                    else f = hub_g2_rhs<SE, cd>(a, A, i, j, k, l, e, A[e]);
                     cd o;
                     if (st == 0) {
                         acc2[q] = cmk(fma(cb, f.x, y2[q].x), fma(cb, f.y, y2[q].y));
@@ -846,14 +855,16 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
                         y2[q] = cmk(fma(cb, f.x, acc2[q].x), fma(cb, f.y, acc2[q].y));
                         o = y2[q];
                     }
-                    outA[e] = o;
+                    if (MIXED && st < 3) st_c(outF, e, o);
+                    else outA[e] = o;
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
             cd f1 = cmk(0.0, 0.0);
             if (tq < n1) {
                 const int sig = tq / ns2, r = tq - sig * ns2;
-                f1 = hub_g1_rhs(a, A, sig, r / ns, r % ns);
+                f1 = (MIXED && st > 0) ? hub_g1_rhs(a, inF, sig, r / ns, r % ns)
+                                       : hub_g1_rhs(a, A, sig, r / ns, r % ns);
             }
             if (tid < n1) {
                 cd o;
@@ -1312,12 +1323,29 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
 bool hub_persistent_ok(const g1g2_ctx* c) {
     const HubbardData& H = c->hub;
     if (H.ncl != 1 || H.has_drive() || c->has_switch() || c->prof) return false;
-    if (c->d.precision != G1G2_FP64) return false;
     if (c->d.flags & (G1G2_HUB_ROW_KERNEL | G1G2_HUB_SLICE_KERNEL)) return false;
     const int sel = c->d.selfenergy;
     if (sel != G1G2_SOA && sel != G1G2_TPP && sel != G1G2_TPH) return false;
     const long long ns = H.hdesc[0].ns, z = H.hdesc[0].zmax;
     return ns * ns * ns * ns <= PERSIST_G2 && 2 * ns * ns <= PERSIST_G1 && 2 * ns * z <= PERSIST_NBR;
+}
+
+template <bool MIXED>
+void launch_persistent(g1g2_ctx* c, const PersistArgs& p) {
+    switch (c->d.selfenergy) {
+        case G1G2_TPP:
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPP, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+                               c->stream, p);
+            break;
+        case G1G2_TPH:
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPH, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+                               c->stream, p);
+            break;
+        default:
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_SOA, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+                               c->stream, p);
+            break;
+    }
 }
 
 g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
@@ -1326,17 +1354,8 @@ g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
     for (int64_t n = 0; n < nsteps;) {
         const int chunk = (int)std::min<int64_t>(nsteps - n, 1024);
         PersistArgs p{H.desc, H.nbr, H.hop, H.d0, H.xdrv, c->y.g1, c->y.g2, dt, chunk, c->dflag};
-        switch (c->d.selfenergy) {
-            case G1G2_TPP:
-                hipLaunchKernelGGL((hub_persistent_kernel<SE_TPP>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
-                break;
-            case G1G2_TPH:
-                hipLaunchKernelGGL((hub_persistent_kernel<SE_TPH>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
-                break;
-            default:
-                hipLaunchKernelGGL((hub_persistent_kernel<SE_SOA>), dim3(1), dim3(PERSIST_THREADS), 0, c->stream, p);
-                break;
-        }
+        if (c->d.precision == G1G2_MIXED) launch_persistent<true>(c, p);
+        else launch_persistent<false>(c, p);
         HIP_OK(c, hipGetLastError());
         n += chunk;
     }

@@ -176,6 +176,31 @@ def test_hubbard_persistent_small_cluster(lib, ns, se):
     pr.close()
 
 
+@pytest.mark.parametrize("ns", [3, 7])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
+def test_hubbard_persistent_small_cluster_mixed(lib, ns, se):
+    """The persistent work-group in mixed precision (binary32 G2 stage copies in
+    LDS): 300 steps against the binary64 oracle at the mixed-precision bar, and
+    against the launched mixed stages of the same library."""
+    from paper_2002_12717_amd import binding as B
+    s = hubbard_chain_system(ns=ns, U=1.5, dt=0.02)
+    say(f"[hubbard persistent mixed] chain{ns} {se} 300 steps")
+    pm = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, precision=B.MIXED)
+    pr = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, precision=B.MIXED,
+                      flags=B.HUB_ROW_KERNEL)
+    pm.step(s.dt, 300)
+    pr.step(s.dt, 300)
+    y, _ = OI.propagate_hubbard(s, nsteps=300, selfenergy=se)
+    ref = np.stack([y[0].numpy(), y[1].numpy()])
+    (g1m, g2m, tm), (g1r, g2r, tr) = pm.get_state(), pr.get_state()
+    e_or, e_rk = rel(g1m, ref), rel(g1m, g1r)
+    say(f"   vs oracle G1 {e_or:.2e}   vs launched mixed G1 {e_rk:.2e} G2 {rel(g2m, g2r):.2e}")
+    assert e_or < 1e-5 and e_rk < 1e-6 and rel(g2m, g2r) < 1e-6 and tm == tr
+    assert e_or > 1e-12                 # the binary32 stage copies are in use
+    pm.close()
+    pr.close()
+
+
 @pytest.mark.parametrize("se", ["gw", "dsl"])
 def test_hubbard_gw_chain_trajectory(lib, se):
     """Hubbard GW and DSL on the 8-site chain, 400 steps: G1 and E against the oracle."""
