@@ -73,6 +73,11 @@ def load(path: str = LIBPATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_2002_12717_amd.build.build()")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading it first makes the library bind to that copy, so the process holds
+    # one HIP runtime (loaded the other way round, the system copy binds first and
+    # torch's device calls fail)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
