@@ -176,6 +176,47 @@ def test_hubbard_persistent_small_cluster(lib, ns, se):
     pr.close()
 
 
+def _small_lattice(kind):
+    """Two small clusters off the open chain: a 2x3 open square cluster (three
+    neighbours at most, spin-dependent on-site energies) and a 6-site ring
+    threaded by a flux (complex hoppings -J exp(i 0.7) around the ring)."""
+    from workloads.systems import HubbardSystem, _neel_init, chain_hopping, square_hopping
+    if kind == "2x3":
+        h = square_hopping(2, 3, periodic=False)
+        stag = np.array([(-1.0) ** (x + y) for y in range(3) for x in range(2)])
+        hu = h + np.diag(np.linspace(-0.3, 0.3, 6))
+        hd = h - np.diag(np.linspace(-0.2, 0.4, 6))
+    else:
+        h = np.zeros((6, 6), dtype=np.complex128)
+        for q in range(6):
+            h[q, (q + 1) % 6] = -np.exp(0.7j)
+            h[(q + 1) % 6, q] = -np.exp(-0.7j)
+        stag = np.array([(-1.0) ** q for q in range(6)])
+        hu = hd = h
+    g1 = _neel_init(h, (3, 3), stag, 0.5)
+    return HubbardSystem(kind, 6, 1.5, np.stack([hu, hd]), g1, 0.02, 300)
+
+
+@pytest.mark.parametrize("kind", ["2x3", "ring6_flux"])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
+def test_hubbard_persistent_lattices(lib, kind, se):
+    """The persistent work-group on a 2D cluster and on a ring with complex
+    hoppings: 300 steps against the oracle and against the launched stages."""
+    from paper_2002_12717_amd import binding as B
+    s = _small_lattice(kind)
+    say(f"[hubbard persistent] {kind} {se} 300 steps")
+    _compare_hubbard_trajectory(s, se, 3, 100, 1e-10)
+    pp = B.Propagator(B.HUBBARD, _se(se), s.ns, s.h0, s.g1, U=s.U)
+    pr = B.Propagator(B.HUBBARD, _se(se), s.ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    pp.step(s.dt, 300)
+    pr.step(s.dt, 300)
+    (g1p, g2p, _), (g1r, g2r, _) = pp.get_state(), pr.get_state()
+    say(f"   persistent vs row kernel: G1 {rel(g1p, g1r):.2e}  G2 {rel(g2p, g2r):.2e}")
+    assert rel(g1p, g1r) < 1e-12 and rel(g2p, g2r) < 1e-12
+    pp.close()
+    pr.close()
+
+
 @pytest.mark.parametrize("ns", [3, 7])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
 def test_hubbard_persistent_small_cluster_mixed(lib, ns, se):
