@@ -745,10 +745,11 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // latency-bound case: up to a few thousand G2 elements, where four launches per
 // step cost more than their work; measured on chains, one work-group beats the
 // launched stages 4.5x at ns = 2 and 1.8x at ns = 7, and loses at ns = 8, where
-// 4096 elements on one compute unit take longer than the launches).  The stage input of G2 and G1 is double-buffered
-// in LDS; y and the running sum acc stay in the registers of the thread that
-// owns the element (PERSIST_PER G2 elements and at most one G1 element per
-// thread); a step is four stages separated by work-group barriers.  Each
+// 4096 elements on one compute unit take longer than the launches).  The stage
+// input of G2 and G1 is double-buffered in LDS; y and the running sum acc stay
+// in the registers of the thread that owns the element (PERSIST_PER G2
+// elements and at most one G1 element per thread); a step is four stages
+// separated by work-group barriers.  Each
 // element's right-hand side is the per-element one (hub_g2_rhs, hub_g1_rhs),
 // and the updates are those of rk_update, so the arithmetic is that of the
 // launched stages.  Single-channel closures (SOA, TPP, TPH), no drive, no
