@@ -13,6 +13,7 @@ struct Cl {
     const double* __restrict__ xdrv;
     const cd* __restrict__ X;       // stage-input G^{<,up}
     const cd* __restrict__ Y;       // stage-input G^{<,down}
+    const cd* __restrict__ hdg;     // [2][ns] diagonals of h^{HF} when precomputed, else unused
 };
 
 __device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, const cd* hop,
@@ -29,6 +30,7 @@ __device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, cons
     a.xdrv = xdrv + d.xoff;
     a.X = g1 + d.g1off;
     a.Y = a.X + d.ns * d.ns;
+    a.hdg = nullptr;
     return a;
 }
 

@@ -48,7 +48,8 @@ __host__ __device__ constexpr int n_diag(int se) { return (has_pol(se) ? 6 : 0) 
 // cluster's block A = G2^{up down up down}:
 //   dA/dt = -i ( [h2_{ud}, A] + Psi + [L - (L_klij)^*] ),
 // L the particle-particle (TPP) or particle-hole (TPH) ladder, none for SOA.
-template <int SE, typename TA>
+// PRE: the diagonals of h^{HF} are read from a.hdg (computed once per stage)
+template <int SE, typename TA, bool PRE = false>
 __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, int i, int j, int k,
                                          int l, int e, cd aval) {
     const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
@@ -57,7 +58,18 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, 
     const cd* hu = a.hop;
     const cd* hd = a.hop + ns * z;
     // two-particle commutator (Sec. VII.A with the on-site terms of h0 + drive)
-    cd ei = hf_diag(a, 0, i), ej = hf_diag(a, 1, j), ek = hf_diag(a, 0, k), el = hf_diag(a, 1, l);
+    cd ei, ej, ek, el;
+    if constexpr (PRE) {
+        ei = a.hdg[i];
+        ej = a.hdg[ns + j];
+        ek = a.hdg[k];
+        el = a.hdg[ns + l];
+    } else {
+        ei = hf_diag(a, 0, i);
+        ej = hf_diag(a, 1, j);
+        ek = hf_diag(a, 0, k);
+        el = hf_diag(a, 1, l);
+    }
     cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), aval);
     for (int q = 0; q < z; ++q) {
         int p = nbu[i * z + q];
@@ -744,12 +756,12 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // Whole Runge-Kutta steps of one small cluster in one work-group (the
 // latency-bound case: up to a few thousand G2 elements, where four launches per
 // step cost more than their work; measured on chains, one work-group beats the
-// launched stages 4.5x at ns = 2 and 1.8x at ns = 7, and loses at ns = 8, where
-// 4096 elements on one compute unit take longer than the launches).  The stage
-// input of G2 and G1 is double-buffered in LDS; y and the running sum acc stay
-// in the registers of the thread that owns the element (PERSIST_PER G2
-// elements and at most one G1 element per thread); a step is four stages
-// separated by work-group barriers.  Each
+// graph-replayed launched stages 2.3x at ns = 2, 2.3x at ns = 7 and 1.13x at
+// ns = 8).  The stage input of G2 and G1 is double-buffered in LDS; y and the
+// running sum acc stay in the registers of the thread that owns the element
+// (PERSIST_PER G2 elements, their indices packed one byte each, and at most
+// one G1 element per thread); the 2 ns diagonals of h^HF are computed once per
+// stage; a step is four stages separated by work-group barriers.  Each
 // element's right-hand side is the per-element one (hub_g2_rhs, hub_g1_rhs),
 // and the updates are those of rk_update, so the arithmetic is that of the
 // launched stages.  Single-channel closures (SOA, TPP, TPH), no drive, no
@@ -759,7 +771,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // writes F1, stage 3 reads F1 and writes F0, stage 4 reads F0 and writes the
 // new y to sA[0].
 constexpr int PERSIST_THREADS = 1024;
-constexpr int PERSIST_G2 = 3072;   // ns^4 <= 3072: ns <= 7
+constexpr int PERSIST_G2 = 4096;   // ns^4 <= 4096: ns <= 8
 constexpr int PERSIST_G1 = 128;    // 2 ns^2
 constexpr int PERSIST_PER = PERSIST_G2 / PERSIST_THREADS;
 constexpr int PERSIST_NBR = 128;   // 2 ns zmax: neighbour table and hoppings, staged in LDS
@@ -787,6 +799,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
     __shared__ int snbr[PERSIST_NBR];
     __shared__ cd shop[PERSIST_NBR];
     __shared__ double sd0[PERSIST_G1], sxd[PERSIST_G1];
+    __shared__ cd shd[16];   // diagonals of h^{HF} at the stage (2 ns <= 16)
     const ClusterDesc d = p.desc[0];
     const int ns = d.ns, ns2 = ns * ns, n2 = ns2 * ns2, n1 = 2 * ns2;
     const int tid = threadIdx.x;
@@ -798,9 +811,13 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
     if (tid < ns) sxd[tid] = p.xdrv[d.xoff + tid];
     cd y2[PERSIST_PER], acc2[PERSIST_PER];
     cd y1 = cmk(0.0, 0.0), acc1 = cmk(0.0, 0.0);
+    // the indices (i, j, k, l) of each owned element, one byte each (ns <= 8)
+    unsigned pk[PERSIST_PER];
 #pragma unroll
     for (int q = 0; q < PERSIST_PER; ++q) {
         const int e = tid + q * PERSIST_THREADS;
+        const int l = e % ns, k = (e / ns) % ns, j = (e / ns2) % ns, i = e / (ns2 * ns);
+        pk[q] = (unsigned)i | ((unsigned)j << 8) | ((unsigned)k << 16) | ((unsigned)l << 24);
         y2[q] = e < n2 ? p.y2[e] : cmk(0.0, 0.0);
         acc2[q] = cmk(0.0, 0.0);
         if (e < n2) sA[0][e] = y2[q];
@@ -824,6 +841,9 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
             a.hop = shop;
             a.d0 = sd0;
             a.xdrv = sxd;
+            if (tid < 2 * ns) shd[tid] = hf_diag(a, tid / ns, tid % ns);
+            __syncthreads();
+            a.hdg = shd;
             const cd* A = MIXED ? sA[0] : sA[cur];
             cd* outA = MIXED ? sA[0] : sA[cur ^ 1];
             const float2* inF = sF + (st == 2 ? PERSIST_G2 : 0);
@@ -841,10 +861,12 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
             for (int q = 0; q < PERSIST_PER; ++q) {
                 const int e = tq + q * PERSIST_THREADS;
                 if (e < n2) {
-                    const int l = e % ns, k = (e / ns) % ns, j = (e / ns2) % ns, i = e / (ns2 * ns);
+                    unsigned u = pk[q];
+                    asm volatile("" : "+v"(u));   // keep derived offsets out of the step loop
+                    const int i = u & 255, j = (u >> 8) & 255, k = (u >> 16) & 255, l = u >> 24;
                     cd f;
-                    if (MIXED && st > 0) f = hub_g2_rhs<SE, float2>(a, inF, i, j, k, l, e, ld_c(inF, e));
-                    else f = hub_g2_rhs<SE, cd>(a, A, i, j, k, l, e, A[e]);
+                    if (MIXED && st > 0) f = hub_g2_rhs<SE, float2, true>(a, inF, i, j, k, l, e, ld_c(inF, e));
+                    else f = hub_g2_rhs<SE, cd, true>(a, A, i, j, k, l, e, A[e]);
                     cd o;
                     if (st == 0) {
                         acc2[q] = cmk(fma(cb, f.x, y2[q].x), fma(cb, f.y, y2[q].y));

@@ -155,10 +155,10 @@ def test_hubbard_chain_full_trajectory(lib):
     _compare_hubbard_trajectory(hubbard_chain_system(), "soa", 10, 100, 1e-10)
 
 
-@pytest.mark.parametrize("ns", [2, 3, 5, 7])
+@pytest.mark.parametrize("ns", [2, 3, 5, 7, 8])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
 def test_hubbard_persistent_small_cluster(lib, ns, se):
-    """Clusters of at most 3072 G2 elements (ns <= 7) run whole Runge-Kutta
+    """Clusters of at most 4096 G2 elements (ns <= 8) run whole Runge-Kutta
     steps in one persistent work-group: 300 steps against the oracle, and
     against the launched stages (row kernel) of the same library."""
     from paper_2002_12717_amd import binding as B
@@ -217,7 +217,7 @@ def test_hubbard_persistent_lattices(lib, kind, se):
     pr.close()
 
 
-@pytest.mark.parametrize("ns", [3, 7])
+@pytest.mark.parametrize("ns", [3, 8])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
 def test_hubbard_persistent_small_cluster_mixed(lib, ns, se):
     """The persistent work-group in mixed precision (binary32 G2 stage copies in
