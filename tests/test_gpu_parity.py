@@ -176,6 +176,37 @@ def test_hubbard_persistent_small_cluster(lib, ns, se):
     pr.close()
 
 
+def test_hubbard_persistent_long_call_and_one_cluster_batch(lib):
+    """A call of 2,500 steps (three launches of the persistent work-group, the
+    last one partial) against 25 calls of 100 steps of the launched stages;
+    and a batch made of one small cluster, which takes the same path, against
+    the oracle."""
+    from paper_2002_12717_amd import binding as B
+    s = hubbard_chain_system(ns=5, U=1.5, nup=2, ndn=2, dt=0.02)
+    say("[hubbard persistent] chain5 tpp, 2500 steps in one call")
+    pp = B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=s.U)
+    pr = B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    pp.step(s.dt, 2500)
+    for _ in range(25):
+        pr.step(s.dt, 100)
+    (g1p, g2p, tp), (g1r, g2r, tr) = pp.get_state(), pr.get_state()
+    say(f"   vs launched stages: G1 {rel(g1p, g1r):.2e}  G2 {rel(g2p, g2r):.2e}  t {tp} {tr}")
+    # same arithmetic; 1e-10 leaves room for rounding growth over 2,500 steps
+    assert rel(g1p, g1r) < 1e-10 and rel(g2p, g2r) < 1e-10 and abs(tp - tr) < 1e-9
+    pp.close()
+    pr.close()
+    c = hubbard_chain_system(ns=6, U=1.5, dt=0.02)
+    say("[hubbard persistent] batch of one 6-site chain, tph, 200 steps")
+    b = B.Batch(B.TPH, [c.ns], [c.U], [c.h0], [c.g1])
+    b.step(c.dt, 200)
+    y, _ = OI.propagate_hubbard(c, nsteps=200, selfenergy="tph")
+    g1, g2 = b.get_cluster(0)
+    e1, e2 = rel(g1, np.stack([y[0].numpy(), y[1].numpy()])), rel(g2, y[2].numpy())
+    say(f"   vs oracle: G1 {e1:.2e}  G2 {e2:.2e}")
+    assert e1 < 1e-10 and e2 < 1e-10
+    b.close()
+
+
 def _small_lattice(kind):
     """Two small clusters off the open chain: a 2x3 open square cluster (three
     neighbours at most, spin-dependent on-site energies) and a 6-site ring
