@@ -14,6 +14,7 @@ struct Cl {
     const cd* __restrict__ X;       // stage-input G^{<,up}
     const cd* __restrict__ Y;       // stage-input G^{<,down}
     const cd* __restrict__ hdg;     // [2][ns] diagonals of h^{HF} when precomputed, else unused
+    const double* __restrict__ hopr; // [2][ns][zmax] real parts of hop when all hoppings are real, else unused
 };
 
 __device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, const cd* hop,
@@ -31,6 +32,7 @@ __device__ __forceinline__ Cl make_cl(const ClusterDesc& d, const int* nbr, cons
     a.X = g1 + d.g1off;
     a.Y = a.X + d.ns * d.ns;
     a.hdg = nullptr;
+    a.hopr = nullptr;
     return a;
 }
 

@@ -48,8 +48,9 @@ __host__ __device__ constexpr int n_diag(int se) { return (has_pol(se) ? 6 : 0) 
 // cluster's block A = G2^{up down up down}:
 //   dA/dt = -i ( [h2_{ud}, A] + Psi + [L - (L_klij)^*] ),
 // L the particle-particle (TPP) or particle-hole (TPH) ladder, none for SOA.
-// PRE: the diagonals of h^{HF} are read from a.hdg (computed once per stage)
-template <int SE, typename TA, bool PRE = false>
+// PRE: the diagonals of h^{HF} are read from a.hdg (computed once per stage);
+// RH: every hopping is real and read from a.hopr (a real-by-complex product)
+template <int SE, typename TA, bool PRE = false, bool RH = false>
 __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, int i, int j, int k,
                                          int l, int e, cd aval) {
     const int ns = a.ns, ns2 = ns * ns, ns3 = ns2 * ns, z = a.zmax;
@@ -71,22 +72,38 @@ __device__ __forceinline__ cd hub_g2_rhs(const Cl& a, const TA* __restrict__ A, 
         el = hf_diag(a, 1, l);
     }
     cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), aval);
+    const double* hru = a.hopr;
+    const double* hrd = a.hopr + ns * z;
+    // acc + h v for a real hopping h
+    auto rfma = [](cd acc, double h, cd v) { return cmk(fma(h, v.x, acc.x), fma(h, v.y, acc.y)); };
     for (int q = 0; q < z; ++q) {
         int p = nbu[i * z + q];
-        if (p >= 0) c = cfma(c, hu[i * z + q], ld_c(A, e + (p - i) * ns3));
+        if (p >= 0) {
+            const cd v = ld_c(A, e + (p - i) * ns3);
+            c = RH ? rfma(c, hru[i * z + q], v) : cfma(c, hu[i * z + q], v);
+        }
     }
     for (int q = 0; q < z; ++q) {
         int p = nbd[j * z + q];
-        if (p >= 0) c = cfma(c, hd[j * z + q], ld_c(A, e + (p - j) * ns2));
+        if (p >= 0) {
+            const cd v = ld_c(A, e + (p - j) * ns2);
+            c = RH ? rfma(c, hrd[j * z + q], v) : cfma(c, hd[j * z + q], v);
+        }
     }
     cd r = cmk(0.0, 0.0);
     for (int q = 0; q < z; ++q) {  // sum_p A_ijpl h_pk, h_pk = conj(h_kp)
         int p = nbu[k * z + q];
-        if (p >= 0) r = cfma_conjb(r, ld_c(A, e + (p - k) * ns), hu[k * z + q]);
+        if (p >= 0) {
+            const cd v = ld_c(A, e + (p - k) * ns);
+            r = RH ? rfma(r, hru[k * z + q], v) : cfma_conjb(r, v, hu[k * z + q]);
+        }
     }
     for (int q = 0; q < z; ++q) {  // sum_p A_ijkp h_pl
         int p = nbd[l * z + q];
-        if (p >= 0) r = cfma_conjb(r, ld_c(A, e + (p - l)), hd[l * z + q]);
+        if (p >= 0) {
+            const cd v = ld_c(A, e + (p - l));
+            r = RH ? rfma(r, hrd[l * z + q], v) : cfma_conjb(r, v, hd[l * z + q]);
+        }
     }
     c = csub(c, r);
     // source Psi = U Phi / (i)^2 with Phi from eq:soa-cubic-scheme
@@ -756,12 +773,13 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // Whole Runge-Kutta steps of one small cluster in one work-group (the
 // latency-bound case: up to a few thousand G2 elements, where four launches per
 // step cost more than their work; measured on chains, one work-group beats the
-// graph-replayed launched stages 2.3x at ns = 2, 2.3x at ns = 7 and 1.13x at
+// graph-replayed launched stages 2.3x at ns = 2, 2.4x at ns = 7 and 1.21x at
 // ns = 8).  The stage input of G2 and G1 is double-buffered in LDS; y and the
 // running sum acc stay in the registers of the thread that owns the element
 // (PERSIST_PER G2 elements, their indices packed one byte each, and at most
 // one G1 element per thread); the 2 ns diagonals of h^HF are computed once per
-// stage; a step is four stages separated by work-group barriers.  Each
+// stage; with real hoppings (RH) the neighbour terms read binary64 reals; a
+// step is four stages separated by work-group barriers.  Each
 // element's right-hand side is the per-element one (hub_g2_rhs, hub_g1_rhs),
 // and the updates are those of rk_update, so the arithmetic is that of the
 // launched stages.  Single-channel closures (SOA, TPP, TPH), no drive, no
@@ -789,7 +807,7 @@ struct PersistArgs {
     int* flag;
 };
 
-template <int SE, bool MIXED>
+template <int SE, bool MIXED, bool RH>
 __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(PersistArgs p) {
     __shared__ cd sA[2][PERSIST_G2];
     float2* const sF = reinterpret_cast<float2*>(sA[1]);
@@ -798,6 +816,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
     // (a few hundred bytes, read by every element every stage) in LDS
     __shared__ int snbr[PERSIST_NBR];
     __shared__ cd shop[PERSIST_NBR];
+    __shared__ double shr[PERSIST_NBR];   // real parts of the hoppings (RH: all are real)
     __shared__ double sd0[PERSIST_G1], sxd[PERSIST_G1];
     __shared__ cd shd[16];   // diagonals of h^{HF} at the stage (2 ns <= 16)
     const ClusterDesc d = p.desc[0];
@@ -806,6 +825,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
     for (int q = tid; q < 2 * ns * d.zmax; q += PERSIST_THREADS) {
         snbr[q] = p.nbr[d.nbroff + q];
         shop[q] = p.hop[d.nbroff + q];
+        shr[q] = p.hop[d.nbroff + q].x;
     }
     if (tid < 2 * ns) sd0[tid] = p.d0[d.d0off + tid];
     if (tid < ns) sxd[tid] = p.xdrv[d.xoff + tid];
@@ -839,6 +859,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
             Cl a = make_cl(d, p.nbr, p.hop, p.d0, p.xdrv, sG[cur], 0.0, 1.0);
             a.nbr = snbr;
             a.hop = shop;
+            a.hopr = shr;
             a.d0 = sd0;
             a.xdrv = sxd;
             if (tid < 2 * ns) shd[tid] = hf_diag(a, tid / ns, tid % ns);
@@ -865,8 +886,8 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
                     asm volatile("" : "+v"(u));   // keep derived offsets out of the step loop
                     const int i = u & 255, j = (u >> 8) & 255, k = (u >> 16) & 255, l = u >> 24;
                     cd f;
-                    if (MIXED && st > 0) f = hub_g2_rhs<SE, float2, true>(a, inF, i, j, k, l, e, ld_c(inF, e));
-                    else f = hub_g2_rhs<SE, cd, true>(a, A, i, j, k, l, e, A[e]);
+                    if (MIXED && st > 0) f = hub_g2_rhs<SE, float2, true, RH>(a, inF, i, j, k, l, e, ld_c(inF, e));
+                    else f = hub_g2_rhs<SE, cd, true, RH>(a, A, i, j, k, l, e, A[e]);
                     cd o;
                     if (st == 0) {
                         acc2[q] = cmk(fma(cb, f.x, y2[q].x), fma(cb, f.y, y2[q].y));
@@ -1353,19 +1374,19 @@ bool hub_persistent_ok(const g1g2_ctx* c) {
     return ns * ns * ns * ns <= PERSIST_G2 && 2 * ns * ns <= PERSIST_G1 && 2 * ns * z <= PERSIST_NBR;
 }
 
-template <bool MIXED>
+template <bool MIXED, bool RH>
 void launch_persistent(g1g2_ctx* c, const PersistArgs& p) {
     switch (c->d.selfenergy) {
         case G1G2_TPP:
-            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPP, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPP, MIXED, RH>), dim3(1), dim3(PERSIST_THREADS), 0,
                                c->stream, p);
             break;
         case G1G2_TPH:
-            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPH, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_TPH, MIXED, RH>), dim3(1), dim3(PERSIST_THREADS), 0,
                                c->stream, p);
             break;
         default:
-            hipLaunchKernelGGL((hub_persistent_kernel<SE_SOA, MIXED>), dim3(1), dim3(PERSIST_THREADS), 0,
+            hipLaunchKernelGGL((hub_persistent_kernel<SE_SOA, MIXED, RH>), dim3(1), dim3(PERSIST_THREADS), 0,
                                c->stream, p);
             break;
     }
@@ -1377,8 +1398,14 @@ g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
     for (int64_t n = 0; n < nsteps;) {
         const int chunk = (int)std::min<int64_t>(nsteps - n, 1024);
         PersistArgs p{H.desc, H.nbr, H.hop, H.d0, H.xdrv, c->y.g1, c->y.g2, dt, chunk, c->dflag};
-        if (c->d.precision == G1G2_MIXED) launch_persistent<true>(c, p);
-        else launch_persistent<false>(c, p);
+        const bool mixed = c->d.precision == G1G2_MIXED;
+        if (H.realhop) {
+            if (mixed) launch_persistent<true, true>(c, p);
+            else launch_persistent<false, true>(c, p);
+        } else {
+            if (mixed) launch_persistent<true, false>(c, p);
+            else launch_persistent<false, false>(c, p);
+        }
         HIP_OK(c, hipGetLastError());
         n += chunk;
     }
