@@ -247,10 +247,10 @@ def run_hubbard(args, torch, B, kind):
     from workloads import adjoint_system, hubbard_chain_system
     system = hubbard_chain_system(ns=args.ns) if kind == "hubbard_chain" else adjoint_system()
     ns = system.ns
-    # one SOA/TPP/TPH cluster of at most 4,096 G2 elements with no drive runs whole
+    # one SOA/TPP/TPH cluster of at most 2,401 G2 elements with no drive runs whole
     # steps in the persistent single-work-group kernel (both precisions); the per-launch
     # profile below always times the launched stages
-    persistent = (ns ** 4 <= 4096 and system.drive is None and (args.selfenergy or "soa")
+    persistent = (ns ** 4 <= 2401 and system.drive is None and (args.selfenergy or "soa")
                   in ("soa", "tpp", "tph"))
     stream = torch.cuda.Stream()
     se = args.selfenergy or "soa"
@@ -579,7 +579,7 @@ def main():
                          "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
                          "tpp, tph or dsl (default dsl)")
     ap.add_argument("--ns", type=int, default=8,
-                    help="hubbard_chain: number of sites (default 8; 2-8 take the persistent kernel)")
+                    help="hubbard_chain: number of sites (default 8; 2-7 take the persistent kernel)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

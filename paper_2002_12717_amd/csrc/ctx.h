@@ -147,7 +147,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* ns, const double* U, cons
 void hub_free(g1g2_ctx* c);
 // Whole RK4 steps of one small single-channel cluster in one persistent
 // work-group (ns^4 <= 4096, binary64, no drive or ramp, no kernel flag).
-// Whole RK4 steps of one small cluster (SOA, TPP or TPH, ns <= 8, no drive, no
+// Whole RK4 steps of one small cluster (SOA, TPP or TPH, ns <= 7, no drive, no
 // switching ramp, no per-launch profile) in one persistent work-group: whether
 // the context qualifies, and nsteps steps of size dt on its state.
 bool hub_persistent_ok(const g1g2_ctx* c);

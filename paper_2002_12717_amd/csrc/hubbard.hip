@@ -586,6 +586,13 @@ constexpr int SLICE_DIAG = 128;
 // below this many G2 elements in all, the row kernel is the default: whole
 // slices would give too few work-groups
 constexpr long long SLICE_MIN_ELEMS = 1LL << 20;
+// except for one small cluster with a single-channel closure (at most
+// SMALL_SLICE_MAX elements): the slice kernel in items of at most SLICE_SMALL
+// elements, which spreads a stage over enough work-groups (measured on the
+// 8-site chain: SOA 62k, TPP 55k and TPH 36k steps/s, against 28k, 22k and 18k
+// for the row kernel and 34k, 27k and 28k for the persistent work-group)
+constexpr long long SMALL_SLICE_MAX = 4096;
+constexpr int SLICE_SMALL = 256;
 
 // n / d for n < 2^16 and 1 <= d <= 4096, with mg = slice_magic(d)
 __host__ __device__ constexpr unsigned slice_magic(unsigned d) { return d == 1 ? 0u : 0xffffffffu / d + 1u; }
@@ -773,8 +780,8 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
 // Whole Runge-Kutta steps of one small cluster in one work-group (the
 // latency-bound case: up to a few thousand G2 elements, where four launches per
 // step cost more than their work; measured on chains, one work-group beats the
-// graph-replayed launched stages 2.3x at ns = 2, 2.4x at ns = 7 and 1.21x at
-// ns = 8).  The stage input of G2 and G1 is double-buffered in LDS; y and the
+// graph-replayed row-kernel stages 2.3x at ns = 2 and 2.4x at ns = 7; the
+// kernel holds up to 4,096 elements, and is dispatched up to ns = 7).  The stage input of G2 and G1 is double-buffered in LDS; y and the
 // running sum acc stay in the registers of the thread that owns the element
 // (PERSIST_PER G2 elements, their indices packed one byte each, and at most
 // one G1 element per thread); the 2 ns diagonals of h^HF are computed once per
@@ -793,6 +800,9 @@ constexpr int PERSIST_G2 = 4096;   // ns^4 <= 4096: ns <= 8
 constexpr int PERSIST_G1 = 128;    // 2 ns^2
 constexpr int PERSIST_PER = PERSIST_G2 / PERSIST_THREADS;
 constexpr int PERSIST_NBR = 128;   // 2 ns zmax: neighbour table and hoppings, staged in LDS
+// the dispatcher takes the persistent work-group up to ns = 7 (2,401 elements);
+// at ns = 8 the slice kernel in small items is faster (SMALL_SLICE_MAX)
+constexpr int PERSIST_MAX_G2 = 2401;
 
 struct PersistArgs {
     const ClusterDesc* desc;
@@ -1234,8 +1244,9 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         return set_error(c, G1G2_EINVAL, "G1G2_HUB_ROW_KERNEL and G1G2_HUB_SLICE_KERNEL exclude each other");
     long long total = 0;
     for (int cl = 0; cl < ncl; ++cl) total += (long long)nsv[cl] * nsv[cl] * nsv[cl] * nsv[cl];
+    const bool small1 = ncl == 1 && nch == 1 && total <= SMALL_SLICE_MAX;
     const bool slicek = rowk && !(fl & G1G2_HUB_ROW_KERNEL) &&
-                        ((fl & G1G2_HUB_SLICE_KERNEL) || total * nch >= SLICE_MIN_ELEMS);
+                        ((fl & G1G2_HUB_SLICE_KERNEL) || total * nch >= SLICE_MIN_ELEMS || small1);
     long long g2off = 0;
     long long g1off = 0, xoff = 0, doff = 0;
     for (int cl = 0; cl < ncl; ++cl) {
@@ -1285,6 +1296,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
             int per = SLICE_ELEMS / (ns * ns);
             // the particle-particle ladder keeps the diagonal entries of its slices in LDS
             if (has_pp(se)) per = std::max(1, std::min(per, SLICE_DIAG / ns));
+            if (small1) per = std::max(1, std::min(per, SLICE_SMALL / (ns * ns)));
             const int nsl = ns * ns;
             chunks[cl] = per * ns * ns;
             for (int chn = 0; chn < nch; ++chn)
@@ -1371,7 +1383,7 @@ bool hub_persistent_ok(const g1g2_ctx* c) {
     const int sel = c->d.selfenergy;
     if (sel != G1G2_SOA && sel != G1G2_TPP && sel != G1G2_TPH) return false;
     const long long ns = H.hdesc[0].ns, z = H.hdesc[0].zmax;
-    return ns * ns * ns * ns <= PERSIST_G2 && 2 * ns * ns <= PERSIST_G1 && 2 * ns * z <= PERSIST_NBR;
+    return ns * ns * ns * ns <= PERSIST_MAX_G2 && 2 * ns * ns <= PERSIST_G1 && 2 * ns * z <= PERSIST_NBR;
 }
 
 template <bool MIXED, bool RH>

@@ -158,9 +158,11 @@ def test_hubbard_chain_full_trajectory(lib):
 @pytest.mark.parametrize("ns", [2, 3, 5, 7, 8])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
 def test_hubbard_persistent_small_cluster(lib, ns, se):
-    """Clusters of at most 4096 G2 elements (ns <= 8) run whole Runge-Kutta
-    steps in one persistent work-group: 300 steps against the oracle, and
-    against the launched stages (row kernel) of the same library."""
+    """Clusters of at most 2401 G2 elements (ns <= 7) run whole Runge-Kutta
+    steps in one persistent work-group; at ns = 8 the default is the slice
+    kernel in items of at most 256 elements, checked the same way.  Each case:
+    300 steps against the oracle, and against the row-kernel stages of the
+    same library."""
     from paper_2002_12717_amd import binding as B
     s = hubbard_chain_system(ns=ns, U=1.5, nup=max(1, ns // 2), ndn=max(1, ns // 2), dt=0.02)
     say(f"[hubbard persistent] chain{ns} {se} 300 steps")
