@@ -1,17 +1,20 @@
 """Benchmark of the G1-G2 hot path on one MI355X.
 
-Default workload (the configuration the headline metric is quoted on):
-general-basis second-Born G1-G2 propagation, Nb = 32 spin orbitals, random GUE
-h (sigma = 1), w = sum_Q B^Q x B^Q from a rank-64 Hermitian factor, 8 particles
-in the Aufbau state of h, G2(0) = 0, RK4 with dt = 0.01.  Inputs are seeded and
-synthetic (workloads.general_system).
+Default workload (the headline: the largest single-GPU configuration of the
+metric): general-basis GW G1-G2 propagation, Nb = 64 spin orbitals (G2 is
+64^4 complex, 268 MB in binary64), random GUE h (sigma = 1), w = sum_Q B^Q x
+B^Q from a rank-128 Hermitian factor, 16 particles in the Aufbau state of h,
+G2(0) = 0, a one-step kick dh = 0.1 GUE, RK4 with dt = 0.01 (500 steps).
+Inputs are seeded and synthetic (workloads.gw_system).
 
 One "step" = one full RK4 step (four right-hand sides) of G1 and G2.  The
 binary64 path is the headline value; the mixed path (binary32 matrix-core
-contractions, binary64 state) is reported beside it with its error against
-the binary64 run.  Other workloads of the paper's shape are available with
---workload (hubbard_chain, with --ns for the chain length; hubbard_2d, hubbard_batch,
-hubbard_adjoint, general_gw, general_ladder, scaling).
+contractions, binary64 state) is reported beside it, with the errors of both
+against the binary64 run over the whole 500-step propagation (and against the
+stored oracle trajectory of tests/golden/ when present).  The Nb = 32 SOA
+workload is reported as an extra key.  Other workloads of the paper's shape
+are available with --workload (general_soa, general_ladder, hubbard_chain with
+--ns, hubbard_2d, hubbard_batch, hubbard_adjoint, scaling).
 
 Prints ONE JSON line.
 """
@@ -111,6 +114,7 @@ def timed_steps(p, dt, steps, warmup, stream, torch):
     """Wall and event time of `steps` RK4 steps after `warmup` steps."""
     if warmup:
         p.step(dt, warmup)
+    p.prepare_graph(dt)             # the replayed graph is captured before the timed region
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -129,6 +133,53 @@ def timed_steps(p, dt, steps, warmup, stream, torch):
 
 def kernel_table(prof: dict) -> dict:
     return {k: {"ms_avg": round(v[0] / max(v[1], 1), 6), "launches": v[1]} for k, v in prof.items()}
+
+
+def host_info() -> dict:
+    """CPU model, logical CPUs and the BLAS that torch's CPU kernels call."""
+    import torch
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    for line in torch.__config__.show().splitlines():
+        if "Math Kernel Library" in line or "OpenBLAS" in line:
+            blas = line.strip(" -")
+            break
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas,
+            "torch_threads": torch.get_num_threads()}
+
+
+def cpu_baseline_gw(system, seconds: float = 12.0):
+    """The FP64 oracle's right-hand side of the Nb = 64 GW workload on the host
+    cores (at the initial state; the cost of every term is independent of the
+    values), timed over a bounded number of evaluations; an RK4 step is four."""
+    import torch
+    from oracle import general as OG
+    nthreads = torch.get_num_threads()
+    T = lambda x: torch.as_tensor(x, dtype=torch.complex128)  # noqa: E731
+    h, w, g1 = T(system.h0), T(system.w), T(system.g1)
+    g2 = torch.zeros((system.nb,) * 4, dtype=torch.complex128)
+    OG.rhs(h, w, g1, g2, "gw")                      # warm-up
+    n, t0 = 0, time.perf_counter()
+    while True:
+        OG.rhs(h, w, g1, g2, "gw")
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds or n >= 20:
+            break
+    per_rhs = el / n
+    return {"value": round(1.0 / (4.0 * per_rhs), 5), "unit": "RK4 steps/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{n} right-hand sides of the Nb=64 GW workload (torch CPU complex128, {nthreads} "
+                      f"threads, {el:.1f} s, {per_rhs:.2f} s each), four per RK4 step",
+            "host": host_info()}
 
 
 def cpu_baseline_general(system, seconds: float = 15.0):
@@ -150,7 +201,7 @@ def cpu_baseline_general(system, seconds: float = 15.0):
             break
     return {"value": round(n / el, 4), "unit": "RK4 steps/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} RK4 steps of the Nb=32 SOA workload from t=0 (torch CPU complex128, "
-                      f"{nthreads} threads, {el:.1f} s)"}
+                      f"{nthreads} threads, {el:.1f} s)", "host": host_info()}
 
 
 def cpu_baseline_hubbard(system, seconds: float = 15.0, selfenergy: str = "soa"):
@@ -180,12 +231,84 @@ def base_line(args, steps_per_s, ms_step, dtype, config):
 
 
 # --------------------------------------------------------------------------- workloads
-def run_general(args, torch, B, se="soa"):
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def trajectory(B, system, code, prec, stream, nsteps, stops):
+    """Propagate the workload from t = 0 (one-step kick included) for nsteps
+    steps; G1 and E_tot at every step in `stops` (and at 0 and nsteps)."""
+    p = B.Propagator(B.GENERAL, code, system.nb, system.h0, system.g1, w=system.w, precision=prec,
+                     stream=stream.cuda_stream)
+    stops = sorted(set(q for q in stops if 0 < q <= nsteps) | {nsteps})
+    out = {}
+
+    def record(n):
+        g1, _, _ = p.get_state(with_g2=False)
+        out[n] = (g1, p.observables()["E_tot"])
+
+    record(0)
+    n = 0
+    if system.kick is not None:
+        p.set_h0(system.h0 + system.kick)
+        p.step(system.dt, 1)
+        p.set_h0(system.h0)
+        n = 1
+        if 1 in stops:
+            record(1)
+    for q in stops:
+        if q > n:
+            p.step(system.dt, q - n)
+            n = q
+            record(n)
+    p.close()
+    return out
+
+
+def trajectory_error(a, ref):
+    """Max over common times of max|dG1| / max|G1_ref| and |dE| / max(|E_ref(0)|, 1)."""
+    import numpy as np
+    common = sorted(set(a) & set(ref))
+    e_scale = max(abs(ref[0][1]), 1.0)
+    eg = max(float(np.abs(a[n][0] - ref[n][0]).max() / np.abs(ref[n][0]).max()) for n in common)
+    ee = max(abs(a[n][1] - ref[n][1]) / e_scale for n in common)
+    return {"G1": eg, "E": ee, "steps_compared": len(common)}
+
+
+def golden_error(traj, g):
+    """Errors of a trajectory against the stored oracle trajectory: G1 in full
+    where stored, at the stored entries elsewhere; E where stored."""
+    import numpy as np
+    eg, ee, n_g1 = 0.0, 0.0, 0
+    e_scale = max(abs(float(g["E_tot"][0])), 1.0)
+    for k, n in enumerate(g["full_steps"]):
+        if int(n) in traj:
+            ref = g["full_g1"][k]
+            eg = max(eg, float(np.abs(traj[int(n)][0] - ref).max() / np.abs(ref).max()))
+            n_g1 += 1
+    if "g1_idx" in g.files:
+        idx = g["g1_idx"]
+        for k, n in enumerate(g["samp_steps"]):
+            if int(n) in traj:
+                got = traj[int(n)][0][idx[:, 0], idx[:, 1]]
+                eg = max(eg, float(np.abs(got - g["samp_g1"][k]).max() / g["samp_scale"][k]))
+                n_g1 += 1
+    n_e = 0
+    for k, n in enumerate(g["obs_steps"]):
+        if int(n) in traj:
+            ee = max(ee, abs(traj[int(n)][1] - float(g["E_tot"][k])) / e_scale)
+            n_e += 1
+    return {"G1": eg, "E": ee, "G1_times": n_g1, "E_times": n_e}
+
+
+def run_general(args, torch, B, se="soa", accuracy=True, steps=None, warmup=None, profile_steps=None):
     import numpy as np
     from workloads import general_system, gw_system
     gw = se != "soa"               # every closure beyond SOA runs on the Nb = 64 system
     system = gw_system() if gw else general_system()
     nb = system.nb
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    profile_steps = args.profile_steps if profile_steps is None else profile_steps
     stream = torch.cuda.Stream()
     fl = soa_flops(nb) if se == "soa" else (gw_flops(nb) if se == "gw" else ladder_flops(nb, se))
     code = {"soa": B.SOA, "gw": B.GW, "tpp": B.TPP, "tph": B.TPH, "dsl": B.DSL}[se]
@@ -197,48 +320,78 @@ def run_general(args, torch, B, se="soa"):
             p.set_h0(system.h0 + system.kick)
             p.step(system.dt, 1)
             p.set_h0(system.h0)
-        ms, wall = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
-        g1, _, t = p.get_state()
-        obs = p.observables()
-        prof = p.profile(system.dt, args.profile_steps)
-        res[prec] = dict(ms=ms, wall=wall, g1=g1, obs=obs, prof=prof, t=t)
+        ms, wall = timed_steps(p, system.dt, steps, warmup, stream, torch)
+        prof = p.profile(system.dt, profile_steps)
+        res[prec] = dict(ms=ms, wall=wall, prof=prof)
         p.close()
     f64, mx = res["fp64"], res["mixed"]
-    ms_step = f64["ms"] / args.steps
-    mx_step = mx["ms"] / args.steps
+    ms_step = f64["ms"] / steps
+    mx_step = mx["ms"] / steps
     dom = "gen_gemm" if gw else "gen_main"
     tot_ms, cnt = f64["prof"][dom]
     achieved = fl[dom] * cnt / (tot_ms * 1e-3) / 1e12
     rhs_flops = fl["total"] if gw else fl["soa_total"]
     config = {"workload": (f"general-basis {se.upper()} G1-G2, Nb={nb} spin orbitals, "
                            f"rank-{system.meta['rank']} w, {system.meta['nocc']} particles, "
-                           f"dt={system.dt}, RK4"),
+                           + ("one-step kick 0.1 GUE, " if system.kick is not None else "")
+                           + f"dt={system.dt}, RK4, {system.nsteps} steps"),
               "nb": nb, "rank": system.meta["rank"], "nocc": system.meta["nocc"], "dt": system.dt,
-              "selfenergy": se.upper(), "parallelism": "single GPU"}
+              "nsteps": system.nsteps, "selfenergy": se.upper(), "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    out["steps"], out["warmup"] = steps, warmup
     mx_tot, mx_cnt = mx["prof"][dom]
     mx_ach = fl[dom] * mx_cnt / (mx_tot * 1e-3) / 1e12
     out.update({
         "g2_rhs_tflops": round(4 * rhs_flops / (ms_step * 1e-3) / 1e12, 3),
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_MFMA, 4),
-                     "traffic": None if gw else traffic("gen_main/f64"), "kernel_ms_avg": round(tot_ms / cnt, 6),
+                     "traffic": traffic("gen_gemm/f64") if gw else traffic("gen_main/f64"),
+                     "kernel_ms_avg": round(tot_ms / cnt, 6),
                      "flop_per_launch": fl[dom], "launches": cnt},
         "kernels": kernel_table(f64["prof"]),
         "mixed": {"dtype": "f32 contractions / f64 state", "value": round(1e3 / mx_step, 3),
                   "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
                   "g2_rhs_tflops": round(4 * rhs_flops / (mx_step * 1e-3) / 1e12, 3),
-                  "err_G1_vs_fp64": float(np.abs(mx["g1"] - f64["g1"]).max() / np.abs(f64["g1"]).max()),
-                  "err_E_vs_fp64": abs(mx["obs"]["E_tot"] - f64["obs"]["E_tot"])
-                  / max(abs(f64["obs"]["E_tot"]), 1.0),
                   "roofline": {"kernel": dom, "achieved": round(mx_ach, 3), "peak": PEAK_FP32_MFMA,
                                "unit": "TFLOP/s", "frac": round(mx_ach / PEAK_FP32_MFMA, 4),
-                               "traffic": None if gw else traffic("gen_main/f32")},
+                               "traffic": traffic("gen_gemm/f32") if gw else traffic("gen_main/f32")},
                   "kernels": kernel_table(mx["prof"])},
-        "sim_time": f64["t"],
     })
-    if not args.no_cpu_baseline and not gw:
-        out["cpu_baseline"] = cpu_baseline_general(system)
+    if accuracy and se in ("soa", "gw"):
+        every = 25 if gw else 50
+        gname = "general_gw_nb64.npz" if gw else "general_soa_nb32.npz"
+        gpath = os.path.join(GOLDEN, gname)
+        g = np.load(gpath) if os.path.exists(gpath) else None
+        stops = set(range(every, system.nsteps + 1, every))
+        if g is not None:
+            stops |= set(int(n) for n in g["full_steps"]) | set(int(n) for n in g["samp_steps"])
+        tr = {prec: trajectory(B, system, code, B.FP64 if prec == "fp64" else B.MIXED, stream,
+                               system.nsteps, stops) for prec in ("fp64", "mixed")}
+        mvf = trajectory_error(tr["mixed"], tr["fp64"])
+        acc = {"steps": system.nsteps, "mixed_vs_fp64": mvf}
+        if g is not None:
+            acc["fp64_vs_oracle"] = golden_error(tr["fp64"], g)
+            acc["mixed_vs_oracle"] = golden_error(tr["mixed"], g)
+            acc["oracle_trajectory"] = f"tests/golden/{gname} (written by tests/golden/make_golden.py)"
+        out["accuracy"] = acc
+        out["mixed"]["err_G1_vs_fp64"] = mvf["G1"]
+        out["mixed"]["err_E_vs_fp64"] = mvf["E"]
+    if not args.no_cpu_baseline:
+        if se == "gw":
+            out["cpu_baseline"] = cpu_baseline_gw(system)
+        elif se == "soa":
+            out["cpu_baseline"] = cpu_baseline_general(system)
+    return out
+
+
+def summary(line: dict) -> dict:
+    """The compact form of a workload's line, for an extra key of the headline."""
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "g2_rhs_tflops",
+            "roofline", "accuracy")
+    out = {k: line[k] for k in keep if k in line}
+    m = line.get("mixed", {})
+    out["mixed"] = {k: m[k] for k in ("value", "ms_per_step", "speedup_vs_fp64", "err_G1_vs_fp64",
+                                      "err_E_vs_fp64", "roofline") if k in m}
     return out
 
 
@@ -247,11 +400,6 @@ def run_hubbard(args, torch, B, kind):
     from workloads import adjoint_system, hubbard_chain_system
     system = hubbard_chain_system(ns=args.ns) if kind == "hubbard_chain" else adjoint_system()
     ns = system.ns
-    # one SOA/TPP/TPH cluster of at most 2,401 G2 elements with no drive runs whole
-    # steps in the persistent single-work-group kernel (both precisions); the per-launch
-    # profile below always times the launched stages
-    persistent = (ns ** 4 <= 2401 and system.drive is None and (args.selfenergy or "soa")
-                  in ("soa", "tpp", "tph"))
     stream = torch.cuda.Stream()
     se = args.selfenergy or "soa"
 
@@ -261,14 +409,18 @@ def run_hubbard(args, torch, B, kind):
         if system.drive is not None:
             d = system.drive
             p.set_drive(d.x, d.c, d.t_center, d.tau)
+        path = p.step_path()        # the library's own choice of kernels for these steps
         ms, _ = timed_steps(p, system.dt, args.steps, args.warmup, stream, torch)
         prof = p.profile(system.dt, args.profile_steps)
         obs = p.observables()
         g1, _, _ = p.get_state()
         p.close()
-        return ms, prof, obs, g1
+        return ms, prof, obs, g1, path
 
-    ms, prof, obs, g1_64 = run(B.FP64)
+    ms, prof, obs, g1_64, path = run(B.FP64)
+    # a small cluster runs whole steps in the persistent work-group: its time is
+    # not that of the launched stages the per-launch profile times
+    persistent = path == "hub_persistent"
     ms_step = ms / args.steps
     n4 = float(ns) ** 4
     tot_ms, cnt = prof["hub_stage"]
@@ -281,23 +433,25 @@ def run_hubbard(args, torch, B, kind):
               "ns": ns, "U": system.U, "dt": system.dt, "selfenergy": se.upper(),
               "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    stage_roof = {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
+                  "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                  # the counters were taken on the SOA instantiation
+                  "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" and se == "soa" else None,
+                  "kernel_ms_avg": round(tot_ms / cnt, 6),
+                  "bytes_per_launch": bytes_per_launch, "launches": cnt}
     out.update({
-        "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
-                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                     # the counters were taken on the SOA instantiation
-                     "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" and se == "soa" else None,
-                     "kernel_ms_avg": round(tot_ms / cnt, 6),
-                     "bytes_per_launch": bytes_per_launch, "launches": cnt},
+        "path": path,
+        # the persistent kernel keeps the state on chip: no HBM roofline applies
+        # to it (it is bound by its LDS reads and barriers), so none is reported
+        "roofline": None if persistent else stage_roof,
         "kernels": kernel_table(prof),
         "observables": {k: obs[k] for k in ("t", "E_tot", "docc")},
     })
     if persistent:
-        out["path"] = ("hub_persistent_kernel (whole RK4 steps in one work-group, binary64 and "
-                       "mixed); the roofline entries are of the launched stages, timed by the "
-                       "per-launch profile")
+        out["launched_stage_roofline"] = stage_roof
     # mixed precision: binary32 G2 stage copies, 52 B per element and launch
     # (binary64 y and acc, binary32 stage input and output)
-    mx_ms, mx_prof, mx_obs, g1_mx = run(B.MIXED)
+    mx_ms, mx_prof, mx_obs, g1_mx, _ = run(B.MIXED)
     mx_step = mx_ms / args.steps
     mx_tot, mx_cnt = mx_prof["hub_stage"]
     mx_ach = 52.0 * n4 * HUB_CHANNELS[se] * mx_cnt / (mx_tot * 1e-3) / 1e9
@@ -532,6 +686,8 @@ def run_adjoint(args, torch, B):
     L2, g2c, g2U = p.adjoint(a_imb, b_imb, nmodes)
     t3 = time.perf_counter()
     obs = p.observables()
+    # per-kernel times of one more reverse sweep (events after every launch)
+    aprof = p.profile_adjoint(a_docc, b_docc)
     prof = p.profile(s.dt, args.profile_steps)
     p.close()
     fwd_ms = (t1 - t0) * 1e3
@@ -541,6 +697,13 @@ def run_adjoint(args, torch, B):
     tot_ms, cnt = prof["hub_stage"]
     bytes_per_launch = 64.0 * float(ns) ** 4
     achieved = bytes_per_launch * cnt / (tot_ms * 1e-3) / 1e9
+    # adj_slice_red, the reverse sweep's dominant kernel: per G2 element it reads
+    # the cotangent, the stage state, lambda and the running sum and writes the
+    # running sum and the next cotangent where the stage has them: 64, 96, 96
+    # and 64 B over the four stages of a step, 80 B per launch on average
+    a_tot, a_cnt = aprof["adj_slice_red"]
+    a_bytes = 80.0 * float(ns) ** 4
+    a_ach = a_bytes * a_cnt / (a_tot * 1e-3) / 1e9
     config = {"workload": f"gradient of the final-time mean double occupation and density imbalance "
                           f"of the driven 8x8 Hubbard cluster (SOA, U={s.U}, {nmodes} Gaussian pulses) "
                           f"with respect to the pulse coefficients and U, checkpointed discrete adjoint "
@@ -551,10 +714,15 @@ def run_adjoint(args, torch, B):
     out["unit"] = "gradient RK4 steps/s"
     out.update({
         "forward_ms": round(fwd_ms, 3), "reverse_ms_per_loss": round(rev_ms, 3),
-        "roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
-                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                     "traffic": None, "kernel_ms_avg": round(tot_ms / cnt, 6),
-                     "bytes_per_launch": bytes_per_launch, "launches": cnt},
+        "roofline": {"kernel": "adj_slice_red", "bound": "hbm", "achieved": round(a_ach, 2),
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": round(a_ach / PEAK_HBM, 4),
+                     "traffic": None, "kernel_ms_avg": round(a_tot / a_cnt, 6),
+                     "bytes_per_launch": a_bytes, "launches": a_cnt},
+        "forward_roofline": {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
+                             "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
+                             "kernel_ms_avg": round(tot_ms / cnt, 6), "bytes_per_launch": bytes_per_launch,
+                             "launches": cnt},
+        "adjoint_kernels": kernel_table(aprof),
         "losses": {"docc": L1, "imbalance": L2},
         "grad_norms": {"docc_c": float(np.linalg.norm(g1c)), "docc_U": g1U,
                        "imbalance_c": float(np.linalg.norm(g2c)), "imbalance_U": g2U},
@@ -568,10 +736,16 @@ def run_adjoint(args, torch, B):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--workload", default="general_soa",
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed RK4 steps (default: 40 for general_gw and general_ladder, 500 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps before them (default 8 / 20)")
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="steps of the per-launch profile (default 8 for the Nb = 64 workloads, 50 otherwise)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the full-length accuracy runs of the general workloads")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="general_gw: skip the Nb = 32 SOA line reported beside the headline")
+    ap.add_argument("--workload", default="general_gw",
                     choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
                              "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "scaling"])
     ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
@@ -586,18 +760,28 @@ def main():
         print("bench.py measures one GPU only: this G1-G2 workload runs on a single MI355X; "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    big = args.workload in ("general_gw", "general_ladder")
+    if args.steps is None:
+        args.steps = 40 if big else 500
+    if args.warmup is None:
+        args.warmup = 8 if big else 20
+    if args.profile_steps is None:
+        args.profile_steps = 8 if big else 50
     import torch
     from paper_2002_12717_amd import binding as B
     torch.cuda.set_device(0)
     if args.workload == "general_soa":
-        out = run_general(args, torch, B)
+        out = run_general(args, torch, B, accuracy=not args.no_accuracy)
     elif args.workload == "general_gw":
-        out = run_general(args, torch, B, se="gw")
+        out = run_general(args, torch, B, se="gw", accuracy=not args.no_accuracy)
+        if not args.no_extra:   # the Nb = 32 SOA workload beside it, its own step counts
+            out["general_soa_nb32"] = summary(run_general(args, torch, B, se="soa", accuracy=not args.no_accuracy,
+                                                          steps=500, warmup=20, profile_steps=50))
     elif args.workload == "general_ladder":
         se = args.selfenergy or "dsl"
         if se not in ("tpp", "tph", "dsl"):
             ap.error("general_ladder takes --selfenergy tpp, tph or dsl")
-        out = run_general(args, torch, B, se=se)
+        out = run_general(args, torch, B, se=se, accuracy=False)
     elif args.workload == "hubbard_batch":
         out = run_batch(args, torch, B)
     elif args.workload == "scaling":

@@ -128,8 +128,12 @@ typedef struct {
     double imbalance;       /* Hubbard: (N_left - N_right) / N with left/right the
                                sites of negative/positive drive profile x_i
                                (g1g2_set_drive); 0 without a drive profile      */
-    int32_t diverged;       /* 1 once the divergence guard has fired                */
+    int32_t diverged;       /* 1 once the divergence guard has fired (for this
+                               cluster, in g1g2_batch_observables)                 */
     int64_t step;           /* completed Runge-Kutta steps                          */
+    int64_t diverged_step;  /* the first step at whose end the guard fired (the
+                               count of completed steps then), -1 if it has not;
+                               cleared by g1g2_set_state                          */
 } g1g2_obs;
 
 typedef struct g1g2_ctx g1g2_ctx;
@@ -152,9 +156,36 @@ g1g2_status g1g2_rhs(g1g2_ctx* ctx, double t, const void* G1, const void* G2,
                      void* dG1, void* dG2);
 
 /* Advance the internal state by nsteps classical fourth-order Runge-Kutta
- * steps of size dt (h0(t) and U evaluated at the stage times).  Returns
- * EDIVERGED (state kept, step count in g1g2_obs.step) when the guard fires. */
+ * steps of size dt (h0(t) and U evaluated at the stage times).  The guard
+ * checks G1 at the end of every step: a non-finite element or an occupation
+ * outside [-0.5, 1.5] marks the cluster (the general basis is one cluster)
+ * with the number of that step.  All nsteps steps still run; then the call
+ * returns EDIVERGED, and g1g2_last_error names the first step and cluster
+ * (g1g2_obs.diverged / diverged_step per cluster).  With a stream, whole
+ * groups of 8 steps replay one captured HIP graph (captured at the first call
+ * with 8 or more steps, again only when dt changes).                        */
 g1g2_status g1g2_step_rk4(g1g2_ctx* ctx, double dt, int64_t nsteps);
+
+/* Which kernels g1g2_step_rk4 uses for this context, as decided by the
+ * library (sizes, selfenergy, flags, drive and switching ramp as they are
+ * now): GENERAL (the general-basis matrix-core stages), HUB_PERSISTENT
+ * (whole steps of one small Hubbard cluster in one work-group), HUB_SLICE,
+ * HUB_ROW or HUB_ELEMENT (one launch per Runge-Kutta stage).               */
+enum {
+    G1G2_PATH_GENERAL = 0,
+    G1G2_PATH_HUB_PERSISTENT = 1,
+    G1G2_PATH_HUB_SLICE = 2,
+    G1G2_PATH_HUB_ROW = 3,
+    G1G2_PATH_HUB_ELEMENT = 4
+};
+g1g2_status g1g2_step_path(const g1g2_ctx* ctx, int32_t* path);
+
+/* Capture now the HIP graph of 8 steps of size dt that g1g2_step_rk4
+ * replays, so that no later call pays for the capture (before a timed or
+ * latency-bound loop).  Returns OK and does nothing when steps are not
+ * replayed from graphs: no stream given, a drive or switching ramp set, or
+ * the persistent small-cluster kernel takes the steps.  EINVAL for dt <= 0. */
+g1g2_status g1g2_prepare_graph(g1g2_ctx* ctx, double dt);
 
 /* Observables of the current state; synchronizes the stream. */
 g1g2_status g1g2_observables(g1g2_ctx* ctx, g1g2_obs* out);
@@ -249,6 +280,11 @@ g1g2_status g1g2_adjoint(g1g2_ctx* ctx, const double* a, const double* b, double
 g1g2_status g1g2_profile(g1g2_ctx* ctx, double dt, int64_t nsteps, int32_t max_kernels,
                          double* ms_total, int32_t* launches, int32_t* count);
 const char* g1g2_profile_name(const g1g2_ctx* ctx, int32_t k);
+/* The same per-kernel timing for one reverse sweep of g1g2_adjoint with the
+ * loss weights a, b (after g1g2_forward_checkpointed; the gradients are not
+ * returned, the final state is left in place).  Errors as g1g2_adjoint.     */
+g1g2_status g1g2_profile_adjoint(g1g2_ctx* ctx, const double* a, const double* b, int32_t max_kernels,
+                                 double* ms_total, int32_t* launches, int32_t* count);
 
 void g1g2_destroy(g1g2_ctx* ctx);
 const char* g1g2_strerror(g1g2_status status);

@@ -21,6 +21,7 @@ SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL, DSL_EXCHANGE = 1, 2, 4, 8, 16
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
+PATHS = {0: "general", 1: "hub_persistent", 2: "hub_slice", 3: "hub_row", 4: "hub_element"}
 
 
 class Desc(ctypes.Structure):
@@ -32,7 +33,7 @@ class Obs(ctypes.Structure):
     _fields_ = [("t", c_double), ("N", c_double * 2), ("E_kin", c_double), ("E_mf", c_double),
                 ("E_corr", c_double), ("E_tot", c_double), ("docc", c_double),
                 ("herm_resid", c_double), ("exch_resid", c_double), ("imbalance", c_double),
-                ("diverged", c_int32), ("step", c_int64)]
+                ("diverged", c_int32), ("step", c_int64), ("diverged_step", c_int64)]
 
 
 _SIGS = {
@@ -51,6 +52,10 @@ _SIGS = {
     "g1g2_profile": (c_int32, [c_void_p, c_double, c_int64, c_int32, c_void_p, c_void_p,
                                POINTER(c_int32)]),
     "g1g2_profile_name": (ctypes.c_char_p, [c_void_p, c_int32]),
+    "g1g2_profile_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                       POINTER(c_int32)]),
+    "g1g2_prepare_graph": (c_int32, [c_void_p, c_double]),
+    "g1g2_step_path": (c_int32, [c_void_p, POINTER(c_int32)]),
     "g1g2_batch_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_int32, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p]),
     "g1g2_batch_observables": (c_int32, [c_void_p, c_void_p]),
@@ -164,19 +169,21 @@ class Propagator:
         self._check(self.lib.g1g2_observables(self.ctx, ctypes.byref(o)))
         return dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
                     E_tot=o.E_tot, docc=o.docc, herm_resid=o.herm_resid, exch_resid=o.exch_resid,
-                    imbalance=o.imbalance, diverged=o.diverged, step=o.step)
+                    imbalance=o.imbalance, diverged=o.diverged, step=o.step,
+                    diverged_step=o.diverged_step)
 
     def site_observables(self):
         nu, nd, dc = (np.zeros(self.nb) for _ in range(3))
         self._check(self.lib.g1g2_site_observables(self.ctx, _ptr(nu), _ptr(nd), _ptr(dc)))
         return nu, nd, dc
 
-    def get_state(self, G1=None, G2=None):
-        """Copy the state out; host numpy arrays are allocated when not given."""
+    def get_state(self, G1=None, G2=None, with_g2: bool = True):
+        """Copy the state out; host numpy arrays are allocated when not given
+        (with_g2=False copies G1 and t only)."""
         s1, s2 = self.shapes()
         if G1 is None:
             G1 = np.zeros(s1, np.complex128)
-        if G2 is None and not (self.flags & PTR_DEVICE):
+        if G2 is None and with_g2 and not (self.flags & PTR_DEVICE):
             G2 = np.zeros(s2, np.complex128)
         t = c_double()
         self._check(self.lib.g1g2_get_state(self.ctx, _ptr(G1), _ptr(G2), ctypes.byref(t)))
@@ -228,6 +235,29 @@ class Propagator:
         return {self.lib.g1g2_profile_name(self.ctx, k).decode(): (float(ms[k]), int(cnt[k]))
                 for k in range(n.value)}
 
+    def profile_adjoint(self, a, b) -> dict:
+        """Per-kernel time of one reverse sweep (after forward_checkpointed):
+        {name: (total_ms, launches)}."""
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        ms = np.zeros(64)
+        cnt = np.zeros(64, np.int32)
+        n = c_int32()
+        self._check(self.lib.g1g2_profile_adjoint(self.ctx, _ptr(a), _ptr(b), 64, _ptr(ms), _ptr(cnt),
+                                                  ctypes.byref(n)))
+        return {self.lib.g1g2_profile_name(self.ctx, k).decode(): (float(ms[k]), int(cnt[k]))
+                for k in range(n.value)}
+
+    def step_path(self) -> str:
+        """The kernels the library takes for g1g2_step_rk4 on this context."""
+        v = c_int32()
+        self._check(self.lib.g1g2_step_path(self.ctx, ctypes.byref(v)))
+        return PATHS[v.value]
+
+    def prepare_graph(self, dt: float):
+        """Capture the replayed steps of size dt now (no-op without a stream)."""
+        self._check(self.lib.g1g2_prepare_graph(self.ctx, float(dt)))
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.g1g2_destroy(self.ctx)
@@ -270,7 +300,7 @@ class Batch(Propagator):
         self._check(self.lib.g1g2_batch_observables(self.ctx, obs))
         return [dict(t=o.t, N=(o.N[0], o.N[1]), E_kin=o.E_kin, E_mf=o.E_mf, E_corr=o.E_corr,
                      E_tot=o.E_tot, docc=o.docc, imbalance=o.imbalance, diverged=o.diverged,
-                     step=o.step) for o in obs]
+                     step=o.step, diverged_step=o.diverged_step) for o in obs]
 
     def get_cluster(self, c: int, with_g2: bool = True):
         ns = self.ns[c]

@@ -122,11 +122,44 @@ g1g2_status rk4_step(g1g2_ctx* c, double t, double dt) {
     return stage(c, RK_LAST, t + dt, c->s0, c->y, c->acc, c->y, dt / 6.0, 0.0);
 }
 
+__global__ void guard_count_kernel(unsigned long long* div, unsigned long long steps) { div[0] = steps; }
+
+// Allocate the divergence guard of n clusters, all clear.
+g1g2_status guard_alloc(g1g2_ctx* c, int n) {
+    HIP_OK(c, hipMalloc(&c->dflag, sizeof(int)));
+    HIP_OK(c, hipMalloc(&c->ddiv, (size_t)(n + 1) * sizeof(unsigned long long)));
+    c->nguard = n;
+    return G1G2_OK;
+}
+
+// Clear the guard: no cluster has diverged.
+g1g2_status guard_clear(g1g2_ctx* c) {
+    HIP_OK(c, hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    HIP_OK(c, hipMemsetAsync(c->ddiv, 0xff, (size_t)(c->nguard + 1) * sizeof(unsigned long long), c->stream));
+    return G1G2_OK;
+}
+
+// First diverged step of every cluster (-1: none); synchronizes the stream.
+g1g2_status guard_read(g1g2_ctx* c, std::vector<long long>& first) {
+    std::vector<unsigned long long> h((size_t)c->nguard + 1);
+    HIP_OK(c, hipMemcpyAsync(h.data(), c->ddiv, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    first.assign(c->nguard, -1);
+    for (int q = 0; q < c->nguard; ++q)
+        if (h[q + 1] != ~0ull) first[q] = (long long)h[q + 1];
+    return G1G2_OK;
+}
+
 void drop_graph(g1g2_ctx* c) {
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     c->graph = nullptr;
     c->graph_steps = 0;
 }
+
+// Steps per captured graph: g1g2_step_rk4 replays it for every whole group of
+// that many steps and launches the rest one by one.
+constexpr int GRAPH_STEPS = 8;
 
 // Kernel arguments of a step do not depend on t unless a drive or a switching
 // ramp is set, so a captured sequence of steps can be replayed for any t.
@@ -183,6 +216,7 @@ void g1g2_destroy(g1g2_ctx* c) {
     free_regs(c->s1);
     free_regs(c->io);
     if (c->dflag) (void)hipFree(c->dflag);
+    if (c->ddiv) (void)hipFree(c->ddiv);
     if (c->dscratch) (void)hipFree(c->dscratch);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
@@ -236,8 +270,7 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     };
     for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1, &c->io})
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
-    if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
-    if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    if ((s = guard_alloc(c, 1)) != G1G2_OK || (s = guard_clear(c)) != G1G2_OK) return fail(s);
     c->nscratch = 8 + 3 * 256 + 3 * (int)nb + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
 
@@ -292,15 +325,21 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
     const int64_t step0 = c->step;
     g1g2_status s;
     int64_t n = 0;
+    if (nsteps > 0) {   // the steps of this call are numbered from the completed ones
+        hipLaunchKernelGGL(guard_count_kernel, dim3(1), dim3(1), 0, c->stream, c->ddiv,
+                           (unsigned long long)step0);
+        HIP_OK(c, hipGetLastError());
+        prof_mark(c, "guard_count");
+    }
     if (c->d.basis == G1G2_HUBBARD && hub_persistent_ok(c)) {
         if ((s = hub_step_persistent(c, dt, nsteps)) != G1G2_OK) return s;
         n = nsteps;
     }
-    if (n < nsteps && can_capture(c) && nsteps >= 4) {
-        const int gs = (int)std::min<int64_t>(nsteps, 8);
-        if (!c->graph || c->graph_dt != dt || c->graph_steps != gs)
-            if ((s = capture(c, dt, gs)) != G1G2_OK) return s;
-        for (; n + gs <= nsteps; n += gs) HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
+    if (n < nsteps && can_capture(c) && nsteps >= GRAPH_STEPS) {
+        // one graph of GRAPH_STEPS steps per dt, captured on first use and kept
+        if (!c->graph || c->graph_dt != dt)
+            if ((s = capture(c, dt, GRAPH_STEPS)) != G1G2_OK) return s;
+        for (; n + GRAPH_STEPS <= nsteps; n += GRAPH_STEPS) HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
     }
     for (; n < nsteps; ++n)
         if ((s = rk4_step(c, t0 + (double)n * dt, dt)) != G1G2_OK) return s;
@@ -309,8 +348,42 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
     int flag = 0;
     HIP_OK(c, hipMemcpyAsync(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
-    if (flag) return set_error(c, G1G2_EDIVERGED, "non-finite state or occupation outside [-0.5, 1.5]");
+    if (flag) {
+        std::vector<long long> first;
+        if ((s = guard_read(c, first)) != G1G2_OK) return s;
+        int q0 = -1, nbad = 0;
+        for (int q = 0; q < c->nguard; ++q)
+            if (first[q] >= 0) {
+                ++nbad;
+                if (q0 < 0 || first[q] < first[q0]) q0 = q;
+            }
+        std::string msg = "non-finite state or occupation outside [-0.5, 1.5]";
+        if (q0 >= 0) {
+            msg += " after step " + std::to_string(first[q0]);
+            if (c->nguard > 1)
+                msg += " in cluster " + std::to_string(q0) + " (" + std::to_string(nbad) + " of " +
+                       std::to_string(c->nguard) + " clusters flagged; see g1g2_batch_observables)";
+        }
+        return set_error(c, G1G2_EDIVERGED, msg);
+    }
     return G1G2_OK;
+}
+
+g1g2_status g1g2_step_path(const g1g2_ctx* c, int32_t* path) {
+    if (!c || !path) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_GENERAL) *path = G1G2_PATH_GENERAL;
+    else if (hub_persistent_ok(c)) *path = G1G2_PATH_HUB_PERSISTENT;
+    else if (c->hub.slices) *path = G1G2_PATH_HUB_SLICE;
+    else if (c->hub.rows) *path = G1G2_PATH_HUB_ROW;
+    else *path = G1G2_PATH_HUB_ELEMENT;
+    return G1G2_OK;
+}
+
+g1g2_status g1g2_prepare_graph(g1g2_ctx* c, double dt) {
+    if (!c || !(dt > 0.0) || !std::isfinite(dt)) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_HUBBARD && hub_persistent_ok(c)) return G1G2_OK;
+    if (!can_capture(c) || (c->graph && c->graph_dt == dt)) return G1G2_OK;
+    return capture(c, dt, GRAPH_STEPS);
 }
 
 g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
@@ -321,11 +394,12 @@ g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
     g1g2_status s = c->d.basis == G1G2_HUBBARD ? hub_observables(c, c->y, c->t, o)
                                                : gen_observables(c, c->y, c->t, o);
     if (s != G1G2_OK) return s;
-    int flag = 0;
-    HIP_OK(c, hipMemcpy(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<long long> first;
+    if ((s = guard_read(c, first)) != G1G2_OK) return s;
     o->t = c->t;
     o->step = c->step;
-    o->diverged = flag;
+    o->diverged = first[0] >= 0;
+    o->diverged_step = first[0];
     return G1G2_OK;
 }
 
@@ -361,7 +435,7 @@ g1g2_status g1g2_set_state(g1g2_ctx* c, const void* G1, const void* G2, double t
     } else {
         HIP_OK(c, hipMemsetAsync(c->y.g2, 0, c->n2 * sizeof(cd), c->stream));
     }
-    HIP_OK(c, hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream));
+    if ((s = guard_clear(c)) != G1G2_OK) return s;
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->t = t;
     return G1G2_OK;
@@ -475,8 +549,7 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const
     };
     for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1})
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
-    if (hipMalloc(&c->dflag, sizeof(int)) != hipSuccess) return fail(G1G2_ENOMEM);
-    if (hipMemsetAsync(c->dflag, 0, sizeof(int), c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    if ((s = guard_alloc(c, n)) != G1G2_OK || (s = guard_clear(c)) != G1G2_OK) return fail(s);
     c->nscratch = 8 + 3 * 256 + 3 * nsmax + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
     std::vector<int> nsv(ns, ns + n), ch(n, 0);
@@ -504,12 +577,13 @@ g1g2_status g1g2_batch_observables(g1g2_ctx* c, g1g2_obs* o) {
     std::memset(o, 0, n * sizeof(g1g2_obs));
     g1g2_status s = hub_batch_observables(c, c->y, c->t, o);
     if (s != G1G2_OK) return s;
-    int flag = 0;
-    HIP_OK(c, hipMemcpy(&flag, c->dflag, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<long long> first;
+    if ((s = guard_read(c, first)) != G1G2_OK) return s;
     for (int q = 0; q < n; ++q) {
         o[q].t = c->t;
         o[q].step = c->step;
-        o[q].diverged = flag;
+        o[q].diverged = first[q] >= 0;
+        o[q].diverged_step = first[q];
     }
     return G1G2_OK;
 }
@@ -528,22 +602,21 @@ g1g2_status g1g2_batch_get_state(g1g2_ctx* c, int32_t cluster, void* G1, void* G
     return G1G2_OK;
 }
 
-g1g2_status g1g2_profile(g1g2_ctx* c, double dt, int64_t nsteps, int32_t max_kernels,
-                         double* ms_total, int32_t* launches, int32_t* count) {
-    if (!c || nsteps < 0 || max_kernels < 1 || !ms_total || !launches || !count) return G1G2_EINVAL;
-    if (nsteps > 0 && !(dt > 0.0)) return G1G2_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Per-kernel timing: prof_begin turns on an event after every kernel launch
+// (prof_mark), prof_end sums the time between consecutive events per kernel.
+g1g2_status prof_begin(g1g2_ctx* c) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->prof = true;
     c->prof_used = 0;
     prof_mark(c, "start");
-    g1g2_status s;
-    if (nsteps == 0) {
-        s = stage(c, RK_RHS, c->t, c->y, c->y, c->y, c->s1, 0.0, 0.0);
-    } else {
-        s = g1g2_step_rk4(c, dt, nsteps);
-    }
-    c->prof = false;
-    if (s != G1G2_OK) return s;
+    return G1G2_OK;
+}
+
+g1g2_status prof_end(g1g2_ctx* c, int32_t max_kernels, double* ms_total, int32_t* launches, int32_t* count) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->prof_kernels.clear();
     std::vector<double> tot;
@@ -569,6 +642,37 @@ g1g2_status g1g2_profile(g1g2_ctx* c, double dt, int64_t nsteps, int32_t max_ker
         launches[q] = cnt[q];
     }
     return G1G2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+g1g2_status g1g2_profile(g1g2_ctx* c, double dt, int64_t nsteps, int32_t max_kernels,
+                         double* ms_total, int32_t* launches, int32_t* count) {
+    if (!c || nsteps < 0 || max_kernels < 1 || !ms_total || !launches || !count) return G1G2_EINVAL;
+    if (nsteps > 0 && !(dt > 0.0)) return G1G2_EINVAL;
+    g1g2_status s;
+    if ((s = prof_begin(c)) != G1G2_OK) return s;
+    if (nsteps == 0) {
+        s = stage(c, RK_RHS, c->t, c->y, c->y, c->y, c->s1, 0.0, 0.0);
+    } else {
+        s = g1g2_step_rk4(c, dt, nsteps);
+    }
+    c->prof = false;
+    if (s != G1G2_OK) return s;
+    return prof_end(c, max_kernels, ms_total, launches, count);
+}
+
+g1g2_status g1g2_profile_adjoint(g1g2_ctx* c, const double* a, const double* b, int32_t max_kernels,
+                                 double* ms_total, int32_t* launches, int32_t* count) {
+    if (!c || !a || !b || max_kernels < 1 || !ms_total || !launches || !count) return G1G2_EINVAL;
+    g1g2_status s;
+    if ((s = prof_begin(c)) != G1G2_OK) return s;
+    s = g1g2_adjoint(c, a, b, nullptr, nullptr, nullptr);
+    c->prof = false;
+    if (s != G1G2_OK) return s;
+    return prof_end(c, max_kernels, ms_total, launches, count);
 }
 
 const char* g1g2_profile_name(const g1g2_ctx* c, int32_t k) {

@@ -504,6 +504,7 @@ void free_reg(Regs& r) {
 g1g2_status copy_reg(g1g2_ctx* c, const Regs& dst, const Regs& src) {
     HIP_OK(c, hipMemcpyAsync(dst.g1, src.g1, c->n1 * sizeof(cd), hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(c, hipMemcpyAsync(dst.g2, src.g2, c->n2 * sizeof(cd), hipMemcpyDeviceToDevice, c->stream));
+    prof_mark(c, "state_copy");
     return G1G2_OK;
 }
 
@@ -554,16 +555,20 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
 g1g2_status vjp(g1g2_ctx* c, const AdjArgs& s) {
     const int ns = s.a.ns, ns2 = ns * ns;
     hipLaunchKernelGGL(adj_slice_red_kernel, dim3(ns2), dim3(256), 0, c->stream, s);
+    prof_mark(c, "adj_slice_red");
     hipLaunchKernelGGL(adj_lane_red_kernel, dim3(ns * s.nparts), dim3(256), 0, c->stream, s);
+    prof_mark(c, "adj_lane_red");
     hipLaunchKernelGGL(adj_slice_fin_kernel, dim3((9 * ns2 + 255) / 256), dim3(256), 0, c->stream, s);
+    prof_mark(c, "adj_slice_fin");
     HIP_OK(c, hipGetLastError());
-    prof_mark(c, "adj_red");
     const int g1blocks = (2 * ns2 + 255) / 256;
     hipLaunchKernelGGL(adj_e_kernel, dim3(1), dim3(256), 0, c->stream, s);
+    prof_mark(c, "adj_e");
     hipLaunchKernelGGL(adj_g1e_kernel, dim3(g1blocks), dim3(256), 0, c->stream, s);
+    prof_mark(c, "adj_g1e");
     hipLaunchKernelGGL(adj_gsum_kernel, dim3(1), dim3(64), 0, c->stream, s, g1blocks);
+    prof_mark(c, "adj_gsum");
     HIP_OK(c, hipGetLastError());
-    prof_mark(c, "adj_g1");
     return G1G2_OK;
 }
 
@@ -656,12 +661,14 @@ g1g2_status g1g2_adjoint(g1g2_ctx* c, const double* wa, const double* wb, double
     HIP_OK(c, hipMemcpyAsync(st->dev_ab + ns, wb, ns * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, hipMemsetAsync(st->LAM.g1, 0, c->n1 * sizeof(cd), c->stream));
     HIP_OK(c, hipMemsetAsync(st->LAM.g2, 0, c->n2 * sizeof(cd), c->stream));
+    prof_mark(c, "adj_init");
     {
         const Regs& fin = st->ckpt[st->nck];
         AdjArgs tmp = make_adj(c, st->t0 + st->nsteps * dt, fin, fin, 1.0, fin, fin, fin, 0, 0, 0, 0, nullptr);
         hipLaunchKernelGGL(adj_terminal_kernel, dim3(1), dim3(1), 0, c->stream, tmp.a, fin.g2, st->dev_ab,
                            st->dev_ab + ns, st->LAM.g1, st->LAM.g2, st->dev_ab + 2 * ns);
         HIP_OK(c, hipGetLastError());
+        prof_mark(c, "adj_terminal");
     }
     Regs lam = st->LAM, lacc = st->LACC;
     for (int q = st->nck - 1; q >= 0; --q) {

@@ -25,6 +25,27 @@ __host__ __device__ __forceinline__ cd cfma_conjb(cd acc, cd a, cd b) {
     return cmk(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.y, b.x, fma(-a.x, b.y, acc.y)));
 }
 
+// Divergence guard of the Runge-Kutta steps.  div[0] counts the steps begun:
+// the host sets it to the number of completed steps before it launches steps,
+// and one thread of the first stage of every step advances it, so the last
+// stage of a step reads that step's number.  div[1 + c] keeps the first step at
+// whose end cluster c (0 for the general basis) failed the guard (~0: never),
+// and *flag says whether any cluster did.
+struct DivGuard {
+    int* flag;
+    unsigned long long* div;
+};
+__device__ __forceinline__ void guard_begin_step(const DivGuard& g) { g.div[0] += 1ull; }
+__device__ __forceinline__ void guard_fire(const DivGuard& g, int cluster, unsigned long long step) {
+    atomicOr(g.flag, 1);
+    atomicMin(g.div + 1 + cluster, step);
+}
+// The guard itself: a non-finite element, or an occupation n_ii = Im G^<_ii
+// far outside [0, 1].
+__device__ __forceinline__ bool guard_bad(cd v, bool diagonal) {
+    return !(isfinite(v.x) && isfinite(v.y)) || (diagonal && (v.y < -0.5 || v.y > 1.5));
+}
+
 // Complex loads and stores from binary64 or binary32 storage; arithmetic is
 // always binary64.
 __device__ __forceinline__ cd ld_c(const cd* __restrict__ p, long long i) { return p[i]; }

@@ -103,6 +103,8 @@ struct g1g2_ctx {
     size_t n1 = 0, n2 = 0;     // internal element counts of G1 and G2
     Regs y, acc, s0, s1, io;   // RK4 registers; io = scratch for g1g2_rhs
     int* dflag = nullptr;      // divergence flag (device int)
+    unsigned long long* ddiv = nullptr;   // [1 + clusters]: step counter and first diverged step (DivGuard)
+    int nguard = 0;                       // clusters covered by ddiv
     double* dscratch = nullptr;  // small device scratch for reductions
     int nscratch = 0;
     HubbardData hub;
@@ -125,6 +127,9 @@ struct g1g2_ctx {
     size_t prof_used = 0;
     std::vector<const char*> prof_kernels;   // distinct kernel names of the last profile
 };
+
+// The context's divergence guard (kernel argument).
+inline DivGuard guard_of(const g1g2_ctx* c) { return DivGuard{c->dflag, c->ddiv}; }
 
 // Record a timing event after the kernel `name` when profiling is active.
 void prof_mark(g1g2_ctx* c, const char* name);

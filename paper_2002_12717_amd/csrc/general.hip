@@ -455,7 +455,7 @@ struct G1Args {
     cd* out;
     cd* icoll;         // I, written by right-hand-side evaluations
     int nb;
-    int* flag;
+    DivGuard guard;
 };
 
 template <int MODE>
@@ -465,12 +465,8 @@ __device__ __forceinline__ void g1_update(const G1Args& g, int e, cd comm, cd Ii
     if (MODE == RK_RHS) g.icoll[e] = Iij;
     rk_update<MODE>(e, f, g.gl[e], g.y, g.acc, g.out, cb, cc);
     const int i = e / nbp, j = e % nbp;
-    if (MODE == RK_LAST && i < g.nb) {
-        cd v = g.out[e];
-        bool bad = !(isfinite(v.x) && isfinite(v.y));
-        if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
-        if (bad) atomicOr(g.flag, 1);
-    }
+    if (MODE == RK_FIRST && e == 0) guard_begin_step(g.guard);   // one thread per launch
+    if (MODE == RK_LAST && i < g.nb && guard_bad(g.out[e], i == j)) guard_fire(g.guard, 0, g.guard.div[0]);
 }
 
 // The elements (i,j) and (j,i), i <= j: both need I_ij and I_ji, so each
@@ -1011,7 +1007,7 @@ g1g2_status run_combine(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     const int n = g.nbp * g.nbp;
     const int nt = n / 32, ntiles = nt * (nt + 1) / 2;
     const G1Args g1{g.ipart, g.nipart, g.hhf, in.g1, y.g1, acc.g1, out.g1,
-                    g.icoll, g.nb, c->dflag};
+                    g.icoll, g.nb, guard_of(c)};
     const int ng1 = (g.nbp * (g.nbp + 1) / 2 + 3) / 4;   // work-groups of the G1 pairs
     if (c->d.selfenergy == G1G2_GW || c->d.selfenergy == G1G2_DSL)
         hipLaunchKernelGGL((gen_combine_kernel<MODE, S, true>), dim3(ng1 + ntiles), dim3(256), 0, c->stream,

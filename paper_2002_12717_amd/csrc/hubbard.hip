@@ -192,7 +192,7 @@ struct StageArgs {
     cd* out1;
     cd* out2;
     double cb, cc;
-    int* flag;
+    DivGuard guard;
     const cd* diag;   // per cluster: GW's six [ns]^3 layouts, then TPH's R and S (hub_diag_kernel)
 };
 
@@ -233,16 +233,13 @@ __global__ __launch_bounds__(256) void hub_stage_kernel(StageArgs s) {
         cd* acc = s.acc1 + d.g1off;
         cd* out = s.out1 + d.g1off;
         const int ns2 = ns * ns;
+        if (MODE == RK_FIRST && w.cluster == 0 && threadIdx.x == 0) guard_begin_step(s.guard);
+        const unsigned long long step = MODE == RK_LAST ? s.guard.div[0] : 0ull;
         for (int e = threadIdx.x; e < 2 * ns2; e += blockDim.x) {
             int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
             cd f = hub_g1_rhs(a, A, sig, i, j);
             rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
-            if (MODE == RK_LAST) {
-                cd v = out[e];
-                bool bad = !(isfinite(v.x) && isfinite(v.y));
-                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;  // n_ii = -i G_ii = G_ii.y
-                if (bad) atomicOr(s.flag, 1);
-            }
+            if (MODE == RK_LAST && guard_bad(out[e], i == j)) guard_fire(s.guard, w.cluster, step);
         }
     }
 }
@@ -348,16 +345,13 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
         const cd* y = s.y1 + d.g1off;
         cd* acc = s.acc1 + d.g1off;
         cd* out = s.out1 + d.g1off;
+        if (MODE == RK_FIRST && w.cluster == 0 && tid == 0) guard_begin_step(s.guard);
+        const unsigned long long step = MODE == RK_LAST ? s.guard.div[0] : 0ull;
         for (int e = tid; e < 2 * ns2; e += blockDim.x) {
             int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
             cd f = hub_g1_rhs(a, A, sig, i, j);
             rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
-            if (MODE == RK_LAST) {
-                cd v = out[e];
-                bool bad = !(isfinite(v.x) && isfinite(v.y));
-                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
-                if (bad) atomicOr(s.flag, 1);
-            }
+            if (MODE == RK_LAST && guard_bad(out[e], i == j)) guard_fire(s.guard, w.cluster, step);
         }
         return;
     }
@@ -627,16 +621,13 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
         const cd* y = s.y1 + d.g1off;
         cd* acc = s.acc1 + d.g1off;
         cd* out = s.out1 + d.g1off;
+        if (MODE == RK_FIRST && w.cluster == 0 && tid == 0) guard_begin_step(s.guard);
+        const unsigned long long step = MODE == RK_LAST ? s.guard.div[0] : 0ull;
         for (int e = tid; e < 2 * ns2; e += SLICE_THREADS) {
             int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
             cd f = hub_g1_rhs(a, A, sig, i, j);
             rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
-            if (MODE == RK_LAST) {
-                cd v = out[e];
-                bool bad = !(isfinite(v.x) && isfinite(v.y));
-                if (i == j && (v.y < -0.5 || v.y > 1.5)) bad = true;
-                if (bad) atomicOr(s.flag, 1);
-            }
+            if (MODE == RK_LAST && guard_bad(out[e], i == j)) guard_fire(s.guard, w.cluster, step);
         }
         return;
     }
@@ -814,7 +805,7 @@ struct PersistArgs {
     cd* y2;        // G2 state [ns]^4
     double dt;
     int nsteps;
-    int* flag;
+    DivGuard guard;   // steps are numbered from guard.div[0] as the launch finds it
 };
 
 template <int SE, bool MIXED, bool RH>
@@ -858,6 +849,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
     }
     __syncthreads();
     const double h = p.dt;
+    const unsigned long long step0 = p.guard.div[0];
     int cur = 0;
     for (int step = 0; step < p.nsteps; ++step) {
 #pragma unroll 1
@@ -932,9 +924,7 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
                     y1 = cmk(fma(cb, f1.x, acc1.x), fma(cb, f1.y, acc1.y));
                     o = y1;
                     const int r = tid % ns2, i = r / ns, j = r % ns;
-                    bool bad = !(isfinite(o.x) && isfinite(o.y));
-                    if (i == j && (o.y < -0.5 || o.y > 1.5)) bad = true;
-                    if (bad) atomicOr(p.flag, 1);
+                    if (guard_bad(o, i == j)) guard_fire(p.guard, 0, step0 + step + 1);
                 }
                 outG[tid] = o;
             }
@@ -948,6 +938,8 @@ __global__ __launch_bounds__(PERSIST_THREADS) void hub_persistent_kernel(Persist
         if (e < n2) p.y2[e] = y2[q];
     }
     if (tid < n1) p.y1[tid] = y1;
+    __syncthreads();   // every thread has read guard.div[0]
+    if (tid == 0) p.guard.div[0] = step0 + (unsigned long long)p.nsteps;
 }
 
 StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const Regs& acc,
@@ -972,7 +964,7 @@ StageArgs make_stage(g1g2_ctx* c, double t, const Regs& in, const Regs& y, const
     s.out2 = out.g2;
     s.cb = cb;
     s.cc = cc;
-    s.flag = c->dflag;
+    s.guard = guard_of(c);
     s.diag = H.diag;
     return s;
 }
@@ -1409,7 +1401,7 @@ g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
     // bounded launches: at most 1024 steps (a few ms) per launch
     for (int64_t n = 0; n < nsteps;) {
         const int chunk = (int)std::min<int64_t>(nsteps - n, 1024);
-        PersistArgs p{H.desc, H.nbr, H.hop, H.d0, H.xdrv, c->y.g1, c->y.g2, dt, chunk, c->dflag};
+        PersistArgs p{H.desc, H.nbr, H.hop, H.d0, H.xdrv, c->y.g1, c->y.g2, dt, chunk, guard_of(c)};
         const bool mixed = c->d.precision == G1G2_MIXED;
         if (H.realhop) {
             if (mixed) launch_persistent<true, true>(c, p);

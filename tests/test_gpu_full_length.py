@@ -1,0 +1,191 @@
+"""Full-length parity of the HIP library with the FP64 oracle at the sizes of
+the benchmark workloads.
+
+The oracle needs minutes (Nb = 32, 2000 steps) to hours (Nb = 64 GW, 500
+steps) for these runs, so its values are stored under tests/golden/ by
+tests/golden/make_golden.py, which calls only the oracle and the seeded input
+generators.  Error metrics as in the other parity tests: G1 relative to the
+largest |G1| of the oracle at that time, E relative to max(|E(0)|, 1), G2
+elements relative to the largest sampled |G2| at that time.  Binary64 must
+agree to 1e-10 over the whole run, mixed precision to 1e-5; the particle
+number to 1e-9 (binary64) and 1e-5 N (mixed: binary32 contractions leave
+the trace of the collision integral real only to their rounding).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import adjoint_system, general_system, gw_system, random_g2, random_gless, rng
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    assert os.path.exists(path), f"{path} missing: run tests/golden/make_golden.py"
+    return np.load(path)
+
+
+def _run_against_golden(p, s, g, nsteps, n_tol, g1_idx=None, kick=None):
+    """Step the library from one stored time to the next and compare with the
+    stored oracle trajectory; returns the three error maxima."""
+    full = {int(n): k for k, n in enumerate(g["full_steps"])}
+    samp = {int(n): k for k, n in enumerate(g["samp_steps"])}
+    obs = {int(n): k for k, n in enumerate(g["obs_steps"])}
+    g2at = {int(n): k for k, n in enumerate(g["g2_steps"])}
+    idx2 = tuple(np.asarray(g["g2_idx"]).T)
+    e_scale = max(abs(float(g["E_tot"][0])), 1.0)
+    stops = sorted(set(full) | set(samp) | set(obs) | set(g2at) | {nsteps})
+    err_g1 = err_e = err_g2 = 0.0
+    n = 0
+    while True:
+        need_g2 = n in g2at and n > 0
+        G1, G2, t = p.get_state(with_g2=need_g2)
+        if n in full:
+            ref = g["full_g1"][full[n]]
+            err_g1 = max(err_g1, float(np.abs(G1 - ref).max() / np.abs(ref).max()))
+        if n in samp and g1_idx is not None:
+            k = samp[n]
+            got = G1[g1_idx[:, 0], g1_idx[:, 1]]
+            err_g1 = max(err_g1, float(np.abs(got - g["samp_g1"][k]).max() / g["samp_scale"][k]))
+        if n in obs:
+            o = p.observables()
+            err_e = max(err_e, abs(o["E_tot"] - float(g["E_tot"][obs[n]])) / e_scale)
+            assert abs(o["N"][0] - float(g["N"][obs[n]])) < n_tol
+        if need_g2:
+            ref = g["g2_vals"][g2at[n]]
+            err_g2 = max(err_g2, float(np.abs(G2[idx2] - ref).max() / np.abs(ref).max()))
+        if n == nsteps:
+            break
+        if kick is not None and n == 0:          # one-step kick, then the static h0
+            p.set_h0(s.h0 + kick)
+            p.step(s.dt, 1)
+            p.set_h0(s.h0)
+            step = 1
+        else:
+            step = min(q for q in stops if q > n) - n
+            p.step(s.dt, step)
+        n += step
+    return err_g1, err_e, err_g2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_general_soa_nb32_full_propagation(lib, prec):
+    """The Nb = 32 SOA molecule (rank-64 w, 8 particles, dt = 0.01) over all
+    2000 RK4 steps: G1 every 250 steps, E(t) every 50, 256 G2 elements every
+    250, against the stored oracle trajectory."""
+    from paper_2002_12717_amd import binding as B
+    g = golden("general_soa_nb32.npz")
+    s = general_system()
+    say(f"[full length] general SOA nb=32, 2000 steps, {prec}")
+    p = B.Propagator(B.GENERAL, B.SOA, s.nb, s.h0, s.g1, w=s.w,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED)
+    e1, ee, e2 = _run_against_golden(p, s, g, 2000, 1e-9 if prec == "fp64" else 1e-5 * s.meta["nocc"])
+    p.close()
+    say(f"   max err G1 {e1:.2e}  E {ee:.2e}  G2 {e2:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert e1 < tol and ee < tol and e2 < tol
+    if prec == "mixed":
+        assert e1 > 1e-12                      # the binary32 contractions are in use
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_general_gw_nb64_full_propagation(lib, prec):
+    """The Nb = 64 GW molecule (rank-128 w, 16 particles, one-step kick
+    0.1 GUE, dt = 0.01) over all 500 RK4 steps: G1 in full at steps 1, 5, 100
+    and 500 and at 256 entries every 25 steps, E(t) every 25 steps, and 320
+    G2 elements at steps 5 and 500, against the stored oracle trajectory."""
+    from paper_2002_12717_amd import binding as B
+    g = golden("general_gw_nb64.npz")
+    s = gw_system()
+    say(f"[full length] general GW nb=64, 500 steps with kick, {prec}")
+    p = B.Propagator(B.GENERAL, B.GW, s.nb, s.h0, s.g1, w=s.w,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED)
+    e1, ee, e2 = _run_against_golden(p, s, g, 500, 1e-9 if prec == "fp64" else 1e-5 * s.meta["nocc"], g1_idx=np.asarray(g["g1_idx"]), kick=s.kick)
+    p.close()
+    say(f"   max err G1 {e1:.2e}  E {ee:.2e}  G2 {e2:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert e1 < tol and ee < tol and e2 < tol
+    if prec == "mixed":
+        assert e1 > 1e-12
+
+
+@pytest.mark.parametrize("se", ["gw", "gw_x"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_general_gw_nb64_rhs_elements(lib, se, prec):
+    """One right-hand side of the Nb = 64 GW closure (without and with
+    exchange) at a seeded random correlated state, in the launch configuration
+    of the benchmark: 320 dG2 elements that cover every 64-row and 64-column
+    block of the (Nb^2)^3 polarization product and of its partner gather,
+    against the stored element-wise oracle."""
+    from paper_2002_12717_amd import binding as B
+    g = golden("general_gw_nb64_rhs.npz")
+    s = gw_system()
+    nb = s.nb
+    r = rng(371, nb)
+    gl, g2 = random_gless(nb, r), random_g2(nb, r, scale=0.02)
+    say(f"[full size] nb=64 {se} {prec} rhs, 320 stored elements")
+    p = B.Propagator(B.GENERAL, B.GW, nb, s.h0, gl, w=s.w, flags=B.GW_EXCHANGE if se == "gw_x" else 0,
+                     precision=B.FP64 if prec == "fp64" else B.MIXED)
+    G1d = torch.as_tensor(gl, dtype=torch.complex128).cuda()
+    G2d = torch.as_tensor(g2, dtype=torch.complex128).cuda()
+    del g2
+    dG1d, dG2d = torch.zeros_like(G1d), torch.zeros_like(G2d)
+    p.rhs(0.0, G1d, G2d, dG1d, dG2d)
+    p.close()
+    idx = torch.as_tensor(np.asarray(g["idx"]), device="cuda")
+    got = dG2d[idx[:, 0], idx[:, 1], idx[:, 2], idx[:, 3]].cpu().numpy()
+    ref = g[se]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    say(f"   err dG2 (320 elements) {err:.2e}")
+    assert err < (1e-12 if prec == "fp64" else 2e-5)
+
+
+def test_adjoint_8x8_full_length_finite_differences(lib):
+    """The 8x8 adjoint workload at its full length (4000 steps, dt = 0.01, 64
+    Gaussian drive pulses, U = 2), with the default sqrt(n) checkpoint
+    interval: dL/dU and two dL/dc_m of the mean double occupation plus the
+    density imbalance against central differences (h = 1e-6) of the forward
+    map."""
+    from paper_2002_12717_amd import binding as B
+    s = adjoint_system()
+    nst = s.nsteps
+    assert nst == 4000
+    ns, lx = s.ns, s.meta["lx"]
+    a = np.full(ns, 1.0 / ns)
+    b = np.array([1.0 if (q % lx) < lx / 2 else -1.0 for q in range(ns)]) / ns
+    d = s.drive
+    say(f"[adjoint] 8x8, {nst} steps, default checkpoint interval")
+    p = B.Propagator(B.HUBBARD, B.SOA, s.ns, s.h0, s.g1, U=s.U)
+    p.set_drive(d.x, d.c, d.t_center, d.tau)
+    p.forward_checkpointed(s.dt, nst, 0)
+    L, gc, gU = p.adjoint(a, b, len(d.c))
+    p.close()
+
+    def loss_at(cv, Uv):
+        q = B.Propagator(B.HUBBARD, B.SOA, s.ns, s.h0, s.g1, U=Uv)
+        q.set_drive(d.x, cv, d.t_center, d.tau)
+        q.step(s.dt, nst)
+        nu, nd, docc = q.site_observables()
+        q.close()
+        return float(np.dot(a, docc) + np.dot(b, nu + nd))
+
+    h = 1e-6
+    fd_u = (loss_at(d.c, s.U + h) - loss_at(d.c, s.U - h)) / (2 * h)
+    say(f"   L {L:.12e}  dL/dU adjoint {gU:.10e} fd {fd_u:.10e}")
+    assert abs(fd_u - gU) < 1e-6 * max(1e-3, abs(fd_u))
+    for m in (10, 40):
+        cp, cm = d.c.copy(), d.c.copy()
+        cp[m] += h
+        cm[m] -= h
+        fd = (loss_at(cp, s.U) - loss_at(cm, s.U)) / (2 * h)
+        say(f"   dL/dc{m} adjoint {gc[m]:.10e} fd {fd:.10e}")
+        assert abs(fd - gc[m]) < 1e-6 * max(1e-3, abs(fd))

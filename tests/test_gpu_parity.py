@@ -169,6 +169,8 @@ def test_hubbard_persistent_small_cluster(lib, ns, se):
     _compare_hubbard_trajectory(s, se, 3, 100, 1e-10)
     pp = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U)
     pr = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    assert pp.step_path() == ("hub_persistent" if ns <= 7 else "hub_slice")
+    assert pr.step_path() == "hub_row"
     pp.step(s.dt, 300)
     pr.step(s.dt, 300)
     (g1p, g2p, tp), (g1r, g2r, tr) = pp.get_state(), pr.get_state()
@@ -188,6 +190,7 @@ def test_hubbard_persistent_long_call_and_one_cluster_batch(lib):
     say("[hubbard persistent] chain5 tpp, 2500 steps in one call")
     pp = B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=s.U)
     pr = B.Propagator(B.HUBBARD, B.TPP, s.ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    assert pp.step_path() == "hub_persistent" and pr.step_path() == "hub_row"
     pp.step(s.dt, 2500)
     for _ in range(25):
         pr.step(s.dt, 100)
@@ -200,6 +203,7 @@ def test_hubbard_persistent_long_call_and_one_cluster_batch(lib):
     c = hubbard_chain_system(ns=6, U=1.5, dt=0.02)
     say("[hubbard persistent] batch of one 6-site chain, tph, 200 steps")
     b = B.Batch(B.TPH, [c.ns], [c.U], [c.h0], [c.g1])
+    assert b.step_path() == "hub_persistent"
     b.step(c.dt, 200)
     y, _ = OI.propagate_hubbard(c, nsteps=200, selfenergy="tph")
     g1, g2 = b.get_cluster(0)
@@ -241,6 +245,7 @@ def test_hubbard_persistent_lattices(lib, kind, se):
     _compare_hubbard_trajectory(s, se, 3, 100, 1e-10)
     pp = B.Propagator(B.HUBBARD, _se(se), s.ns, s.h0, s.g1, U=s.U)
     pr = B.Propagator(B.HUBBARD, _se(se), s.ns, s.h0, s.g1, U=s.U, flags=B.HUB_ROW_KERNEL)
+    assert pp.step_path() == "hub_persistent"
     pp.step(s.dt, 300)
     pr.step(s.dt, 300)
     (g1p, g2p, _), (g1r, g2r, _) = pp.get_state(), pr.get_state()
@@ -250,18 +255,26 @@ def test_hubbard_persistent_lattices(lib, kind, se):
     pr.close()
 
 
-@pytest.mark.parametrize("ns", [3, 8])
+@pytest.mark.parametrize("kind", ["chain3", "chain7", "2x3", "ring6_flux"])
 @pytest.mark.parametrize("se", ["soa", "tpp", "tph"])
-def test_hubbard_persistent_small_cluster_mixed(lib, ns, se):
+def test_hubbard_persistent_small_cluster_mixed(lib, kind, se):
     """The persistent work-group in mixed precision (binary32 G2 stage copies in
-    LDS): 300 steps against the binary64 oracle at the mixed-precision bar, and
-    against the launched mixed stages of the same library."""
+    LDS), from the smallest chain to the largest cluster it takes (ns = 7), on
+    a 2D cluster and with complex hoppings: 300 steps against the binary64
+    oracle at the mixed-precision bar, and against the launched mixed stages of
+    the same library."""
     from paper_2002_12717_amd import binding as B
-    s = hubbard_chain_system(ns=ns, U=1.5, dt=0.02)
-    say(f"[hubbard persistent mixed] chain{ns} {se} 300 steps")
+    if kind.startswith("chain"):
+        ns = int(kind[5:])
+        s = hubbard_chain_system(ns=ns, U=1.5, dt=0.02)
+    else:
+        s = _small_lattice(kind)
+        ns = s.ns
+    say(f"[hubbard persistent mixed] {kind} {se} 300 steps")
     pm = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, precision=B.MIXED)
     pr = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, s.g1, U=s.U, precision=B.MIXED,
                       flags=B.HUB_ROW_KERNEL)
+    assert pm.step_path() == "hub_persistent" and pr.step_path() == "hub_row"
     pm.step(s.dt, 300)
     pr.step(s.dt, 300)
     y, _ = OI.propagate_hubbard(s, nsteps=300, selfenergy=se)
@@ -360,6 +373,13 @@ def _compare_general_trajectory(system, se, chunks, chunk_steps, prec, tol, swit
         p.set_switch(*switch)
     f = OI.general_rhs_fn(system.h0, system.w, se, switch=switch)
     g1, g2 = T(system.g1), torch.zeros((system.nb,) * 4, dtype=torch.complex128)
+    Th, Tw = T(system.h0), T(system.w)
+
+    def energy(tt, a1, a2):
+        wt = Tw if switch is None else Tw * OI.switch_factor(tt, switch)
+        return OO.general_observables(Th, wt, a1, a2, tt)["E_tot"]
+
+    e_scale = max(abs(energy(0.0, g1, g2)), 1.0)
     t = 0.0
     errs = []
     for ch in range(chunks):
@@ -368,8 +388,10 @@ def _compare_general_trajectory(system, se, chunks, chunk_steps, prec, tol, swit
             g1, g2 = OI.rk4_step(f, t, (g1, g2), system.dt)
             t += system.dt
         G1, G2, _ = p.get_state()
-        errs.append(max(rel(G1, g1.numpy()), rel(G2, g2.numpy()) * 0))
-        say(f"   t={t:.3f} err G1 {errs[-1]:.2e}  err G2 {rel(G2, g2.numpy()):.2e}")
+        e1, e2 = rel(G1, g1.numpy()), rel(G2, g2.numpy())
+        ee = abs(p.observables()["E_tot"] - energy(t, g1, g2)) / e_scale
+        errs.append(max(e1, e2, ee))
+        say(f"   t={t:.3f} err G1 {e1:.2e}  err G2 {e2:.2e}  err E {ee:.2e}")
     assert max(errs) < tol
     o = p.observables()
     p.close()
@@ -427,8 +449,8 @@ def test_general_trajectory_nb20(lib, se, prec):
                                         (64, "soa", "fp64")])
 def test_general_stepper_matches_rhs(lib, nb, se, prec):
     """Padded sizes 48 and 64, where no trajectory is cheap enough for the
-    oracle: four steps of the library's stepper (fused Runge-Kutta updates,
-    one captured graph of four steps) against RK4 assembled on the host from
+    oracle: four steps of the library's stepper (fused Runge-Kutta updates)
+    against RK4 assembled on the host from
     the library's right-hand side, whose parity with the oracle is tested
     above.  The stage arithmetic is the same, so the two agree to rounding."""
     from paper_2002_12717_amd import binding as B
@@ -582,7 +604,44 @@ def test_abi_errors(lib):
     with pytest.raises(B.G1G2Error) as e:
         p.step(0.01, 2)
     assert e.value.status == B.EDIVERGED
+    assert "after step 1" in str(e.value)
+    o = p.observables()
+    assert o["diverged"] == 1 and o["diverged_step"] == 1 and o["step"] == 2
+    p.set_state(s.g1)                       # a new state clears the guard
+    p.step(0.01, 2)
+    assert p.observables()["diverged_step"] == -1
     p.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_divergence_is_per_cluster(lib, graph):
+    """The divergence guard of a ragged batch is per cluster: one cluster whose
+    initial occupation is set far out of range on the host is flagged, with the
+    step at whose end the guard first fired; the others are not, and they keep
+    following the oracle."""
+    from paper_2002_12717_amd import binding as B
+    from workloads import batched_clusters
+    cl = batched_clusters(n=6)
+    bad = 3
+    g1s = [c.g1.copy() for c in cl]
+    g1s[bad][0, 0, 0] = 3j
+    say(f"[batch] divergence guard, cluster {bad} out of range, graph={graph}")
+    stream = torch.cuda.Stream() if graph else None
+    b = B.Batch(B.SOA, [c.ns for c in cl], [c.U for c in cl], [c.h0 for c in cl], g1s,
+                stream=stream.cuda_stream if graph else 0)
+    nst = 16 if graph else 5
+    with pytest.raises(B.G1G2Error) as e:
+        b.step(cl[0].dt, nst)
+    assert e.value.status == B.EDIVERGED
+    assert f"after step 1 in cluster {bad} (1 of 6" in str(e.value), str(e.value)
+    obs = b.observables()
+    assert [o["diverged"] for o in obs] == [int(q == bad) for q in range(6)]
+    assert [o["diverged_step"] for o in obs] == [1 if q == bad else -1 for q in range(6)]
+    for q in (0, 5):
+        y, _ = OI.propagate_hubbard(cl[q], nsteps=nst, selfenergy="soa")
+        g1, _ = b.get_cluster(q, with_g2=False)
+        assert rel(g1, np.stack([y[0].numpy(), y[1].numpy()])) < 1e-10
+    b.close()
 
 
 def test_hubbard_mixed_chain_full_trajectory(lib):
