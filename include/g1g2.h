@@ -155,6 +155,21 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, con
 g1g2_status g1g2_rhs(g1g2_ctx* ctx, double t, const void* G1, const void* G2,
                      void* dG1, void* dG2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): g1g2_rhs of
+ * one Hubbard cluster that allocates nothing, copies nothing and does not
+ * synchronize.  It reads G1, G2 and writes dG1, dG2 (device pointers, the
+ * layouts above), ordered on the context's stream; the call returns before the
+ * work completes.  The diagonal gathers of TPH, GW and DSL (2, 6 and 8 ns^3
+ * complex elements) go to a static scratch array of 32 MiB per GPU (enough for
+ * every closure up to ns = 64), held until the process ends and shared by every
+ * call on that GPU: calls that overlap on one GPU race for it, so order them
+ * (one stream, or events between streams).  The results equal g1g2_rhs.
+ * EUNSUPPORTED for the general basis, ESTATE on a batch, EINVAL when the
+ * gathers exceed the scratch (nothing is launched then).                     */
+g1g2_status g1g2_rhs_noalloc(g1g2_ctx* ctx, double t, const void* G1, const void* G2,
+                             void* dG1, void* dG2);
+
 /* Advance the internal state by nsteps classical fourth-order Runge-Kutta
  * steps of size dt (h0(t) and U evaluated at the stage times).  The guard
  * checks G1 at the end of every step: a non-finite element or an occupation

@@ -40,6 +40,7 @@ _SIGS = {
     "g1g2_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p]),
     "g1g2_rhs": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "g1g2_rhs_noalloc": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "g1g2_step_rk4": (c_int32, [c_void_p, c_double, c_int64]),
     "g1g2_observables": (c_int32, [c_void_p, POINTER(Obs)]),
     "g1g2_site_observables": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -160,6 +161,10 @@ class Propagator:
     # ------------------------------------------------------------------ ABI calls
     def rhs(self, t: float, G1, G2, dG1, dG2):
         self._check(self.lib.g1g2_rhs(self.ctx, float(t), _ptr(G1), _ptr(G2), _ptr(dG1), _ptr(dG2)))
+
+    def rhs_noalloc(self, t: float, G1, G2, dG1, dG2):
+        """g1g2_rhs_noalloc: device tensors only; stream-ordered, no synchronization."""
+        self._check(self.lib.g1g2_rhs_noalloc(self.ctx, float(t), _ptr(G1), _ptr(G2), _ptr(dG1), _ptr(dG2)))
 
     def step(self, dt: float, nsteps: int):
         self._check(self.lib.g1g2_step_rk4(self.ctx, float(dt), int(nsteps)))

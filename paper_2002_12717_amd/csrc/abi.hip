@@ -271,6 +271,7 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1, &c->io})
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
     if ((s = guard_alloc(c, 1)) != G1G2_OK || (s = guard_clear(c)) != G1G2_OK) return fail(s);
+    if (d->basis == G1G2_HUBBARD && (s = hub_noalloc_setup(c)) != G1G2_OK) return fail(s);
     c->nscratch = 8 + 3 * 256 + 3 * (int)nb + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
 
@@ -550,6 +551,7 @@ g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* d, int32_t n, const
     for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1})
         if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
     if ((s = guard_alloc(c, n)) != G1G2_OK || (s = guard_clear(c)) != G1G2_OK) return fail(s);
+    if ((s = hub_noalloc_setup(c)) != G1G2_OK) return fail(s);
     c->nscratch = 8 + 3 * 256 + 3 * nsmax + 64;
     if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
     std::vector<int> nsv(ns, ns + n), ch(n, 0);

@@ -51,6 +51,7 @@ struct HubbardData {
     WorkItem* dwork = nullptr;     // TPH, GW, DSL: work list of the diagonal gather
     int ndwork = 0;
     cd* diag = nullptr;            // per cluster n_diag [ns]^3 gathered diagonal tensors
+    long long diag_elems = 0;      // complex elements of diag (0: the closure gathers none)
     std::vector<int> chunk;        // elements of G2 per work-group, per cluster
     int* nbr = nullptr;            // concatenated neighbour tables
     cd* hop = nullptr;
@@ -157,9 +158,17 @@ void hub_free(g1g2_ctx* c);
 // the context qualifies, and nsteps steps of size dt on its state.
 bool hub_persistent_ok(const g1g2_ctx* c);
 g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps);
-// One RK4 stage (or a plain RHS evaluation, mode RK_RHS) of the Hubbard system.
+// One RK4 stage (or a plain RHS evaluation, mode RK_RHS) of the Hubbard system;
+// hub_stage_diag takes the buffer of the TPH/GW/DSL diagonal gathers
+// (hub_diag_bytes) instead of the context's own.
 g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc);
+g1g2_status hub_stage_diag(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
+                           const Regs& acc, const Regs& out, double cb, double cc, cd* diag);
+size_t hub_diag_bytes(const g1g2_ctx* c);
+// The static device scratch of g1g2_rhs_noalloc on the context's device:
+// looked up once per device at context set-up.
+g1g2_status hub_noalloc_setup(g1g2_ctx* c);
 g1g2_status hub_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
 g1g2_status hub_site_observables(g1g2_ctx* c, const Regs& s, double* nu, double* nd, double* docc);
 g1g2_status hub_batch_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);

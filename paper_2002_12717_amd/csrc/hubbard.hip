@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -974,7 +975,7 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
     if (n_diag(SE) > 0) {
         using TI = typename StageTypes<MODE, MIXED>::In;
         hipLaunchKernelGGL((hub_diag_kernel<TI, SE>), dim3(c->hub.ndwork), dim3(256), 0, c->stream,
-                           c->hub.desc, c->hub.dwork, s.in2, c->hub.diag);
+                           c->hub.desc, c->hub.dwork, s.in2, const_cast<cd*>(s.diag));
     }
     if (c->hub.slices) {
         if (c->hub.realhop)
@@ -1345,6 +1346,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     H.slices = slicek;
     H.realhop = realhop;
     H.ndwork = (int)dwork.size();
+    H.diag_elems = n_diag(se) > 0 ? n_diag(se) * doff : 0;
     H.hdesc = desc;
     H.chunk = chunks;
     H.nwork = (int)work.size();
@@ -1418,7 +1420,13 @@ g1g2_status hub_step_persistent(g1g2_ctx* c, double dt, int64_t nsteps) {
 
 g1g2_status hub_stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
                       const Regs& acc, const Regs& out, double cb, double cc) {
+    return hub_stage_diag(c, mode, t, in, y, acc, out, cb, cc, c->hub.diag);
+}
+
+g1g2_status hub_stage_diag(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y,
+                           const Regs& acc, const Regs& out, double cb, double cc, cd* diag) {
     StageArgs s = make_stage(c, t, in, y, acc, out, cb, cc);
+    s.diag = diag;
     switch (mode) {
         case RK_RHS: return launch_stage<RK_RHS>(c, s);
         case RK_FIRST: return launch_stage<RK_FIRST>(c, s);
@@ -1496,4 +1504,60 @@ g1g2_status hub_site_observables(g1g2_ctx* c, const Regs& s, double* nu, double*
     if (nd) std::memcpy(nd, h.data() + ns, ns * sizeof(double));
     if (docc) std::memcpy(docc, h.data() + 2 * ns, ns * sizeof(double));
     return G1G2_OK;
+}
+
+// --------------------------------------------------------------------------- allocation-free RHS
+// The right-hand side of one Hubbard cluster without any allocation: the
+// diagonal gathers of TPH, GW and DSL (n_diag ns^3 complex elements) go to a
+// static device array of NOALLOC_SCRATCH_BYTES instead of the context's
+// buffer.  Each GPU holds its own copy of the array until the process ends;
+// every call on a GPU shares it.  Host code never passes the array's name to a
+// kernel: its device address is looked up per device at context set-up
+// (hub_noalloc_setup) and that address is what the kernels receive.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;   // DSL at ns = 64: 8 * 64^3 * 16 B
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+void* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+size_t hub_diag_bytes(const g1g2_ctx* c) { return (size_t)c->hub.diag_elems * sizeof(cd); }
+
+g1g2_status hub_noalloc_setup(g1g2_ctx* c) {
+    int dev = -1;
+    HIP_OK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return set_error(c, G1G2_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[dev]) return G1G2_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return set_error(c, G1G2_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    noalloc_ptr[dev] = p;
+    return G1G2_OK;
+}
+
+extern "C" g1g2_status g1g2_rhs_noalloc(g1g2_ctx* c, double t, const void* G1, const void* G2, void* dG1,
+                                        void* dG2) {
+    if (!c || !G1 || !G2 || !dG1 || !dG2) return G1G2_EINVAL;
+    if (c->d.basis != G1G2_HUBBARD)
+        return set_error(c, G1G2_EUNSUPPORTED, "g1g2_rhs_noalloc: Hubbard basis only");
+    if (c->hub.ncl != 1) return set_error(c, G1G2_ESTATE, "g1g2_rhs_noalloc: single-cluster call on a batch");
+    const size_t need = hub_diag_bytes(c);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return set_error(c, G1G2_EINVAL,
+                         "g1g2_rhs_noalloc: the diagonal gathers need " + std::to_string(need) +
+                             " bytes of scratch, more than its " + std::to_string(NOALLOC_SCRATCH_BYTES));
+    void* ptr = nullptr;
+    if (c->device >= 0 && c->device < NOALLOC_MAX_DEVICES) {
+        std::lock_guard<std::mutex> lock(noalloc_mu);
+        ptr = noalloc_ptr[c->device];
+    }
+    if (!ptr) return set_error(c, G1G2_ESTATE, "g1g2_rhs_noalloc: no scratch address for the context's device");
+    Regs in{(cd*)G1, (cd*)G2};
+    Regs out{(cd*)dG1, (cd*)dG2};
+    return hub_stage_diag(c, RK_RHS, t, in, in, in, out, 0.0, 0.0, (cd*)ptr);
 }
