@@ -553,16 +553,13 @@ def run_batch(args, torch, B):
     clusters = batched_clusters()
     ns = [c.ns for c in clusters]
     n4 = float(sum(n ** 4 for n in ns))
-    chunks = autotune.chunks_for(ns)
-    flags = autotune.flags_for()
     stream = torch.cuda.Stream()
     dt = clusters[0].dt
     se = args.selfenergy or "tpp"
     res = {}
     for prec in ("fp64", "mixed"):
-        b = B.Batch(SE_CODES[se](B), ns, [c.U for c in clusters], [c.h0 for c in clusters],
-                    [c.g1 for c in clusters], chunk=chunks, stream=stream.cuda_stream,
-                    precision=B.FP64 if prec == "fp64" else B.MIXED, flags=flags)
+        b = autotune.make_batch(B, clusters, SE_CODES[se](B), stream=stream.cuda_stream,
+                                precision=B.FP64 if prec == "fp64" else B.MIXED)
         ms, wall = timed_steps(b, dt, args.steps, args.warmup, stream, torch)
         g1 = [b.get_cluster(q, with_g2=False)[0] for q in range(len(ns))]
         obs = b.observables()

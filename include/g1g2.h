@@ -247,11 +247,12 @@ g1g2_status g1g2_set_switch(g1g2_ctx* ctx, double t_on, double tau);
  * c: ns[c] sites, on-site U[c], h0[c] and G1_0[c] as host arrays
  * [2][ns][ns]; G2(0) = 0.  chunk[c] sets the G2 elements handled by one
  * work-group of cluster c (NULL or 0: default), e.g. from an autotuning
- * table: chunk > 0 is the granularity of the row stage kernel (one wave per
- * G2 row A[i][j][k][:], rounded to whole wave units of rows; the slice kernel
- * always stages whole slices, see G1G2_HUB_SLICE_KERNEL), chunk < 0 selects
- * the per-element kernel with |chunk| elements per work-group (any negative
- * entry selects the per-element kernel for the whole batch).
+ * table: chunk > 0 is, for the slice kernel, the most G2 elements one work
+ * item stages (whole (i,j) slices, at least one, at most 4096 elements), and,
+ * for the row kernel, the granularity of its work (one wave per G2 row
+ * A[i][j][k][:], rounded to whole wave units of rows); chunk < 0 selects the
+ * per-element kernel with |chunk| elements per work-group (any negative entry
+ * selects the per-element kernel for the whole batch).
  * g1g2_step_rk4, g1g2_profile and g1g2_destroy act on the whole batch; the
  * single-cluster calls (rhs, get/set_state, set_h0/U/drive) return ESTATE. */
 g1g2_status g1g2_batch_init(g1g2_ctx** out, const g1g2_desc* desc, int32_t n, const int32_t* ns,
@@ -264,7 +265,10 @@ g1g2_status g1g2_batch_observables(g1g2_ctx* ctx, g1g2_obs* out);
 g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void* G2);
 
 /* Discrete adjoint of the Runge-Kutta propagation (single-cluster Hubbard,
- * SOA, with or without drive).  g1g2_forward_checkpointed advances the state
+ * SOA, with or without drive; binary64, or MIXED: the forward pass and its
+ * recomputed segments keep the G2 stage copies in binary32 like the mixed
+ * stages of g1g2_step_rk4, and the reverse sweep reads them as such, with
+ * every cotangent and sum in binary64).  g1g2_forward_checkpointed advances the state
  * by nsteps steps of size dt exactly like g1g2_step_rk4 and keeps a device
  * copy of the state every `interval` steps (interval <= 0:
  * ceil(sqrt(nsteps / 4))); g1g2_adjoint recomputes one segment at a time and
@@ -279,7 +283,8 @@ g1g2_status g1g2_batch_get_state(g1g2_ctx* ctx, int32_t cluster, void* G1, void*
  * by the reverse sweep of the discrete RK4 map with each checkpoint segment
  * recomputed once.  a, b: host arrays of nb doubles.  The final state is left
  * in place.  ESTATE without a preceding forward_checkpointed;
- * EUNSUPPORTED for other bases, selfenergies, batches or MIXED precision.   */
+ * EUNSUPPORTED for other bases, selfenergies or batches, and with a
+ * switching ramp set.                                                       */
 g1g2_status g1g2_forward_checkpointed(g1g2_ctx* ctx, double dt, int64_t nsteps, int32_t interval);
 g1g2_status g1g2_adjoint(g1g2_ctx* ctx, const double* a, const double* b, double* grad_c,
                          double* grad_U, double* loss);

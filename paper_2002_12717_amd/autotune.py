@@ -1,12 +1,14 @@
 """Autotuner of the ragged Hubbard batch.  It first chooses the stage kernel
 (the slice kernel, the row kernel, or the per-element kernel, which negative
-chunks select), then, for the row and per-element kernels, per cluster size
-class, the number of G2 elements handled by one work-group of the flat work
-list of g1g2_batch_init (the row kernel rounds it to whole wave units of
-rows; the slice kernel always stages whole slices and has no such knob).
-Coordinate descent over the classes; each candidate is timed with HIP events
-over whole RK4 steps on the real batch.  The table is written as JSON and read
-back by ``chunks_for`` and ``flags_for``.
+chunks select), then, per cluster size class, the number of G2 elements one
+work-group of the flat work list of g1g2_batch_init handles: for the slice
+kernel the most elements a work item stages in LDS (whole (i,j) slices; the
+launch sizes its LDS for the longest item, so shorter items leave room for
+more work-groups per compute unit), for the row kernel its granularity
+(rounded to whole wave units of rows), for the per-element kernel its
+elements per work-group.  Coordinate descent over the classes; each candidate
+is timed with HIP events over whole RK4 steps on the real batch.  The table is
+written as JSON and read back by ``chunks_for`` and ``flags_for``.
 """
 from __future__ import annotations
 
@@ -22,7 +24,10 @@ CLASSES = [(1, 16), (17, 25), (26, 49)]          # ns ranges (inclusive)
 # < 0: per-element stage kernel with |value| elements per work-group
 CANDIDATES_ROW = [256, 512, 1024, 2048, 4096]
 CANDIDATES_FLAT = [-256, -512, -1024, -2048]
+# slice kernel: elements per work item (4096 is the library's default and limit)
+CANDIDATES_SLICE = [1024, 2048, 3072, 4096]
 DEFAULT = 1024
+START = {"slice": 4096, "row": DEFAULT, "element": -256}
 
 
 def class_of(ns: int) -> int:
@@ -55,6 +60,16 @@ def flags_for(table=None) -> int:
     return {"slice": B.HUB_SLICE_KERNEL, "row": B.HUB_ROW_KERNEL}.get(table.get("kernel"), 0)
 
 
+def make_batch(B, clusters, selfenergy, stream=0, precision=None, table=None):
+    """g1g2_batch_init of the clusters with the stage kernel and the per-class
+    chunks of the tuning table (the stored one by default)."""
+    table = load_table() if table is None else table
+    ns = [c.ns for c in clusters]
+    return B.Batch(selfenergy, ns, [c.U for c in clusters], [c.h0 for c in clusters],
+                   [c.g1 for c in clusters], chunk=chunks_for(ns, table), stream=stream,
+                   precision=B.FP64 if precision is None else precision, flags=flags_for(table))
+
+
 def _time(B, torch, clusters, selfenergy, chunks, steps, stream, flags=0):
     b = B.Batch(selfenergy, [c.ns for c in clusters], [c.U for c in clusters],
                 [c.h0 for c in clusters], [c.g1 for c in clusters], chunk=chunks,
@@ -85,13 +100,13 @@ def tune(n_clusters: int = 512, steps: int = 8, selfenergy_name: str = "tpp", ou
     kflags = {"slice": B.HUB_SLICE_KERNEL, "row": B.HUB_ROW_KERNEL, "element": 0}
     best, base, kernel = None, float("inf"), None
     for kern in KERNELS:
-        trial = [-256 if kern == "element" else DEFAULT] * len(CLASSES)
+        trial = [START[kern]] * len(CLASSES)
         ms = _time(B, torch, clusters, se, [trial[class_of(n)] for n in ns], steps, stream, kflags[kern])
         log.append({"kernel": kern, "chunk_per_class": trial, "ms_per_step": ms})
         print(f"kernel {kern} {trial} {ms:.3f} ms/step", flush=True)
         if ms < base:
             base, best, kernel = ms, trial, kern
-    cands = {"row": CANDIDATES_ROW, "element": CANDIDATES_FLAT}.get(kernel, [])
+    cands = {"slice": CANDIDATES_SLICE, "row": CANDIDATES_ROW, "element": CANDIDATES_FLAT}[kernel]
     for q in range(len(CLASSES)):
         for cand in cands:
             if cand == best[q]:

@@ -41,7 +41,8 @@ namespace {
 
 struct AdjArgs {
     Cl a;                       // stage state (X, Y) and model data
-    const cd* A;                // stage state G2
+    const void* A;              // stage state G2: binary64, or binary32 (a32) for the
+    int a32;                    // mixed-precision stage copies Y2, Y3, Y4
     const cd* gin1;             // cotangent of dG1 (scaled by gscale)
     const cd* gin2;             // cotangent of dG2
     double gscale;
@@ -66,6 +67,11 @@ struct AdjArgs {
 enum { R_X = 0, R_Y = 6, R_M02 = 12, R_M13 = 13, R_UP = 14, R_N = 15 };
 
 __device__ __forceinline__ cd cmul3(cd a, cd b, cd c) { return cmul(cmul(a, b), c); }
+
+// Element e of the stage state G2 (binary64 arithmetic whatever its storage).
+__device__ __forceinline__ cd ld_a(const AdjArgs& s, long long e) {
+    return s.a32 ? ld_c(static_cast<const float2*>(s.A), e) : ld_c(static_cast<const cd*>(s.A), e);
+}
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
             }
             // source-term reductions
             const cd B = cscale(cmul_i(g), gs);
-            const cd cav = cconj(s.A[e]);
+            const cd cav = cconj(ld_a(s, e));
             const cd xik = X[i * ns + k], xjk = X[j * ns + k], yjk = Y[j * ns + k];
             const cd xlk = X[l * ns + k], ykl = Y[k * ns + l];
             const double dd = (double)(i == j) - (double)(k == l);
@@ -414,7 +420,7 @@ __global__ __launch_bounds__(256) void adj_g1e_kernel(AdjArgs s) {
         if (i == j) mu = cadd(mu, cscale(cmul_i(eb[i]), a.U));
         // collision-integral part of dL/dU: I_ij = -i U A..., Ibar_ij = B_ij + conj(B_ji)
         cd bb = cadd(cscale(cmul_i(gg[r]), gs), cconj(cscale(cmul_i(gg[j * ns + i]), gs)));
-        cd av = sig == 0 ? s.A[((i * ns + i) * ns + j) * ns + i] : s.A[((i * ns + i) * ns + i) * ns + j];
+        cd av = sig == 0 ? ld_a(s, ((i * ns + i) * ns + j) * ns + i) : ld_a(s, ((i * ns + i) * ns + i) * ns + j);
         cd dI = cmul_mi(av);   // dI/dU
         ubar = dI.x * bb.x + dI.y * bb.y;
         cd base = s.init ? s.lam1[e] : s.lacc1[e];
@@ -467,6 +473,7 @@ namespace {
 
 struct AdjState {
     int64_t nsteps = 0;
+    bool mixed = false;        // binary32 G2 stage copies (Y2, Y3, Y4), as the mixed forward stages
     int interval = 0;
     double dt = 0.0, t0 = 0.0;
     int nck = 0;
@@ -489,9 +496,10 @@ constexpr int ADJ_PAIRS_PER_PART = 64;
 
 AdjState* adj_of(g1g2_ctx* c) { return reinterpret_cast<AdjState*>(c->adj); }
 
-g1g2_status alloc_reg(g1g2_ctx* c, Regs& r) {
+// half32: the G2 part holds binary32 values only (a mixed-precision stage copy)
+g1g2_status alloc_reg(g1g2_ctx* c, Regs& r, bool half32 = false) {
     HIP_OK(c, hipMalloc(&r.g1, c->n1 * sizeof(cd)));
-    HIP_OK(c, hipMalloc(&r.g2, c->n2 * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&r.g2, c->n2 * (half32 ? sizeof(float2) : sizeof(cd))));
     return G1G2_OK;
 }
 
@@ -508,9 +516,10 @@ g1g2_status copy_reg(g1g2_ctx* c, const Regs& dst, const Regs& src) {
     return G1G2_OK;
 }
 
-AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double gscale, const Regs& lam,
-                 const Regs& lacc, const Regs& gnext, double alpha, double beta, int init, int has_next,
-                 double* grads) {
+// S32: the G2 of S holds binary32 values (a mixed-precision stage copy).
+AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, bool S32, const Regs& gin, double gscale,
+                 const Regs& lam, const Regs& lacc, const Regs& gnext, double alpha, double beta, int init,
+                 int has_next, double* grads) {
     HubbardData& H = c->hub;
     AdjState* st = adj_of(c);
     const ClusterDesc& d = H.hdesc[0];
@@ -528,6 +537,7 @@ AdjArgs make_adj(g1g2_ctx* c, double t, const Regs& S, const Regs& gin, double g
     a.Y = S.g1 + d.ns * d.ns;
     s.a = a;
     s.A = S.g2;
+    s.a32 = S32 ? 1 : 0;
     s.gin1 = gin.g1;
     s.gin2 = gin.g2;
     s.gscale = gscale;
@@ -603,14 +613,13 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     if (c->d.basis != G1G2_HUBBARD || c->d.selfenergy != G1G2_SOA || c->hub.ncl != 1)
         return set_error(c, G1G2_EUNSUPPORTED, "the adjoint covers the single-cluster Hubbard SOA system");
     if (c->hub.hdesc[0].ns > 64) return set_error(c, G1G2_EUNSUPPORTED, "adjoint supports ns <= 64");
-    if (c->d.precision != G1G2_FP64)
-        return set_error(c, G1G2_EUNSUPPORTED, "the adjoint runs in binary64 only");
     if (c->has_switch())
         return set_error(c, G1G2_EUNSUPPORTED, "the adjoint takes a constant U (switching is set)");
     adj_free(c);
     AdjState* st = new AdjState();
     c->adj = st;
     st->nsteps = nsteps;
+    st->mixed = c->d.precision == G1G2_MIXED;
     // default: the interval that minimizes checkpoints + four states per segment step
     st->interval = interval > 0 ? interval
                                 : std::max<int>(1, (int)std::ceil(std::sqrt((double)nsteps / 4.0)));
@@ -624,7 +633,7 @@ g1g2_status g1g2_forward_checkpointed(g1g2_ctx* c, double dt, int64_t nsteps, in
     for (auto* v : {&st->seg, &st->seg2, &st->seg3, &st->seg4}) {
         v->resize(st->interval);
         for (auto& r : *v)
-            if ((s = alloc_reg(c, r)) != G1G2_OK) return s;
+            if ((s = alloc_reg(c, r, st->mixed && v != &st->seg)) != G1G2_OK) return s;
     }
     for (Regs* r : {&st->LAM, &st->LACC, &st->CA, &st->CB})
         if ((s = alloc_reg(c, *r)) != G1G2_OK) return s;
@@ -664,7 +673,7 @@ g1g2_status g1g2_adjoint(g1g2_ctx* c, const double* wa, const double* wb, double
     prof_mark(c, "adj_init");
     {
         const Regs& fin = st->ckpt[st->nck];
-        AdjArgs tmp = make_adj(c, st->t0 + st->nsteps * dt, fin, fin, 1.0, fin, fin, fin, 0, 0, 0, 0, nullptr);
+        AdjArgs tmp = make_adj(c, st->t0 + st->nsteps * dt, fin, false, fin, 1.0, fin, fin, fin, 0, 0, 0, 0, nullptr);
         hipLaunchKernelGGL(adj_terminal_kernel, dim3(1), dim3(1), 0, c->stream, tmp.a, fin.g2, st->dev_ab,
                            st->dev_ab + ns, st->LAM.g1, st->LAM.g2, st->dev_ab + 2 * ns);
         HIP_OK(c, hipGetLastError());
@@ -692,10 +701,11 @@ g1g2_status g1g2_adjoint(g1g2_ctx* c, const double* wa, const double* wb, double
             const Regs& y = st->seg[m];
             const double t = st->t0 + (double)n * dt;
             double* g = st->grads + (size_t)8 * n;
-            if ((s = vjp(c, make_adj(c, t + dt, st->seg4[m], lam, dt / 6.0, lam, lacc, st->CA, dt / 3.0, dt, 1, 1, g + 6))) != G1G2_OK) return s;
-            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg3[m], st->CA, 1.0, lam, lacc, st->CB, dt / 3.0, dt / 2.0, 0, 1, g + 4))) != G1G2_OK) return s;
-            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg2[m], st->CB, 1.0, lam, lacc, st->CA, dt / 6.0, dt / 2.0, 0, 1, g + 2))) != G1G2_OK) return s;
-            if ((s = vjp(c, make_adj(c, t, y, st->CA, 1.0, lam, lacc, st->CB, 0.0, 0.0, 0, 0, g + 0))) != G1G2_OK) return s;
+            const bool m32 = st->mixed;   // the stage copies Y2, Y3, Y4 are binary32 in mixed precision
+            if ((s = vjp(c, make_adj(c, t + dt, st->seg4[m], m32, lam, dt / 6.0, lam, lacc, st->CA, dt / 3.0, dt, 1, 1, g + 6))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg3[m], m32, st->CA, 1.0, lam, lacc, st->CB, dt / 3.0, dt / 2.0, 0, 1, g + 4))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t + 0.5 * dt, st->seg2[m], m32, st->CB, 1.0, lam, lacc, st->CA, dt / 6.0, dt / 2.0, 0, 1, g + 2))) != G1G2_OK) return s;
+            if ((s = vjp(c, make_adj(c, t, y, false, st->CA, 1.0, lam, lacc, st->CB, 0.0, 0.0, 0, 0, g + 0))) != G1G2_OK) return s;
             std::swap(lam, lacc);
         }
     }

@@ -48,6 +48,7 @@ struct HubbardData {
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
     bool realhop = false;          // every hopping (off-diagonal h0) is real
     bool slices = false;           // slice stage kernel (every selfenergy, on row-kernel clusters)
+    int slice_elems = 0;           // slice kernel: G2 elements of the longest item (its LDS stage)
     WorkItem* dwork = nullptr;     // TPH, GW, DSL: work list of the diagonal gather
     int ndwork = 0;
     cd* diag = nullptr;            // per cluster n_diag [ns]^3 gathered diagonal tensors

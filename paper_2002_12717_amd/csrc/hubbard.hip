@@ -601,7 +601,9 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
     constexpr int ZR = Z_MAX_ROW;
-    __shared__ cd P[SLICE_ELEMS];
+    // the staged slices: as many elements as the longest item of the launch
+    // (at most SLICE_ELEMS), so that shorter items leave LDS for more work-groups
+    extern __shared__ cd P[];
     __shared__ cd eu[NS_MAX_ROW], ed[NS_MAX_ROW];
     // per site and neighbour slot (padded to ZR; a missing neighbour has offset
     // 0 and hopping 0): element offsets of the neighbour along l (p - l),
@@ -978,12 +980,13 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
                            c->hub.desc, c->hub.dwork, s.in2, const_cast<cd*>(s.diag));
     }
     if (c->hub.slices) {
+        const size_t lds = (size_t)c->hub.slice_elems * sizeof(cd);
         if (c->hub.realhop)
             hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork),
-                               dim3(SLICE_THREADS), 0, c->stream, s);
+                               dim3(SLICE_THREADS), lds, c->stream, s);
         else
             hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork),
-                               dim3(SLICE_THREADS), 0, c->stream, s);
+                               dim3(SLICE_THREADS), lds, c->stream, s);
         return;
     }
     if constexpr (!has_pol(SE)) {   // GW and DSL run on the row and slice kernels only (checked at setup)
@@ -1242,6 +1245,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
                         ((fl & G1G2_HUB_SLICE_KERNEL) || total * nch >= SLICE_MIN_ELEMS || small1);
     long long g2off = 0;
     long long g1off = 0, xoff = 0, doff = 0;
+    int slice_elems = 0;
     for (int cl = 0; cl < ncl; ++cl) {
         const int ns = nsv[cl];
         const cd* h0 = h0s[cl];
@@ -1285,13 +1289,16 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
         const long long n4 = (long long)ns * ns * ns * ns;
         if (slicek) {
             // slice items: at most floor(SLICE_ELEMS / ns^2) whole (i, j) slices of
-            // one channel each; slice index = channel ns^2 + i ns + j
+            // one channel each, or fewer when chunk (elements per item) asks for
+            // it; slice index = channel ns^2 + i ns + j
             int per = SLICE_ELEMS / (ns * ns);
+            if (chunk_in && chunk_in[cl] > 0) per = std::max(1, std::min(per, chunk_in[cl] / (ns * ns)));
             // the particle-particle ladder keeps the diagonal entries of its slices in LDS
             if (has_pp(se)) per = std::max(1, std::min(per, SLICE_DIAG / ns));
             if (small1) per = std::max(1, std::min(per, SLICE_SMALL / (ns * ns)));
             const int nsl = ns * ns;
             chunks[cl] = per * ns * ns;
+            slice_elems = std::max(slice_elems, per * ns * ns);
             for (int chn = 0; chn < nch; ++chn)
                 for (int s0 = 0; s0 < nsl; s0 += per) {
                     const int s1 = std::min(nsl, s0 + per);
@@ -1346,6 +1353,7 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     H.slices = slicek;
     H.realhop = realhop;
     H.ndwork = (int)dwork.size();
+    H.slice_elems = slice_elems;
     H.diag_elems = n_diag(se) > 0 ? n_diag(se) * doff : 0;
     H.hdesc = desc;
     H.chunk = chunks;

@@ -87,3 +87,37 @@ def test_autotune_table_lookup():
     assert autotune.flags_for({"kernel": "slice"}) == B.HUB_SLICE_KERNEL
     assert autotune.flags_for({"kernel": "element"}) == 0
     assert autotune.flags_for({}) == 0
+
+
+def test_tuning_table_drives_batch_init(monkeypatch):
+    """The batch the benchmark and the tests build takes the tuning table's
+    stage kernel and per-class chunks as the g1g2_batch_init arguments."""
+    import numpy as np
+    from paper_2002_12717_amd import autotune
+    from paper_2002_12717_amd import binding as B
+    from workloads import batched_clusters
+    seen = {}
+
+    class FakeLib:
+        def g1g2_batch_init(self, ctx, desc, n, ns, U, h0, g1, chunk, stream):
+            seen["flags"] = desc._obj.flags
+            seen["n"] = n
+            seen["chunk"] = np.ctypeslib.as_array(ctypes.cast(chunk, ctypes.POINTER(ctypes.c_int32)),
+                                                  (n,)).copy()
+            return B.OK
+
+        def g1g2_destroy(self, ctx):
+            pass
+
+    monkeypatch.setattr(B, "load", lambda *a: FakeLib())
+    cl = batched_clusters(n=40)
+    table = {"kernel": "slice", "chunk_per_class": [1024, 2048, 3072]}
+    b = autotune.make_batch(B, cl, B.TPP, table=table)
+    assert seen["flags"] == B.HUB_SLICE_KERNEL and seen["n"] == 40
+    want = [1024 if c.ns <= 16 else (2048 if c.ns <= 25 else 3072) for c in cl]
+    assert list(seen["chunk"]) == want and len(set(want)) > 1
+    b.ctx = None
+    table = {"kernel": "row", "chunk_per_class": [256, 512, 4096]}
+    autotune.make_batch(B, cl, B.TPP, table=table)
+    assert seen["flags"] == B.HUB_ROW_KERNEL
+    assert list(seen["chunk"]) == [256 if c.ns <= 16 else (512 if c.ns <= 25 else 4096) for c in cl]
