@@ -20,8 +20,9 @@ G2 is the paper's time-diagonal correlated pair function (eq:gscor-def).
 
 Every function is pinned by ``tests/test_oracle_pins.py`` against something
 other than itself: exact diagonalization of small systems, the brute-force
-HF-GKBA collision integral, the equivalence of the general-basis equations
-with the Hubbard reformulations and of the direct sums with the reformulated
-ones, conservation laws and closed forms (w = 0).  None is parity unpinned.
+HF-GKBA collision integrals (second Born and GW), the equivalence of the
+general-basis equations with the Hubbard reformulations, with the jellium
+momentum-space equations and of the direct sums with the reformulated ones,
+conservation laws and closed forms (w = 0).  None is parity unpinned.
 """
-from . import general, hubbard, integrate, observables, ed  # noqa: F401
+from . import general, hubbard, integrate, jellium, observables, ed  # noqa: F401

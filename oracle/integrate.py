@@ -155,3 +155,29 @@ def propagate_hubbard(system, nsteps=None, selfenergy="soa", U=None, c=None, g2_
         h0u, h0d = hubbard_h0(system, t, c)
         rec.append(hubbard_observables(h0u, h0d, UU * switch_factor(t, switch), y[0], y[1], y[2], t))
     return y, rec
+
+
+# --------------------------------------------------------------------------- jellium
+def propagate_jellium(system, nsteps=None, selfenergy="soa", state=None, t0=0.0, observables_every=0):
+    """RK4 propagation of a ``workloads.JelliumSystem`` (uncorrelated start
+    unless ``state`` = (G1 [2][Nb], G2 [2][2][Nb]^3) is given); returns the
+    final (G1, G2) and the observables every ``observables_every`` steps."""
+    from . import jellium
+    nsteps = system.nsteps if nsteps is None else nsteps
+    nb = system.nb
+    if state is None:
+        g1 = _t(system.g1)
+        g2 = torch.zeros((2, 2, nb, nb, nb), dtype=torch.complex128)
+    else:
+        g1, g2 = state
+    f = lambda t, y: jellium.rhs(system.eps, system.v, y[0], y[1], system.dims, selfenergy)  # noqa: E731
+    rec = []
+    t = t0
+    for n in range(nsteps):
+        if observables_every and n % observables_every == 0:
+            rec.append(jellium.observables(system.eps, system.v, g1, g2, system.dims, t))
+        g1, g2 = rk4_step(f, t, (g1, g2), system.dt)
+        t = t0 + (n + 1) * system.dt
+    if observables_every:
+        rec.append(jellium.observables(system.eps, system.v, g1, g2, system.dims, t))
+    return (g1, g2), rec

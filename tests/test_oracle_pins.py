@@ -587,3 +587,85 @@ def test_elementwise_rhs_equals_full_rhs(se):
     got = E.g2_rhs_elements(h, w, gl, g2, se, idx)
     ref = torch.stack([d2[e] for e in idx])
     assert float((got - ref).abs().max()) < 1e-13 * max(1.0, float(ref.abs().max()))
+
+
+# --------------------------------------------------------------------------- jellium
+def _jellium_case(dims, key):
+    from workloads import random_jellium_state
+    nb = int(np.prod(dims))
+    r = rng(41, nb, key)
+    gl, g2 = random_jellium_state(dims, r)
+    eps = r.uniform(-1, 1, (2, nb))
+    v = r.uniform(0.1, 0.5, nb)
+    v[0] = 0.0
+    d3 = (list(dims) + [1, 1])[:3]
+    n = np.arange(nb)
+    c = np.stack([n % d3[0], (n // d3[0]) % d3[1], n // (d3[0] * d3[1])], 1)
+    neg = (-c[:, 0] % d3[0]) + d3[0] * ((-c[:, 1] % d3[1]) + d3[1] * (-c[:, 2] % d3[2]))
+    v = 0.5 * (v + v[neg])                     # v[q] = v[-q]: a Hermitian w
+    return nb, eps, v, gl, g2
+
+
+@pytest.mark.parametrize("dims", [(4,), (2, 3), (2, 2, 2)])
+@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph"])
+def test_jellium_equals_general_basis_with_plane_wave_w(dims, se):
+    """Sec. III.E, IV.D, V.A, V.B: the momentum-space equations of jellium are
+    the general-basis equations with the plane-wave interaction of
+    eq:jellium-w-matrix.  At a random momentum-conserving state the general
+    right-hand side is diagonal in G1, its G2 in the momentum-transfer layout
+    equals the jellium one, and it has nothing outside the jellium channels
+    but the spin-flip blocks (a b b a) that the exchange terms feed and that
+    feed nothing back."""
+    from oracle import jellium as J
+    nb, eps, v, gl, g2 = _jellium_case(dims, len(se))
+    w = J.plane_wave_w(v, dims)
+    h = np.zeros((2 * nb, 2 * nb), complex)
+    h[:nb, :nb], h[nb:, nb:] = np.diag(eps[0]), np.diag(eps[1])
+    glg = np.zeros((2 * nb, 2 * nb), complex)
+    glg[:nb, :nb], glg[nb:, nb:] = np.diag(gl[0]), np.diag(gl[1])
+    d1, d2 = G.rhs(T(h), T(w), T(glg), J.to_general(T(g2), dims), se)
+    j1, j2 = J.rhs(eps, v, T(gl), T(g2), dims, se)
+    diag = torch.stack([torch.diagonal(d1)[:nb], torch.diagonal(d1)[nb:]])
+    assert (diag - j1).abs().max() < 1e-13 * max(j1.abs().max(), 1.0)
+    assert (d1 - torch.diag(torch.diagonal(d1))).abs().max() == 0.0
+    assert (J.from_general(d2, nb, dims) - j2).abs().max() < 1e-13 * j2.abs().max()
+    rest = d2 - J.to_general(J.from_general(d2, nb, dims), dims)
+    s = torch.arange(2 * nb) // nb
+    flip = (s[:, None, None, None] == s[None, None, None, :]) & (s[None, :, None, None] == s[None, None, :, None]) \
+        & (s[:, None, None, None] != s[None, :, None, None])
+    assert rest[~flip].abs().max() == 0.0
+    if se == "gw":
+        assert rest.abs().max() == 0.0          # no exchange term, no spin-flip block
+
+
+def test_jellium_conservation_and_symmetry():
+    """An interaction quench on a 3x3 grid (GW and T-matrix closures): the
+    particle number of each spin is conserved, the pair symmetries of the
+    momentum-transfer layout (eq:Gsymm_a/b) are kept, and the largest energy
+    drift over t <= 2 falls as dt^4 (RK4; time-independent Hamiltonian)."""
+    from oracle import jellium as J
+    from oracle import integrate as OI
+    from workloads import jellium_system
+    import dataclasses
+    add, sub = J.add_table((3, 3))
+    nb = 9
+    P = torch.arange(nb)[:, None, None]
+    Pb = torch.arange(nb)[None, :, None]
+    Q = torch.arange(nb)[None, None, :]
+    neg = sub[0]
+    for se in ("gw", "tpp", "tph"):
+        s = jellium_system(dims=(3, 3), lbox=4.0, coupling=6.0)
+        drift = []
+        for dt in (0.1, 0.05):
+            sd = dataclasses.replace(s, dt=dt, nsteps=int(round(2.0 / dt)))
+            (g1, g2), rec = OI.propagate_jellium(sd, selfenergy=se, observables_every=int(round(0.1 / dt)))
+            drift.append(max(abs(r["E_tot"] - rec[0]["E_tot"]) for r in rec))
+            assert abs(rec[-1]["N_up"] - rec[0]["N_up"]) < 1e-12
+            assert abs(rec[-1]["N_dn"] - rec[0]["N_dn"]) < 1e-12
+            assert abs(rec[-1]["E_corr"]) > 1e-4
+            ex = torch.stack([torch.stack([g2[b, a][Pb, P, neg[Q]] for b in range(2)]) for a in range(2)])
+            he = torch.stack([torch.stack([g2[a, b][sub[P, Q], add[Pb, Q], neg[Q]].conj() for b in range(2)])
+                              for a in range(2)])
+            assert (g2 - ex).abs().max() < 1e-13 * g2.abs().max()
+            assert (g2 - he).abs().max() < 1e-13 * g2.abs().max()
+        assert 12.0 < drift[0] / drift[1] < 40.0, (se, drift)    # measured 19.5-22.6

@@ -30,6 +30,7 @@ __all__ = [
     "HubbardSystem", "GeneralSystem", "Drive",
     "hubbard_chain_system", "general_system", "gw_system",
     "batched_clusters", "adjoint_system",
+    "JelliumSystem", "momentum_components", "jellium_system", "random_jellium_state",
 ]
 
 
@@ -287,3 +288,89 @@ def adjoint_system(lx: int = 8, ly: int = 8, U: float = 2.0, nmodes: int = 64,
         nsteps = int(round(T / dt))
     return HubbardSystem("hubbard_adjoint", ns, U, np.stack([hop, hop]), g1, dt, nsteps,
                          drive=drive, meta=dict(lx=lx, ly=ly))
+
+
+# ----------------------------------------------------------------------------
+# jellium (plane waves on a periodic momentum grid)
+# ----------------------------------------------------------------------------
+
+@dataclass
+class JelliumSystem:
+    """Uniform electron gas in a plane-wave basis: momenta on a periodic grid
+    ``dims`` (index n = x + Lx (y + Ly z), components added modulo the grid),
+    one-particle energies eps[spin][n], pair interaction v[q] (v[0] = 0),
+    diagonal G^{<,s}_n = i n^s_n."""
+    name: str
+    dims: tuple
+    nb: int
+    eps: np.ndarray           # [2, Nb] float64
+    v: np.ndarray             # [Nb] float64
+    g1: np.ndarray            # [2, Nb] complex128
+    dt: float
+    nsteps: int
+    meta: dict = field(default_factory=dict)
+
+
+def momentum_components(dims) -> np.ndarray:
+    """Minimum-image integer components m(n) of every grid index, [Nb, 3]
+    (each component in [-L/2, L/2) for even L)."""
+    d = (list(dims) + [1, 1])[:3]
+    n = np.arange(d[0] * d[1] * d[2])
+    c = np.stack([n % d[0], (n // d[0]) % d[1], n // (d[0] * d[1])], 1)
+    L = np.asarray(d)
+    return np.where(c >= (L + 1) // 2, c - L, c)
+
+
+def jellium_system(dims=(6, 6, 6), lbox: float = 2.0 * math.pi, coupling: float = 10.0,
+                   temperature: float = 1.0, mu=(2.0, 1.5), dt: float = 0.02,
+                   nsteps: int = 500) -> JelliumSystem:
+    """Jellium after an interaction quench: momenta k = 2 pi m / lbox on the
+    grid, eps = |k|^2 / 2 for both spins, Coulomb v[q] = coupling 4 pi / (Omega
+    |k(q)|^2) with Omega = lbox^3 (v[0] = 0), and an uncorrelated spin-polarized
+    Fermi-Dirac start n^s = 1 / (exp((eps - mu_s) / T) + 1).  No random draws."""
+    m = momentum_components(dims)
+    k = 2.0 * math.pi / lbox * m
+    k2 = (k * k).sum(1)
+    eps1 = 0.5 * k2
+    omega = lbox ** 3
+    v = np.zeros_like(k2)
+    v[k2 > 0] = coupling * 4.0 * math.pi / (omega * k2[k2 > 0])
+    occ = np.stack([1.0 / (np.exp((eps1 - mu[s]) / temperature) + 1.0) for s in range(2)])
+    g1 = (1j * occ).astype(np.complex128)
+    nb = len(eps1)
+    return JelliumSystem("jellium", tuple(dims), nb, np.stack([eps1, eps1]), v, g1, dt, nsteps,
+                         meta=dict(lbox=lbox, coupling=coupling, temperature=temperature, mu=tuple(mu)))
+
+
+def random_jellium_state(dims, r: np.random.Generator, scale: float = 0.05):
+    """Random diagonal G^< (occupations in (0, 1)) and a random G2 in the
+    momentum-transfer layout g2[a][b][P][Pb][Q] with the pair symmetries of
+    eq:Gsymm_a/b in that layout: g2[a][b][P][Pb][Q] = g2[b][a][Pb][P][-Q] and
+    g2[a][b][P][Pb][Q] = conj(g2[a][b][P-Q][Pb+Q][-Q]).  Draw order: 2 nb
+    uniform occupations, then the real and imaginary parts of the 4 nb^3 G2
+    entries."""
+    d = (list(dims) + [1, 1])[:3]
+    nb = d[0] * d[1] * d[2]
+    gl = (1j * r.uniform(0.05, 0.95, (2, nb))).astype(np.complex128)
+    x = scale * (r.standard_normal((2, 2, nb, nb, nb)) + 1j * r.standard_normal((2, 2, nb, nb, nb)))
+    c = np.stack([np.arange(nb) % d[0], (np.arange(nb) // d[0]) % d[1], np.arange(nb) // (d[0] * d[1])], 1)
+
+    def idx(comp):
+        return (comp[..., 0] % d[0]) + d[0] * ((comp[..., 1] % d[1]) + d[1] * (comp[..., 2] % d[2]))
+
+    add = idx(c[:, None] + c[None, :])
+    sub = idx(c[:, None] - c[None, :])
+    neg = idx(-c)
+    P = np.arange(nb)[:, None, None]
+    Pb = np.arange(nb)[None, :, None]
+    Q = np.arange(nb)[None, None, :]
+    ex = np.empty_like(x)
+    for a in range(2):
+        for b in range(2):
+            ex[a, b] = x[b, a][Pb, P, neg[Q]]
+    x = 0.5 * (x + ex)
+    he = np.empty_like(x)
+    for a in range(2):
+        for b in range(2):
+            he[a, b] = np.conj(x[a, b][sub[P, Q], add[Pb, Q], neg[Q]])
+    return gl, 0.5 * (x + he)
