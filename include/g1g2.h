@@ -71,8 +71,10 @@ typedef enum { G1G2_SOA = 0, G1G2_GW = 1, G1G2_TPP = 2, G1G2_TPH = 3, G1G2_DSL =
 
 /* GENERAL: arbitrary orthonormal basis with a four-index w (Sec. III.C).
  * HUBBARD: Fermi-Hubbard model with on-site U (Sec. III.D); h0 per spin may be
- *          any Hermitian matrix (hopping plus on-site potentials).            */
-typedef enum { G1G2_GENERAL = 0, G1G2_HUBBARD = 1 } g1g2_basis;
+ *          any Hermitian matrix (hopping plus on-site potentials).
+ * JELLIUM: uniform electron gas in plane waves (Sec. III.E); created with
+ *          g1g2_jellium_init.                                                   */
+typedef enum { G1G2_GENERAL = 0, G1G2_HUBBARD = 1, G1G2_JELLIUM = 2 } g1g2_basis;
 
 /* FP64: every operation in binary64.
  * MIXED: general basis: the O(nb^5) and O(nb^6) tensor contractions run in
@@ -148,6 +150,29 @@ typedef struct g1g2_ctx g1g2_ctx;
 g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, const void* w,
                       const void* G1_0, const void* G2_0, void* hip_stream);
 
+/* Jellium (uniform electron gas, Sec. III.E, Sec. IV.D) in a plane-wave basis
+ * on a periodic momentum grid dims[3] = (Lx, Ly, Lz), momentum index
+ * n = x + Lx (y + Ly z), components added modulo the grid (so momentum
+ * conservation is exact in the finite basis); desc->nb = Lx Ly Lz <= 1024.
+ * The pair interaction is eq:jellium-w-matrix in the convention of eq:h:
+ * w = delta(k1 + k2 - k3 - k4) v[k1 - k3] between equal spins of each particle,
+ * v[nb] a host array of reals with v[0] = 0 (the neutralizing background; the
+ * Hartree term then vanishes), and eps[2][nb] (host, reals) the one-particle
+ * energies per spin.  Layouts crossing this boundary:
+ *   G1 = [2][nb] complex: the diagonal G^{<,s}_p (eq:jellium-g1);
+ *   G2 = [3][nb][nb][nb] complex, blocks up-up, up-down, down-down, element
+ *        [c][P][Pb][Q] = G2^{a b a b}_{(P-Q, a), (Pb+Q, b), (P, a), (Pb, b)}
+ *        (eq:g2-def-jellium; down-up follows from eq:Gsymm_a).
+ * G2_0 may be NULL (uncorrelated start).  Selfenergies SOA (eq:jellium-g2) and
+ * GW (eq:jellium-gwpi, Psi^- with G1G2_GW_EXCHANGE); FP64 or MIXED (binary32
+ * G2 stage copies, like the Hubbard basis).  EUNSUPPORTED for the T matrices
+ * and DSL; EINVAL for bad dims, nb != Lx Ly Lz or v[0] != 0.  Every other call
+ * works as for the other bases except set_h0, set_U, set_drive, set_switch, the
+ * adjoint and the batch calls (EUNSUPPORTED or ESTATE).  Observables: N per
+ * spin, E_kin = sum eps n, E_mf the Fock energy, E_corr.                    */
+g1g2_status g1g2_jellium_init(g1g2_ctx** out, const g1g2_desc* desc, const int32_t* dims, const double* eps,
+                              const double* v, const void* G1_0, const void* G2_0, void* hip_stream);
+
 /* One evaluation of the right-hand side (dG1/dt, dG2/dt) of the closed system
  * eq:eom_gone-2 + eq:eom_gone-I + the G2 equation of the selfenergy, at time t
  * with the context's current h0, U and drive.  G1, G2 in, dG1, dG2 out: device
@@ -185,13 +210,14 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* ctx, double dt, int64_t nsteps);
  * library (sizes, selfenergy, flags, drive and switching ramp as they are
  * now): GENERAL (the general-basis matrix-core stages), HUB_PERSISTENT
  * (whole steps of one small Hubbard cluster in one work-group), HUB_SLICE,
- * HUB_ROW or HUB_ELEMENT (one launch per Runge-Kutta stage).               */
+ * HUB_ROW or HUB_ELEMENT (one launch per Runge-Kutta stage), JELLIUM.      */
 enum {
     G1G2_PATH_GENERAL = 0,
     G1G2_PATH_HUB_PERSISTENT = 1,
     G1G2_PATH_HUB_SLICE = 2,
     G1G2_PATH_HUB_ROW = 3,
-    G1G2_PATH_HUB_ELEMENT = 4
+    G1G2_PATH_HUB_ELEMENT = 4,
+    G1G2_PATH_JELLIUM = 5
 };
 g1g2_status g1g2_step_path(const g1g2_ctx* ctx, int32_t* path);
 

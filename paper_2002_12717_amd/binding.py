@@ -16,12 +16,12 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(PKG, "libg1g2.so")
 
-GENERAL, HUBBARD = 0, 1
+GENERAL, HUBBARD, JELLIUM = 0, 1, 2
 SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL, DSL_EXCHANGE = 1, 2, 4, 8, 16
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PATHS = {0: "general", 1: "hub_persistent", 2: "hub_slice", 3: "hub_row", 4: "hub_element"}
+PATHS = {0: "general", 1: "hub_persistent", 2: "hub_slice", 3: "hub_row", 4: "hub_element", 5: "jellium"}
 
 
 class Desc(ctypes.Structure):
@@ -39,6 +39,8 @@ class Obs(ctypes.Structure):
 _SIGS = {
     "g1g2_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_void_p, c_void_p, c_void_p, c_void_p,
                             c_void_p]),
+    "g1g2_jellium_init": (c_int32, [POINTER(c_void_p), POINTER(Desc), c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p]),
     "g1g2_rhs": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "g1g2_rhs_noalloc": (c_int32, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, c_void_p]),
     "g1g2_step_rk4": (c_int32, [c_void_p, c_double, c_int64]),
@@ -151,8 +153,12 @@ class Propagator:
 
     def shapes(self):
         """G1 and G2 shapes of the ABI layout; Hubbard GW stores three G2 channels
-        (up-down-up-down, up-up-up-up, down-down-down-down), and so does Hubbard DSL."""
+        (up-down-up-down, up-up-up-up, down-down-down-down), and so does Hubbard DSL;
+        jellium keeps the diagonal G1 [2][nb] and the up-up, up-down and down-down
+        blocks [3][nb]^3 of G2 in the momentum-transfer layout."""
         nb = self.nb
+        if self.basis == JELLIUM:
+            return (2, nb), (3, nb, nb, nb)
         g1 = (2, nb, nb) if self.basis == HUBBARD else (nb, nb)
         if self.basis == HUBBARD and self.desc.selfenergy in (GW, DSL):
             return g1, (3, nb, nb, nb, nb)
@@ -314,3 +320,29 @@ class Batch(Propagator):
         g2 = np.zeros(shape, np.complex128) if with_g2 else None
         self._check(self.lib.g1g2_batch_get_state(self.ctx, int(c), _ptr(g1), _ptr(g2)))
         return g1, g2
+
+
+class Jellium(Propagator):
+    """A jellium context (g1g2_jellium_init): momenta on the periodic grid
+    ``dims``, energies eps [2][nb], interaction v [nb] (v[0] = 0), G1_0 the
+    diagonal G^< [2][nb]; G2_0 [3][nb]^3 or None."""
+
+    def __init__(self, selfenergy: int, dims, eps, v, G1_0, G2_0=None, precision: int = FP64,
+                 flags: int = 0, stream: int = 0):
+        self.lib = load()
+        d3 = (list(dims) + [1, 1])[:3]
+        self.dims = tuple(int(x) for x in d3)
+        self.basis = JELLIUM
+        self.nb = self.dims[0] * self.dims[1] * self.dims[2]
+        self.flags = flags
+        self.desc = Desc(JELLIUM, selfenergy, precision, flags, self.nb, 0.0)
+        dm = np.asarray(self.dims, np.int32)
+        ep = np.ascontiguousarray(eps, np.float64)
+        vv = np.ascontiguousarray(v, np.float64)
+        g1, g2 = _c128(G1_0), _c128(G2_0)
+        ctx = c_void_p()
+        st = self.lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(self.desc), _ptr(dm), _ptr(ep), _ptr(vv),
+                                        _ptr(g1), _ptr(g2), c_void_p(stream) if stream else None)
+        if st != OK:
+            raise G1G2Error(st, self.lib.g1g2_strerror(st).decode())
+        self.ctx = ctx

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libg1g2.so")
-SOURCES = ["abi.hip", "hubbard.hip", "general.hip", "adjoint.hip"]
+SOURCES = ["abi.hip", "hubbard.hip", "general.hip", "adjoint.hip", "jellium.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

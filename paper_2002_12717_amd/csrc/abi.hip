@@ -52,6 +52,7 @@ g1g2_status fetch(g1g2_ctx* c, const void* src, size_t n, HostCopy& out) {
 
 size_t g1_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
+    if (c->d.basis == G1G2_JELLIUM) return 2 * nb;
     return c->d.basis == G1G2_HUBBARD ? 2 * nb * nb : nb * nb;
 }
 // Channels of the stored G2: Hubbard GW and DSL keep up-down-up-down,
@@ -61,6 +62,7 @@ size_t g2_channels(const g1g2_desc& d) {
 }
 size_t g2_count(const g1g2_ctx* c) {
     const size_t nb = c->d.nb;
+    if (c->d.basis == G1G2_JELLIUM) return 3 * nb * nb * nb;   // up-up, up-down, down-down blocks
     return g2_channels(c->d) * nb * nb * nb * nb;
 }
 
@@ -83,7 +85,7 @@ void free_regs(Regs& r) {
 g1g2_status load_component(g1g2_ctx* c, const void* src, bool device, cd* dst, int rank) {
     const size_t n = rank == 2 ? g1_count(c) : g2_count(c);
     const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (c->d.basis == G1G2_HUBBARD) {
+    if (c->d.basis != G1G2_GENERAL) {   // internal layout = ABI layout
         HIP_OK(c, hipMemcpyAsync(dst, src, n * sizeof(cd), kind, c->stream));
         return G1G2_OK;
     }
@@ -95,7 +97,7 @@ g1g2_status load_component(g1g2_ctx* c, const void* src, bool device, cd* dst, i
 g1g2_status store_component(g1g2_ctx* c, const cd* src, void* dst, bool device, int rank) {
     const size_t n = rank == 2 ? g1_count(c) : g2_count(c);
     const hipMemcpyKind kind = device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (c->d.basis == G1G2_HUBBARD) {
+    if (c->d.basis != G1G2_GENERAL) {
         HIP_OK(c, hipMemcpyAsync(dst, src, n * sizeof(cd), kind, c->stream));
         return G1G2_OK;
     }
@@ -109,6 +111,7 @@ g1g2_status store_component(g1g2_ctx* c, const cd* src, void* dst, bool device, 
 g1g2_status stage(g1g2_ctx* c, int mode, double t, const Regs& in, const Regs& y, const Regs& acc,
                   const Regs& out, double cb, double cc) {
     if (c->d.basis == G1G2_HUBBARD) return hub_stage(c, mode, t, in, y, acc, out, cb, cc);
+    if (c->d.basis == G1G2_JELLIUM) return jel_stage(c, mode, in, y, acc, out, cb, cc);
     return gen_stage(c, mode, t, in, y, acc, out, cb, cc);
 }
 
@@ -223,6 +226,7 @@ void g1g2_destroy(g1g2_ctx* c) {
     adj_free(c);
     hub_free(c);
     gen_free(c);
+    jel_free(c);
     delete c;
 }
 
@@ -231,7 +235,7 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     if (!out || !d || !h0 || !G1_0) return G1G2_EINVAL;
     *out = nullptr;
     if (d->nb <= 0) return G1G2_EINVAL;
-    if (d->basis != G1G2_GENERAL && d->basis != G1G2_HUBBARD) return G1G2_EINVAL;
+    if (d->basis != G1G2_GENERAL && d->basis != G1G2_HUBBARD) return G1G2_EINVAL;   // jellium: g1g2_jellium_init
     if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
     if (d->basis == G1G2_GENERAL && !w) return G1G2_EINVAL;
@@ -297,15 +301,68 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* d, const void* h0, const 
     return G1G2_OK;
 }
 
+g1g2_status g1g2_jellium_init(g1g2_ctx** out, const g1g2_desc* d, const int32_t* dims, const double* eps,
+                              const double* v, const void* G1_0, const void* G2_0, void* hip_stream) {
+    if (!out || !d || !dims || !eps || !v || !G1_0) return G1G2_EINVAL;
+    *out = nullptr;
+    if (d->basis != G1G2_JELLIUM) return G1G2_EINVAL;
+    if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
+    if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
+    if (d->flags & ~(G1G2_PTR_DEVICE | G1G2_GW_EXCHANGE)) return G1G2_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (dims[k] < 1 || dims[k] > 1024) return G1G2_EINVAL;
+    const long long nbl = (long long)dims[0] * dims[1] * dims[2];
+    if (nbl != d->nb) return G1G2_EINVAL;
+    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_GW) return G1G2_EUNSUPPORTED;
+    if (nbl > jel_max_nb()) return G1G2_EUNSUPPORTED;
+    if (v[0] != 0.0) return G1G2_EINVAL;   // the neutralizing background removes v_0
+    for (long long q = 0; q < nbl; ++q)
+        if (!std::isfinite(v[q]) || !std::isfinite(eps[q]) || !std::isfinite(eps[nbl + q])) return G1G2_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return G1G2_EDEVICE;
+    g1g2_ctx* c = new (std::nothrow) g1g2_ctx();
+    if (!c) return G1G2_ENOMEM;
+    c->d = *d;
+    c->stream = (hipStream_t)hip_stream;
+    {
+        const char* ng = std::getenv("G1G2_NO_GRAPH");
+        c->graphs = !(ng && ng[0] == '1');
+    }
+    (void)hipGetDevice(&c->device);
+    const size_t nb = (size_t)nbl;
+    c->n1 = 2 * nb;
+    c->n2 = 3 * nb * nb * nb;
+    auto fail = [&](g1g2_status st) {
+        g1g2_destroy(c);
+        return st;
+    };
+    g1g2_status s;
+    for (Regs* r : {&c->y, &c->acc, &c->s0, &c->s1, &c->io})
+        if ((s = alloc_regs(c, *r)) != G1G2_OK) return fail(s);
+    if ((s = guard_alloc(c, 1)) != G1G2_OK || (s = guard_clear(c)) != G1G2_OK) return fail(s);
+    c->nscratch = 64;
+    if (hipMalloc(&c->dscratch, c->nscratch * sizeof(double)) != hipSuccess) return fail(G1G2_ENOMEM);
+    const int dd[3] = {dims[0], dims[1], dims[2]};
+    if ((s = jel_setup(c, dd, eps, v)) != G1G2_OK) return fail(s);
+    const bool dev = d->flags & G1G2_PTR_DEVICE;
+    if ((s = load_component(c, G1_0, dev, c->y.g1, 2)) != G1G2_OK) return fail(s);
+    if (G2_0 && (s = load_component(c, G2_0, dev, c->y.g2, 4)) != G1G2_OK) return fail(s);
+    if ((s = jel_state_changed(c)) != G1G2_OK) return fail(s);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(G1G2_EDEVICE);
+    *out = c;
+    return G1G2_OK;
+}
+
 g1g2_status g1g2_rhs(g1g2_ctx* c, double t, const void* G1, const void* G2, void* dG1, void* dG2) {
     if (!c || !G1 || !G2 || !dG1 || !dG2) return G1G2_EINVAL;
     if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
         return set_error(c, G1G2_ESTATE, "single-cluster call on a batch");
     g1g2_status s;
-    if (c->d.basis == G1G2_HUBBARD) {
+    if (c->d.basis != G1G2_GENERAL) {   // caller buffers in the internal layout
         Regs in{(cd*)G1, (cd*)G2};
         Regs out{(cd*)dG1, (cd*)dG2};
-        s = hub_stage(c, RK_RHS, t, in, in, in, out, 0.0, 0.0);
+        s = c->d.basis == G1G2_HUBBARD ? hub_stage(c, RK_RHS, t, in, in, in, out, 0.0, 0.0)
+                                       : jel_stage(c, RK_RHS, in, in, in, out, 0.0, 0.0);
         if (s != G1G2_OK) return s;
         HIP_OK(c, hipStreamSynchronize(c->stream));
         return G1G2_OK;
@@ -373,6 +430,7 @@ g1g2_status g1g2_step_rk4(g1g2_ctx* c, double dt, int64_t nsteps) {
 g1g2_status g1g2_step_path(const g1g2_ctx* c, int32_t* path) {
     if (!c || !path) return G1G2_EINVAL;
     if (c->d.basis == G1G2_GENERAL) *path = G1G2_PATH_GENERAL;
+    else if (c->d.basis == G1G2_JELLIUM) *path = G1G2_PATH_JELLIUM;
     else if (hub_persistent_ok(c)) *path = G1G2_PATH_HUB_PERSISTENT;
     else if (c->hub.slices) *path = G1G2_PATH_HUB_SLICE;
     else if (c->hub.rows) *path = G1G2_PATH_HUB_ROW;
@@ -392,8 +450,9 @@ g1g2_status g1g2_observables(g1g2_ctx* c, g1g2_obs* o) {
     if (c->d.basis == G1G2_HUBBARD && c->hub.ncl != 1)
         return set_error(c, G1G2_ESTATE, "use g1g2_batch_observables on a batch");
     std::memset(o, 0, sizeof(*o));
-    g1g2_status s = c->d.basis == G1G2_HUBBARD ? hub_observables(c, c->y, c->t, o)
-                                               : gen_observables(c, c->y, c->t, o);
+    g1g2_status s = c->d.basis == G1G2_HUBBARD   ? hub_observables(c, c->y, c->t, o)
+                    : c->d.basis == G1G2_JELLIUM ? jel_observables(c, c->y, o)
+                                                 : gen_observables(c, c->y, c->t, o);
     if (s != G1G2_OK) return s;
     std::vector<long long> first;
     if ((s = guard_read(c, first)) != G1G2_OK) return s;
@@ -437,6 +496,7 @@ g1g2_status g1g2_set_state(g1g2_ctx* c, const void* G1, const void* G2, double t
         HIP_OK(c, hipMemsetAsync(c->y.g2, 0, c->n2 * sizeof(cd), c->stream));
     }
     if ((s = guard_clear(c)) != G1G2_OK) return s;
+    if (c->d.basis == G1G2_JELLIUM && (s = jel_state_changed(c)) != G1G2_OK) return s;
     HIP_OK(c, hipStreamSynchronize(c->stream));
     c->t = t;
     return G1G2_OK;
@@ -444,6 +504,7 @@ g1g2_status g1g2_set_state(g1g2_ctx* c, const void* G1, const void* G2, double t
 
 g1g2_status g1g2_set_h0(g1g2_ctx* c, const void* h0) {
     if (!c || !h0) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_JELLIUM) return set_error(c, G1G2_EUNSUPPORTED, "jellium: energies are set at init");
     HostCopy hh;
     g1g2_status s = fetch(c, h0, g1_count(c), hh);
     if (s != G1G2_OK) return s;
@@ -494,6 +555,7 @@ g1g2_status g1g2_set_drive(g1g2_ctx* c, const double* x, int32_t M, const double
 
 g1g2_status g1g2_set_switch(g1g2_ctx* c, double t_on, double tau) {
     if (!c || !std::isfinite(t_on) || !std::isfinite(tau) || tau < 0.0) return G1G2_EINVAL;
+    if (c->d.basis == G1G2_JELLIUM) return set_error(c, G1G2_EUNSUPPORTED, "jellium: no switching ramp");
     HIP_OK(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     c->switch_t_on = t_on;

@@ -95,6 +95,22 @@ struct GeneralData {
     float2* w_ph32 = nullptr;
 };
 
+// Jellium: momenta on a periodic grid; G1 [2][nb] (diagonal), G2 [3][nb]^3 in
+// the momentum-transfer layout (jellium.hip).  sc/sb hold the partial sums of
+// the polarization sums S of a G2 register: sets 0 and 1 alternate over the
+// four stages of a step, set 2 serves single right-hand sides and observables.
+struct JelliumData {
+    int dims[3] = {1, 1, 1};
+    int nb = 0;
+    double* eps = nullptr;   // [2][nb] one-particle energies
+    double* v = nullptr;     // [nb] pair interaction v_q (v_0 = 0)
+    cd* hhf = nullptr;       // [2][nb] h^HF of the current stage input
+    cd* stot = nullptr;      // [2][nb][nb] S^a_{P,Q} of the current stage input
+    cd* sc[3] = {};          // [3][nb][nb] per-block sums over the middle momentum
+    cd* sb[3] = {};          // [nb][nb] down-spin sums of the up-down block
+    int parity = 0;          // buffer set holding the sums of the next stage input
+};
+
 struct g1g2_ctx {
     g1g2_desc d{};
     hipStream_t stream = nullptr;
@@ -111,6 +127,7 @@ struct g1g2_ctx {
     int nscratch = 0;
     HubbardData hub;
     GeneralData gen;
+    JelliumData jel;
     // adiabatic switching of the interaction (U or w) by phi(t), a sin^2 ramp
     // from 0 at switch_t_on to 1 at switch_t_on + switch_tau; switch_tau = 0: off
     double switch_t_on = 0.0, switch_tau = 0.0;
@@ -184,6 +201,16 @@ g1g2_status gen_observables(g1g2_ctx* c, const Regs& s, double t, g1g2_obs* o);
 g1g2_status gen_pad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
 g1g2_status gen_unpad(g1g2_ctx* c, const cd* src_dev, cd* dst_dev, int rank);
 void gen_free(g1g2_ctx* c);
+
+// ---- jellium (jellium.hip)
+int jel_max_nb();
+g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const double* v);
+void jel_free(g1g2_ctx* c);
+// the state register y changed (init, set_state): recompute the sums of its G2
+g1g2_status jel_state_changed(g1g2_ctx* c);
+g1g2_status jel_stage(g1g2_ctx* c, int mode, const Regs& in, const Regs& y, const Regs& acc, const Regs& out,
+                      double cb, double cc);
+g1g2_status jel_observables(g1g2_ctx* c, const Regs& s, g1g2_obs* o);
 
 // ---- adjoint (adjoint.hip)
 void adj_free(g1g2_ctx* c);

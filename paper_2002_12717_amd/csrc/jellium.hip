@@ -1,0 +1,521 @@
+// Jellium (uniform electron gas) G1-G2 kernels in a plane-wave basis (Sec.
+// III.E, Sec. IV.D).
+//
+// Momenta live on a periodic grid (dims Lx, Ly, Lz; index n = x + Lx (y + Ly
+// z); components add modulo the grid), so momentum conservation is exact in
+// the finite basis.  G1 is diagonal: G^{<,s}_p, [2][nb].  G2 is kept in the
+// momentum-transfer form of eq:g2-def-jellium, one [nb]^3 block per spin pair
+// (up-up, up-down, down-down; down-up follows from eq:Gsymm_a):
+//   G2[c][P][Pb][Q] = G2^{a b a b}_{(P-Q, a), (Pb+Q, b), (P, a), (Pb, b)}.
+// Every element of the right-hand side (eq:jellium-g2, eq:jellium-gwpi) is a
+// pointwise function of the element, of G1 at four momenta and, for GW, of the
+// polarization sums S^a_{P,Q} = sum_{s,K} G2^{a s}_{P,K,Q}; the collision
+// integral is I^a_P = -i sum_Q v_Q S^a_{P,Q} (eq:jellium-g1).  A stage is
+// therefore one streaming pass over G2 (no inner sum, no neighbour reads: the
+// O(nb^3) cost of Tab. I) plus a small prologue on nb^2 numbers:
+//   jel_prep  : S of the stage input from the partial sums the previous pass
+//               left, I, the G1 update, h^HF of the stage input;
+//   jel_stage : the G2 right-hand side with its fused Runge-Kutta update, and
+//               the partial sums of S of the values it writes (the next stage
+//               input), so that no separate pass over G2 computes them.
+// The middle sums (over Pb) are exact per work-group; the down-spin sums that
+// the up-down block feeds (a sum over its first momentum) are accumulated with
+// binary64 atomics.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "ctx.h"
+
+namespace {
+
+constexpr int JEL_PB = 4;        // momenta P per work-group (one per inner iteration)
+constexpr int JEL_MAX_NB = 1024; // momenta of the grid (the stage kernel stages h and G1 in LDS)
+constexpr int JEL_QB = 64;       // momenta Q per work-group (one per lane)
+constexpr int JEL_THREADS = 256;
+
+struct JGrid {
+    int lx, ly, lz, nb;
+};
+
+__device__ __forceinline__ int jwrap(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
+
+struct JMom {   // components of one momentum
+    int x, y, z;
+};
+
+__device__ __forceinline__ JMom jdec(const JGrid& g, int n) {
+    JMom m;
+    m.x = n % g.lx;
+    const int r = n / g.lx;
+    m.y = r % g.ly;
+    m.z = r / g.ly;
+    return m;
+}
+__device__ __forceinline__ int jenc(const JGrid& g, int x, int y, int z) { return x + g.lx * (y + g.ly * z); }
+__device__ __forceinline__ int jadd(const JGrid& g, const JMom& a, const JMom& b) {
+    return jenc(g, jwrap(a.x + b.x, g.lx), jwrap(a.y + b.y, g.ly), jwrap(a.z + b.z, g.lz));
+}
+__device__ __forceinline__ JMom jsubm(const JGrid& g, const JMom& a, const JMom& b) {
+    JMom m;
+    m.x = jwrap(a.x - b.x, g.lx);
+    m.y = jwrap(a.y - b.y, g.ly);
+    m.z = jwrap(a.z - b.z, g.lz);
+    return m;
+}
+__device__ __forceinline__ int jidx(const JGrid& g, const JMom& a) { return jenc(g, a.x, a.y, a.z); }
+
+// spins (a, b) of block c: up-up, up-down, down-down
+__host__ __device__ __forceinline__ int spin_a(int c) { return c == 2 ? 1 : 0; }
+__host__ __device__ __forceinline__ int spin_b(int c) { return c == 0 ? 0 : 1; }
+
+struct PrepArgs {
+    JGrid g;
+    const double* eps;        // [2][nb]
+    const double* v;          // [nb]
+    const cd* in1;            // stage-input G1 [2][nb]
+    const cd* y1;
+    cd* acc1;
+    cd* out1;
+    double cb, cc;
+    const cd* sc;             // [3][nb][nb] middle sums of the stage input
+    const cd* sb;             // [nb][nb] down-spin sums from the up-down block
+    cd* sb_next;              // zeroed here: the stage pass accumulates into it
+    cd* stot;                 // [2][nb][nb] S^a_{P,Q} of the stage input (out)
+    cd* hhf;                  // [2][nb] h^HF of the stage input (out)
+    DivGuard guard;
+};
+
+// One work-group per (spin a, momentum P); threads over Q (and over the summed
+// momentum of h^HF).
+template <int MODE>
+__global__ __launch_bounds__(JEL_THREADS) void jel_prep_kernel(PrepArgs s) {
+    __shared__ double red[4][JEL_THREADS];
+    const JGrid g = s.g;
+    const int nb = g.nb;
+    const int a = blockIdx.x / nb, P = blockIdx.x - a * nb;
+    const int tid = threadIdx.x;
+    const JMom mP = jdec(g, P);
+    double ir = 0.0, ii = 0.0, hr = 0.0, hi = 0.0;
+    for (int q = tid; q < nb; q += JEL_THREADS) {
+        const size_t pq = (size_t)P * nb + q;
+        cd S = a == 0 ? cadd(s.sc[pq], s.sc[(size_t)nb * nb + pq]) : cadd(s.sc[2 * (size_t)nb * nb + pq], s.sb[pq]);
+        s.stot[(size_t)a * nb * nb + pq] = S;
+        const double vq = s.v[q];
+        ir += vq * S.x;
+        ii += vq * S.y;
+        // h^HF_P = eps_P + i sum_pb v[P - pb] G^<_pb
+        const cd gl = s.in1[a * nb + q];
+        const double vpq = s.v[jidx(g, jsubm(g, mP, jdec(g, q)))];
+        hr -= vpq * gl.y;
+        hi += vpq * gl.x;
+        if (a == 0 && s.sb_next) s.sb_next[pq] = cmk(0.0, 0.0);
+    }
+    red[0][tid] = ir;
+    red[1][tid] = ii;
+    red[2][tid] = hr;
+    red[3][tid] = hi;
+    __syncthreads();
+    for (int st = JEL_THREADS / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + st];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    const int e = a * nb + P;
+    s.hhf[e] = cmk(s.eps[e] + red[2][0], red[3][0]);
+    // I = -i sum_Q v_Q S_{P,Q};  dG^</dt = -i (I + conj(I)) = -2 i Re(I)
+    const cd I = cmul_mi(cmk(red[0][0], red[1][0]));
+    const cd f = cmk(0.0, -2.0 * I.x);
+    if (MODE == RK_FIRST && e == 0) guard_begin_step(s.guard);
+    rk_update<MODE>(e, f, s.in1[e], s.y1, s.acc1, s.out1, s.cb, s.cc);
+    if (MODE == RK_LAST && guard_bad(s.out1[e], true)) guard_fire(s.guard, 0, s.guard.div[0]);
+}
+
+struct StageArgsJ {
+    JGrid g;
+    const double* v;          // [nb]
+    const cd* g1;             // stage-input G1 [2][nb]
+    const cd* hhf;            // [2][nb]
+    const cd* stot;           // [2][nb][nb] (GW)
+    const void* in2;          // stage input G2 [3][nb]^3 (binary64 or binary32 storage)
+    const cd* y2;
+    cd* acc2;
+    void* out2;
+    double cb, cc;
+    int exch;                 // source with the exchange term (Psi^-)
+    cd* sc_next;              // [3][nb][nb] middle sums of the values written (exact)
+    cd* sb_next;              // [nb][nb] their down-spin sums from the up-down block (atomics)
+};
+
+template <typename TO>
+__device__ __forceinline__ cd stored_value(cd v) {
+    if constexpr (std::is_same<TO, float2>::value) return cmk((double)(float)v.x, (double)(float)v.y);
+    else return v;
+}
+
+__device__ __forceinline__ void atomic_add_c(cd* p, cd v) {
+    atomicAdd(&p->x, v.x);
+    atomicAdd(&p->y, v.y);
+}
+
+// Work-group (block c, JEL_PB momenta P, JEL_QB momenta Q); lane = Q, wave w
+// takes Pb = w, w + 4, ... and, for each, the JEL_PB momenta P.  Loads of a
+// fixed (P, Pb) are JEL_QB consecutive elements.  REDUCE: only the partial sums
+// of the input (no right-hand side); MODE == RK_RHS: the right-hand side into
+// out2, no sums.
+template <int MODE, bool GW, typename TI, typename TO, bool REDUCE>
+__global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
+    // h^HF and G1 of both spins and v, staged in LDS (dynamic: 2 nb + 2 nb complex, nb real)
+    extern __shared__ cd sh_dyn[];
+    cd* sh_h = sh_dyn;
+    cd* sh_g = sh_dyn + 2 * s.g.nb;
+    double* sh_v = reinterpret_cast<double*>(sh_dyn + 4 * s.g.nb);
+    __shared__ cd sh_red[4][JEL_PB][JEL_QB];
+    const JGrid g = s.g;
+    const int nb = g.nb;
+    const int npb = (nb + JEL_PB - 1) / JEL_PB, nqb = (nb + JEL_QB - 1) / JEL_QB;
+    int b = blockIdx.x;
+    const int c = b / (npb * nqb);
+    b -= c * npb * nqb;
+    const int pblk = b / nqb, qblk = b - pblk * nqb;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (!REDUCE) {
+        for (int q = tid; q < 2 * nb; q += JEL_THREADS) {
+            sh_h[q] = s.hhf[q];
+            sh_g[q] = s.g1[q];
+        }
+        for (int q = tid; q < nb; q += JEL_THREADS) sh_v[q] = s.v[q];
+        __syncthreads();
+    }
+    const int sa = spin_a(c), sb = spin_b(c);
+    const int Q = qblk * JEL_QB + lane;
+    const bool qok = Q < nb;
+    const int Qc = qok ? Q : 0;
+    const JMom mQ = jdec(g, Qc);
+    const int negQ = jidx(g, jsubm(g, JMom{0, 0, 0}, mQ));
+    const cd* hA = sh_h + sa * nb;
+    const cd* hB = sh_h + sb * nb;
+    const cd* gA = sh_g + sa * nb;
+    const cd* gB = sh_g + sb * nb;
+    // per owned P: index of P - Q, its components, and the P-dependent factors
+    int Pv[JEL_PB], Pm[JEL_PB];
+    JMom mPm[JEL_PB];
+    cd ePm[JEL_PB], gPm[JEL_PB], gP[JEL_PB], SaP[JEL_PB];
+    cd sa_acc[JEL_PB];
+#pragma unroll
+    for (int j = 0; j < JEL_PB; ++j) {
+        const int P = pblk * JEL_PB + j;
+        Pv[j] = P < nb ? P : -1;
+        const int Pc = P < nb ? P : 0;
+        mPm[j] = jsubm(g, jdec(g, Pc), mQ);
+        Pm[j] = jidx(g, mPm[j]);
+        sa_acc[j] = cmk(0.0, 0.0);
+        if (!REDUCE) {
+            ePm[j] = csub(hA[Pm[j]], hA[Pc]);          // h^a_{P-Q} - h^a_P
+            gPm[j] = gA[Pm[j]];
+            gP[j] = gA[Pc];
+            SaP[j] = GW && qok ? s.stot[((size_t)sa * nb + Pc) * nb + Qc] : cmk(0.0, 0.0);
+        }
+    }
+    const double vQ = REDUCE ? 0.0 : sh_v[Qc];
+    const size_t n3 = (size_t)nb * nb * nb;
+    const TI* in = static_cast<const TI*>(s.in2) + c * n3;
+    const cd* y = s.y2 + c * n3;
+    cd* acc = s.acc2 + c * n3;
+    TO* out = static_cast<TO*>(s.out2) + c * n3;
+    for (int Pb = wave; Pb < nb; Pb += 4) {
+        const JMom mPb = jdec(g, __builtin_amdgcn_readfirstlane(Pb));
+        const int Pbp = jidx(g, JMom{jwrap(mPb.x + mQ.x, g.lx), jwrap(mPb.y + mQ.y, g.ly), jwrap(mPb.z + mQ.z, g.lz)});
+        cd hb = cmk(0.0, 0.0), gl2 = cmk(0.0, 0.0), gl4 = cmk(0.0, 0.0), SbP = cmk(0.0, 0.0);
+        if (!REDUCE) {
+            hb = csub(hB[Pbp], hB[Pb]);                   // h^b_{Pb+Q} - h^b_Pb
+            gl2 = gB[Pbp];
+            gl4 = gB[Pb];
+            if (GW && qok) SbP = s.stot[((size_t)sb * nb + Pbp) * nb + Qc];
+        }
+        cd sb_sum = cmk(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < JEL_PB; ++j) {
+            if (!qok || Pv[j] < 0) continue;
+            const size_t e = ((size_t)Pv[j] * nb + Pb) * nb + Q;
+            const cd av = ld_c(in, (long long)e);
+            cd o;
+            if (REDUCE) {
+                o = av;
+            } else {
+                // commutator: G2 (h^a_{P-Q} + h^b_{Pb+Q} - h^a_P - h^b_Pb)
+                cd r = cmul(av, cadd(ePm[j], hb));
+                // source (eq:jellium-g2): -w Phi, w = v_Q - delta_ab v_{P-Q-Pb}
+                const cd gl1 = gPm[j], gl3 = gP[j];
+                const cd gg1 = cmk(gl1.x, gl1.y - 1.0), gg2 = cmk(gl2.x, gl2.y - 1.0);
+                const cd gg3 = cmk(gl3.x, gl3.y - 1.0), gg4 = cmk(gl4.x, gl4.y - 1.0);
+                const cd phi = csub(cmul(cmul(gg1, gg2), cmul(gl3, gl4)), cmul(cmul(gl1, gl2), cmul(gg3, gg4)));
+                double w = vQ;
+                if (s.exch && sa == sb) w -= sh_v[jidx(g, jsubm(g, mPm[j], mPb))];
+                r = csub(r, cscale(phi, w));
+                if (GW) {   // Pi - conj(Pi^{ba}_{Pb+Q, P-Q, Q}) (eq:jellium-gwpi)
+                    const cd fb = csub(cmul(gg2, gl4), cmul(gl2, gg4));
+                    const cd fa = csub(cmul(gg3, gl1), cmul(gl3, gg1));
+                    const cd pi = cscale(cmul(fb, SaP[j]), vQ);
+                    const cd pt = cscale(cmul(fa, SbP), vQ);
+                    r = cadd(r, csub(pi, cconj(pt)));
+                }
+                const cd f = cmul_mi(r);
+                if (MODE == RK_RHS) {
+                    o = f;
+                    st_c(out, (long long)e, f);
+                } else if (MODE == RK_FIRST) {
+                    acc[e] = cmk(fma(s.cb, f.x, av.x), fma(s.cb, f.y, av.y));
+                    o = cmk(fma(s.cc, f.x, av.x), fma(s.cc, f.y, av.y));
+                    st_c(out, (long long)e, o);
+                } else if (MODE == RK_MID) {
+                    const cd ac = acc[e], yv = y[e];
+                    acc[e] = cmk(fma(s.cb, f.x, ac.x), fma(s.cb, f.y, ac.y));
+                    o = cmk(fma(s.cc, f.x, yv.x), fma(s.cc, f.y, yv.y));
+                    st_c(out, (long long)e, o);
+                } else {
+                    const cd ac = acc[e];
+                    o = cmk(fma(s.cb, f.x, ac.x), fma(s.cb, f.y, ac.y));
+                    st_c(out, (long long)e, o);
+                }
+                o = stored_value<TO>(o);                    // as stored (rounded when binary32)
+            }
+            if (MODE != RK_RHS) {
+                sa_acc[j] = cadd(sa_acc[j], o);
+                sb_sum = cadd(sb_sum, o);
+            }
+        }
+        if (MODE != RK_RHS && c == 1 && qok) atomic_add_c(s.sb_next + (size_t)Pb * nb + negQ, sb_sum);
+    }
+    if (MODE == RK_RHS) return;
+#pragma unroll
+    for (int j = 0; j < JEL_PB; ++j) sh_red[wave][j][lane] = sa_acc[j];
+    __syncthreads();
+    if (wave == 0 && qok) {
+#pragma unroll
+        for (int j = 0; j < JEL_PB; ++j) {
+            if (Pv[j] < 0) continue;
+            const cd t = cadd(cadd(sh_red[0][j][lane], sh_red[1][j][lane]), cadd(sh_red[2][j][lane], sh_red[3][j][lane]));
+            s.sc_next[((size_t)c * nb + Pv[j]) * nb + Q] = t;
+        }
+    }
+}
+
+// Observables from G1 and S of the state (one work-group): N^s, E_kin = sum eps n,
+// the Fock energy -1/2 sum_s sum v[p - pb] n^s_p n^s_pb and E_corr = -1/2 Re sum v_Q S.
+__global__ __launch_bounds__(JEL_THREADS) void jel_obs_kernel(JGrid g, const double* __restrict__ eps,
+                                                           const double* __restrict__ v,
+                                                           const cd* __restrict__ g1,
+                                                           const cd* __restrict__ sc,
+                                                           const cd* __restrict__ sb,
+                                                           double* __restrict__ res) {
+    __shared__ double red[5][JEL_THREADS];
+    const int nb = g.nb, tid = threadIdx.x;
+    double nu = 0, nd = 0, ek = 0, ef = 0, ec = 0;
+    for (int e = tid; e < 2 * nb; e += JEL_THREADS) {
+        const int s = e / nb, p = e - s * nb;
+        const double n = g1[e].y;
+        if (s == 0) nu += n;
+        else nd += n;
+        ek += eps[e] * n;
+        const JMom mp = jdec(g, p);
+        for (int q = 0; q < nb; ++q) ef -= 0.5 * v[jidx(g, jsubm(g, mp, jdec(g, q)))] * n * g1[s * nb + q].y;
+    }
+    const size_t nn = (size_t)nb * nb;
+    for (size_t e = tid; e < nn; e += JEL_THREADS) {
+        const double vq = v[e % nb];
+        const cd su = cadd(sc[e], sc[nn + e]), sd = cadd(sc[2 * nn + e], sb[e]);
+        ec -= 0.5 * vq * (su.x + sd.x);
+    }
+    red[0][tid] = nu;
+    red[1][tid] = nd;
+    red[2][tid] = ek;
+    red[3][tid] = ef;
+    red[4][tid] = ec;
+    __syncthreads();
+    for (int st = JEL_THREADS / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int k = 0; k < 5; ++k) red[k][tid] += red[k][tid + st];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int k = 0; k < 5; ++k) res[k] = red[k][0];
+}
+
+__global__ void jel_zero_kernel(cd* p, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        p[e] = cmk(0.0, 0.0);
+}
+
+JGrid grid_of(const g1g2_ctx* c) {
+    const JelliumData& J = c->jel;
+    return JGrid{J.dims[0], J.dims[1], J.dims[2], J.nb};
+}
+
+int stage_blocks(const g1g2_ctx* c) {
+    const int nb = c->jel.nb;
+    return 3 * ((nb + JEL_PB - 1) / JEL_PB) * ((nb + JEL_QB - 1) / JEL_QB);
+}
+
+size_t stage_lds(const g1g2_ctx* c) { return (size_t)c->jel.nb * (4 * sizeof(cd) + sizeof(double)); }
+
+// Partial sums of S of a G2 register (binary64) into buffer set `buf`.
+g1g2_status jel_reduce(g1g2_ctx* c, const cd* g2, int buf) {
+    JelliumData& J = c->jel;
+    const size_t nn = (size_t)J.nb * J.nb;
+    hipLaunchKernelGGL(jel_zero_kernel, dim3(256), dim3(256), 0, c->stream, J.sb[buf], nn);
+    StageArgsJ s{};
+    s.g = grid_of(c);
+    s.in2 = g2;
+    s.sc_next = J.sc[buf];
+    s.sb_next = J.sb[buf];
+    hipLaunchKernelGGL((jel_stage_kernel<RK_FIRST, false, cd, cd, true>), dim3(stage_blocks(c)), dim3(JEL_THREADS),
+                       stage_lds(c), c->stream, s);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "jel_reduce");
+    return G1G2_OK;
+}
+
+template <int MODE, bool GW, bool MIXED>
+void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
+    using TI = typename std::conditional<MIXED && (MODE == RK_MID || MODE == RK_LAST), float2, cd>::type;
+    using TO = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
+    hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false>), dim3(stage_blocks(c)), dim3(JEL_THREADS),
+                       stage_lds(c), c->stream, s);
+}
+
+template <int MODE>
+g1g2_status jel_stage_t(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& acc, const Regs& out, double cb,
+                        double cc, int rbuf, int wbuf) {
+    JelliumData& J = c->jel;
+    PrepArgs p{};
+    p.g = grid_of(c);
+    p.eps = J.eps;
+    p.v = J.v;
+    p.in1 = in.g1;
+    p.y1 = y.g1;
+    p.acc1 = acc.g1;
+    p.out1 = out.g1;
+    p.cb = cb;
+    p.cc = cc;
+    p.sc = J.sc[rbuf];
+    p.sb = J.sb[rbuf];
+    p.sb_next = MODE == RK_RHS ? nullptr : J.sb[wbuf];   // a plain right-hand side accumulates nothing
+    p.stot = J.stot;
+    p.hhf = J.hhf;
+    p.guard = guard_of(c);
+    hipLaunchKernelGGL(jel_prep_kernel<MODE>, dim3(2 * J.nb), dim3(JEL_THREADS), 0, c->stream, p);
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "jel_prep");
+    StageArgsJ s{};
+    s.g = p.g;
+    s.v = J.v;
+    s.g1 = in.g1;
+    s.hhf = J.hhf;
+    s.stot = J.stot;
+    s.in2 = in.g2;
+    s.y2 = y.g2;
+    s.acc2 = acc.g2;
+    s.out2 = out.g2;
+    s.cb = cb;
+    s.cc = cc;
+    s.exch = c->d.selfenergy != G1G2_GW || (c->d.flags & G1G2_GW_EXCHANGE) ? 1 : 0;
+    s.sc_next = J.sc[wbuf];
+    s.sb_next = J.sb[wbuf];
+    const bool gw = c->d.selfenergy == G1G2_GW;
+    const bool mixed = MODE != RK_RHS && c->d.precision == G1G2_MIXED;
+    if (gw) {
+        if (mixed) launch_stage<MODE, true, true>(c, s);
+        else launch_stage<MODE, true, false>(c, s);
+    } else {
+        if (mixed) launch_stage<MODE, false, true>(c, s);
+        else launch_stage<MODE, false, false>(c, s);
+    }
+    HIP_OK(c, hipGetLastError());
+    prof_mark(c, "jel_stage");
+    return G1G2_OK;
+}
+
+}  // namespace
+
+int jel_max_nb() { return JEL_MAX_NB; }
+
+g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const double* v) {
+    JelliumData& J = c->jel;
+    J.dims[0] = dims[0];
+    J.dims[1] = dims[1];
+    J.dims[2] = dims[2];
+    J.nb = dims[0] * dims[1] * dims[2];
+    const size_t nb = J.nb, nn = nb * nb;
+    HIP_OK(c, hipMalloc(&J.eps, 2 * nb * sizeof(double)));
+    HIP_OK(c, hipMalloc(&J.v, nb * sizeof(double)));
+    HIP_OK(c, hipMalloc(&J.hhf, 2 * nb * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&J.stot, 2 * nn * sizeof(cd)));
+    for (int b = 0; b < 3; ++b) {
+        HIP_OK(c, hipMalloc(&J.sc[b], 3 * nn * sizeof(cd)));
+        HIP_OK(c, hipMalloc(&J.sb[b], nn * sizeof(cd)));
+    }
+    HIP_OK(c, hipMemcpyAsync(J.eps, eps, 2 * nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipMemcpyAsync(J.v, v, nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    return G1G2_OK;
+}
+
+void jel_free(g1g2_ctx* c) {
+    JelliumData& J = c->jel;
+    for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot})
+        if (p) (void)hipFree(p);
+    for (int b = 0; b < 3; ++b) {
+        if (J.sc[b]) (void)hipFree(J.sc[b]);
+        if (J.sb[b]) (void)hipFree(J.sb[b]);
+    }
+    J = JelliumData{};
+}
+
+g1g2_status jel_state_changed(g1g2_ctx* c) {
+    c->jel.parity = 0;
+    return jel_reduce(c, c->y.g2, 0);
+}
+
+g1g2_status jel_stage(g1g2_ctx* c, int mode, const Regs& in, const Regs& y, const Regs& acc, const Regs& out,
+                      double cb, double cc) {
+    JelliumData& J = c->jel;
+    if (mode == RK_RHS) {   // a plain right-hand side of a caller state: its sums in buffer set 2
+        g1g2_status s = jel_reduce(c, in.g2, 2);
+        if (s != G1G2_OK) return s;
+        return jel_stage_t<RK_RHS>(c, in, y, acc, out, cb, cc, 2, 2);
+    }
+    // the propagated registers alternate between buffer sets 0 and 1: a step
+    // starts with the sums of y in set 0 and its last stage leaves those of the
+    // new y there again (four stages per step)
+    const int rbuf = J.parity, wbuf = J.parity ^ 1;
+    J.parity ^= 1;
+    switch (mode) {
+        case RK_FIRST: return jel_stage_t<RK_FIRST>(c, in, y, acc, out, cb, cc, rbuf, wbuf);
+        case RK_MID: return jel_stage_t<RK_MID>(c, in, y, acc, out, cb, cc, rbuf, wbuf);
+        default: return jel_stage_t<RK_LAST>(c, in, y, acc, out, cb, cc, rbuf, wbuf);
+    }
+}
+
+g1g2_status jel_observables(g1g2_ctx* c, const Regs& s, g1g2_obs* o) {
+    JelliumData& J = c->jel;
+    g1g2_status st = jel_reduce(c, s.g2, 2);
+    if (st != G1G2_OK) return st;
+    hipLaunchKernelGGL(jel_obs_kernel, dim3(1), dim3(JEL_THREADS), 0, c->stream, grid_of(c), J.eps, J.v, s.g1,
+                       J.sc[2], J.sb[2], c->dscratch);
+    HIP_OK(c, hipGetLastError());
+    double h[5];
+    HIP_OK(c, hipMemcpyAsync(h, c->dscratch, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    o->N[0] = h[0];
+    o->N[1] = h[1];
+    o->E_kin = h[2];
+    o->E_mf = h[3];
+    o->E_corr = h[4];
+    o->E_tot = h[2] + h[3] + h[4];
+    return G1G2_OK;
+}

@@ -121,3 +121,30 @@ def test_tuning_table_drives_batch_init(monkeypatch):
     autotune.make_batch(B, cl, B.TPP, table=table)
     assert seen["flags"] == B.HUB_ROW_KERNEL
     assert list(seen["chunk"]) == [256 if c.ns <= 16 else (512 if c.ns <= 25 else 4096) for c in cl]
+
+
+def test_jellium_init_rejects_bad_arguments_without_device(so_path):
+    """Jellium argument checks precede any device call: the grid must match
+    nb, v[0] must vanish, and the T-matrix closures are not offered."""
+    import numpy as np
+    from paper_2002_12717_amd import binding
+    lib = binding.load(so_path)
+    ctx = ctypes.c_void_p()
+    dims = np.array([2, 2, 1], np.int32)
+    eps = np.zeros(8)
+    v = np.full(4, 0.1)
+    g1 = np.zeros(8, np.complex128)
+    P = lambda a: a.ctypes.data  # noqa: E731
+    d = binding.Desc(binding.JELLIUM, binding.SOA, 0, 0, 5, 0.0)          # nb != 2 * 2 * 1
+    v0 = v.copy()
+    v0[0] = 0.0
+    assert lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(d), P(dims), P(eps), P(v0), P(g1), None,
+                                 None) == binding.EINVAL
+    d = binding.Desc(binding.JELLIUM, binding.SOA, 0, 0, 4, 0.0)
+    assert lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(d), P(dims), P(eps), P(v), P(g1), None,
+                                 None) == binding.EINVAL                # v[0] != 0
+    d = binding.Desc(binding.JELLIUM, binding.TPP, 0, 0, 4, 0.0)
+    assert lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(d), P(dims), P(eps), P(v0), P(g1), None,
+                                 None) == binding.EUNSUPPORTED
+    d = binding.Desc(binding.JELLIUM, binding.SOA, 0, 0, 4, 0.0)         # g1g2_init is not the entry
+    assert lib.g1g2_init(ctypes.byref(ctx), ctypes.byref(d), P(eps), P(v0), P(g1), None, None) == binding.EINVAL
