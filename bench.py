@@ -468,6 +468,96 @@ def run_hubbard(args, torch, B, kind):
     return out
 
 
+def run_jellium(args, torch, B):
+    """Jellium after an interaction quench (6 x 6 x 6 momenta, spin-polarized
+    Fermi-Dirac start, Coulomb v): steps/s of both precisions, the HBM roofline
+    of the streaming stage kernel, and the mixed-precision error against
+    binary64 over the whole propagation."""
+    import numpy as np
+    from workloads import jellium_system
+    se = args.selfenergy or "gw"
+    if se not in ("soa", "gw"):
+        raise SystemExit("jellium takes --selfenergy soa or gw")
+    s = jellium_system()
+    nb = s.nb
+    code = B.GW if se == "gw" else B.SOA
+    stream = torch.cuda.Stream()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        p = B.Jellium(code, s.dims, s.eps, s.v, s.g1, stream=stream.cuda_stream,
+                      precision=B.FP64 if prec == "fp64" else B.MIXED)
+        ms, _ = timed_steps(p, s.dt, args.steps, args.warmup, stream, torch)
+        prof = p.profile(s.dt, args.profile_steps)
+        p.close()
+        # the whole propagation from t = 0, G1 and E every 50 steps
+        q = B.Jellium(code, s.dims, s.eps, s.v, s.g1, stream=stream.cuda_stream,
+                      precision=B.FP64 if prec == "fp64" else B.MIXED)
+        traj = {0: (q.get_state(with_g2=False)[0], q.observables()["E_tot"])}
+        for n in range(50, s.nsteps + 1, 50):
+            q.step(s.dt, 50)
+            traj[n] = (q.get_state(with_g2=False)[0], q.observables()["E_tot"])
+        q.close()
+        res[prec] = dict(ms=ms, prof=prof, traj=traj)
+    f64, mx = res["fp64"], res["mixed"]
+    ms_step = f64["ms"] / args.steps
+    mx_step = mx["ms"] / args.steps
+    n2 = 3.0 * nb ** 3
+    tot, cnt = f64["prof"]["jel_stage"]
+    bytes_launch = 64.0 * n2          # 48, 80, 80, 48 B per element over the four stages
+    ach = bytes_launch * cnt / (tot * 1e-3) / 1e9
+    mtot, mcnt = mx["prof"]["jel_stage"]
+    mbytes = 52.0 * n2                # binary32 stage copies: 40, 64, 64, 40 B
+    mach = mbytes * mcnt / (mtot * 1e-3) / 1e9
+    err = trajectory_error(mx["traj"], f64["traj"])
+    e0 = f64["traj"][0][1]
+    drift = max(abs(v[1] - e0) for v in f64["traj"].values()) / max(abs(e0), 1.0)
+    m = s.meta
+    config = {"workload": f"jellium {se.upper()} G1-G2, {s.dims[0]}x{s.dims[1]}x{s.dims[2]} plane waves "
+                          f"(periodic momentum grid), Coulomb v with coupling {m['coupling']}, box {m['lbox']:.4f}, "
+                          f"Fermi-Dirac start T={m['temperature']}, mu={m['mu']}, dt={s.dt}, RK4, {s.nsteps} steps",
+              "nb": nb, "g2_elements": int(n2), "selfenergy": se.upper(), "parallelism": "single GPU"}
+    out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
+    out.update({
+        "roofline": {"kernel": "jel_stage", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM,
+                     "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4), "traffic": None,
+                     "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt},
+        "kernels": kernel_table(f64["prof"]),
+        "energy_drift_rel": drift,
+        "mixed": {"dtype": "f32 G2 stage copies / f64 state and arithmetic", "value": round(1e3 / mx_step, 3),
+                  "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
+                  "err_G1_vs_fp64": err["G1"], "err_E_vs_fp64": err["E"],
+                  "roofline": {"kernel": "jel_stage", "achieved": round(mach, 2), "peak": PEAK_HBM,
+                               "unit": "GB/s", "frac": round(mach / PEAK_HBM, 4), "bytes_per_launch": mbytes},
+                  "kernels": kernel_table(mx["prof"])},
+    })
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_jellium(s, se)
+    return out
+
+
+def cpu_baseline_jellium(system, se, seconds: float = 12.0):
+    """The oracle's jellium right-hand side on the host cores at the workload's
+    initial state, over a bounded number of evaluations; four per RK4 step."""
+    import torch
+    from oracle import jellium as OJ
+    nthreads = torch.get_num_threads()
+    g1 = torch.as_tensor(system.g1, dtype=torch.complex128)
+    nb = system.nb
+    g2 = torch.zeros((2, 2, nb, nb, nb), dtype=torch.complex128)
+    OJ.rhs(system.eps, system.v, g1, g2, system.dims, se)   # warm-up
+    n, t0 = 0, time.perf_counter()
+    while True:
+        OJ.rhs(system.eps, system.v, g1, g2, system.dims, se)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > seconds or n >= 20:
+            break
+    per = el / n
+    return {"value": round(1.0 / (4.0 * per), 5), "unit": "RK4 steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} right-hand sides of the jellium workload (torch CPU complex128, {nthreads} threads, "
+                      f"{el:.1f} s, {per:.2f} s each), four per RK4 step", "host": host_info()}
+
+
 def cpu_baseline_batch(clusters, seconds: float = 15.0, selfenergy: str = "tpp"):
     """Oracle on the host: one RK4 step per cluster for the first clusters of the
     batch until the time budget is spent; the whole-batch rate is extrapolated
@@ -744,7 +834,7 @@ def main():
                     help="general_gw: skip the Nb = 32 SOA line reported beside the headline")
     ap.add_argument("--workload", default="general_gw",
                     choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
-                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "scaling"])
+                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "jellium", "scaling"])
     ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
                          "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
@@ -785,6 +875,8 @@ def main():
         out = run_scaling(args, torch, B)
     elif args.workload == "hubbard_adjoint":
         out = run_adjoint(args, torch, B)
+    elif args.workload == "jellium":
+        out = run_jellium(args, torch, B)
     else:
         out = run_hubbard(args, torch, B, args.workload)
     print(json.dumps(out), flush=True)

@@ -106,6 +106,7 @@ struct JelliumData {
     double* v = nullptr;     // [nb] pair interaction v_q (v_0 = 0)
     cd* hhf = nullptr;       // [2][nb] h^HF of the current stage input
     cd* stot = nullptr;      // [2][nb][nb] S^a_{P,Q} of the current stage input
+    cd* skew = nullptr;      // [2][nb][nb] the same at [a][Pb][Q] = S^a_{Pb+Q,Q}
     cd* sc[3] = {};          // [3][nb][nb] per-block sums over the middle momentum
     cd* sb[3] = {};          // [nb][nb] down-spin sums of the up-down block
     int parity = 0;          // buffer set holding the sums of the next stage input

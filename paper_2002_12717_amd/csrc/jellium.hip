@@ -35,7 +35,8 @@ namespace {
 constexpr int JEL_PB = 4;        // momenta P per work-group (one per inner iteration)
 constexpr int JEL_MAX_NB = 1024; // momenta of the grid (the stage kernel stages h and G1 in LDS)
 constexpr int JEL_QB = 64;       // momenta Q per work-group (one per lane)
-constexpr int JEL_THREADS = 256;
+constexpr int JEL_THREADS = 256; // prologue and observables
+constexpr int JEL_WAVES = 8;     // stage pass: wave w takes Pb = w, w + JEL_WAVES, ...
 
 struct JGrid {
     int lx, ly, lz, nb;
@@ -85,6 +86,7 @@ struct PrepArgs {
     const cd* sb;             // [nb][nb] down-spin sums from the up-down block
     cd* sb_next;              // zeroed here: the stage pass accumulates into it
     cd* stot;                 // [2][nb][nb] S^a_{P,Q} of the stage input (out)
+    cd* skew;                 // [2][nb][nb] skew[a][Pb][Q] = S^a_{Pb+Q,Q} (out; GW partner, coalesced)
     cd* hhf;                  // [2][nb] h^HF of the stage input (out)
     DivGuard guard;
 };
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(JEL_THREADS) void jel_prep_kernel(PrepArgs s) {
         const size_t pq = (size_t)P * nb + q;
         cd S = a == 0 ? cadd(s.sc[pq], s.sc[(size_t)nb * nb + pq]) : cadd(s.sc[2 * (size_t)nb * nb + pq], s.sb[pq]);
         s.stot[(size_t)a * nb * nb + pq] = S;
+        s.skew[((size_t)a * nb + jidx(g, jsubm(g, mP, jdec(g, q)))) * nb + q] = S;
         const double vq = s.v[q];
         ir += vq * S.x;
         ii += vq * S.y;
@@ -141,6 +144,7 @@ struct StageArgsJ {
     const cd* g1;             // stage-input G1 [2][nb]
     const cd* hhf;            // [2][nb]
     const cd* stot;           // [2][nb][nb] (GW)
+    const cd* skew;           // [2][nb][nb] S^a_{Pb+Q,Q} at [a][Pb][Q] (GW)
     const void* in2;          // stage input G2 [3][nb]^3 (binary64 or binary32 storage)
     const cd* y2;
     cd* acc2;
@@ -163,18 +167,21 @@ __device__ __forceinline__ void atomic_add_c(cd* p, cd v) {
 }
 
 // Work-group (block c, JEL_PB momenta P, JEL_QB momenta Q); lane = Q, wave w
-// takes Pb = w, w + 4, ... and, for each, the JEL_PB momenta P.  Loads of a
+// takes Pb = w, w + JEL_WAVES, ... and, for each, the JEL_PB momenta P.  The
+// P-dependent factors stay in registers (about 250 VGPRs, two waves per SIMD):
+// measured, reading them from LDS per element instead (four waves per SIMD)
+// was slower for GW (0.61 against 0.47 ms per launch on 6x6x6).  Loads of a
 // fixed (P, Pb) are JEL_QB consecutive elements.  REDUCE: only the partial sums
 // of the input (no right-hand side); MODE == RK_RHS: the right-hand side into
 // out2, no sums.
 template <int MODE, bool GW, typename TI, typename TO, bool REDUCE>
-__global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
+__global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s) {
     // h^HF and G1 of both spins and v, staged in LDS (dynamic: 2 nb + 2 nb complex, nb real)
     extern __shared__ cd sh_dyn[];
     cd* sh_h = sh_dyn;
     cd* sh_g = sh_dyn + 2 * s.g.nb;
     double* sh_v = reinterpret_cast<double*>(sh_dyn + 4 * s.g.nb);
-    __shared__ cd sh_red[4][JEL_PB][JEL_QB];
+    __shared__ cd sh_red[JEL_WAVES][JEL_PB][JEL_QB];
     const JGrid g = s.g;
     const int nb = g.nb;
     const int npb = (nb + JEL_PB - 1) / JEL_PB, nqb = (nb + JEL_QB - 1) / JEL_QB;
@@ -184,11 +191,11 @@ __global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
     const int pblk = b / nqb, qblk = b - pblk * nqb;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (!REDUCE) {
-        for (int q = tid; q < 2 * nb; q += JEL_THREADS) {
+        for (int q = tid; q < 2 * nb; q += 64 * JEL_WAVES) {
             sh_h[q] = s.hhf[q];
             sh_g[q] = s.g1[q];
         }
-        for (int q = tid; q < nb; q += JEL_THREADS) sh_v[q] = s.v[q];
+        for (int q = tid; q < nb; q += 64 * JEL_WAVES) sh_v[q] = s.v[q];
         __syncthreads();
     }
     const int sa = spin_a(c), sb = spin_b(c);
@@ -227,7 +234,7 @@ __global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
     const cd* y = s.y2 + c * n3;
     cd* acc = s.acc2 + c * n3;
     TO* out = static_cast<TO*>(s.out2) + c * n3;
-    for (int Pb = wave; Pb < nb; Pb += 4) {
+    for (int Pb = wave; Pb < nb; Pb += JEL_WAVES) {
         const JMom mPb = jdec(g, __builtin_amdgcn_readfirstlane(Pb));
         const int Pbp = jidx(g, JMom{jwrap(mPb.x + mQ.x, g.lx), jwrap(mPb.y + mQ.y, g.ly), jwrap(mPb.z + mQ.z, g.lz)});
         cd hb = cmk(0.0, 0.0), gl2 = cmk(0.0, 0.0), gl4 = cmk(0.0, 0.0), SbP = cmk(0.0, 0.0);
@@ -235,7 +242,7 @@ __global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
             hb = csub(hB[Pbp], hB[Pb]);                   // h^b_{Pb+Q} - h^b_Pb
             gl2 = gB[Pbp];
             gl4 = gB[Pb];
-            if (GW && qok) SbP = s.stot[((size_t)sb * nb + Pbp) * nb + Qc];
+            if (GW && qok) SbP = s.skew[((size_t)sb * nb + Pb) * nb + Qc];
         }
         cd sb_sum = cmk(0.0, 0.0);
 #pragma unroll
@@ -299,7 +306,8 @@ __global__ __launch_bounds__(JEL_THREADS) void jel_stage_kernel(StageArgsJ s) {
 #pragma unroll
         for (int j = 0; j < JEL_PB; ++j) {
             if (Pv[j] < 0) continue;
-            const cd t = cadd(cadd(sh_red[0][j][lane], sh_red[1][j][lane]), cadd(sh_red[2][j][lane], sh_red[3][j][lane]));
+            cd t = sh_red[0][j][lane];
+            for (int w = 1; w < JEL_WAVES; ++w) t = cadd(t, sh_red[w][j][lane]);
             s.sc_next[((size_t)c * nb + Pv[j]) * nb + Q] = t;
         }
     }
@@ -373,8 +381,8 @@ g1g2_status jel_reduce(g1g2_ctx* c, const cd* g2, int buf) {
     s.in2 = g2;
     s.sc_next = J.sc[buf];
     s.sb_next = J.sb[buf];
-    hipLaunchKernelGGL((jel_stage_kernel<RK_FIRST, false, cd, cd, true>), dim3(stage_blocks(c)), dim3(JEL_THREADS),
-                       stage_lds(c), c->stream, s);
+    hipLaunchKernelGGL((jel_stage_kernel<RK_FIRST, false, cd, cd, true>), dim3(stage_blocks(c)),
+                       dim3(64 * JEL_WAVES), stage_lds(c), c->stream, s);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "jel_reduce");
     return G1G2_OK;
@@ -384,7 +392,7 @@ template <int MODE, bool GW, bool MIXED>
 void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
     using TI = typename std::conditional<MIXED && (MODE == RK_MID || MODE == RK_LAST), float2, cd>::type;
     using TO = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
-    hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false>), dim3(stage_blocks(c)), dim3(JEL_THREADS),
+    hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false>), dim3(stage_blocks(c)), dim3(64 * JEL_WAVES),
                        stage_lds(c), c->stream, s);
 }
 
@@ -406,6 +414,7 @@ g1g2_status jel_stage_t(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     p.sb = J.sb[rbuf];
     p.sb_next = MODE == RK_RHS ? nullptr : J.sb[wbuf];   // a plain right-hand side accumulates nothing
     p.stot = J.stot;
+    p.skew = J.skew;
     p.hhf = J.hhf;
     p.guard = guard_of(c);
     hipLaunchKernelGGL(jel_prep_kernel<MODE>, dim3(2 * J.nb), dim3(JEL_THREADS), 0, c->stream, p);
@@ -417,6 +426,7 @@ g1g2_status jel_stage_t(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     s.g1 = in.g1;
     s.hhf = J.hhf;
     s.stot = J.stot;
+    s.skew = J.skew;
     s.in2 = in.g2;
     s.y2 = y.g2;
     s.acc2 = acc.g2;
@@ -455,6 +465,7 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
     HIP_OK(c, hipMalloc(&J.v, nb * sizeof(double)));
     HIP_OK(c, hipMalloc(&J.hhf, 2 * nb * sizeof(cd)));
     HIP_OK(c, hipMalloc(&J.stot, 2 * nn * sizeof(cd)));
+    HIP_OK(c, hipMalloc(&J.skew, 2 * nn * sizeof(cd)));
     for (int b = 0; b < 3; ++b) {
         HIP_OK(c, hipMalloc(&J.sc[b], 3 * nn * sizeof(cd)));
         HIP_OK(c, hipMalloc(&J.sb[b], nn * sizeof(cd)));
@@ -467,7 +478,7 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
 
 void jel_free(g1g2_ctx* c) {
     JelliumData& J = c->jel;
-    for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot})
+    for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot, (void*)J.skew})
         if (p) (void)hipFree(p);
     for (int b = 0; b < 3; ++b) {
         if (J.sc[b]) (void)hipFree(J.sc[b]);
