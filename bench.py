@@ -582,6 +582,31 @@ def cpu_baseline_batch(clusters, seconds: float = 15.0, selfenergy: str = "tpp")
                       f"extrapolated to the whole batch by G2 element count"}
 
 
+def run_copy_calibration(args, torch):
+    """A plain device copy of 1 GiB (torch's copy kernel), four times: the
+    achievable copy bandwidth of the part, and the program that calibrates the
+    HBM traffic counters (its FETCH_SIZE / WRITE_SIZE per dispatch correspond to
+    1 GiB read and 1 GiB written)."""
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 4
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    gbs = 2.0 * (1 << 30) / (ms * 1e-3) / 1e9
+    return {"metric": "device copy bandwidth (read + write)", "value": round(gbs, 1), "unit": "GB/s",
+            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "copy of a 1 GiB device buffer, 4 repetitions"},
+            "ms_per_copy": round(ms, 4), "frac_of_peak": round(gbs / PEAK_HBM, 4)}
+
+
 def run_scaling(args, torch, B):
     """Cost of an RK4 step against the basis size, fitted as a power law, next
     to the paper's scalings (Sec. VII, Tab. I): general basis SOA ~ Nb^5, GW
@@ -834,7 +859,8 @@ def main():
                     help="general_gw: skip the Nb = 32 SOA line reported beside the headline")
     ap.add_argument("--workload", default="general_gw",
                     choices=["general_soa", "general_gw", "general_ladder", "hubbard_chain",
-                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "jellium", "scaling"])
+                             "hubbard_2d", "hubbard_batch", "hubbard_adjoint", "jellium", "scaling",
+                             "copy_calibration"])
     ap.add_argument("--selfenergy", default=None, choices=["soa", "gw", "tpp", "tph", "dsl"],
                     help="Hubbard workloads: override the workload's selfenergy (hubbard_batch: "
                          "TPP, hubbard_chain/hubbard_2d: SOA; any of the five); general_ladder: "
@@ -877,6 +903,8 @@ def main():
         out = run_adjoint(args, torch, B)
     elif args.workload == "jellium":
         out = run_jellium(args, torch, B)
+    elif args.workload == "copy_calibration":
+        out = run_copy_calibration(args, torch)
     else:
         out = run_hubbard(args, torch, B, args.workload)
     print(json.dumps(out), flush=True)

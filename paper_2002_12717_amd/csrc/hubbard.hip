@@ -564,16 +564,21 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 
 // Slice version of the stage (every selfenergy; every cluster with ns <= 64 and
 // at most Z_MAX_ROW neighbours per site).  A work-group of SLICE_THREADS threads
-// stages up to floor(SLICE_ELEMS / ns^2) consecutive (i, j) slices
-// A[i][j][:][:] of one channel of the stage input in LDS with coalesced loads and then gives
-// one element to each thread (m = tid, tid + SLICE_THREADS, ... over the staged
-// elements), so the lanes are filled whatever ns is.  The k- and
+// (SLICE_THREADS_BIG for one cluster in items of SLICE_ELEMS elements: twice the
+// waves per compute unit for the same LDS; measured on the 8x8 cluster, 0.353
+// against 0.365 ms per launch, while the ragged batch, whose items are
+// shorter, stays faster with SLICE_THREADS) stages up to floor(SLICE_ELEMS /
+// ns^2) consecutive (i, j) slices A[i][j][:][:] of one channel of the stage
+// input in LDS with coalesced loads and then gives one element to each thread
+// (m = tid, tid + blockDim, ... over the staged elements), so the lanes are
+// filled whatever ns is.  The k- and
 // l-neighbours of the commutator lie in the same slice and are read from LDS;
 // the i- and j-neighbours, the ladder's diagonal slices and the Runge-Kutta
 // registers come from global memory.  A work item is a range [start, end) of
 // slices (channel ns^2 + i ns + j) of one channel of one cluster, at most
 // floor(SLICE_ELEMS / ns^2) long.
 constexpr int SLICE_THREADS = 512;
+constexpr int SLICE_THREADS_BIG = 1024;
 constexpr int SLICE_ELEMS = 4096;
 // TPP: the diagonal entries A_ppij of the staged slices (p < ns), kept in LDS;
 // a TPP item holds at most SLICE_DIAG / ns slices
@@ -596,7 +601,7 @@ __device__ __forceinline__ int slice_div(int n, unsigned mg) {
 }
 
 template <int MODE, int SE, bool MIXED, bool REALH>
-__global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s) {
+__global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs s) {
     constexpr bool TPP = has_pp(SE), TPH = has_ph(SE), GW = has_pol(SE);
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive, s.u_scale);
     const int ns = d.ns, z = d.zmax, ns2 = ns * ns, ns3 = ns2 * ns;
     const TI* __restrict__ A = reinterpret_cast<const TI*>(s.in2) + d.g2off;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
     if (w.start < 0) {   // G1 update of the cluster (the collision integral reads channel A)
         const cd* g1 = s.in1 + d.g1off;
         const cd* y = s.y1 + d.g1off;
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
         cd* out = s.out1 + d.g1off;
         if (MODE == RK_FIRST && w.cluster == 0 && tid == 0) guard_begin_step(s.guard);
         const unsigned long long step = MODE == RK_LAST ? s.guard.div[0] : 0ull;
-        for (int e = tid; e < 2 * ns2; e += SLICE_THREADS) {
+        for (int e = tid; e < 2 * ns2; e += nthr) {
             int sig = e / ns2, r = e % ns2, i = r / ns, j = r % ns;
             cd f = hub_g1_rhs(a, A, sig, i, j);
             rk_update<MODE>(e, f, g1[e], y, acc, out, s.cb, s.cc);
@@ -634,7 +639,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
         }
         return;
     }
-    for (int q = tid; q < ns; q += SLICE_THREADS) {
+    for (int q = tid; q < ns; q += nthr) {
         eu[q] = hf_diag(a, 0, q);
         ed[q] = hf_diag(a, 1, q);
     }
@@ -643,7 +648,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     // and all down
     const int ch = GW ? w.start / ns2 : 0;
     const int sI = ch == 2 ? 1 : 0, sJ = ch == 1 ? 0 : 1;
-    for (int q = tid; q < 2 * ns * ZR; q += SLICE_THREADS) {
+    for (int q = tid; q < 2 * ns * ZR; q += nthr) {
         const int row = q / ZR, qq = q - row * ZR, spin = row / ns, site = row - spin * ns;
         const int p = qq < z ? a.nbr[row * z + qq] : -1;
         const int dp = p >= 0 ? p - site : 0;
@@ -663,9 +668,9 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const int E = (w.end - w.start) * ns2;
     const int slice0 = w.start - ch * ns2;   // first (i, j) of the item
     const unsigned e0 = (unsigned)slice0 * (unsigned)ns2;
-    for (int m = tid; m < E; m += SLICE_THREADS) P[m] = ldo(Ach, e0 + (unsigned)m);
+    for (int m = tid; m < E; m += nthr) P[m] = ldo(Ach, e0 + (unsigned)m);
     if (TPP && ch == 0)   // the host keeps (end - start) ns <= SLICE_DIAG for these items
-        for (int q = tid; q < min((w.end - w.start) * ns, SLICE_DIAG); q += SLICE_THREADS) {
+        for (int q = tid; q < min((w.end - w.start) * ns, SLICE_DIAG); q += nthr) {
             const int sl = q / ns, p = q - sl * ns;
             DK[q] = ldo(A, (p * ns + p) * ns2 + slice0 + sl);
         }
@@ -692,7 +697,7 @@ __global__ __launch_bounds__(SLICE_THREADS, 4) void hub_slice_kernel(StageArgs s
     const cd* __restrict__ D2 = GW ? DG + (ch == 0 ? 5 : (ch == 1 ? 1 : 3)) * n3 : nullptr;   // TC, TA, WA
     const cd* __restrict__ S1 = ch == 1 ? X : Y;
     const cd* __restrict__ S2 = ch == 2 ? Y : X;
-    for (int m = tid; m < E; m += SLICE_THREADS) {
+    for (int m = tid; m < E; m += nthr) {
         const int sl = slice_div(m, mg2), r = m - sl * ns2;
         const int k = slice_div(r, mg1), l = r - k * ns;
         const int slice = slice0 + sl;
@@ -981,12 +986,13 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
     }
     if (c->hub.slices) {
         const size_t lds = (size_t)c->hub.slice_elems * sizeof(cd);
+        const int nthr = c->hub.ncl == 1 && c->hub.slice_elems == SLICE_ELEMS ? SLICE_THREADS_BIG : SLICE_THREADS;
         if (c->hub.realhop)
-            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork),
-                               dim3(SLICE_THREADS), lds, c->stream, s);
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork), dim3(nthr), lds,
+                               c->stream, s);
         else
-            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork),
-                               dim3(SLICE_THREADS), lds, c->stream, s);
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork), dim3(nthr), lds,
+                               c->stream, s);
         return;
     }
     if constexpr (!has_pol(SE)) {   // GW and DSL run on the row and slice kernels only (checked at setup)
