@@ -48,6 +48,7 @@ struct HubbardData {
     bool rows = false;             // row stage kernel (every ns <= 64, <= 4 neighbours)
     bool realhop = false;          // every hopping (off-diagonal h0) is real
     bool slices = false;           // slice stage kernel (every selfenergy, on row-kernel clusters)
+    bool row64 = false;            // slice kernel: every cluster has ns = 64 (a wave per G2 row)
     int slice_elems = 0;           // slice kernel: G2 elements of the longest item (its LDS stage)
     WorkItem* dwork = nullptr;     // TPH, GW, DSL: work list of the diagonal gather
     int ndwork = 0;

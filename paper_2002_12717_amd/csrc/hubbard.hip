@@ -312,6 +312,7 @@ __device__ __forceinline__ double wave_uniform(double v) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 __device__ __forceinline__ cd wave_uniform(cd v) { return cmk(wave_uniform(v.x), wave_uniform(v.y)); }
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Element i of an array below 4 GiB, addressed as base + 32-bit byte offset:
 // with a wave-uniform base the load takes the scalar-base + vector-offset form
@@ -600,8 +601,8 @@ __device__ __forceinline__ int slice_div(int n, unsigned mg) {
     return mg == 0u ? n : (int)__umulhi((unsigned)n, mg);
 }
 
-template <int MODE, int SE, bool MIXED, bool REALH>
-__global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs s) {
+template <int MODE, int SE, bool MIXED, bool REALH, bool ROW64>
+__global__ __launch_bounds__(SLICE_THREADS_BIG) __attribute__((amdgpu_waves_per_eu(ROW64 ? 8 : 1))) void hub_slice_kernel(StageArgs s) {
     constexpr bool TPP = has_pp(SE), TPH = has_ph(SE), GW = has_pol(SE);
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
@@ -614,10 +615,20 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
     // 0 and hopping 0): element offsets of the neighbour along l (p - l),
     // k ((p - k) ns), i ((p - i) ns^3) and j ((p - j) ns^2), each for the spin
     // that index carries in the work item's channel
+    // (ROW64 keeps the i and j ones in scalar registers and the hoppings, all
+    // real there, as binary64 reals: the LDS of two 1,024-thread work-groups
+    // per compute unit)
     __shared__ int ofl[NS_MAX_ROW * ZR], ofk[NS_MAX_ROW * ZR];
-    __shared__ int ofi[NS_MAX_ROW * ZR], ofj[NS_MAX_ROW * ZR];
-    __shared__ cd shp[2 * NS_MAX_ROW * ZR];   // hoppings [spin][site][slot]
-    __shared__ cd DK[TPP ? SLICE_DIAG : 1];    // TPP: DK[slice][p] = A_pp,ij
+    __shared__ int ofi[ROW64 ? 1 : NS_MAX_ROW * ZR], ofj[ROW64 ? 1 : NS_MAX_ROW * ZR];
+    __shared__ cd shp[ROW64 ? 1 : 2 * NS_MAX_ROW * ZR];   // hoppings [spin][site][slot]
+    __shared__ double shr[ROW64 ? 2 * NS_MAX_ROW * ZR : 1];
+    __shared__ cd DK[TPP ? (ROW64 ? 64 : SLICE_DIAG) : 1];   // TPP: DK[slice][p] = A_pp,ij
+    // ROW64: the entries of G1 and of the diagonal tensors that the item's
+    // slice (i, j) indexes by i, j or k only, one per index q < 64: X_iq, Y_iq,
+    // X_jq, Y_jq, then X_qj, Y_qj, R_jqi (TPH, from RT), S2_qi, D1_iqj (GW,
+    // from RG)
+    constexpr int RT = 4, RG = 4 + (TPH ? 3 : 0);
+    __shared__ cd rowv[ROW64 ? (RG + (GW ? 2 : 0)) * 64 : 1];
     const WorkItem w = s.work[blockIdx.x];
     const ClusterDesc d = s.desc[w.cluster];
     const Cl a = make_cl(d, s.nbr, s.hop, s.d0, s.xdrv, s.in1, s.s_drive, s.u_scale);
@@ -652,14 +663,17 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
         const int row = q / ZR, qq = q - row * ZR, spin = row / ns, site = row - spin * ns;
         const int p = qq < z ? a.nbr[row * z + qq] : -1;
         const int dp = p >= 0 ? p - site : 0;
-        shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
+        if constexpr (ROW64)
+            shr[q] = p >= 0 ? a.hop[row * z + qq].x : 0.0;
+        else
+            shp[q] = p >= 0 ? a.hop[row * z + qq] : cmk(0.0, 0.0);
         if (spin == sI) {
             ofk[site * ZR + qq] = dp * ns;
-            ofi[site * ZR + qq] = dp * ns3;
+            if (!ROW64) ofi[site * ZR + qq] = dp * ns3;
         }
         if (spin == sJ) {
             ofl[site * ZR + qq] = dp;
-            ofj[site * ZR + qq] = dp * ns2;
+            if (!ROW64) ofj[site * ZR + qq] = dp * ns2;
         }
     }
     // stage the slices [start, end) of the channel
@@ -674,10 +688,34 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
             const int sl = q / ns, p = q - sl * ns;
             DK[q] = ldo(A, (p * ns + p) * ns2 + slice0 + sl);
         }
+    if constexpr (ROW64) {
+        const int i = slice0 >> 6, j = slice0 & 63;
+        const cd* __restrict__ Xs = a.X;
+        const cd* __restrict__ Ys = a.Y;
+        for (int q = tid; q < 64; q += nthr) {
+            rowv[q] = ldo(Xs, i * 64 + q);
+            rowv[64 + q] = ldo(Ys, i * 64 + q);
+            rowv[2 * 64 + q] = ldo(Xs, j * 64 + q);
+            rowv[3 * 64 + q] = ldo(Ys, j * 64 + q);
+            if (TPH && (!GW || ch == 0)) {
+                const cd* R = s.diag + (long long)n_diag(SE) * d.doff + (GW ? 6 * ns3 : 0);
+                rowv[RT * 64 + q] = ldo(Xs, q * 64 + j);
+                rowv[(RT + 1) * 64 + q] = ldo(Ys, q * 64 + j);
+                rowv[(RT + 2) * 64 + q] = ldo(R, (j * 64 + q) * 64 + i);
+            }
+            if (GW) {
+                const cd* G = s.diag + (long long)n_diag(SE) * d.doff;
+                rowv[RG * 64 + q] = ldo(ch == 2 ? Ys : Xs, q * 64 + i);
+                rowv[(RG + 1) * 64 + q] = ldo(G + (ch == 0 ? 4 : (ch == 1 ? 0 : 2)) * (long long)ns3, (i * 64 + q) * 64 + j);
+            }
+        }
+    }
     __syncthreads();
     const unsigned mg2 = slice_magic((unsigned)ns2), mg1 = slice_magic((unsigned)ns);
     const cd* hI = shp + sI * ns * ZR;   // hoppings of the spin of i and k
     const cd* hJ = shp + sJ * ns * ZR;   // of j and l
+    const double* hIr = shr + sI * ns * ZR;   // the same, ROW64
+    const double* hJr = shr + sJ * ns * ZR;
     const cd* eI = sI ? ed : eu;
     const cd* eJ = sJ ? ed : eu;
     const cd* __restrict__ X = a.X;
@@ -697,19 +735,44 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
     const cd* __restrict__ D2 = GW ? DG + (ch == 0 ? 5 : (ch == 1 ? 1 : 3)) * n3 : nullptr;   // TC, TA, WA
     const cd* __restrict__ S1 = ch == 1 ? X : Y;
     const cd* __restrict__ S2 = ch == 2 ? Y : X;
-    for (int m = tid; m < E; m += nthr) {
-        const int sl = slice_div(m, mg2), r = m - sl * ns2;
-        const int k = slice_div(r, mg1), l = r - k * ns;
-        const int slice = slice0 + sl;
-        const int i = slice_div(slice, mg1), j = slice - i * ns;
+    const bool src = !GW || ch == 0;   // the source and the ladders live on channel A only
+    // ROW64 (every cluster has ns = 64): an item is one (i, j) slice and a wave
+    // one row (i, j, k) with lane = l.  The G1 and diagonal-tensor entries
+    // indexed by i, j and k only (and rows i and j of G1) come from the rows
+    // staged in LDS, the neighbour tables of i and j sit in scalar registers,
+    // and only the entries that depend on k and l take vector loads.
+    // Otherwise every entry is a vector load where it is used.
+    static_assert(!ROW64 || REALH, "the ns = 64 form is built for real hoppings");
+    int oi[ZR], oj[ZR];
+    double hi_[ZR], hj_[ZR];
+    if constexpr (ROW64) {
+        const int i = slice0 >> 6, j = slice0 & 63;
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            const int pi = q < z ? a.nbr[(sI * ns + i) * z + q] : -1;
+            const int pj = q < z ? a.nbr[(sJ * ns + j) * z + q] : -1;
+            oi[q] = wave_uniform(pi >= 0 ? (pi - i) * ns3 : 0);
+            oj[q] = wave_uniform(pj >= 0 ? (pj - j) * ns2 : 0);
+            hi_[q] = wave_uniform(hIr[i * ZR + q]);
+            hj_[q] = wave_uniform(hJr[j * ZR + q]);
+        }
+    }
+    // values indexed by i, j or k only: in ROW64 mode wave-uniform, kept in
+    // scalar registers
+    auto uni = [](auto v) {
+        if constexpr (ROW64) return wave_uniform(v);
+        else return v;
+    };
+    auto element = [&](const int m, const int sl, const int k, const int l, const int i, const int j) {
         const unsigned e = e0 + (unsigned)m;
         const cd av = P[m];
         // sum_p A_ijpl h_pk + sum_p A_ijkp h_pl, with h_pk = conj(h_kp)
         cd rr = cmk(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
-            const cd vl = P[m + ofl[l * ZR + q]], vk = P[m + ofk[k * ZR + q]];
-            const cd hl = hJ[l * ZR + q], hk = hI[k * ZR + q];
+            const cd vl = P[m + ofl[l * ZR + q]], vk = P[m + uni(ofk[k * ZR + q])];
+            const cd hl = ROW64 ? cmk(hJr[l * ZR + q], 0.0) : hJ[l * ZR + q];
+            const cd hk = ROW64 ? cmk(uni(hIr[k * ZR + q]), 0.0) : hI[k * ZR + q];
             if (REALH) {
                 rr.x = fma(vl.x, hl.x, fma(vk.x, hk.x, rr.x));
                 rr.y = fma(vl.y, hl.x, fma(vk.y, hk.x, rr.y));
@@ -718,13 +781,14 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
                 rr = cfma_conjb(rr, vk, hk);
             }
         }
-        const cd ei = eI[i], ej = eJ[j], ek = eI[k], el = eJ[l];
+        const cd ei = uni(eI[i]), ej = uni(eJ[j]), ek = uni(eI[k]), el = eJ[l];
         cd c = cmul(cmk(ei.x + ej.x - ek.x - el.x, ei.y + ej.y - ek.y - el.y), av);
         c = csub(c, rr);
 #pragma unroll
         for (int q = 0; q < ZR; ++q) {
-            const cd vi = ldo(Ach, e + ofi[i * ZR + q]), vj = ldo(Ach, e + ofj[j * ZR + q]);
-            const cd hi = hI[i * ZR + q], hj = hJ[j * ZR + q];
+            const cd hi = ROW64 ? cmk(hi_[q], 0.0) : hI[i * ZR + q], hj = ROW64 ? cmk(hj_[q], 0.0) : hJ[j * ZR + q];
+            const cd vi = ldo(Ach, e + (ROW64 ? oi[q] : ofi[i * ZR + q]));
+            const cd vj = ldo(Ach, e + (ROW64 ? oj[q] : ofj[j * ZR + q]));
             if (REALH) {
                 c.x = fma(hi.x, vi.x, fma(hj.x, vj.x, c.x));
                 c.y = fma(hi.x, vi.y, fma(hj.x, vj.y, c.y));
@@ -734,45 +798,74 @@ __global__ __launch_bounds__(SLICE_THREADS_BIG) void hub_slice_kernel(StageArgs 
             }
         }
         if (GW) {   // polarization terms of the channel (Sec. VII.B, reading of the partner spins)
-            const cd s1 = ldo(S1, j * ns + l), s2 = ldo(S2, k * ns + i);
-            const cd p1 = cmul_mi(cmul(s1, csub(ldo(D1, (i * ns + k) * ns + j), ldo(D1, (i * ns + k) * ns + l))));
+            const cd s1 = ldo(S1, j * ns + l);
+            const cd s2 = ROW64 ? uni(rowv[RG * 64 + k]) : ldo(S2, k * ns + i);
+            const cd d1j = ROW64 ? uni(rowv[(RG + 1) * 64 + k]) : ldo(D1, (i * ns + k) * ns + j);
+            const cd p1 = cmul_mi(cmul(s1, csub(d1j, ldo(D1, (i * ns + k) * ns + l))));
             const cd p2 = cmul_mi(cmul(s2, csub(ldo(D2, (k * ns + j) * ns + l), ldo(D2, (i * ns + j) * ns + l))));
             c = cadd(c, cscale(csub(p1, cconj(p2)), a.U));
         }
-        const cd xil = ldo(X, i * ns + l), yil = ldo(Y, i * ns + l);
-        const cd xkl = ldo(X, k * ns + l), ykl = ldo(Y, k * ns + l);
-        const cd xij = ldo(X, i * ns + j), yji = ldo(Y, j * ns + i);
-        if (!GW || ch == 0) {   // source (eq:soa-cubic-scheme), channel A only; X_lk = -conj(X_kl)
-            const cd yjl = ldo(Y, j * ns + l);
-            const cd xik = ldo(X, i * ns + k), xjk = ldo(X, j * ns + k), yjk = ldo(Y, j * ns + k);
-            const cd xlk = cmk(-xkl.x, xkl.y);
-            const double dd = (double)(i == j) - (double)(k == l);
-            const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
-            const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
-            c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
-        }
-        if (TPP && ch == 0) {   // ladder (Sec. VII.C) and its partner, channel A only
-            const int kl = k * ns + l;
-            const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
-            cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
-            if (i == j) l1 = cadd(l1, dii);
-            const cd dkk = DK[sl * ns + k], dll = DK[sl * ns + l];
-            const cd ylk = cmk(-ykl.x, ykl.y);
-            cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
-            if (k == l) l2 = cadd(l2, dkk);
-            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
-        }
-        if (TPH && ch == 0) {   // particle-hole ladder (Sec. VII.C) and its partner, channel A only
-            //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
-            //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
-            const cd rjki = ldo(DR, (j * ns + k) * ns + i), rjkl = ldo(DR, (j * ns + k) * ns + l);
-            const cd sikl = ldo(DS, (i * ns + k) * ns + l), sijl = ldo(DS, (i * ns + j) * ns + l);
-            const cd ykj = ldo(Y, k * ns + j), xkj = ldo(X, k * ns + j);
-            const cd l1 = cmul_i(csub(cmul(yil, rjki), cmul(xil, rjkl)));
-            const cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
-            c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+        if (src) {
+            const cd xil = ROW64 ? rowv[l] : ldo(X, i * ns + l), yil = ROW64 ? rowv[64 + l] : ldo(Y, i * ns + l);
+            const cd xkl = ldo(X, k * ns + l), ykl = ldo(Y, k * ns + l);
+            const cd xij = ROW64 ? uni(rowv[j]) : ldo(X, i * ns + j);
+            const cd yji = ROW64 ? uni(rowv[3 * 64 + i]) : ldo(Y, j * ns + i);
+            {   // source (eq:soa-cubic-scheme), channel A only; X_lk = -conj(X_kl)
+                const cd yjl = ROW64 ? rowv[3 * 64 + l] : ldo(Y, j * ns + l);
+                const cd xik = ROW64 ? uni(rowv[k]) : ldo(X, i * ns + k);
+                const cd xjk = ROW64 ? uni(rowv[2 * 64 + k]) : ldo(X, j * ns + k);
+                const cd yjk = ROW64 ? uni(rowv[3 * 64 + k]) : ldo(Y, j * ns + k);
+                const cd xlk = cmk(-xkl.x, xkl.y);
+                const double dd = (double)(i == j) - (double)(k == l);
+                const cd t1 = cmul(csub(cmul(xij, xjk), cmul(xlk, xil)), yjl);
+                const cd t2 = cmul(csub(cmul(yji, yil), cmul(ykl, yjk)), xik);
+                c = cadd(c, cadd(cscale(cmul(xik, yjl), a.U * dd), cscale(cmul_i(cadd(t1, t2)), a.U)));
+            }
+            if (TPP) {   // ladder (Sec. VII.C) and its partner, channel A only
+                const int kl = k * ns + l;
+                const cd dii = ldo(A, (i * ns + i) * ns2 + kl), djj = ldo(A, (j * ns + j) * ns2 + kl);
+                cd l1 = cmul_i(cadd(cmul(yji, dii), cmul(xij, djj)));
+                if (i == j) l1 = cadd(l1, dii);
+                const cd dkk = DK[sl * ns + k], dll = DK[sl * ns + l];
+                const cd ylk = cmk(-ykl.x, ykl.y);
+                cd l2 = cmul_i(cadd(cmul(ylk, dkk), cmul(xkl, dll)));
+                if (k == l) l2 = cadd(l2, dkk);
+                c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+            }
+            if (TPH) {   // particle-hole ladder (Sec. VII.C) and its partner, channel A only
+                //   L_ijkl = i U (Y_il A_ijki - X_il A_ljkl)
+                //   L_klij = i U (Y_kj A_klik - X_kj A_jlij)
+                const cd rjki = ROW64 ? uni(rowv[(RT + 2) * 64 + k]) : ldo(DR, (j * ns + k) * ns + i);
+                const cd rjkl = ldo(DR, (j * ns + k) * ns + l);
+                const cd sikl = ldo(DS, (i * ns + k) * ns + l), sijl = ldo(DS, (i * ns + j) * ns + l);
+                const cd ykj = ROW64 ? uni(rowv[(RT + 1) * 64 + k]) : ldo(Y, k * ns + j);
+                const cd xkj = ROW64 ? uni(rowv[RT * 64 + k]) : ldo(X, k * ns + j);
+                const cd l1 = cmul_i(csub(cmul(yil, rjki), cmul(xil, rjkl)));
+                const cd l2 = cmul_i(csub(cmul(ykj, sikl), cmul(xkj, sijl)));
+                c = cadd(c, cscale(csub(l1, cconj(l2)), a.U));
+            }
         }
         rk_update<MODE, TO, true>((int)e, cmul_mi(c), av, y, acc, out, s.cb, s.cc);
+    };
+    if constexpr (ROW64) {
+        const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), nw = nthr >> 6;
+        const int i = slice0 >> 6, j = slice0 & 63;
+#pragma unroll 1
+        for (int k = wid; k < 64; k += nw) {
+            // l is the lane; kept opaque so that its LDS reads stay in the loop
+            // instead of holding registers across it
+            int l = tid & 63;
+            asm volatile("" : "+v"(l));
+            element(k * 64 + l, 0, k, l, i, j);
+        }
+    } else {
+        for (int m = tid; m < E; m += nthr) {
+            const int sl = slice_div(m, mg2), r2 = m - sl * ns2;
+            const int k = slice_div(r2, mg1), l = r2 - k * ns;
+            const int slice = slice0 + sl;
+            const int i = slice_div(slice, mg1), j = slice - i * ns;
+            element(m, sl, k, l, i, j);
+        }
     }
 }
 
@@ -987,12 +1080,15 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
     if (c->hub.slices) {
         const size_t lds = (size_t)c->hub.slice_elems * sizeof(cd);
         const int nthr = c->hub.ncl == 1 && c->hub.slice_elems == SLICE_ELEMS ? SLICE_THREADS_BIG : SLICE_THREADS;
-        if (c->hub.realhop)
-            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true>), dim3(c->hub.nwork), dim3(nthr), lds,
-                               c->stream, s);
+        if (SE != SE_DSL && c->hub.realhop && c->hub.row64)
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true, SE != SE_DSL>), dim3(c->hub.nwork),
+                               dim3(nthr), lds, c->stream, s);
+        else if (c->hub.realhop)
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true, false>), dim3(c->hub.nwork), dim3(nthr),
+                               lds, c->stream, s);
         else
-            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false>), dim3(c->hub.nwork), dim3(nthr), lds,
-                               c->stream, s);
+            hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, false, false>), dim3(c->hub.nwork), dim3(nthr),
+                               lds, c->stream, s);
         return;
     }
     if constexpr (!has_pol(SE)) {   // GW and DSL run on the row and slice kernels only (checked at setup)
@@ -1358,6 +1454,15 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     H.rows = rowk;
     H.slices = slicek;
     H.realhop = realhop;
+    // every cluster has ns = 64: one (i, j) slice per item, a wave per row.
+    // Measured per stage on the 8x8 cluster against the general slice form:
+    // TPP 0.367 / 0.399 ms, TPH 0.373 / 0.412, GW 1.09 / 1.15, and 9-15%
+    // faster for every closure in mixed precision; binary64 SOA, whose middle
+    // stage spills at the 64 registers that two work-groups per compute unit
+    // allow, 0.366 / 0.353, keeps the general form, and DSL (too much LDS for
+    // two work-groups) too.
+    H.row64 = slicek && std::all_of(nsv, nsv + ncl, [](int n) { return n == 64; }) && se != SE_DSL &&
+              !(se == SE_SOA && c->d.precision != G1G2_MIXED);
     H.ndwork = (int)dwork.size();
     H.slice_elems = slice_elems;
     H.diag_elems = n_diag(se) > 0 ? n_diag(se) * doff : 0;

@@ -913,11 +913,12 @@ def test_adjoint_autograd_function_and_finite_differences(lib):
 
 
 # --------------------------------------------------------------------------- full sizes and edge cases
-@pytest.mark.parametrize("se", ["soa", "tph", "gw", "dsl"])
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw", "dsl"])
 def test_full_size_hubbard_8x8_driven_rhs(lib, se):
     """The 8x8 workload (ns = 64) with its drive switched on, at a random
     correlated state: every element of one right-hand side, in the launch
-    configuration of the benchmark (row kernel, one launch per stage)."""
+    configuration of the benchmark (the slice kernel's ns = 64 form: a wave
+    per G2 row, the i-, j- and k-indexed entries through the scalar cache)."""
     from paper_2002_12717_amd import binding as B
     s = adjoint_system()
     ns, d = s.ns, s.drive
@@ -944,6 +945,37 @@ def test_full_size_hubbard_8x8_driven_rhs(lib, se):
     say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
     assert e1 < 1e-12 and e2 < 1e-12
     p.close()
+
+
+@pytest.mark.parametrize("se", ["soa", "tpp", "tph", "gw"])
+def test_full_size_hubbard_8x8_mixed_steps(lib, se):
+    """The 8x8 cluster (ns = 64) in mixed precision, whose stages take the
+    slice kernel's ns = 64 form for every closure here: 20 graph-replayed RK4
+    steps from a random correlated state against the binary64 steps of the
+    same library, which the element-wise test above ties to the oracle."""
+    from paper_2002_12717_amd import binding as B
+    s = adjoint_system()
+    ns = s.ns
+    r = rng(106, len(se))
+    X, Y = random_gless(ns, r), random_gless(ns, r)
+    nch = 3 if se == "gw" else 1
+    g2 = np.stack([random_g2(ns, r, scale=0.05, exchange=False) for _ in range(nch)])
+    g2 = g2 if nch == 3 else g2[0]
+    say(f"[full size] 8x8 {se}: 20 mixed steps against binary64")
+    stream = torch.cuda.Stream()
+    out = {}
+    for prec in (B.FP64, B.MIXED):
+        p = B.Propagator(B.HUBBARD, _se(se), ns, s.h0, np.stack([X, Y]), U=s.U, precision=prec,
+                         stream=stream.cuda_stream)
+        p.set_state(np.stack([X, Y]), g2, 0.0)
+        p.step(0.01, 20)
+        out[prec] = p.get_state()
+        p.close()
+    e1 = rel(out[B.MIXED][0], out[B.FP64][0])
+    e2 = rel(out[B.MIXED][1], out[B.FP64][1])
+    say(f"   err G1 {e1:.2e}  err G2 {e2:.2e}")
+    assert e1 < 1e-6 and e2 < 1e-6
+    assert e2 > 1e-12                          # the binary32 stage copies are in use
 
 
 def test_full_size_batch_sampled_clusters(lib):
