@@ -476,11 +476,12 @@ def run_jellium(args, torch, B):
     import numpy as np
     from workloads import jellium_system
     se = args.selfenergy or "gw"
-    if se not in ("soa", "gw"):
-        raise SystemExit("jellium takes --selfenergy soa or gw")
+    if se not in ("soa", "gw", "tpp", "tph"):
+        raise SystemExit("jellium takes --selfenergy soa, gw, tpp or tph")
+    ladder = se in ("tpp", "tph")
     s = jellium_system()
     nb = s.nb
-    code = B.GW if se == "gw" else B.SOA
+    code = {"soa": B.SOA, "gw": B.GW, "tpp": B.TPP, "tph": B.TPH}[se]
     stream = torch.cuda.Stream()
     res = {}
     for prec in ("fp64", "mixed"):
@@ -503,11 +504,32 @@ def run_jellium(args, torch, B):
     mx_step = mx["ms"] / args.steps
     n2 = 3.0 * nb ** 3
     tot, cnt = f64["prof"]["jel_stage"]
-    bytes_launch = 64.0 * n2          # 48, 80, 80, 48 B per element over the four stages
+    # 48, 80, 80, 48 B per element over the four stages; the T matrices read
+    # the ladder sums at the element and at its partner (32 B more)
+    extra = 32.0 if ladder else 0.0
+    bytes_launch = (64.0 + extra) * n2
     ach = bytes_launch * cnt / (tot * 1e-3) / 1e9
     mtot, mcnt = mx["prof"]["jel_stage"]
-    mbytes = 52.0 * n2                # binary32 stage copies: 40, 64, 64, 40 B
+    mbytes = (52.0 + extra) * n2      # binary32 stage copies: 40, 64, 64, 40 B
     mach = mbytes * mcnt / (mtot * 1e-3) / 1e9
+    stage_roof = {"kernel": "jel_stage", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM,
+                  "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4), "traffic": None,
+                  "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt}
+    roof, lad_roof, mx_lad = stage_roof, None, None
+    if ladder:
+        # the ladder product: 3 nb^2 rows x nb x nb complex-by-real multiply-adds (4 flops)
+        lflops = 12.0 * float(nb) ** 4
+        ltot, lcnt = f64["prof"]["jel_lad"]
+        lach = lflops * lcnt / (ltot * 1e-3) / 1e12
+        lad_roof = {"kernel": "jel_lad", "bound": "mfma", "achieved": round(lach, 3), "peak": PEAK_FP64_MFMA,
+                    "unit": "TFLOP/s", "frac": round(lach / PEAK_FP64_MFMA, 4), "traffic": None,
+                    "kernel_ms_avg": round(ltot / lcnt, 6), "flop_per_launch": lflops, "launches": lcnt}
+        mlt, mlc = mx["prof"]["jel_lad"]
+        mx_lad = {"kernel": "jel_lad", "achieved": round(lflops * mlc / (mlt * 1e-3) / 1e12, 3),
+                  "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
+                  "frac": round(lflops * mlc / (mlt * 1e-3) / 1e12 / PEAK_FP64_MFMA, 4)}
+        if ltot > tot:
+            roof = lad_roof
     err = trajectory_error(mx["traj"], f64["traj"])
     e0 = f64["traj"][0][1]
     drift = max(abs(v[1] - e0) for v in f64["traj"].values()) / max(abs(e0), 1.0)
@@ -518,9 +540,7 @@ def run_jellium(args, torch, B):
               "nb": nb, "g2_elements": int(n2), "selfenergy": se.upper(), "parallelism": "single GPU"}
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     out.update({
-        "roofline": {"kernel": "jel_stage", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM,
-                     "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4), "traffic": None,
-                     "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt},
+        "roofline": roof,
         "kernels": kernel_table(f64["prof"]),
         "energy_drift_rel": drift,
         "mixed": {"dtype": "f32 G2 stage copies / f64 state and arithmetic", "value": round(1e3 / mx_step, 3),
@@ -530,6 +550,9 @@ def run_jellium(args, torch, B):
                                "unit": "GB/s", "frac": round(mach / PEAK_HBM, 4), "bytes_per_launch": mbytes},
                   "kernels": kernel_table(mx["prof"])},
     })
+    if ladder:
+        out["stage_roofline" if roof is lad_roof else "ladder_roofline"] = stage_roof if roof is lad_roof else lad_roof
+        out["mixed"]["ladder_roofline"] = mx_lad
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_jellium(s, se)
     return out
@@ -544,7 +567,8 @@ def cpu_baseline_jellium(system, se, seconds: float = 12.0):
     g1 = torch.as_tensor(system.g1, dtype=torch.complex128)
     nb = system.nb
     g2 = torch.zeros((2, 2, nb, nb, nb), dtype=torch.complex128)
-    OJ.rhs(system.eps, system.v, g1, g2, system.dims, se)   # warm-up
+    if se in ("soa", "gw"):   # warm-up (one T-matrix right-hand side takes seconds to a minute)
+        OJ.rhs(system.eps, system.v, g1, g2, system.dims, se)
     n, t0 = 0, time.perf_counter()
     while True:
         OJ.rhs(system.eps, system.v, g1, g2, system.dims, se)

@@ -163,10 +163,13 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, con
  *   G2 = [3][nb][nb][nb] complex, blocks up-up, up-down, down-down, element
  *        [c][P][Pb][Q] = G2^{a b a b}_{(P-Q, a), (Pb+Q, b), (P, a), (Pb, b)}
  *        (eq:g2-def-jellium; down-up follows from eq:Gsymm_a).
- * G2_0 may be NULL (uncorrelated start).  Selfenergies SOA (eq:jellium-g2) and
- * GW (eq:jellium-gwpi, Psi^- with G1G2_GW_EXCHANGE); FP64 or MIXED (binary32
- * G2 stage copies, like the Hubbard basis).  EUNSUPPORTED for the T matrices
- * and DSL; EINVAL for bad dims, nb != Lx Ly Lz or v[0] != 0.  Every other call
+ * G2_0 may be NULL (uncorrelated start).  Selfenergies SOA (eq:jellium-g2),
+ * GW (eq:jellium-gwpi, Psi^- with G1G2_GW_EXCHANGE), TPP (eq:jellium-lambdapp)
+ * and TPH (eq:jellium-lambdaph), the T matrices with Psi^- and the partner
+ * conj(Lambda_{P-Q, Pb+Q, -Q}); they hold one more [3][nb]^3 buffer (the
+ * ladder sums, 484 MB at 6x6x6).  FP64 or MIXED (binary32 G2 stage copies,
+ * like the Hubbard basis).  EUNSUPPORTED for DSL; EINVAL for bad dims,
+ * nb != Lx Ly Lz or v[0] != 0.  Every other call
  * works as for the other bases except set_h0, set_U, set_drive, set_switch, the
  * adjoint and the batch calls (EUNSUPPORTED or ESTATE).  Observables: N per
  * spin, E_kin = sum eps n, E_mf the Fock energy, E_corr.                    */

@@ -313,7 +313,7 @@ g1g2_status g1g2_jellium_init(g1g2_ctx** out, const g1g2_desc* d, const int32_t*
         if (dims[k] < 1 || dims[k] > 1024) return G1G2_EINVAL;
     const long long nbl = (long long)dims[0] * dims[1] * dims[2];
     if (nbl != d->nb) return G1G2_EINVAL;
-    if (d->selfenergy != G1G2_SOA && d->selfenergy != G1G2_GW) return G1G2_EUNSUPPORTED;
+    if (d->selfenergy == G1G2_DSL) return G1G2_EUNSUPPORTED;
     if (nbl > jel_max_nb()) return G1G2_EUNSUPPORTED;
     if (v[0] != 0.0) return G1G2_EINVAL;   // the neutralizing background removes v_0
     for (long long q = 0; q < nbl; ++q)

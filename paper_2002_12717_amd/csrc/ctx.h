@@ -111,6 +111,13 @@ struct JelliumData {
     cd* sc[3] = {};          // [3][nb][nb] per-block sums over the middle momentum
     cd* sb[3] = {};          // [nb][nb] down-spin sums of the up-down block
     int parity = 0;          // buffer set holding the sums of the next stage input
+    // T-matrix closures: the ladder sums of the stage input [3][nb]^3, the
+    // product's real operand [nb rounded up to 4][nbp] and the index table of
+    // S - K [nb][nb]; nbp = nb rounded up to 16
+    cd* lad = nullptr;
+    double* vmat = nullptr;
+    int* subt = nullptr;
+    int nbp = 0;
 };
 
 struct g1g2_ctx {

@@ -21,6 +21,15 @@
 // The middle sums (over Pb) are exact per work-group; the down-spin sums that
 // the up-down block feeds (a sum over its first momentum) are accumulated with
 // binary64 atomics.
+//
+// The T-matrix closures (eq:jellium-lambdapp, eq:jellium-lambdaph) add one
+// O(nb^4) product per stage, on the matrix cores before the stage pass:
+//   jel_lad (TPP): L[c][P][Pb][Q]  = sum_K G2[c][P][Pb][K] v_{K-Q}
+//   jel_lad (TPH): M[c][P][S][Pb]  = sum_K G2[c][P][K][S-K] v_{Pb-K}
+// (TPH sums along the anti-diagonals Pb + Q = S of a (Pb, Q) plane, which
+// makes it the same complex-by-real matrix product on gathered rows).  The
+// stage pass adds Lambda = -f L at the element and the partner's
+// -conj(Lambda_{P-Q, Pb+Q, -Q}), both read from that buffer.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -29,6 +38,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "mfma.h"
 
 namespace {
 
@@ -37,6 +47,8 @@ constexpr int JEL_MAX_NB = 1024; // momenta of the grid (the stage kernel stages
 constexpr int JEL_QB = 64;       // momenta Q per work-group (one per lane)
 constexpr int JEL_THREADS = 256; // prologue and observables
 constexpr int JEL_WAVES = 8;     // stage pass: wave w takes Pb = w, w + JEL_WAVES, ...
+constexpr int LAD_NT = 7;        // ladder product: column tiles of 16 per pass of a wave
+enum { LAD_NONE = 0, LAD_PP = 1, LAD_PH = 2 };
 
 struct JGrid {
     int lx, ly, lz, nb;
@@ -151,6 +163,7 @@ struct StageArgsJ {
     void* out2;
     double cb, cc;
     int exch;                 // source with the exchange term (Psi^-)
+    const cd* lad;            // [3][nb]^3 ladder sums of the stage input (TPP: L, TPH: M)
     cd* sc_next;              // [3][nb][nb] middle sums of the values written (exact)
     cd* sb_next;              // [nb][nb] their down-spin sums from the up-down block (atomics)
 };
@@ -174,7 +187,7 @@ __device__ __forceinline__ void atomic_add_c(cd* p, cd v) {
 // fixed (P, Pb) are JEL_QB consecutive elements.  REDUCE: only the partial sums
 // of the input (no right-hand side); MODE == RK_RHS: the right-hand side into
 // out2, no sums.
-template <int MODE, bool GW, typename TI, typename TO, bool REDUCE>
+template <int MODE, bool GW, typename TI, typename TO, bool REDUCE, int LAD>
 __global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s) {
     // h^HF and G1 of both spins and v, staged in LDS (dynamic: 2 nb + 2 nb complex, nb real)
     extern __shared__ cd sh_dyn[];
@@ -271,6 +284,26 @@ __global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s)
                     const cd pt = cscale(cmul(fa, SbP), vQ);
                     r = cadd(r, csub(pi, cconj(pt)));
                 }
+                if (LAD != LAD_NONE) {
+                    // Lambda - conj(Lambda_{P-Q, Pb+Q, -Q}), Lambda = -f L with
+                    //   pp (eq:jellium-lambdapp): f = G>_{P-Q} G>_{Pb+Q} - G<_{P-Q} G<_{Pb+Q}
+                    //   ph (eq:jellium-lambdaph): f = G>_{P-Q} G<_{Pb} - G<_{P-Q} G>_{Pb}
+                    // and f at the partner element from the same four G1 values
+                    const cd* __restrict__ L = s.lad + c * n3;
+                    cd lo, lp, fo, fp;
+                    if (LAD == LAD_PP) {
+                        lo = L[e];
+                        lp = L[((size_t)Pm[j] * nb + Pbp) * nb + negQ];
+                        fo = csub(cmul(gg1, gg2), cmul(gl1, gl2));
+                        fp = csub(cmul(gg3, gg4), cmul(gl3, gl4));
+                    } else {
+                        lo = L[((size_t)Pv[j] * nb + Pbp) * nb + Pb];
+                        lp = L[((size_t)Pm[j] * nb + Pb) * nb + Pbp];
+                        fo = csub(cmul(gg1, gl4), cmul(gl1, gg4));
+                        fp = csub(cmul(gg3, gl2), cmul(gl3, gg2));
+                    }
+                    r = csub(r, csub(cmul(fo, lo), cconj(cmul(fp, lp))));
+                }
                 const cd f = cmul_mi(r);
                 if (MODE == RK_RHS) {
                     o = f;
@@ -311,6 +344,76 @@ __global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s)
             s.sc_next[((size_t)c * nb + Pv[j]) * nb + Q] = t;
         }
     }
+}
+
+struct LadArgs {
+    int nb, nbp;              // momenta, and nb rounded up to the 16-wide column tiles
+    const void* in2;          // stage input G2 [3][nb]^3
+    const double* vmat;       // [nkp][nbp] B[K][n]: TPP v_{K-n}, TPH v_{n-K} (zero padded)
+    const int* subt;          // [nb][nb] index of S - K (TPH)
+    cd* out;                  // [3][nb]^3
+};
+
+// The ladder sums as a complex-by-real matrix product on the matrix cores,
+// out[row][n] = sum_K A[row][K] B[K][n] over rows (c, P, X):
+//   TPP: A[row][K] = G2[c][P][X][K]          (X = Pb)
+//   TPH: A[row][K] = G2[c][P][K][X - K]      (X = S, the anti-diagonal)
+// A wave owns 16 rows and sweeps the columns in passes of LAD_NT tiles of 16,
+// with one binary64 16x16x4 product each for the real and the imaginary part
+// of A per tile and 4-deep step of K (K padded to a multiple of 4 with zero
+// rows of B).  B (at most 1024 x 1024 binary64 values, read by every wave)
+// stays in the L2 cache.
+template <int KIND, typename TI>
+__global__ __launch_bounds__(256) void jel_lad_kernel(LadArgs s) {
+    const int nb = s.nb, nbp = s.nbp;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const long long nn = (long long)nb * nb, rows = 3 * nn;
+    const long long r0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (r0 >= rows) return;   // no barrier in this kernel
+    const long long row = r0 + li;
+    const bool rok = row < rows;
+    const long long rc = rok ? row : r0;
+    const int c = (int)(rc / nn);
+    const long long rem = rc - c * nn;
+    const int P = (int)(rem / nb), X = (int)(rem - (long long)P * nb);
+    const TI* __restrict__ in = static_cast<const TI*>(s.in2) + (size_t)c * nn * nb;
+    const size_t base = KIND == LAD_PP ? ((size_t)P * nb + X) * nb : (size_t)P * nb * nb;
+    for (int j0 = 0; j0 < nbp; j0 += 16 * LAD_NT) {
+        v4d ar[LAD_NT], ai[LAD_NT];
+#pragma unroll
+        for (int t = 0; t < LAD_NT; ++t) ar[t] = ai[t] = MF<double>::zero();
+        for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int K = k0 + lk;
+            cd a = cmk(0.0, 0.0);
+            if (rok && K < nb) {
+                const size_t idx = KIND == LAD_PP ? base + K : base + (size_t)K * nb + s.subt[X * nb + K];
+                a = ld_c(in, (long long)idx);
+            }
+            const double* __restrict__ brow = s.vmat + (size_t)K * nbp + j0 + li;
+#pragma unroll
+            for (int t = 0; t < LAD_NT; ++t) {
+                const int n = j0 + 16 * t + li;
+                const double b = n < nbp ? brow[16 * t] : 0.0;
+                ar[t] = MF<double>::mac(a.x, b, ar[t]);
+                ai[t] = MF<double>::mac(a.y, b, ai[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < LAD_NT; ++t) {
+            const int n = j0 + 16 * t + tile_col();
+            if (n >= nb) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long ro = r0 + tile_row<double>(r);
+                if (ro < rows) s.out[ro * nb + n] = cmk(ar[t][r], ai[t][r]);
+            }
+        }
+    }
+}
+
+int lad_blocks(const g1g2_ctx* c) {
+    const long long rows = 3LL * c->jel.nb * c->jel.nb;
+    return (int)((rows + 63) / 64);
 }
 
 // Observables from G1 and S of the state (one work-group): N^s, E_kin = sum eps n,
@@ -381,19 +484,30 @@ g1g2_status jel_reduce(g1g2_ctx* c, const cd* g2, int buf) {
     s.in2 = g2;
     s.sc_next = J.sc[buf];
     s.sb_next = J.sb[buf];
-    hipLaunchKernelGGL((jel_stage_kernel<RK_FIRST, false, cd, cd, true>), dim3(stage_blocks(c)),
+    hipLaunchKernelGGL((jel_stage_kernel<RK_FIRST, false, cd, cd, true, LAD_NONE>), dim3(stage_blocks(c)),
                        dim3(64 * JEL_WAVES), stage_lds(c), c->stream, s);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "jel_reduce");
     return G1G2_OK;
 }
 
-template <int MODE, bool GW, bool MIXED>
+template <int MODE, bool GW, bool MIXED, int LAD>
 void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
     using TI = typename std::conditional<MIXED && (MODE == RK_MID || MODE == RK_LAST), float2, cd>::type;
     using TO = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
-    hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false>), dim3(stage_blocks(c)), dim3(64 * JEL_WAVES),
-                       stage_lds(c), c->stream, s);
+    if constexpr (LAD != LAD_NONE) {   // the ladder sums of the stage input first
+        LadArgs la{};
+        la.nb = c->jel.nb;
+        la.nbp = c->jel.nbp;
+        la.in2 = s.in2;
+        la.vmat = c->jel.vmat;
+        la.subt = c->jel.subt;
+        la.out = c->jel.lad;
+        hipLaunchKernelGGL((jel_lad_kernel<LAD, TI>), dim3(lad_blocks(c)), dim3(256), 0, c->stream, la);
+        prof_mark(c, "jel_lad");
+    }
+    hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false, LAD>), dim3(stage_blocks(c)),
+                       dim3(64 * JEL_WAVES), stage_lds(c), c->stream, s);
 }
 
 template <int MODE>
@@ -436,14 +550,21 @@ g1g2_status jel_stage_t(g1g2_ctx* c, const Regs& in, const Regs& y, const Regs& 
     s.exch = c->d.selfenergy != G1G2_GW || (c->d.flags & G1G2_GW_EXCHANGE) ? 1 : 0;
     s.sc_next = J.sc[wbuf];
     s.sb_next = J.sb[wbuf];
-    const bool gw = c->d.selfenergy == G1G2_GW;
+    s.lad = J.lad;
+    const int se = c->d.selfenergy;
     const bool mixed = MODE != RK_RHS && c->d.precision == G1G2_MIXED;
-    if (gw) {
-        if (mixed) launch_stage<MODE, true, true>(c, s);
-        else launch_stage<MODE, true, false>(c, s);
+    if (se == G1G2_GW) {
+        if (mixed) launch_stage<MODE, true, true, LAD_NONE>(c, s);
+        else launch_stage<MODE, true, false, LAD_NONE>(c, s);
+    } else if (se == G1G2_TPP) {
+        if (mixed) launch_stage<MODE, false, true, LAD_PP>(c, s);
+        else launch_stage<MODE, false, false, LAD_PP>(c, s);
+    } else if (se == G1G2_TPH) {
+        if (mixed) launch_stage<MODE, false, true, LAD_PH>(c, s);
+        else launch_stage<MODE, false, false, LAD_PH>(c, s);
     } else {
-        if (mixed) launch_stage<MODE, false, true>(c, s);
-        else launch_stage<MODE, false, false>(c, s);
+        if (mixed) launch_stage<MODE, false, true, LAD_NONE>(c, s);
+        else launch_stage<MODE, false, false, LAD_NONE>(c, s);
     }
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "jel_stage");
@@ -461,6 +582,34 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
     J.dims[2] = dims[2];
     J.nb = dims[0] * dims[1] * dims[2];
     const size_t nb = J.nb, nn = nb * nb;
+    const int se = c->d.selfenergy;
+    if (se == G1G2_TPP || se == G1G2_TPH) {
+        // the ladder product's operands: B[K][n] = v_{K-n} (TPP) or v_{n-K}
+        // (TPH), zero padded to [nb rounded up to 4][nb rounded up to 16], the
+        // index table of S - K (TPH), and the [3][nb]^3 buffer of the sums
+        J.nbp = (J.nb + 15) / 16 * 16;
+        const int nkp = (J.nb + 3) / 4 * 4;
+        auto sub = [&](int a, int b) {   // index of momentum a - b on the grid
+            const int ax = a % dims[0], ay = (a / dims[0]) % dims[1], az = a / (dims[0] * dims[1]);
+            const int bx = b % dims[0], by = (b / dims[0]) % dims[1], bz = b / (dims[0] * dims[1]);
+            const int x = (ax - bx + dims[0]) % dims[0], y = (ay - by + dims[1]) % dims[1];
+            const int z = (az - bz + dims[2]) % dims[2];
+            return x + dims[0] * (y + dims[1] * z);
+        };
+        std::vector<double> vm((size_t)nkp * J.nbp, 0.0);
+        std::vector<int> st(nn);
+        for (int k = 0; k < J.nb; ++k)
+            for (int n = 0; n < J.nb; ++n) {
+                vm[(size_t)k * J.nbp + n] = se == G1G2_TPP ? v[sub(k, n)] : v[sub(n, k)];
+                st[(size_t)k * nb + n] = sub(k, n);
+            }
+        HIP_OK(c, hipMalloc(&J.vmat, vm.size() * sizeof(double)));
+        HIP_OK(c, hipMalloc(&J.subt, st.size() * sizeof(int)));
+        HIP_OK(c, hipMalloc(&J.lad, 3 * nn * nb * sizeof(cd)));
+        HIP_OK(c, hipMemcpyAsync(J.vmat, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(J.subt, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+    }
     HIP_OK(c, hipMalloc(&J.eps, 2 * nb * sizeof(double)));
     HIP_OK(c, hipMalloc(&J.v, nb * sizeof(double)));
     HIP_OK(c, hipMalloc(&J.hhf, 2 * nb * sizeof(cd)));
@@ -478,7 +627,8 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
 
 void jel_free(g1g2_ctx* c) {
     JelliumData& J = c->jel;
-    for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot, (void*)J.skew})
+    for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot, (void*)J.skew, (void*)J.lad,
+                    (void*)J.vmat, (void*)J.subt})
         if (p) (void)hipFree(p);
     for (int b = 0; b < 3; ++b) {
         if (J.sc[b]) (void)hipFree(J.sc[b]);

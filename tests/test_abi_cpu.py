@@ -125,7 +125,7 @@ def test_tuning_table_drives_batch_init(monkeypatch):
 
 def test_jellium_init_rejects_bad_arguments_without_device(so_path):
     """Jellium argument checks precede any device call: the grid must match
-    nb, v[0] must vanish, and the T-matrix closures are not offered."""
+    nb, v[0] must vanish, and DSL is not offered."""
     import numpy as np
     from paper_2002_12717_amd import binding
     lib = binding.load(so_path)
@@ -143,7 +143,7 @@ def test_jellium_init_rejects_bad_arguments_without_device(so_path):
     d = binding.Desc(binding.JELLIUM, binding.SOA, 0, 0, 4, 0.0)
     assert lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(d), P(dims), P(eps), P(v), P(g1), None,
                                  None) == binding.EINVAL                # v[0] != 0
-    d = binding.Desc(binding.JELLIUM, binding.TPP, 0, 0, 4, 0.0)
+    d = binding.Desc(binding.JELLIUM, binding.DSL, 0, 0, 4, 0.0)
     assert lib.g1g2_jellium_init(ctypes.byref(ctx), ctypes.byref(d), P(dims), P(eps), P(v0), P(g1), None,
                                  None) == binding.EUNSUPPORTED
     d = binding.Desc(binding.JELLIUM, binding.SOA, 0, 0, 4, 0.0)         # g1g2_init is not the entry

@@ -37,14 +37,15 @@ def three(g2):
 
 
 def _se(B, se):
-    return (B.GW, B.GW_EXCHANGE) if se == "gw_x" else ({"soa": B.SOA, "gw": B.GW}[se], 0)
+    return (B.GW, B.GW_EXCHANGE) if se == "gw_x" else ({"soa": B.SOA, "gw": B.GW, "tpp": B.TPP, "tph": B.TPH}[se], 0)
 
 
 @pytest.mark.parametrize("dims", [(5,), (3, 3), (2, 3, 2), (4, 4, 4)])
-@pytest.mark.parametrize("se", ["soa", "gw", "gw_x"])
+@pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph"])
 def test_jellium_rhs_parity(lib, dims, se):
     """One right-hand side at a random momentum-conserving state with the pair
-    symmetries, every element of dG1 and of the three G2 blocks."""
+    symmetries, every element of dG1 and of the three G2 blocks (the ladder
+    product's row and column tiles of 16 are ragged at every size here)."""
     from paper_2002_12717_amd import binding as B
     nb = int(np.prod(dims))
     r = rng(611, nb, len(se))
@@ -66,7 +67,9 @@ def test_jellium_rhs_parity(lib, dims, se):
 
 @pytest.mark.parametrize("dims,se,prec", [((3, 3), "soa", "fp64"), ((3, 3), "gw", "fp64"),
                                           ((4, 4, 2), "gw", "fp64"), ((4, 4, 2), "soa", "mixed"),
-                                          ((3, 3), "gw_x", "mixed"), ((4, 4, 4), "gw", "fp64")])
+                                          ((3, 3), "gw_x", "mixed"), ((4, 4, 4), "gw", "fp64"),
+                                          ((3, 3), "tpp", "fp64"), ((2, 3, 2), "tph", "fp64"),
+                                          ((4, 4, 2), "tpp", "mixed"), ((3, 3), "tph", "mixed")])
 def test_jellium_trajectory_parity(lib, dims, se, prec):
     """An interaction quench from the spin-polarized Fermi-Dirac state: G1, the
     three G2 blocks and E against the oracle's propagation."""
@@ -99,10 +102,11 @@ def test_jellium_trajectory_parity(lib, dims, se, prec):
         assert worst > 1e-12
 
 
-@pytest.mark.parametrize("se", ["soa", "gw"])
+@pytest.mark.parametrize("se", ["soa", "gw", "tpp", "tph"])
 def test_jellium_full_size_rhs(lib, se):
     """The benchmark grid (6 x 6 x 6 momenta, G2 of 3 x 216^3 elements) at a
-    random symmetric state: every element of one right-hand side."""
+    random symmetric state: every element of one right-hand side (the oracle
+    needs about 40 s for TPH here)."""
     from paper_2002_12717_amd import binding as B
     dims = (6, 6, 6)
     r = rng(612, len(se))
