@@ -41,8 +41,11 @@ PEAK_HBM = 8000.0          # GB/s
 TRAFFIC = {
     "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "0b1e2ffc0f8c"},
     "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "0b1e2ffc0f8c"},
-    "hub_stage/2d": {"bytes": 2.36e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "ac8fa635b98d"},
-    "hub_stage/2d/mixed": {"bytes": 1.63e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "ac8fa635b98d"},
+    "hub_stage/2d": {"bytes": 2.37e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
+    "hub_stage/2d/mixed": {"bytes": 1.75e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
+    "hub_stage/2d/tpp": {"bytes": 2.60e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
+    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "kernel": "jel_stage_kernel", "sha1": "2e7ebd346cdc"},
+    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "kernel": "jel_stage_kernel", "sha1": "2e7ebd346cdc"},
 }
 
 
@@ -435,8 +438,9 @@ def run_hubbard(args, torch, B, kind):
     out = base_line(args, 1e3 / ms_step, ms_step, "f64", config)
     stage_roof = {"kernel": "hub_stage", "bound": "hbm", "achieved": round(achieved, 2),
                   "peak": PEAK_HBM, "unit": "GB/s", "frac": round(achieved / PEAK_HBM, 4),
-                  # the counters were taken on the SOA instantiation
-                  "traffic": traffic("hub_stage/2d") if kind == "hubbard_2d" and se == "soa" else None,
+                  # the counters were taken on the SOA and TPP instantiations
+                  "traffic": (traffic("hub_stage/2d") if se == "soa" else traffic("hub_stage/2d/tpp")
+                              if se == "tpp" else None) if kind == "hubbard_2d" else None,
                   "kernel_ms_avg": round(tot_ms / cnt, 6),
                   "bytes_per_launch": bytes_per_launch, "launches": cnt}
     out.update({
@@ -494,7 +498,7 @@ def run_jellium(args, torch, B):
         q = B.Jellium(code, s.dims, s.eps, s.v, s.g1, stream=stream.cuda_stream,
                       precision=B.FP64 if prec == "fp64" else B.MIXED)
         traj = {0: (q.get_state(with_g2=False)[0], q.observables()["E_tot"])}
-        for n in range(50, s.nsteps + 1, 50):
+        for n in range(50, 0 if args.no_accuracy else s.nsteps + 1, 50):
             q.step(s.dt, 50)
             traj[n] = (q.get_state(with_g2=False)[0], q.observables()["E_tot"])
         q.close()
@@ -513,7 +517,8 @@ def run_jellium(args, torch, B):
     mbytes = (52.0 + extra) * n2      # binary32 stage copies: 40, 64, 64, 40 B
     mach = mbytes * mcnt / (mtot * 1e-3) / 1e9
     stage_roof = {"kernel": "jel_stage", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM,
-                  "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4), "traffic": None,
+                  "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4),
+                  "traffic": traffic("jel_stage/gw") if se == "gw" else None,
                   "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt}
     roof, lad_roof, mx_lad = stage_roof, None, None
     if ladder:
@@ -547,7 +552,8 @@ def run_jellium(args, torch, B):
                   "ms_per_step": round(mx_step, 6), "speedup_vs_fp64": round(ms_step / mx_step, 3),
                   "err_G1_vs_fp64": err["G1"], "err_E_vs_fp64": err["E"],
                   "roofline": {"kernel": "jel_stage", "achieved": round(mach, 2), "peak": PEAK_HBM,
-                               "unit": "GB/s", "frac": round(mach / PEAK_HBM, 4), "bytes_per_launch": mbytes},
+                               "unit": "GB/s", "frac": round(mach / PEAK_HBM, 4), "bytes_per_launch": mbytes,
+                               "traffic": traffic("jel_stage/gw/mixed") if se == "gw" else None},
                   "kernels": kernel_table(mx["prof"])},
     })
     if ladder:
