@@ -522,17 +522,20 @@ def run_jellium(args, torch, B):
                   "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt}
     roof, lad_roof, mx_lad = stage_roof, None, None
     if ladder:
-        # the ladder product: 3 nb^2 rows x nb x nb complex-by-real multiply-adds (4 flops)
-        lflops = 12.0 * float(nb) ** 4
+        # the ladder sums, a transform of each G2 row: the stage input read once
+        # and the sums written once, 32 B per element (binary64; 24 B when the
+        # stage input is binary32, three of the four stages of a mixed step)
+        lbytes = 32.0 * n2
         ltot, lcnt = f64["prof"]["jel_lad"]
-        lach = lflops * lcnt / (ltot * 1e-3) / 1e12
-        lad_roof = {"kernel": "jel_lad", "bound": "mfma", "achieved": round(lach, 3), "peak": PEAK_FP64_MFMA,
-                    "unit": "TFLOP/s", "frac": round(lach / PEAK_FP64_MFMA, 4), "traffic": None,
-                    "kernel_ms_avg": round(ltot / lcnt, 6), "flop_per_launch": lflops, "launches": lcnt}
+        lach = lbytes * lcnt / (ltot * 1e-3) / 1e9
+        lad_roof = {"kernel": "jel_lad", "bound": "hbm", "achieved": round(lach, 2), "peak": PEAK_HBM,
+                    "unit": "GB/s", "frac": round(lach / PEAK_HBM, 4), "traffic": None,
+                    "kernel_ms_avg": round(ltot / lcnt, 6), "bytes_per_launch": lbytes, "launches": lcnt}
         mlt, mlc = mx["prof"]["jel_lad"]
-        mx_lad = {"kernel": "jel_lad", "achieved": round(lflops * mlc / (mlt * 1e-3) / 1e12, 3),
-                  "peak": PEAK_FP64_MFMA, "unit": "TFLOP/s",
-                  "frac": round(lflops * mlc / (mlt * 1e-3) / 1e12 / PEAK_FP64_MFMA, 4)}
+        mlb = 26.0 * n2
+        mx_lad = {"kernel": "jel_lad", "achieved": round(mlb * mlc / (mlt * 1e-3) / 1e9, 2), "peak": PEAK_HBM,
+                  "unit": "GB/s", "frac": round(mlb * mlc / (mlt * 1e-3) / 1e9 / PEAK_HBM, 4),
+                  "bytes_per_launch": mlb}
         if ltot > tot:
             roof = lad_roof
     err = trajectory_error(mx["traj"], f64["traj"])

@@ -112,12 +112,12 @@ struct JelliumData {
     cd* sb[3] = {};          // [nb][nb] down-spin sums of the up-down block
     int parity = 0;          // buffer set holding the sums of the next stage input
     // T-matrix closures: the ladder sums of the stage input [3][nb]^3, the
-    // product's real operand [nb rounded up to 4][nbp] and the index table of
-    // S - K [nb][nb]; nbp = nb rounded up to 16
+    // transform of v over the grid divided by nb [nb], the twiddles of the
+    // three dimensions [Lx + Ly + Lz] and the index table of S - K [nb][nb]
     cd* lad = nullptr;
-    double* vmat = nullptr;
+    cd* vhat = nullptr;
+    cd* tw = nullptr;
     int* subt = nullptr;
-    int nbp = 0;
 };
 
 struct g1g2_ctx {

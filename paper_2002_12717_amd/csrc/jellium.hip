@@ -22,14 +22,18 @@
 // the up-down block feeds (a sum over its first momentum) are accumulated with
 // binary64 atomics.
 //
-// The T-matrix closures (eq:jellium-lambdapp, eq:jellium-lambdaph) add one
-// O(nb^4) product per stage, on the matrix cores before the stage pass:
+// The T-matrix closures (eq:jellium-lambdapp, eq:jellium-lambdaph) need the
+// ladder sums of the stage input before the stage pass:
 //   jel_lad (TPP): L[c][P][Pb][Q]  = sum_K G2[c][P][Pb][K] v_{K-Q}
 //   jel_lad (TPH): M[c][P][S][Pb]  = sum_K G2[c][P][K][S-K] v_{Pb-K}
-// (TPH sums along the anti-diagonals Pb + Q = S of a (Pb, Q) plane, which
-// makes it the same complex-by-real matrix product on gathered rows).  The
-// stage pass adds Lambda = -f L at the element and the partner's
-// -conj(Lambda_{P-Q, Pb+Q, -Q}), both read from that buffer.
+// (TPH sums along the anti-diagonals Pb + Q = S of a (Pb, Q) plane).  Both are
+// cyclic correlations or convolutions over the periodic grid, so per row they
+// are a discrete Fourier transform, a product with the transform of v and
+// the inverse transform, each transform taken one grid dimension at a time:
+// Lx + Ly + Lz multiply-adds per output instead of the nb of the direct sum
+// (O(nb^3 (Lx + Ly + Lz)) per stage against the O(nb^4) of Tab. I; the same
+// sums up to rounding).  The stage pass adds Lambda = -f L at the element and
+// the partner's -conj(Lambda_{P-Q, Pb+Q, -Q}), both read from that buffer.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -38,7 +42,6 @@
 #include <vector>
 
 #include "ctx.h"
-#include "mfma.h"
 
 namespace {
 
@@ -47,7 +50,6 @@ constexpr int JEL_MAX_NB = 1024; // momenta of the grid (the stage kernel stages
 constexpr int JEL_QB = 64;       // momenta Q per work-group (one per lane)
 constexpr int JEL_THREADS = 256; // prologue and observables
 constexpr int JEL_WAVES = 8;     // stage pass: wave w takes Pb = w, w + JEL_WAVES, ...
-constexpr int LAD_NT = 7;        // ladder product: column tiles of 16 per pass of a wave
 enum { LAD_NONE = 0, LAD_PP = 1, LAD_PH = 2 };
 
 struct JGrid {
@@ -347,74 +349,107 @@ __global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s)
 }
 
 struct LadArgs {
-    int nb, nbp;              // momenta, and nb rounded up to the 16-wide column tiles
+    int nb;                   // momenta
+    int len[3], stride[3];    // grid lengths and index strides (1, Lx, Lx Ly)
+    int toff[3];              // offsets of each dimension's twiddles
     const void* in2;          // stage input G2 [3][nb]^3
-    const double* vmat;       // [nkp][nbp] B[K][n]: TPP v_{K-n}, TPH v_{n-K} (zero padded)
+    const cd* vhat;           // [nb] the transform of v over nb: sum_m v_m e^{-2 pi i k.m/L} / nb
+    const cd* tw;             // e^{-2 pi i q / L_d}, q < L_d, for d = 0, 1, 2
     const int* subt;          // [nb][nb] index of S - K (TPH)
     cd* out;                  // [3][nb]^3
 };
 
-// The ladder sums as a complex-by-real matrix product on the matrix cores,
-// out[row][n] = sum_K A[row][K] B[K][n] over rows (c, P, X):
-//   TPP: A[row][K] = G2[c][P][X][K]          (X = Pb)
-//   TPH: A[row][K] = G2[c][P][K][X - K]      (X = S, the anti-diagonal)
-// A wave owns 16 rows and sweeps the columns in passes of LAD_NT tiles of 16,
-// with one binary64 16x16x4 product each for the real and the imaginary part
-// of A per tile and 4-deep step of K (K padded to a multiple of 4 with zero
-// rows of B).  B (at most 1024 x 1024 binary64 values, read by every wave)
-// stays in the L2 cache.
+constexpr int LAD_ROWS = 2;   // rows per work-group of the ladder transform
+
+// The ladder sums of LAD_ROWS rows per work-group, rows (c, P, X):
+//   TPP: g[K] = G2[c][P][X][K]      (X = Pb), out = F-[vhat F+[g]]
+//   TPH: h[K] = G2[c][P][K][X - K]  (X = S),  out = F+[vhat F-[h]]
+// with F+/- the transforms with e^{+/-2 pi i k.m/L} over the grid, each the
+// product of one-dimensional transforms along x, y and z.  Thread n owns
+// momentum n of every row: in a pass along d it sums the L_d elements of its
+// line of each row (read from LDS) times its twiddles, so its line offset and
+// twiddle index are computed once per pass.  The rows and a ping-pong copy
+// live in LDS.
 template <int KIND, typename TI>
-__global__ __launch_bounds__(256) void jel_lad_kernel(LadArgs s) {
-    const int nb = s.nb, nbp = s.nbp;
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+__global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
+    extern __shared__ cd lad_sh[];   // [2][LAD_ROWS][nb]
+    const int nb = s.nb, n = threadIdx.x;
+    cd* const buf0 = lad_sh;
+    cd* const buf1 = lad_sh + LAD_ROWS * nb;
+    const bool nok = n < nb;
     const long long nn = (long long)nb * nb, rows = 3 * nn;
-    const long long r0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (r0 >= rows) return;   // no barrier in this kernel
-    const long long row = r0 + li;
-    const bool rok = row < rows;
-    const long long rc = rok ? row : r0;
-    const int c = (int)(rc / nn);
-    const long long rem = rc - c * nn;
-    const int P = (int)(rem / nb), X = (int)(rem - (long long)P * nb);
-    const TI* __restrict__ in = static_cast<const TI*>(s.in2) + (size_t)c * nn * nb;
-    const size_t base = KIND == LAD_PP ? ((size_t)P * nb + X) * nb : (size_t)P * nb * nb;
-    for (int j0 = 0; j0 < nbp; j0 += 16 * LAD_NT) {
-        v4d ar[LAD_NT], ai[LAD_NT];
+    const long long r0 = (long long)blockIdx.x * LAD_ROWS;
+    const TI* __restrict__ in = static_cast<const TI*>(s.in2);
 #pragma unroll
-        for (int t = 0; t < LAD_NT; ++t) ar[t] = ai[t] = MF<double>::zero();
-        for (int k0 = 0; k0 < nb; k0 += 4) {
-            const int K = k0 + lk;
-            cd a = cmk(0.0, 0.0);
-            if (rok && K < nb) {
-                const size_t idx = KIND == LAD_PP ? base + K : base + (size_t)K * nb + s.subt[X * nb + K];
-                a = ld_c(in, (long long)idx);
-            }
-            const double* __restrict__ brow = s.vmat + (size_t)K * nbp + j0 + li;
-#pragma unroll
-            for (int t = 0; t < LAD_NT; ++t) {
-                const int n = j0 + 16 * t + li;
-                const double b = n < nbp ? brow[16 * t] : 0.0;
-                ar[t] = MF<double>::mac(a.x, b, ar[t]);
-                ai[t] = MF<double>::mac(a.y, b, ai[t]);
-            }
+    for (int r = 0; r < LAD_ROWS; ++r) {
+        const long long row = r0 + r;
+        cd x = cmk(0.0, 0.0);
+        if (nok && row < rows) {
+            const int c = (int)(row / nn);
+            const int rem = (int)(row - c * nn), P = rem / nb, X = rem - P * nb;
+            const size_t idx = (size_t)c * nn * nb +
+                               (KIND == LAD_PP ? ((size_t)P * nb + X) * nb + n
+                                               : ((size_t)P * nb + n) * nb + s.subt[X * nb + n]);
+            x = ld_c(in, (long long)idx);
         }
-#pragma unroll
-        for (int t = 0; t < LAD_NT; ++t) {
-            const int n = j0 + 16 * t + tile_col();
-            if (n >= nb) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const long long ro = r0 + tile_row<double>(r);
-                if (ro < rows) s.out[ro * nb + n] = cmk(ar[t][r], ai[t][r]);
-            }
-        }
+        if (nok) buf0[r * nb + n] = x;
     }
+    __syncthreads();
+    bool cur = false;   // false: data in buf0
+    auto passes = [&](bool plus) {
+        for (int d = 0; d < 3; ++d) {
+            const int L = s.len[d], sd = s.stride[d];
+            if (L == 1) continue;
+            const cd* __restrict__ src = cur ? buf1 : buf0;
+            cd* __restrict__ dst = cur ? buf0 : buf1;
+            if (nok) {
+                const cd* __restrict__ t = s.tw + s.toff[d];
+                const int kd = (n / sd) % L, base = n - kd * sd;
+                cd acc[LAD_ROWS];
+#pragma unroll
+                for (int r = 0; r < LAD_ROWS; ++r) acc[r] = cmk(0.0, 0.0);
+                int q = 0;
+                for (int m = 0; m < L; ++m) {
+                    const cd w = t[q];
+                    const double wi = plus ? -w.y : w.y;
+#pragma unroll
+                    for (int r = 0; r < LAD_ROWS; ++r) {
+                        const cd x = src[r * nb + base + m * sd];
+                        acc[r].x = fma(x.x, w.x, fma(-x.y, wi, acc[r].x));
+                        acc[r].y = fma(x.x, wi, fma(x.y, w.x, acc[r].y));
+                    }
+                    q += kd;
+                    if (q >= L) q -= L;
+                }
+#pragma unroll
+                for (int r = 0; r < LAD_ROWS; ++r) dst[r * nb + n] = acc[r];
+            }
+            __syncthreads();
+            cur = !cur;
+        }
+    };
+    passes(KIND == LAD_PP);
+    if (nok) {
+        cd* b = cur ? buf1 : buf0;
+        const cd vh = s.vhat[n];
+#pragma unroll
+        for (int r = 0; r < LAD_ROWS; ++r) b[r * nb + n] = cmul(b[r * nb + n], vh);
+    }
+    __syncthreads();
+    passes(KIND != LAD_PP);
+    const cd* res = cur ? buf1 : buf0;
+    if (nok)
+#pragma unroll
+        for (int r = 0; r < LAD_ROWS; ++r)
+            if (r0 + r < rows) s.out[(r0 + r) * nb + n] = res[r * nb + n];
 }
 
 int lad_blocks(const g1g2_ctx* c) {
     const long long rows = 3LL * c->jel.nb * c->jel.nb;
-    return (int)((rows + 63) / 64);
+    return (int)((rows + LAD_ROWS - 1) / LAD_ROWS);
 }
+
+int lad_threads(const g1g2_ctx* c) { return (c->jel.nb + 63) / 64 * 64; }
 
 // Observables from G1 and S of the state (one work-group): N^s, E_kin = sum eps n,
 // the Fock energy -1/2 sum_s sum v[p - pb] n^s_p n^s_pb and E_corr = -1/2 Re sum v_Q S.
@@ -496,14 +531,23 @@ void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
     using TI = typename std::conditional<MIXED && (MODE == RK_MID || MODE == RK_LAST), float2, cd>::type;
     using TO = typename std::conditional<MIXED && (MODE == RK_FIRST || MODE == RK_MID), float2, cd>::type;
     if constexpr (LAD != LAD_NONE) {   // the ladder sums of the stage input first
+        const JelliumData& J = c->jel;
         LadArgs la{};
-        la.nb = c->jel.nb;
-        la.nbp = c->jel.nbp;
+        la.nb = J.nb;
+        for (int d = 0; d < 3; ++d) la.len[d] = J.dims[d];
+        la.stride[0] = 1;
+        la.stride[1] = J.dims[0];
+        la.stride[2] = J.dims[0] * J.dims[1];
+        la.toff[0] = 0;
+        la.toff[1] = J.dims[0];
+        la.toff[2] = J.dims[0] + J.dims[1];
         la.in2 = s.in2;
-        la.vmat = c->jel.vmat;
-        la.subt = c->jel.subt;
-        la.out = c->jel.lad;
-        hipLaunchKernelGGL((jel_lad_kernel<LAD, TI>), dim3(lad_blocks(c)), dim3(256), 0, c->stream, la);
+        la.vhat = J.vhat;
+        la.tw = J.tw;
+        la.subt = J.subt;
+        la.out = J.lad;
+        hipLaunchKernelGGL((jel_lad_kernel<LAD, TI>), dim3(lad_blocks(c)), dim3(lad_threads(c)),
+                           2 * LAD_ROWS * J.nb * sizeof(cd), c->stream, la);
         prof_mark(c, "jel_lad");
     }
     hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false, LAD>), dim3(stage_blocks(c)),
@@ -584,29 +628,41 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
     const size_t nb = J.nb, nn = nb * nb;
     const int se = c->d.selfenergy;
     if (se == G1G2_TPP || se == G1G2_TPH) {
-        // the ladder product's operands: B[K][n] = v_{K-n} (TPP) or v_{n-K}
-        // (TPH), zero padded to [nb rounded up to 4][nb rounded up to 16], the
-        // index table of S - K (TPH), and the [3][nb]^3 buffer of the sums
-        J.nbp = (J.nb + 15) / 16 * 16;
-        const int nkp = (J.nb + 3) / 4 * 4;
-        auto sub = [&](int a, int b) {   // index of momentum a - b on the grid
-            const int ax = a % dims[0], ay = (a / dims[0]) % dims[1], az = a / (dims[0] * dims[1]);
-            const int bx = b % dims[0], by = (b / dims[0]) % dims[1], bz = b / (dims[0] * dims[1]);
-            const int x = (ax - bx + dims[0]) % dims[0], y = (ay - by + dims[1]) % dims[1];
-            const int z = (az - bz + dims[2]) % dims[2];
-            return x + dims[0] * (y + dims[1] * z);
+        // the ladder sums' operands: the transform of v over the grid divided
+        // by nb, the twiddles of each dimension, the index table of S - K
+        // (TPH) and the [3][nb]^3 buffer of the sums
+        const double tpi = 6.283185307179586476925286766559;
+        auto comp = [&](int n, int d) {
+            return d == 0 ? n % dims[0] : (d == 1 ? (n / dims[0]) % dims[1] : n / (dims[0] * dims[1]));
         };
-        std::vector<double> vm((size_t)nkp * J.nbp, 0.0);
-        std::vector<int> st(nn);
-        for (int k = 0; k < J.nb; ++k)
-            for (int n = 0; n < J.nb; ++n) {
-                vm[(size_t)k * J.nbp + n] = se == G1G2_TPP ? v[sub(k, n)] : v[sub(n, k)];
-                st[(size_t)k * nb + n] = sub(k, n);
+        std::vector<cd> vh(nb), tw(dims[0] + dims[1] + dims[2]);
+        for (size_t k = 0; k < nb; ++k) {
+            double re = 0.0, im = 0.0;
+            for (size_t m = 0; m < nb; ++m) {
+                double ph = 0.0;
+                for (int d = 0; d < 3; ++d) ph += (double)((comp((int)k, d) * comp((int)m, d)) % dims[d]) / dims[d];
+                re += v[m] * std::cos(tpi * ph);
+                im -= v[m] * std::sin(tpi * ph);
             }
-        HIP_OK(c, hipMalloc(&J.vmat, vm.size() * sizeof(double)));
+            vh[k] = cmk(re / nb, im / nb);
+        }
+        for (int d = 0, o = 0; d < 3; o += dims[d], ++d)
+            for (int q = 0; q < dims[d]; ++q)
+                tw[o + q] = cmk(std::cos(tpi * q / dims[d]), -std::sin(tpi * q / dims[d]));
+        std::vector<int> st(nn);
+        for (int a = 0; a < J.nb; ++a)
+            for (int b = 0; b < J.nb; ++b) {
+                int x = (comp(a, 0) - comp(b, 0) + dims[0]) % dims[0];
+                int y = (comp(a, 1) - comp(b, 1) + dims[1]) % dims[1];
+                int z = (comp(a, 2) - comp(b, 2) + dims[2]) % dims[2];
+                st[(size_t)a * nb + b] = x + dims[0] * (y + dims[1] * z);
+            }
+        HIP_OK(c, hipMalloc(&J.vhat, vh.size() * sizeof(cd)));
+        HIP_OK(c, hipMalloc(&J.tw, tw.size() * sizeof(cd)));
         HIP_OK(c, hipMalloc(&J.subt, st.size() * sizeof(int)));
         HIP_OK(c, hipMalloc(&J.lad, 3 * nn * nb * sizeof(cd)));
-        HIP_OK(c, hipMemcpyAsync(J.vmat, vm.data(), vm.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(J.vhat, vh.data(), vh.size() * sizeof(cd), hipMemcpyHostToDevice, c->stream));
+        HIP_OK(c, hipMemcpyAsync(J.tw, tw.data(), tw.size() * sizeof(cd), hipMemcpyHostToDevice, c->stream));
         HIP_OK(c, hipMemcpyAsync(J.subt, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
         HIP_OK(c, hipStreamSynchronize(c->stream));
     }
@@ -628,7 +684,7 @@ g1g2_status jel_setup(g1g2_ctx* c, const int* dims, const double* eps, const dou
 void jel_free(g1g2_ctx* c) {
     JelliumData& J = c->jel;
     for (void* p : {(void*)J.eps, (void*)J.v, (void*)J.hhf, (void*)J.stot, (void*)J.skew, (void*)J.lad,
-                    (void*)J.vmat, (void*)J.subt})
+                    (void*)J.vhat, (void*)J.tw, (void*)J.subt})
         if (p) (void)hipFree(p);
     for (int b = 0; b < 3; ++b) {
         if (J.sc[b]) (void)hipFree(J.sc[b]);
