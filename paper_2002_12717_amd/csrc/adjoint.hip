@@ -184,7 +184,10 @@ __global__ __launch_bounds__(256) void adj_slice_red_kernel(AdjArgs s) {
             const cd B = cscale(cmul_i(g), gs);
             const cd cav = cconj(ld_a(s, e));
             const cd xik = X[i * ns + k], xjk = X[j * ns + k], yjk = Y[j * ns + k];
-            const cd xlk = X[l * ns + k], ykl = Y[k * ns + l];
+            // X_lk = -conj(X_kl) (G^< is anti-Hermitian, as the forward stage reads it): a row
+            // read instead of a column gather
+            const cd xkl = X[k * ns + l], ykl = Y[k * ns + l];
+            const cd xlk = cmk(-xkl.x, xkl.y);
             const double dd = (double)(i == j) - (double)(k == l);
             // kind 0
             cd w0 = cscale(cconj(yjl), U * dd);
