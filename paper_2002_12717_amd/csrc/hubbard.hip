@@ -580,6 +580,14 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 // floor(SLICE_ELEMS / ns^2) long.
 constexpr int SLICE_THREADS = 512;
 constexpr int SLICE_THREADS_BIG = 1024;
+// ns = 64 row form: two work-groups per compute unit (64 KB of staged slice
+// each) of 12 waves (80 registers per thread), or of 16 waves for TPH (64
+// registers).  Measured per stage on the 8x8 cluster, 12 against 16 waves:
+// SOA 0.332 / 0.366 ms (16 waves spill in the middle stage), TPP 0.358 /
+// 0.367, GW 1.090 / 1.093, mixed SOA, TPP and GW 3-11% faster; TPH 0.378 /
+// 0.373 and mixed TPH 3% slower.
+__host__ __device__ constexpr int row64_waves(int se, bool) { return se == SE_TPH ? 8 : 6; }
+__host__ __device__ constexpr int row64_threads(int se, bool mixed) { return 128 * row64_waves(se, mixed); }
 constexpr int SLICE_ELEMS = 4096;
 // TPP: the diagonal entries A_ppij of the staged slices (p < ns), kept in LDS;
 // a TPP item holds at most SLICE_DIAG / ns slices
@@ -602,7 +610,7 @@ __device__ __forceinline__ int slice_div(int n, unsigned mg) {
 }
 
 template <int MODE, int SE, bool MIXED, bool REALH, bool ROW64>
-__global__ __launch_bounds__(SLICE_THREADS_BIG) __attribute__((amdgpu_waves_per_eu(ROW64 ? 8 : 1))) void hub_slice_kernel(StageArgs s) {
+__global__ __launch_bounds__(SLICE_THREADS_BIG) __attribute__((amdgpu_waves_per_eu(ROW64 ? row64_waves(SE, MIXED) : 1))) void hub_slice_kernel(StageArgs s) {
     constexpr bool TPP = has_pp(SE), TPH = has_ph(SE), GW = has_pol(SE);
     using TI = typename StageTypes<MODE, MIXED>::In;
     using TO = typename StageTypes<MODE, MIXED>::Out;
@@ -1079,7 +1087,8 @@ void launch_stage_t(g1g2_ctx* c, const StageArgs& s) {
     }
     if (c->hub.slices) {
         const size_t lds = (size_t)c->hub.slice_elems * sizeof(cd);
-        const int nthr = c->hub.ncl == 1 && c->hub.slice_elems == SLICE_ELEMS ? SLICE_THREADS_BIG : SLICE_THREADS;
+        const int nthr = c->hub.row64 ? row64_threads(SE, MIXED)
+                         : c->hub.ncl == 1 && c->hub.slice_elems == SLICE_ELEMS ? SLICE_THREADS_BIG : SLICE_THREADS;
         if (SE != SE_DSL && c->hub.realhop && c->hub.row64)
             hipLaunchKernelGGL((hub_slice_kernel<MODE, SE, MIXED, true, SE != SE_DSL>), dim3(c->hub.nwork),
                                dim3(nthr), lds, c->stream, s);
@@ -1456,13 +1465,11 @@ g1g2_status hub_setup(g1g2_ctx* c, int ncl, const int* nsv, const double* Uv, co
     H.realhop = realhop;
     // every cluster has ns = 64: one (i, j) slice per item, a wave per row.
     // Measured per stage on the 8x8 cluster against the general slice form:
-    // TPP 0.367 / 0.399 ms, TPH 0.373 / 0.412, GW 1.09 / 1.15, and 9-15%
-    // faster for every closure in mixed precision; binary64 SOA, whose middle
-    // stage spills at the 64 registers that two work-groups per compute unit
-    // allow, 0.366 / 0.353, keeps the general form, and DSL (too much LDS for
-    // two work-groups) too.
-    H.row64 = slicek && std::all_of(nsv, nsv + ncl, [](int n) { return n == 64; }) && se != SE_DSL &&
-              !(se == SE_SOA && c->d.precision != G1G2_MIXED);
+    // SOA 0.333 / 0.354 ms, TPP 0.367 / 0.399, TPH 0.373 / 0.412, GW 1.09 /
+    // 1.15, and 9-15% faster for every closure in mixed precision.  DSL needs
+    // too much LDS for two work-groups per compute unit and keeps the general
+    // form.
+    H.row64 = slicek && std::all_of(nsv, nsv + ncl, [](int n) { return n == 64; }) && se != SE_DSL;
     H.ndwork = (int)dwork.size();
     H.slice_elems = slice_elems;
     H.diag_elems = n_diag(se) > 0 ? n_diag(se) * doff : 0;
