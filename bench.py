@@ -36,43 +36,36 @@ PEAK_HBM = 8000.0          # GB/s
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration; profiles/hbm_traffic_counters.md).  A figure is only
-# reported while the kernel's source text still has the hash it had when the
-# counters were taken (kernel_hash below: the text of the kernel function).
+# reported while the kernel's source file still has the hash it had when the
+# counters were taken (source_hash below: the whole file, so that a change of
+# the kernel or of how it is launched voids it).
 TRAFFIC = {
-    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "0b1e2ffc0f8c"},
-    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "kernel": "gen_main_kernel", "sha1": "0b1e2ffc0f8c"},
-    "hub_stage/2d": {"bytes": 2.37e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
-    "hub_stage/2d/mixed": {"bytes": 1.75e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
-    "hub_stage/2d/tpp": {"bytes": 2.60e9, "src": "hubbard.hip", "kernel": "hub_slice_kernel", "sha1": "3a42c4dc62dc"},
-    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "kernel": "jel_stage_kernel", "sha1": "2e7ebd346cdc"},
-    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "kernel": "jel_stage_kernel", "sha1": "2e7ebd346cdc"},
+    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "sha1": "da9e0b147f78"},
+    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "sha1": "da9e0b147f78"},
+    "gen_gemm/f64": {"bytes": 6.683e9, "src": "general.hip", "sha1": "da9e0b147f78"},
+    "gen_gemm/f32": {"bytes": 3.446e9, "src": "general.hip", "sha1": "da9e0b147f78"},
+    "hub_stage/2d": {"bytes": 2.385e9, "src": "hubbard.hip", "sha1": "a4316c3858a0"},
+    "hub_stage/2d/mixed": {"bytes": 1.634e9, "src": "hubbard.hip", "sha1": "a4316c3858a0"},
+    "hub_stage/2d/tpp": {"bytes": 2.443e9, "src": "hubbard.hip", "sha1": "a4316c3858a0"},
+    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "sha1": "bd2b7db3a376"},
+    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "sha1": "bd2b7db3a376"},
+    "jel_stage/tpp": {"bytes": 4.651e9, "src": "jellium.hip", "sha1": "bd2b7db3a376"},
+    "jel_lad/tpp": {"bytes": 0.968e9, "src": "jellium.hip", "sha1": "bd2b7db3a376"},
 }
 
 
-def kernel_hash(src: str, kernel: str) -> str:
-    """sha1 (first 12 hex digits) of the text of a kernel function: from its
-    name to the brace that closes its body."""
+def source_hash(src: str) -> str:
+    """sha1 (first 12 hex digits) of a kernel source file of the library."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2002_12717_amd", "csrc", src)) as f:
-        text = f.read()
-    a = text.index(kernel + "(")
-    b = text.index("{", a)
-    depth = 0
-    for q in range(b, len(text)):
-        if text[q] == "{":
-            depth += 1
-        elif text[q] == "}":
-            depth -= 1
-            if depth == 0:
-                return hashlib.sha1(text[a:q + 1].encode()).hexdigest()[:12]
-    raise ValueError(kernel)
+    with open(os.path.join(ROOT, "paper_2002_12717_amd", "csrc", src), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
 def traffic(key):
     t = TRAFFIC.get(key)
     if t is None:
         return None
-    return t["bytes"] if kernel_hash(t["src"], t["kernel"]) == t["sha1"] else None
+    return t["bytes"] if source_hash(t["src"]) == t["sha1"] else None
 
 
 SE_CODES = {"soa": lambda B: B.SOA, "gw": lambda B: B.GW, "tpp": lambda B: B.TPP, "tph": lambda B: B.TPH,
@@ -518,7 +511,7 @@ def run_jellium(args, torch, B):
     mach = mbytes * mcnt / (mtot * 1e-3) / 1e9
     stage_roof = {"kernel": "jel_stage", "bound": "hbm", "achieved": round(ach, 2), "peak": PEAK_HBM,
                   "unit": "GB/s", "frac": round(ach / PEAK_HBM, 4),
-                  "traffic": traffic("jel_stage/gw") if se == "gw" else None,
+                  "traffic": traffic("jel_stage/gw") if se == "gw" else traffic("jel_stage/tpp") if se == "tpp" else None,
                   "kernel_ms_avg": round(tot / cnt, 6), "bytes_per_launch": bytes_launch, "launches": cnt}
     roof, lad_roof, mx_lad = stage_roof, None, None
     if ladder:
@@ -529,7 +522,8 @@ def run_jellium(args, torch, B):
         ltot, lcnt = f64["prof"]["jel_lad"]
         lach = lbytes * lcnt / (ltot * 1e-3) / 1e9
         lad_roof = {"kernel": "jel_lad", "bound": "hbm", "achieved": round(lach, 2), "peak": PEAK_HBM,
-                    "unit": "GB/s", "frac": round(lach / PEAK_HBM, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(lach / PEAK_HBM, 4),
+                    "traffic": traffic("jel_lad/tpp") if se == "tpp" else None,
                     "kernel_ms_avg": round(ltot / lcnt, 6), "bytes_per_launch": lbytes, "launches": lcnt}
         mlt, mlc = mx["prof"]["jel_lad"]
         mlb = 26.0 * n2
