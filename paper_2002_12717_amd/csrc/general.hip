@@ -739,19 +739,24 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
 //   1 (TPP): D[(i,j)][(k,l)] += C[(i,j)][(k,l)]               (D in storage S)
 //   2 (TPH): D[(i,j)][(k,l)] += C[(i,l)][(j,k)]
 template <typename T, typename S, int OUT>
-__global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
                                                       void* __restrict__ dst, int n, int nbp) {
     constexpr int KS = 16;                    // depth of one staged K slice
     constexpr int PER = 64 * KS / 256;          // elements of A (and of B) per thread and slice
-    __shared__ T a_re[64][KS + 1], a_im[64][KS + 1], b_re[KS][65], b_im[KS][65];
+    // three real products per complex multiply-add instead of four,
+    //   Re = Ar Br - Ai Bi,  Im = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi,
+    // with the operand sums formed once when a slice is staged
+    __shared__ T a_re[64][KS + 1], a_im[64][KS + 1], a_s[64][KS + 1];
+    __shared__ T b_re[KS][65], b_im[KS][65], b_s[KS][65];
     const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
     const int wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    CAcc<T> acc[2][2];
     double accd[2][2][2][4];
+    typename MF<T>::acc p1[2][2], p2[2][2], p3[2][2];   // Ar Br, Ai Bi, (Ar + Ai)(Br + Bi)
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
-            acc[a][b].clear();
+            p1[a][b] = p2[a][b] = p3[a][b] = MF<T>::zero();
             for (int r4 = 0; r4 < 4; ++r4) accd[a][b][0][r4] = accd[a][b][1][r4] = 0.0;
         }
     // the next K slice is loaded into registers while the current one runs
@@ -773,33 +778,50 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
             a_im[idx / KS][idx % KS] = pa_im[q];
             b_re[idx / 64][idx % 64] = pb_re[q];
             b_im[idx / 64][idx % 64] = pb_im[q];
+            a_s[idx / KS][idx % KS] = pa_re[q] + pa_im[q];
+            b_s[idx / 64][idx % 64] = pb_re[q] + pb_im[q];
         }
         __syncthreads();
         if (k0 + KS < n) fetch(k0 + KS);
+        {
+            const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+            for (int k4 = 0; k4 < KS; k4 += 4) {
+                T ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                cgemm_tile<T, KS>(
-                    acc[a][b],
-                    [&](int i, int k, T& r, T& m) {
-                        r = a_re[i][k];
-                        m = a_im[i][k];
-                    },
-                    [&](int k, int j, T& r, T& m) {
-                        r = b_re[k][j];
-                        m = b_im[k][j];
-                    },
-                    wm + a * 16, wn + b * 16);
+                for (int a = 0; a < 2; ++a) {
+                    const int i = wm + a * 16 + li;
+                    ar[a] = a_re[i][k4 + lk];
+                    ai[a] = a_im[i][k4 + lk];
+                    as[a] = a_s[i][k4 + lk];
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int j = wn + b * 16 + li;
+                    br[b] = b_re[k4 + lk][j];
+                    bi[b] = b_im[k4 + lk][j];
+                    bs[b] = b_s[k4 + lk][j];
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        p1[a][b] = MF<T>::mac(ar[a], br[b], p1[a][b]);
+                        p2[a][b] = MF<T>::mac(ai[a], bi[b], p2[a][b]);
+                        p3[a][b] = MF<T>::mac(as[a], bs[b], p3[a][b]);
+                    }
+            }
+        }
         __syncthreads();
         if (sizeof(T) == 4 && ((k0 + KS) % 64 == 0 || k0 + KS >= n)) {
             for (int a = 0; a < 2; ++a)
                 for (int b = 0; b < 2; ++b) {
                     for (int r4 = 0; r4 < 4; ++r4) {
-                        accd[a][b][0][r4] += (double)acc[a][b].re(r4);
-                        accd[a][b][1][r4] += (double)acc[a][b].im(r4);
+                        const double d1 = p1[a][b][r4], d2 = p2[a][b][r4], d3 = p3[a][b][r4];
+                        accd[a][b][0][r4] += d1 - d2;
+                        accd[a][b][1][r4] += d3 - d1 - d2;
                     }
-                    acc[a][b].clear();
+                    p1[a][b] = p2[a][b] = p3[a][b] = MF<T>::zero();
                 }
         }
     }
@@ -809,8 +831,9 @@ __global__ __launch_bounds__(256) void gen_gemm_kernel(const S* __restrict__ A, 
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int row = bm + wm + a * 16 + tile_row<T>(r4);
                 const int col = bn + wn + b * 16 + tile_col();
-                double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)acc[a][b].re(r4);
-                double vi = sizeof(T) == 4 ? accd[a][b][1][r4] : (double)acc[a][b].im(r4);
+                const double vr = sizeof(T) == 4 ? accd[a][b][0][r4] : (double)(p1[a][b][r4] - p2[a][b][r4]);
+                const double vi = sizeof(T) == 4 ? accd[a][b][1][r4]
+                                                 : (double)(p3[a][b][r4] - p1[a][b][r4] - p2[a][b][r4]);
                 if (OUT == 0) {
                     const int i = row / nbp, k = row % nbp, j = col / nbp, l = col % nbp;
                     ((cd*)dst)[(((size_t)i * nbp + j) * nbp + k) * nbp + l] = make_double2(vr, vi);
