@@ -566,13 +566,13 @@ __global__ __launch_bounds__(256) void hub_row_kernel(StageArgs s) {
 // Slice version of the stage (every selfenergy; every cluster with ns <= 64 and
 // at most Z_MAX_ROW neighbours per site).  A work-group of SLICE_THREADS threads
 // (SLICE_THREADS_BIG for one cluster in items of SLICE_ELEMS elements: twice the
-// waves per compute unit for the same LDS; measured on the 8x8 cluster, 0.353
-// against 0.365 ms per launch, while the ragged batch, whose items are
-// shorter, stays faster with SLICE_THREADS) stages up to floor(SLICE_ELEMS /
-// ns^2) consecutive (i, j) slices A[i][j][:][:] of one channel of the stage
-// input in LDS with coalesced loads and then gives one element to each thread
-// (m = tid, tid + blockDim, ... over the staged elements), so the lanes are
-// filled whatever ns is.  The k- and
+// waves per compute unit for the same LDS, while the ragged batch, whose items
+// are shorter, stays faster with SLICE_THREADS; row64_threads for the ns = 64
+// row form below) stages up to floor(SLICE_ELEMS / ns^2) consecutive (i, j)
+// slices A[i][j][:][:] of one channel of the stage input in LDS with coalesced
+// loads and then gives one element to each thread (m = tid, tid + blockDim,
+// ... over the staged elements), so the lanes are filled whatever ns is.  The
+// k- and
 // l-neighbours of the commutator lie in the same slice and are read from LDS;
 // the i- and j-neighbours, the ladder's diagonal slices and the Runge-Kutta
 // registers come from global memory.  A work item is a range [start, end) of
