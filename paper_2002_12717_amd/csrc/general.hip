@@ -747,11 +747,15 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
     // three real products per complex multiply-add instead of four,
     //   Re = Ar Br - Ai Bi,  Im = (Ar + Ai)(Br + Bi) - Ar Br - Ai Bi;
     // the operand sums are formed from the values read for the first two
-    // products (one add per operand and MFMA step) rather than staged in LDS:
-    // 34 KB of LDS per work-group instead of 51 KB, a third fewer LDS writes,
-    // 6.42 instead of 6.85 ms per Nb = 64 launch
-    __shared__ T a_re[64][KS + 1], a_im[64][KS + 1];
-    __shared__ T b_re[KS][65], b_im[KS][65];
+    // products (one add per operand and MFMA step) rather than staged in LDS.
+    // The slices are kept as interleaved complex values, so an operand pair is
+    // one 16-byte (binary64) or 8-byte LDS access.  Measured per Nb = 64
+    // launch in binary64: split re/im arrays with staged sums (51 KB) 6.85 ms,
+    // without the sums (34 KB) 6.42 ms, interleaved (34 KB) 6.27 ms; a 32-deep
+    // slice or a second LDS buffer was slower
+    typedef typename std::conditional<sizeof(T) == 8, double2, float2>::type CT;
+    __shared__ CT a_c[64][KS + 1];
+    __shared__ CT b_c[KS][65];
     const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
     const int wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -777,10 +781,8 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = threadIdx.x + q * 256;
-            a_re[idx / KS][idx % KS] = pa_re[q];
-            a_im[idx / KS][idx % KS] = pa_im[q];
-            b_re[idx / 64][idx % 64] = pb_re[q];
-            b_im[idx / 64][idx % 64] = pb_im[q];
+            a_c[idx / KS][idx % KS] = CT{pa_re[q], pa_im[q]};
+            b_c[idx / 64][idx % 64] = CT{pb_re[q], pb_im[q]};
         }
         __syncthreads();
         if (k0 + KS < n) fetch(k0 + KS);
@@ -792,15 +794,17 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
                     const int i = wm + a * 16 + li;
-                    ar[a] = a_re[i][k4 + lk];
-                    ai[a] = a_im[i][k4 + lk];
+                    const CT v = a_c[i][k4 + lk];
+                    ar[a] = v.x;
+                    ai[a] = v.y;
                     as[a] = ar[a] + ai[a];
                 }
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     const int j = wn + b * 16 + li;
-                    br[b] = b_re[k4 + lk][j];
-                    bi[b] = b_im[k4 + lk][j];
+                    const CT v = b_c[k4 + lk][j];
+                    br[b] = v.x;
+                    bi[b] = v.y;
                     bs[b] = br[b] + bi[b];
                 }
 #pragma unroll
