@@ -150,20 +150,114 @@ __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
 // --------------------------------------------------------------------------- K2
 // Right sandwich on row blocks of W: Vt[k][l][p][q] = (G<^T W_pq G<)[k][l].
 // Work-groups nvt.. of the launch compute the rows of h^HF (K1).
+// Nb = 64 takes eight waves of two tiles (the other sizes one wave per tile row).
+template <int NB>
+__host__ __device__ constexpr int vt_threads() { return NB == 64 ? 512 : Shape<NB>::THREADS; }
+
 template <typename T, typename S, int NB>
-__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_vt_kernel(const S* __restrict__ wrows,
-                                                                   const cd* __restrict__ gl,
-                                                                   S* __restrict__ vt, int nvt,
-                                                                   HfArgs hf) {
+__global__ __launch_bounds__(vt_threads<NB>()) void gen_vt_kernel(const S* __restrict__ wrows,
+                                                                 const cd* __restrict__ gl,
+                                                                 S* __restrict__ vt, int nvt,
+                                                                 HfArgs hf) {
     typedef Shape<NB> SH;
     constexpr int LD = SH::LD;
     if ((int)blockIdx.x >= nvt) {
-        hf_row<SH::THREADS>(hf, blockIdx.x - nvt);
+        hf_row<vt_threads<NB>()>(hf, blockIdx.x - nvt);
         return;
     }
     __shared__ T w_re[NB * LD], w_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
     const int wave = threadIdx.x >> 6;
     const int b0 = xcd_block(blockIdx.x, nvt);
+    if constexpr (NB == 64) {
+        // Wave w computes the first product's tiles (o, 2h), (o, 2h + 1) and the
+        // second product's tiles (2h, o), (2h + 1, o), with o = w / 2, h = w % 2.
+        // The G^< operand of both is then the same per lane,
+        //   first  A[i][k] = G^<_(k, 16 o + i),  second B[k][j] = G^<_(k, 16 o + j),
+        // and is held in registers for the whole launch; W and Q come from LDS,
+        // and the next W block is loaded into registers during the products.
+        // Each tile's k-steps run in the order of cgemm_tile, so the results
+        // equal those of the general path bit for bit.
+        constexpr int TH = vt_threads<NB>(), PER = NB * NB / TH;
+        const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+        const int o = wave >> 1, h = wave & 1;
+        T g_re[NB / 4], g_im[NB / 4];
+#pragma unroll
+        for (int s4 = 0; s4 < NB / 4; ++s4) ldc(gl + (4 * s4 + lk) * NB + o * 16 + li, g_re[s4], g_im[s4]);
+        T pw_re[PER], pw_im[PER];
+        auto fetch = [&](int blk) {
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                ldc(wrows + (size_t)blk * NB * NB + threadIdx.x + q * TH, pw_re[q], pw_im[q]);
+        };
+        auto put = [&]() {
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int idx = threadIdx.x + q * TH, r = idx / NB, cc = idx % NB;
+                w_re[r * LD + cc] = pw_re[q];
+                w_im[r * LD + cc] = pw_im[q];
+            }
+        };
+        if (b0 < NB * NB) {
+            fetch(b0);
+            put();
+        }
+        __syncthreads();
+        for (int blk = b0; blk < NB * NB; blk += nvt) {
+            const int nxt = blk + nvt;
+            if (nxt < NB * NB) fetch(nxt);
+            CAcc<T> acc[2];
+            acc[0].clear();
+            acc[1].clear();
+#pragma unroll
+            for (int s4 = 0; s4 < NB / 4; ++s4) {
+                const int k = 4 * s4 + lk;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int j = (2 * h + t) * 16 + li;
+                    const T br = w_re[k * LD + j], bi = w_im[k * LD + j];
+                    acc[t].vr = MF<T>::mac(g_re[s4], br, acc[t].vr);
+                    acc[t].vr = MF<T>::mac(-g_im[s4], bi, acc[t].vr);
+                    acc[t].vi = MF<T>::mac(g_re[s4], bi, acc[t].vi);
+                    acc[t].vi = MF<T>::mac(g_im[s4], br, acc[t].vi);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    const int row = o * 16 + tile_row<T>(r4), col = (2 * h + t) * 16 + tile_col();
+                    q_re[row * LD + col] = acc[t].re(r4);
+                    q_im[row * LD + col] = acc[t].im(r4);
+                }
+            __syncthreads();
+            acc[0].clear();
+            acc[1].clear();
+#pragma unroll
+            for (int s4 = 0; s4 < NB / 4; ++s4) {
+                const int k = 4 * s4 + lk;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int i = (2 * h + t) * 16 + li;
+                    const T ar = q_re[i * LD + k], ai = q_im[i * LD + k];
+                    acc[t].vr = MF<T>::mac(ar, g_re[s4], acc[t].vr);
+                    acc[t].vr = MF<T>::mac(-ai, g_im[s4], acc[t].vr);
+                    acc[t].vi = MF<T>::mac(ar, g_im[s4], acc[t].vi);
+                    acc[t].vi = MF<T>::mac(ai, g_re[s4], acc[t].vi);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    const int row = (2 * h + t) * 16 + tile_row<T>(r4), col = o * 16 + tile_col();
+                    stc(vt + (size_t)(row * NB + col) * NB * NB + blk, hf.ws * acc[t].re(r4),
+                        hf.ws * acc[t].im(r4));
+                }
+            if (nxt < NB * NB) put();   // every read of W ended at the barrier above
+            __syncthreads();
+        }
+        return;
+    }
     if constexpr (SH::TPW == 1) {
         constexpr int PER = NB * NB / SH::THREADS;
         const int ti = wave / SH::NT, tj = wave % SH::NT;
@@ -972,7 +1066,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     // wants several blocks per work-group; the larger shapes want the wider grid
     const int grid_vt = std::min(NB * NB, Shape<NB>::TPW == 1 ? 512 : 1024);
     const HfArgs hf{g.w_hf, g.h0, in.g1, g.hhf, g.gg, g.nbp, g.nb, ws};
-    hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt + NB * NB), dim3(Shape<NB>::THREADS), 0,
+    hipLaunchKernelGGL((gen_vt_kernel<T, S, NB>), dim3(grid_vt + NB * NB), dim3(vt_threads<NB>()), 0,
                        c->stream, wrows, in.g1, (S*)g.vt, grid_vt, hf);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_vt");
