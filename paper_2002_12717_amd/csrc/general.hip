@@ -369,12 +369,23 @@ struct SmallOps {
     T h_re[STAGE ? NB * LD : 1], h_im[STAGE ? NB * LD : 1];
 };
 
+// Nb = 64 runs eight waves of two tiles (two waves per SIMD at one work-group
+// per compute unit) instead of four waves of four: 0.82 instead of 1.11 ms per
+// launch (binary64); holding a wave's rows of G> in registers as well gained
+// nothing in binary64 and lost in binary32
+template <int NB>
+struct MainShape : Shape<NB> {
+    static constexpr int WAVES = NB == 64 ? 8 : Shape<NB>::WAVES;
+    static constexpr int TPW = Shape<NB>::TILES / WAVES;
+    static constexpr int THREADS = 64 * WAVES;
+};
+
 template <typename T, typename S, int NB>
-__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_main_kernel(
+__global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_main_kernel(
     const cd* __restrict__ g2, const S* __restrict__ vt, const S* __restrict__ wcoll,
     const cd* __restrict__ gg, const cd* __restrict__ hhf, S* __restrict__ dout,
     cd* __restrict__ ipart, double ws) {
-    typedef Shape<NB> SH;
+    typedef MainShape<NB> SH;
     constexpr int LD = SH::LD;
     using Acc = typename std::conditional<SH::TPW == 1, CAcc4<T>, CAcc<T>>::type;
     constexpr bool STAGE = NB <= 32;
@@ -1087,7 +1098,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_gemm");
     }
-    hipLaunchKernelGGL((gen_main_kernel<T, S, NB>), dim3(g.nipart), dim3(Shape<NB>::THREADS), 0,
+    hipLaunchKernelGGL((gen_main_kernel<T, S, NB>), dim3(g.nipart), dim3(MainShape<NB>::THREADS), 0,
                        c->stream, in.g2, (const S*)g.vt, wcoll, g.gg, g.hhf, (S*)g.dmat, g.ipart, ws);
     HIP_OK(c, hipGetLastError());
     prof_mark(c, "gen_main");
