@@ -369,10 +369,12 @@ struct SmallOps {
     T h_re[STAGE ? NB * LD : 1], h_im[STAGE ? NB * LD : 1];
 };
 
-// Nb = 64 runs eight waves of two tiles (two waves per SIMD at one work-group
-// per compute unit) instead of four waves of four: 0.82 instead of 1.11 ms per
-// launch (binary64); holding a wave's rows of G> in registers as well gained
-// nothing in binary64 and lost in binary32
+// Nb = 64 runs eight waves of two tiles instead of four waves of four.  In
+// gen_main (one work-group per compute unit) that is two waves per SIMD: 0.82
+// instead of 1.11 ms per launch in binary64; holding a wave's rows of G> in
+// registers as well gained nothing in binary64 and lost in binary32.  In
+// gen_heps (two work-groups per compute unit) it is 0.30 instead of 0.36 ms;
+// gen_hlad (one work-group per compute unit) takes the same shape.
 template <int NB>
 struct MainShape : Shape<NB> {
     static constexpr int WAVES = NB == 64 ? 8 : Shape<NB>::WAVES;
@@ -690,10 +692,10 @@ __global__ __launch_bounds__(256) void gen_combine_kernel(const S* __restrict__ 
 // --------------------------------------------------------------------------- GW kernels
 // H[(p,q)][(j,l)] = h^eps_qjpl = i (G< M_pq - M_pq G<)[j][l], M_pq[s][r] = w_sqrp.
 template <typename T, typename S, int NB>
-__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* __restrict__ wgw,
+__global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_heps_kernel(const S* __restrict__ wgw,
                                                                      const cd* __restrict__ gl,
                                                                      S* __restrict__ heps, double ws) {
-    typedef Shape<NB> SH;
+    typedef MainShape<NB> SH;
     constexpr int LD = SH::LD;
     __shared__ T m_re[NB * LD], m_im[NB * LD];
     const int wave = threadIdx.x >> 6;
@@ -742,11 +744,11 @@ __global__ __launch_bounds__(Shape<NB>::THREADS) void gen_heps_kernel(const S* _
 // h^pp as the pair matrix [(ij)][(kl)] and h^ph as the left GEMM operand
 // [(il)][(jk)] of Lambda^ph_ijkl = sum_pq h^ph_ipql G2_qjkp (eq:lambdaph).
 template <typename T, typename S, int NB, int KIND>
-__global__ __launch_bounds__(Shape<NB>::THREADS) void gen_hlad_kernel(const S* __restrict__ wl,
+__global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_hlad_kernel(const S* __restrict__ wl,
                                                                      const cd* __restrict__ gl,
                                                                      const cd* __restrict__ gg,
                                                                      S* __restrict__ out, double ws) {
-    typedef Shape<NB> SH;
+    typedef MainShape<NB> SH;
     constexpr int LD = SH::LD;
     __shared__ T m_re[NB * LD], m_im[NB * LD], q_re[NB * LD], q_im[NB * LD];
     const int wave = threadIdx.x >> 6;
@@ -1085,7 +1087,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     const int n = NB * NB;
     if (se == G1G2_GW || se == G1G2_DSL) {
         const S* wgw = mixed ? (const S*)g.w_gw32 : (const S*)g.w_gw;
-        hipLaunchKernelGGL((gen_heps_kernel<T, S, NB>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+        hipLaunchKernelGGL((gen_heps_kernel<T, S, NB>), dim3(grid_vt), dim3(MainShape<NB>::THREADS), 0,
                            c->stream, wgw, in.g1, (S*)g.heps, ws);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_heps");
@@ -1106,7 +1108,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     // the partner [Lambda_klij]^* of eq:g2-eq-tpp-lambda / eq:g2-eq-tph-lambda
     if (se == G1G2_TPP || se == G1G2_DSL) {
         const S* wpp = mixed ? (const S*)g.w_pp32 : (const S*)g.w_pp;
-        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 0>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 0>), dim3(grid_vt), dim3(MainShape<NB>::THREADS), 0,
                            c->stream, wpp, in.g1, g.gg, (S*)g.heps, ws);
         hipLaunchKernelGGL((gen_bmat_kernel<S, 1>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
                            NB);
@@ -1119,7 +1121,7 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
     }
     if (se == G1G2_TPH || se == G1G2_DSL) {
         const S* wph = mixed ? (const S*)g.w_ph32 : (const S*)g.w_ph;
-        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 1>), dim3(grid_vt), dim3(Shape<NB>::THREADS), 0,
+        hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 1>), dim3(grid_vt), dim3(MainShape<NB>::THREADS), 0,
                            c->stream, wph, in.g1, g.gg, (S*)g.heps, ws);
         hipLaunchKernelGGL((gen_bmat_kernel<S, 2>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
                            NB);
