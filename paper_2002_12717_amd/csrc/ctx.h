@@ -83,7 +83,7 @@ struct GeneralData {
     // GW and the ladders: quasi-Hamiltonian and permuted G2 operand of a GEMM
     cd* heps = nullptr;      // GW: [(p,q)][(j,l)] = h^eps_qjpl; ladders: h^pp, h^ph (nbp^4)
     cd* bmat = nullptr;      // GW: [(i,k)][(p,q)] = G2_ipkq; ladders: see gen_bmat  (nbp^4)
-    cd* pimat = nullptr;     // [(i,k)][(j,l)] = Pi_ijkl                           (nbp^4)
+    cd* pimat = nullptr;     // Pi_ijkl at [i][j][k][l], then at [l][k][j][i]       (2 nbp^4)
     cd* w_gw = nullptr;      // GW layout: [p][q][s][r] = w_sqrp                   (nbp^4)
     cd* w_pp = nullptr;      // TPP layout: [k][l][p][q] = w_pqkl                  (nbp^4)
     cd* w_ph = nullptr;      // TPH layout: [j][k][p][q] = w_pjkq                  (nbp^4)
