@@ -845,7 +845,10 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
 //            pim[n^2 + ((l nbp + k) nbp + j) nbp + i]          (binary64 buffer)
 //   1 (TPP): D[(i,j)][(k,l)] += C[(i,j)][(k,l)]               (D in storage S)
 //   2 (TPH): D[(i,j)][(k,l)] += C[(i,l)][(j,k)]
-template <typename T, typename S, int OUT>
+// AG2 reads the GW operand B[(i,k)][(p,q)] = G2_ipkq in place from the binary64
+// G2 instead of a permuted copy: within a K slice p = k0 / nbp is uniform and q
+// runs over 16 consecutive values, so the loads keep their 256-byte rows.
+template <typename T, typename S, int OUT, bool AG2 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
                                                       void* __restrict__ dst, int n, int nbp) {
@@ -875,11 +878,18 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
         }
     // the next K slice is loaded into registers while the current one runs
     T pa_re[PER], pa_im[PER], pb_re[PER], pb_im[PER];
+    size_t arow[PER];   // AG2: the (i, k) part i nbp^3 + k nbp of each A row's G2 index
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int row = bm + (threadIdx.x + q * 256) / KS;
+        arow[q] = AG2 ? ((size_t)(row / nbp) * nbp * nbp + row % nbp) * nbp : (size_t)row * n;
+    }
     auto fetch = [&](int k0) {
+        const size_t acol = AG2 ? (size_t)(k0 / nbp) * nbp * nbp + k0 % nbp : (size_t)k0;
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = threadIdx.x + q * 256;
-            ldc(A + (size_t)(bm + idx / KS) * n + k0 + idx % KS, pa_re[q], pa_im[q]);
+            ldc(A + arow[q] + acol + idx % KS, pa_re[q], pa_im[q]);
             ldc(B + (size_t)(k0 + idx / 64) * n + bn + idx % 64, pb_re[q], pb_im[q]);
         }
     };
@@ -1096,12 +1106,17 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
                            c->stream, wgw, in.g1, (S*)g.heps, ws);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_heps");
-        hipLaunchKernelGGL((gen_bmat_kernel<S, 0>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
-                           NB);
-        HIP_OK(c, hipGetLastError());
-        prof_mark(c, "gen_bmat");
-        hipLaunchKernelGGL((gen_gemm_kernel<T, S, 0>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
-                           (const S*)g.bmat, (const S*)g.heps, (void*)g.pimat, n, NB);
+        if constexpr (std::is_same<S, cd>::value) {   // binary64: the G2 operand is read in place
+            hipLaunchKernelGGL((gen_gemm_kernel<T, S, 0, true>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                               (const S*)in.g2, (const S*)g.heps, (void*)g.pimat, n, NB);
+        } else {                                      // binary32: from a permuted binary32 copy
+            hipLaunchKernelGGL((gen_bmat_kernel<S, 0>), dim3(2048), dim3(256), 0, c->stream, in.g2,
+                               (S*)g.bmat, NB);
+            HIP_OK(c, hipGetLastError());
+            prof_mark(c, "gen_bmat");
+            hipLaunchKernelGGL((gen_gemm_kernel<T, S, 0>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                               (const S*)g.bmat, (const S*)g.heps, (void*)g.pimat, n, NB);
+        }
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_gemm");
     }
@@ -1115,12 +1130,15 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
         const S* wpp = mixed ? (const S*)g.w_pp32 : (const S*)g.w_pp;
         hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 0>), dim3(grid_vt), dim3(MainShape<NB>::THREADS), 0,
                            c->stream, wpp, in.g1, g.gg, (S*)g.heps, ws);
-        hipLaunchKernelGGL((gen_bmat_kernel<S, 1>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
-                           NB);
+        // the TPP operand is G2 itself: binary64 reads it in place, binary32 from a copy
+        const S* g2op = (const S*)g.bmat;
+        if constexpr (std::is_same<S, cd>::value) g2op = (const S*)in.g2;
+        else hipLaunchKernelGGL((gen_bmat_kernel<S, 1>), dim3(2048), dim3(256), 0, c->stream, in.g2,
+                                (S*)g.bmat, NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_hlad");
         hipLaunchKernelGGL((gen_gemm_kernel<T, S, 1>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
-                           (const S*)g.heps, (const S*)g.bmat, (void*)g.dmat, n, NB);
+                           (const S*)g.heps, g2op, (void*)g.dmat, n, NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_gemm");
     }
