@@ -101,10 +101,13 @@ struct HfArgs {
     double ws;       // switching factor phi(t) of the interaction (1 without a ramp)
 };
 
-// Row (ij) of h^HF by one work-group of THREADS threads.
+// Row (ij) of h^HF by one work-group of THREADS threads, of which at most four
+// waves sum the row: the order of the sum, and so h^HF to the last bit, does not
+// depend on the block size of the launch the rows run in.
 template <int THREADS>
 __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
-    constexpr int NW = THREADS / 64;
+    constexpr int EFF = THREADS < 256 ? THREADS : 256;
+    constexpr int NW = EFF / 64;
     __shared__ double part[2][NW];
     const int nbp = a.nbp, n2 = nbp * nbp;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -112,11 +115,11 @@ __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
     // are read contiguously
     const cd* row = a.whf + (size_t)ij * n2;
     double ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
-    for (int m0 = threadIdx.x; m0 < n2; m0 += 4 * THREADS) {
+    for (int m0 = threadIdx.x; threadIdx.x < EFF && m0 < n2; m0 += 4 * EFF) {
         cd w[4], g[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int m = m0 + THREADS * u;
+            const int m = m0 + EFF * u;
             w[u] = m < n2 ? row[m] : make_double2(0.0, 0.0);
             g[u] = m < n2 ? a.gl[m] : make_double2(0.0, 0.0);
         }
@@ -127,7 +130,7 @@ __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
         }
     }
     const double wr = wave_sum(ar[0] + ar[1]), wi = wave_sum(ai[0] + ai[1]);
-    if (lane == 0) {
+    if (lane == 0 && wave < NW) {
         part[0][wave] = wr;
         part[1][wave] = wi;
     }
