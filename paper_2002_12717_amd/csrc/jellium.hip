@@ -359,9 +359,13 @@ struct LadArgs {
     cd* out;                  // [3][nb]^3
 };
 
-constexpr int LAD_ROWS = 2;   // rows per work-group of the ladder transform
+// rows per work-group of the ladder transform: four where their two copies fit
+// the 64 KB of LDS a launch gets by default (nb <= 512), else two; four rows
+// took the 6x6x6 TPH transform from 0.62 to 0.56 ms (TPP 0.565 -> 0.554)
+constexpr int LAD_ROWS_MAX = 4;
+int lad_rows(int nb) { return 2 * LAD_ROWS_MAX * nb * (int)sizeof(cd) <= 65536 ? LAD_ROWS_MAX : 2; }
 
-// The ladder sums of LAD_ROWS rows per work-group, rows (c, P, X):
+// The ladder sums of ROWS rows per work-group, rows (c, P, X):
 //   TPP: g[K] = G2[c][P][X][K]      (X = Pb), out = F-[vhat F+[g]]
 //   TPH: h[K] = G2[c][P][K][X - K]  (X = S),  out = F+[vhat F-[h]]
 // with F+/- the transforms with e^{+/-2 pi i k.m/L} over the grid, each the
@@ -370,18 +374,18 @@ constexpr int LAD_ROWS = 2;   // rows per work-group of the ladder transform
 // line of each row (read from LDS) times its twiddles, so its line offset and
 // twiddle index are computed once per pass.  The rows and a ping-pong copy
 // live in LDS.
-template <int KIND, typename TI>
+template <int KIND, typename TI, int ROWS>
 __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
-    extern __shared__ cd lad_sh[];   // [2][LAD_ROWS][nb]
+    extern __shared__ cd lad_sh[];   // [2][ROWS][nb]
     const int nb = s.nb, n = threadIdx.x;
     cd* const buf0 = lad_sh;
-    cd* const buf1 = lad_sh + LAD_ROWS * nb;
+    cd* const buf1 = lad_sh + ROWS * nb;
     const bool nok = n < nb;
     const long long nn = (long long)nb * nb, rows = 3 * nn;
-    const long long r0 = (long long)blockIdx.x * LAD_ROWS;
+    const long long r0 = (long long)blockIdx.x * ROWS;
     const TI* __restrict__ in = static_cast<const TI*>(s.in2);
 #pragma unroll
-    for (int r = 0; r < LAD_ROWS; ++r) {
+    for (int r = 0; r < ROWS; ++r) {
         const long long row = r0 + r;
         cd x = cmk(0.0, 0.0);
         if (nok && row < rows) {
@@ -405,15 +409,15 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
             if (nok) {
                 const cd* __restrict__ t = s.tw + s.toff[d];
                 const int kd = (n / sd) % L, base = n - kd * sd;
-                cd acc[LAD_ROWS];
+                cd acc[ROWS];
 #pragma unroll
-                for (int r = 0; r < LAD_ROWS; ++r) acc[r] = cmk(0.0, 0.0);
+                for (int r = 0; r < ROWS; ++r) acc[r] = cmk(0.0, 0.0);
                 int q = 0;
                 for (int m = 0; m < L; ++m) {
                     const cd w = t[q];
                     const double wi = plus ? -w.y : w.y;
 #pragma unroll
-                    for (int r = 0; r < LAD_ROWS; ++r) {
+                    for (int r = 0; r < ROWS; ++r) {
                         const cd x = src[r * nb + base + m * sd];
                         acc[r].x = fma(x.x, w.x, fma(-x.y, wi, acc[r].x));
                         acc[r].y = fma(x.x, wi, fma(x.y, w.x, acc[r].y));
@@ -422,7 +426,7 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
                     if (q >= L) q -= L;
                 }
 #pragma unroll
-                for (int r = 0; r < LAD_ROWS; ++r) dst[r * nb + n] = acc[r];
+                for (int r = 0; r < ROWS; ++r) dst[r * nb + n] = acc[r];
             }
             __syncthreads();
             cur = !cur;
@@ -433,20 +437,21 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
         cd* b = cur ? buf1 : buf0;
         const cd vh = s.vhat[n];
 #pragma unroll
-        for (int r = 0; r < LAD_ROWS; ++r) b[r * nb + n] = cmul(b[r * nb + n], vh);
+        for (int r = 0; r < ROWS; ++r) b[r * nb + n] = cmul(b[r * nb + n], vh);
     }
     __syncthreads();
     passes(KIND != LAD_PP);
     const cd* res = cur ? buf1 : buf0;
     if (nok)
 #pragma unroll
-        for (int r = 0; r < LAD_ROWS; ++r)
+        for (int r = 0; r < ROWS; ++r)
             if (r0 + r < rows) s.out[(r0 + r) * nb + n] = res[r * nb + n];
 }
 
 int lad_blocks(const g1g2_ctx* c) {
     const long long rows = 3LL * c->jel.nb * c->jel.nb;
-    return (int)((rows + LAD_ROWS - 1) / LAD_ROWS);
+    const int r = lad_rows(c->jel.nb);
+    return (int)((rows + r - 1) / r);
 }
 
 int lad_threads(const g1g2_ctx* c) { return (c->jel.nb + 63) / 64 * 64; }
@@ -546,8 +551,13 @@ void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
         la.tw = J.tw;
         la.subt = J.subt;
         la.out = J.lad;
-        hipLaunchKernelGGL((jel_lad_kernel<LAD, TI>), dim3(lad_blocks(c)), dim3(lad_threads(c)),
-                           2 * LAD_ROWS * J.nb * sizeof(cd), c->stream, la);
+        const int lr = lad_rows(J.nb);
+        if (lr == LAD_ROWS_MAX)
+            hipLaunchKernelGGL((jel_lad_kernel<LAD, TI, LAD_ROWS_MAX>), dim3(lad_blocks(c)), dim3(lad_threads(c)),
+                               2 * lr * J.nb * sizeof(cd), c->stream, la);
+        else
+            hipLaunchKernelGGL((jel_lad_kernel<LAD, TI, 2>), dim3(lad_blocks(c)), dim3(lad_threads(c)),
+                               2 * lr * J.nb * sizeof(cd), c->stream, la);
         prof_mark(c, "jel_lad");
     }
     hipLaunchKernelGGL((jel_stage_kernel<MODE, GW, TI, TO, false, LAD>), dim3(stage_blocks(c)),

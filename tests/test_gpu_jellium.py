@@ -40,12 +40,13 @@ def _se(B, se):
     return (B.GW, B.GW_EXCHANGE) if se == "gw_x" else ({"soa": B.SOA, "gw": B.GW, "tpp": B.TPP, "tph": B.TPH}[se], 0)
 
 
-@pytest.mark.parametrize("dims", [(5,), (3, 3), (2, 3, 2), (4, 4, 4)])
+@pytest.mark.parametrize("dims", [(5,), (3, 3), (2, 3, 2), (4, 4, 4), (10,)])
 @pytest.mark.parametrize("se", ["soa", "gw", "gw_x", "tpp", "tph"])
 def test_jellium_rhs_parity(lib, dims, se):
     """One right-hand side at a random momentum-conserving state with the pair
-    symmetries, every element of dG1 and of the three G2 blocks (the ladder
-    product's row and column tiles of 16 are ragged at every size here)."""
+    symmetries, every element of dG1 and of the three G2 blocks, on one-, two-
+    and three-dimensional grids (the stage's 64-momentum tiles are ragged on
+    all of them; the 10-point grid has a dimension longer than the others)."""
     from paper_2002_12717_amd import binding as B
     nb = int(np.prod(dims))
     r = rng(611, nb, len(se))
