@@ -40,17 +40,17 @@ PEAK_HBM = 8000.0          # GB/s
 # counters were taken (source_hash below: the whole file, so that a change of
 # the kernel or of how it is launched voids it).
 TRAFFIC = {
-    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "sha1": "ac91d46b3f84"},
-    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "sha1": "ac91d46b3f84"},
-    "gen_gemm/f64": {"bytes": 7.511e9, "src": "general.hip", "sha1": "ac91d46b3f84"},
-    "gen_gemm/f32": {"bytes": 4.002e9, "src": "general.hip", "sha1": "ac91d46b3f84"},
+    "gen_main/f64": {"bytes": 75.9e6, "src": "general.hip", "sha1": "93fc8312f356"},
+    "gen_main/f32": {"bytes": 50.7e6, "src": "general.hip", "sha1": "93fc8312f356"},
+    "gen_gemm/f64": {"bytes": 7.505e9, "src": "general.hip", "sha1": "93fc8312f356"},
+    "gen_gemm/f32": {"bytes": 4.003e9, "src": "general.hip", "sha1": "93fc8312f356"},
     "hub_stage/2d": {"bytes": 2.385e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
     "hub_stage/2d/mixed": {"bytes": 1.634e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
     "hub_stage/2d/tpp": {"bytes": 2.443e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
-    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "sha1": "224f7e3c42ea"},
-    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "sha1": "224f7e3c42ea"},
-    "jel_stage/tpp": {"bytes": 4.651e9, "src": "jellium.hip", "sha1": "224f7e3c42ea"},
-    "jel_lad/tpp": {"bytes": 0.968e9, "src": "jellium.hip", "sha1": "224f7e3c42ea"},
+    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "sha1": "e5a973bb30e9"},
+    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "sha1": "e5a973bb30e9"},
+    "jel_stage/tpp": {"bytes": 4.651e9, "src": "jellium.hip", "sha1": "e5a973bb30e9"},
+    "jel_lad/tpp": {"bytes": 0.968e9, "src": "jellium.hip", "sha1": "e5a973bb30e9"},
 }
 
 
