@@ -816,10 +816,13 @@ __global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_hlad_kernel(const 
     }
 }
 
-// Permuted copy of G2 (binary64 or binary32) as the right operand of a GEMM:
+// Permuted copy of G2 as a GEMM operand (the left one of the GW product, the
+// right one of the ladder products):
 //   MODE 0 (GW):   b[(i,k)][(p,q)] = G2_ipkq
 //   MODE 1 (TPP):  b[(p,q)][(k,l)] = G2_pqkl
 //   MODE 2 (TPH):  b[(p,q)][(j,k)] = G2_qjkp
+// The binary64 GW and TPP products read G2 in place, so modes 0 and 1 run for
+// the binary32 copies only; mode 2 runs in both precisions.
 template <typename S, int MODE>
 __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2, S* __restrict__ b,
                                                       int nbp) {
