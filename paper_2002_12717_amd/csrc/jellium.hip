@@ -293,14 +293,14 @@ __global__ __launch_bounds__(64 * JEL_WAVES) void jel_stage_kernel(StageArgsJ s)
                     // and f at the partner element from the same four G1 values
                     const cd* __restrict__ L = s.lad + c * n3;
                     cd lo, lp, fo, fp;
+                    // both ladders are stored in the layout of G2: the own sum at
+                    // e, the partner's at (P - Q, Pb + Q, -Q)
+                    lo = L[e];
+                    lp = L[((size_t)Pm[j] * nb + Pbp) * nb + negQ];
                     if (LAD == LAD_PP) {
-                        lo = L[e];
-                        lp = L[((size_t)Pm[j] * nb + Pbp) * nb + negQ];
                         fo = csub(cmul(gg1, gg2), cmul(gl1, gl2));
                         fp = csub(cmul(gg3, gg4), cmul(gl3, gl4));
                     } else {
-                        lo = L[((size_t)Pv[j] * nb + Pbp) * nb + Pb];
-                        lp = L[((size_t)Pm[j] * nb + Pb) * nb + Pbp];
                         fo = csub(cmul(gg1, gl4), cmul(gl1, gg4));
                         fp = csub(cmul(gg3, gl2), cmul(gl3, gg2));
                     }
@@ -368,6 +368,8 @@ int lad_rows(int nb) { return 2 * LAD_ROWS_MAX * nb * (int)sizeof(cd) <= 65536 ?
 // The ladder sums of ROWS rows per work-group, rows (c, P, X):
 //   TPP: g[K] = G2[c][P][X][K]      (X = Pb), out = F-[vhat F+[g]]
 //   TPH: h[K] = G2[c][P][K][X - K]  (X = S),  out = F+[vhat F-[h]]
+// Both are stored in the layout of G2, L[c][P][Pb][Q] (TPH: output Pb of row
+// (c, P, S) at Q = S - Pb).
 // with F+/- the transforms with e^{+/-2 pi i k.m/L} over the grid, each the
 // product of one-dimensional transforms along x, y and z.  Thread n owns
 // momentum n of every row: in a pass along d it sums the L_d elements of its
@@ -444,8 +446,20 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
     const cd* res = cur ? buf1 : buf0;
     if (nok)
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r)
-            if (r0 + r < rows) s.out[(r0 + r) * nb + n] = res[r * nb + n];
+        for (int r = 0; r < ROWS; ++r) {
+            const long long row = r0 + r;
+            if (row >= rows) continue;
+            if (KIND == LAD_PP) {
+                s.out[row * nb + n] = res[r * nb + n];   // L[c][P][Pb][Q], Q = n
+            } else {
+                // output n of row (c, P, S) is M[P][n][S - n]: stored at
+                // [c][P][n][S - n], the layout of the stage's own element, so the
+                // stage reads it coalesced; a thread's rows fill 64-byte pieces
+                const int c = (int)(row / nn);
+                const int rem = (int)(row - c * nn), P = rem / nb, X = rem - P * nb;
+                s.out[((size_t)(c * nb + P) * nb + n) * nb + s.subt[X * nb + n]] = res[r * nb + n];
+            }
+        }
 }
 
 int lad_blocks(const g1g2_ctx* c) {
