@@ -444,22 +444,25 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
     __syncthreads();
     passes(KIND != LAD_PP);
     const cd* res = cur ? buf1 : buf0;
-    if (nok)
+    if (KIND == LAD_PP) {
+        if (nok)
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r) {
+            for (int r = 0; r < ROWS; ++r)
+                if (r0 + r < rows) s.out[(r0 + r) * nb + n] = res[r * nb + n];   // L[c][P][Pb][Q], Q = n
+    } else {
+        // output m of row (c, P, S) is M[P][m][S - m]: stored at [c][P][m][S - m],
+        // the layout of the stage's own element, so the stage reads it coalesced.
+        // Consecutive lanes take the ROWS outputs of one m (adjacent S - m), so a
+        // store instruction writes pieces of 16 ROWS bytes rather than 16 bytes
+        for (int e = threadIdx.x; e < ROWS * nb; e += blockDim.x) {
+            const int m = e / ROWS, r = e - m * ROWS;
             const long long row = r0 + r;
             if (row >= rows) continue;
-            if (KIND == LAD_PP) {
-                s.out[row * nb + n] = res[r * nb + n];   // L[c][P][Pb][Q], Q = n
-            } else {
-                // output n of row (c, P, S) is M[P][n][S - n]: stored at
-                // [c][P][n][S - n], the layout of the stage's own element, so the
-                // stage reads it coalesced; a thread's rows fill 64-byte pieces
-                const int c = (int)(row / nn);
-                const int rem = (int)(row - c * nn), P = rem / nb, X = rem - P * nb;
-                s.out[((size_t)(c * nb + P) * nb + n) * nb + s.subt[X * nb + n]] = res[r * nb + n];
-            }
+            const int c = (int)(row / nn);
+            const int rem = (int)(row - c * nn), P = rem / nb, X = rem - P * nb;
+            s.out[((size_t)(c * nb + P) * nb + m) * nb + s.subt[X * nb + m]] = res[r * nb + m];
         }
+    }
 }
 
 int lad_blocks(const g1g2_ctx* c) {
