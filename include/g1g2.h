@@ -103,7 +103,12 @@ enum {
      * diagonalization only the exchange form reaches that order (density
      * error O(w^4) instead of O(w^3)) in a general basis.  EUNSUPPORTED with
      * any other basis or selfenergy. */
-    G1G2_DSL_EXCHANGE = 16
+    G1G2_DSL_EXCHANGE = 16,
+    /* Jellium T matrices: the ladder transform with two rows per work-group
+     * whatever nb (by default four, two only above 512 momenta, where four
+     * would exceed 64 KB of LDS); the rows are independent, so the results are
+     * the same.  For tests of the two-row form on grids the oracle can take. */
+    G1G2_JEL_LAD_ROWS2 = 32
 };
 
 typedef struct {
@@ -168,7 +173,8 @@ g1g2_status g1g2_init(g1g2_ctx** out, const g1g2_desc* desc, const void* h0, con
  * and TPH (eq:jellium-lambdaph), the T matrices with Psi^- and the partner
  * conj(Lambda_{P-Q, Pb+Q, -Q}); they hold one more [3][nb]^3 buffer (the
  * ladder sums, 484 MB at 6x6x6).  FP64 or MIXED (binary32 G2 stage copies,
- * like the Hubbard basis).  EUNSUPPORTED for DSL; EINVAL for bad dims,
+ * like the Hubbard basis).  Flags: G1G2_PTR_DEVICE, G1G2_GW_EXCHANGE,
+ * G1G2_JEL_LAD_ROWS2.  EUNSUPPORTED for DSL; EINVAL for other flags, bad dims,
  * nb != Lx Ly Lz or v[0] != 0.  Every other call
  * works as for the other bases except set_h0, set_U, set_drive, set_switch, the
  * adjoint and the batch calls (EUNSUPPORTED or ESTATE).  Observables: N per

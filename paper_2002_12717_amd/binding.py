@@ -19,7 +19,7 @@ LIBPATH = os.path.join(PKG, "libg1g2.so")
 GENERAL, HUBBARD, JELLIUM = 0, 1, 2
 SOA, GW, TPP, TPH, DSL = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
-PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL, DSL_EXCHANGE = 1, 2, 4, 8, 16
+PTR_DEVICE, GW_EXCHANGE, HUB_ROW_KERNEL, HUB_SLICE_KERNEL, DSL_EXCHANGE, JEL_LAD_ROWS2 = 1, 2, 4, 8, 16, 32
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EDIVERGED, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PATHS = {0: "general", 1: "hub_persistent", 2: "hub_slice", 3: "hub_row", 4: "hub_element", 5: "jellium"}
 

@@ -308,7 +308,7 @@ g1g2_status g1g2_jellium_init(g1g2_ctx** out, const g1g2_desc* d, const int32_t*
     if (d->basis != G1G2_JELLIUM) return G1G2_EINVAL;
     if (d->selfenergy < G1G2_SOA || d->selfenergy > G1G2_DSL) return G1G2_EINVAL;
     if (d->precision != G1G2_FP64 && d->precision != G1G2_MIXED) return G1G2_EINVAL;
-    if (d->flags & ~(G1G2_PTR_DEVICE | G1G2_GW_EXCHANGE)) return G1G2_EINVAL;
+    if (d->flags & ~(G1G2_PTR_DEVICE | G1G2_GW_EXCHANGE | G1G2_JEL_LAD_ROWS2)) return G1G2_EINVAL;
     for (int k = 0; k < 3; ++k)
         if (dims[k] < 1 || dims[k] > 1024) return G1G2_EINVAL;
     const long long nbl = (long long)dims[0] * dims[1] * dims[2];

@@ -363,7 +363,10 @@ struct LadArgs {
 // the 64 KB of LDS a launch gets by default (nb <= 512), else two; four rows
 // took the 6x6x6 TPH transform from 0.62 to 0.56 ms (TPP 0.565 -> 0.554)
 constexpr int LAD_ROWS_MAX = 4;
-int lad_rows(int nb) { return 2 * LAD_ROWS_MAX * nb * (int)sizeof(cd) <= 65536 ? LAD_ROWS_MAX : 2; }
+int lad_rows(const g1g2_ctx* c) {
+    if (c->d.flags & G1G2_JEL_LAD_ROWS2) return 2;
+    return 2 * LAD_ROWS_MAX * c->jel.nb * (int)sizeof(cd) <= 65536 ? LAD_ROWS_MAX : 2;
+}
 
 // The ladder sums of ROWS rows per work-group, rows (c, P, X):
 //   TPP: g[K] = G2[c][P][X][K]      (X = Pb), out = F-[vhat F+[g]]
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(JEL_MAX_NB) void jel_lad_kernel(LadArgs s) {
 
 int lad_blocks(const g1g2_ctx* c) {
     const long long rows = 3LL * c->jel.nb * c->jel.nb;
-    const int r = lad_rows(c->jel.nb);
+    const int r = lad_rows(c);
     return (int)((rows + r - 1) / r);
 }
 
@@ -568,7 +571,7 @@ void launch_stage(g1g2_ctx* c, const StageArgsJ& s) {
         la.tw = J.tw;
         la.subt = J.subt;
         la.out = J.lad;
-        const int lr = lad_rows(J.nb);
+        const int lr = lad_rows(c);
         if (lr == LAD_ROWS_MAX)
             hipLaunchKernelGGL((jel_lad_kernel<LAD, TI, LAD_ROWS_MAX>), dim3(lad_blocks(c)), dim3(lad_threads(c)),
                                2 * lr * J.nb * sizeof(cd), c->stream, la);

@@ -127,6 +127,37 @@ def test_jellium_full_size_rhs(lib, se):
     assert e1 < 1e-12 and e2 < 1e-12
 
 
+@pytest.mark.parametrize("dims,se", [((6, 6, 6), "tpp"), ((6, 6, 6), "tph"), ((2, 3, 2), "tph"), ((10,), "tpp")])
+def test_jellium_ladder_rows_agree(lib, dims, se):
+    """The ladder transform with two rows per work-group (the form grids of
+    more than 512 momenta take, forced here by G1G2_JEL_LAD_ROWS2) against the
+    default four: the rows are transformed independently and alike, so the two
+    agree to the rounding of the down-spin polarization sums, which are summed
+    with atomics (1e-13 relative; a wrong row or momentum index would differ at
+    order one).  With the oracle parity of the default this pins the two-row
+    form, for one right-hand side and for two steps of the stepper."""
+    from paper_2002_12717_amd import binding as B
+    r = rng(613, int(np.prod(dims)), len(se))
+    gl, g2 = random_jellium_state(dims, r, scale=0.02)
+    s = jellium_system(dims=dims)
+    code, fl = _se(B, se)
+    say(f"[jellium ladder rows] dims={dims} {se}")
+    out = []
+    for extra in (0, B.JEL_LAD_ROWS2):
+        p = B.Jellium(code, dims, s.eps, s.v, gl, flags=fl | extra)
+        G1 = torch.as_tensor(gl, dtype=torch.complex128).cuda()
+        G2 = torch.as_tensor(three(g2), dtype=torch.complex128).cuda()
+        d1, d2 = torch.zeros_like(G1), torch.zeros_like(G2)
+        p.rhs(0.0, G1, G2, d1, d2)
+        p.set_state(gl, three(g2))
+        p.step(0.02, 2)
+        a, b, _ = p.get_state()
+        p.close()
+        out.append((d1.cpu().numpy(), d2.cpu().numpy(), a, b))
+    for x, y in zip(out[0], out[1]):
+        assert rel(x, y) < 1e-13
+
+
 def test_jellium_edge_cases_and_graphs(lib):
     """A single momentum (no interaction: v[0] = 0), zero steps, graph-replayed
     steps against eager launches (the down-spin sums use atomics, so the two
