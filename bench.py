@@ -47,10 +47,10 @@ TRAFFIC = {
     "hub_stage/2d": {"bytes": 2.385e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
     "hub_stage/2d/mixed": {"bytes": 1.634e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
     "hub_stage/2d/tpp": {"bytes": 2.443e9, "src": "hubbard.hip", "sha1": "94601047d47b"},
-    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "sha1": "3816edff7478"},
-    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "sha1": "3816edff7478"},
-    "jel_stage/tpp": {"bytes": 4.651e9, "src": "jellium.hip", "sha1": "3816edff7478"},
-    "jel_lad/tpp": {"bytes": 0.968e9, "src": "jellium.hip", "sha1": "3816edff7478"},
+    "jel_stage/gw": {"bytes": 2.03e9, "src": "jellium.hip", "sha1": "370a4e568f25"},
+    "jel_stage/gw/mixed": {"bytes": 1.70e9, "src": "jellium.hip", "sha1": "370a4e568f25"},
+    "jel_stage/tpp": {"bytes": 4.651e9, "src": "jellium.hip", "sha1": "370a4e568f25"},
+    "jel_lad/tpp": {"bytes": 0.968e9, "src": "jellium.hip", "sha1": "370a4e568f25"},
 }
 
 
