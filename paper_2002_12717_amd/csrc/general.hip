@@ -153,7 +153,7 @@ __device__ __forceinline__ void hf_row(const HfArgs& a, int ij) {
 // --------------------------------------------------------------------------- K2
 // Right sandwich on row blocks of W: Vt[k][l][p][q] = (G<^T W_pq G<)[k][l].
 // Work-groups nvt.. of the launch compute the rows of h^HF (K1).
-// Nb = 64 takes eight waves of two tiles (the other sizes one wave per tile row).
+// Nb = 64 takes eight waves of two tiles; the other sizes take Shape's waves.
 template <int NB>
 __host__ __device__ constexpr int vt_threads() { return NB == 64 ? 512 : Shape<NB>::THREADS; }
 
