@@ -909,6 +909,10 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
         }
         __syncthreads();
         if (k0 + KS < n) fetch(k0 + KS);
+        // the wave issues its matrix-core work at raised priority, so that of the
+        // two work-groups on a compute unit the one past its barrier goes first
+        // (0.5% in binary64, 1% in binary32)
+        __builtin_amdgcn_s_setprio(1);
         {
             const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -940,6 +944,7 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
                     }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (sizeof(T) == 4 && ((k0 + KS) % 64 == 0 || k0 + KS >= n)) {
             for (int a = 0; a < 2; ++a)
