@@ -1182,3 +1182,55 @@ def test_zero_steps_and_uncorrelated_limits(lib):
     ref = Ut @ g.g1 @ Ut.conj().T
     assert rel(g1d, ref) < 1e-6
     p.close()
+
+
+@pytest.mark.parametrize("case", ["general_gw", "general_dsl", "general_soa_mixed", "hubbard_soa_row",
+                                  "hubbard_tpp_slice", "hubbard_8x8"])
+def test_results_reproducible(lib, case):
+    """The scheme is a deterministic map (reading 12), and the general-basis and
+    Hubbard paths sum in fixed orders (no atomics on their data), so the same
+    right-hand side evaluated twice in one context and once in a fresh one
+    gives the same bits, and so do four Runge-Kutta steps from the same state
+    in the two contexts.  (The jellium stage sums its down-spin polarization
+    sums with atomics and agrees only to rounding; it is not included.)"""
+    from paper_2002_12717_amd import binding as B
+    say(f"[reproducible] {case}")
+    r = rng(109, len(case))
+    if case.startswith("general"):
+        se = case.split("_")[1]
+        h, w, g1, g2 = _general_inputs(20, 7)
+        code, flags = _gen_se(se)
+        prec = B.MIXED if case.endswith("mixed") else B.FP64
+
+        def make():
+            return B.Propagator(B.GENERAL, code, 20, h, g1, w=w, precision=prec, flags=flags)
+    else:
+        if case == "hubbard_8x8":   # the 64-site row form
+            s = adjoint_system()
+            h0, ns = s.h0, s.ns
+        else:
+            h0 = _hubbard_h0("sq3x3", r)
+            ns = h0.shape[1]
+        g1 = np.stack([random_gless(ns, r), random_gless(ns, r)])
+        g2 = random_g2(ns, r, scale=0.02, exchange=False)
+        se = case.split("_")[1] if case != "hubbard_8x8" else "soa"
+        flags = {"row": B.HUB_ROW_KERNEL, "slice": B.HUB_SLICE_KERNEL}.get(case.split("_")[-1], 0)
+
+        def make():
+            return B.Propagator(B.HUBBARD, _se(se), ns, h0, g1, U=1.3, flags=flags)
+    rhs, steps = [], []
+    for ctx in range(2):
+        p = make()
+        for _ in range(2 - ctx):
+            G1d, G2d = cuda(g1), cuda(g2)
+            d1, d2 = torch.zeros_like(G1d), torch.zeros_like(G2d)
+            p.rhs(0.0, G1d, G2d, d1, d2)
+            rhs.append((d1.cpu().numpy(), d2.cpu().numpy()))
+        p.set_state(g1, g2)
+        p.step(0.01, 4)
+        a, b, _ = p.get_state()
+        steps.append((a, b))
+        p.close()
+    for x in rhs[1:]:
+        assert np.array_equal(x[0], rhs[0][0]) and np.array_equal(x[1], rhs[0][1])
+    assert np.array_equal(steps[0][0], steps[1][0]) and np.array_equal(steps[0][1], steps[1][1])
