@@ -743,8 +743,10 @@ __global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_heps_kernel(const 
 //                         = [-(G> M G<) + (G< M G>)]_il,      M_pq = w_pjkq, block (j,k)
 // wl holds the blocks M contiguously (w_pp / w_ph layouts).  The NB x NB
 // result (r, c) of block blk is stored at out[(r NB + c) NB^2 + blk], which is
-// h^pp as the pair matrix [(ij)][(kl)] and h^ph as the left GEMM operand
-// [(il)][(jk)] of Lambda^ph_ijkl = sum_pq h^ph_ipql G2_qjkp (eq:lambdaph).
+// h^pp as the pair matrix [(ij)][(kl)]; h^ph, the left GEMM operand of
+// Lambda^ph_ijkl = sum_pq h^ph_ipql G2_qjkp (eq:lambdaph), is stored with its
+// column pair swapped, [(il)][(kj)]: the product runs over K = (q, p), so that
+// its right operand G2_qjkp is contiguous along the inner index p.
 template <typename T, typename S, int NB, int KIND>
 __global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_hlad_kernel(const S* __restrict__ wl,
                                                                      const cd* __restrict__ gl,
@@ -810,7 +812,8 @@ __global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_hlad_kernel(const 
 #pragma unroll
             for (int r4 = 0; r4 < 4; ++r4) {
                 int row = ti * 16 + tile_row<T>(r4), col = tj * 16 + tile_col();
-                stc(out + (size_t)(row * NB + col) * NB * NB + blk, ws * acc[t].re(r4), ws * acc[t].im(r4));
+                stc(out + (size_t)(row * NB + col) * NB * NB + (KIND == 1 ? (blk % NB) * NB + blk / NB : blk),
+                    ws * acc[t].re(r4), ws * acc[t].im(r4));
             }
         }
     }
@@ -820,9 +823,9 @@ __global__ __launch_bounds__(MainShape<NB>::THREADS) void gen_hlad_kernel(const 
 // right one of the ladder products):
 //   MODE 0 (GW):   b[(i,k)][(p,q)] = G2_ipkq
 //   MODE 1 (TPP):  b[(p,q)][(k,l)] = G2_pqkl
-//   MODE 2 (TPH):  b[(p,q)][(j,k)] = G2_qjkp
-// The binary64 GW and TPP products read G2 in place, so modes 0 and 1 run for
-// the binary32 copies only; mode 2 runs in both precisions.
+//   MODE 2 (TPH):  b[(q,p)][(j,k)] = G2_qjkp   (the TPH product runs over K = (q, p))
+// The binary64 products read G2 in place, so these copies are made for the
+// binary32 operands only.
 template <typename S, int MODE>
 __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2, S* __restrict__ b,
                                                       int nbp) {
@@ -836,7 +839,7 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
         size_t src;
         if (MODE == 0) src = ((x0 * nbp + x2) * nbp + x1) * nbp + x3;        // (i,k,p,q) <- G2_ipkq
         else if (MODE == 1) src = e;
-        else src = ((x1 * nbp + x2) * nbp + x3) * nbp + x0;                  // (p,q,j,k) <- G2_qjkp
+        else src = ((x0 * nbp + x2) * nbp + x3) * nbp + x1;                  // (q,p,j,k) <- G2_qjkp
         cd v = g2[src];
         stc(b + e, v.x, v.y);
     }
@@ -854,7 +857,10 @@ __global__ __launch_bounds__(256) void gen_bmat_kernel(const cd* __restrict__ g2
 // AG2 reads the GW operand B[(i,k)][(p,q)] = G2_ipkq in place from the binary64
 // G2 instead of a permuted copy: within a K slice p = k0 / nbp is uniform and q
 // runs over 16 consecutive values, so the loads keep their 256-byte rows.
-template <typename T, typename S, int OUT, bool AG2 = false>
+// BG2T reads the TPH operand B[(q,p)][(j,k)] = G2_qjkp in place, at
+// q nbp^3 + (j nbp + k) nbp + p: a K slice is one q and 16 consecutive p, so a
+// column's 16 values are one 256-byte row; they are stored to LDS transposed.
+template <typename T, typename S, int OUT, bool AG2 = false, bool BG2T = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
                                                       void* __restrict__ dst, int n, int nbp) {
@@ -892,11 +898,15 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
     }
     auto fetch = [&](int k0) {
         const size_t acol = AG2 ? (size_t)(k0 / nbp) * nbp * nbp + k0 % nbp : (size_t)k0;
+        const size_t bq = (size_t)(k0 / nbp) * nbp * nbp * nbp + k0 % nbp;   // BG2T
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const int idx = threadIdx.x + q * 256;
             ldc(A + arow[q] + acol + idx % KS, pa_re[q], pa_im[q]);
-            ldc(B + (size_t)(k0 + idx / 64) * n + bn + idx % 64, pb_re[q], pb_im[q]);
+            if (BG2T)
+                ldc(B + bq + (size_t)(bn + idx / KS) * nbp + idx % KS, pb_re[q], pb_im[q]);
+            else
+                ldc(B + (size_t)(k0 + idx / 64) * n + bn + idx % 64, pb_re[q], pb_im[q]);
         }
     };
     fetch(0);
@@ -905,7 +915,10 @@ void gen_gemm_kernel(const S* __restrict__ A, const S* __restrict__ B,
         for (int q = 0; q < PER; ++q) {
             const int idx = threadIdx.x + q * 256;
             a_c[idx / KS][idx % KS] = CT{pa_re[q], pa_im[q]};
-            b_c[idx / 64][idx % 64] = CT{pb_re[q], pb_im[q]};
+            if (BG2T)
+                b_c[idx % KS][idx / KS] = CT{pb_re[q], pb_im[q]};
+            else
+                b_c[idx / 64][idx % 64] = CT{pb_re[q], pb_im[q]};
         }
         __syncthreads();
         if (k0 + KS < n) fetch(k0 + KS);
@@ -1157,12 +1170,18 @@ g1g2_status run_blocks(g1g2_ctx* c, const Regs& in, double ws) {
         const S* wph = mixed ? (const S*)g.w_ph32 : (const S*)g.w_ph;
         hipLaunchKernelGGL((gen_hlad_kernel<T, S, NB, 1>), dim3(grid_vt), dim3(MainShape<NB>::THREADS), 0,
                            c->stream, wph, in.g1, g.gg, (S*)g.heps, ws);
-        hipLaunchKernelGGL((gen_bmat_kernel<S, 2>), dim3(2048), dim3(256), 0, c->stream, in.g2, (S*)g.bmat,
-                           NB);
+        // the TPH operand G2_qjkp: binary64 reads it in place, binary32 from a copy
+        if constexpr (!std::is_same<S, cd>::value)
+            hipLaunchKernelGGL((gen_bmat_kernel<S, 2>), dim3(2048), dim3(256), 0, c->stream, in.g2,
+                               (S*)g.bmat, NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_hlad");
-        hipLaunchKernelGGL((gen_gemm_kernel<T, S, 2>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
-                           (const S*)g.heps, (const S*)g.bmat, (void*)g.dmat, n, NB);
+        if constexpr (std::is_same<S, cd>::value)
+            hipLaunchKernelGGL((gen_gemm_kernel<T, S, 2, false, true>), dim3(n / 64, n / 64), dim3(256), 0,
+                               c->stream, (const S*)g.heps, (const S*)in.g2, (void*)g.dmat, n, NB);
+        else
+            hipLaunchKernelGGL((gen_gemm_kernel<T, S, 2>), dim3(n / 64, n / 64), dim3(256), 0, c->stream,
+                               (const S*)g.heps, (const S*)g.bmat, (void*)g.dmat, n, NB);
         HIP_OK(c, hipGetLastError());
         prof_mark(c, "gen_gemm");
     }
